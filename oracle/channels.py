@@ -1,0 +1,98 @@
+"""Kraus channels, the CPTP condition and unitary-mixture detection.
+
+Sec. 2.2 (noise-channel paragraph): a channel is a set of Kraus operators
+{K_i} with sum_i K_i^dagger K_i = I (CPTP); a trajectory applies K_i with
+probability <psi|K_i^dagger K_i|psi>.  Feature 2 of the same section: a
+unitary-mixture channel has K_i proportional to a unitary U_i.  The printed
+"K_i = p_i U_i" is read as K_i = sqrt(p_i) U_i, i.e. K_i^dagger K_i = p_i I,
+which makes p_i independent of the state.
+
+Conventions (the paper names none):
+* depolarizing(1q, p): {sqrt(1-p) I, sqrt(p/3) X, sqrt(p/3) Y, sqrt(p/3) Z};
+* depolarizing(2q, p): {sqrt(1-p) II} then sqrt(p/15) P_a (x) P_b for the 15
+  non-identity pairs, index k = 4a + b in I,X,Y,Z order, where P_a acts on the
+  site's second qubit (matrix bit 1) and P_b on its first (matrix bit 0);
+* xflip(p): {sqrt(1-p) I, sqrt(p) X};
+* pauli(px, py, pz): {sqrt(1-px-py-pz) I, sqrt(px) X, sqrt(py) Y, sqrt(pz) Z};
+* u3_mixture(p, angles): {sqrt(1-p) I, sqrt(p) U3(angles)};
+* amplitude_damping(gamma): {[[1,0],[0,sqrt(1-gamma)]], [[0,sqrt(gamma)],[0,0]]}.
+Index 0 is the no-error operator of every channel above.
+"""
+
+import math
+
+import numpy as np
+
+from .gates import PAULIS, u3, I2
+
+
+def kraus_ops(ch):
+    name = ch["name"]
+    if name == "depolarizing":
+        p = ch["p"]
+        if ch["nq"] == 1:
+            a0 = math.sqrt(1.0 - p)
+            a = math.sqrt(p / 3.0)
+            return [a0 * PAULIS[0]] + [a * P for P in PAULIS[1:]]
+        a0 = math.sqrt(1.0 - p)
+        a = math.sqrt(p / 15.0)
+        ops = []
+        for ia in range(4):
+            for ib in range(4):
+                m = np.kron(PAULIS[ia], PAULIS[ib])
+                ops.append((a0 if (ia == 0 and ib == 0) else a) * m)
+        return ops
+    if name == "xflip":
+        p = ch["p"]
+        return [math.sqrt(1.0 - p) * PAULIS[0], math.sqrt(p) * PAULIS[1]]
+    if name == "pauli":
+        px, py, pz = ch["probs"]
+        return [math.sqrt(1.0 - px - py - pz) * PAULIS[0], math.sqrt(px) * PAULIS[1],
+                math.sqrt(py) * PAULIS[2], math.sqrt(pz) * PAULIS[3]]
+    if name == "u3_mixture":
+        p = ch["p"]
+        return [math.sqrt(1.0 - p) * I2, math.sqrt(p) * u3(*ch["params"])]
+    if name == "amplitude_damping":
+        g = ch["gamma"]
+        return [np.array([[1, 0], [0, math.sqrt(1.0 - g)]], dtype=np.complex128),
+                np.array([[0, math.sqrt(g)], [0, 0]], dtype=np.complex128)]
+    raise ValueError(f"unknown channel {name}")
+
+
+def cptp_error(kraus):
+    """max_ij | (sum_k K_k^dagger K_k - I)_ij |."""
+    d = kraus[0].shape[0]
+    acc = np.zeros((d, d), dtype=np.complex128)
+    for K in kraus:
+        acc += K.conj().T @ K
+    return float(np.max(np.abs(acc - np.eye(d))))
+
+
+def kraus_weight(K):
+    """tr(K^dagger K) / d, summed element by element in row-major order.
+
+    For K = sqrt(p) U this is p.  A plain sequential loop, so the value does not
+    depend on a library's summation order."""
+    d = K.shape[0]
+    s = 0.0
+    for i in range(d):
+        for j in range(d):
+            z = K[i, j]
+            s += z.real * z.real + z.imag * z.imag
+    return s / d
+
+
+def unitary_mixture(kraus, tol=1e-12):
+    """Return (probs, unitaries) if every K_k^dagger K_k = p_k I within ``tol``, else None.
+
+    U_k = K_k / sqrt(p_k); a zero-probability operator keeps U_k = I (never drawn)."""
+    d = kraus[0].shape[0]
+    probs = []
+    unitaries = []
+    for K in kraus:
+        p = kraus_weight(K)
+        if np.max(np.abs(K.conj().T @ K - p * np.eye(d))) > tol:
+            return None
+        probs.append(p)
+        unitaries.append(K / math.sqrt(p) if p > 0 else np.eye(d, dtype=np.complex128))
+    return probs, unitaries

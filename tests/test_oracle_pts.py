@@ -1,0 +1,134 @@
+"""Pins of the oracle's pre-trajectory sampling (Sec. 3.1) and its random streams."""
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import rng as orng
+from oracle.pts import (_categorical, alg2_draw, allocate_multiplicity, allocate_reweight,
+                        joint_prob, most_likely, most_likely_bruteforce, proportional, score,
+                        costs)
+
+# --- Philox4x64-10 written out from the published description (Salmon et al., SC'11):
+# two 64x64->128 multiplies per round, Weyl key schedule, 10 rounds.
+M0, M1 = 0xD2E7470EE14C6C93, 0xCA5A826395121157
+W0, W1 = 0x9E3779B97F4A7C15, 0xBB67AE8584CAA73B
+MASK = (1 << 64) - 1
+
+
+def _philox_block(ctr, key):
+    c = list(ctr)
+    k = list(key)
+    for r in range(10):
+        if r:
+            k = [(k[0] + W0) & MASK, (k[1] + W1) & MASK]
+        p0 = M0 * c[0]
+        p1 = M1 * c[2]
+        c = [(p1 >> 64) ^ c[1] ^ k[0], p1 & MASK, (p0 >> 64) ^ c[3] ^ k[1], p0 & MASK]
+    return c
+
+
+@pytest.mark.parametrize("key", [(0, 0), (0, orng.key1(2, 3, 17)), (12345, orng.key1(1, 5, 999)),
+                                 (2**63 + 5, 2**64 - 1)])
+def test_philox_stream_matches_published_definition(key):
+    w = orng.words(key[0], key[1], 13)
+    for j in range(13):
+        # word j of a stream is word j % 4 of the block with counter j // 4 + 1
+        assert int(w[j]) == _philox_block([j // 4 + 1, 0, 0, 0], key)[j % 4]
+
+
+def test_uniform_construction():
+    w = orng.words(7, 9, 8)
+    u = orng.uniforms(7, 9, 8)
+    for a, b in zip(w, u):
+        assert b == (int(a) >> 11) / 2.0**53
+        assert 0.0 <= b < 1.0
+
+
+def test_categorical_upper_bound_rule():
+    p = [0.5, 0.25, 0.25]
+    assert _categorical(0.0, p) == 0
+    assert _categorical(0.4999999, p) == 0
+    assert _categorical(0.5, p) == 1
+    assert _categorical(0.7499999, p) == 1
+    assert _categorical(0.75, p) == 2
+    assert _categorical(1.0 - 2.0**-53, p) == 2
+    assert _categorical(0.3, [0.0, 1.0]) == 1      # zero-probability index never selected
+
+
+def _chi2_ok(counts, probs, n, thresh=40.0):
+    """Pearson statistic small for 3-4 bins (p-value far from tiny)."""
+    exp = np.asarray(probs) * n
+    return float(np.sum((np.asarray(counts) - exp) ** 2 / exp)) < thresh
+
+
+def test_proportional_per_site_frequencies():
+    sp = [[0.7, 0.1, 0.1, 0.1], [0.6, 0.4], [0.5, 0.2, 0.2, 0.1]]
+    T = 6000
+    recs, cnt = proportional(sp, 4, 1, T, merge=False)
+    for s, probs in enumerate(sp):
+        c = np.zeros(len(probs))
+        for rec in recs:
+            c[dict(rec).get(s, 0)] += 1
+        assert _chi2_ok(c, probs, T)
+
+
+def test_alg2_literal_closed_form_bias():
+    """Algorithm 2 as printed on a 1q depolarizing site: P(X) = q, P(Y) = (1-q) q,
+    P(Z) = (1-q)^2 q, P(none) = (1-q)^3 with q = p/3 -- not the channel's p/3 each."""
+    p = 0.45
+    q = p / 3
+    sp = [[1 - p, q, q, q]]
+    T = 8000
+    c = np.zeros(4)
+    for t in range(T):
+        rec = alg2_draw(sp, 2, 1, t)
+        c[dict(rec).get(0, 0)] += 1
+    expect = [(1 - q) ** 3, q, (1 - q) * q, (1 - q) ** 2 * q]
+    assert _chi2_ok(c, expect, T)
+    # the bias against the channel's own probabilities is visible at this size
+    assert not _chi2_ok(c, sp[0], T, thresh=100.0)
+
+
+def test_multiplicity_allocation_by_hand():
+    assert allocate_multiplicity([3, 1], 4, 10) == [8, 2]
+    assert allocate_multiplicity([1, 1, 1], 3, 10) == [4, 3, 3]
+    assert allocate_multiplicity([2, 1, 1], 4, 1000) == [500, 250, 250]
+    m = allocate_multiplicity([5, 3, 2, 1, 1], 12, 10**6 + 7)
+    assert sum(m) == 10**6 + 7
+
+
+def test_reweight_allocation_by_hand():
+    assert allocate_reweight([0.5, 0.25, 0.25], 8) == [4, 2, 2]
+    assert allocate_reweight([0.2, 0.2, 0.2], 10) == [4, 3, 3]
+    m = allocate_reweight([0.3, 1e-9, 0.1, 0.05], 10**9)
+    assert sum(m) == 10**9
+
+
+def test_joint_probability_product():
+    sp = [[0.9, 0.1], [0.8, 0.05, 0.15]]
+    assert joint_prob((), sp) == 0.9 * 0.8
+    assert joint_prob(((1, 2),), sp) == 0.9 * 0.15
+    assert joint_prob(((0, 1), (1, 1)), sp) == 0.1 * 0.05
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_most_likely_matches_exhaustive_sort(seed):
+    rng = np.random.default_rng(seed)
+    n_sites = int(rng.integers(3, 9))
+    proto = [[1 - 0.1, 0.1 / 3, 0.1 / 3, 0.1 / 3], [0.8, 0.2], [0.7, 0.1, 0.15, 0.05]]
+    sp = [proto[int(rng.integers(3))] for _ in range(n_sites)]   # repeated types -> exact ties
+    total = int(np.prod([len(p) for p in sp]))
+    for K in (1, 5, 17, min(200, total), total):
+        r1, s1 = most_likely(sp, K)
+        r2, s2 = most_likely_bruteforce(sp, K)
+        assert r1 == r2
+        assert s1 == s2
+
+
+def test_score_is_order_canonical():
+    sp = [[0.9, 0.1], [0.9, 0.1], [0.8, 0.2]]
+    c = costs(sp)
+    assert score(((0, 1), (2, 1)), c) == score(((1, 1), (2, 1)), c)
+    assert math.isclose(score(((0, 1),), c), -math.log(0.1 / 0.9))
