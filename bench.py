@@ -1,0 +1,175 @@
+"""PTSBE throughput on one MI355X.
+
+Workload (default): 20 qubits, 40 brick layers of random U3 + CZ with a coherent
+RZ(eps) over-rotation per CZ, 1q depolarizing 1e-3 and 2q depolarizing 5e-3;
+512 proportional pre-sampled draws sharing 10^6 shots (about 480 unique
+trajectories), complex64 states with FP64 norms and CDFs.
+
+One step = one ptsbe_run_batch call over the whole trajectory set: state
+preparation of every trajectory (fused tile passes), FP64 norm + CDF scans,
+and the sorted-uniform sampler writing 10^6 tagged shots -- inputs (plan
+tables) resident, outputs left on the device.
+
+Printed JSON: value = shots/s of batched PTSBE; the per-shot trajectory
+baseline (Algorithm 1: one state preparation per shot, same kernels, same
+GPU), the roofline of the dominant kernel (the tile pass) from the library's
+HIP-event stage timer, and the FP64 oracle timed on the host on a bounded sample.
+"""
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "shots/s batched PTSBE vs per-shot trajectories; gate-kernel HBM GB/s"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    sys.stderr.write(msg + "\n")
+    sys.stderr.flush()
+
+
+def cpu_baseline(wl, n_traj_sample, g):
+    """The oracle (complex128 NumPy) on the first ``n_traj_sample`` trajectories:
+    state preparation + sampling of their shots, extrapolated to whole-job shots/s
+    by the average number of shots per trajectory."""
+    import numpy as np
+    from oracle.noise import expand, site_channels
+    from oracle.sampling import sample
+    from oracle.statevector import run_record
+    circ = wl["circuit"]
+    ss = expand(circ)
+    ch = site_channels(circ)
+    avg_m = float(np.mean(g["m"]))
+    t0 = time.perf_counter()
+    for a in range(n_traj_sample):
+        psi, _ = run_record(circ, g["records"][a], steps_sites=ss, chans=ch)
+        sample(psi, int(round(avg_m)), wl["seed"], wl["cfg"], a)
+    dt = time.perf_counter() - t0
+    threads = os.environ.get("OMP_NUM_THREADS") or os.environ.get("OPENBLAS_NUM_THREADS")
+    return {"value": n_traj_sample * avg_m / dt, "unit": "shots/s", "cores": int(threads) if threads else 1,
+            "kind": "oracle",
+            "sample": f"{n_traj_sample} of {len(g['m'])} trajectories prepared by the complex128 oracle "
+                      f"and sampled at the average {avg_m:.0f} shots each ({dt:.1f} s), extrapolated "
+                      f"linearly to the whole job"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-baseline", action="store_true", help="skip the per-shot GPU baseline")
+    ap.add_argument("--baseline-shots", type=int, default=512)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: the PTSBE path here is single-GPU (inter-trajectory "
+              f"sharding is a partition of the trajectory set, not built); --gpus {args.gpus} is "
+              f"not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2504_16297_amd as P
+    from workloads import c2_workload
+
+    torch.cuda.set_device(0)
+    wl = c2_workload()
+    circ = wl["circuit"]
+    pts = wl["pts"]
+    t0 = time.perf_counter()
+    plan = P.ptsbe_plan(circ, precision=wl["precision"])
+    t_plan = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=pts["n_draws"], total_shots=pts["total_shots"],
+                              seed=wl["seed"], cfg=wl["cfg"])
+    t_pts = time.perf_counter() - t0
+    g = ts.get()
+    B = len(g["m"])
+    S = int(g["total_shots"])
+    log(f"[bench] {wl['name']}: {B} unique trajectories, {plan.info['n_passes']} tile passes, "
+        f"plan {t_plan*1e3:.1f} ms, PTS {t_pts*1e3:.1f} ms")
+
+    ws_bytes = P.ptsbe_workspace_size(plan, ts, mode="shots")
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    out = {"bits": torch.empty(S, dtype=torch.int32, device="cuda"),
+           "traj": torch.empty(S, dtype=torch.int32, device="cuda")}
+    stream = torch.cuda.current_stream()
+
+    def step(timing=None):
+        return P.ptsbe_run_batch(plan, ts, mode="shots", seed=wl["seed"], cfg=wl["cfg"], workspace=ws,
+                                 out=out, stream=stream, timing=timing)
+
+    for i in range(args.warmup):
+        step()
+        log(f"[bench] warmup {i + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+    timings = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        tm = np.zeros(8)
+        step(tm)
+        timings.append(tm)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = dt * 1e3 / args.steps
+    value = S * args.steps / dt
+    T = np.sum(timings, axis=0)
+    pass_ms = T[0] / T[1]
+    pass_bytes = T[6] / T[1]
+    gbs = pass_bytes / (pass_ms * 1e-3) / 1e9
+    log(f"[bench] {ms_per_step:.2f} ms/step, {value:.4g} shots/s; passes {T[0]/args.steps:.2f} ms/step "
+        f"({T[1]/args.steps:.0f} launches), scan {T[3]/args.steps:.2f} ms, sampler {T[4]/args.steps:.2f} ms")
+
+    result = {"metric": METRIC, "value": value, "unit": "shots/s", "n_gpus": 1, "steps": args.steps,
+              "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+              "vs_baseline": None, "dtype": "c64 (fp32 state, fp64 norm/CDF)", "data": "synthetic",
+              "config": {"workload": wl["name"], "n_qubits": 20, "layers": 40, "draws": pts["n_draws"],
+                         "unique_trajectories": B, "total_shots": S, "parallelism": "single GPU, batched"},
+              "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                           "kernel": "k_pass (fused tile pass)",
+                           "avg_launch_ms": pass_ms, "bytes_per_launch": pass_bytes},
+              "stages_ms_per_step": {"passes": T[0] / args.steps, "scan": T[3] / args.steps,
+                                     "sampler": T[4] / args.steps, "total_events": T[5] / args.steps},
+              "plan_ms": t_plan * 1e3, "pts_ms": t_pts * 1e3}
+
+    if not args.no_baseline:
+        nb = args.baseline_shots
+        tb = P.ptsbe_sample_kraus(plan, "per_shot", n_draws=nb, seed=wl["seed"], cfg=wl["cfg"])
+        bws = torch.empty(P.ptsbe_workspace_size(plan, tb, mode="shots"), dtype=torch.uint8, device="cuda")
+        bout = {"bits": torch.empty(nb, dtype=torch.int32, device="cuda"),
+                "traj": torch.empty(nb, dtype=torch.int32, device="cuda")}
+        P.ptsbe_run_batch(plan, tb, seed=wl["seed"], cfg=wl["cfg"], workspace=bws, out=bout)
+        torch.cuda.synchronize()
+        reps = 2
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            P.ptsbe_run_batch(plan, tb, seed=wl["seed"], cfg=wl["cfg"], workspace=bws, out=bout)
+        torch.cuda.synchronize()
+        bdt = time.perf_counter() - t0
+        base = nb * reps / bdt
+        result["per_shot_baseline"] = {"value": base, "unit": "shots/s",
+                                       "shots": nb * reps, "seconds": bdt,
+                                       "note": "Algorithm 1: one fresh draw and one full state "
+                                               "preparation per shot, batched, same kernels"}
+        result["speedup_vs_per_shot"] = value / base
+        log(f"[bench] per-shot baseline {base:.4g} shots/s, speedup {value / base:.1f}x")
+        del bws
+
+    if not args.no_cpu:
+        log("[bench] timing the oracle on the host ...")
+        result["cpu_baseline"] = cpu_baseline(wl, 1, g)
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

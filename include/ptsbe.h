@@ -1,0 +1,295 @@
+/*
+ * ptsbe.h -- C ABI of the PTSBE hot path on MI355X (gfx950).
+ *
+ * Pre-Trajectory Sampling with Batched Execution (arXiv 2504.16297):
+ *   1. PTS (Sec. 3.1): choose whole Kraus-operator sequences alpha and a shot
+ *      count m_alpha for each, before any state is simulated.
+ *   2. BE (Sec. 3): prepare each fixed-Kraus state once on the GPU, then draw
+ *      all m_alpha bitstrings from |psi_alpha|^2 in bulk; each shot carries
+ *      the id of its trajectory, whose error record is kept on the host
+ *      (Sec. 1, third innovation: error provenance as lightweight metadata).
+ *
+ * Conventions
+ *  - Basis index x = sum_q x_q 2^q (qubit 0 is the least significant bit).
+ *    A k-qubit matrix acting on qubits (q_0..q_{k-1}) has row/column bit j
+ *    <-> qubit q_j.  Matrices are complex128, row-major, interleaved (re, im).
+ *  - Every call returns a ptsbe_status; on error nothing has been enqueued on
+ *    the stream, outputs are undefined and ptsbe_last_error() (thread-local)
+ *    explains.  No C++ exception crosses this boundary.
+ *  - Handles (plans, trajectory sets) are library-owned host objects,
+ *    immutable after creation, shareable across threads, freed by their
+ *    destroy call.  A handle must outlive the stream work enqueued with it.
+ *  - Every device buffer (workspace, outputs, uniforms) is owned by the
+ *    caller.  The library never allocates device memory.
+ *  - Device launches are asynchronous on the caller's hipStream_t (passed as
+ *    void*; NULL is the null stream).  Device-side conditions (a
+ *    non-deterministic measure-reset) are written to a status word in the
+ *    workspace; ptsbe_run_status() waits for the stream and reads it.
+ */
+#ifndef PTSBE_H
+#define PTSBE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PTSBE_OK = 0,
+    PTSBE_E_ARG = 1,            /* invalid argument: null pointer, bad qubit, size mismatch */
+    PTSBE_E_NOT_CPTP = 2,       /* a channel violates sum_k K_k^dagger K_k = I (Sec. 2.2) beyond 1e-12 */
+    PTSBE_E_UNSUPPORTED = 3,    /* valid but not implemented (a non-unitary-mixture noise channel, n > 34) */
+    PTSBE_E_CAPACITY = 4,       /* output capacity below the total shot count */
+    PTSBE_E_OOM = 5,            /* workspace smaller than ptsbe_workspace_size() */
+    PTSBE_E_DEVICE = 6,         /* a HIP call failed */
+    PTSBE_E_NONDET_MEASURE = 7  /* a measure-reset outcome was not deterministic (device status) */
+} ptsbe_status;
+
+/* Thread-local description of the last error of this thread. */
+const char* ptsbe_last_error(void);
+/* Library version string. */
+const char* ptsbe_version(void);
+
+/* ------------------------------------------------------------------ circuit */
+
+enum {
+    PTSBE_OP_GATE = 0,          /* fixed matrix `mat` on q[0..nq-1], nq <= 4 */
+    PTSBE_OP_PARAM = 1,         /* exp(-i theta P / 2) on q[0], theta = params[index], P = gen */
+    PTSBE_OP_NOISE = 2,         /* explicit noise site: channel `index` on q[0..nq-1] */
+    PTSBE_OP_MEASURE_RESET = 3, /* mid-circuit measure of q[0] (recorded), then reset to |0> */
+    PTSBE_OP_PROJECT0 = 4       /* apply |0><0| on q[0] and renormalise (no record) */
+};
+enum { PTSBE_GEN_X = 1, PTSBE_GEN_Y = 2, PTSBE_GEN_Z = 3 };
+
+typedef struct {
+    uint32_t kind;              /* PTSBE_OP_* */
+    uint32_t nq;                /* number of qubits the op acts on (1..4; 1 for PARAM/MR/PROJECT0) */
+    uint32_t q[4];              /* distinct qubits, each < n_qubits */
+    const double* mat;          /* GATE: 2^nq x 2^nq complex128, read during ptsbe_plan only */
+    int32_t index;              /* PARAM: parameter index; NOISE: channel index */
+    uint32_t gen;               /* PARAM: PTSBE_GEN_X/Y/Z */
+    uint32_t tag;               /* caller's gate-type tag, matched by PTSBE_ATTACH_AFTER_TAG rules */
+    uint32_t reserved;
+} ptsbe_op;
+
+typedef struct {
+    uint32_t n_qubits;          /* 1..34 */
+    uint32_t n_ops;
+    const ptsbe_op* ops;
+} ptsbe_circuit;
+
+/* ------------------------------------------------------------- noise model */
+
+/* A channel {K_0 .. K_{n_kraus-1}} on nq (1 or 2) qubits: n_kraus consecutive
+ * 2^nq x 2^nq complex128 matrices.  It must be CPTP (Sec. 2.2) and a unitary
+ * mixture, K_k^dagger K_k = p_k I (Sec. 2.2 feature 2, read as
+ * K_k = sqrt(p_k) U_k); then p_k is state independent and the site can be
+ * pre-sampled.  K_0 is taken as the "no error" operator of the record.
+ * At most 16 operators per channel. */
+typedef struct {
+    uint32_t nq;
+    uint32_t n_kraus;
+    const double* kraus;
+} ptsbe_channel;
+
+enum {
+    PTSBE_ATTACH_AFTER_TAG = 0,      /* a site after every GATE/PARAM op with op.tag == tag, on its qubits */
+    PTSBE_ATTACH_BEFORE_MEASURE = 1, /* a site before every MEASURE_RESET, on its qubit */
+    PTSBE_ATTACH_BEFORE_READOUT = 2  /* at the end, one site per qubit set in qmask, ascending */
+};
+
+typedef struct {
+    uint32_t when;
+    uint32_t tag;
+    uint32_t channel;
+    uint32_t reserved;
+    uint64_t qmask;
+} ptsbe_attach;
+
+typedef struct {
+    uint32_t n_channels;
+    const ptsbe_channel* channels;
+    uint32_t n_rules;
+    const ptsbe_attach* rules;
+} ptsbe_noise_model;
+
+/* Site order ("NoisyCircuit" of Algorithm 2): walking the ops in order, the
+ * BEFORE_MEASURE sites of an MEASURE_RESET come before it (rule order); an
+ * explicit NOISE op is a site at its position; AFTER_TAG sites follow their
+ * op (rule order); BEFORE_READOUT sites come last (rule order, then qubit). */
+
+/* -------------------------------------------------------------------- plan */
+
+enum { PTSBE_C64 = 0, PTSBE_C128 = 1 };
+
+typedef struct {
+    uint32_t precision;         /* PTSBE_C64 (FP32 state) or PTSBE_C128 (FP64 state) */
+    uint32_t tile_qubits;       /* 0 = automatic; else qubits per LDS tile (4..13) */
+    uint32_t flags;             /* reserved, 0 */
+    uint32_t reserved;
+} ptsbe_plan_opts;
+
+typedef struct ptsbe_plan_s* ptsbe_plan_t;
+typedef struct ptsbe_trajset_s* ptsbe_trajset_t;
+
+typedef struct {
+    uint32_t n_qubits;
+    uint32_t n_sites;           /* noise sites after rule expansion */
+    uint32_t n_params;          /* 1 + largest PARAM index, 0 if none */
+    uint32_t n_measure;         /* MEASURE_RESET ops (record length per trajectory) */
+    uint32_t n_passes;          /* fused state passes (tile kernels) per trajectory */
+    uint32_t n_steps;           /* passes + measurement steps */
+    uint32_t precision;
+    uint32_t tile_qubits;
+    uint32_t max_kraus;         /* largest channel size */
+    uint32_t total_kraus;       /* sum over sites of the channel size */
+} ptsbe_plan_info;
+
+/* Validate a circuit and noise model and build the execution plan: expand the
+ * noise rules into sites, check CPTP and the unitary-mixture form of every
+ * channel, and fuse the operations into tile passes.  `opts` may be NULL.
+ * The matrices are copied; the caller's arrays may be freed afterwards. */
+ptsbe_status ptsbe_plan(const ptsbe_circuit* circuit, const ptsbe_noise_model* noise,
+                        const ptsbe_plan_opts* opts, ptsbe_plan_t* out);
+ptsbe_status ptsbe_plan_get_info(ptsbe_plan_t plan, ptsbe_plan_info* out);
+/* Per-site probabilities p_{s,k}: offsets[n_sites+1] into probs[total_kraus];
+ * qubits[2*n_sites] (second entry 0xffffffff for 1-qubit sites); either may be NULL. */
+ptsbe_status ptsbe_plan_get_sites(ptsbe_plan_t plan, uint32_t* offsets, double* probs,
+                                  uint32_t* qubits);
+void ptsbe_plan_destroy(ptsbe_plan_t plan);
+
+/* ---------------------------------------------------- pre-trajectory sampling */
+
+enum {
+    PTSBE_PTS_PROPORTIONAL = 0, /* per site one exact categorical draw: records appear with p_alpha */
+    PTSBE_PTS_ALG2_LITERAL = 1, /* Algorithm 2 as printed (r <= p per operator, first compatible wins) */
+    PTSBE_PTS_MOST_LIKELY = 2,  /* the k_max records of highest joint probability (Sec. 3.1) */
+    PTSBE_PTS_PER_SHOT = 3      /* conventional trajectories (Algorithm 1): one undeduplicated draw per shot */
+};
+enum {
+    PTSBE_ALLOC_MULTIPLICITY = 0, /* m_alpha = count_alpha * total_shots / n_draws, largest remainder */
+    PTSBE_ALLOC_REWEIGHT = 1,     /* m_alpha ~ p_alpha / sum_selected p_beta (Sec. 3.1), largest remainder */
+    PTSBE_ALLOC_UNIFORM = 2       /* m_alpha = nshots for every record (Algorithm 2) */
+};
+
+typedef struct {
+    uint32_t mode;              /* PTSBE_PTS_* */
+    uint32_t alloc;             /* PTSBE_ALLOC_* (PER_SHOT forces one shot per draw) */
+    uint64_t n_draws;           /* PROPORTIONAL, ALG2_LITERAL, PER_SHOT */
+    uint64_t k_max;             /* MOST_LIKELY */
+    uint64_t total_shots;       /* MULTIPLICITY, REWEIGHT */
+    uint64_t nshots;            /* UNIFORM */
+    uint64_t seed;              /* first Philox key word */
+    uint32_t cfg;               /* workload id, bits 48..55 of the second key word */
+    uint32_t stream;            /* 0: default (1 = PTS, 3 = PER_SHOT); bits 56..63 of the key */
+    double p_min, p_max;        /* probability band on p_alpha; both 0 = no band (Sec. 3.1) */
+} ptsbe_pts_opts;
+
+/* Run a PTS algorithm (Sec. 3.1).  Draw t of PROPORTIONAL uses the Philox4x64-10
+ * stream keyed [seed, stream<<56 | cfg<<48 | t]; its word s (NumPy's raw order:
+ * counter block s/4 + 1, word s%4) gives site s the uniform (word >> 11) 2^-53
+ * and k_s = the smallest k with u < p_0 + ... + p_k.  Equal records merge
+ * (uniqueKraus) in order of first appearance. */
+ptsbe_status ptsbe_sample_kraus(ptsbe_plan_t plan, const ptsbe_pts_opts* opts,
+                                ptsbe_trajset_t* out);
+/* A trajectory set from caller records: rec_off[n_traj+1] into rec_site/rec_kraus
+ * (site ids ascending within a record, kraus index >= 1), m[n_traj] shots each.
+ * p_alpha is recomputed; counts are 1.  alpha0 is the global id of record 0. */
+ptsbe_status ptsbe_trajset_from_records(ptsbe_plan_t plan, uint32_t n_traj, const uint32_t* rec_off,
+                                        const uint32_t* rec_site, const uint8_t* rec_kraus,
+                                        const uint64_t* m, uint64_t alpha0, ptsbe_trajset_t* out);
+/* Trajectories [begin, end) as a new set that keeps their global ids, so the
+ * counter-based sampler reproduces them bit for bit (resume by range). */
+ptsbe_status ptsbe_trajset_slice(ptsbe_trajset_t ts, uint32_t begin, uint32_t end,
+                                 ptsbe_trajset_t* out);
+/* Query a trajectory set.  Scalars may be NULL; arrays are caller-owned host
+ * arrays of n_traj (m, p, count), n_traj+1 (rec_off) or n_entries (rec_site,
+ * rec_kraus) elements, or NULL to skip. */
+ptsbe_status ptsbe_trajset_get(ptsbe_trajset_t ts, uint32_t* n_traj, uint64_t* total_shots,
+                               uint32_t* n_entries, uint64_t* alpha0, uint64_t* m, double* p,
+                               uint64_t* count, uint32_t* rec_off, uint32_t* rec_site,
+                               uint8_t* rec_kraus);
+void ptsbe_trajset_destroy(ptsbe_trajset_t ts);
+
+/* ------------------------------------------------------- batched execution */
+
+enum {
+    PTSBE_RUN_SHOTS = 0,        /* prepare, then sample m_alpha shots per trajectory */
+    PTSBE_RUN_STATES = 1,       /* prepare, normalise, copy states to d_state_out */
+    PTSBE_RUN_EXPECTATION = 2   /* prepare, then <O>_alpha per trajectory (diagonal O) */
+};
+
+typedef struct {
+    uint32_t mode;              /* PTSBE_RUN_* */
+    uint32_t cfg;               /* sampler key: [seed, 2<<56 | cfg<<48 | alpha] */
+    uint64_t seed;
+    uint32_t sort_chunk;        /* shots sorted per chunk: power of two, 256..4096 (0 = 4096) */
+    uint32_t max_batch;         /* trajectories resident at once (0 = as many as fit) */
+    const double* d_uniforms;   /* optional device FP64 uniforms, one per shot in output order */
+    const double* params;       /* host array of n_params values (NULL if none) */
+    void* d_state_out;          /* STATES: n_traj x 2^n amplitudes (complex64 / complex128) */
+    double* d_expval;           /* EXPECTATION: n_traj FP64 values */
+    const double* obs_coef;     /* EXPECTATION: n_terms coefficients (host) */
+    const uint64_t* obs_zmask;  /* EXPECTATION: n_terms Z-string qubit masks (host) */
+    uint32_t n_terms;
+    uint32_t reserved;
+    double* timing;             /* optional host array[8]: measured with HIP events on `stream`
+                                   (the call then waits for the stream): [0] ms in tile passes,
+                                   [1] pass launches, [2] ms in measure-reset steps, [3] ms in
+                                   norm/CDF scans, [4] ms in the sampler, [5] ms total,
+                                   [6] state bytes moved by the passes (2 x state size per loaded
+                                   pass, 1 x for the initialising pass), [7] sampler launches */
+} ptsbe_run_opts;
+
+/* Device workspace in bytes needed by ptsbe_run_batch / ptsbe_adjoint_grad. */
+ptsbe_status ptsbe_workspace_size(ptsbe_plan_t plan, ptsbe_trajset_t ts, const ptsbe_run_opts* opts,
+                                  size_t* bytes);
+
+/* Batched execution (Sec. 3, BE): every trajectory's state is prepared once
+ * by the gfx950 tile kernels, normalised, turned into an FP64 cumulative
+ * distribution (in place), and its m_alpha shots are drawn by an upper-bound
+ * search of sorted uniforms.  Output j of trajectory alpha lands at
+ * shot_offset(alpha) + j with shot_offset the exclusive prefix sum of m:
+ * d_bits[j] is the basis index (uint32 if n <= 32, else uint64), d_traj[j]
+ * the global trajectory id.  d_mr_bits (optional, n_traj x n_measure bytes)
+ * receives each trajectory's measure-reset record.  All device pointers are
+ * caller-owned; the call only enqueues work on `stream`. */
+ptsbe_status ptsbe_run_batch(ptsbe_plan_t plan, ptsbe_trajset_t ts, const ptsbe_run_opts* opts,
+                             void* d_ws, size_t ws_bytes, void* d_bits, uint32_t* d_traj,
+                             uint64_t capacity, uint8_t* d_mr_bits, void* stream);
+
+/* Wait for `stream` and read the device status word of a workspace last used
+ * by ptsbe_run_batch: PTSBE_OK or PTSBE_E_NONDET_MEASURE. */
+ptsbe_status ptsbe_run_status(ptsbe_plan_t plan, const void* d_ws, void* stream);
+
+/* Adjoint gradient of E(theta) = sum_alpha w_alpha <psi_alpha|O|psi_alpha>,
+ * w_alpha = count_alpha / sum count (for unitary-mixture noise w does not depend
+ * on theta): forward preparation, lambda = O psi, then a reverse sweep that
+ * un-applies each operation on psi and lambda and accumulates
+ * 2 Re <lambda| dG/dtheta |psi> in FP64.  O = sum_t coef_t Z-string(zmask_t).
+ * d_params: device FP64 parameters; d_expval: 1 FP64; d_grad: n_params FP64. */
+ptsbe_status ptsbe_adjoint_grad(ptsbe_plan_t plan, ptsbe_trajset_t ts, const double* params,
+                                const double* obs_coef, const uint64_t* obs_zmask, uint32_t n_terms,
+                                void* d_ws, size_t ws_bytes, double* d_expval, double* d_grad,
+                                void* stream);
+
+/* ---------------------------------------------------------- gate library */
+
+/* Standard gate matrices (complex128, row-major interleaved) for building
+ * circuits: name in {U3, RX, RY, RZ, H, X, Y, Z, S, T, CZ, CNOT, SWAP};
+ * params as in the usual definitions (U3: theta, phi, lambda).  out holds
+ * 2 * 4^nq doubles; *nq receives the qubit count. */
+ptsbe_status ptsbe_std_gate(const char* name, const double* params, double* out, uint32_t* nq);
+/* Standard channels: name in {depolarizing (nq 1|2, p), xflip (p), pauli (px, py, pz),
+ * u3_mixture (p, theta, phi, lambda), amplitude_damping (gamma)}.  out holds
+ * n_kraus * 2 * 4^nq doubles; *n_kraus receives the operator count. */
+ptsbe_status ptsbe_std_channel(const char* name, uint32_t nq, const double* params, double* out,
+                               uint32_t* n_kraus);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PTSBE_H */

@@ -1,0 +1,357 @@
+"""PTSBE on MI355X: Python binding of libptsbe (include/ptsbe.h).
+
+Argument marshalling only: circuits described as plain dictionaries (see
+``workloads``) are turned into the C structures of the ABI, torch tensors are
+passed as raw device pointers with torch's current HIP stream, and every step
+of planning, pre-trajectory sampling and batched execution runs inside the
+library (host planner in C++, hot path in gfx950 HIP kernels).
+"""
+
+import ctypes as C
+import zlib
+
+import numpy as np
+
+from . import _lib as L
+from ._lib import PtsbeError, lib, check
+
+__all__ = ["ptsbe_plan", "ptsbe_sample_kraus", "ptsbe_trajset_from_records", "ptsbe_workspace_size",
+           "ptsbe_run_batch", "ptsbe_run_status", "ptsbe_adjoint_grad", "std_gate", "std_channel",
+           "Plan", "TrajSet", "PtsbeError", "tag_id"]
+
+
+def tag_id(tag):
+    return zlib.crc32(str(tag).encode()) & 0xFFFFFFFF
+
+
+def _dptr(a):
+    return C.cast(a.ctypes.data, C.POINTER(C.c_double))
+
+
+def std_gate(name, params=()):
+    out = np.zeros(32, dtype=np.float64)
+    p = np.asarray(params, dtype=np.float64) if len(params) else np.zeros(1)
+    nq = C.c_uint32()
+    check(lib().ptsbe_std_gate(name.encode(), _dptr(p), _dptr(out), C.byref(nq)))
+    d = 1 << nq.value
+    return out[:2 * d * d].copy(), nq.value
+
+
+def std_channel(ch):
+    name = ch["name"]
+    if name in ("depolarizing", "xflip"):
+        p = [ch["p"]]
+    elif name == "pauli":
+        p = list(ch["probs"])
+    elif name == "u3_mixture":
+        p = [ch["p"]] + list(ch["params"])
+    elif name == "amplitude_damping":
+        p = [ch["gamma"]]
+    else:
+        raise ValueError(name)
+    nq = int(ch.get("nq", 1))
+    out = np.zeros(16 * 2 * 16, dtype=np.float64)
+    pa = np.asarray(p, dtype=np.float64)
+    nk = C.c_uint32()
+    check(lib().ptsbe_std_channel(name.encode(), nq, _dptr(pa), _dptr(out), C.byref(nk)))
+    d = 1 << nq
+    return out[:2 * d * d * nk.value].copy(), nq, nk.value
+
+
+class Plan:
+    """Owning wrapper of a ptsbe_plan_t."""
+
+    def __init__(self, handle, keep):
+        self.handle = handle
+        self._keep = keep
+        info = L.PlanInfo()
+        check(lib().ptsbe_plan_get_info(handle, C.byref(info)))
+        self.info = {f: getattr(info, f) for f, _ in L.PlanInfo._fields_}
+
+    def site_probs(self):
+        ns = self.info["n_sites"]
+        off = np.zeros(ns + 1, dtype=np.uint32)
+        p = np.zeros(max(1, self.info["total_kraus"]), dtype=np.float64)
+        q = np.zeros(max(1, 2 * ns), dtype=np.uint32)
+        check(lib().ptsbe_plan_get_sites(self.handle, off.ctypes.data, p.ctypes.data, q.ctypes.data))
+        return [p[off[s]:off[s + 1]].copy() for s in range(ns)], q[:2 * ns].reshape(-1, 2)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            lib().ptsbe_plan_destroy(h)
+            self.handle = None
+
+
+def ptsbe_plan(circuit, precision="c64", tile_qubits=0):
+    """Build the execution plan of a circuit dictionary (ops, channels, rules)."""
+    ops = circuit["ops"]
+    arr = (L.Op * max(1, len(ops)))()
+    keep = []
+    for i, op in enumerate(ops):
+        o = arr[i]
+        qs = tuple(op["qubits"])
+        o.nq = len(qs)
+        for j, q in enumerate(qs):
+            o.q[j] = int(q)
+        kind = op["kind"]
+        if kind == "gate":
+            m, nq = std_gate(op["name"], op.get("params", ()))
+            if nq != len(qs):
+                raise ValueError(f"op {i}: {op['name']} acts on {nq} qubits")
+            keep.append(m)
+            o.kind = L.OP_GATE
+            o.mat = _dptr(m)
+            o.tag = tag_id(op.get("tag", op["name"]))
+        elif kind == "param":
+            o.kind = L.OP_PARAM
+            o.index = int(op["index"])
+            o.gen = L.GEN[op["gen"]]
+            o.tag = tag_id(op.get("tag", "R" + op["gen"]))
+        elif kind == "noise":
+            o.kind = L.OP_NOISE
+            o.index = int(op["channel"])
+        elif kind == "measure_reset":
+            o.kind = L.OP_MEASURE_RESET
+        elif kind == "project0":
+            o.kind = L.OP_PROJECT0
+        else:
+            raise ValueError(kind)
+    chans = circuit.get("channels", [])
+    carr = (L.Channel * max(1, len(chans)))()
+    for i, ch in enumerate(chans):
+        k, nq, nk = std_channel(ch)
+        keep.append(k)
+        carr[i].nq = nq
+        carr[i].n_kraus = nk
+        carr[i].kraus = _dptr(k)
+    rules = circuit.get("rules", [])
+    rarr = (L.Attach * max(1, len(rules)))()
+    for i, r in enumerate(rules):
+        w = r["when"]
+        rarr[i].channel = int(r["channel"])
+        if w == "after_tag":
+            rarr[i].when = L.ATTACH_AFTER_TAG
+            rarr[i].tag = tag_id(r["tag"])
+        elif w == "before_measure":
+            rarr[i].when = L.ATTACH_BEFORE_MEASURE
+        elif w == "before_readout":
+            rarr[i].when = L.ATTACH_BEFORE_READOUT
+            mask = 0
+            for q in r["qubits"]:
+                mask |= 1 << int(q)
+            rarr[i].qmask = mask
+        else:
+            raise ValueError(w)
+    c = L.Circuit(circuit["n_qubits"], len(ops), arr)
+    nm = L.NoiseModel(len(chans), carr, len(rules), rarr)
+    po = L.PlanOpts({"c64": L.C64, "c128": L.C128}[precision], int(tile_qubits), 0, 0)
+    h = C.c_void_p()
+    check(lib().ptsbe_plan(C.byref(c), C.byref(nm), C.byref(po), C.byref(h)))
+    return Plan(h, None)
+
+
+class TrajSet:
+    """Owning wrapper of a ptsbe_trajset_t (PTS output: records, m_alpha, p_alpha)."""
+
+    def __init__(self, handle, plan):
+        self.handle = handle
+        self.plan = plan
+
+    def get(self):
+        n = C.c_uint32()
+        tot = C.c_uint64()
+        ne = C.c_uint32()
+        a0 = C.c_uint64()
+        check(lib().ptsbe_trajset_get(self.handle, C.byref(n), C.byref(tot), C.byref(ne), C.byref(a0),
+                                      None, None, None, None, None, None))
+        B = n.value
+        m = np.zeros(max(1, B), dtype=np.uint64)
+        p = np.zeros(max(1, B), dtype=np.float64)
+        cnt = np.zeros(max(1, B), dtype=np.uint64)
+        off = np.zeros(B + 1, dtype=np.uint32)
+        site = np.zeros(max(1, ne.value), dtype=np.uint32)
+        kr = np.zeros(max(1, ne.value), dtype=np.uint8)
+        check(lib().ptsbe_trajset_get(self.handle, None, None, None, None, m.ctypes.data, p.ctypes.data,
+                                      cnt.ctypes.data, off.ctypes.data, site.ctypes.data, kr.ctypes.data))
+        recs = [tuple((int(site[j]), int(kr[j])) for j in range(off[a], off[a + 1])) for a in range(B)]
+        return {"records": recs, "m": m[:B], "p": p[:B], "count": cnt[:B], "total_shots": tot.value,
+                "alpha0": a0.value, "rec_off": off, "rec_site": site[:ne.value], "rec_kraus": kr[:ne.value]}
+
+    @property
+    def n_traj(self):
+        n = C.c_uint32()
+        check(lib().ptsbe_trajset_get(self.handle, C.byref(n), None, None, None, None, None, None, None,
+                                      None, None))
+        return n.value
+
+    def slice(self, begin, end):
+        h = C.c_void_p()
+        check(lib().ptsbe_trajset_slice(self.handle, begin, end, C.byref(h)))
+        return TrajSet(h, self.plan)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            lib().ptsbe_trajset_destroy(h)
+            self.handle = None
+
+
+def ptsbe_sample_kraus(plan, mode="proportional", n_draws=0, k_max=0, total_shots=0, nshots=0, seed=0,
+                       cfg=0, alloc=None, stream=0, p_band=None):
+    """Pre-trajectory sampling (Sec. 3.1) with the library's samplers."""
+    if alloc is None:
+        alloc = {"proportional": "multiplicity", "alg2_literal": "uniform", "most_likely": "reweight",
+                 "per_shot": "multiplicity"}[mode]
+    o = L.PtsOpts(L.PTS_MODES[mode], L.ALLOCS[alloc], int(n_draws), int(k_max), int(total_shots),
+                  int(nshots), int(seed), int(cfg), int(stream),
+                  float(p_band[0]) if p_band else 0.0, float(p_band[1]) if p_band else 0.0)
+    h = C.c_void_p()
+    check(lib().ptsbe_sample_kraus(plan.handle, C.byref(o), C.byref(h)))
+    return TrajSet(h, plan)
+
+
+def ptsbe_trajset_from_records(plan, records, m, alpha0=0):
+    off = np.zeros(len(records) + 1, dtype=np.uint32)
+    site = []
+    kr = []
+    for a, rec in enumerate(records):
+        for s, k in rec:
+            site.append(s)
+            kr.append(k)
+        off[a + 1] = len(site)
+    site = np.asarray(site if site else [0], dtype=np.uint32)
+    kr = np.asarray(kr if kr else [0], dtype=np.uint8)
+    mm = np.asarray(m, dtype=np.uint64)
+    h = C.c_void_p()
+    check(lib().ptsbe_trajset_from_records(plan.handle, len(records), off.ctypes.data, site.ctypes.data,
+                                           kr.ctypes.data, mm.ctypes.data, int(alpha0), C.byref(h)))
+    return TrajSet(h, plan)
+
+
+def _run_opts(mode, seed, cfg, sort_chunk, max_batch, uniforms, params, state_out, expval, observable,
+              timing=None):
+    o = L.RunOpts()
+    if timing is not None:
+        o.timing = _dptr(timing)
+    o.mode = mode
+    o.seed = int(seed)
+    o.cfg = int(cfg)
+    o.sort_chunk = int(sort_chunk)
+    o.max_batch = int(max_batch)
+    o.d_uniforms = uniforms.data_ptr() if uniforms is not None else None
+    keep = []
+    if params is not None and len(params):
+        pa = np.ascontiguousarray(params, dtype=np.float64)
+        keep.append(pa)
+        o.params = _dptr(pa)
+    o.d_state_out = state_out.data_ptr() if state_out is not None else None
+    o.d_expval = expval.data_ptr() if expval is not None else None
+    if observable:
+        coef = np.asarray([c for c, _ in observable], dtype=np.float64)
+        zm = np.asarray([sum(1 << int(q) for q in qs) for _, qs in observable], dtype=np.uint64)
+        keep += [coef, zm]
+        o.obs_coef = _dptr(coef)
+        o.obs_zmask = C.cast(zm.ctypes.data, C.POINTER(C.c_uint64))
+        o.n_terms = len(observable)
+    return o, keep
+
+
+def ptsbe_workspace_size(plan, ts, mode="shots", sort_chunk=0, max_batch=0, params=None):
+    m = {"shots": L.RUN_SHOTS, "states": L.RUN_STATES, "expectation": L.RUN_EXPECTATION}[mode]
+    o, keep = _run_opts(m, 0, 0, sort_chunk, max_batch, None, params, None, None, None)
+    n = C.c_size_t()
+    check(lib().ptsbe_workspace_size(plan.handle, ts.handle, C.byref(o), C.byref(n)))
+    return n.value
+
+
+def _stream(torch, stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def ptsbe_run_batch(plan, ts, mode="shots", seed=0, cfg=0, sort_chunk=0, max_batch=0, uniforms=None,
+                    params=None, observable=None, workspace=None, out=None, stream=None, timing=None):
+    """Batched execution (Sec. 3).  Returns a dict of device tensors:
+    shots: bits (int32 or int64 basis indices), traj (int32 trajectory ids), mr_bits;
+    states: states (n_traj x 2^n complex); expectation: expval (n_traj float64).
+    ``timing``: optional float64 numpy array of 8 entries filled by the library's
+    HIP-event stage timer (the call then waits for the stream)."""
+    import torch
+    dev = torch.device("cuda")
+    n = plan.info["n_qubits"]
+    B = ts.n_traj
+    mcode = {"shots": L.RUN_SHOTS, "states": L.RUN_STATES, "expectation": L.RUN_EXPECTATION}[mode]
+    res = dict(out) if out else {}
+    state_out = expval = None
+    if mode == "states":
+        dt = torch.complex64 if plan.info["precision"] == L.C64 else torch.complex128
+        state_out = res.get("states")
+        if state_out is None:
+            state_out = torch.empty((B, 1 << n), dtype=dt, device=dev)
+        res["states"] = state_out
+    if mode == "expectation":
+        expval = res.get("expval")
+        if expval is None:
+            expval = torch.empty(B, dtype=torch.float64, device=dev)
+        res["expval"] = expval
+    o, keep = _run_opts(mcode, seed, cfg, sort_chunk, max_batch, uniforms, params, state_out, expval,
+                        observable, timing)
+    need = C.c_size_t()
+    check(lib().ptsbe_workspace_size(plan.handle, ts.handle, C.byref(o), C.byref(need)))
+    ws = workspace
+    if ws is None:
+        ws = torch.empty(need.value, dtype=torch.uint8, device=dev)
+    total = ts.get()["total_shots"] if mode == "shots" else 0
+    bits = traj = None
+    if mode == "shots":
+        bits = res.get("bits")
+        if bits is None:
+            bits = torch.empty(max(1, total), dtype=torch.int32 if n <= 32 else torch.int64, device=dev)
+        traj = res.get("traj")
+        if traj is None:
+            traj = torch.empty(max(1, total), dtype=torch.int32, device=dev)
+        res["bits"], res["traj"] = bits, traj
+    nm = plan.info["n_measure"]
+    mr = None
+    if nm:
+        mr = res.get("mr_bits")
+        if mr is None:
+            mr = torch.empty((B, nm), dtype=torch.uint8, device=dev)
+        res["mr_bits"] = mr
+    cap = bits.numel() if bits is not None else 0
+    check(lib().ptsbe_run_batch(plan.handle, ts.handle, C.byref(o), C.c_void_p(ws.data_ptr()),
+                                ws.numel(), C.c_void_p(bits.data_ptr()) if bits is not None else None,
+                                C.c_void_p(traj.data_ptr()) if traj is not None else None, cap,
+                                C.c_void_p(mr.data_ptr()) if mr is not None else None,
+                                _stream(torch, stream)))
+    res["workspace"] = ws
+    res["_keep"] = keep
+    return res
+
+
+def ptsbe_run_status(plan, workspace, stream=None):
+    import torch
+    check(lib().ptsbe_run_status(plan.handle, C.c_void_p(workspace.data_ptr()), _stream(torch, stream)))
+
+
+def ptsbe_adjoint_grad(plan, ts, params, observable, workspace=None, stream=None):
+    """E and dE/dparams (FP64 device tensors) of the probability-weighted ensemble."""
+    import torch
+    dev = torch.device("cuda")
+    pa = np.ascontiguousarray(params, dtype=np.float64)
+    coef = np.asarray([c for c, _ in observable], dtype=np.float64)
+    zm = np.asarray([sum(1 << int(q) for q in qs) for _, qs in observable], dtype=np.uint64)
+    o, keep = _run_opts(L.RUN_EXPECTATION, 0, 0, 0, 0, None, pa, None, None, observable)
+    need = C.c_size_t()
+    check(lib().ptsbe_workspace_size(plan.handle, ts.handle, C.byref(o), C.byref(need)))
+    ws = workspace
+    if ws is None:
+        ws = torch.empty(2 * need.value + (1 << 20), dtype=torch.uint8, device=dev)
+    E = torch.zeros(1, dtype=torch.float64, device=dev)
+    G = torch.zeros(max(1, pa.size), dtype=torch.float64, device=dev)
+    check(lib().ptsbe_adjoint_grad(plan.handle, ts.handle, _dptr(pa), _dptr(coef),
+                                   C.cast(zm.ctypes.data, C.POINTER(C.c_uint64)), len(observable),
+                                   C.c_void_p(ws.data_ptr()), ws.numel(), C.c_void_p(E.data_ptr()),
+                                   C.c_void_p(G.data_ptr()), _stream(torch, stream)))
+    return E, G[:pa.size]

@@ -1,0 +1,149 @@
+// Host-side objects of the PTSBE library: the execution plan (expanded noisy
+// circuit + fused tile passes) and trajectory sets (PTS output).
+#pragma once
+
+#include <complex>
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/ptsbe.h"
+#include "tables.hpp"
+
+namespace ptsbe {
+
+using cd = std::complex<double>;
+using Mat = std::vector<cd>;  // row-major d x d
+
+// Thread-local error reporting.
+ptsbe_status fail(ptsbe_status st, const std::string& msg);
+
+struct Channel {
+  int nq = 1;
+  int K = 0;
+  std::vector<double> p;       // p_k = tr(K_k^dagger K_k) / d
+  std::vector<Mat> U;          // U_k = K_k / sqrt(p_k)
+  std::vector<bool> diag;      // U_k diagonal
+  bool all_diag = false;
+  // 2-qubit channels whose every U_k is a product A_k (x) B_k (B on matrix bit 0):
+  bool product = false;
+  std::vector<Mat> f0, f1;     // factors on matrix bit 0 / bit 1 (2x2 each)
+};
+
+enum StepKind { ST_GATE, ST_PARAM, ST_SITE, ST_MR, ST_P0 };
+
+struct Step {
+  StepKind kind;
+  int nq = 1;
+  int q[4] = {0, 0, 0, 0};
+  Mat mat;                     // GATE
+  bool diag = false;           // diagonal in the computational basis (for every variant)
+  int param = -1, gen = 0;     // PARAM
+  int site = -1;               // SITE
+  int mr = -1;                 // MR record index
+};
+
+struct Site {
+  int channel;
+  int nq;
+  int q[2];
+  int step;
+};
+
+// One factor of a fused slot: a step, or one half of a product 2-qubit site.
+struct Part {
+  int step;
+  int half;                    // -1: whole step; 0 / 1: factor on the site's first / second qubit
+};
+
+struct Slot {
+  uint8_t type;                // DOP_M1 / DOP_M2 / DOP_D1 / DOP_D2
+  int q[2];                    // global qubits (matrix bit 0, bit 1)
+  std::vector<Part> parts;     // applied in order
+  std::vector<int> sites;      // sites whose choice changes this slot
+  bool uses_params = false;
+};
+
+struct Pass {
+  int k = 0;
+  std::vector<int> tq;         // tile qubits ascending
+  std::vector<int> oq;         // other qubits ascending
+  std::vector<DOp> ops;
+  std::vector<Slot> slots;
+  uint32_t flags = 0;
+};
+
+// Execution step: a tile pass, or a measurement of a group of measure-resets.
+struct ExecStep {
+  int pass = -1;               // >= 0: tile pass index
+  std::vector<int> mr_qubits;  // measurement: qubits
+  std::vector<int> mr_index;   // measurement: record indices
+};
+
+struct Plan {
+  int n = 0;
+  int precision = PTSBE_C64;
+  int tile_bits = 12;
+  int n_params = 0;
+  int n_measure = 0;
+  std::vector<Channel> channels;
+  std::vector<Step> steps;
+  std::vector<Site> sites;
+  std::vector<uint32_t> site_off; // offsets into site_p
+  std::vector<double> site_p;     // p_{s,k}
+  std::vector<Pass> passes;
+  std::vector<ExecStep> exec;
+  // site -> (pass, slot) list
+  std::vector<std::vector<std::pair<int, int>>> site_slots;
+};
+
+struct TrajSet {
+  std::shared_ptr<const Plan> plan;
+  uint64_t alpha0 = 0;
+  std::vector<uint64_t> m;
+  std::vector<double> p;
+  std::vector<uint64_t> count;
+  std::vector<uint32_t> rec_off;   // n_traj + 1
+  std::vector<uint32_t> rec_site;
+  std::vector<uint8_t> rec_kraus;
+  uint64_t total_shots = 0;
+  uint64_t total_count = 0;
+  // Cached device tables (host copy), keyed by the parameter values they used.
+  std::mutex mu;
+  std::vector<double> cached_params;
+  std::vector<uint8_t> table_blob;
+  TableLayout layout{};
+  bool table_valid = false;
+  size_t pool_elems = 0;
+  std::vector<uint64_t> chunk_off;
+  uint32_t cached_chunk = 0;
+};
+
+// Matrix helpers
+Mat mat_identity(int d);
+Mat mat_mul(const Mat& a, const Mat& b, int d);        // a * b
+bool mat_is_diag(const Mat& a, int d, double tol = 0.0);
+Mat rot_matrix(int gen, double theta);
+
+// Slot matrix for a trajectory: choice(site) gives its Kraus index.
+Mat slot_matrix(const Plan& plan, const Slot& s, const double* params,
+                const std::map<int, int>& choice);
+
+// Planner
+ptsbe_status build_plan(const ptsbe_circuit* c, const ptsbe_noise_model* nm,
+                        const ptsbe_plan_opts* o, std::shared_ptr<Plan>* out);
+
+// Build the device tables of a trajectory set (cached in ts).
+ptsbe_status build_tables(TrajSet& ts, const double* params, uint32_t chunk);
+
+}  // namespace ptsbe
+
+struct ptsbe_plan_s {
+  std::shared_ptr<ptsbe::Plan> plan;
+};
+struct ptsbe_trajset_s {
+  std::shared_ptr<ptsbe::TrajSet> ts;
+};

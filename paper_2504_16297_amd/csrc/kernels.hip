@@ -1,0 +1,502 @@
+// gfx950 kernels of the PTSBE hot path.
+//
+//  k_pass      one fused tile pass: a 2^k-amplitude tile (k tile qubits, the
+//              lowest ones always included so that global accesses are runs of
+//              >= 128 contiguous bytes) is staged in LDS, every fused 1- and
+//              2-qubit operation of the pass is applied to it in order (with
+//              the trajectory's own matrices for slots touched by its noise
+//              record), and the tile is written back.  Grid: (tile, state).
+//  k_marginal  FP64 partial sums of |psi|^2 restricted to x_q = 1 for a group
+//              of measured qubits (general Kraus branch of Algorithm 1).
+//  k_mr_decide per trajectory: outcome b = [p1 > 1/2], determinism check,
+//              renormalisation factor.
+//  k_blocksum / k_scan_partials / k_cdf
+//              FP64 norm and inclusive prefix sum of |psi|^2 per state:
+//              per-thread sequential sums, wavefront shuffles, an LDS tree,
+//              then block offsets (reduce-then-scan, no inter-block waiting).
+//  k_sample    per (trajectory, chunk of shots): Philox4x64-10 uniforms, an
+//              LDS bitonic sort, and an upper-bound search of u * total in the
+//              CDF; writes the basis index and the trajectory id of each shot.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+#include "philox.hpp"
+
+namespace ptsbe {
+
+template <typename V>
+struct Real;
+template <>
+struct Real<float2> {
+  using T = float;
+};
+template <>
+struct Real<double2> {
+  using T = double;
+};
+
+template <typename V>
+__device__ __forceinline__ V cmul(V a, V b) {
+  V r;
+  r.x = a.x * b.x - a.y * b.y;
+  r.y = a.x * b.y + a.y * b.x;
+  return r;
+}
+
+template <typename V>
+__device__ __forceinline__ V cfma2(V m0, V x0, V m1, V x1) {
+  V r;
+  r.x = m0.x * x0.x - m0.y * x0.y + m1.x * x1.x - m1.y * x1.y;
+  r.y = m0.x * x0.y + m0.y * x0.x + m1.x * x1.y + m1.y * x1.x;
+  return r;
+}
+
+__device__ __forceinline__ uint64_t tile_offset(uint32_t L, const uint8_t* tq, uint32_t k) {
+  uint64_t off = 0;
+#pragma unroll
+  for (int j = 0; j < kMaxTileBits; ++j)
+    if (j < (int)k) off |= (uint64_t)((L >> j) & 1u) << tq[j];
+  return off;
+}
+
+template <typename V>
+__global__ __launch_bounds__(256) void k_pass(PassArgs<V> a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const DPass& P = a.passes[a.pass];
+  const uint32_t k = P.k;
+  const uint32_t nt = 1u << k;
+  V* tile = reinterpret_cast<V*>(smem);
+  uint32_t* slot_off = reinterpret_cast<uint32_t*>(smem + sizeof(V) * nt);
+  __shared__ uint8_t tq[16];
+  const uint32_t tid = threadIdx.x;
+  const uint32_t t = a.t0 + blockIdx.y;               // trajectory (set-local index)
+  const uint64_t tile_id = blockIdx.x;
+  if (tid < 16) tq[tid] = P.tq[tid];
+  uint64_t base = 0;
+  for (uint32_t i = 0; i < a.n - k; ++i)
+    if ((tile_id >> i) & 1) base |= 1ull << P.oq[i];
+  V* st = a.states + (uint64_t)blockIdx.y * a.N;
+  for (uint32_t s = tid; s < P.n_slots; s += blockDim.x) slot_off[s] = a.slot_default[P.slot_begin + s];
+  __syncthreads();
+  {
+    const uint32_t ob = a.ov_off[(uint64_t)t * a.n_passes + a.pass];
+    const uint32_t oe = a.ov_off[(uint64_t)t * a.n_passes + a.pass + 1];
+    for (uint32_t i = ob + tid; i < oe; i += blockDim.x) slot_off[a.ov[i].slot] = a.ov[i].off;
+  }
+  const bool init = (P.flags & PASS_INIT_ZERO) != 0;
+  for (uint32_t L = tid; L < nt; L += blockDim.x) {
+    V v;
+    if (init) {
+      v.x = (base == 0 && L == 0) ? 1 : 0;
+      v.y = 0;
+    } else {
+      v = st[base + tile_offset(L, tq, k)];
+    }
+    tile[L] = v;
+  }
+  __syncthreads();
+  const DOp* ops = a.ops + P.op_begin;
+  for (uint32_t o = 0; o < P.n_ops; ++o) {
+    const DOp op = ops[o];
+    if (op.type == DOP_M1) {
+      const V* m = a.pool + slot_off[op.slot];
+      const V m00 = m[0], m01 = m[1], m10 = m[2], m11 = m[3];
+      const uint32_t bit = 1u << op.a, lo = bit - 1;
+      for (uint32_t pr = tid; pr < nt / 2; pr += blockDim.x) {
+        const uint32_t i0 = ((pr & ~lo) << 1) | (pr & lo);
+        const uint32_t i1 = i0 | bit;
+        const V x0 = tile[i0], x1 = tile[i1];
+        tile[i0] = cfma2(m00, x0, m01, x1);
+        tile[i1] = cfma2(m10, x0, m11, x1);
+      }
+    } else if (op.type == DOP_M2) {
+      const V* m = a.pool + slot_off[op.slot];
+      const uint32_t A = 1u << op.a, B = 1u << op.b;
+      const uint32_t l1 = min(A, B) - 1, l2 = max(A, B) - 1;
+      for (uint32_t qd = tid; qd < nt / 4; qd += blockDim.x) {
+        uint32_t i = ((qd & ~l1) << 1) | (qd & l1);
+        i = ((i & ~l2) << 1) | (i & l2);
+        const uint32_t idx[4] = {i, i | A, i | B, i | A | B};
+        V x[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) x[r] = tile[idx[r]];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          V acc = cfma2(m[r * 4 + 0], x[0], m[r * 4 + 1], x[1]);
+          V acc2 = cfma2(m[r * 4 + 2], x[2], m[r * 4 + 3], x[3]);
+          acc.x += acc2.x;
+          acc.y += acc2.y;
+          tile[idx[r]] = acc;
+        }
+      }
+    } else if (op.type == DOP_D1 || op.type == DOP_D2) {
+      const V* m = a.pool + slot_off[op.slot];
+      const bool two = op.type == DOP_D2;
+      const uint32_t dd = two ? 5 : 3;  // stride of the diagonal in a 4x4 / 2x2 row-major matrix
+      const uint32_t fa = op.a == 255 ? (uint32_t)((base >> op.ga) & 1) : 0;
+      const uint32_t fb = (two && op.b == 255) ? (uint32_t)((base >> op.gb) & 1) : 0;
+      for (uint32_t L = tid; L < nt; L += blockDim.x) {
+        uint32_t ba = op.a == 255 ? fa : (L >> op.a) & 1u;
+        uint32_t bb = two ? (op.b == 255 ? fb : (L >> op.b) & 1u) : 0;
+        const V ph = m[(ba + 2 * bb) * dd];
+        tile[L] = cmul(ph, tile[L]);
+      }
+    } else if (op.type == DOP_MR) {
+      const uint64_t ri = (uint64_t)t * a.n_measure + op.slot;
+      const uint32_t b = a.mr_bits[ri];
+      const typename Real<V>::T sc = (typename Real<V>::T)a.mr_norm[ri];
+      const uint32_t bit = 1u << op.a, lo = bit - 1;
+      for (uint32_t pr = tid; pr < nt / 2; pr += blockDim.x) {
+        const uint32_t i0 = ((pr & ~lo) << 1) | (pr & lo);
+        const uint32_t i1 = i0 | bit;
+        V x = b ? tile[i1] : tile[i0];
+        x.x *= sc;
+        x.y *= sc;
+        V z;
+        z.x = 0;
+        z.y = 0;
+        tile[i0] = x;
+        tile[i1] = z;
+      }
+    }
+    __syncthreads();
+  }
+  for (uint32_t L = tid; L < nt; L += blockDim.x) st[base + tile_offset(L, tq, k)] = tile[L];
+}
+
+// ------------------------------------------------------------ FP64 reductions
+
+__device__ __forceinline__ double wave_incl_scan(double v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    double o = __shfl_up(v, d, 64);
+    if (lane >= d) v += o;
+  }
+  return v;
+}
+
+// Exclusive prefix of `v` over the block (256 threads, fixed order) and the
+// block total; identical arithmetic wherever it is called.
+__device__ __forceinline__ void block_excl_scan(double v, double* excl, double* total) {
+  __shared__ double wsum[4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double inc = wave_incl_scan(v);
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  double woff = 0.0;
+  for (int i = 0; i < w; ++i) woff += wsum[i];
+  double tot = 0.0;
+  for (int i = 0; i < 4; ++i) tot += wsum[i];
+  *excl = woff + (inc - v);
+  *total = tot;
+  __syncthreads();
+}
+
+template <typename V>
+__device__ __forceinline__ double norm2(V v) {
+  return (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+}
+
+// partial[t * nblk + b] = sum over block b of |psi|^2 (FP64), same order as k_cdf.
+template <typename V>
+__global__ __launch_bounds__(256) void k_blocksum(ScanArgs<V> a) {
+  const uint32_t b = blockIdx.x;
+  const V* st = a.states + (uint64_t)blockIdx.y * a.N;
+  const uint64_t e0 = (uint64_t)b * a.per_block;
+  const uint32_t per = a.per_thread;
+  double s = 0.0;
+  if (threadIdx.x * per < a.per_block) {
+    const V* p = st + e0 + (uint64_t)threadIdx.x * per;
+    for (uint32_t i = 0; i < per; ++i) s += norm2(p[i]);
+  }
+  double ex, tot;
+  block_excl_scan(s, &ex, &tot);
+  if (threadIdx.x == 0) a.partial[(uint64_t)blockIdx.y * a.nblk + b] = tot;
+}
+
+// offs[t*nblk+b] = exclusive prefix of partial over blocks; total[t] = full sum.
+__global__ __launch_bounds__(256) void k_scan_partials(double* partial, double* offs, double* total, uint32_t nblk) {
+  const double* p = partial + (uint64_t)blockIdx.x * nblk;
+  double* o = offs + (uint64_t)blockIdx.x * nblk;
+  const uint32_t per = (nblk + 255) / 256;
+  const uint32_t b0 = threadIdx.x * per;
+  double s = 0.0;
+  for (uint32_t i = 0; i < per; ++i)
+    if (b0 + i < nblk) s += p[b0 + i];
+  double ex, tot;
+  block_excl_scan(s, &ex, &tot);
+  double run = ex;
+  for (uint32_t i = 0; i < per; ++i)
+    if (b0 + i < nblk) {
+      o[b0 + i] = run;
+      run += p[b0 + i];
+    }
+  if (threadIdx.x == 255) total[blockIdx.x] = run;
+}
+
+// Inclusive FP64 prefix sum of |psi|^2, written in place over each complex64
+// slot (or to `cdf` for complex128).
+template <typename V>
+__global__ __launch_bounds__(256) void k_cdf(ScanArgs<V> a) {
+  const uint32_t b = blockIdx.x;
+  V* st = a.states + (uint64_t)blockIdx.y * a.N;
+  double* out = a.cdf ? a.cdf + (uint64_t)blockIdx.y * a.N : reinterpret_cast<double*>(st);
+  const uint64_t e0 = (uint64_t)b * a.per_block;
+  const uint32_t per = a.per_thread;
+  const bool active = threadIdx.x * per < a.per_block;
+  double v[16];
+  double s = 0.0;
+  if (active) {
+    const V* p = st + e0 + (uint64_t)threadIdx.x * per;
+    for (uint32_t i = 0; i < per; ++i) {
+      s += norm2(p[i]);
+      v[i] = s;
+    }
+  }
+  double ex, tot;
+  block_excl_scan(s, &ex, &tot);
+  const double off = a.offs[(uint64_t)blockIdx.y * a.nblk + b];
+  if (active) {
+    double* q = out + e0 + (uint64_t)threadIdx.x * per;
+    for (uint32_t i = 0; i < per; ++i) q[i] = off + (ex + v[i]);
+  }
+}
+
+// ------------------------------------------------------------ measure-reset
+
+template <typename V>
+__global__ __launch_bounds__(256) void k_marginal(MarginalArgs<V> a) {
+  const V* st = a.states + (uint64_t)blockIdx.y * a.N;
+  const uint64_t e0 = (uint64_t)blockIdx.x * a.per_block;
+  double s[kMaxGroup + 1];
+  for (int j = 0; j <= kMaxGroup; ++j) s[j] = 0.0;
+  for (uint32_t i = threadIdx.x; i < a.per_block; i += blockDim.x) {
+    const uint64_t x = e0 + i;
+    const double w = norm2(st[x]);
+    s[0] += w;
+    for (uint32_t j = 0; j < a.nq; ++j)
+      if ((x >> a.q[j]) & 1) s[j + 1] += w;
+  }
+  for (uint32_t j = 0; j <= a.nq; ++j) {
+    double ex, tot;
+    block_excl_scan(s[j], &ex, &tot);
+    if (threadIdx.x == 0) a.partial[((uint64_t)blockIdx.y * a.nblk + blockIdx.x) * (kMaxGroup + 1) + j] = tot;
+  }
+}
+
+__global__ void k_mr_decide(MrDecideArgs a) {
+  const uint32_t tb = blockIdx.x;  // batch-local trajectory
+  const uint32_t j = threadIdx.x;
+  if (j >= a.nq) return;
+  double tot = 0.0, one = 0.0;
+  for (uint32_t b = 0; b < a.nblk; ++b) {
+    const double* p = a.partial + ((uint64_t)tb * a.nblk + b) * (kMaxGroup + 1);
+    tot += p[0];
+    one += p[j + 1];
+  }
+  const double p1 = one / tot;
+  const uint32_t bit = p1 > 0.5 ? 1u : 0u;
+  const double pb = bit ? p1 : 1.0 - p1;
+  if (fmin(p1, 1.0 - p1) > a.tol) atomicOr(a.status, 1u);
+  const uint64_t ri = (uint64_t)(a.t0 + tb) * a.n_measure + a.idx[j];
+  a.mr_bits[ri] = (uint8_t)bit;
+  a.mr_norm[ri] = 1.0 / sqrt(pb * tot);
+}
+
+// ------------------------------------------------------------------ sampler
+
+template <typename BitT>
+__global__ __launch_bounds__(256) void k_sample(SampleArgs<BitT> a) {
+  __shared__ double u[4096];
+  const uint64_t item = a.item0 + blockIdx.x;
+  // trajectory of this item: chunk_off[t] <= item < chunk_off[t+1], t in [b0, b1)
+  uint32_t lo = a.b0, hi = a.b1;
+  while (hi - lo > 1) {
+    uint32_t mid = (lo + hi) >> 1;
+    if (a.chunk_off[mid] <= item)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  const uint32_t t = lo;
+  const uint64_t c = item - a.chunk_off[t];
+  const uint64_t m = a.shot_off[t + 1] - a.shot_off[t];
+  const uint32_t C = a.chunk;
+  const uint64_t j0 = c * C;
+  const uint32_t cnt = (uint32_t)min((uint64_t)C, m - j0);
+  const uint64_t alpha = a.alpha0 + t;
+  const uint64_t k1 = stream_key1(2, a.cfg, alpha);
+  const uint64_t out0 = a.shot_off[t] + j0;
+  // uniforms: shot j uses word j of the trajectory's sampler stream
+  for (uint32_t i = threadIdx.x * 4; i < C; i += blockDim.x * 4) {
+    if (a.uniforms) {
+      for (int w = 0; w < 4; ++w) u[i + w] = (i + w < cnt) ? a.uniforms[out0 + i + w] : 2.0;
+    } else {
+      const uint64_t j = j0 + i;  // multiple of 4 because C and i are
+      U64x4 r = philox4x64_10(j / 4 + 1, 0, 0, 0, a.seed, k1);
+      for (int w = 0; w < 4; ++w) u[i + w] = (i + w < cnt) ? word_to_uniform(r.v[w]) : 2.0;
+    }
+  }
+  __syncthreads();
+  // bitonic sort of C values in LDS (padding 2.0 sorts last)
+  for (uint32_t size = 2; size <= C; size <<= 1) {
+    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+      for (uint32_t i = threadIdx.x; i < C / 2; i += blockDim.x) {
+        const uint32_t lo_i = 2 * i - (i & (stride - 1));
+        const uint32_t hi_i = lo_i + stride;
+        const bool up = ((lo_i & size) == 0);
+        const double x = u[lo_i], y = u[hi_i];
+        if ((x > y) == up) {
+          u[lo_i] = y;
+          u[hi_i] = x;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  const double* cdf = a.cdf_base + (uint64_t)(t - a.b0) * a.cdf_stride;
+  const double total = a.total[t - a.b0];
+  const uint64_t N = a.N;
+  for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
+    const double v = u[i] * total;
+    uint64_t l = 0, h = N;  // first index with cdf > v
+    while (l < h) {
+      const uint64_t mid = (l + h) >> 1;
+      if (cdf[mid] > v)
+        h = mid;
+      else
+        l = mid + 1;
+    }
+    if (l > N - 1) l = N - 1;
+    a.bits[out0 + i] = (BitT)l;
+    a.traj[out0 + i] = (uint32_t)alpha;
+  }
+}
+
+// ------------------------------------------------------------ states / <O>
+
+template <typename V>
+__global__ __launch_bounds__(256) void k_copy_normalised(const V* states, V* out, const double* total, uint64_t N) {
+  const double s = 1.0 / sqrt(total[blockIdx.y]);
+  const V* st = states + (uint64_t)blockIdx.y * N;
+  V* o = out + (uint64_t)blockIdx.y * N;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (uint64_t)gridDim.x * blockDim.x) {
+    V v = st[i];
+    v.x = (typename Real<V>::T)((double)v.x * s);
+    v.y = (typename Real<V>::T)((double)v.y * s);
+    o[i] = v;
+  }
+}
+
+template <typename V>
+__global__ __launch_bounds__(256) void k_expval(ExpArgs<V> a) {
+  const V* st = a.states + (uint64_t)blockIdx.y * a.N;
+  const uint64_t e0 = (uint64_t)blockIdx.x * a.per_block;
+  double s = 0.0;
+  for (uint32_t i = threadIdx.x; i < a.per_block; i += blockDim.x) {
+    const uint64_t x = e0 + i;
+    double o = 0.0;
+    for (uint32_t j = 0; j < a.n_terms; ++j)
+      o += (__popcll(x & a.zmask[j]) & 1) ? -a.coef[j] : a.coef[j];
+    s += norm2(st[x]) * o;
+  }
+  double ex, tot;
+  block_excl_scan(s, &ex, &tot);
+  if (threadIdx.x == 0) a.partial[(uint64_t)blockIdx.y * a.nblk + blockIdx.x] = tot;
+}
+
+__global__ void k_expval_finish(const double* partial, const double* total, double* out, uint32_t nblk, uint32_t t0) {
+  if (threadIdx.x != 0) return;
+  double s = 0.0;
+  for (uint32_t b = 0; b < nblk; ++b) s += partial[(uint64_t)blockIdx.x * nblk + b];
+  out[t0 + blockIdx.x] = s / total[blockIdx.x];
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// -------------------------------------------------------------- launchers
+
+template <typename V>
+hipError_t launch_pass(const PassArgs<V>& a, uint32_t k, uint32_t n_slots, uint32_t batch, hipStream_t s) {
+  dim3 grid(1u << (a.n - k), batch);
+  size_t lds = sizeof(V) * (size_t(1) << k) + 4 * (size_t)n_slots;
+  hipLaunchKernelGGL(k_pass<V>, grid, dim3(256), lds, s, a);
+  return hipGetLastError();
+}
+
+template <typename V>
+hipError_t launch_scan(const ScanArgs<V>& a, uint32_t batch, double* total, hipStream_t s) {
+  dim3 grid(a.nblk, batch);
+  hipLaunchKernelGGL(k_blocksum<V>, grid, dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_scan_partials, dim3(batch), dim3(256), 0, s, a.partial, a.offs, total, a.nblk);
+  hipLaunchKernelGGL(k_cdf<V>, grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename V>
+hipError_t launch_norm(const ScanArgs<V>& a, uint32_t batch, double* total, hipStream_t s) {
+  dim3 grid(a.nblk, batch);
+  hipLaunchKernelGGL(k_blocksum<V>, grid, dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_scan_partials, dim3(batch), dim3(256), 0, s, a.partial, a.offs, total, a.nblk);
+  return hipGetLastError();
+}
+
+template <typename V>
+hipError_t launch_marginal(const MarginalArgs<V>& a, const MrDecideArgs& d, uint32_t batch, hipStream_t s) {
+  hipLaunchKernelGGL(k_marginal<V>, dim3(a.nblk, batch), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_mr_decide, dim3(batch), dim3(64), 0, s, d);
+  return hipGetLastError();
+}
+
+template <typename BitT>
+hipError_t launch_sample(const SampleArgs<BitT>& a, uint64_t items, hipStream_t s) {
+  const uint64_t maxg = 0x7fffffffull;
+  for (uint64_t done = 0; done < items; done += maxg) {
+    SampleArgs<BitT> b = a;
+    b.item0 = a.item0 + done;
+    uint64_t g = items - done < maxg ? items - done : maxg;
+    hipLaunchKernelGGL(k_sample<BitT>, dim3((uint32_t)g), dim3(256), 0, s, b);
+  }
+  return hipGetLastError();
+}
+
+template <typename V>
+hipError_t launch_copy_normalised(const V* states, V* out, const double* total, uint64_t N, uint32_t batch,
+                                  hipStream_t s) {
+  uint32_t gx = (uint32_t)((N + 255) / 256 < 65536 ? (N + 255) / 256 : 65536);
+  hipLaunchKernelGGL(k_copy_normalised<V>, dim3(gx, batch), dim3(256), 0, s, states, out, total, N);
+  return hipGetLastError();
+}
+
+template <typename V>
+hipError_t launch_expval(const ExpArgs<V>& a, const double* total, double* out, uint32_t batch, uint32_t t0,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_expval<V>, dim3(a.nblk, batch), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_expval_finish, dim3(batch), dim3(64), 0, s, a.partial, total, out, a.nblk, t0);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {
+  uint32_t g = (uint32_t)((n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024);
+  if (g == 0) g = 1;
+  hipLaunchKernelGGL(k_fill_u32, dim3(g), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+#define PTSBE_INST(V)                                                                                   \
+  template hipError_t launch_pass<V>(const PassArgs<V>&, uint32_t, uint32_t, uint32_t, hipStream_t);      \
+  template hipError_t launch_scan<V>(const ScanArgs<V>&, uint32_t, double*, hipStream_t);                 \
+  template hipError_t launch_norm<V>(const ScanArgs<V>&, uint32_t, double*, hipStream_t);                 \
+  template hipError_t launch_marginal<V>(const MarginalArgs<V>&, const MrDecideArgs&, uint32_t, hipStream_t); \
+  template hipError_t launch_copy_normalised<V>(const V*, V*, const double*, uint64_t, uint32_t, hipStream_t); \
+  template hipError_t launch_expval<V>(const ExpArgs<V>&, const double*, double*, uint32_t, uint32_t, hipStream_t);
+PTSBE_INST(float2)
+PTSBE_INST(double2)
+template hipError_t launch_sample<uint32_t>(const SampleArgs<uint32_t>&, uint64_t, hipStream_t);
+template hipError_t launch_sample<uint64_t>(const SampleArgs<uint64_t>&, uint64_t, hipStream_t);
+
+}  // namespace ptsbe

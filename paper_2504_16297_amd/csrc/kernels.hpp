@@ -1,0 +1,118 @@
+// Kernel argument blocks and launchers of the gfx950 hot path.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tables.hpp"
+
+namespace ptsbe {
+
+constexpr int kMaxGroup = 16;   // measure-resets measured together
+constexpr uint32_t kScanBlock = 4096;
+
+template <typename V>
+struct PassArgs {
+  const DPass* passes;
+  const DOp* ops;
+  const uint32_t* slot_default;
+  const V* pool;
+  const uint32_t* ov_off;
+  const DOverride* ov;
+  const uint8_t* mr_bits;
+  const double* mr_norm;
+  V* states;        // batch of states, state b at states + b * N
+  uint64_t N;
+  uint32_t n;
+  uint32_t pass;
+  uint32_t n_passes;
+  uint32_t t0;      // set-local index of the batch's first trajectory
+  uint32_t n_measure;
+};
+
+template <typename V>
+struct ScanArgs {
+  V* states;
+  double* cdf;      // nullptr: write the CDF in place over complex64 slots
+  double* partial;  // batch x nblk
+  double* offs;     // batch x nblk
+  uint64_t N;
+  uint32_t nblk;
+  uint32_t per_block;
+  uint32_t per_thread;
+};
+
+template <typename V>
+struct MarginalArgs {
+  const V* states;
+  double* partial;  // batch x nblk x (kMaxGroup + 1)
+  uint64_t N;
+  uint32_t nblk;
+  uint32_t per_block;
+  uint32_t nq;
+  uint32_t q[kMaxGroup];
+};
+
+struct MrDecideArgs {
+  const double* partial;
+  uint8_t* mr_bits;
+  double* mr_norm;
+  uint32_t* status;
+  double tol;
+  uint32_t nblk;
+  uint32_t nq;
+  uint32_t t0;
+  uint32_t n_measure;
+  uint32_t idx[kMaxGroup];
+};
+
+template <typename BitT>
+struct SampleArgs {
+  const double* cdf_base;   // CDF of batch state 0
+  uint64_t cdf_stride;      // elements between consecutive states' CDFs
+  const double* total;      // batch x 1
+  const uint64_t* shot_off; // set-local prefix of m
+  const uint64_t* chunk_off;
+  const double* uniforms;   // optional
+  BitT* bits;
+  uint32_t* traj;
+  uint64_t N;
+  uint64_t seed;
+  uint64_t alpha0;
+  uint64_t item0;
+  uint32_t b0, b1;          // trajectories of this batch (set-local)
+  uint32_t chunk;
+  uint32_t cfg;
+};
+
+template <typename V>
+struct ExpArgs {
+  const V* states;
+  double* partial;
+  uint64_t N;
+  uint32_t nblk;
+  uint32_t per_block;
+  uint32_t n_terms;
+  double coef[64];
+  uint64_t zmask[64];
+};
+
+template <typename V>
+hipError_t launch_pass(const PassArgs<V>& a, uint32_t k, uint32_t n_slots, uint32_t batch, hipStream_t s);
+template <typename V>
+hipError_t launch_scan(const ScanArgs<V>& a, uint32_t batch, double* total, hipStream_t s);
+template <typename V>
+hipError_t launch_norm(const ScanArgs<V>& a, uint32_t batch, double* total, hipStream_t s);
+template <typename V>
+hipError_t launch_marginal(const MarginalArgs<V>& a, const MrDecideArgs& d, uint32_t batch, hipStream_t s);
+template <typename BitT>
+hipError_t launch_sample(const SampleArgs<BitT>& a, uint64_t items, hipStream_t s);
+template <typename V>
+hipError_t launch_copy_normalised(const V* states, V* out, const double* total, uint64_t N, uint32_t batch,
+                                  hipStream_t s);
+template <typename V>
+hipError_t launch_expval(const ExpArgs<V>& a, const double* total, double* out, uint32_t batch, uint32_t t0,
+                         hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
+
+}  // namespace ptsbe

@@ -1,0 +1,579 @@
+// Plan construction: validation of the noisy circuit, unitary-mixture analysis
+// of every channel (Sec. 2.2), expansion into noise sites (the NoisyCircuit of
+// Algorithm 2), and fusion of the operations into LDS tile passes.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <set>
+#include <sstream>
+
+#include "host.hpp"
+
+namespace ptsbe {
+
+static thread_local std::string g_last_error;
+
+ptsbe_status fail(ptsbe_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+const char* last_error_cstr() { return g_last_error.c_str(); }
+
+Mat mat_identity(int d) {
+  Mat m(d * d, cd(0, 0));
+  for (int i = 0; i < d; ++i) m[i * d + i] = 1.0;
+  return m;
+}
+
+Mat mat_mul(const Mat& a, const Mat& b, int d) {
+  Mat c(d * d, cd(0, 0));
+  for (int i = 0; i < d; ++i)
+    for (int k = 0; k < d; ++k) {
+      cd aik = a[i * d + k];
+      if (aik == cd(0, 0)) continue;
+      for (int j = 0; j < d; ++j) c[i * d + j] += aik * b[k * d + j];
+    }
+  return c;
+}
+
+bool mat_is_diag(const Mat& a, int d, double tol) {
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j)
+      if (i != j && std::abs(a[i * d + j]) > tol) return false;
+  return true;
+}
+
+Mat rot_matrix(int gen, double theta) {
+  double c = std::cos(theta / 2), s = std::sin(theta / 2);
+  Mat m(4);
+  if (gen == PTSBE_GEN_X) {
+    m = {cd(c, 0), cd(0, -s), cd(0, -s), cd(c, 0)};
+  } else if (gen == PTSBE_GEN_Y) {
+    m = {cd(c, 0), cd(-s, 0), cd(s, 0), cd(c, 0)};
+  } else {
+    m = {cd(c, -s), cd(0, 0), cd(0, 0), cd(c, s)};
+  }
+  return m;
+}
+
+static Mat read_mat(const double* p, int d) {
+  Mat m(d * d);
+  for (int i = 0; i < d * d; ++i) m[i] = cd(p[2 * i], p[2 * i + 1]);
+  return m;
+}
+
+// tr(K^dagger K)/d, element by element in row-major order.
+static double kraus_weight(const Mat& K, int d) {
+  double s = 0.0;
+  for (int i = 0; i < d * d; ++i) s += K[i].real() * K[i].real() + K[i].imag() * K[i].imag();
+  return s / d;
+}
+
+// U = A (x) B with A on matrix bit 1 and B on bit 0?  Fills a, b when so.
+static bool split_product(const Mat& U, Mat* a, Mat* b) {
+  // R[(r1 c1), (r0 c0)] = U[2 r1 + r0][2 c1 + c0] must be rank one.
+  cd R[4][4];
+  for (int r1 = 0; r1 < 2; ++r1)
+    for (int c1 = 0; c1 < 2; ++c1)
+      for (int r0 = 0; r0 < 2; ++r0)
+        for (int c0 = 0; c0 < 2; ++c0) R[r1 * 2 + c1][r0 * 2 + c0] = U[(2 * r1 + r0) * 4 + 2 * c1 + c0];
+  int bi = 0, bj = 0;
+  double best = -1;
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j)
+      if (std::abs(R[i][j]) > best) {
+        best = std::abs(R[i][j]);
+        bi = i;
+        bj = j;
+      }
+  if (best <= 0) return false;
+  Mat A(4), B(4);
+  for (int i = 0; i < 4; ++i) A[i] = R[i][bj];
+  for (int j = 0; j < 4; ++j) B[j] = R[bi][j] / R[bi][bj];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j)
+      if (std::abs(R[i][j] - A[i] * B[j]) > 1e-12) return false;
+  // A[r1*2+c1] is the 2x2 on bit 1; B[r0*2+c0] on bit 0.
+  *a = A;
+  *b = B;
+  return true;
+}
+
+static ptsbe_status analyse_channel(const ptsbe_channel& ch, int idx, Channel* out) {
+  if (ch.nq < 1 || ch.nq > 2) return fail(PTSBE_E_ARG, "channel " + std::to_string(idx) + ": nq must be 1 or 2");
+  if (ch.n_kraus < 1 || ch.n_kraus > 16 || !ch.kraus)
+    return fail(PTSBE_E_ARG, "channel " + std::to_string(idx) + ": 1..16 Kraus operators required");
+  int d = 1 << ch.nq;
+  Channel c;
+  c.nq = ch.nq;
+  c.K = ch.n_kraus;
+  std::vector<Mat> K;
+  for (uint32_t k = 0; k < ch.n_kraus; ++k) K.push_back(read_mat(ch.kraus + 2 * k * d * d, d));
+  // CPTP: sum_k K^dagger K = I (Sec. 2.2)
+  Mat acc(d * d, cd(0, 0));
+  for (auto& m : K)
+    for (int i = 0; i < d; ++i)
+      for (int j = 0; j < d; ++j)
+        for (int l = 0; l < d; ++l) acc[i * d + j] += std::conj(m[l * d + i]) * m[l * d + j];
+  double err = 0;
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j) err = std::max(err, std::abs(acc[i * d + j] - (i == j ? 1.0 : 0.0)));
+  if (err > 1e-12) {
+    std::ostringstream os;
+    os << "channel " << idx << " is not CPTP: max |sum K^dag K - I| = " << err;
+    return fail(PTSBE_E_NOT_CPTP, os.str());
+  }
+  // unitary mixture: K^dagger K = p I (Sec. 2.2 feature 2)
+  c.all_diag = true;
+  for (int k = 0; k < c.K; ++k) {
+    double p = kraus_weight(K[k], d);
+    for (int i = 0; i < d; ++i)
+      for (int j = 0; j < d; ++j) {
+        cd v(0, 0);
+        for (int l = 0; l < d; ++l) v += std::conj(K[k][l * d + i]) * K[k][l * d + j];
+        if (std::abs(v - (i == j ? p : 0.0)) > 1e-12)
+          return fail(PTSBE_E_UNSUPPORTED, "channel " + std::to_string(idx) +
+                                               " is not a unitary mixture; state-dependent channels are not "
+                                               "pre-samplable");
+      }
+    Mat U = K[k];
+    if (p > 0) {
+      double s = 1.0 / std::sqrt(p);
+      for (auto& x : U) x *= s;
+    } else {
+      U = mat_identity(d);
+    }
+    c.p.push_back(p);
+    bool dg = mat_is_diag(U, d);
+    c.diag.push_back(dg);
+    c.all_diag = c.all_diag && dg;
+    c.U.push_back(U);
+  }
+  if (c.nq == 2) {
+    c.product = true;
+    for (int k = 0; k < c.K; ++k) {
+      Mat a, b;
+      if (!split_product(c.U[k], &a, &b)) {
+        c.product = false;
+        break;
+      }
+      c.f1.push_back(a);
+      c.f0.push_back(b);
+    }
+    if (!c.product) {
+      c.f0.clear();
+      c.f1.clear();
+    }
+  }
+  *out = std::move(c);
+  return PTSBE_OK;
+}
+
+// ------------------------------------------------------------------ fusion
+
+static Mat part_matrix(const Plan& plan, const Part& pt, const double* params, const std::map<int, int>& choice) {
+  const Step& st = plan.steps[pt.step];
+  switch (st.kind) {
+    case ST_GATE:
+    case ST_P0:
+      return st.mat;
+    case ST_PARAM:
+      return rot_matrix(st.gen, params ? params[st.param] : 0.0);
+    case ST_SITE: {
+      const Site& s = plan.sites[st.site];
+      const Channel& ch = plan.channels[s.channel];
+      auto it = choice.find(st.site);
+      int k = it == choice.end() ? 0 : it->second;
+      if (pt.half < 0) return ch.U[k];
+      return pt.half == 0 ? ch.f0[k] : ch.f1[k];
+    }
+    default:
+      return mat_identity(2);
+  }
+}
+
+Mat slot_matrix(const Plan& plan, const Slot& s, const double* params, const std::map<int, int>& choice) {
+  int d = (s.type == DOP_M2 || s.type == DOP_D2) ? 4 : 2;
+  Mat M = mat_identity(d);
+  for (const Part& pt : s.parts) M = mat_mul(part_matrix(plan, pt, params, choice), M, d);
+  return M;
+}
+
+namespace {
+
+struct Fuser {
+  Plan& plan;
+  Pass& pass;
+  std::vector<int> run;  // qubit -> open slot index or -1
+  std::vector<int> local;
+
+  Fuser(Plan& pl, Pass& ps) : plan(pl), pass(ps), run(pl.n, -1), local(pl.n, -1) {
+    for (int j = 0; j < ps.k; ++j) local[ps.tq[j]] = j;
+  }
+
+  int new_slot(uint8_t type, int q0, int q1) {
+    Slot s;
+    s.type = type;
+    s.q[0] = q0;
+    s.q[1] = q1;
+    pass.slots.push_back(s);
+    return (int)pass.slots.size() - 1;
+  }
+
+  void add_part(int slot, const Part& pt) {
+    Slot& s = pass.slots[slot];
+    s.parts.push_back(pt);
+    const Step& st = plan.steps[pt.step];
+    if (st.kind == ST_SITE) {
+      if (std::find(s.sites.begin(), s.sites.end(), st.site) == s.sites.end()) s.sites.push_back(st.site);
+    }
+    if (st.kind == ST_PARAM) s.uses_params = true;
+  }
+
+  void emit(int slot) {
+    Slot& s = pass.slots[slot];
+    DOp op{};
+    op.type = s.type;
+    op.slot = (uint16_t)slot;
+    if (s.type == DOP_M1) {
+      op.a = (uint8_t)local[s.q[0]];
+    } else if (s.type == DOP_M2) {
+      op.a = (uint8_t)local[s.q[0]];
+      op.b = (uint8_t)local[s.q[1]];
+    } else if (s.type == DOP_D1) {
+      op.ga = (uint8_t)s.q[0];
+      op.a = local[s.q[0]] >= 0 ? (uint8_t)local[s.q[0]] : (uint8_t)255;
+    } else {
+      op.ga = (uint8_t)s.q[0];
+      op.gb = (uint8_t)s.q[1];
+      op.a = local[s.q[0]] >= 0 ? (uint8_t)local[s.q[0]] : (uint8_t)255;
+      op.b = local[s.q[1]] >= 0 ? (uint8_t)local[s.q[1]] : (uint8_t)255;
+    }
+    pass.ops.push_back(op);
+  }
+
+  void flush(int q) {
+    if (run[q] >= 0) {
+      emit(run[q]);
+      run[q] = -1;
+    }
+  }
+
+  void one_qubit(int q, const Part& pt) {
+    if (run[q] < 0) run[q] = new_slot(local[q] >= 0 ? DOP_M1 : DOP_D1, q, -1);
+    add_part(run[q], pt);
+  }
+
+  void take(int si) {
+    const Step& st = plan.steps[si];
+    if (st.kind == ST_MR) {
+      flush(st.q[0]);
+      DOp op{};
+      op.type = DOP_MR;
+      op.a = (uint8_t)local[st.q[0]];
+      op.slot = (uint16_t)st.mr;
+      pass.ops.push_back(op);
+      return;
+    }
+    if (st.nq == 1) {
+      one_qubit(st.q[0], Part{si, -1});
+      return;
+    }
+    if (st.kind == ST_SITE) {
+      const Channel& ch = plan.channels[plan.sites[st.site].channel];
+      if (ch.product) {
+        one_qubit(st.q[0], Part{si, 0});
+        one_qubit(st.q[1], Part{si, 1});
+        return;
+      }
+    }
+    // 2-qubit operation
+    flush(st.q[0]);
+    flush(st.q[1]);
+    int s = new_slot(st.diag ? DOP_D2 : DOP_M2, st.q[0], st.q[1]);
+    add_part(s, Part{si, -1});
+    emit(s);
+  }
+
+  void finish() {
+    for (int q = 0; q < plan.n; ++q) flush(q);
+  }
+};
+
+}  // namespace
+
+static ptsbe_status schedule(Plan& plan) {
+  const int n = plan.n;
+  const int k = std::min(n, plan.tile_bits);
+  const int contiguous = std::min(k, plan.precision == PTSBE_C64 ? 4 : 3);
+  std::vector<int> rem(plan.steps.size());
+  for (size_t i = 0; i < rem.size(); ++i) rem[i] = (int)i;
+  std::vector<char> measured(plan.steps.size(), 0);
+  bool first = true;
+  int guard = 0;
+  while (!rem.empty()) {
+    if (++guard > 1000000) return fail(PTSBE_E_ARG, "scheduler made no progress");
+    // greedy tile choice + take, in circuit order
+    std::vector<char> inQ(n, 0), blocked(n, 0);
+    int qcount = 0;
+    for (int q = 0; q < contiguous; ++q) {
+      inQ[q] = 1;
+      ++qcount;
+    }
+    std::vector<int> taken, keep;
+    for (int si : rem) {
+      const Step& st = plan.steps[si];
+      bool blk = false;
+      for (int j = 0; j < st.nq; ++j) blk = blk || blocked[st.q[j]];
+      bool can = false;
+      if (!blk) {
+        if (st.kind == ST_MR && !measured[si]) {
+          can = false;
+        } else if (st.diag && st.kind != ST_MR) {
+          can = true;
+        } else {
+          int nnew = 0;
+          for (int j = 0; j < st.nq; ++j) nnew += inQ[st.q[j]] ? 0 : 1;
+          if (qcount + nnew <= k) {
+            for (int j = 0; j < st.nq; ++j)
+              if (!inQ[st.q[j]]) {
+                inQ[st.q[j]] = 1;
+                ++qcount;
+              }
+            can = true;
+          }
+        }
+      }
+      if (can) {
+        taken.push_back(si);
+      } else {
+        for (int j = 0; j < st.nq; ++j) blocked[st.q[j]] = 1;
+        keep.push_back(si);
+      }
+    }
+    if (taken.empty()) {
+      // every frontier operation is an unmeasured measure-reset: measure them together
+      ExecStep ex;
+      std::vector<char> blk(n, 0);
+      for (int si : rem) {
+        const Step& st = plan.steps[si];
+        bool b = false;
+        for (int j = 0; j < st.nq; ++j) b = b || blk[st.q[j]];
+        if (!b && st.kind == ST_MR && !measured[si]) {
+          ex.mr_qubits.push_back(st.q[0]);
+          ex.mr_index.push_back(st.mr);
+          measured[si] = 1;
+        }
+        for (int j = 0; j < st.nq; ++j) blk[st.q[j]] = 1;
+      }
+      if (ex.mr_qubits.empty()) return fail(PTSBE_E_UNSUPPORTED, "an operation does not fit in a tile");
+      if (first) {
+        // the state must exist before it is measured
+        Pass p;
+        p.k = k;
+        for (int q = 0; q < n; ++q) (q < k ? p.tq : p.oq).push_back(q);
+        p.flags = PASS_INIT_ZERO;
+        plan.passes.push_back(p);
+        ExecStep e0;
+        e0.pass = (int)plan.passes.size() - 1;
+        plan.exec.push_back(e0);
+        first = false;
+      }
+      plan.exec.push_back(ex);
+      continue;
+    }
+    for (int q = 0; q < n && qcount < k; ++q)
+      if (!inQ[q]) {
+        inQ[q] = 1;
+        ++qcount;
+      }
+    Pass p;
+    p.k = k;
+    for (int q = 0; q < n; ++q) (inQ[q] ? p.tq : p.oq).push_back(q);
+    if (first) p.flags = PASS_INIT_ZERO;
+    first = false;
+    plan.passes.push_back(p);
+    Pass& ps = plan.passes.back();
+    Fuser fz(plan, ps);
+    for (int si : taken) fz.take(si);
+    fz.finish();
+    ExecStep e;
+    e.pass = (int)plan.passes.size() - 1;
+    plan.exec.push_back(e);
+    rem.swap(keep);
+  }
+  if (first) {
+    Pass p;
+    p.k = k;
+    for (int q = 0; q < n; ++q) (q < k ? p.tq : p.oq).push_back(q);
+    p.flags = PASS_INIT_ZERO;
+    plan.passes.push_back(p);
+    ExecStep e;
+    e.pass = 0;
+    plan.exec.push_back(e);
+  }
+  // site -> slots
+  plan.site_slots.assign(plan.sites.size(), {});
+  for (size_t p = 0; p < plan.passes.size(); ++p)
+    for (size_t s = 0; s < plan.passes[p].slots.size(); ++s)
+      for (int site : plan.passes[p].slots[s].sites) plan.site_slots[site].push_back({(int)p, (int)s});
+  for (auto& ps : plan.passes)
+    if (ps.slots.size() > 4096) return fail(PTSBE_E_UNSUPPORTED, "too many fused slots in one pass");
+  return PTSBE_OK;
+}
+
+ptsbe_status build_plan(const ptsbe_circuit* c, const ptsbe_noise_model* nm, const ptsbe_plan_opts* o,
+                        std::shared_ptr<Plan>* out) {
+  if (!c || !out) return fail(PTSBE_E_ARG, "null circuit or output handle");
+  if (c->n_qubits < 1 || c->n_qubits > (uint32_t)kMaxQubits)
+    return fail(c->n_qubits > (uint32_t)kMaxQubits ? PTSBE_E_UNSUPPORTED : PTSBE_E_ARG,
+                "n_qubits must be in 1..34");
+  if (c->n_ops && !c->ops) return fail(PTSBE_E_ARG, "null op array");
+  auto plan = std::make_shared<Plan>();
+  Plan& P = *plan;
+  P.n = (int)c->n_qubits;
+  P.precision = o ? (int)o->precision : PTSBE_C64;
+  if (P.precision != PTSBE_C64 && P.precision != PTSBE_C128) return fail(PTSBE_E_ARG, "bad precision");
+  int tb = (P.precision == PTSBE_C64) ? 12 : 11;
+  if (o && o->tile_qubits) {
+    if (o->tile_qubits < 4 || o->tile_qubits > (uint32_t)kMaxTileBits)
+      return fail(PTSBE_E_ARG, "tile_qubits must be in 4..13");
+    tb = (int)o->tile_qubits;
+    if (P.precision == PTSBE_C128 && tb > 12) return fail(PTSBE_E_ARG, "tile_qubits <= 12 for complex128");
+  }
+  P.tile_bits = tb;
+  // channels
+  uint32_t n_ch = nm ? nm->n_channels : 0;
+  if (n_ch && !nm->channels) return fail(PTSBE_E_ARG, "null channel array");
+  for (uint32_t i = 0; i < n_ch; ++i) {
+    Channel ch;
+    ptsbe_status st = analyse_channel(nm->channels[i], (int)i, &ch);
+    if (st != PTSBE_OK) return st;
+    P.channels.push_back(std::move(ch));
+  }
+  uint32_t n_rules = nm ? nm->n_rules : 0;
+  if (n_rules && !nm->rules) return fail(PTSBE_E_ARG, "null rule array");
+  for (uint32_t r = 0; r < n_rules; ++r) {
+    const ptsbe_attach& a = nm->rules[r];
+    if (a.channel >= n_ch) return fail(PTSBE_E_ARG, "rule " + std::to_string(r) + ": bad channel index");
+    if (a.when > PTSBE_ATTACH_BEFORE_READOUT) return fail(PTSBE_E_ARG, "rule " + std::to_string(r) + ": bad kind");
+    if (a.when != PTSBE_ATTACH_AFTER_TAG && P.channels[a.channel].nq != 1)
+      return fail(PTSBE_E_ARG, "rule " + std::to_string(r) + ": measurement/readout channels act on one qubit");
+    if (a.when == PTSBE_ATTACH_BEFORE_READOUT && P.n < 64 && (a.qmask >> P.n))
+      return fail(PTSBE_E_ARG, "rule " + std::to_string(r) + ": readout mask names a qubit >= n");
+  }
+  auto add_site = [&](int ch, int nq, const int* q) -> ptsbe_status {
+    if (P.channels[ch].nq != nq) return fail(PTSBE_E_ARG, "channel arity does not match the site's qubits");
+    Site s;
+    s.channel = ch;
+    s.nq = nq;
+    s.q[0] = q[0];
+    s.q[1] = nq > 1 ? q[1] : -1;
+    s.step = (int)P.steps.size();
+    P.sites.push_back(s);
+    Step st;
+    st.kind = ST_SITE;
+    st.nq = nq;
+    for (int j = 0; j < nq; ++j) st.q[j] = q[j];
+    st.site = (int)P.sites.size() - 1;
+    st.diag = P.channels[ch].all_diag;
+    P.steps.push_back(st);
+    return PTSBE_OK;
+  };
+  int max_param = -1;
+  for (uint32_t i = 0; i < c->n_ops; ++i) {
+    const ptsbe_op& op = c->ops[i];
+    std::string where = "op " + std::to_string(i) + ": ";
+    if (op.nq < 1 || op.nq > 4) return fail(PTSBE_E_ARG, where + "nq must be 1..4");
+    int q[4];
+    for (uint32_t j = 0; j < op.nq; ++j) {
+      if (op.q[j] >= (uint32_t)P.n) return fail(PTSBE_E_ARG, where + "qubit out of range");
+      q[j] = (int)op.q[j];
+      for (uint32_t l = 0; l < j; ++l)
+        if (op.q[l] == op.q[j]) return fail(PTSBE_E_ARG, where + "repeated qubit");
+    }
+    if (op.kind == PTSBE_OP_GATE) {
+      if (!op.mat) return fail(PTSBE_E_ARG, where + "null gate matrix");
+      if (op.nq > 2) return fail(PTSBE_E_UNSUPPORTED, where + "gates on more than 2 qubits are not supported");
+      Step st;
+      st.kind = ST_GATE;
+      st.nq = (int)op.nq;
+      for (int j = 0; j < st.nq; ++j) st.q[j] = q[j];
+      st.mat = read_mat(op.mat, 1 << op.nq);
+      for (auto& x : st.mat)
+        if (!std::isfinite(x.real()) || !std::isfinite(x.imag())) return fail(PTSBE_E_ARG, where + "non-finite matrix");
+      st.diag = mat_is_diag(st.mat, 1 << op.nq);
+      P.steps.push_back(st);
+    } else if (op.kind == PTSBE_OP_PARAM) {
+      if (op.nq != 1) return fail(PTSBE_E_ARG, where + "parametrised gates act on one qubit");
+      if (op.gen < PTSBE_GEN_X || op.gen > PTSBE_GEN_Z) return fail(PTSBE_E_ARG, where + "bad generator");
+      if (op.index < 0 || op.index > 1000000) return fail(PTSBE_E_ARG, where + "bad parameter index");
+      Step st;
+      st.kind = ST_PARAM;
+      st.nq = 1;
+      st.q[0] = q[0];
+      st.param = op.index;
+      st.gen = (int)op.gen;
+      st.diag = op.gen == PTSBE_GEN_Z;
+      max_param = std::max(max_param, op.index);
+      P.steps.push_back(st);
+    } else if (op.kind == PTSBE_OP_NOISE) {
+      if (op.index < 0 || (uint32_t)op.index >= n_ch) return fail(PTSBE_E_ARG, where + "bad channel index");
+      if (op.nq > 2) return fail(PTSBE_E_ARG, where + "noise ops act on 1 or 2 qubits");
+      ptsbe_status s2 = add_site(op.index, (int)op.nq, q);
+      if (s2 != PTSBE_OK) return fail(s2, where + last_error_cstr());
+      continue;
+    } else if (op.kind == PTSBE_OP_MEASURE_RESET) {
+      if (op.nq != 1) return fail(PTSBE_E_ARG, where + "measure-reset acts on one qubit");
+      for (uint32_t r = 0; r < n_rules; ++r)
+        if (nm->rules[r].when == PTSBE_ATTACH_BEFORE_MEASURE) add_site((int)nm->rules[r].channel, 1, q);
+      Step st;
+      st.kind = ST_MR;
+      st.nq = 1;
+      st.q[0] = q[0];
+      st.mr = P.n_measure++;
+      P.steps.push_back(st);
+      continue;
+    } else if (op.kind == PTSBE_OP_PROJECT0) {
+      if (op.nq != 1) return fail(PTSBE_E_ARG, where + "PROJECT0 acts on one qubit");
+      Step st;
+      st.kind = ST_P0;
+      st.nq = 1;
+      st.q[0] = q[0];
+      st.mat = {cd(1, 0), cd(0, 0), cd(0, 0), cd(0, 0)};
+      st.diag = true;
+      P.steps.push_back(st);
+      continue;
+    } else {
+      return fail(PTSBE_E_ARG, where + "unknown op kind");
+    }
+    for (uint32_t r = 0; r < n_rules; ++r) {
+      const ptsbe_attach& a = nm->rules[r];
+      if (a.when == PTSBE_ATTACH_AFTER_TAG && a.tag == op.tag) {
+        ptsbe_status s2 = add_site((int)a.channel, (int)op.nq, q);
+        if (s2 != PTSBE_OK) return fail(s2, where + "rule " + std::to_string(r) + ": " + last_error_cstr());
+      }
+    }
+  }
+  for (uint32_t r = 0; r < n_rules; ++r) {
+    const ptsbe_attach& a = nm->rules[r];
+    if (a.when != PTSBE_ATTACH_BEFORE_READOUT) continue;
+    for (int qq = 0; qq < P.n; ++qq)
+      if ((a.qmask >> qq) & 1) add_site((int)a.channel, 1, &qq);
+  }
+  if (P.n_measure > 65535) return fail(PTSBE_E_UNSUPPORTED, "too many measure-reset ops");
+  P.n_params = max_param + 1;
+  P.site_off.push_back(0);
+  for (auto& s : P.sites) {
+    const Channel& ch = P.channels[s.channel];
+    for (double p : ch.p) P.site_p.push_back(p);
+    P.site_off.push_back((uint32_t)P.site_p.size());
+  }
+  ptsbe_status st = schedule(P);
+  if (st != PTSBE_OK) return st;
+  *out = plan;
+  return PTSBE_OK;
+}
+
+}  // namespace ptsbe

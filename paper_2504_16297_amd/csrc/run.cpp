@@ -1,0 +1,322 @@
+// Batched execution (Sec. 3, BE): workspace carving, table upload and the
+// launch sequence of one ptsbe_run_batch call.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "host.hpp"
+#include "kernels.hpp"
+
+namespace ptsbe {
+
+namespace {
+
+uint64_t a256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+
+struct WsLayout {
+  uint64_t status, tables, states, cdf, partial, offs, total, mr_partial, mr_bits, mr_norm, end;
+  uint32_t batch;
+  uint32_t nblk, per_block, per_thread;
+};
+
+WsLayout layout_for(const Plan& P, const TrajSet& ts, uint32_t mode, uint32_t batch, uint64_t table_bytes) {
+  WsLayout L{};
+  const uint64_t N = 1ull << P.n;
+  const uint64_t esz = P.precision == PTSBE_C64 ? 8 : 16;
+  const uint64_t Btot = ts.m.size();
+  L.batch = batch;
+  L.per_block = (uint32_t)std::min<uint64_t>(N, kScanBlock);
+  L.nblk = (uint32_t)(N / L.per_block);
+  L.per_thread = std::max<uint32_t>(1, L.per_block / 256);
+  uint64_t o = 0;
+  L.status = o; o = a256(o + 16);
+  L.tables = o; o = a256(o + table_bytes);
+  L.states = o; o = a256(o + (uint64_t)batch * N * esz);
+  L.cdf = o;
+  if (mode == PTSBE_RUN_SHOTS && P.precision == PTSBE_C128) o = a256(o + (uint64_t)batch * N * 8);
+  L.partial = o; o = a256(o + (uint64_t)batch * L.nblk * 8);
+  L.offs = o; o = a256(o + (uint64_t)batch * L.nblk * 8);
+  L.total = o; o = a256(o + (uint64_t)batch * 8);
+  L.mr_partial = o;
+  if (P.n_measure) o = a256(o + (uint64_t)batch * L.nblk * (kMaxGroup + 1) * 8);
+  L.mr_bits = o; o = a256(o + std::max<uint64_t>(1, Btot * P.n_measure));
+  L.mr_norm = o; o = a256(o + std::max<uint64_t>(1, Btot * P.n_measure) * 8);
+  L.end = o;
+  return L;
+}
+
+ptsbe_status hip_check(hipError_t e, const char* what) {
+  if (e == hipSuccess) return PTSBE_OK;
+  return fail(PTSBE_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define CK(expr, what)                                  \
+  do {                                                  \
+    ptsbe_status _s = hip_check((expr), (what));        \
+    if (_s != PTSBE_OK) return _s;                      \
+  } while (0)
+
+// Stage timer: HIP events recorded on the caller's stream between launches;
+// the time between two marks is charged to the stage named by the later mark.
+struct StageTimer {
+  hipStream_t s;
+  bool on;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> cat;
+  StageTimer(hipStream_t st, bool enabled) : s(st), on(enabled) {}
+  ~StageTimer() {
+    for (auto e : ev) hipEventDestroy(e);
+  }
+  hipError_t mark(int c) {
+    if (!on) return hipSuccess;
+    hipEvent_t e;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return r;
+    ev.push_back(e);
+    cat.push_back(c);
+    return hipEventRecord(e, s);
+  }
+  hipError_t collect(double* out) {
+    if (!on || ev.empty()) return hipSuccess;
+    hipError_t r = hipEventSynchronize(ev.back());
+    if (r != hipSuccess) return r;
+    for (size_t i = 1; i < ev.size(); ++i) {
+      float ms = 0;
+      r = hipEventElapsedTime(&ms, ev[i - 1], ev[i]);
+      if (r != hipSuccess) return r;
+      if (cat[i] >= 0) out[cat[i]] += ms;
+      out[5] += ms;
+    }
+    return hipSuccess;
+  }
+};
+enum { T_PASS = 0, T_MEASURE = 2, T_SCAN = 3, T_SAMPLE = 4, T_OTHER = -1 };
+
+template <typename V, typename BitT>
+ptsbe_status run_typed(const Plan& P, TrajSet& ts, const ptsbe_run_opts& o, uint8_t* ws, const WsLayout& L,
+                       void* d_bits, uint32_t* d_traj, uint8_t* d_mr_bits, hipStream_t s) {
+  const uint32_t B = (uint32_t)ts.m.size();
+  const uint64_t N = 1ull << P.n;
+  const TableLayout& T = ts.layout;
+  uint8_t* tb = ws + L.tables;
+  CK(hipMemcpyAsync(tb, ts.table_blob.data(), ts.table_blob.size(), hipMemcpyHostToDevice, s), "table upload");
+  uint32_t* status = reinterpret_cast<uint32_t*>(ws + L.status);
+  CK(launch_fill_u32(status, 0, 4, s), "status reset");
+  V* states = reinterpret_cast<V*>(ws + L.states);
+  double* partial = reinterpret_cast<double*>(ws + L.partial);
+  double* offs = reinterpret_cast<double*>(ws + L.offs);
+  double* total = reinterpret_cast<double*>(ws + L.total);
+  uint8_t* mr_bits = ws + L.mr_bits;
+  double* mr_norm = reinterpret_cast<double*>(ws + L.mr_norm);
+  const uint32_t chunk = o.sort_chunk ? o.sort_chunk : 4096;
+  StageTimer tm(s, o.timing != nullptr);
+  if (o.timing)
+    for (int i = 0; i < 8; ++i) o.timing[i] = 0.0;
+  CK(tm.mark(T_OTHER), "timer");
+
+  PassArgs<V> pa{};
+  pa.passes = reinterpret_cast<const DPass*>(tb + T.passes);
+  pa.ops = reinterpret_cast<const DOp*>(tb + T.ops);
+  pa.slot_default = reinterpret_cast<const uint32_t*>(tb + T.slot_default);
+  pa.pool = reinterpret_cast<const V*>(tb + T.pool);
+  pa.ov_off = reinterpret_cast<const uint32_t*>(tb + T.ov_off);
+  pa.ov = reinterpret_cast<const DOverride*>(tb + T.ov);
+  pa.mr_bits = mr_bits;
+  pa.mr_norm = mr_norm;
+  pa.states = states;
+  pa.N = N;
+  pa.n = (uint32_t)P.n;
+  pa.n_passes = (uint32_t)P.passes.size();
+  pa.n_measure = (uint32_t)P.n_measure;
+
+  for (uint32_t b0 = 0; b0 < B; b0 += L.batch) {
+    const uint32_t bb = std::min<uint32_t>(L.batch, B - b0);
+    pa.t0 = b0;
+    for (const ExecStep& ex : P.exec) {
+      if (ex.pass >= 0) {
+        const Pass& ps = P.passes[ex.pass];
+        pa.pass = (uint32_t)ex.pass;
+        CK(launch_pass<V>(pa, (uint32_t)ps.k, (uint32_t)ps.slots.size(), bb, s), "tile pass");
+        CK(tm.mark(T_PASS), "timer");
+        if (o.timing) {
+          o.timing[1] += 1;
+          o.timing[6] += (double)bb * (double)N * sizeof(V) * ((ps.flags & PASS_INIT_ZERO) ? 1.0 : 2.0);
+        }
+      } else {
+        for (size_t g0 = 0; g0 < ex.mr_qubits.size(); g0 += kMaxGroup) {
+          size_t g1 = std::min(ex.mr_qubits.size(), g0 + kMaxGroup);
+          MarginalArgs<V> ma{};
+          ma.states = states;
+          ma.partial = reinterpret_cast<double*>(ws + L.mr_partial);
+          ma.N = N;
+          ma.nblk = L.nblk;
+          ma.per_block = L.per_block;
+          ma.nq = (uint32_t)(g1 - g0);
+          MrDecideArgs da{};
+          da.partial = ma.partial;
+          da.mr_bits = mr_bits;
+          da.mr_norm = mr_norm;
+          da.status = status;
+          da.tol = 1e-6;
+          da.nblk = L.nblk;
+          da.nq = ma.nq;
+          da.t0 = b0;
+          da.n_measure = (uint32_t)P.n_measure;
+          for (size_t j = g0; j < g1; ++j) {
+            ma.q[j - g0] = (uint32_t)ex.mr_qubits[j];
+            da.idx[j - g0] = (uint32_t)ex.mr_index[j];
+          }
+          CK(launch_marginal<V>(ma, da, bb, s), "measure-reset");
+          CK(tm.mark(T_MEASURE), "timer");
+        }
+      }
+    }
+    ScanArgs<V> sa{};
+    sa.states = states;
+    sa.partial = partial;
+    sa.offs = offs;
+    sa.N = N;
+    sa.nblk = L.nblk;
+    sa.per_block = L.per_block;
+    sa.per_thread = L.per_thread;
+    if (o.mode == PTSBE_RUN_SHOTS) {
+      sa.cdf = P.precision == PTSBE_C128 ? reinterpret_cast<double*>(ws + L.cdf) : nullptr;
+      CK(launch_scan<V>(sa, bb, total, s), "probability scan");
+      CK(tm.mark(T_SCAN), "timer");
+      SampleArgs<BitT> sm{};
+      sm.cdf_base = sa.cdf ? sa.cdf : reinterpret_cast<const double*>(states);
+      sm.cdf_stride = sa.cdf ? N : N * sizeof(V) / 8;
+      sm.total = total;
+      sm.shot_off = reinterpret_cast<const uint64_t*>(tb + T.shot_off);
+      sm.chunk_off = reinterpret_cast<const uint64_t*>(tb + T.chunk_off);
+      sm.uniforms = o.d_uniforms;
+      sm.bits = reinterpret_cast<BitT*>(d_bits);
+      sm.traj = d_traj;
+      sm.N = N;
+      sm.seed = o.seed;
+      sm.alpha0 = ts.alpha0;
+      sm.b0 = b0;
+      sm.b1 = b0 + bb;
+      sm.chunk = chunk;
+      sm.cfg = o.cfg;
+      sm.item0 = ts.chunk_off[b0];
+      const uint64_t items = ts.chunk_off[b0 + bb] - ts.chunk_off[b0];
+      if (items) {
+        CK(launch_sample<BitT>(sm, items, s), "sampler");
+        CK(tm.mark(T_SAMPLE), "timer");
+        if (o.timing) o.timing[7] += 1;
+      }
+    } else if (o.mode == PTSBE_RUN_STATES) {
+      CK(launch_norm<V>(sa, bb, total, s), "norm");
+      CK(launch_copy_normalised<V>(states, reinterpret_cast<V*>(o.d_state_out) + (uint64_t)b0 * N, total, N, bb, s),
+         "state copy");
+    } else {
+      CK(launch_norm<V>(sa, bb, total, s), "norm");
+      ExpArgs<V> ea{};
+      ea.states = states;
+      ea.partial = partial;
+      ea.N = N;
+      ea.nblk = L.nblk;
+      ea.per_block = L.per_block;
+      ea.n_terms = o.n_terms;
+      for (uint32_t j = 0; j < o.n_terms; ++j) {
+        ea.coef[j] = o.obs_coef[j];
+        ea.zmask[j] = o.obs_zmask[j];
+      }
+      CK(launch_expval<V>(ea, total, o.d_expval, bb, b0, s), "expectation");
+    }
+  }
+  if (d_mr_bits && P.n_measure)
+    CK(hipMemcpyAsync(d_mr_bits, mr_bits, (size_t)B * P.n_measure, hipMemcpyDeviceToDevice, s), "record copy");
+  CK(tm.mark(T_OTHER), "timer");
+  if (o.timing) CK(tm.collect(o.timing), "timer");
+  return PTSBE_OK;
+}
+
+ptsbe_status check_opts(const Plan& P, const TrajSet& ts, const ptsbe_run_opts* o) {
+  if (!o) return fail(PTSBE_E_ARG, "null run options");
+  if (o->mode > PTSBE_RUN_EXPECTATION) return fail(PTSBE_E_ARG, "bad run mode");
+  uint32_t c = o->sort_chunk ? o->sort_chunk : 4096;
+  if (c < 256 || c > 4096 || (c & (c - 1))) return fail(PTSBE_E_ARG, "sort_chunk must be a power of two in 256..4096");
+  if (P.n_params && !o->params) return fail(PTSBE_E_ARG, "the circuit has parameters: params required");
+  if (o->mode == PTSBE_RUN_STATES && !o->d_state_out) return fail(PTSBE_E_ARG, "STATES mode needs d_state_out");
+  if (o->mode == PTSBE_RUN_EXPECTATION) {
+    if (!o->d_expval) return fail(PTSBE_E_ARG, "EXPECTATION mode needs d_expval");
+    if (o->n_terms > 64 || (o->n_terms && (!o->obs_coef || !o->obs_zmask)))
+      return fail(PTSBE_E_ARG, "observable: at most 64 Z-string terms with coefficients and masks");
+  }
+  (void)ts;
+  return PTSBE_OK;
+}
+
+}  // namespace
+
+ptsbe_status workspace_size(const Plan& P, TrajSet& ts, const ptsbe_run_opts* o, size_t* bytes) {
+  ptsbe_status st = check_opts(P, ts, o);
+  if (st != PTSBE_OK) return st;
+  uint32_t chunk = o->sort_chunk ? o->sort_chunk : 4096;
+  {
+    std::lock_guard<std::mutex> lk(ts.mu);
+    st = build_tables(ts, o->params, chunk);
+    if (st != PTSBE_OK) return st;
+  }
+  uint32_t B = (uint32_t)ts.m.size();
+  uint32_t batch = o->max_batch ? std::min<uint32_t>(o->max_batch, std::max<uint32_t>(B, 1)) : std::max<uint32_t>(B, 1);
+  batch = std::min<uint32_t>(batch, 65535);
+  *bytes = layout_for(P, ts, o->mode, batch, ts.table_blob.size()).end;
+  return PTSBE_OK;
+}
+
+ptsbe_status run_batch(const Plan& P, TrajSet& ts, const ptsbe_run_opts* o, void* d_ws, size_t ws_bytes,
+                       void* d_bits, uint32_t* d_traj, uint64_t capacity, uint8_t* d_mr_bits, void* stream) {
+  ptsbe_status st = check_opts(P, ts, o);
+  if (st != PTSBE_OK) return st;
+  if (!d_ws) return fail(PTSBE_E_ARG, "null workspace");
+  if (reinterpret_cast<uintptr_t>(d_ws) % 256) return fail(PTSBE_E_ARG, "workspace must be 256-byte aligned");
+  if (o->mode == PTSBE_RUN_SHOTS) {
+    if (capacity < ts.total_shots) {
+      return fail(PTSBE_E_CAPACITY, "output capacity " + std::to_string(capacity) + " < total shots " +
+                                        std::to_string(ts.total_shots));
+    }
+    if (ts.total_shots && (!d_bits || !d_traj)) return fail(PTSBE_E_ARG, "null shot outputs");
+  }
+  std::lock_guard<std::mutex> lk(ts.mu);
+  uint32_t chunk = o->sort_chunk ? o->sort_chunk : 4096;
+  st = build_tables(ts, o->params, chunk);
+  if (st != PTSBE_OK) return st;
+  const uint32_t B = (uint32_t)ts.m.size();
+  if (B == 0) return PTSBE_OK;
+  uint32_t batch = o->max_batch ? std::min(o->max_batch, B) : B;
+  batch = std::min<uint32_t>(batch, 65535);  // grid.y limit of the per-state launches
+  WsLayout L = layout_for(P, ts, o->mode, batch, ts.table_blob.size());
+  while (L.end > ws_bytes && batch > 1) {
+    batch = std::max<uint32_t>(1, batch / 2);
+    L = layout_for(P, ts, o->mode, batch, ts.table_blob.size());
+  }
+  if (L.end > ws_bytes)
+    return fail(PTSBE_E_OOM, "workspace of " + std::to_string(ws_bytes) + " bytes is below the " +
+                                 std::to_string(L.end) + " bytes needed for one trajectory");
+  uint8_t* ws = static_cast<uint8_t*>(d_ws);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (P.precision == PTSBE_C64) {
+    if (P.n <= 32) return run_typed<float2, uint32_t>(P, ts, *o, ws, L, d_bits, d_traj, d_mr_bits, s);
+    return run_typed<float2, uint64_t>(P, ts, *o, ws, L, d_bits, d_traj, d_mr_bits, s);
+  }
+  if (P.n <= 32) return run_typed<double2, uint32_t>(P, ts, *o, ws, L, d_bits, d_traj, d_mr_bits, s);
+  return run_typed<double2, uint64_t>(P, ts, *o, ws, L, d_bits, d_traj, d_mr_bits, s);
+}
+
+ptsbe_status run_status(const void* d_ws, void* stream) {
+  if (!d_ws) return fail(PTSBE_E_ARG, "null workspace");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  CK(hipStreamSynchronize(s), "stream synchronize");
+  uint32_t v = 0;
+  CK(hipMemcpy(&v, d_ws, 4, hipMemcpyDeviceToHost), "status read");
+  if (v & 1u) return fail(PTSBE_E_NONDET_MEASURE, "a measure-reset outcome was not deterministic (min(p1, 1-p1) > 1e-6)");
+  return PTSBE_OK;
+}
+
+}  // namespace ptsbe

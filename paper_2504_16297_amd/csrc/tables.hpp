@@ -1,0 +1,58 @@
+// Device-visible tables of a PTSBE run: the fused tile passes of the plan,
+// their matrix slots, and each trajectory's per-pass overrides.  Built on the
+// host once per (plan, trajectory set, parameters) and copied into the head
+// of the caller's workspace with one transfer.
+#pragma once
+
+#include <stdint.h>
+
+namespace ptsbe {
+
+constexpr int kMaxTileBits = 13;
+constexpr int kMaxQubits = 34;
+
+// Fused operation types inside a tile pass.
+enum DOpType : uint8_t {
+  DOP_M1 = 1,     // 2x2 matrix on local bit a
+  DOP_M2 = 2,     // 4x4 matrix on local bits (a = matrix bit 0, b = matrix bit 1)
+  DOP_D1 = 3,     // diagonal (2 entries) on global qubit ga
+  DOP_D2 = 4,     // diagonal (4 entries) on global qubits (ga = matrix bit 0, gb = bit 1)
+  DOP_MR = 5,     // measure-reset apply on local bit a: |0><b| / sqrt(p_b), b from the device record
+};
+
+struct DOp {
+  uint8_t type;
+  uint8_t a, b;        // local tile bits (M1, M2, MR); for D1/D2 the local bit of ga/gb or 255
+  uint8_t ga, gb;      // global qubits (D1, D2)
+  uint8_t pad0;
+  uint16_t slot;       // matrix slot within the pass (M1, M2, D1, D2); record index for MR
+  uint16_t pad1;
+};
+
+enum DPassFlags : uint32_t {
+  PASS_INIT_ZERO = 1,  // the tile starts from |0...0> instead of being loaded
+};
+
+struct DPass {
+  uint32_t k;          // tile bits
+  uint32_t n_ops;
+  uint32_t op_begin;   // index into the DOp array
+  uint32_t slot_begin; // index into the slot-default array
+  uint32_t n_slots;
+  uint32_t flags;
+  uint8_t tq[16];      // local bit j -> global qubit (ascending)
+  uint8_t oq[48];      // other qubits, ascending (n - k entries)
+};
+
+struct DOverride {
+  uint32_t slot;       // slot index within the pass
+  uint32_t off;        // matrix offset in the pool (complex elements)
+};
+
+// Offsets (bytes) of each table inside the uploaded block.
+struct TableLayout {
+  uint64_t passes, ops, slot_default, pool, ov_off, ov, shot_off, alpha, chunk_off, mr_index;
+  uint64_t total;
+};
+
+}  // namespace ptsbe

@@ -1,0 +1,201 @@
+"""GPU parity of the batched-execution hot path against the FP64 oracle.
+
+Amplitudes: <= 1e-5 max abs (complex64 states) and <= 1e-12 (complex128).
+Shots: identical basis indices given the same Philox streams (or the same
+caller uniforms), except where a uniform lies within 1e-6 of an oracle CDF
+boundary.  Every call goes through the C ABI of libptsbe.so.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2504_16297_amd as P
+from gpu_helpers import compare_shots, log, oracle_states
+from oracle.noise import site_probs
+from oracle.pts import proportional, sample_kraus
+from oracle.sampling import sample
+from oracle.stabilizer import frame_run
+from workloads import c1_workload, c3_workload, random_small_circuit
+from workloads.circuits import hea_circuit, zz_ring
+
+pytestmark = pytest.mark.gpu
+
+
+def _states(plan, ts, params=None):
+    r = P.ptsbe_run_batch(plan, ts, mode="states", params=params)
+    torch.cuda.synchronize()
+    return r["states"].cpu().numpy()
+
+
+CASES = [(1, 6, "c64", 0), (2, 10, "c64", 0), (3, 25, "c128", 0), (5, 40, "c64", 0), (5, 40, "c64", 4),
+         (8, 60, "c64", 4), (8, 60, "c128", 5), (10, 80, "c64", 6), (10, 80, "c64", 0), (11, 60, "c128", 7),
+         (13, 50, "c64", 5)]
+
+
+@pytest.mark.parametrize("n,gates,prec,tile", CASES)
+def test_states_random_circuits(n, gates, prec, tile):
+    log(f"[states] n={n} gates={gates} {prec} tile={tile}")
+    rng = np.random.default_rng(1000 + n * 7 + tile)
+    circ = random_small_circuit(n, gates, rng, p1=0.2, p2=0.3)
+    plan = P.ptsbe_plan(circ, precision=prec, tile_qubits=tile)
+    ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=24, total_shots=24, seed=3, cfg=1)
+    g = ts.get()
+    gpu = _states(plan, ts)
+    ref, _ = oracle_states(circ, g["records"])
+    tol = 1e-5 if prec == "c64" else 1e-12
+    err = max(float(np.max(np.abs(gpu[a] - ref[a]))) for a in range(len(ref)))
+    log(f"  passes={plan.info['n_passes']} trajectories={len(ref)} max|d|={err:.3e}")
+    assert err <= tol
+
+
+def test_states_with_parameters_and_diagonals():
+    rng = np.random.default_rng(77)
+    circ = random_small_circuit(9, 70, rng, with_params=True)
+    plan = P.ptsbe_plan(circ, tile_qubits=5)
+    ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=10, total_shots=10, seed=1, cfg=1)
+    params = np.asarray(circ["params"])
+    gpu = _states(plan, ts, params=params)
+    ref, _ = oracle_states(circ, ts.get()["records"], params=params)
+    err = max(float(np.max(np.abs(gpu[a] - ref[a]))) for a in range(len(ref)))
+    assert err <= 1e-5
+
+
+def test_c1_full_shots_bit_exact():
+    wl = c1_workload()
+    circ = wl["circuit"]
+    plan = P.ptsbe_plan(circ, precision="c128")
+    pts = wl["pts"]
+    ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=pts["n_draws"], total_shots=pts["total_shots"],
+                              seed=wl["seed"], cfg=wl["cfg"])
+    g = ts.get()
+    r = P.ptsbe_run_batch(plan, ts, mode="shots", seed=wl["seed"], cfg=wl["cfg"])
+    torch.cuda.synchronize()
+    bits = r["bits"].cpu().numpy()
+    traj = r["traj"].cpu().numpy()
+    ref, _ = oracle_states(circ, g["records"])
+    off = np.concatenate([[0], np.cumsum(g["m"].astype(np.int64))])
+    total_bad = total_exc = 0
+    for a in range(len(ref)):
+        seg = slice(off[a], off[a + 1])
+        assert np.all(traj[seg] == a)
+        bad, exc = compare_shots(ref[a], bits[seg], int(g["m"][a]), wl["seed"], wl["cfg"], a)
+        total_bad += bad
+        total_exc += exc
+    log(f"[C1] {off[-1]} shots, unexcused mismatches {total_bad}, boundary-excused {total_exc}")
+    assert total_bad == 0
+
+
+def test_caller_uniforms_and_edges():
+    rng = np.random.default_rng(5)
+    circ = random_small_circuit(6, 30, rng)
+    plan = P.ptsbe_plan(circ)
+    recs = [(), ((0, 1),)] if plan.info["n_sites"] else [(), ()]
+    m = [5000, 3]
+    ts = P.ptsbe_trajset_from_records(plan, recs, m)
+    u = rng.random(sum(m))
+    u[0] = 0.0
+    u[1] = 1.0 - 2.0 ** -53
+    u[4999] = 0.5
+    ud = torch.tensor(u, dtype=torch.float64, device="cuda")
+    r = P.ptsbe_run_batch(plan, ts, mode="shots", uniforms=ud, sort_chunk=1024)
+    torch.cuda.synchronize()
+    bits = r["bits"].cpu().numpy()
+    ref, _ = oracle_states(circ, recs)
+    bad, _ = compare_shots(ref[0], bits[:5000], 5000, 0, 0, 0, chunk=1024, u=u[:5000])
+    assert bad == 0
+    bad, _ = compare_shots(ref[1], bits[5000:], 3, 0, 0, 1, chunk=1024, u=u[5000:])
+    assert bad == 0
+
+
+def test_zero_shot_trajectories_and_capacity_error():
+    circ = random_small_circuit(4, 20, np.random.default_rng(9))
+    plan = P.ptsbe_plan(circ)
+    ts = P.ptsbe_trajset_from_records(plan, [(), (), ()], [0, 7, 0])
+    r = P.ptsbe_run_batch(plan, ts, mode="shots", seed=1, cfg=1)
+    torch.cuda.synchronize()
+    assert np.all(r["traj"].cpu().numpy()[:7] == 1)
+    small = {"bits": torch.empty(3, dtype=torch.int32, device="cuda"),
+             "traj": torch.empty(3, dtype=torch.int32, device="cuda")}
+    with pytest.raises(P.PtsbeError) as e:
+        P.ptsbe_run_batch(plan, ts, mode="shots", out=small)
+    assert e.value.status == 4
+
+
+def test_batches_slices_and_repeat_are_bit_identical():
+    circ = random_small_circuit(12, 60, np.random.default_rng(12), p1=0.2, p2=0.3)
+    plan = P.ptsbe_plan(circ, tile_qubits=8)
+    ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=40, total_shots=50000, seed=4, cfg=3)
+    full = P.ptsbe_run_batch(plan, ts, seed=4, cfg=3)
+    b1 = full["bits"].clone()
+    again = P.ptsbe_run_batch(plan, ts, seed=4, cfg=3)
+    small = P.ptsbe_run_batch(plan, ts, seed=4, cfg=3, max_batch=3)
+    torch.cuda.synchronize()
+    assert torch.equal(b1, again["bits"]) and torch.equal(b1, small["bits"])
+    B = ts.n_traj
+    h = B // 2
+    s1, s2 = ts.slice(0, h), ts.slice(h, B)
+    r1 = P.ptsbe_run_batch(plan, s1, seed=4, cfg=3)
+    r2 = P.ptsbe_run_batch(plan, s2, seed=4, cfg=3)
+    torch.cuda.synchronize()
+    cat = torch.cat([r1["bits"][:s1.get()["total_shots"]], r2["bits"][:s2.get()["total_shots"]]])
+    assert torch.equal(cat, b1)
+    tcat = torch.cat([r1["traj"][:s1.get()["total_shots"]], r2["traj"][:s2.get()["total_shots"]]])
+    assert torch.equal(tcat, full["traj"])
+
+
+def test_surface_code_records_and_shots():
+    wl = c3_workload()
+    circ = wl["circuit"]
+    plan = P.ptsbe_plan(circ)
+    ts = P.ptsbe_sample_kraus(plan, "most_likely", k_max=4096, total_shots=10**6)
+    g = ts.get()
+    log(f"[C3] passes={plan.info['n_passes']} steps={plan.info['n_steps']} trajectories={len(g['m'])}")
+    r = P.ptsbe_run_batch(plan, ts, seed=0, cfg=3)
+    P.ptsbe_run_status(plan, r["workspace"])
+    torch.cuda.synchronize()
+    mr = r["mr_bits"].cpu().numpy()
+    for a, rec in enumerate(g["records"]):
+        fb, _ = frame_run(circ, rec)
+        assert list(mr[a]) == fb, f"trajectory {a}"
+    bits = r["bits"].cpu().numpy()
+    off = np.concatenate([[0], np.cumsum(g["m"].astype(np.int64))])
+    picks = [0, 1, 2000, 4095]
+    ref, rbits = oracle_states(circ, [g["records"][a] for a in picks])
+    for j, a in enumerate(picks):
+        assert rbits[j] == list(mr[a])
+        bad, _ = compare_shots(ref[j], bits[off[a]:off[a + 1]], int(g["m"][a]), 0, 3, a)
+        assert bad == 0
+
+
+def test_nondeterministic_measure_is_reported():
+    circ = {"n_qubits": 2, "ops": [{"kind": "gate", "name": "H", "qubits": (0,), "params": (), "tag": "H"},
+                                   {"kind": "measure_reset", "qubits": (0,)}],
+            "channels": [], "rules": [], "params": []}
+    plan = P.ptsbe_plan(circ)
+    ts = P.ptsbe_trajset_from_records(plan, [()], [4])
+    r = P.ptsbe_run_batch(plan, ts)
+    with pytest.raises(P.PtsbeError) as e:
+        P.ptsbe_run_status(plan, r["workspace"])
+    assert e.value.status == 7
+
+
+def test_expectation_mode_matches_oracle():
+    circ = hea_circuit(10, 3, np.random.default_rng(2), 0.05)
+    plan = P.ptsbe_plan(circ, tile_qubits=6)
+    ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=50, total_shots=50, seed=0, cfg=5)
+    params = np.asarray(circ["params"])
+    obs = zz_ring(10)
+    r = P.ptsbe_run_batch(plan, ts, mode="expectation", params=params, observable=obs)
+    torch.cuda.synchronize()
+    e = r["expval"].cpu().numpy()
+    ref, _ = oracle_states(circ, ts.get()["records"], params=params)
+    x = np.arange(1 << 10)
+    od = np.zeros(1 << 10)
+    for c, qs in obs:
+        s = np.ones(1 << 10)
+        for q in qs:
+            s *= 1 - 2 * ((x >> q) & 1)
+        od += c * s
+    for a, psi in enumerate(ref):
+        assert abs(e[a] - float(np.sum(np.abs(psi) ** 2 * od))) < 1e-5

@@ -1,0 +1,119 @@
+"""Host-side parity of the C++ planner and PTS samplers (through the C ABI, no GPU)
+against the oracle: identical site lists and probabilities, identical records,
+counts, shot allocations and joint probabilities, bit for bit."""
+
+import numpy as np
+import pytest
+
+import paper_2504_16297_amd as P
+from oracle.noise import expand, site_probs
+from oracle.pts import (alg2_literal, allocate_multiplicity, allocate_reweight, joint_prob,
+                        most_likely, proportional, sample_kraus)
+from workloads import (c1_workload, c2_workload, c3_workload, c5_workload, random_small_circuit)
+
+
+def _sites_equal(plan, circ):
+    gp, _ = plan.site_probs()
+    op = site_probs(circ)
+    assert len(gp) == len(op)
+    for a, b in zip(gp, op):
+        assert list(a) == list(b)          # bitwise: same arithmetic in the same order
+
+
+@pytest.mark.parametrize("wl", [c1_workload(), c2_workload(), c5_workload()], ids=["C1", "C2", "C5"])
+def test_proportional_matches_oracle_on_workloads(wl):
+    circ = wl["circuit"]
+    plan = P.ptsbe_plan(circ, precision=wl["precision"])
+    _sites_equal(plan, circ)
+    pts = wl["pts"]
+    ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=pts["n_draws"],
+                              total_shots=pts["total_shots"], seed=wl["seed"], cfg=wl["cfg"])
+    g = ts.get()
+    ref = sample_kraus(site_probs(circ), pts, wl["seed"], wl["cfg"])
+    assert g["records"] == ref["records"]
+    assert list(g["count"]) == ref["counts"]
+    assert list(g["m"]) == ref["m"]
+    assert list(g["p"]) == ref["p"]
+    assert g["total_shots"] == pts["total_shots"]
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_random_circuits_all_samplers(seed):
+    rng = np.random.default_rng(seed)
+    circ = random_small_circuit(int(rng.integers(2, 7)), 40, rng, p1=0.1, p2=0.15)
+    plan = P.ptsbe_plan(circ)
+    _sites_equal(plan, circ)
+    sp = site_probs(circ)
+    # proportional
+    ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=300, total_shots=12345, seed=seed, cfg=7)
+    g = ts.get()
+    recs, counts = proportional(sp, seed, 7, 300)
+    assert g["records"] == recs and list(g["count"]) == counts
+    assert list(g["m"]) == allocate_multiplicity(counts, 300, 12345)
+    # per-shot (Algorithm 1 draws, stream 3, no merging)
+    ts = P.ptsbe_sample_kraus(plan, "per_shot", n_draws=50, seed=seed, cfg=7)
+    g = ts.get()
+    recs, _ = proportional(sp, seed, 7, 50, stream=3, merge=False)
+    assert g["records"] == recs and list(g["m"]) == [1] * 50
+    # Algorithm 2 as printed
+    ts = P.ptsbe_sample_kraus(plan, "alg2_literal", n_draws=200, nshots=17, seed=seed, cfg=7)
+    g = ts.get()
+    recs, m = alg2_literal(sp, seed, 7, 200, 17)
+    assert g["records"] == recs and list(g["m"]) == m
+    # most likely first
+    for K in (1, 10, 200):
+        ts = P.ptsbe_sample_kraus(plan, "most_likely", k_max=K, total_shots=10**6, seed=seed)
+        g = ts.get()
+        recs, _ = most_likely(sp, K)
+        assert g["records"] == recs
+        assert list(g["m"]) == allocate_reweight([joint_prob(r, sp) for r in recs], 10**6)
+        assert list(g["p"]) == [joint_prob(r, sp) for r in recs]
+
+
+def test_most_likely_surface_code_top_4096():
+    wl = c3_workload()
+    circ = wl["circuit"]
+    plan = P.ptsbe_plan(circ)
+    assert plan.info["n_sites"] == 209 and plan.info["n_measure"] == 40
+    _sites_equal(plan, circ)
+    ts = P.ptsbe_sample_kraus(plan, "most_likely", k_max=4096, total_shots=10**9)
+    g = ts.get()
+    sp = site_probs(circ)
+    recs, _ = most_likely(sp, 4096)
+    assert g["records"] == recs
+    assert list(g["m"]) == allocate_reweight([joint_prob(r, sp) for r in recs], 10**9)
+    assert int(g["m"].sum()) == 10**9
+
+
+def test_probability_band_and_slices():
+    circ = random_small_circuit(4, 30, np.random.default_rng(3), p1=0.1, p2=0.2)
+    plan = P.ptsbe_plan(circ)
+    sp = site_probs(circ)
+    ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=400, total_shots=4000, seed=1, cfg=2)
+    g = ts.get()
+    lo, hi = np.quantile(g["p"], [0.25, 0.75])
+    tb = P.ptsbe_sample_kraus(plan, "proportional", n_draws=400, total_shots=4000, seed=1, cfg=2,
+                              p_band=(lo, hi))
+    gb = tb.get()
+    assert all(lo <= p <= hi for p in gb["p"])
+    keep = [(r, c) for r, c, p in zip(g["records"], g["count"], g["p"]) if lo <= p <= hi]
+    assert gb["records"] == [r for r, _ in keep]
+    assert int(gb["m"].sum()) == 4000
+    s = ts.slice(5, 9).get()
+    assert s["alpha0"] == 5 and s["records"] == g["records"][5:9]
+    fr = P.ptsbe_trajset_from_records(plan, g["records"][:3], [7, 8, 9], alpha0=11).get()
+    assert fr["records"] == g["records"][:3] and list(fr["m"]) == [7, 8, 9]
+    assert list(fr["p"]) == [joint_prob(r, sp) for r in g["records"][:3]]
+
+
+def test_plan_site_order_matches_expansion():
+    circ = c3_workload()["circuit"]
+    plan = P.ptsbe_plan(circ)
+    _, q = plan.site_probs()
+    _, sites = expand(circ)
+    for s, row in zip(sites, q):
+        assert row[0] == s["qubits"][0]
+        if len(s["qubits"]) > 1:
+            assert row[1] == s["qubits"][1]
+        else:
+            assert row[1] == 0xFFFFFFFF
