@@ -260,6 +260,16 @@ ptsbe_status ptsbe_run_batch(ptsbe_plan_t plan, ptsbe_trajset_t ts, const ptsbe_
                              void* d_ws, size_t ws_bytes, void* d_bits, uint32_t* d_traj,
                              uint64_t capacity, uint8_t* d_mr_bits, void* stream);
 
+/* Inspection: the device tables a run of `ts` would upload (fused passes, ops,
+ * slot matrices, per-trajectory overrides, shot and chunk offsets, execution
+ * steps), for host-side checks of the fused program.  With out == NULL only
+ * *bytes is set.  offsets receives 16 uint64 values: byte offsets of passes,
+ * ops, slot defaults, matrix pool, override offsets, overrides, shot offsets,
+ * chunk offsets, execution steps, then the counts of passes, ops, slots, pool
+ * entries, overrides and execution steps, then the total size. */
+ptsbe_status ptsbe_trajset_tables(ptsbe_trajset_t ts, const double* params, uint32_t sort_chunk, void* out,
+                                  size_t* bytes, uint64_t* offsets);
+
 /* Wait for `stream` and read the device status word of a workspace last used
  * by ptsbe_run_batch: PTSBE_OK or PTSBE_E_NONDET_MEASURE. */
 ptsbe_status ptsbe_run_status(ptsbe_plan_t plan, const void* d_ws, void* stream);

@@ -101,6 +101,8 @@ _SIGS = {
                                   C.c_size_t, C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p,
                                   C.c_void_p]),
     "ptsbe_run_status": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ptsbe_trajset_tables": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_uint32, C.c_void_p,
+                                       C.POINTER(C.c_size_t), C.c_void_p]),
     "ptsbe_adjoint_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_double),
                                      C.POINTER(C.c_double), C.POINTER(C.c_uint64), C.c_uint32,
                                      C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p]),

@@ -25,9 +25,9 @@ ptsbe_status adjoint_grad(const Plan& P, TrajSet& ts, const double* params, cons
 
 using namespace ptsbe;
 
-#define FENCE(body)                                                  \
+#define FENCE(...)                                                   \
   try {                                                              \
-    body                                                             \
+    __VA_ARGS__                                                      \
   } catch (const std::bad_alloc&) {                                  \
     return fail(PTSBE_E_OOM, "host allocation failed");              \
   } catch (const std::exception& e) {                                \
@@ -153,6 +153,34 @@ ptsbe_status ptsbe_run_batch(ptsbe_plan_t plan, ptsbe_trajset_t ts, const ptsbe_
     if (!plan || !ts) return fail(PTSBE_E_ARG, "null argument");
     if (ts->ts->plan.get() != plan->plan.get()) return fail(PTSBE_E_ARG, "trajectory set belongs to another plan");
     return run_batch(*plan->plan, *ts->ts, opts, d_ws, ws_bytes, d_bits, d_traj, capacity, d_mr_bits, stream);
+  })
+}
+
+ptsbe_status ptsbe_trajset_tables(ptsbe_trajset_t h, const double* params, uint32_t sort_chunk, void* out,
+                                  size_t* bytes, uint64_t* offsets) {
+  FENCE({
+    if (!h || !bytes) return fail(PTSBE_E_ARG, "null argument");
+    TrajSet& ts = *h->ts;
+    uint32_t chunk = sort_chunk ? sort_chunk : 4096;
+    if (chunk < 256 || chunk > 4096 || (chunk & (chunk - 1)))
+      return fail(PTSBE_E_ARG, "sort_chunk must be a power of two in 256..4096");
+    if (ts.plan->n_params && !params) return fail(PTSBE_E_ARG, "the circuit has parameters: params required");
+    std::lock_guard<std::mutex> lk(ts.mu);
+    ptsbe_status st = build_tables(ts, params, chunk);
+    if (st != PTSBE_OK) return st;
+    if (out) {
+      if (*bytes < ts.table_blob.size()) return fail(PTSBE_E_ARG, "output buffer too small");
+      std::memcpy(out, ts.table_blob.data(), ts.table_blob.size());
+    }
+    *bytes = ts.table_blob.size();
+    if (offsets) {
+      const TableLayout& L = ts.layout;
+      const uint64_t v[16] = {L.passes, L.ops,    L.slot_default, L.pool,  L.ov_off,  L.ov,
+                              L.shot_off, L.chunk_off, L.exec,    L.n_passes, L.n_ops, L.n_slots,
+                              L.n_pool, L.n_ov,   L.n_exec,       L.total};
+      std::memcpy(offsets, v, sizeof(v));
+    }
+    return PTSBE_OK;
   })
 }
 

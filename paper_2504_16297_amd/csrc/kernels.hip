@@ -301,7 +301,9 @@ __global__ void k_mr_decide(MrDecideArgs a) {
   if (fmin(p1, 1.0 - p1) > a.tol) atomicOr(a.status, 1u);
   const uint64_t ri = (uint64_t)(a.t0 + tb) * a.n_measure + a.idx[j];
   a.mr_bits[ri] = (uint8_t)bit;
-  a.mr_norm[ri] = 1.0 / sqrt(pb * tot);
+  // Every measure-reset of the group scales the whole state once; the group's
+  // first one also carries the 1/||psi|| renormalisation.
+  a.mr_norm[ri] = j == 0 ? 1.0 / sqrt(pb * tot) : 1.0 / sqrt(pb);
 }
 
 // ------------------------------------------------------------------ sampler

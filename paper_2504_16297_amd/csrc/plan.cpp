@@ -306,7 +306,9 @@ struct Fuser {
 static ptsbe_status schedule(Plan& plan) {
   const int n = plan.n;
   const int k = std::min(n, plan.tile_bits);
-  const int contiguous = std::min(k, plan.precision == PTSBE_C64 ? 4 : 3);
+  // The lowest qubits are always in the tile (runs of >= 128 contiguous bytes),
+  // leaving at least two free tile bits so that any 2-qubit operation fits.
+  const int contiguous = std::max(0, std::min(k - 2, plan.precision == PTSBE_C64 ? 4 : 3));
   std::vector<int> rem(plan.steps.size());
   for (size_t i = 0; i < rem.size(); ++i) rem[i] = (int)i;
   std::vector<char> measured(plan.steps.size(), 0);

@@ -435,10 +435,27 @@ ptsbe_status build_tables(TrajSet& ts, const double* params, uint32_t chunk) {
   L.ov_off = o; o = align256(o + ov_off.size() * 4);
   L.ov = o; o = align256(o + std::max<size_t>(1, ov.size()) * sizeof(DOverride));
   L.shot_off = o; o = align256(o + shot_off.size() * 8);
-  L.alpha = o; o = align256(o + 8);
   L.chunk_off = o; o = align256(o + chunk_off.size() * 8);
-  L.mr_index = o; o = align256(o + 8);
+  std::vector<DExec> exec(P.exec.size());
+  for (size_t e = 0; e < P.exec.size(); ++e) {
+    DExec& d = exec[e];
+    std::memset(&d, 0, sizeof(d));
+    const ExecStep& ex = P.exec[e];
+    d.pass = ex.pass >= 0 ? (uint32_t)ex.pass : 0xffffffffu;
+    d.nq = (uint32_t)std::min<size_t>(16, ex.mr_qubits.size());
+    for (uint32_t j = 0; j < d.nq; ++j) {
+      d.q[j] = (uint32_t)ex.mr_qubits[j];
+      d.idx[j] = (uint32_t)ex.mr_index[j];
+    }
+  }
+  L.exec = o; o = align256(o + std::max<size_t>(1, exec.size()) * sizeof(DExec));
   L.total = o;
+  L.n_passes = passes.size();
+  L.n_ops = ops.size();
+  L.n_slots = slot_default.size();
+  L.n_pool = pool.size();
+  L.n_ov = ov.size();
+  L.n_exec = exec.size();
   std::vector<uint8_t> blob(L.total, 0);
   put(blob, L.passes, passes.data(), passes.size());
   put(blob, L.ops, ops.data(), ops.size());
@@ -462,6 +479,7 @@ ptsbe_status build_tables(TrajSet& ts, const double* params, uint32_t chunk) {
   put(blob, L.ov, ov.data(), ov.size());
   put(blob, L.shot_off, shot_off.data(), shot_off.size());
   put(blob, L.chunk_off, chunk_off.data(), chunk_off.size());
+  put(blob, L.exec, exec.data(), exec.size());
   ts.table_blob.swap(blob);
   ts.layout = L;
   ts.cached_params = pv;

@@ -49,9 +49,19 @@ struct DOverride {
   uint32_t off;        // matrix offset in the pool (complex elements)
 };
 
+// Execution step as recorded in the tables (read by the host and by
+// inspection tools, not by kernels): a tile pass, or a group of measure-resets.
+struct DExec {
+  uint32_t pass;       // pass index, or 0xffffffff for a measurement step
+  uint32_t nq;         // measurement: number of qubits
+  uint32_t q[16];
+  uint32_t idx[16];    // measurement: record indices
+};
+
 // Offsets (bytes) of each table inside the uploaded block.
 struct TableLayout {
-  uint64_t passes, ops, slot_default, pool, ov_off, ov, shot_off, alpha, chunk_off, mr_index;
+  uint64_t passes, ops, slot_default, pool, ov_off, ov, shot_off, chunk_off, exec;
+  uint64_t n_passes, n_ops, n_slots, n_pool, n_ov, n_exec;
   uint64_t total;
 };
 

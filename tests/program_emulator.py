@@ -1,0 +1,153 @@
+"""NumPy emulator of the fused device program exported by ptsbe_trajset_tables.
+
+It executes the tile passes, slot matrices, per-trajectory overrides and
+measure-reset steps exactly as the tables describe them (complex128), so the
+planner's fusion can be checked against the oracle on the CPU.  Test helper
+only: it re-implements the device program's semantics, not the method.
+"""
+
+import ctypes as C
+
+import numpy as np
+
+import paper_2504_16297_amd as P
+from paper_2504_16297_amd import _lib as L
+
+PASS_DT = np.dtype([("k", "<u4"), ("n_ops", "<u4"), ("op_begin", "<u4"), ("slot_begin", "<u4"),
+                    ("n_slots", "<u4"), ("flags", "<u4"), ("tq", "u1", 16), ("oq", "u1", 48)])
+OP_DT = np.dtype([("type", "u1"), ("a", "u1"), ("b", "u1"), ("ga", "u1"), ("gb", "u1"), ("pad0", "u1"),
+                  ("slot", "<u2"), ("pad1", "<u2")])
+OV_DT = np.dtype([("slot", "<u4"), ("off", "<u4")])
+EXEC_DT = np.dtype([("pass", "<u4"), ("nq", "<u4"), ("q", "<u4", 16), ("idx", "<u4", 16)])
+M1, M2, D1, D2, MR = 1, 2, 3, 4, 5
+
+
+def export_tables(ts, params=None, sort_chunk=0):
+    n = C.c_size_t()
+    pp = None
+    if params is not None and len(params):
+        pa = np.ascontiguousarray(params, dtype=np.float64)
+        pp = C.cast(pa.ctypes.data, C.POINTER(C.c_double))
+    offs = np.zeros(16, dtype=np.uint64)
+    P.check(L.lib().ptsbe_trajset_tables(ts.handle, pp, sort_chunk, None, C.byref(n), offs.ctypes.data))
+    buf = np.zeros(n.value, dtype=np.uint8)
+    P.check(L.lib().ptsbe_trajset_tables(ts.handle, pp, sort_chunk, buf.ctypes.data, C.byref(n),
+                                         offs.ctypes.data))
+    o = [int(x) for x in offs]
+    prec = ts.plan.info["precision"]
+    cdt = np.complex64 if prec == L.C64 else np.complex128
+    B = ts.n_traj
+    t = {
+        "passes": np.frombuffer(buf, PASS_DT, o[9], o[0]),
+        "ops": np.frombuffer(buf, OP_DT, o[10], o[1]),
+        "slot_default": np.frombuffer(buf, "<u4", o[11], o[2]),
+        "pool": np.frombuffer(buf, cdt, o[12], o[3]).astype(np.complex128),
+        "ov_off": np.frombuffer(buf, "<u4", B * o[9] + 1, o[4]),
+        "ov": np.frombuffer(buf, OV_DT, o[13], o[5]),
+        "shot_off": np.frombuffer(buf, "<u8", B + 1, o[6]),
+        "chunk_off": np.frombuffer(buf, "<u8", B + 1, o[7]),
+        "exec": np.frombuffer(buf, EXEC_DT, o[14], o[8]),
+    }
+    return t
+
+
+def _apply_1q(T, a, m):
+    nt = T.shape[1]
+    v = T.reshape(T.shape[0], nt >> (a + 1), 2, 1 << a)
+    x0 = v[:, :, 0, :].copy()
+    x1 = v[:, :, 1, :].copy()
+    v[:, :, 0, :] = m[0, 0] * x0 + m[0, 1] * x1
+    v[:, :, 1, :] = m[1, 0] * x0 + m[1, 1] * x1
+
+
+def run_program(tables, n, B, mr_tol=1e-6):
+    """Return (normalised states [B, 2^n], mr bits [B, n_measure] as lists)."""
+    N = 1 << n
+    passes, ops = tables["passes"], tables["ops"]
+    NP = len(passes)
+    states = []
+    allbits = []
+    x = np.arange(N, dtype=np.int64)
+    for t in range(B):
+        psi = np.zeros(N, dtype=np.complex128)
+        bits = {}
+        norms = {}
+        for ex in tables["exec"]:
+            if ex["pass"] != 0xFFFFFFFF:
+                p = int(ex["pass"])
+                ps = passes[p]
+                k = int(ps["k"])
+                tq = [int(q) for q in ps["tq"][:k]]
+                oq = [int(q) for q in ps["oq"][:n - k]]
+                nt = 1 << k
+                Lidx = np.arange(nt)
+                off = np.zeros(nt, dtype=np.int64)
+                for j, q in enumerate(tq):
+                    off |= ((Lidx >> j) & 1) << q
+                tiles = np.arange(1 << (n - k))
+                base = np.zeros(tiles.size, dtype=np.int64)
+                for i, q in enumerate(oq):
+                    base |= ((tiles >> i) & 1) << q
+                idx = base[:, None] + off[None, :]
+                slot = [int(s) for s in tables["slot_default"][ps["slot_begin"]:ps["slot_begin"] + ps["n_slots"]]]
+                ob, oe = tables["ov_off"][t * NP + p], tables["ov_off"][t * NP + p + 1]
+                for e in tables["ov"][ob:oe]:
+                    slot[int(e["slot"])] = int(e["off"])
+                if ps["flags"] & 1:
+                    T = np.zeros((tiles.size, nt), dtype=np.complex128)
+                    T[0, 0] = 1.0
+                else:
+                    T = psi[idx].copy()
+                for op in ops[ps["op_begin"]:ps["op_begin"] + ps["n_ops"]]:
+                    ty = int(op["type"])
+                    pool = tables["pool"]
+                    if ty == M1:
+                        m = pool[slot[op["slot"]]:slot[op["slot"]] + 4].reshape(2, 2)
+                        _apply_1q(T, int(op["a"]), m)
+                    elif ty == M2:
+                        m = pool[slot[op["slot"]]:slot[op["slot"]] + 16].reshape(4, 4)
+                        a, b = int(op["a"]), int(op["b"])
+                        ba = (Lidx >> a) & 1
+                        bb = (Lidx >> b) & 1
+                        r = ba + 2 * bb
+                        i00 = Lidx[(ba == 0) & (bb == 0)]
+                        grp = [i00, i00 | (1 << a), i00 | (1 << b), i00 | (1 << a) | (1 << b)]
+                        X = np.stack([T[:, g] for g in grp], axis=-1)
+                        Y = X @ m.T
+                        for j, g in enumerate(grp):
+                            T[:, g] = Y[..., j]
+                        del r
+                    elif ty in (D1, D2):
+                        dd = 3 if ty == D1 else 5
+                        m = pool[slot[op["slot"]]:slot[op["slot"]] + (4 if ty == D1 else 16)]
+                        ga = ((idx >> int(op["ga"])) & 1)
+                        gb = ((idx >> int(op["gb"])) & 1) if ty == D2 else 0
+                        T *= m[(ga + 2 * gb) * dd]
+                    elif ty == MR:
+                        r = int(op["slot"])
+                        b = bits[r]
+                        a = int(op["a"])
+                        v = T.reshape(T.shape[0], nt >> (a + 1), 2, 1 << a)
+                        keep = v[:, :, b, :].copy() * norms[r]
+                        v[:, :, 0, :] = keep
+                        v[:, :, 1, :] = 0
+                    else:
+                        raise ValueError(ty)
+                psi = np.zeros(N, dtype=np.complex128) if ps["flags"] & 1 else psi
+                psi[idx] = T
+            else:
+                w = np.abs(psi) ** 2
+                tot = w.sum()
+                for j in range(int(ex["nq"])):
+                    q = int(ex["q"][j])
+                    p1 = w[((x >> q) & 1) == 1].sum() / tot
+                    if min(p1, 1 - p1) > mr_tol:
+                        raise RuntimeError(f"non-deterministic measure-reset on qubit {q}")
+                    b = 1 if p1 > 0.5 else 0
+                    r = int(ex["idx"][j])
+                    bits[r] = b
+                    pb = p1 if b else 1 - p1
+                    norms[r] = 1.0 / np.sqrt(pb * tot) if j == 0 else 1.0 / np.sqrt(pb)
+        states.append(psi / np.linalg.norm(psi))
+        allbits.append([bits[r] for r in sorted(bits)])
+    return states, allbits
