@@ -68,7 +68,19 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-baseline", action="store_true", help="skip the per-shot GPU baseline")
     ap.add_argument("--baseline-shots", type=int, default=512)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 2 GiB device copy (calibrates FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        n = 1 << 28                      # 2^28 float64 = 2 GiB read + 2 GiB written per copy
+        x = torch.ones(n, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "copies": 3}))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the PTSBE path here is single-GPU (inter-trajectory "
               f"sharding is a partition of the trajectory set, not built); --gpus {args.gpus} is "

@@ -141,6 +141,19 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs<V> a) {
         const V ph = m[(ba + 2 * bb) * dd];
         tile[L] = cmul(ph, tile[L]);
       }
+    } else if (op.type == DOP_DSIGN) {
+      const uint32_t fa = op.a == 255 ? (uint32_t)((base >> op.ga) & 1) : 0;
+      const uint32_t fb = op.b == 255 ? (uint32_t)((base >> op.gb) & 1) : 0;
+      for (uint32_t L = tid; L < nt; L += blockDim.x) {
+        const uint32_t ba = op.a == 255 ? fa : (L >> op.a) & 1u;
+        const uint32_t bb = op.b == 254 ? 0u : (op.b == 255 ? fb : (L >> op.b) & 1u);
+        if ((op.slot >> (ba + 2 * bb)) & 1u) {
+          V v = tile[L];
+          v.x = -v.x;
+          v.y = -v.y;
+          tile[L] = v;
+        }
+      }
     } else if (op.type == DOP_MR) {
       const uint64_t ri = (uint64_t)t * a.n_measure + op.slot;
       const uint32_t b = a.mr_bits[ri];
@@ -162,6 +175,308 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs<V> a) {
     __syncthreads();
   }
   for (uint32_t L = tid; L < nt; L += blockDim.x) st[base + tile_offset(L, tq, k)] = tile[L];
+}
+
+// ------------------------------------------------------- register tile pass
+//
+// Each thread keeps 16 amplitudes of the tile in registers; they span the 4
+// local bits R (the "register bits"), the thread index supplies the other
+// k - 4 local bits.  Gates on register bits are applied in registers with no
+// data movement; a DOP_PHASE op changes R by writing the registers to LDS and
+// reading them back in the new layout (XOR-swizzled to spread LDS banks).
+// Loads and stores use R = the top 4 local bits, so the low local bits (the
+// contiguous low qubits) run across lanes.
+
+template <typename V>
+struct Amp16 {
+  V v[16];
+};
+
+template <int J, typename V>
+__device__ __forceinline__ void reg_1q(Amp16<V>& s, V m00, V m01, V m10, V m11) {
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    if (r & (1 << J)) continue;
+    const V x0 = s.v[r], x1 = s.v[r | (1 << J)];
+    s.v[r] = cfma2(m00, x0, m01, x1);
+    s.v[r | (1 << J)] = cfma2(m10, x0, m11, x1);
+  }
+}
+
+template <typename V>
+__device__ __forceinline__ V cdot4(const V* row, V x0, V x1, V x2, V x3) {
+  V acc = cfma2(row[0], x0, row[1], x1);
+  V acc2 = cfma2(row[2], x2, row[3], x3);
+  acc.x += acc2.x;
+  acc.y += acc2.y;
+  return acc;
+}
+
+template <int J, typename V>
+__device__ __forceinline__ void reg_mr(Amp16<V>& s, uint32_t b, typename Real<V>::T sc) {
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    if (r & (1 << J)) continue;
+    V x = b ? s.v[r | (1 << J)] : s.v[r];
+    x.x *= sc;
+    x.y *= sc;
+    s.v[r] = x;
+    s.v[r | (1 << J)].x = 0;
+    s.v[r | (1 << J)].y = 0;
+  }
+}
+
+// Negate the amplitudes whose bit r is set in `neg` by flipping IEEE sign bits.
+__device__ __forceinline__ void reg_flip_signs(Amp16<float2>& s, uint32_t neg) {
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const uint32_t m = (neg << (31 - r)) & 0x80000000u;
+    s.v[r].x = __uint_as_float(__float_as_uint(s.v[r].x) ^ m);
+    s.v[r].y = __uint_as_float(__float_as_uint(s.v[r].y) ^ m);
+  }
+}
+
+__device__ __forceinline__ void reg_flip_signs(Amp16<double2>& s, uint32_t neg) {
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const unsigned long long m = (unsigned long long)((neg >> r) & 1u) << 63;
+    s.v[r].x = __longlong_as_double((long long)((unsigned long long)__double_as_longlong(s.v[r].x) ^ m));
+    s.v[r].y = __longlong_as_double((long long)((unsigned long long)__double_as_longlong(s.v[r].y) ^ m));
+  }
+}
+
+__device__ __forceinline__ uint32_t lds_swz(uint32_t L) { return L ^ ((L >> 4) & 15u); }
+
+// Local index of register r given the thread part and the 4 register bit values.
+__device__ __forceinline__ uint32_t reg_local(uint32_t Lt, const uint32_t* rb, int r) {
+  return Lt | ((r & 1) ? rb[0] : 0) | ((r & 2) ? rb[1] : 0) | ((r & 4) ? rb[2] : 0) | ((r & 8) ? rb[3] : 0);
+}
+
+// Thread part of the local index: tid with zeros inserted at the register bits
+// (ascending).
+__device__ __forceinline__ uint32_t thread_local_part(uint32_t tid, const uint32_t* R) {
+  uint32_t L = tid;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint32_t lo = (1u << R[j]) - 1u;
+    L = ((L & ~lo) << 1) | (L & lo);
+  }
+  return L;
+}
+
+// LDS of the register kernel: tile | first 4 entries of every slot matrix | ops | slot offsets.
+template <typename V>
+__host__ __device__ inline size_t reg_lds_bytes(uint32_t k, uint32_t n_slots, uint32_t n_ops) {
+  return sizeof(V) * ((size_t(1) << k) + 4 * (size_t)n_slots) + sizeof(DOp) * (size_t)n_ops + 4 * (size_t)n_slots;
+}
+
+template <typename V>
+__global__ __launch_bounds__(256) void k_pass_reg(PassArgs<V> a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const DPass& P = a.passes[a.pass];
+  const uint32_t k = P.k;
+  const uint32_t n_slots = P.n_slots, n_ops = P.n_ops;
+  V* tile = reinterpret_cast<V*>(smem);
+  V* mats = tile + (size_t(1) << k);
+  DOp* opl = reinterpret_cast<DOp*>(mats + 4 * (size_t)n_slots);
+  uint32_t* slot_off = reinterpret_cast<uint32_t*>(opl + n_ops);
+  const uint32_t tid = threadIdx.x;
+  const uint32_t t = a.t0 + blockIdx.y;
+  const uint64_t tile_id = blockIdx.x;
+  uint64_t base = 0;
+  for (uint32_t i = 0; i < a.n - k; ++i)
+    if ((tile_id >> i) & 1) base |= 1ull << P.oq[i];
+  V* st = a.states + (uint64_t)blockIdx.y * a.N;
+  for (uint32_t s = tid; s < n_slots; s += blockDim.x) slot_off[s] = a.slot_default[P.slot_begin + s];
+  {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(a.ops + P.op_begin);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(opl);
+    for (uint32_t i = tid; i < 3 * n_ops; i += blockDim.x) dst[i] = src[i];
+  }
+  __syncthreads();
+  {
+    const uint32_t ob = a.ov_off[(uint64_t)t * a.n_passes + a.pass];
+    const uint32_t oe = a.ov_off[(uint64_t)t * a.n_passes + a.pass + 1];
+    for (uint32_t i = ob + tid; i < oe; i += blockDim.x) slot_off[a.ov[i].slot] = a.ov[i].off;
+  }
+  __syncthreads();
+  // every slot matrix has at least 4 entries; 1-qubit ops read theirs from LDS
+  for (uint32_t i = tid; i < 4 * n_slots; i += blockDim.x) mats[i] = a.pool[slot_off[i >> 2] + (i & 3)];
+  __syncthreads();
+
+  // load layout: register bits = the top 4 local bits, thread index = the low k - 4 bits
+  uint32_t R[4] = {k - 4, k - 3, k - 2, k - 1};
+  uint32_t rb[4] = {1u << R[0], 1u << R[1], 1u << R[2], 1u << R[3]};
+  uint32_t Lt = tid;
+  const uint64_t ot = tile_offset(Lt, P.tq, k);
+  uint64_t og[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) og[j] = 1ull << P.tq[R[j]];
+  Amp16<V> s;
+  const bool init = (P.flags & PASS_INIT_ZERO) != 0;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const uint64_t off = ot + ((r & 1) ? og[0] : 0) + ((r & 2) ? og[1] : 0) + ((r & 4) ? og[2] : 0) +
+                         ((r & 8) ? og[3] : 0);
+    if (init) {
+      s.v[r].x = (base == 0 && Lt == 0 && r == 0) ? 1 : 0;
+      s.v[r].y = 0;
+    } else {
+      s.v[r] = st[base + off];
+    }
+  }
+
+  const DOp* ops = opl;
+  uint32_t neg = 0;
+  const uint32_t M[4] = {0xAAAAu, 0xCCCCu, 0xF0F0u, 0xFF00u};
+  V cs;                 // pending block-uniform scalar (phases/signs of qubits outside the tile)
+  cs.x = 1;
+  cs.y = 0;
+  bool pending = false;
+  for (uint32_t o = 0; o < n_ops; ++o) {
+    const DOp op = ops[o];
+    const uint32_t type = op.type;
+    if (type == DOP_M1) {
+      const V* m = mats + 4 * (uint32_t)op.slot;
+      V m00 = m[0], m01 = m[1], m10 = m[2], m11 = m[3];
+      if (pending) {
+        // every amplitude passes through this 2x2 once: the pending scalar rides on it
+        m00 = cmul(cs, m00);
+        m01 = cmul(cs, m01);
+        m10 = cmul(cs, m10);
+        m11 = cmul(cs, m11);
+        cs.x = 1;
+        cs.y = 0;
+        pending = false;
+      }
+      const uint32_t la = op.a;
+      if (la == R[0]) reg_1q<0>(s, m00, m01, m10, m11);
+      else if (la == R[1]) reg_1q<1>(s, m00, m01, m10, m11);
+      else if (la == R[2]) reg_1q<2>(s, m00, m01, m10, m11);
+      else reg_1q<3>(s, m00, m01, m10, m11);
+    } else if (type == DOP_M2) {
+      // general 4x4 matrices go through the LDS tile (any two local bits)
+      const uint32_t off = __builtin_amdgcn_readfirstlane(slot_off[op.slot]);
+      const V* m = a.pool + off;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) tile[lds_swz(reg_local(Lt, rb, r))] = s.v[r];
+      __syncthreads();
+      const uint32_t A = 1u << op.a, B = 1u << op.b;
+      const uint32_t l1 = min(A, B) - 1, l2 = max(A, B) - 1;
+      const uint32_t nq4 = 1u << (k - 2);
+      for (uint32_t qd = tid; qd < nq4; qd += blockDim.x) {
+        uint32_t i = ((qd & ~l1) << 1) | (qd & l1);
+        i = ((i & ~l2) << 1) | (i & l2);
+        const uint32_t i0 = lds_swz(i), i1 = lds_swz(i | A), i2 = lds_swz(i | B), i3 = lds_swz(i | A | B);
+        const V x0 = tile[i0], x1 = tile[i1], x2 = tile[i2], x3 = tile[i3];
+        tile[i0] = cdot4(m, x0, x1, x2, x3);
+        tile[i1] = cdot4(m + 4, x0, x1, x2, x3);
+        tile[i2] = cdot4(m + 8, x0, x1, x2, x3);
+        tile[i3] = cdot4(m + 12, x0, x1, x2, x3);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < 16; ++r) s.v[r] = tile[lds_swz(reg_local(Lt, rb, r))];
+      __syncthreads();
+    } else if (type == DOP_DSIGN) {
+      uint32_t A1, B1, B0;
+      if (op.a == 255) {
+        A1 = ((base >> op.ga) & 1) ? 0xFFFFu : 0u;
+      } else {
+        const uint32_t la = op.a;
+        A1 = la == R[0] ? M[0] : la == R[1] ? M[1] : la == R[2] ? M[2] : la == R[3] ? M[3]
+                                                                    : (((Lt >> la) & 1) ? 0xFFFFu : 0u);
+      }
+      if (op.b == 254) {
+        B1 = 0u;
+      } else if (op.b == 255) {
+        B1 = ((base >> op.gb) & 1) ? 0xFFFFu : 0u;
+      } else {
+        const uint32_t lb = op.b;
+        B1 = lb == R[0] ? M[0] : lb == R[1] ? M[1] : lb == R[2] ? M[2] : lb == R[3] ? M[3]
+                                                                    : (((Lt >> lb) & 1) ? 0xFFFFu : 0u);
+      }
+      const uint32_t A0 = ~A1 & 0xFFFFu;
+      B0 = ~B1 & 0xFFFFu;
+      const uint32_t mk = op.slot;
+      neg ^= ((mk & 1) ? (A0 & B0) : 0u) | ((mk & 2) ? (A1 & B0) : 0u) | ((mk & 4) ? (A0 & B1) : 0u) |
+             ((mk & 8) ? (A1 & B1) : 0u);
+      const bool last = (o + 1 == n_ops) || ops[o + 1].type != DOP_DSIGN;
+      if (last) {
+        if (neg == 0xFFFFu) {
+          // a sign common to the whole tile joins the pending scalar
+          cs.x = -cs.x;
+          cs.y = -cs.y;
+          pending = true;
+        } else if (neg) {
+          reg_flip_signs(s, neg);
+        }
+        neg = 0;
+      }
+    } else if ((type == DOP_D1 && op.a == 255) || (type == DOP_D2 && op.a == 255 && op.b == 255)) {
+      // diagonal on qubits outside the tile: one phase for the whole tile, folded
+      // into the pending scalar (applied through the next 2x2 matrix or at the end)
+      const V* m = mats + 4 * (uint32_t)op.slot;
+      V ph;
+      if (type == DOP_D1) {
+        ph = ((base >> op.ga) & 1) ? m[3] : m[0];
+      } else {
+        const uint32_t i = (uint32_t)((base >> op.ga) & 1) + 2 * (uint32_t)((base >> op.gb) & 1);
+        ph = a.pool[__builtin_amdgcn_readfirstlane(slot_off[op.slot]) + 5 * i];
+      }
+      cs = cmul(cs, ph);
+      pending = true;
+    } else if (type == DOP_D1 || type == DOP_D2) {
+      const uint32_t off = __builtin_amdgcn_readfirstlane(slot_off[op.slot]);
+      const V* m = a.pool + off;
+      const bool two = type == DOP_D2;
+      const uint32_t dd = two ? 5 : 3;
+      const V d0 = m[0], d1 = m[dd], d2 = two ? m[2 * dd] : m[0], d3 = two ? m[3 * dd] : m[0];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const uint32_t L = reg_local(Lt, rb, r);
+        const uint32_t ba = op.a == 255 ? (uint32_t)((base >> op.ga) & 1) : (L >> op.a) & 1u;
+        const uint32_t bb = !two ? 0u : (op.b == 255 ? (uint32_t)((base >> op.gb) & 1) : (L >> op.b) & 1u);
+        const uint32_t i = ba + 2 * bb;
+        const V ph = i == 0 ? d0 : i == 1 ? d1 : i == 2 ? d2 : d3;
+        s.v[r] = cmul(ph, s.v[r]);
+      }
+    } else if (type == DOP_MR) {
+      const uint64_t ri = (uint64_t)t * a.n_measure + op.slot;
+      const uint32_t b = a.mr_bits[ri];
+      const typename Real<V>::T sc = (typename Real<V>::T)a.mr_norm[ri];
+      const uint32_t la = op.a;
+      if (la == R[0]) reg_mr<0>(s, b, sc);
+      else if (la == R[1]) reg_mr<1>(s, b, sc);
+      else if (la == R[2]) reg_mr<2>(s, b, sc);
+      else reg_mr<3>(s, b, sc);
+    } else if (type == DOP_PHASE) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) tile[lds_swz(reg_local(Lt, rb, r))] = s.v[r];
+      __syncthreads();
+      R[0] = op.a;
+      R[1] = op.b;
+      R[2] = op.ga;
+      R[3] = op.gb;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) rb[j] = 1u << R[j];
+      Lt = thread_local_part(tid, R);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) s.v[r] = tile[lds_swz(reg_local(Lt, rb, r))];
+      __syncthreads();
+    }
+  }
+  if (pending) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) s.v[r] = cmul(cs, s.v[r]);
+  }
+  // the program ends in the load layout again
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const uint64_t off = ot + ((r & 1) ? og[0] : 0) + ((r & 2) ? og[1] : 0) + ((r & 4) ? og[2] : 0) +
+                         ((r & 8) ? og[3] : 0);
+    st[base + off] = s.v[r];
+  }
 }
 
 // ------------------------------------------------------------ FP64 reductions
@@ -198,21 +513,49 @@ __device__ __forceinline__ double norm2(V v) {
   return (double)v.x * (double)v.x + (double)v.y * (double)v.y;
 }
 
-// partial[t * nblk + b] = sum over block b of |psi|^2 (FP64), same order as k_cdf.
+// One block handles per_block (<= 4096) consecutive amplitudes of a state:
+// |psi_x|^2 in FP64 is staged in LDS with coalesced loads (padded every 16
+// entries), then each thread sums a contiguous run sequentially and the block
+// combines the runs with wavefront shuffles and an LDS tree.  The block-sum
+// and CDF kernels share this code, so a block's total is bit-identical in both
+// and the CDF is monotone across block boundaries.
+__device__ __forceinline__ uint32_t scan_pad(uint32_t e) { return e + (e >> 4); }
+
+template <typename V, bool kWriteCdf>
+__device__ __forceinline__ void block_prob_scan(const ScanArgs<V>& a) {
+  __shared__ double sh[kScanBlock + kScanBlock / 16];
+  const uint32_t b = blockIdx.x;
+  V* st = a.states + (uint64_t)blockIdx.y * a.N;
+  const uint64_t e0 = (uint64_t)b * a.per_block;
+  const uint32_t E = a.per_block, per = a.per_thread, tid = threadIdx.x;
+  for (uint32_t e = tid; e < E; e += blockDim.x) sh[scan_pad(e)] = norm2(st[e0 + e]);
+  __syncthreads();
+  const bool active = tid * per < E;
+  double v[16];
+  double s = 0.0;
+  if (active)
+    for (uint32_t i = 0; i < per; ++i) {
+      s += sh[scan_pad(tid * per + i)];
+      v[i] = s;
+    }
+  double ex, tot;
+  block_excl_scan(s, &ex, &tot);   // ends with a barrier
+  if (!kWriteCdf) {
+    if (tid == 0) a.partial[(uint64_t)blockIdx.y * a.nblk + b] = tot;
+    return;
+  }
+  const double off = a.offs[(uint64_t)blockIdx.y * a.nblk + b];
+  if (active)
+    for (uint32_t i = 0; i < per; ++i) sh[scan_pad(tid * per + i)] = off + (ex + v[i]);
+  __syncthreads();
+  double* out = a.cdf ? a.cdf + (uint64_t)blockIdx.y * a.N : reinterpret_cast<double*>(st);
+  for (uint32_t e = tid; e < E; e += blockDim.x) out[e0 + e] = sh[scan_pad(e)];
+}
+
+// partial[t * nblk + b] = sum over block b of |psi|^2 (FP64).
 template <typename V>
 __global__ __launch_bounds__(256) void k_blocksum(ScanArgs<V> a) {
-  const uint32_t b = blockIdx.x;
-  const V* st = a.states + (uint64_t)blockIdx.y * a.N;
-  const uint64_t e0 = (uint64_t)b * a.per_block;
-  const uint32_t per = a.per_thread;
-  double s = 0.0;
-  if (threadIdx.x * per < a.per_block) {
-    const V* p = st + e0 + (uint64_t)threadIdx.x * per;
-    for (uint32_t i = 0; i < per; ++i) s += norm2(p[i]);
-  }
-  double ex, tot;
-  block_excl_scan(s, &ex, &tot);
-  if (threadIdx.x == 0) a.partial[(uint64_t)blockIdx.y * a.nblk + b] = tot;
+  block_prob_scan<V, false>(a);
 }
 
 // offs[t*nblk+b] = exclusive prefix of partial over blocks; total[t] = full sum.
@@ -239,28 +582,7 @@ __global__ __launch_bounds__(256) void k_scan_partials(double* partial, double* 
 // slot (or to `cdf` for complex128).
 template <typename V>
 __global__ __launch_bounds__(256) void k_cdf(ScanArgs<V> a) {
-  const uint32_t b = blockIdx.x;
-  V* st = a.states + (uint64_t)blockIdx.y * a.N;
-  double* out = a.cdf ? a.cdf + (uint64_t)blockIdx.y * a.N : reinterpret_cast<double*>(st);
-  const uint64_t e0 = (uint64_t)b * a.per_block;
-  const uint32_t per = a.per_thread;
-  const bool active = threadIdx.x * per < a.per_block;
-  double v[16];
-  double s = 0.0;
-  if (active) {
-    const V* p = st + e0 + (uint64_t)threadIdx.x * per;
-    for (uint32_t i = 0; i < per; ++i) {
-      s += norm2(p[i]);
-      v[i] = s;
-    }
-  }
-  double ex, tot;
-  block_excl_scan(s, &ex, &tot);
-  const double off = a.offs[(uint64_t)blockIdx.y * a.nblk + b];
-  if (active) {
-    double* q = out + e0 + (uint64_t)threadIdx.x * per;
-    for (uint32_t i = 0; i < per; ++i) q[i] = off + (ex + v[i]);
-  }
+  block_prob_scan<V, true>(a);
 }
 
 // ------------------------------------------------------------ measure-reset
@@ -423,10 +745,18 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t v, uint64_t n) {
 // -------------------------------------------------------------- launchers
 
 template <typename V>
-hipError_t launch_pass(const PassArgs<V>& a, uint32_t k, uint32_t n_slots, uint32_t batch, hipStream_t s) {
+hipError_t launch_pass(const PassArgs<V>& a, uint32_t k, uint32_t n_slots, uint32_t n_ops, uint32_t batch,
+                       hipStream_t s) {
   dim3 grid(1u << (a.n - k), batch);
-  size_t lds = sizeof(V) * (size_t(1) << k) + 4 * (size_t)n_slots;
-  hipLaunchKernelGGL(k_pass<V>, grid, dim3(256), lds, s, a);
+  if (k >= kMinRegTile && k <= 12) {
+    const size_t lds = reg_lds_bytes<V>(k, n_slots, n_ops);
+    if (lds > 65536) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(k_pass_reg<V>, grid, dim3(1u << (k - kRegBits)), lds, s, a);
+  } else {
+    const size_t lds = sizeof(V) * (size_t(1) << k) + 4 * (size_t)n_slots;
+    if (lds > 65536) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(k_pass<V>, grid, dim3(256), lds, s, a);
+  }
   return hipGetLastError();
 }
 
@@ -490,7 +820,7 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {
 }
 
 #define PTSBE_INST(V)                                                                                   \
-  template hipError_t launch_pass<V>(const PassArgs<V>&, uint32_t, uint32_t, uint32_t, hipStream_t);      \
+  template hipError_t launch_pass<V>(const PassArgs<V>&, uint32_t, uint32_t, uint32_t, uint32_t, hipStream_t); \
   template hipError_t launch_scan<V>(const ScanArgs<V>&, uint32_t, double*, hipStream_t);                 \
   template hipError_t launch_norm<V>(const ScanArgs<V>&, uint32_t, double*, hipStream_t);                 \
   template hipError_t launch_marginal<V>(const MarginalArgs<V>&, const MrDecideArgs&, uint32_t, hipStream_t); \

@@ -98,7 +98,8 @@ struct ExpArgs {
 };
 
 template <typename V>
-hipError_t launch_pass(const PassArgs<V>& a, uint32_t k, uint32_t n_slots, uint32_t batch, hipStream_t s);
+hipError_t launch_pass(const PassArgs<V>& a, uint32_t k, uint32_t n_slots, uint32_t n_ops, uint32_t batch,
+                       hipStream_t s);
 template <typename V>
 hipError_t launch_scan(const ScanArgs<V>& a, uint32_t batch, double* total, hipStream_t s);
 template <typename V>

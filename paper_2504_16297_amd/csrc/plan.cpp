@@ -303,6 +303,166 @@ struct Fuser {
 
 }  // namespace
 
+// Diagonal slots made of one fixed gate whose entries are all +-1 (CZ, Z, ...)
+// become sign ops: the kernels flip signs instead of multiplying by phases.
+static void lower_signs(const Plan& plan, Pass& ps) {
+  for (DOp& op : ps.ops) {
+    if (op.type != DOP_D1 && op.type != DOP_D2) continue;
+    const Slot& s = ps.slots[op.slot];
+    if (s.parts.size() != 1 || !s.sites.empty() || s.uses_params) continue;
+    const Step& st = plan.steps[s.parts[0].step];
+    if (st.kind != ST_GATE && st.kind != ST_P0) continue;
+    const int d = op.type == DOP_D1 ? 2 : 4;
+    uint16_t mask = 0;
+    bool ok = true;
+    for (int i = 0; i < d; ++i) {
+      cd v = st.mat[i * d + i];
+      if (v == cd(1, 0)) continue;
+      if (v == cd(-1, 0)) {
+        mask |= (uint16_t)(1u << i);
+        continue;
+      }
+      ok = false;
+    }
+    if (!ok) continue;
+    if (op.type == DOP_D1) {
+      op.b = 254;
+      op.gb = 0;
+    }
+    op.type = DOP_DSIGN;
+    op.slot = mask;
+  }
+}
+
+static bool is_diag_op(const DOp& op) { return op.type == DOP_D1 || op.type == DOP_D2 || op.type == DOP_DSIGN; }
+
+static int op_qubits(const Pass& ps, const DOp& op, int* q) {
+  switch (op.type) {
+    case DOP_M1:
+    case DOP_MR:
+      q[0] = ps.tq[op.a];
+      return 1;
+    case DOP_M2:
+      q[0] = ps.tq[op.a];
+      q[1] = ps.tq[op.b];
+      return 2;
+    case DOP_D1:
+      q[0] = op.ga;
+      return 1;
+    case DOP_D2:
+      q[0] = op.ga;
+      q[1] = op.gb;
+      return 2;
+    case DOP_DSIGN:
+      q[0] = op.ga;
+      if (op.b == 254) return 1;
+      q[1] = op.gb;
+      return 2;
+    default:
+      return 0;
+  }
+}
+
+// Order the pass's operations into register phases for the register kernel:
+// each thread holds 2^kRegBits amplitudes spanning kRegBits local bits; an
+// operation runs when its local bits are register bits (diagonal operations run
+// anywhere).  A DOP_PHASE op switches the register bits through LDS.  Any
+// topological order of the dependency graph (operations sharing a qubit, unless
+// both are diagonal) is valid; the greedy walk below keeps phases few.  The pass
+// starts and ends with the top kRegBits local bits in registers so that global
+// loads and stores keep the lowest local bits across lanes.
+static void schedule_phases(Pass& ps) {
+  const int k = ps.k;
+  if (k < (int)kMinRegTile) return;
+  const int nops = (int)ps.ops.size();
+  std::vector<std::vector<int>> preds(nops);
+  for (int i = 0; i < nops; ++i) {
+    int qi[2];
+    int ni = op_qubits(ps, ps.ops[i], qi);
+    for (int j = 0; j < i; ++j) {
+      if (is_diag_op(ps.ops[i]) && is_diag_op(ps.ops[j])) continue;
+      int qj[2];
+      int nj = op_qubits(ps, ps.ops[j], qj);
+      bool share = false;
+      for (int x = 0; x < ni; ++x)
+        for (int y = 0; y < nj; ++y) share = share || qi[x] == qj[y];
+      if (share) preds[i].push_back(j);
+    }
+  }
+  std::vector<char> done(nops, 0);
+  int ndone = 0;
+  std::vector<int> R_io;
+  for (int j = k - (int)kRegBits; j < k; ++j) R_io.push_back(j);
+  std::vector<int> R = R_io;
+  auto inR = [&](int bit) { return std::find(R.begin(), R.end(), bit) != R.end(); };
+  auto ready = [&](int i) {
+    for (int p : preds[i])
+      if (!done[p]) return false;
+    return true;
+  };
+  // register bits an operation needs (4x4 matrices go through LDS and need none)
+  auto local_bits = [&](const DOp& op, int* b) -> int {
+    if (op.type == DOP_M1 || op.type == DOP_MR) {
+      b[0] = op.a;
+      return 1;
+    }
+    return 0;
+  };
+  auto fits = [&](const DOp& op) {
+    int b[2];
+    int nb = local_bits(op, b);
+    for (int x = 0; x < nb; ++x)
+      if (!inR(b[x])) return false;
+    return true;
+  };
+  auto phase_op = [](const std::vector<int>& r) {
+    DOp op{};
+    op.type = DOP_PHASE;
+    op.a = (uint8_t)r[0];
+    op.b = (uint8_t)r[1];
+    op.ga = (uint8_t)r[2];
+    op.gb = (uint8_t)r[3];
+    return op;
+  };
+  std::vector<DOp> out;
+  while (ndone < nops) {
+    bool prog = true;
+    while (prog) {
+      prog = false;
+      for (int i = 0; i < nops; ++i)
+        if (!done[i] && ready(i) && fits(ps.ops[i])) {
+          out.push_back(ps.ops[i]);
+          done[i] = 1;
+          ++ndone;
+          prog = true;
+        }
+    }
+    if (ndone == nops) break;
+    std::vector<int> nr;
+    auto try_add = [&](const DOp& op) {
+      int b[2];
+      int nb = local_bits(op, b);
+      int add = 0;
+      for (int x = 0; x < nb; ++x)
+        if (std::find(nr.begin(), nr.end(), b[x]) == nr.end()) ++add;
+      if ((int)nr.size() + add > (int)kRegBits) return;
+      for (int x = 0; x < nb; ++x)
+        if (std::find(nr.begin(), nr.end(), b[x]) == nr.end()) nr.push_back(b[x]);
+    };
+    for (int i = 0; i < nops && (int)nr.size() < (int)kRegBits; ++i)
+      if (!done[i] && ready(i)) try_add(ps.ops[i]);
+    for (int i = 0; i < nops && (int)nr.size() < (int)kRegBits; ++i)
+      if (!done[i]) try_add(ps.ops[i]);
+    for (int j = k - 1; j >= 0 && (int)nr.size() < (int)kRegBits; --j)
+      if (std::find(nr.begin(), nr.end(), j) == nr.end()) nr.push_back(j);
+    std::sort(nr.begin(), nr.end());
+    out.push_back(phase_op(nr));
+    R = nr;
+  }
+  if (R != R_io) out.push_back(phase_op(R_io));
+  ps.ops.swap(out);
+}
+
 static ptsbe_status schedule(Plan& plan) {
   const int n = plan.n;
   const int k = std::min(n, plan.tile_bits);
@@ -400,6 +560,8 @@ static ptsbe_status schedule(Plan& plan) {
     Fuser fz(plan, ps);
     for (int si : taken) fz.take(si);
     fz.finish();
+    lower_signs(plan, ps);
+    schedule_phases(ps);
     ExecStep e;
     e.pass = (int)plan.passes.size() - 1;
     plan.exec.push_back(e);
@@ -439,8 +601,8 @@ ptsbe_status build_plan(const ptsbe_circuit* c, const ptsbe_noise_model* nm, con
   if (P.precision != PTSBE_C64 && P.precision != PTSBE_C128) return fail(PTSBE_E_ARG, "bad precision");
   int tb = (P.precision == PTSBE_C64) ? 12 : 11;
   if (o && o->tile_qubits) {
-    if (o->tile_qubits < 4 || o->tile_qubits > (uint32_t)kMaxTileBits)
-      return fail(PTSBE_E_ARG, "tile_qubits must be in 4..13");
+    if (o->tile_qubits < 4 || o->tile_qubits > 12)
+      return fail(PTSBE_E_ARG, "tile_qubits must be in 4..12");
     tb = (int)o->tile_qubits;
     if (P.precision == PTSBE_C128 && tb > 12) return fail(PTSBE_E_ARG, "tile_qubits <= 12 for complex128");
   }

@@ -139,7 +139,8 @@ ptsbe_status run_typed(const Plan& P, TrajSet& ts, const ptsbe_run_opts& o, uint
       if (ex.pass >= 0) {
         const Pass& ps = P.passes[ex.pass];
         pa.pass = (uint32_t)ex.pass;
-        CK(launch_pass<V>(pa, (uint32_t)ps.k, (uint32_t)ps.slots.size(), bb, s), "tile pass");
+        CK(launch_pass<V>(pa, (uint32_t)ps.k, (uint32_t)ps.slots.size(), (uint32_t)ps.ops.size(), bb, s),
+           "tile pass");
         CK(tm.mark(T_PASS), "timer");
         if (o.timing) {
           o.timing[1] += 1;

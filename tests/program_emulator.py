@@ -16,10 +16,10 @@ from paper_2504_16297_amd import _lib as L
 PASS_DT = np.dtype([("k", "<u4"), ("n_ops", "<u4"), ("op_begin", "<u4"), ("slot_begin", "<u4"),
                     ("n_slots", "<u4"), ("flags", "<u4"), ("tq", "u1", 16), ("oq", "u1", 48)])
 OP_DT = np.dtype([("type", "u1"), ("a", "u1"), ("b", "u1"), ("ga", "u1"), ("gb", "u1"), ("pad0", "u1"),
-                  ("slot", "<u2"), ("pad1", "<u2")])
+                  ("pad1", "u1"), ("pad2", "u1"), ("slot", "<u2"), ("pad3", "<u2")])
 OV_DT = np.dtype([("slot", "<u4"), ("off", "<u4")])
 EXEC_DT = np.dtype([("pass", "<u4"), ("nq", "<u4"), ("q", "<u4", 16), ("idx", "<u4", 16)])
-M1, M2, D1, D2, MR = 1, 2, 3, 4, 5
+M1, M2, D1, D2, MR, DSIGN, PHASE = 1, 2, 3, 4, 5, 6, 7
 
 
 def export_tables(ts, params=None, sort_chunk=0):
@@ -98,9 +98,15 @@ def run_program(tables, n, B, mr_tol=1e-6):
                     T[0, 0] = 1.0
                 else:
                     T = psi[idx].copy()
+                reg = set(range(k - 4, k)) if k >= 6 else None   # register bits of the register kernel
                 for op in ops[ps["op_begin"]:ps["op_begin"] + ps["n_ops"]]:
                     ty = int(op["type"])
                     pool = tables["pool"]
+                    if reg is not None and ty in (M1, MR):
+                        assert int(op["a"]) in reg, "operation outside the register bits"
+                    if ty == PHASE:
+                        reg = {int(op["a"]), int(op["b"]), int(op["ga"]), int(op["gb"])}
+                        assert len(reg) == 4 and max(reg) < k
                     if ty == M1:
                         m = pool[slot[op["slot"]]:slot[op["slot"]] + 4].reshape(2, 2)
                         _apply_1q(T, int(op["a"]), m)
@@ -123,6 +129,13 @@ def run_program(tables, n, B, mr_tol=1e-6):
                         ga = ((idx >> int(op["ga"])) & 1)
                         gb = ((idx >> int(op["gb"])) & 1) if ty == D2 else 0
                         T *= m[(ga + 2 * gb) * dd]
+                    elif ty == DSIGN:
+                        ga = ((idx >> int(op["ga"])) & 1)
+                        gb = 0 if int(op["b"]) == 254 else ((idx >> int(op["gb"])) & 1)
+                        neg = (int(op["slot"]) >> (ga + 2 * gb)) & 1
+                        T *= np.where(neg == 1, -1.0, 1.0)
+                    elif ty == PHASE:
+                        pass
                     elif ty == MR:
                         r = int(op["slot"])
                         b = bits[r]
@@ -133,6 +146,8 @@ def run_program(tables, n, B, mr_tol=1e-6):
                         v[:, :, 1, :] = 0
                     else:
                         raise ValueError(ty)
+                if reg is not None:
+                    assert reg == set(range(k - 4, k)), "pass must end in the load/store register layout"
                 psi = np.zeros(N, dtype=np.complex128) if ps["flags"] & 1 else psi
                 psi[idx] = T
             else:
