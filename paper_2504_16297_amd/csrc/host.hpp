@@ -87,6 +87,7 @@ struct Plan {
   int n = 0;
   int precision = PTSBE_C64;
   int tile_bits = 12;
+  int min_fill = 3;            // phase scheduler: fewest 2x2 matrices worth a partial wave
   int n_params = 0;
   int n_measure = 0;
   std::vector<Channel> channels;

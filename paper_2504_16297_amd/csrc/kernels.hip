@@ -99,7 +99,7 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs<V> a) {
   for (uint32_t o = 0; o < P.n_ops; ++o) {
     const DOp op = ops[o];
     if (op.type == DOP_M1) {
-      const V* m = a.pool + slot_off[op.slot];
+      const V* m = a.pool + slot_off[op.slot[0]];
       const V m00 = m[0], m01 = m[1], m10 = m[2], m11 = m[3];
       const uint32_t bit = 1u << op.a, lo = bit - 1;
       for (uint32_t pr = tid; pr < nt / 2; pr += blockDim.x) {
@@ -110,7 +110,7 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs<V> a) {
         tile[i1] = cfma2(m10, x0, m11, x1);
       }
     } else if (op.type == DOP_M2) {
-      const V* m = a.pool + slot_off[op.slot];
+      const V* m = a.pool + slot_off[op.slot[0]];
       const uint32_t A = 1u << op.a, B = 1u << op.b;
       const uint32_t l1 = min(A, B) - 1, l2 = max(A, B) - 1;
       for (uint32_t qd = tid; qd < nt / 4; qd += blockDim.x) {
@@ -130,7 +130,7 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs<V> a) {
         }
       }
     } else if (op.type == DOP_D1 || op.type == DOP_D2) {
-      const V* m = a.pool + slot_off[op.slot];
+      const V* m = a.pool + slot_off[op.slot[0]];
       const bool two = op.type == DOP_D2;
       const uint32_t dd = two ? 5 : 3;  // stride of the diagonal in a 4x4 / 2x2 row-major matrix
       const uint32_t fa = op.a == 255 ? (uint32_t)((base >> op.ga) & 1) : 0;
@@ -147,7 +147,7 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs<V> a) {
       for (uint32_t L = tid; L < nt; L += blockDim.x) {
         const uint32_t ba = op.a == 255 ? fa : (L >> op.a) & 1u;
         const uint32_t bb = op.b == 254 ? 0u : (op.b == 255 ? fb : (L >> op.b) & 1u);
-        if ((op.slot >> (ba + 2 * bb)) & 1u) {
+        if ((op.slot[0] >> (ba + 2 * bb)) & 1u) {
           V v = tile[L];
           v.x = -v.x;
           v.y = -v.y;
@@ -155,7 +155,7 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs<V> a) {
         }
       }
     } else if (op.type == DOP_MR) {
-      const uint64_t ri = (uint64_t)t * a.n_measure + op.slot;
+      const uint64_t ri = (uint64_t)t * a.n_measure + op.slot[0];
       const uint32_t b = a.mr_bits[ri];
       const typename Real<V>::T sc = (typename Real<V>::T)a.mr_norm[ri];
       const uint32_t bit = 1u << op.a, lo = bit - 1;
@@ -210,6 +210,14 @@ __device__ __forceinline__ V cdot4(const V* row, V x0, V x1, V x2, V x3) {
   acc.x += acc2.x;
   acc.y += acc2.y;
   return acc;
+}
+
+template <int J, typename V>
+__device__ __forceinline__ void reg_1q_lds(Amp16<V>& s, const V* m) {
+  // keep the matrix loads next to their use (hoisting them raises register pressure)
+  asm volatile("" ::: "memory");
+  const V m00 = m[0], m01 = m[1], m10 = m[2], m11 = m[3];
+  reg_1q<J>(s, m00, m01, m10, m11);
 }
 
 template <int J, typename V>
@@ -291,7 +299,7 @@ __global__ __launch_bounds__(256) void k_pass_reg(PassArgs<V> a) {
   {
     const uint32_t* src = reinterpret_cast<const uint32_t*>(a.ops + P.op_begin);
     uint32_t* dst = reinterpret_cast<uint32_t*>(opl);
-    for (uint32_t i = tid; i < 3 * n_ops; i += blockDim.x) dst[i] = src[i];
+    for (uint32_t i = tid; i < 4 * n_ops; i += blockDim.x) dst[i] = src[i];
   }
   __syncthreads();
   {
@@ -336,27 +344,27 @@ __global__ __launch_bounds__(256) void k_pass_reg(PassArgs<V> a) {
   for (uint32_t o = 0; o < n_ops; ++o) {
     const DOp op = ops[o];
     const uint32_t type = op.type;
-    if (type == DOP_M1) {
-      const V* m = mats + 4 * (uint32_t)op.slot;
-      V m00 = m[0], m01 = m[1], m10 = m[2], m11 = m[3];
+    if (type == DOP_M1G) {
+      const uint32_t mk = op.mask;
       if (pending) {
-        // every amplitude passes through this 2x2 once: the pending scalar rides on it
-        m00 = cmul(cs, m00);
-        m01 = cmul(cs, m01);
-        m10 = cmul(cs, m10);
-        m11 = cmul(cs, m11);
+        // the pending scalar rides on the group's first matrix: fold it into
+        // that slot's LDS copy (every thread reads before anyone writes)
+        const uint32_t s0 = (mk & 1u) ? op.slot[0] : (mk & 2u) ? op.slot[1] : (mk & 4u) ? op.slot[2] : op.slot[3];
+        V* m = mats + 4u * s0;
+        if (tid < 4) m[tid] = cmul(cs, m[tid]);
+        __syncthreads();
         cs.x = 1;
         cs.y = 0;
         pending = false;
       }
-      const uint32_t la = op.a;
-      if (la == R[0]) reg_1q<0>(s, m00, m01, m10, m11);
-      else if (la == R[1]) reg_1q<1>(s, m00, m01, m10, m11);
-      else if (la == R[2]) reg_1q<2>(s, m00, m01, m10, m11);
-      else reg_1q<3>(s, m00, m01, m10, m11);
+      // all four positions, idle ones through the identity slot: one straight line
+      reg_1q_lds<0>(s, mats + 4u * (uint32_t)op.slot[0]);
+      reg_1q_lds<1>(s, mats + 4u * (uint32_t)op.slot[1]);
+      reg_1q_lds<2>(s, mats + 4u * (uint32_t)op.slot[2]);
+      reg_1q_lds<3>(s, mats + 4u * (uint32_t)op.slot[3]);
     } else if (type == DOP_M2) {
       // general 4x4 matrices go through the LDS tile (any two local bits)
-      const uint32_t off = __builtin_amdgcn_readfirstlane(slot_off[op.slot]);
+      const uint32_t off = __builtin_amdgcn_readfirstlane(slot_off[op.slot[0]]);
       const V* m = a.pool + off;
 #pragma unroll
       for (int r = 0; r < 16; ++r) tile[lds_swz(reg_local(Lt, rb, r))] = s.v[r];
@@ -398,36 +406,34 @@ __global__ __launch_bounds__(256) void k_pass_reg(PassArgs<V> a) {
       }
       const uint32_t A0 = ~A1 & 0xFFFFu;
       B0 = ~B1 & 0xFFFFu;
-      const uint32_t mk = op.slot;
+      const uint32_t mk = op.slot[0];
       neg ^= ((mk & 1) ? (A0 & B0) : 0u) | ((mk & 2) ? (A1 & B0) : 0u) | ((mk & 4) ? (A0 & B1) : 0u) |
              ((mk & 8) ? (A1 & B1) : 0u);
-      const bool last = (o + 1 == n_ops) || ops[o + 1].type != DOP_DSIGN;
-      if (last) {
-        if (neg == 0xFFFFu) {
-          // a sign common to the whole tile joins the pending scalar
-          cs.x = -cs.x;
-          cs.y = -cs.y;
-          pending = true;
-        } else if (neg) {
-          reg_flip_signs(s, neg);
-        }
+    } else if (type == DOP_SFLIP) {
+      if (neg == 0xFFFFu) {
+        // a sign common to the whole tile joins the pending scalar
+        cs.x = -cs.x;
+        cs.y = -cs.y;
+        pending = true;
         neg = 0;
       }
+      reg_flip_signs(s, neg);
+      neg = 0;
     } else if ((type == DOP_D1 && op.a == 255) || (type == DOP_D2 && op.a == 255 && op.b == 255)) {
       // diagonal on qubits outside the tile: one phase for the whole tile, folded
       // into the pending scalar (applied through the next 2x2 matrix or at the end)
-      const V* m = mats + 4 * (uint32_t)op.slot;
+      const V* m = mats + 4 * (uint32_t)op.slot[0];
       V ph;
       if (type == DOP_D1) {
         ph = ((base >> op.ga) & 1) ? m[3] : m[0];
       } else {
         const uint32_t i = (uint32_t)((base >> op.ga) & 1) + 2 * (uint32_t)((base >> op.gb) & 1);
-        ph = a.pool[__builtin_amdgcn_readfirstlane(slot_off[op.slot]) + 5 * i];
+        ph = a.pool[__builtin_amdgcn_readfirstlane(slot_off[op.slot[0]]) + 5 * i];
       }
       cs = cmul(cs, ph);
       pending = true;
     } else if (type == DOP_D1 || type == DOP_D2) {
-      const uint32_t off = __builtin_amdgcn_readfirstlane(slot_off[op.slot]);
+      const uint32_t off = __builtin_amdgcn_readfirstlane(slot_off[op.slot[0]]);
       const V* m = a.pool + off;
       const bool two = type == DOP_D2;
       const uint32_t dd = two ? 5 : 3;
@@ -442,7 +448,7 @@ __global__ __launch_bounds__(256) void k_pass_reg(PassArgs<V> a) {
         s.v[r] = cmul(ph, s.v[r]);
       }
     } else if (type == DOP_MR) {
-      const uint64_t ri = (uint64_t)t * a.n_measure + op.slot;
+      const uint64_t ri = (uint64_t)t * a.n_measure + op.slot[0];
       const uint32_t b = a.mr_bits[ri];
       const typename Real<V>::T sc = (typename Real<V>::T)a.mr_norm[ri];
       const uint32_t la = op.a;

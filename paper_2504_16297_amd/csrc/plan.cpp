@@ -235,7 +235,7 @@ struct Fuser {
     Slot& s = pass.slots[slot];
     DOp op{};
     op.type = s.type;
-    op.slot = (uint16_t)slot;
+    op.slot[0] = (uint16_t)slot;
     if (s.type == DOP_M1) {
       op.a = (uint8_t)local[s.q[0]];
     } else if (s.type == DOP_M2) {
@@ -272,7 +272,7 @@ struct Fuser {
       DOp op{};
       op.type = DOP_MR;
       op.a = (uint8_t)local[st.q[0]];
-      op.slot = (uint16_t)st.mr;
+      op.slot[0] = (uint16_t)st.mr;
       pass.ops.push_back(op);
       return;
     }
@@ -308,7 +308,7 @@ struct Fuser {
 static void lower_signs(const Plan& plan, Pass& ps) {
   for (DOp& op : ps.ops) {
     if (op.type != DOP_D1 && op.type != DOP_D2) continue;
-    const Slot& s = ps.slots[op.slot];
+    const Slot& s = ps.slots[op.slot[0]];
     if (s.parts.size() != 1 || !s.sites.empty() || s.uses_params) continue;
     const Step& st = plan.steps[s.parts[0].step];
     if (st.kind != ST_GATE && st.kind != ST_P0) continue;
@@ -330,7 +330,7 @@ static void lower_signs(const Plan& plan, Pass& ps) {
       op.gb = 0;
     }
     op.type = DOP_DSIGN;
-    op.slot = mask;
+    op.slot[0] = mask;
   }
 }
 
@@ -371,10 +371,17 @@ static int op_qubits(const Pass& ps, const DOp& op, int* q) {
 // both are diagonal) is valid; the greedy walk below keeps phases few.  The pass
 // starts and ends with the top kRegBits local bits in registers so that global
 // loads and stores keep the lowest local bits across lanes.
-static void schedule_phases(Pass& ps) {
+static void schedule_phases(Pass& ps, int min_fill) {
   const int k = ps.k;
   if (k < (int)kMinRegTile) return;
   const int nops = (int)ps.ops.size();
+  const int identity_slot = (int)ps.slots.size();  // 2x2 identity for idle register positions
+  {
+    Slot idn;
+    idn.type = DOP_M1;
+    idn.q[0] = idn.q[1] = -1;
+    ps.slots.push_back(idn);
+  }
   std::vector<std::vector<int>> preds(nops);
   for (int i = 0; i < nops; ++i) {
     int qi[2];
@@ -426,16 +433,73 @@ static void schedule_phases(Pass& ps) {
   };
   std::vector<DOp> out;
   while (ndone < nops) {
-    bool prog = true;
-    while (prog) {
-      prog = false;
+    // Waves: every operation ready at the start of a wave is independent of the
+    // others in it.  The wave's 2x2 matrices (at most one per register position)
+    // become one M1G op, run as straight-line code on all 16 amplitudes.
+    while (true) {
+      std::vector<int> wave;
       for (int i = 0; i < nops; ++i)
-        if (!done[i] && ready(i) && fits(ps.ops[i])) {
+        if (!done[i] && ready(i) && fits(ps.ops[i])) wave.push_back(i);
+      if (wave.empty()) break;
+      // A wave with few 2x2 matrices leaves register positions idle; when other
+      // tile bits hold at least min_fill ready ones, emit only its diagonal ops
+      // and switch registers instead.
+      int m1_here = 0, m1_other = 0;
+      for (int i = 0; i < nops; ++i)
+        if (!done[i] && ready(i) && ps.ops[i].type == DOP_M1) (fits(ps.ops[i]) ? m1_here : m1_other) += 1;
+      if (m1_here > 0 && m1_here < min_fill && std::min(m1_other, (int)kRegBits) >= min_fill) {
+        std::vector<int> diag;
+        bool any_sign = false;
+        for (int i : wave)
+          if (is_diag_op(ps.ops[i])) diag.push_back(i);
+        for (int i : diag) {
           out.push_back(ps.ops[i]);
+          any_sign = any_sign || ps.ops[i].type == DOP_DSIGN;
           done[i] = 1;
           ++ndone;
-          prog = true;
         }
+        if (any_sign) {
+          DOp f{};
+          f.type = DOP_SFLIP;
+          out.push_back(f);
+        }
+        if (diag.empty()) break;
+        continue;
+      }
+      DOp g{};
+      g.type = DOP_M1G;
+      for (int i : wave) {
+        const DOp& op = ps.ops[i];
+        if (op.type == DOP_M1) {
+          const int j = (int)(std::find(R.begin(), R.end(), (int)op.a) - R.begin());
+          g.mask |= (uint8_t)(1u << j);
+          g.slot[j] = op.slot[0];
+        }
+      }
+      if (g.mask) {
+        // idle positions get the identity: the kernel runs all four as one straight line
+        for (int j = 0; j < (int)kRegBits; ++j)
+          if (!((g.mask >> j) & 1)) g.slot[j] = (uint16_t)identity_slot;
+        out.push_back(g);
+      }
+      // sign diagonals: accumulated, then applied once by a DOP_SFLIP
+      bool any_sign = false;
+      for (int i : wave)
+        if (ps.ops[i].type == DOP_DSIGN) {
+          out.push_back(ps.ops[i]);
+          any_sign = true;
+        }
+      if (any_sign) {
+        DOp f{};
+        f.type = DOP_SFLIP;
+        out.push_back(f);
+      }
+      for (int i : wave)
+        if (ps.ops[i].type != DOP_M1 && ps.ops[i].type != DOP_DSIGN) out.push_back(ps.ops[i]);
+      for (int i : wave) {
+        done[i] = 1;
+        ++ndone;
+      }
     }
     if (ndone == nops) break;
     std::vector<int> nr;
@@ -561,7 +625,7 @@ static ptsbe_status schedule(Plan& plan) {
     for (int si : taken) fz.take(si);
     fz.finish();
     lower_signs(plan, ps);
-    schedule_phases(ps);
+    schedule_phases(ps, plan.min_fill);
     ExecStep e;
     e.pass = (int)plan.passes.size() - 1;
     plan.exec.push_back(e);
@@ -607,6 +671,8 @@ ptsbe_status build_plan(const ptsbe_circuit* c, const ptsbe_noise_model* nm, con
     if (P.precision == PTSBE_C128 && tb > 12) return fail(PTSBE_E_ARG, "tile_qubits <= 12 for complex128");
   }
   P.tile_bits = tb;
+  // flags bits 0..2: phase-scheduler fill threshold (0 = default 3)
+  if (o && (o->flags & 7u)) P.min_fill = (int)(o->flags & 7u);
   // channels
   uint32_t n_ch = nm ? nm->n_channels : 0;
   if (n_ch && !nm->channels) return fail(PTSBE_E_ARG, "null channel array");

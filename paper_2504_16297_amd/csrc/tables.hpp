@@ -21,20 +21,24 @@ enum DOpType : uint8_t {
   DOP_DSIGN = 6,  // +-1 diagonal on (ga, gb): negate where bit (ba + 2 bb) of `slot` is set;
                   // a / b are the local bits of ga / gb or 255 (b = 254: one-qubit sign on ga)
   DOP_PHASE = 7,  // register kernel: new set of 4 register bits (a, b, ga, gb), via an LDS transpose
+  DOP_M1G = 8,    // register kernel: 2x2 matrix slot[j] on register position j = 0..3 (the
+                  // ascending register bits); `mask` marks the non-identity positions
+  DOP_SFLIP = 9,  // register kernel: apply the signs accumulated by the preceding DOP_DSIGNs
 };
 
 constexpr uint32_t kRegBits = 4;      // amplitudes per thread = 2^kRegBits in the register kernel
 constexpr uint32_t kMinRegTile = 6;   // smallest tile run by the register kernel (one wavefront)
 
-struct DOp {             // 12 bytes: three 32-bit words
+struct DOp {             // 16 bytes: four 32-bit words
   uint8_t type;
   uint8_t a, b;        // local tile bits (M1, M2, MR); for D1/D2 the local bit of ga/gb or 255
   uint8_t ga, gb;      // global qubits (D1, D2)
-  uint8_t pad0, pad1, pad2;
-  uint16_t slot;       // matrix slot within the pass (M1, M2, D1, D2); record index for MR
-  uint16_t pad3;
+  uint8_t mask;        // M1G: register positions present
+  uint8_t pad0, pad1;
+  uint16_t slot[4];    // slot[0]: matrix slot (M1, M2, D1, D2), sign mask (DSIGN), record index
+                       // (MR); M1G: slot of register position j
 };
-static_assert(sizeof(DOp) == 12, "DOp layout");
+static_assert(sizeof(DOp) == 16, "DOp layout");
 
 enum DPassFlags : uint32_t {
   PASS_INIT_ZERO = 1,  // the tile starts from |0...0> instead of being loaded

@@ -15,11 +15,11 @@ from paper_2504_16297_amd import _lib as L
 
 PASS_DT = np.dtype([("k", "<u4"), ("n_ops", "<u4"), ("op_begin", "<u4"), ("slot_begin", "<u4"),
                     ("n_slots", "<u4"), ("flags", "<u4"), ("tq", "u1", 16), ("oq", "u1", 48)])
-OP_DT = np.dtype([("type", "u1"), ("a", "u1"), ("b", "u1"), ("ga", "u1"), ("gb", "u1"), ("pad0", "u1"),
-                  ("pad1", "u1"), ("pad2", "u1"), ("slot", "<u2"), ("pad3", "<u2")])
+OP_DT = np.dtype([("type", "u1"), ("a", "u1"), ("b", "u1"), ("ga", "u1"), ("gb", "u1"), ("mask", "u1"),
+                  ("pad0", "u1"), ("pad1", "u1"), ("slots", "<u2", 4)])
 OV_DT = np.dtype([("slot", "<u4"), ("off", "<u4")])
 EXEC_DT = np.dtype([("pass", "<u4"), ("nq", "<u4"), ("q", "<u4", 16), ("idx", "<u4", 16)])
-M1, M2, D1, D2, MR, DSIGN, PHASE = 1, 2, 3, 4, 5, 6, 7
+M1, M2, D1, D2, MR, DSIGN, PHASE, M1G, SFLIP = 1, 2, 3, 4, 5, 6, 7, 8, 9
 
 
 def export_tables(ts, params=None, sort_chunk=0):
@@ -107,11 +107,22 @@ def run_program(tables, n, B, mr_tol=1e-6):
                     if ty == PHASE:
                         reg = {int(op["a"]), int(op["b"]), int(op["ga"]), int(op["gb"])}
                         assert len(reg) == 4 and max(reg) < k
-                    if ty == M1:
-                        m = pool[slot[op["slot"]]:slot[op["slot"]] + 4].reshape(2, 2)
+                    if ty == M1G:
+                        assert reg is not None, "grouped 2x2 op outside the register kernel"
+                        pos = sorted(reg)
+                        for j in range(4):            # idle positions carry the identity slot
+                            sj = slot[int(op["slots"][j])]
+                            m = pool[sj:sj + 4].reshape(2, 2)
+                            if not (int(op["mask"]) >> j) & 1:
+                                assert np.array_equal(m, np.eye(2)), "idle position without identity"
+                            _apply_1q(T, pos[j], m)
+                    elif ty == SFLIP:
+                        pass
+                    elif ty == M1:
+                        m = pool[slot[op["slots"][0]]:slot[op["slots"][0]] + 4].reshape(2, 2)
                         _apply_1q(T, int(op["a"]), m)
                     elif ty == M2:
-                        m = pool[slot[op["slot"]]:slot[op["slot"]] + 16].reshape(4, 4)
+                        m = pool[slot[op["slots"][0]]:slot[op["slots"][0]] + 16].reshape(4, 4)
                         a, b = int(op["a"]), int(op["b"])
                         ba = (Lidx >> a) & 1
                         bb = (Lidx >> b) & 1
@@ -125,19 +136,19 @@ def run_program(tables, n, B, mr_tol=1e-6):
                         del r
                     elif ty in (D1, D2):
                         dd = 3 if ty == D1 else 5
-                        m = pool[slot[op["slot"]]:slot[op["slot"]] + (4 if ty == D1 else 16)]
+                        m = pool[slot[op["slots"][0]]:slot[op["slots"][0]] + (4 if ty == D1 else 16)]
                         ga = ((idx >> int(op["ga"])) & 1)
                         gb = ((idx >> int(op["gb"])) & 1) if ty == D2 else 0
                         T *= m[(ga + 2 * gb) * dd]
                     elif ty == DSIGN:
                         ga = ((idx >> int(op["ga"])) & 1)
                         gb = 0 if int(op["b"]) == 254 else ((idx >> int(op["gb"])) & 1)
-                        neg = (int(op["slot"]) >> (ga + 2 * gb)) & 1
+                        neg = (int(op["slots"][0]) >> (ga + 2 * gb)) & 1
                         T *= np.where(neg == 1, -1.0, 1.0)
                     elif ty == PHASE:
                         pass
                     elif ty == MR:
-                        r = int(op["slot"])
+                        r = int(op["slots"][0])
                         b = bits[r]
                         a = int(op["a"])
                         v = T.reshape(T.shape[0], nt >> (a + 1), 2, 1 << a)
