@@ -218,7 +218,8 @@ void ptsbe_trajset_destroy(ptsbe_trajset_t ts);
 enum {
     PTSBE_RUN_SHOTS = 0,        /* prepare, then sample m_alpha shots per trajectory */
     PTSBE_RUN_STATES = 1,       /* prepare, normalise, copy states to d_state_out */
-    PTSBE_RUN_EXPECTATION = 2   /* prepare, then <O>_alpha per trajectory (diagonal O) */
+    PTSBE_RUN_EXPECTATION = 2,  /* prepare, then <O>_alpha per trajectory (diagonal O) */
+    PTSBE_RUN_ADJOINT = 3       /* workspace query only: ptsbe_adjoint_grad (uses params, max_batch) */
 };
 
 typedef struct {
@@ -243,7 +244,9 @@ typedef struct {
                                    pass, 1 x for the initialising pass), [7] sampler launches */
 } ptsbe_run_opts;
 
-/* Device workspace in bytes needed by ptsbe_run_batch / ptsbe_adjoint_grad. */
+/* Device workspace in bytes needed by ptsbe_run_batch, or with
+ * opts->mode == PTSBE_RUN_ADJOINT by ptsbe_adjoint_grad (max_batch bounds the
+ * trajectories whose psi and lambda are resident together; 0 = all). */
 ptsbe_status ptsbe_workspace_size(ptsbe_plan_t plan, ptsbe_trajset_t ts, const ptsbe_run_opts* opts,
                                   size_t* bytes);
 
@@ -270,6 +273,16 @@ ptsbe_status ptsbe_run_batch(ptsbe_plan_t plan, ptsbe_trajset_t ts, const ptsbe_
 ptsbe_status ptsbe_trajset_tables(ptsbe_trajset_t ts, const double* params, uint32_t sort_chunk, void* out,
                                   size_t* bytes, uint64_t* offsets);
 
+/* Inspection of the adjoint gradient's reverse-sweep program: the same table
+ * blob and 16 offsets as ptsbe_trajset_tables, with DOT operations (type 10,
+ * local pair bit in `a`, generator 1/2/3 = X/Y/Z in `b`, gradient-term index
+ * slot[0] | slot[1] << 16).  *n_dot receives the number of gradient terms and
+ * dot_param (optional, *n_dot entries) the parameter index of each.
+ * PTSBE_E_UNSUPPORTED if the plan has no adjoint program. */
+ptsbe_status ptsbe_trajset_adjoint_tables(ptsbe_trajset_t ts, const double* params, void* out,
+                                          size_t* bytes, uint64_t* offsets, uint32_t* n_dot,
+                                          uint32_t* dot_param);
+
 /* Wait for `stream` and read the device status word of a workspace last used
  * by ptsbe_run_batch: PTSBE_OK or PTSBE_E_NONDET_MEASURE. */
 ptsbe_status ptsbe_run_status(ptsbe_plan_t plan, const void* d_ws, void* stream);
@@ -278,8 +291,14 @@ ptsbe_status ptsbe_run_status(ptsbe_plan_t plan, const void* d_ws, void* stream)
  * w_alpha = count_alpha / sum count (for unitary-mixture noise w does not depend
  * on theta): forward preparation, lambda = O psi, then a reverse sweep that
  * un-applies each operation on psi and lambda and accumulates
- * 2 Re <lambda| dG/dtheta |psi> in FP64.  O = sum_t coef_t Z-string(zmask_t).
- * d_params: device FP64 parameters; d_expval: 1 FP64; d_grad: n_params FP64. */
+ * 2 Re <lambda| dG/dtheta |psi> in FP64 per (trajectory, tile), reduced in a
+ * fixed order (deterministic).  O = sum_t coef_t Z-string(zmask_t), 1..64 terms.
+ * params: host FP64 array of n_params values; d_expval: device, 1 FP64 (E);
+ * d_grad: device, n_params FP64.  The workspace (256-byte aligned, size from
+ * ptsbe_workspace_size with mode PTSBE_RUN_ADJOINT) is split into batches of
+ * trajectories that fit it.  Errors: PTSBE_E_UNSUPPORTED if the plan has no
+ * parameters or holds measure-reset / projection steps; PTSBE_E_OOM if not even
+ * one trajectory fits the workspace.  The call only enqueues work on `stream`. */
 ptsbe_status ptsbe_adjoint_grad(ptsbe_plan_t plan, ptsbe_trajset_t ts, const double* params,
                                 const double* obs_coef, const uint64_t* obs_zmask, uint32_t n_terms,
                                 void* d_ws, size_t ws_bytes, double* d_expval, double* d_grad,

@@ -38,6 +38,16 @@ def std_gate(name, params=()):
 
 
 def std_channel(ch):
+    """(interleaved complex128 Kraus operators, nq, n_kraus) of a channel given by
+    name, or by an explicit ``{"kraus": [K_0, K_1, ...]}`` list of matrices."""
+    if "kraus" in ch:
+        ks = [np.asarray(k, dtype=np.complex128) for k in ch["kraus"]]
+        d = ks[0].shape[0]
+        nq = d.bit_length() - 1
+        flat = np.concatenate([k.reshape(-1) for k in ks])
+        out = np.empty(2 * flat.size, dtype=np.float64)
+        out[0::2], out[1::2] = flat.real, flat.imag
+        return out, nq, len(ks)
     name = ch["name"]
     if name in ("depolarizing", "xflip"):
         p = [ch["p"]]
@@ -258,8 +268,10 @@ def _run_opts(mode, seed, cfg, sort_chunk, max_batch, uniforms, params, state_ou
 
 
 def ptsbe_workspace_size(plan, ts, mode="shots", sort_chunk=0, max_batch=0, params=None):
-    m = {"shots": L.RUN_SHOTS, "states": L.RUN_STATES, "expectation": L.RUN_EXPECTATION}[mode]
-    o, keep = _run_opts(m, 0, 0, sort_chunk, max_batch, None, params, None, None, None)
+    m = {"shots": L.RUN_SHOTS, "states": L.RUN_STATES, "expectation": L.RUN_EXPECTATION,
+         "adjoint": L.RUN_ADJOINT}[mode]
+    pa = None if params is None else np.ascontiguousarray(params, dtype=np.float64)
+    o, keep = _run_opts(m, 0, 0, sort_chunk, max_batch, None, pa, None, None, None)
     n = C.c_size_t()
     check(lib().ptsbe_workspace_size(plan.handle, ts.handle, C.byref(o), C.byref(n)))
     return n.value
@@ -335,19 +347,19 @@ def ptsbe_run_status(plan, workspace, stream=None):
     check(lib().ptsbe_run_status(plan.handle, C.c_void_p(workspace.data_ptr()), _stream(torch, stream)))
 
 
-def ptsbe_adjoint_grad(plan, ts, params, observable, workspace=None, stream=None):
-    """E and dE/dparams (FP64 device tensors) of the probability-weighted ensemble."""
+def ptsbe_adjoint_grad(plan, ts, params, observable, workspace=None, max_batch=0, stream=None):
+    """Adjoint gradient of E(theta) = sum_a w_a <psi_a|O|psi_a> over the trajectory
+    set (w_a = count_a / sum count).  ``observable``: list of (coef, qubits) Z-strings.
+    Returns (E, grad) as FP64 device tensors of shapes (1,) and (n_params,)."""
     import torch
     dev = torch.device("cuda")
     pa = np.ascontiguousarray(params, dtype=np.float64)
     coef = np.asarray([c for c, _ in observable], dtype=np.float64)
     zm = np.asarray([sum(1 << int(q) for q in qs) for _, qs in observable], dtype=np.uint64)
-    o, keep = _run_opts(L.RUN_EXPECTATION, 0, 0, 0, 0, None, pa, None, None, observable)
-    need = C.c_size_t()
-    check(lib().ptsbe_workspace_size(plan.handle, ts.handle, C.byref(o), C.byref(need)))
     ws = workspace
     if ws is None:
-        ws = torch.empty(2 * need.value + (1 << 20), dtype=torch.uint8, device=dev)
+        need = ptsbe_workspace_size(plan, ts, "adjoint", max_batch=max_batch, params=pa)
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
     E = torch.zeros(1, dtype=torch.float64, device=dev)
     G = torch.zeros(max(1, pa.size), dtype=torch.float64, device=dev)
     check(lib().ptsbe_adjoint_grad(plan.handle, ts.handle, _dptr(pa), _dptr(coef),

@@ -21,7 +21,7 @@ ATTACH_AFTER_TAG, ATTACH_BEFORE_MEASURE, ATTACH_BEFORE_READOUT = range(3)
 C64, C128 = 0, 1
 PTS_MODES = {"proportional": 0, "alg2_literal": 1, "most_likely": 2, "per_shot": 3}
 ALLOCS = {"multiplicity": 0, "reweight": 1, "uniform": 2}
-RUN_SHOTS, RUN_STATES, RUN_EXPECTATION = range(3)
+RUN_SHOTS, RUN_STATES, RUN_EXPECTATION, RUN_ADJOINT = range(4)
 
 
 class Op(C.Structure):
@@ -103,6 +103,8 @@ _SIGS = {
     "ptsbe_run_status": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "ptsbe_trajset_tables": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_uint32, C.c_void_p,
                                        C.POINTER(C.c_size_t), C.c_void_p]),
+    "ptsbe_trajset_adjoint_tables": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_void_p,
+                                               C.POINTER(C.c_size_t), C.c_void_p, C.c_void_p, C.c_void_p]),
     "ptsbe_adjoint_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_double),
                                      C.POINTER(C.c_double), C.POINTER(C.c_uint64), C.c_uint32,
                                      C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p]),

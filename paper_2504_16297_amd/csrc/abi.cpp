@@ -21,6 +21,8 @@ ptsbe_status run_status(const void* d_ws, void* stream);
 ptsbe_status adjoint_grad(const Plan& P, TrajSet& ts, const double* params, const double* coef,
                           const uint64_t* zmask, uint32_t n_terms, void* d_ws, size_t ws_bytes, double* d_expval,
                           double* d_grad, void* stream);
+ptsbe_status adjoint_workspace_size(const Plan& P, TrajSet& ts, const double* params, uint32_t max_batch,
+                                    size_t* bytes);
 }  // namespace ptsbe
 
 using namespace ptsbe;
@@ -142,6 +144,8 @@ ptsbe_status ptsbe_workspace_size(ptsbe_plan_t plan, ptsbe_trajset_t ts, const p
   FENCE({
     if (!plan || !ts || !bytes) return fail(PTSBE_E_ARG, "null argument");
     if (ts->ts->plan.get() != plan->plan.get()) return fail(PTSBE_E_ARG, "trajectory set belongs to another plan");
+    if (opts && opts->mode == PTSBE_RUN_ADJOINT)
+      return adjoint_workspace_size(*plan->plan, *ts->ts, opts->params, opts->max_batch, bytes);
     return workspace_size(*plan->plan, *ts->ts, opts, bytes);
   })
 }
@@ -180,6 +184,35 @@ ptsbe_status ptsbe_trajset_tables(ptsbe_trajset_t h, const double* params, uint3
                               L.n_pool, L.n_ov,   L.n_exec,       L.total};
       std::memcpy(offsets, v, sizeof(v));
     }
+    return PTSBE_OK;
+  })
+}
+
+ptsbe_status ptsbe_trajset_adjoint_tables(ptsbe_trajset_t h, const double* params, void* out, size_t* bytes,
+                                          uint64_t* offsets, uint32_t* n_dot, uint32_t* dot_param) {
+  FENCE({
+    if (!h || !bytes) return fail(PTSBE_E_ARG, "null argument");
+    TrajSet& ts = *h->ts;
+    const Plan& P = *ts.plan;
+    if (!params) return fail(PTSBE_E_ARG, "params required");
+    std::lock_guard<std::mutex> lk(ts.mu);
+    ptsbe_status st = build_adj_tables(ts, params);
+    if (st != PTSBE_OK) return st;
+    if (out) {
+      if (*bytes < ts.adj_blob.size()) return fail(PTSBE_E_ARG, "output buffer too small");
+      std::memcpy(out, ts.adj_blob.data(), ts.adj_blob.size());
+    }
+    *bytes = ts.adj_blob.size();
+    if (offsets) {
+      const TableLayout& L = ts.adj_layout;
+      const uint64_t v[16] = {L.passes, L.ops,    L.slot_default, L.pool,  L.ov_off,  L.ov,
+                              L.shot_off, L.chunk_off, L.exec,    L.n_passes, L.n_ops, L.n_slots,
+                              L.n_pool, L.n_ov,   L.n_exec,       L.total};
+      std::memcpy(offsets, v, sizeof(v));
+    }
+    if (n_dot) *n_dot = (uint32_t)P.adj.dot_param.size();
+    if (dot_param)
+      for (size_t d = 0; d < P.adj.dot_param.size(); ++d) dot_param[d] = (uint32_t)P.adj.dot_param[d];
     return PTSBE_OK;
   })
 }

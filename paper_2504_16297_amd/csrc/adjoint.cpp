@@ -1,14 +1,236 @@
 // Adjoint gradient of the probability-weighted trajectory ensemble.
+//
+// Pre-trajectory sampling fixes every trajectory's Kraus operators before
+// execution (Sec. 3), so each trajectory is a fixed unitary circuit U_a(theta)
+// and E(theta) = sum_a w_a <psi_a|O|psi_a>, with w_a = count_a / sum count
+// independent of theta for unitary-mixture noise.  Per trajectory: psi = U|0>
+// (forward program), lambda = O psi, then the reverse-sweep program un-applies
+// every operation on psi and lambda and, just before un-applying a rotation
+// exp(-i theta P / 2), adds Im<lambda|P|psi> = 2 Re<lambda|dG/dtheta|psi_prev>.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
 #include "host.hpp"
+#include "kernels.hpp"
 
 namespace ptsbe {
+
+namespace {
+
+uint64_t a256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+
+struct AdjLayout {
+  uint64_t status, fwd, adj, aux, psi, lam, partial, ev, scan_part, scan_offs, scan_total, gdot, end;
+  uint32_t batch, n_tiles, nblk, per_block, per_thread;
+};
+
+AdjLayout adj_layout(const Plan& P, const TrajSet& ts, uint32_t batch) {
+  AdjLayout L{};
+  const uint64_t N = 1ull << P.n;
+  const uint64_t esz = P.precision == PTSBE_C64 ? 8 : 16;
+  const uint64_t B = ts.m.size();
+  const uint32_t k_adj = P.adj.passes.empty() ? (uint32_t)P.n : (uint32_t)P.adj.passes[0].k;
+  const uint64_t n_dot = P.adj.dot_param.size();
+  L.batch = batch;
+  L.n_tiles = 1u << (P.n - k_adj);
+  L.per_block = (uint32_t)std::min<uint64_t>(N, kScanBlock);
+  L.nblk = (uint32_t)(N / L.per_block);
+  L.per_thread = std::max<uint32_t>(1, L.per_block / 256);
+  uint64_t o = 0;
+  L.status = o; o = a256(o + 16);
+  L.fwd = o; o = a256(o + ts.table_blob.size());
+  L.adj = o; o = a256(o + ts.adj_blob.size());
+  L.aux = o; o = a256(o + B * 8 + std::max<uint64_t>(1, n_dot) * 4);   // weights, dot -> parameter
+  L.psi = o; o = a256(o + (uint64_t)batch * N * esz);
+  L.lam = o; o = a256(o + (uint64_t)batch * N * esz);
+  L.partial = o; o = a256(o + B * L.n_tiles * std::max<uint64_t>(1, n_dot) * 8);
+  L.ev = o; o = a256(o + B * 8);
+  L.scan_part = o; o = a256(o + (uint64_t)batch * L.nblk * 8);
+  L.scan_offs = o; o = a256(o + (uint64_t)batch * L.nblk * 8);
+  L.scan_total = o; o = a256(o + (uint64_t)batch * 8);
+  L.gdot = o; o = a256(o + std::max<uint64_t>(1, n_dot) * 8);
+  L.end = o;
+  return L;
+}
+
+ptsbe_status hip_check(hipError_t e, const char* what) {
+  if (e == hipSuccess) return PTSBE_OK;
+  return fail(PTSBE_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define CK(expr, what)                           \
+  do {                                           \
+    ptsbe_status _s = hip_check((expr), (what)); \
+    if (_s != PTSBE_OK) return _s;               \
+  } while (0)
+
+template <typename V>
+PassArgs<V> pass_args(const Plan& P, uint8_t* tb, const TableLayout& T, uint32_t n_passes, V* states) {
+  PassArgs<V> pa{};
+  pa.passes = reinterpret_cast<const DPass*>(tb + T.passes);
+  pa.ops = reinterpret_cast<const DOp*>(tb + T.ops);
+  pa.slot_default = reinterpret_cast<const uint32_t*>(tb + T.slot_default);
+  pa.pool = reinterpret_cast<const V*>(tb + T.pool);
+  pa.ov_off = reinterpret_cast<const uint32_t*>(tb + T.ov_off);
+  pa.ov = reinterpret_cast<const DOverride*>(tb + T.ov);
+  pa.states = states;
+  pa.N = 1ull << P.n;
+  pa.n = (uint32_t)P.n;
+  pa.n_passes = n_passes;
+  pa.n_measure = 0;
+  return pa;
+}
+
+template <typename V>
+ptsbe_status adjoint_typed(const Plan& P, TrajSet& ts, const double* coef, const uint64_t* zmask, uint32_t n_terms,
+                           uint8_t* ws, const AdjLayout& L, double* d_expval, double* d_grad, hipStream_t s) {
+  const uint32_t B = (uint32_t)ts.m.size();
+  const uint64_t N = 1ull << P.n;
+  const uint32_t n_dot = (uint32_t)P.adj.dot_param.size();
+  CK(hipMemcpyAsync(ws + L.fwd, ts.table_blob.data(), ts.table_blob.size(), hipMemcpyHostToDevice, s), "table upload");
+  CK(hipMemcpyAsync(ws + L.adj, ts.adj_blob.data(), ts.adj_blob.size(), hipMemcpyHostToDevice, s), "table upload");
+  // weights and the dot -> parameter map live with the plan's host data for the whole call
+  std::vector<uint8_t>& aux = ts.adj_aux;
+  aux.assign(B * 8 + std::max<uint32_t>(1, n_dot) * 4, 0);
+  double tot = 0.0;
+  for (uint64_t c : ts.count) tot += (double)c;
+  for (uint32_t t = 0; t < B; ++t) {
+    const double w = (double)ts.count[t] / tot;
+    std::memcpy(aux.data() + 8 * t, &w, 8);
+  }
+  for (uint32_t d = 0; d < n_dot; ++d) {
+    const uint32_t p = (uint32_t)P.adj.dot_param[d];
+    std::memcpy(aux.data() + B * 8 + 4 * d, &p, 4);
+  }
+  CK(hipMemcpyAsync(ws + L.aux, aux.data(), aux.size(), hipMemcpyHostToDevice, s), "weights upload");
+  const double* w = reinterpret_cast<const double*>(ws + L.aux);
+  const uint32_t* dot_param = reinterpret_cast<const uint32_t*>(ws + L.aux + B * 8);
+  V* psi = reinterpret_cast<V*>(ws + L.psi);
+  V* lam = reinterpret_cast<V*>(ws + L.lam);
+  double* ev = reinterpret_cast<double*>(ws + L.ev);
+  double* partial = reinterpret_cast<double*>(ws + L.partial);
+  PassArgs<V> fa = pass_args<V>(P, ws + L.fwd, ts.layout, (uint32_t)P.passes.size(), psi);
+  AdjArgs<V> aa{};
+  aa.p = pass_args<V>(P, ws + L.adj, ts.adj_layout, (uint32_t)P.adj.passes.size(), psi);
+  aa.lam = lam;
+  aa.partial = partial;
+  aa.n_dot = n_dot;
+  for (uint32_t b0 = 0; b0 < B; b0 += L.batch) {
+    const uint32_t bb = std::min<uint32_t>(L.batch, B - b0);
+    fa.t0 = b0;
+    aa.p.t0 = b0;
+    for (const ExecStep& ex : P.exec) {
+      if (ex.pass < 0) return fail(PTSBE_E_UNSUPPORTED, "adjoint: measurement steps are not supported");
+      const Pass& ps = P.passes[ex.pass];
+      fa.pass = (uint32_t)ex.pass;
+      CK(launch_pass<V>(fa, (uint32_t)ps.k, (uint32_t)ps.slots.size(), (uint32_t)ps.ops.size(), bb, s), "forward");
+    }
+    ScanArgs<V> sa{};
+    sa.states = psi;
+    sa.partial = reinterpret_cast<double*>(ws + L.scan_part);
+    sa.offs = reinterpret_cast<double*>(ws + L.scan_offs);
+    sa.N = N;
+    sa.nblk = L.nblk;
+    sa.per_block = L.per_block;
+    sa.per_thread = L.per_thread;
+    double* total = reinterpret_cast<double*>(ws + L.scan_total);
+    CK(launch_norm<V>(sa, bb, total, s), "norm");
+    ExpArgs<V> ea{};
+    ea.states = psi;
+    ea.partial = sa.partial;
+    ea.N = N;
+    ea.nblk = L.nblk;
+    ea.per_block = L.per_block;
+    ea.n_terms = n_terms;
+    ObsArgs<V> oa{};
+    oa.psi = psi;
+    oa.lam = lam;
+    oa.N = N;
+    oa.n_terms = n_terms;
+    for (uint32_t j = 0; j < n_terms; ++j) {
+      ea.coef[j] = oa.coef[j] = coef[j];
+      ea.zmask[j] = oa.zmask[j] = zmask[j];
+    }
+    CK(launch_expval<V>(ea, total, ev, bb, b0, s), "expectation");
+    CK(launch_obs_apply<V>(oa, bb, s), "lambda");
+    for (const ExecStep& ex : P.adj.exec) {
+      const Pass& ps = P.adj.passes[ex.pass];
+      aa.p.pass = (uint32_t)ex.pass;
+      CK(launch_adjoint_pass<V>(aa, (uint32_t)ps.k, (uint32_t)ps.slots.size(), bb, s), "reverse sweep");
+    }
+  }
+  CK(launch_grad_reduce(partial, w, B, L.n_tiles, n_dot, reinterpret_cast<double*>(ws + L.gdot), dot_param,
+                        (uint32_t)P.n_params, d_grad, ev, d_expval, s),
+     "gradient reduction");
+  return PTSBE_OK;
+}
+
+ptsbe_status check_adjoint(const Plan& P, const TrajSet& ts, const double* params, const double* coef,
+                           const uint64_t* zmask, uint32_t n_terms) {
+  if (!P.has_adjoint)
+    return fail(PTSBE_E_UNSUPPORTED,
+                "adjoint gradient needs parametrised gates and no measure-reset / projection operations");
+  if (!params) return fail(PTSBE_E_ARG, "params required");
+  if (n_terms == 0 || n_terms > 64 || !coef || !zmask)
+    return fail(PTSBE_E_ARG, "observable: 1..64 Z-string terms with coefficients and masks");
+  if (P.n < 64)
+    for (uint32_t j = 0; j < n_terms; ++j)
+      if (zmask[j] >> P.n) return fail(PTSBE_E_ARG, "observable names a qubit >= n");
+  if (ts.m.empty()) return fail(PTSBE_E_ARG, "empty trajectory set");
+  return PTSBE_OK;
+}
+
+}  // namespace
+
+ptsbe_status adjoint_workspace_size(const Plan& P, TrajSet& ts, const double* params, uint32_t max_batch,
+                                    size_t* bytes) {
+  if (!P.has_adjoint)
+    return fail(PTSBE_E_UNSUPPORTED,
+                "adjoint gradient needs parametrised gates and no measure-reset / projection operations");
+  if (!params) return fail(PTSBE_E_ARG, "params required");
+  if (ts.m.empty()) return fail(PTSBE_E_ARG, "empty trajectory set");
+  std::lock_guard<std::mutex> lk(ts.mu);
+  ptsbe_status st = build_tables(ts, params, 4096);
+  if (st != PTSBE_OK) return st;
+  st = build_adj_tables(ts, params);
+  if (st != PTSBE_OK) return st;
+  uint32_t batch = std::min<uint32_t>((uint32_t)ts.m.size(), 65535);
+  if (max_batch) batch = std::min(batch, max_batch);
+  *bytes = adj_layout(P, ts, batch).end;
+  return PTSBE_OK;
+}
 
 ptsbe_status adjoint_grad(const Plan& P, TrajSet& ts, const double* params, const double* coef,
                           const uint64_t* zmask, uint32_t n_terms, void* d_ws, size_t ws_bytes, double* d_expval,
                           double* d_grad, void* stream) {
-  (void)P; (void)ts; (void)params; (void)coef; (void)zmask; (void)n_terms; (void)d_ws; (void)ws_bytes;
-  (void)d_expval; (void)d_grad; (void)stream;
-  return fail(PTSBE_E_UNSUPPORTED, "adjoint gradient not built yet");
+  ptsbe_status st = check_adjoint(P, ts, params, coef, zmask, n_terms);
+  if (st != PTSBE_OK) return st;
+  if (!d_ws || !d_expval || !d_grad) return fail(PTSBE_E_ARG, "null device pointer");
+  if (reinterpret_cast<uintptr_t>(d_ws) % 256) return fail(PTSBE_E_ARG, "workspace must be 256-byte aligned");
+  std::lock_guard<std::mutex> lk(ts.mu);
+  st = build_tables(ts, params, 4096);
+  if (st != PTSBE_OK) return st;
+  st = build_adj_tables(ts, params);
+  if (st != PTSBE_OK) return st;
+  const uint32_t B = (uint32_t)ts.m.size();
+  uint32_t batch = std::min<uint32_t>(B, 65535);
+  AdjLayout L = adj_layout(P, ts, batch);
+  while (L.end > ws_bytes && batch > 1) {
+    batch = std::max<uint32_t>(1, batch / 2);
+    L = adj_layout(P, ts, batch);
+  }
+  if (L.end > ws_bytes)
+    return fail(PTSBE_E_OOM, "workspace of " + std::to_string(ws_bytes) + " bytes is below the " +
+                                 std::to_string(L.end) + " bytes needed");
+  uint8_t* ws = static_cast<uint8_t*>(d_ws);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (P.precision == PTSBE_C64)
+    return adjoint_typed<float2>(P, ts, coef, zmask, n_terms, ws, L, d_expval, d_grad, s);
+  return adjoint_typed<double2>(P, ts, coef, zmask, n_terms, ws, L, d_expval, d_grad, s);
 }
 
 }  // namespace ptsbe

@@ -33,7 +33,7 @@ struct Channel {
   std::vector<Mat> f0, f1;     // factors on matrix bit 0 / bit 1 (2x2 each)
 };
 
-enum StepKind { ST_GATE, ST_PARAM, ST_SITE, ST_MR, ST_P0 };
+enum StepKind { ST_GATE, ST_PARAM, ST_SITE, ST_MR, ST_P0, ST_DOT };
 
 struct Step {
   StepKind kind;
@@ -41,9 +41,11 @@ struct Step {
   int q[4] = {0, 0, 0, 0};
   Mat mat;                     // GATE
   bool diag = false;           // diagonal in the computational basis (for every variant)
-  int param = -1, gen = 0;     // PARAM
+  bool dagger = false;         // apply the adjoint of the operation (reverse sweep)
+  int param = -1, gen = 0;     // PARAM, DOT
   int site = -1;               // SITE
   int mr = -1;                 // MR record index
+  int dot = -1;                // DOT: index of the gradient contribution
 };
 
 struct Site {
@@ -83,6 +85,17 @@ struct ExecStep {
   std::vector<int> mr_index;   // measurement: record indices
 };
 
+// A fused device program: steps, the tile passes and execution steps built
+// from them, and the slots each noise site touches.
+struct Program {
+  std::vector<Step> steps;
+  std::vector<Pass> passes;
+  std::vector<ExecStep> exec;
+  std::vector<std::vector<std::pair<int, int>>> site_slots;
+  std::vector<int> dot_param;  // DOT index -> parameter index
+  std::vector<int> dot_gen;    // DOT index -> generator
+};
+
 struct Plan {
   int n = 0;
   int precision = PTSBE_C64;
@@ -99,6 +112,9 @@ struct Plan {
   std::vector<ExecStep> exec;
   // site -> (pass, slot) list
   std::vector<std::vector<std::pair<int, int>>> site_slots;
+  // reverse-sweep program of the adjoint gradient (unitary circuits with parameters)
+  bool has_adjoint = false;
+  Program adj;
 };
 
 struct TrajSet {
@@ -121,6 +137,12 @@ struct TrajSet {
   size_t pool_elems = 0;
   std::vector<uint64_t> chunk_off;
   uint32_t cached_chunk = 0;
+  // the same for the adjoint (reverse-sweep) program
+  std::vector<double> adj_params;
+  std::vector<uint8_t> adj_blob;
+  TableLayout adj_layout{};
+  bool adj_valid = false;
+  std::vector<uint8_t> adj_aux;    // host staging of weights and the dot -> parameter map
 };
 
 // Matrix helpers
@@ -129,8 +151,9 @@ Mat mat_mul(const Mat& a, const Mat& b, int d);        // a * b
 bool mat_is_diag(const Mat& a, int d, double tol = 0.0);
 Mat rot_matrix(int gen, double theta);
 
-// Slot matrix for a trajectory: choice(site) gives its Kraus index.
-Mat slot_matrix(const Plan& plan, const Slot& s, const double* params,
+// Slot matrix for a trajectory: choice(site) gives its Kraus index.  `steps` is
+// the step list of the program the slot belongs to.
+Mat slot_matrix(const Plan& plan, const std::vector<Step>& steps, const Slot& s, const double* params,
                 const std::map<int, int>& choice);
 
 // Planner
@@ -139,6 +162,8 @@ ptsbe_status build_plan(const ptsbe_circuit* c, const ptsbe_noise_model* nm,
 
 // Build the device tables of a trajectory set (cached in ts).
 ptsbe_status build_tables(TrajSet& ts, const double* params, uint32_t chunk);
+// Device tables of the adjoint (reverse-sweep) program, cached in ts.
+ptsbe_status build_adj_tables(TrajSet& ts, const double* params);
 
 }  // namespace ptsbe
 

@@ -591,6 +591,181 @@ __global__ __launch_bounds__(256) void k_cdf(ScanArgs<V> a) {
   block_prob_scan<V, true>(a);
 }
 
+// ------------------------------------------------------------ adjoint sweep
+
+// One unitary op of a tile pass on an LDS tile (all threads; caller syncs).
+template <typename V>
+__device__ __forceinline__ void tile_apply(V* tile, const DOp& op, const V* m, uint64_t base, uint32_t nt,
+                                           uint32_t tid, uint32_t bd) {
+  if (op.type == DOP_M1) {
+    const V m00 = m[0], m01 = m[1], m10 = m[2], m11 = m[3];
+    const uint32_t bit = 1u << op.a, lo = bit - 1;
+    for (uint32_t pr = tid; pr < nt / 2; pr += bd) {
+      const uint32_t i0 = ((pr & ~lo) << 1) | (pr & lo), i1 = i0 | bit;
+      const V x0 = tile[i0], x1 = tile[i1];
+      tile[i0] = cfma2(m00, x0, m01, x1);
+      tile[i1] = cfma2(m10, x0, m11, x1);
+    }
+  } else if (op.type == DOP_M2) {
+    const uint32_t A = 1u << op.a, B = 1u << op.b;
+    const uint32_t l1 = min(A, B) - 1, l2 = max(A, B) - 1;
+    for (uint32_t qd = tid; qd < nt / 4; qd += bd) {
+      uint32_t i = ((qd & ~l1) << 1) | (qd & l1);
+      i = ((i & ~l2) << 1) | (i & l2);
+      const V x0 = tile[i], x1 = tile[i | A], x2 = tile[i | B], x3 = tile[i | A | B];
+      tile[i] = cdot4(m, x0, x1, x2, x3);
+      tile[i | A] = cdot4(m + 4, x0, x1, x2, x3);
+      tile[i | B] = cdot4(m + 8, x0, x1, x2, x3);
+      tile[i | A | B] = cdot4(m + 12, x0, x1, x2, x3);
+    }
+  } else if (op.type == DOP_D1 || op.type == DOP_D2) {
+    const bool two = op.type == DOP_D2;
+    const uint32_t dd = two ? 5 : 3;
+    const uint32_t fa = op.a == 255 ? (uint32_t)((base >> op.ga) & 1) : 0;
+    const uint32_t fb = (two && op.b == 255) ? (uint32_t)((base >> op.gb) & 1) : 0;
+    for (uint32_t L = tid; L < nt; L += bd) {
+      const uint32_t ba = op.a == 255 ? fa : (L >> op.a) & 1u;
+      const uint32_t bb = two ? (op.b == 255 ? fb : (L >> op.b) & 1u) : 0;
+      tile[L] = cmul(m[(ba + 2 * bb) * dd], tile[L]);
+    }
+  } else if (op.type == DOP_DSIGN) {
+    const uint32_t fa = op.a == 255 ? (uint32_t)((base >> op.ga) & 1) : 0;
+    const uint32_t fb = op.b == 255 ? (uint32_t)((base >> op.gb) & 1) : 0;
+    for (uint32_t L = tid; L < nt; L += bd) {
+      const uint32_t ba = op.a == 255 ? fa : (L >> op.a) & 1u;
+      const uint32_t bb = op.b == 254 ? 0u : (op.b == 255 ? fb : (L >> op.b) & 1u);
+      if ((op.slot[0] >> (ba + 2 * bb)) & 1u) {
+        V v = tile[L];
+        v.x = -v.x;
+        v.y = -v.y;
+        tile[L] = v;
+      }
+    }
+  }
+}
+
+template <typename V>
+__device__ __forceinline__ double im_conj_mul(V a, V b) {  // Im(conj(a) b)
+  return (double)a.x * (double)b.y - (double)a.y * (double)b.x;
+}
+template <typename V>
+__device__ __forceinline__ double re_conj_mul(V a, V b) {  // Re(conj(a) b)
+  return (double)a.x * (double)b.x + (double)a.y * (double)b.y;
+}
+
+template <typename V>
+__global__ __launch_bounds__(256) void k_adjoint(AdjArgs<V> a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const PassArgs<V>& pa = a.p;
+  const DPass& P = pa.passes[pa.pass];
+  const uint32_t k = P.k, nt = 1u << k;
+  V* tp = reinterpret_cast<V*>(smem);
+  V* tl = tp + nt;
+  uint32_t* slot_off = reinterpret_cast<uint32_t*>(tl + nt);
+  __shared__ uint8_t tq[16];
+  const uint32_t tid = threadIdx.x, bd = blockDim.x;
+  const uint32_t t = pa.t0 + blockIdx.y;
+  const uint64_t tile_id = blockIdx.x;
+  if (tid < 16) tq[tid] = P.tq[tid];
+  uint64_t base = 0;
+  for (uint32_t i = 0; i < pa.n - k; ++i)
+    if ((tile_id >> i) & 1) base |= 1ull << P.oq[i];
+  V* sp = pa.states + (uint64_t)blockIdx.y * pa.N;
+  V* sl = a.lam + (uint64_t)blockIdx.y * pa.N;
+  for (uint32_t s = tid; s < P.n_slots; s += bd) slot_off[s] = pa.slot_default[P.slot_begin + s];
+  __syncthreads();
+  {
+    const uint32_t ob = pa.ov_off[(uint64_t)t * pa.n_passes + pa.pass];
+    const uint32_t oe = pa.ov_off[(uint64_t)t * pa.n_passes + pa.pass + 1];
+    for (uint32_t i = ob + tid; i < oe; i += bd) slot_off[pa.ov[i].slot] = pa.ov[i].off;
+  }
+  for (uint32_t L = tid; L < nt; L += bd) {
+    const uint64_t off = base + tile_offset(L, tq, k);
+    tp[L] = sp[off];
+    tl[L] = sl[off];
+  }
+  __syncthreads();
+  const DOp* ops = pa.ops + P.op_begin;
+  for (uint32_t o = 0; o < P.n_ops; ++o) {
+    const DOp op = ops[o];
+    if (op.type == DOP_DOT) {
+      // Im<lambda|P_q|psi> restricted to this tile (pairs along local bit a)
+      const uint32_t bit = 1u << op.a, lo = bit - 1;
+      double acc = 0.0;
+      for (uint32_t pr = tid; pr < nt / 2; pr += bd) {
+        const uint32_t i0 = ((pr & ~lo) << 1) | (pr & lo), i1 = i0 | bit;
+        const V l0 = tl[i0], l1 = tl[i1], p0 = tp[i0], p1 = tp[i1];
+        if (op.b == 3)        // Z
+          acc += im_conj_mul(l0, p0) - im_conj_mul(l1, p1);
+        else if (op.b == 1)   // X
+          acc += im_conj_mul(l0, p1) + im_conj_mul(l1, p0);
+        else                  // Y: (Y psi)_0 = -i psi_1, (Y psi)_1 = i psi_0
+          acc += re_conj_mul(l1, p0) - re_conj_mul(l0, p1);
+      }
+      double ex, tot;
+      block_excl_scan(acc, &ex, &tot);
+      const uint32_t d = (uint32_t)op.slot[0] | ((uint32_t)op.slot[1] << 16);
+      if (tid == 0) a.partial[((uint64_t)t * gridDim.x + tile_id) * a.n_dot + d] = tot;
+    } else {
+      // DSIGN carries its sign mask in slot[0] and reads no matrix
+      const V* m = op.type == DOP_DSIGN ? pa.pool : pa.pool + slot_off[op.slot[0]];
+      tile_apply(tp, op, m, base, nt, tid, bd);
+      tile_apply(tl, op, m, base, nt, tid, bd);
+    }
+    __syncthreads();
+  }
+  for (uint32_t L = tid; L < nt; L += bd) {
+    const uint64_t off = base + tile_offset(L, tq, k);
+    sp[off] = tp[L];
+    sl[off] = tl[L];
+  }
+}
+
+// lambda = O psi for a diagonal O = sum_t coef_t Z-string(zmask_t)
+template <typename V>
+__global__ __launch_bounds__(256) void k_obs_apply(ObsArgs<V> a) {
+  const V* p = a.psi + (uint64_t)blockIdx.y * a.N;
+  V* l = a.lam + (uint64_t)blockIdx.y * a.N;
+  for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < a.N; x += (uint64_t)gridDim.x * blockDim.x) {
+    double o = 0.0;
+    for (uint32_t j = 0; j < a.n_terms; ++j) o += (__popcll(x & a.zmask[j]) & 1) ? -a.coef[j] : a.coef[j];
+    V v = p[x];
+    v.x = (typename Real<V>::T)((double)v.x * o);
+    v.y = (typename Real<V>::T)((double)v.y * o);
+    l[x] = v;
+  }
+}
+
+__global__ void k_grad_dot(const double* partial, const double* w, uint32_t n_traj, uint32_t n_tiles, uint32_t n_dot,
+                           double* gdot) {
+  const uint32_t d = blockIdx.x;
+  double s = 0.0;  // fixed order: thread-strided over trajectories, then the block tree
+  for (uint32_t t = threadIdx.x; t < n_traj; t += blockDim.x) {
+    double st = 0.0;
+    for (uint32_t tile = 0; tile < n_tiles; ++tile) st += partial[((uint64_t)t * n_tiles + tile) * n_dot + d];
+    s += w[t] * st;
+  }
+  double ex, tot;
+  block_excl_scan(s, &ex, &tot);
+  if (threadIdx.x == 0) gdot[d] = tot;
+}
+
+__global__ void k_grad_gather(const double* gdot, const uint32_t* dot_param, uint32_t n_dot, uint32_t n_params,
+                              double* grad, const double* ev, const double* w, uint32_t n_traj, double* E) {
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n_params) {
+    double g = 0.0;
+    for (uint32_t d = 0; d < n_dot; ++d)
+      if (dot_param[d] == p) g += gdot[d];
+    grad[p] = g;
+  }
+  if (p == 0) {
+    double e = 0.0;
+    for (uint32_t t = 0; t < n_traj; ++t) e += w[t] * ev[t];
+    *E = e;
+  }
+}
+
 // ------------------------------------------------------------ measure-reset
 
 template <typename V>
@@ -818,6 +993,31 @@ hipError_t launch_expval(const ExpArgs<V>& a, const double* total, double* out, 
   return hipGetLastError();
 }
 
+template <typename V>
+hipError_t launch_adjoint_pass(const AdjArgs<V>& a, uint32_t k, uint32_t n_slots, uint32_t batch, hipStream_t s) {
+  const size_t lds = 2 * sizeof(V) * (size_t(1) << k) + 4 * (size_t)n_slots;
+  if (lds > 65536) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL(k_adjoint<V>, dim3(1u << (a.p.n - k), batch), dim3(256), lds, s, a);
+  return hipGetLastError();
+}
+
+template <typename V>
+hipError_t launch_obs_apply(const ObsArgs<V>& a, uint32_t batch, hipStream_t s) {
+  uint32_t gx = (uint32_t)((a.N + 255) / 256 < 65536 ? (a.N + 255) / 256 : 65536);
+  hipLaunchKernelGGL(k_obs_apply<V>, dim3(gx, batch), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_reduce(const double* partial, const double* w, uint32_t n_traj, uint32_t n_tiles,
+                              uint32_t n_dot, double* gdot, const uint32_t* dot_param, uint32_t n_params,
+                              double* grad, const double* ev, double* E, hipStream_t s) {
+  if (n_dot) hipLaunchKernelGGL(k_grad_dot, dim3(n_dot), dim3(256), 0, s, partial, w, n_traj, n_tiles, n_dot, gdot);
+  const uint32_t np = n_params ? n_params : 1;
+  hipLaunchKernelGGL(k_grad_gather, dim3((np + 255) / 256), dim3(256), 0, s, gdot, dot_param, n_dot, n_params, grad, ev,
+                     w, n_traj, E);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {
   uint32_t g = (uint32_t)((n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024);
   if (g == 0) g = 1;
@@ -834,6 +1034,10 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {
   template hipError_t launch_expval<V>(const ExpArgs<V>&, const double*, double*, uint32_t, uint32_t, hipStream_t);
 PTSBE_INST(float2)
 PTSBE_INST(double2)
+template hipError_t launch_adjoint_pass<float2>(const AdjArgs<float2>&, uint32_t, uint32_t, uint32_t, hipStream_t);
+template hipError_t launch_adjoint_pass<double2>(const AdjArgs<double2>&, uint32_t, uint32_t, uint32_t, hipStream_t);
+template hipError_t launch_obs_apply<float2>(const ObsArgs<float2>&, uint32_t, hipStream_t);
+template hipError_t launch_obs_apply<double2>(const ObsArgs<double2>&, uint32_t, hipStream_t);
 template hipError_t launch_sample<uint32_t>(const SampleArgs<uint32_t>&, uint64_t, hipStream_t);
 template hipError_t launch_sample<uint64_t>(const SampleArgs<uint64_t>&, uint64_t, hipStream_t);
 

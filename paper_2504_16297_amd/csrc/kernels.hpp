@@ -97,6 +97,35 @@ struct ExpArgs {
   uint64_t zmask[64];
 };
 
+// Reverse sweep of the adjoint gradient: psi and lambda tiles in LDS, every op
+// applied to both, DOT ops write Im<lambda|P|psi> partials per (trajectory, tile).
+template <typename V>
+struct AdjArgs {
+  PassArgs<V> p;        // tables of the adjoint program; p.states = psi
+  V* lam;               // lambda states (same layout as psi)
+  double* partial;      // [trajectory][tile][dot]
+  uint32_t n_dot;
+};
+
+template <typename V>
+struct ObsArgs {
+  const V* psi;
+  V* lam;
+  uint64_t N;
+  uint32_t n_terms;
+  double coef[64];
+  uint64_t zmask[64];
+};
+
+template <typename V>
+hipError_t launch_adjoint_pass(const AdjArgs<V>& a, uint32_t k, uint32_t n_slots, uint32_t batch, hipStream_t s);
+template <typename V>
+hipError_t launch_obs_apply(const ObsArgs<V>& a, uint32_t batch, hipStream_t s);
+// gdot[d] = sum_t w[t] sum_tile partial[t][tile][d]; grad[p] = sum over dots of p; E = sum_t w[t] ev[t]
+hipError_t launch_grad_reduce(const double* partial, const double* w, uint32_t n_traj, uint32_t n_tiles,
+                              uint32_t n_dot, double* gdot, const uint32_t* dot_param, uint32_t n_params,
+                              double* grad, const double* ev, double* E, hipStream_t s);
+
 template <typename V>
 hipError_t launch_pass(const PassArgs<V>& a, uint32_t k, uint32_t n_slots, uint32_t n_ops, uint32_t batch,
                        hipStream_t s);

@@ -172,31 +172,48 @@ static ptsbe_status analyse_channel(const ptsbe_channel& ch, int idx, Channel* o
 
 // ------------------------------------------------------------------ fusion
 
-static Mat part_matrix(const Plan& plan, const Part& pt, const double* params, const std::map<int, int>& choice) {
-  const Step& st = plan.steps[pt.step];
+static Mat mat_dagger(const Mat& a) {
+  const int d = a.size() == 16 ? 4 : 2;
+  Mat r(a.size());
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j) r[i * d + j] = std::conj(a[j * d + i]);
+  return r;
+}
+
+static Mat part_matrix(const Plan& plan, const std::vector<Step>& steps, const Part& pt, const double* params,
+                       const std::map<int, int>& choice) {
+  const Step& st = steps[pt.step];
+  Mat m;
   switch (st.kind) {
     case ST_GATE:
     case ST_P0:
-      return st.mat;
+      m = st.mat;
+      break;
     case ST_PARAM:
-      return rot_matrix(st.gen, params ? params[st.param] : 0.0);
+      m = rot_matrix(st.gen, params ? params[st.param] : 0.0);
+      break;
     case ST_SITE: {
       const Site& s = plan.sites[st.site];
       const Channel& ch = plan.channels[s.channel];
       auto it = choice.find(st.site);
       int k = it == choice.end() ? 0 : it->second;
-      if (pt.half < 0) return ch.U[k];
-      return pt.half == 0 ? ch.f0[k] : ch.f1[k];
+      if (pt.half < 0)
+        m = ch.U[k];
+      else
+        m = pt.half == 0 ? ch.f0[k] : ch.f1[k];
+      break;
     }
     default:
       return mat_identity(2);
   }
+  return st.dagger ? mat_dagger(m) : m;
 }
 
-Mat slot_matrix(const Plan& plan, const Slot& s, const double* params, const std::map<int, int>& choice) {
+Mat slot_matrix(const Plan& plan, const std::vector<Step>& steps, const Slot& s, const double* params,
+                const std::map<int, int>& choice) {
   int d = (s.type == DOP_M2 || s.type == DOP_D2) ? 4 : 2;
   Mat M = mat_identity(d);
-  for (const Part& pt : s.parts) M = mat_mul(part_matrix(plan, pt, params, choice), M, d);
+  for (const Part& pt : s.parts) M = mat_mul(part_matrix(plan, steps, pt, params, choice), M, d);
   return M;
 }
 
@@ -204,11 +221,13 @@ namespace {
 
 struct Fuser {
   Plan& plan;
+  const std::vector<Step>& steps;
   Pass& pass;
   std::vector<int> run;  // qubit -> open slot index or -1
   std::vector<int> local;
 
-  Fuser(Plan& pl, Pass& ps) : plan(pl), pass(ps), run(pl.n, -1), local(pl.n, -1) {
+  Fuser(Plan& pl, const std::vector<Step>& st, Pass& ps)
+      : plan(pl), steps(st), pass(ps), run(pl.n, -1), local(pl.n, -1) {
     for (int j = 0; j < ps.k; ++j) local[ps.tq[j]] = j;
   }
 
@@ -224,7 +243,7 @@ struct Fuser {
   void add_part(int slot, const Part& pt) {
     Slot& s = pass.slots[slot];
     s.parts.push_back(pt);
-    const Step& st = plan.steps[pt.step];
+    const Step& st = steps[pt.step];
     if (st.kind == ST_SITE) {
       if (std::find(s.sites.begin(), s.sites.end(), st.site) == s.sites.end()) s.sites.push_back(st.site);
     }
@@ -266,7 +285,19 @@ struct Fuser {
   }
 
   void take(int si) {
-    const Step& st = plan.steps[si];
+    const Step& st = steps[si];
+    if (st.kind == ST_DOT) {
+      // gradient contribution Im<lambda|P_q|psi> at this point of the reverse sweep
+      flush(st.q[0]);
+      DOp op{};
+      op.type = DOP_DOT;
+      op.a = (uint8_t)local[st.q[0]];
+      op.b = (uint8_t)st.gen;
+      op.slot[0] = (uint16_t)(st.dot & 0xffff);
+      op.slot[1] = (uint16_t)(st.dot >> 16);
+      pass.ops.push_back(op);
+      return;
+    }
     if (st.kind == ST_MR) {
       flush(st.q[0]);
       DOp op{};
@@ -305,12 +336,12 @@ struct Fuser {
 
 // Diagonal slots made of one fixed gate whose entries are all +-1 (CZ, Z, ...)
 // become sign ops: the kernels flip signs instead of multiplying by phases.
-static void lower_signs(const Plan& plan, Pass& ps) {
+static void lower_signs(const std::vector<Step>& steps, Pass& ps) {
   for (DOp& op : ps.ops) {
     if (op.type != DOP_D1 && op.type != DOP_D2) continue;
     const Slot& s = ps.slots[op.slot[0]];
     if (s.parts.size() != 1 || !s.sites.empty() || s.uses_params) continue;
-    const Step& st = plan.steps[s.parts[0].step];
+    const Step& st = steps[s.parts[0].step];
     if (st.kind != ST_GATE && st.kind != ST_P0) continue;
     const int d = op.type == DOP_D1 ? 2 : 4;
     uint16_t mask = 0;
@@ -527,15 +558,19 @@ static void schedule_phases(Pass& ps, int min_fill) {
   ps.ops.swap(out);
 }
 
-static ptsbe_status schedule(Plan& plan) {
+// Tile-pass schedule of a step list.  `init_zero`: the first pass starts from
+// |0...0>; `phases`: order the passes for the register kernel.
+static ptsbe_status schedule(Plan& plan, const std::vector<Step>& steps, std::vector<Pass>& passes,
+                             std::vector<ExecStep>& exec, std::vector<std::vector<std::pair<int, int>>>& site_slots,
+                             bool init_zero, bool phases, int tile_bits) {
   const int n = plan.n;
-  const int k = std::min(n, plan.tile_bits);
+  const int k = std::min(n, tile_bits);
   // The lowest qubits are always in the tile (runs of >= 128 contiguous bytes),
   // leaving at least two free tile bits so that any 2-qubit operation fits.
   const int contiguous = std::max(0, std::min(k - 2, plan.precision == PTSBE_C64 ? 4 : 3));
-  std::vector<int> rem(plan.steps.size());
+  std::vector<int> rem(steps.size());
   for (size_t i = 0; i < rem.size(); ++i) rem[i] = (int)i;
-  std::vector<char> measured(plan.steps.size(), 0);
+  std::vector<char> measured(steps.size(), 0);
   bool first = true;
   int guard = 0;
   while (!rem.empty()) {
@@ -549,7 +584,7 @@ static ptsbe_status schedule(Plan& plan) {
     }
     std::vector<int> taken, keep;
     for (int si : rem) {
-      const Step& st = plan.steps[si];
+      const Step& st = steps[si];
       bool blk = false;
       for (int j = 0; j < st.nq; ++j) blk = blk || blocked[st.q[j]];
       bool can = false;
@@ -583,7 +618,7 @@ static ptsbe_status schedule(Plan& plan) {
       ExecStep ex;
       std::vector<char> blk(n, 0);
       for (int si : rem) {
-        const Step& st = plan.steps[si];
+        const Step& st = steps[si];
         bool b = false;
         for (int j = 0; j < st.nq; ++j) b = b || blk[st.q[j]];
         if (!b && st.kind == ST_MR && !measured[si]) {
@@ -600,13 +635,13 @@ static ptsbe_status schedule(Plan& plan) {
         p.k = k;
         for (int q = 0; q < n; ++q) (q < k ? p.tq : p.oq).push_back(q);
         p.flags = PASS_INIT_ZERO;
-        plan.passes.push_back(p);
+        passes.push_back(p);
         ExecStep e0;
-        e0.pass = (int)plan.passes.size() - 1;
-        plan.exec.push_back(e0);
+        e0.pass = (int)passes.size() - 1;
+        exec.push_back(e0);
         first = false;
       }
-      plan.exec.push_back(ex);
+      exec.push_back(ex);
       continue;
     }
     for (int q = 0; q < n && qcount < k; ++q)
@@ -617,36 +652,36 @@ static ptsbe_status schedule(Plan& plan) {
     Pass p;
     p.k = k;
     for (int q = 0; q < n; ++q) (inQ[q] ? p.tq : p.oq).push_back(q);
-    if (first) p.flags = PASS_INIT_ZERO;
+    if (first && init_zero) p.flags = PASS_INIT_ZERO;
     first = false;
-    plan.passes.push_back(p);
-    Pass& ps = plan.passes.back();
-    Fuser fz(plan, ps);
+    passes.push_back(p);
+    Pass& ps = passes.back();
+    Fuser fz(plan, steps, ps);
     for (int si : taken) fz.take(si);
     fz.finish();
-    lower_signs(plan, ps);
-    schedule_phases(ps, plan.min_fill);
+    lower_signs(steps, ps);
+    if (phases) schedule_phases(ps, plan.min_fill);
     ExecStep e;
-    e.pass = (int)plan.passes.size() - 1;
-    plan.exec.push_back(e);
+    e.pass = (int)passes.size() - 1;
+    exec.push_back(e);
     rem.swap(keep);
   }
   if (first) {
     Pass p;
     p.k = k;
     for (int q = 0; q < n; ++q) (q < k ? p.tq : p.oq).push_back(q);
-    p.flags = PASS_INIT_ZERO;
-    plan.passes.push_back(p);
+    p.flags = init_zero ? PASS_INIT_ZERO : 0u;
+    passes.push_back(p);
     ExecStep e;
     e.pass = 0;
-    plan.exec.push_back(e);
+    exec.push_back(e);
   }
   // site -> slots
-  plan.site_slots.assign(plan.sites.size(), {});
-  for (size_t p = 0; p < plan.passes.size(); ++p)
-    for (size_t s = 0; s < plan.passes[p].slots.size(); ++s)
-      for (int site : plan.passes[p].slots[s].sites) plan.site_slots[site].push_back({(int)p, (int)s});
-  for (auto& ps : plan.passes)
+  site_slots.assign(plan.sites.size(), {});
+  for (size_t p = 0; p < passes.size(); ++p)
+    for (size_t s = 0; s < passes[p].slots.size(); ++s)
+      for (int site : passes[p].slots[s].sites) site_slots[site].push_back({(int)p, (int)s});
+  for (auto& ps : passes)
     if (ps.slots.size() > 4096) return fail(PTSBE_E_UNSUPPORTED, "too many fused slots in one pass");
   return PTSBE_OK;
 }
@@ -800,8 +835,40 @@ ptsbe_status build_plan(const ptsbe_circuit* c, const ptsbe_noise_model* nm, con
     for (double p : ch.p) P.site_p.push_back(p);
     P.site_off.push_back((uint32_t)P.site_p.size());
   }
-  ptsbe_status st = schedule(P);
+  ptsbe_status st = schedule(P, P.steps, P.passes, P.exec, P.site_slots, true, true, P.tile_bits);
   if (st != PTSBE_OK) return st;
+  // Reverse-sweep program of the adjoint gradient: the steps in reverse order,
+  // each applied as its adjoint, with a DOT marker (Im<lambda|P|psi>) just before
+  // un-applying every parametrised rotation.  Only for circuits without
+  // measure-reset / projection (state-independent unitary trajectories).
+  bool unitary = true;
+  for (const Step& s : P.steps) unitary = unitary && s.kind != ST_MR && s.kind != ST_P0;
+  if (P.n_params > 0 && unitary) {
+    Program& A = P.adj;
+    int ndot = 0;
+    for (int i = (int)P.steps.size() - 1; i >= 0; --i) {
+      const Step& s = P.steps[i];
+      if (s.kind == ST_PARAM) {
+        Step d;
+        d.kind = ST_DOT;
+        d.nq = 1;
+        d.q[0] = s.q[0];
+        d.gen = s.gen;
+        d.param = s.param;
+        d.dot = ndot++;
+        A.steps.push_back(d);
+        A.dot_param.push_back(s.param);
+        A.dot_gen.push_back(s.gen);
+      }
+      Step r = s;
+      r.dagger = true;
+      A.steps.push_back(r);
+    }
+    // two tiles (psi and lambda) share the LDS: one tile bit less
+    st = schedule(P, A.steps, A.passes, A.exec, A.site_slots, false, false, std::max(4, P.tile_bits - 1));
+    if (st != PTSBE_OK) return st;
+    P.has_adjoint = true;
+  }
   *out = plan;
   return PTSBE_OK;
 }

@@ -353,12 +353,14 @@ static void put(std::vector<uint8_t>& blob, uint64_t off, const T* src, size_t n
   if (n) std::memcpy(blob.data() + off, src, n * sizeof(T));
 }
 
-ptsbe_status build_tables(TrajSet& ts, const double* params, uint32_t chunk) {
-  const Plan& P = *ts.plan;
-  std::vector<double> pv(params ? params : nullptr, params ? params + P.n_params : nullptr);
-  if (ts.table_valid && pv == ts.cached_params && chunk == ts.cached_chunk) return PTSBE_OK;
+// Device tables of one fused program (forward or adjoint) for a trajectory set.
+static void program_tables(const Plan& P, const std::vector<Step>& steps, const std::vector<Pass>& prog_passes,
+                           const std::vector<ExecStep>& prog_exec,
+                           const std::vector<std::vector<std::pair<int, int>>>& site_slots, const TrajSet& ts,
+                           const std::vector<double>& pv, uint32_t chunk, std::vector<uint8_t>& blob_out,
+                           TableLayout& L_out, std::vector<uint64_t>& chunk_off_out) {
   const uint32_t B = (uint32_t)ts.m.size();
-  const uint32_t NP = (uint32_t)P.passes.size();
+  const uint32_t NP = (uint32_t)prog_passes.size();
   std::vector<DPass> passes(NP);
   std::vector<DOp> ops;
   std::vector<uint32_t> slot_default;
@@ -366,7 +368,7 @@ ptsbe_status build_tables(TrajSet& ts, const double* params, uint32_t chunk) {
   std::vector<uint32_t> slot_base(NP);
   std::map<int, int> empty;
   for (uint32_t p = 0; p < NP; ++p) {
-    const Pass& ps = P.passes[p];
+    const Pass& ps = prog_passes[p];
     DPass& d = passes[p];
     std::memset(&d, 0, sizeof(d));
     d.k = (uint32_t)ps.k;
@@ -380,7 +382,7 @@ ptsbe_status build_tables(TrajSet& ts, const double* params, uint32_t chunk) {
     ops.insert(ops.end(), ps.ops.begin(), ps.ops.end());
     slot_base[p] = (uint32_t)slot_default.size();
     for (const Slot& s : ps.slots) {
-      Mat M = slot_matrix(P, s, pv.empty() ? nullptr : pv.data(), empty);
+      Mat M = slot_matrix(P, steps, s, pv.empty() ? nullptr : pv.data(), empty);
       slot_default.push_back((uint32_t)pool.size());
       pool.insert(pool.end(), M.begin(), M.end());
     }
@@ -393,7 +395,7 @@ ptsbe_status build_tables(TrajSet& ts, const double* params, uint32_t chunk) {
     std::map<std::pair<int, int>, std::map<int, int>> touched;  // (pass, slot) -> site choices
     for (uint32_t j = ts.rec_off[a]; j < ts.rec_off[a + 1]; ++j) {
       int site = (int)ts.rec_site[j];
-      for (auto& ps : P.site_slots[site]) touched[ps][site] = ts.rec_kraus[j];
+      for (auto& ps : site_slots[site]) touched[ps][site] = ts.rec_kraus[j];
     }
     std::vector<std::vector<DOverride>> per_pass(NP);
     for (auto& kv : touched) {
@@ -405,7 +407,7 @@ ptsbe_status build_tables(TrajSet& ts, const double* params, uint32_t chunk) {
       if (it != dedupe.end()) {
         off = it->second;
       } else {
-        Mat M = slot_matrix(P, P.passes[p].slots[s], pv.empty() ? nullptr : pv.data(), kv.second);
+        Mat M = slot_matrix(P, steps,prog_passes[p].slots[s], pv.empty() ? nullptr : pv.data(), kv.second);
         off = (uint32_t)pool.size();
         pool.insert(pool.end(), M.begin(), M.end());
         dedupe.emplace(dk, off);
@@ -436,11 +438,11 @@ ptsbe_status build_tables(TrajSet& ts, const double* params, uint32_t chunk) {
   L.ov = o; o = align256(o + std::max<size_t>(1, ov.size()) * sizeof(DOverride));
   L.shot_off = o; o = align256(o + shot_off.size() * 8);
   L.chunk_off = o; o = align256(o + chunk_off.size() * 8);
-  std::vector<DExec> exec(P.exec.size());
-  for (size_t e = 0; e < P.exec.size(); ++e) {
+  std::vector<DExec> exec(prog_exec.size());
+  for (size_t e = 0; e < prog_exec.size(); ++e) {
     DExec& d = exec[e];
     std::memset(&d, 0, sizeof(d));
-    const ExecStep& ex = P.exec[e];
+    const ExecStep& ex = prog_exec[e];
     d.pass = ex.pass >= 0 ? (uint32_t)ex.pass : 0xffffffffu;
     d.nq = (uint32_t)std::min<size_t>(16, ex.mr_qubits.size());
     for (uint32_t j = 0; j < d.nq; ++j) {
@@ -480,13 +482,32 @@ ptsbe_status build_tables(TrajSet& ts, const double* params, uint32_t chunk) {
   put(blob, L.shot_off, shot_off.data(), shot_off.size());
   put(blob, L.chunk_off, chunk_off.data(), chunk_off.size());
   put(blob, L.exec, exec.data(), exec.size());
-  ts.table_blob.swap(blob);
-  ts.layout = L;
+  blob_out.swap(blob);
+  L_out = L;
+  chunk_off_out = chunk_off;
+}
+
+ptsbe_status build_tables(TrajSet& ts, const double* params, uint32_t chunk) {
+  const Plan& P = *ts.plan;
+  std::vector<double> pv(params ? params : nullptr, params ? params + P.n_params : nullptr);
+  if (ts.table_valid && pv == ts.cached_params && chunk == ts.cached_chunk) return PTSBE_OK;
+  program_tables(P, P.steps, P.passes, P.exec, P.site_slots, ts, pv, chunk, ts.table_blob, ts.layout, ts.chunk_off);
   ts.cached_params = pv;
   ts.cached_chunk = chunk;
-  ts.pool_elems = pool.size();
-  ts.chunk_off = chunk_off;
   ts.table_valid = true;
+  return PTSBE_OK;
+}
+
+ptsbe_status build_adj_tables(TrajSet& ts, const double* params) {
+  const Plan& P = *ts.plan;
+  if (!P.has_adjoint) return fail(PTSBE_E_UNSUPPORTED, "no adjoint program (no parameters, or measure-reset/projection)");
+  std::vector<double> pv(params ? params : nullptr, params ? params + P.n_params : nullptr);
+  if (ts.adj_valid && pv == ts.adj_params) return PTSBE_OK;
+  std::vector<uint64_t> chunk_off;
+  program_tables(P, P.adj.steps, P.adj.passes, P.adj.exec, P.adj.site_slots, ts, pv, 4096, ts.adj_blob,
+                 ts.adj_layout, chunk_off);
+  ts.adj_params = pv;
+  ts.adj_valid = true;
   return PTSBE_OK;
 }
 

@@ -1,0 +1,117 @@
+"""The C ABI: libptsbe.so loads on a host without a GPU, exports every entry
+point include/ptsbe.h declares, and rejects bad input with the documented
+status codes before any device work (no compute calls here)."""
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2504_16297_amd as P
+from paper_2504_16297_amd import _lib as L
+from workloads import random_small_circuit
+from workloads.circuits import hea_circuit, zz_ring
+
+HEADER = os.path.join(os.path.dirname(__file__), "..", "include", "ptsbe.h")
+
+E_ARG, E_NOT_CPTP, E_UNSUPPORTED, E_OOM = 1, 2, 3, 5
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ptsbe_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = _declared()
+    assert len(names) >= 18
+    lib = C.CDLL(L.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(names) == set(L.EXPORTED)
+
+
+def test_version_and_last_error():
+    assert P.lib().ptsbe_version().decode().startswith("ptsbe")
+    with pytest.raises(P.PtsbeError):
+        P.ptsbe_plan({"n_qubits": 2, "ops": [{"kind": "gate", "name": "H", "qubits": (5,), "params": ()}],
+                      "channels": [], "rules": []})
+    assert b"qubit" in P.lib().ptsbe_last_error()
+
+
+def _status(fn, *a, **k):
+    with pytest.raises(P.PtsbeError) as e:
+        fn(*a, **k)
+    return e.value.status
+
+
+def _one_gate(ch):
+    return {"n_qubits": 2, "ops": [{"kind": "gate", "name": "H", "qubits": (0,), "params": (), "tag": "H"},
+                                   {"kind": "noise", "channel": 0, "qubits": (0,)}],
+            "channels": [ch], "rules": []}
+
+
+def test_channel_checks():
+    # sum K^dagger K != I
+    bad = {"kraus": [1.05 * np.eye(2)]}
+    assert _status(P.ptsbe_plan, _one_gate(bad)) == E_NOT_CPTP
+    # CPTP but not a unitary mixture: outside batched pre-trajectory sampling
+    assert _status(P.ptsbe_plan, _one_gate({"name": "amplitude_damping", "gamma": 0.2})) == E_UNSUPPORTED
+    # a custom unitary mixture given as explicit Kraus operators is accepted
+    X = np.array([[0, 1], [1, 0]])
+    ok = {"kraus": [np.sqrt(0.9) * np.eye(2), np.sqrt(0.1) * X]}
+    plan = P.ptsbe_plan(_one_gate(ok))
+    assert plan.info["n_sites"] == 1
+
+
+def test_circuit_checks():
+    circ = {"n_qubits": 3, "ops": [{"kind": "gate", "name": "CZ", "qubits": (1, 1), "params": ()}],
+            "channels": [], "rules": []}
+    assert _status(P.ptsbe_plan, circ) == E_ARG
+    circ = {"n_qubits": 3, "ops": [{"kind": "noise", "channel": 4, "qubits": (0,)}], "channels": [],
+            "rules": []}
+    assert _status(P.ptsbe_plan, circ) == E_ARG
+    circ = {"n_qubits": 3, "ops": [{"kind": "param", "gen": "Y", "qubits": (3,), "index": 0}],
+            "channels": [], "rules": []}
+    assert _status(P.ptsbe_plan, circ) == E_ARG
+
+
+def _adjoint_status(plan, ts, params, obs, ws=None, nbytes=0):
+    coef = np.asarray([c for c, _ in obs], dtype=np.float64)
+    zm = np.asarray([sum(1 << q for q in qs) for _, qs in obs], dtype=np.uint64)
+    pa = np.ascontiguousarray(params, dtype=np.float64) if params is not None else None
+    return P.lib().ptsbe_adjoint_grad(plan.handle, ts.handle, P._dptr(pa) if pa is not None else None,
+                                      P._dptr(coef), C.cast(zm.ctypes.data, C.POINTER(C.c_uint64)), len(obs),
+                                      ws, nbytes, None, None, None)
+
+
+def test_adjoint_argument_checks():
+    circ = random_small_circuit(4, 20, np.random.default_rng(1))
+    plan = P.ptsbe_plan(circ)
+    ts = P.ptsbe_trajset_from_records(plan, [()], [1])
+    assert _adjoint_status(plan, ts, [0.0], [(1.0, (0,))]) == E_UNSUPPORTED   # no parameters
+    mr = hea_circuit(3, 1, np.random.default_rng(0), 0.01)
+    mr["ops"].append({"kind": "measure_reset", "qubits": (0,)})
+    plan = P.ptsbe_plan(mr)
+    ts = P.ptsbe_trajset_from_records(plan, [()], [1])
+    assert _adjoint_status(plan, ts, mr["params"], [(1.0, (0,))]) == E_UNSUPPORTED
+    circ = hea_circuit(4, 2, np.random.default_rng(0), 0.01)
+    plan = P.ptsbe_plan(circ)
+    ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=8, total_shots=8, seed=1, cfg=5)
+    assert _adjoint_status(plan, ts, circ["params"], [(1.0, (4,))]) == E_ARG      # qubit >= n
+    assert _adjoint_status(plan, ts, None, zz_ring(4)) == E_ARG                   # no parameters given
+    assert _adjoint_status(plan, ts, circ["params"], zz_ring(4)) == E_ARG         # null device pointers
+
+
+def test_adjoint_workspace_query_runs_on_host():
+    circ = hea_circuit(10, 2, np.random.default_rng(0), 0.02)
+    plan = P.ptsbe_plan(circ)
+    ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=20, total_shots=20, seed=1, cfg=5)
+    full = P.ptsbe_workspace_size(plan, ts, "adjoint", params=circ["params"])
+    one = P.ptsbe_workspace_size(plan, ts, "adjoint", max_batch=1, params=circ["params"])
+    state = (1 << 10) * 8
+    assert full >= one + 2 * (ts.n_traj - 1) * state
+    assert one >= 2 * state

@@ -6,12 +6,13 @@ import numpy as np
 import pytest
 
 import paper_2504_16297_amd as P
-from program_emulator import export_tables, run_program
+from oracle.adjoint import ensemble_value_and_grad, observable_diag
+from program_emulator import export_adjoint_tables, export_tables, run_adjoint, run_program
 from oracle.noise import expand, site_channels
 from oracle.statevector import run_record
 from oracle.stabilizer import frame_run
 from workloads import c1_workload, c3_workload, random_small_circuit
-from workloads.circuits import hea_circuit
+from workloads.circuits import hea_circuit, zz_ring
 
 
 def _check(circ, plan, ts, params=None, tol=1e-10):
@@ -66,3 +67,40 @@ def test_surface_code_program_records():
         fb, _ = frame_run(circ, g["records"][a])
         assert bits[j] == fb, f"trajectory {a}: {g['records'][a]}"
     del tabs
+
+
+@pytest.mark.parametrize("n,tile,prec", [(6, 0, "c128"), (8, 5, "c64"), (9, 6, "c128")])
+def test_adjoint_program_gradient(n, tile, prec):
+    """The reverse-sweep tables, run by the emulator, give the oracle's adjoint
+    gradient (itself pinned by parameter shift)."""
+    circ = random_small_circuit(n, 60, np.random.default_rng(40 + n), p1=0.1, p2=0.15, with_params=True)
+    params = np.asarray(circ["params"])
+    plan = P.ptsbe_plan(circ, precision=prec, tile_qubits=tile)
+    ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=6, total_shots=6, seed=3, cfg=7)
+    g = ts.get()
+    w = g["count"].astype(np.float64) / g["count"].sum()
+    obs = [(0.7, (0,)), (-1.3, (1, n - 1)), (0.4, tuple(range(n)))]
+    fwd = export_tables(ts, params)
+    adj, dot_param = export_adjoint_tables(ts, params)
+    tol = 1e-5 if prec == "c64" else 1e-10
+    E, G = run_adjoint(fwd, adj, dot_param, n, ts.n_traj, params.size, observable_diag(n, obs), w,
+                       back_tol=1e-9 if prec == "c128" else 1e-5)
+    Er, Gr = ensemble_value_and_grad(circ, g["records"], w, params, obs)
+    assert abs(E - Er) <= tol
+    assert np.max(np.abs(G - Gr)) <= tol * max(1.0, np.max(np.abs(Gr)))
+
+
+def test_adjoint_program_hea():
+    circ = hea_circuit(7, 3, np.random.default_rng(5), 0.03)
+    params = np.asarray(circ["params"])
+    plan = P.ptsbe_plan(circ, precision="c128")
+    ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=5, total_shots=5, seed=1, cfg=5)
+    g = ts.get()
+    w = g["count"].astype(np.float64) / g["count"].sum()
+    fwd = export_tables(ts, params)
+    adj, dot_param = export_adjoint_tables(ts, params)
+    assert sorted(set(dot_param.tolist())) == list(range(params.size))
+    E, G = run_adjoint(fwd, adj, dot_param, 7, ts.n_traj, params.size, observable_diag(7, zz_ring(7)), w)
+    Er, Gr = ensemble_value_and_grad(circ, g["records"], w, params, zz_ring(7))
+    assert abs(E - Er) <= 1e-10
+    assert np.max(np.abs(G - Gr)) <= 1e-10 * max(1.0, np.max(np.abs(Gr)))
