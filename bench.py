@@ -28,6 +28,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "shots/s batched PTSBE vs per-shot trajectories; gate-kernel HBM GB/s"
 HBM_PEAK_GBS = 8000.0
+# FP32 vector peak of MI355X: 256 CUs x 2.4 GHz x 256 FLOP/clk/CU
+FP32_PEAK_TFLOPS = 157.3
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "tile_pass_c2_traffic.md")
 
 
 def log(msg):
@@ -35,11 +38,12 @@ def log(msg):
     sys.stderr.flush()
 
 
-def cpu_baseline(wl, n_traj_sample, g):
-    """The oracle (complex128 NumPy) on the first ``n_traj_sample`` trajectories:
-    state preparation + sampling of their shots, extrapolated to whole-job shots/s
-    by the average number of shots per trajectory."""
+def cpu_baseline(wl, g, budget_s=12.0):
+    """The oracle (complex128 NumPy, one thread) on the first trajectories of the
+    set until ``budget_s`` seconds have passed (at least one): state preparation
+    + sampling of the average shot count, extrapolated to whole-job shots/s."""
     import numpy as np
+    from threadpoolctl import threadpool_limits
     from oracle.noise import expand, site_channels
     from oracle.sampling import sample
     from oracle.statevector import run_record
@@ -47,17 +51,28 @@ def cpu_baseline(wl, n_traj_sample, g):
     ss = expand(circ)
     ch = site_channels(circ)
     avg_m = float(np.mean(g["m"]))
-    t0 = time.perf_counter()
-    for a in range(n_traj_sample):
-        psi, _ = run_record(circ, g["records"][a], steps_sites=ss, chans=ch)
-        sample(psi, int(round(avg_m)), wl["seed"], wl["cfg"], a)
-    dt = time.perf_counter() - t0
-    threads = os.environ.get("OMP_NUM_THREADS") or os.environ.get("OPENBLAS_NUM_THREADS")
-    return {"value": n_traj_sample * avg_m / dt, "unit": "shots/s", "cores": int(threads) if threads else 1,
-            "kind": "oracle",
-            "sample": f"{n_traj_sample} of {len(g['m'])} trajectories prepared by the complex128 oracle "
-                      f"and sampled at the average {avg_m:.0f} shots each ({dt:.1f} s), extrapolated "
-                      f"linearly to the whole job"}
+    done = 0
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        while done < len(g["m"]) and (done == 0 or time.perf_counter() - t0 < budget_s):
+            psi, _ = run_record(circ, g["records"][done], steps_sites=ss, chans=ch)
+            sample(psi, int(round(avg_m)), wl["seed"], wl["cfg"], done)
+            done += 1
+        dt = time.perf_counter() - t0
+    return {"value": done * avg_m / dt, "unit": "shots/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} of {len(g['m'])} trajectories prepared by the complex128 oracle on one "
+                      f"thread and sampled at the average {avg_m:.0f} shots each ({dt:.1f} s), "
+                      f"extrapolated linearly to the whole job"}
+
+
+def measured_traffic():
+    """HBM bytes per tile-pass dispatch from the committed counter summary, or
+    None when the kernel source has changed since the counters were taken."""
+    from paper_2504_16297_amd.profile_summary import kernel_source_sha, read_traffic
+    r = read_traffic(TRAFFIC_SUMMARY)
+    if r is None or r[1] != kernel_source_sha():
+        return None
+    return r[0]
 
 
 def main():
@@ -107,8 +122,9 @@ def main():
     g = ts.get()
     B = len(g["m"])
     S = int(g["total_shots"])
-    log(f"[bench] {wl['name']}: {B} unique trajectories, {plan.info['n_passes']} tile passes, "
-        f"plan {t_plan*1e3:.1f} ms, PTS {t_pts*1e3:.1f} ms")
+    n_kernels, t_compile = P.ptsbe_plan_compile(plan)
+    log(f"[bench] {wl['name']}: {B} unique trajectories, {plan.info['n_passes']} tile passes "
+        f"({n_kernels} compiled kernels, {t_compile:.1f} s), plan {t_plan*1e3:.1f} ms, PTS {t_pts*1e3:.1f} ms")
 
     ws_bytes = P.ptsbe_workspace_size(plan, ts, mode="shots")
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
@@ -127,7 +143,7 @@ def main():
     timings = []
     t0 = time.perf_counter()
     for i in range(args.steps):
-        tm = np.zeros(8)
+        tm = np.zeros(10)
         step(tm)
         timings.append(tm)
     torch.cuda.synchronize()
@@ -138,6 +154,8 @@ def main():
     pass_ms = T[0] / T[1]
     pass_bytes = T[6] / T[1]
     gbs = pass_bytes / (pass_ms * 1e-3) / 1e9
+    pass_flops = T[8] / T[1]
+    tflops = pass_flops / (pass_ms * 1e-3) / 1e12
     log(f"[bench] {ms_per_step:.2f} ms/step, {value:.4g} shots/s; passes {T[0]/args.steps:.2f} ms/step "
         f"({T[1]/args.steps:.0f} launches), scan {T[3]/args.steps:.2f} ms, sampler {T[4]/args.steps:.2f} ms")
 
@@ -146,13 +164,17 @@ def main():
               "vs_baseline": None, "dtype": "c64 (fp32 state, fp64 norm/CDF)", "data": "synthetic",
               "config": {"workload": wl["name"], "n_qubits": 20, "layers": 40, "draws": pts["n_draws"],
                          "unique_trajectories": B, "total_shots": S, "parallelism": "single GPU, batched"},
-              "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": gbs / HBM_PEAK_GBS, "traffic": None,
-                           "kernel": "k_pass (fused tile pass)",
-                           "avg_launch_ms": pass_ms, "bytes_per_launch": pass_bytes},
+              "roofline": {"bound": "alu", "achieved": tflops, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                           "frac": tflops / FP32_PEAK_TFLOPS, "traffic": measured_traffic(),
+                           "kernel": "ptsbe_pass_* (compiled fused tile passes)", "avg_launch_ms": pass_ms,
+                           "flops_per_launch": pass_flops, "bytes_per_launch": pass_bytes,
+                           "hbm": {"achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                   "frac": gbs / HBM_PEAK_GBS}},
               "stages_ms_per_step": {"passes": T[0] / args.steps, "scan": T[3] / args.steps,
                                      "sampler": T[4] / args.steps, "total_events": T[5] / args.steps},
-              "plan_ms": t_plan * 1e3, "pts_ms": t_pts * 1e3}
+              "state_passes_per_step": T[9] / args.steps, "state_passes_unshared": B * plan.info["n_passes"],
+              "plan_ms": t_plan * 1e3, "pts_ms": t_pts * 1e3, "compile_s": t_compile,
+              "compiled_kernels": n_kernels}
 
     if not args.no_baseline:
         nb = args.baseline_shots
@@ -179,7 +201,7 @@ def main():
 
     if not args.no_cpu:
         log("[bench] timing the oracle on the host ...")
-        result["cpu_baseline"] = cpu_baseline(wl, 1, g)
+        result["cpu_baseline"] = cpu_baseline(wl, g)
     print(json.dumps(result))
 
 

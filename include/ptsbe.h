@@ -127,9 +127,14 @@ enum { PTSBE_C64 = 0, PTSBE_C128 = 1 };
 typedef struct {
     uint32_t precision;         /* PTSBE_C64 (FP32 state) or PTSBE_C128 (FP64 state) */
     uint32_t tile_qubits;       /* 0 = automatic; else qubits per LDS tile (4..13) */
-    uint32_t flags;             /* reserved, 0 */
+    uint32_t flags;             /* bits 0..2: fewest 2x2 matrices per register group worth a
+                                   partial group (0 = 3); PTSBE_PLAN_NO_COMPILE */
     uint32_t reserved;
 } ptsbe_plan_opts;
+
+/* Run every pass through the generic (interpreting) tile kernels instead of
+ * the per-pass kernels the plan compiles for itself (see ptsbe_plan_compile). */
+#define PTSBE_PLAN_NO_COMPILE 8u
 
 typedef struct ptsbe_plan_s* ptsbe_plan_t;
 typedef struct ptsbe_trajset_s* ptsbe_trajset_t;
@@ -154,6 +159,18 @@ typedef struct {
 ptsbe_status ptsbe_plan(const ptsbe_circuit* circuit, const ptsbe_noise_model* noise,
                         const ptsbe_plan_opts* opts, ptsbe_plan_t* out);
 ptsbe_status ptsbe_plan_get_info(ptsbe_plan_t plan, ptsbe_plan_info* out);
+/* Compile the plan's tile passes into their own gfx950 kernels (hiprtc; host
+ * only, no device needed): each pass's operation list is unrolled into
+ * straight-line register code, structurally equal passes share a kernel.
+ * ptsbe_run_batch calls this on first use; calling it first moves the cost
+ * (about a second per distinct pass, in parallel threads) out of the run.
+ * *n_kernels / *seconds (optional) receive the kernel count and compile time.
+ * PTSBE_E_DEVICE carries the compiler log if compilation fails. */
+ptsbe_status ptsbe_plan_compile(ptsbe_plan_t plan, uint32_t* n_kernels, double* seconds);
+/* Inspection: the generated HIP source of pass `pass` (kernel symbol
+ * "ptsbe_pass"), NUL-terminated; an empty string if that pass runs through the
+ * generic kernels.  With out == NULL only *len (bytes including the NUL) is set. */
+ptsbe_status ptsbe_plan_pass_source(ptsbe_plan_t plan, uint32_t pass, char* out, size_t* len);
 /* Per-site probabilities p_{s,k}: offsets[n_sites+1] into probs[total_kraus];
  * qubits[2*n_sites] (second entry 0xffffffff for 1-qubit sites); either may be NULL. */
 ptsbe_status ptsbe_plan_get_sites(ptsbe_plan_t plan, uint32_t* offsets, double* probs,
@@ -235,14 +252,23 @@ typedef struct {
     const double* obs_coef;     /* EXPECTATION: n_terms coefficients (host) */
     const uint64_t* obs_zmask;  /* EXPECTATION: n_terms Z-string qubit masks (host) */
     uint32_t n_terms;
-    uint32_t reserved;
-    double* timing;             /* optional host array[8]: measured with HIP events on `stream`
+    uint32_t flags;             /* PTSBE_RUN_NO_PREFIX_SHARING: every trajectory runs every pass */
+    double* timing;             /* optional host array[10]: measured with HIP events on `stream`
                                    (the call then waits for the stream): [0] ms in tile passes,
                                    [1] pass launches, [2] ms in measure-reset steps, [3] ms in
                                    norm/CDF scans, [4] ms in the sampler, [5] ms total,
                                    [6] state bytes moved by the passes (2 x state size per loaded
-                                   pass, 1 x for the initialising pass), [7] sampler launches */
+                                   state-pass, 1 x for the initialising pass), [7] sampler
+                                   launches, [8] useful FLOPs of the passes (per amplitude: 14 per
+                                   2x2 matrix, 30 per 4x4, 6 per diagonal), [9] state-passes run */
 } ptsbe_run_opts;
+
+/* Prefix sharing (default for plans without measure-resets): a trajectory's
+ * passes before the first one its noise record changes are not run for it;
+ * one error-free state (double-buffered, two extra states of workspace) is
+ * carried through those passes and each trajectory's first own pass reads it.
+ * Results are bit-identical to running every pass for every trajectory. */
+#define PTSBE_RUN_NO_PREFIX_SHARING 1u
 
 /* Device workspace in bytes needed by ptsbe_run_batch, or with
  * opts->mode == PTSBE_RUN_ADJOINT by ptsbe_adjoint_grad (max_batch bounds the
@@ -262,6 +288,22 @@ ptsbe_status ptsbe_workspace_size(ptsbe_plan_t plan, ptsbe_trajset_t ts, const p
 ptsbe_status ptsbe_run_batch(ptsbe_plan_t plan, ptsbe_trajset_t ts, const ptsbe_run_opts* opts,
                              void* d_ws, size_t ws_bytes, void* d_bits, uint32_t* d_traj,
                              uint64_t capacity, uint8_t* d_mr_bits, void* stream);
+
+/* Captured execution (HIP graph): the same arguments as ptsbe_run_batch.  The
+ * tables are uploaded into the workspace now (the call waits for `stream`),
+ * then the run's device work -- tile passes, measure-resets, scans, sampler --
+ * is captured from `stream` (a created stream, not the default one) and
+ * instantiated.  Each ptsbe_graph_launch replays it: same inputs, same
+ * outputs, no host work.  The workspace and output buffers must outlive the
+ * graph and must not be reused by other calls in between.  opts->timing must
+ * be NULL. */
+typedef struct ptsbe_graph_s* ptsbe_graph_t;
+ptsbe_status ptsbe_graph_create(ptsbe_plan_t plan, ptsbe_trajset_t ts, const ptsbe_run_opts* opts,
+                                void* d_ws, size_t ws_bytes, void* d_bits, uint32_t* d_traj,
+                                uint64_t capacity, uint8_t* d_mr_bits, void* stream,
+                                ptsbe_graph_t* out);
+ptsbe_status ptsbe_graph_launch(ptsbe_graph_t graph, void* stream);
+void ptsbe_graph_destroy(ptsbe_graph_t graph);
 
 /* Inspection: the device tables a run of `ts` would upload (fused passes, ops,
  * slot matrices, per-trajectory overrides, shot and chunk offsets, execution

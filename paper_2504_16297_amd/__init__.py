@@ -15,9 +15,9 @@ import numpy as np
 from . import _lib as L
 from ._lib import PtsbeError, lib, check
 
-__all__ = ["ptsbe_plan", "ptsbe_sample_kraus", "ptsbe_trajset_from_records", "ptsbe_workspace_size",
-           "ptsbe_run_batch", "ptsbe_run_status", "ptsbe_adjoint_grad", "std_gate", "std_channel",
-           "Plan", "TrajSet", "PtsbeError", "tag_id"]
+__all__ = ["ptsbe_plan", "ptsbe_plan_compile", "ptsbe_sample_kraus", "ptsbe_trajset_from_records",
+           "ptsbe_workspace_size", "ptsbe_run_batch", "ptsbe_run_status", "ptsbe_adjoint_grad", "std_gate",
+           "std_channel", "Plan", "TrajSet", "RunGraph", "PtsbeError", "tag_id"]
 
 
 def tag_id(tag):
@@ -93,8 +93,19 @@ class Plan:
             self.handle = None
 
 
-def ptsbe_plan(circuit, precision="c64", tile_qubits=0):
-    """Build the execution plan of a circuit dictionary (ops, channels, rules)."""
+def ptsbe_plan_compile(plan):
+    """Compile the plan's tile passes now (else the first run does); returns
+    (number of kernels, seconds)."""
+    nk = C.c_uint32()
+    sec = C.c_double()
+    check(lib().ptsbe_plan_compile(plan.handle, C.byref(nk), C.byref(sec)))
+    return nk.value, sec.value
+
+
+def ptsbe_plan(circuit, precision="c64", tile_qubits=0, compile=True):
+    """Build the execution plan of a circuit dictionary (ops, channels, rules).
+    ``compile=False`` runs the passes through the generic tile kernels instead of
+    per-pass compiled kernels."""
     ops = circuit["ops"]
     arr = (L.Op * max(1, len(ops)))()
     keep = []
@@ -155,7 +166,8 @@ def ptsbe_plan(circuit, precision="c64", tile_qubits=0):
             raise ValueError(w)
     c = L.Circuit(circuit["n_qubits"], len(ops), arr)
     nm = L.NoiseModel(len(chans), carr, len(rules), rarr)
-    po = L.PlanOpts({"c64": L.C64, "c128": L.C128}[precision], int(tile_qubits), 0, 0)
+    po = L.PlanOpts({"c64": L.C64, "c128": L.C128}[precision], int(tile_qubits),
+                    0 if compile else L.PLAN_NO_COMPILE, 0)
     h = C.c_void_p()
     check(lib().ptsbe_plan(C.byref(c), C.byref(nm), C.byref(po), C.byref(h)))
     return Plan(h, None)
@@ -240,11 +252,14 @@ def ptsbe_trajset_from_records(plan, records, m, alpha0=0):
 
 
 def _run_opts(mode, seed, cfg, sort_chunk, max_batch, uniforms, params, state_out, expval, observable,
-              timing=None):
+              timing=None, prefix_sharing=True):
     o = L.RunOpts()
     if timing is not None:
+        if timing.dtype != np.float64 or timing.size < 10:
+            raise ValueError("timing must be a float64 array of at least 10 entries")
         o.timing = _dptr(timing)
     o.mode = mode
+    o.flags = 0 if prefix_sharing else L.RUN_NO_PREFIX_SHARING
     o.seed = int(seed)
     o.cfg = int(cfg)
     o.sort_chunk = int(sort_chunk)
@@ -267,11 +282,12 @@ def _run_opts(mode, seed, cfg, sort_chunk, max_batch, uniforms, params, state_ou
     return o, keep
 
 
-def ptsbe_workspace_size(plan, ts, mode="shots", sort_chunk=0, max_batch=0, params=None):
+def ptsbe_workspace_size(plan, ts, mode="shots", sort_chunk=0, max_batch=0, params=None, prefix_sharing=True):
     m = {"shots": L.RUN_SHOTS, "states": L.RUN_STATES, "expectation": L.RUN_EXPECTATION,
          "adjoint": L.RUN_ADJOINT}[mode]
     pa = None if params is None else np.ascontiguousarray(params, dtype=np.float64)
-    o, keep = _run_opts(m, 0, 0, sort_chunk, max_batch, None, pa, None, None, None)
+    o, keep = _run_opts(m, 0, 0, sort_chunk, max_batch, None, pa, None, None, None,
+                        prefix_sharing=prefix_sharing)
     n = C.c_size_t()
     check(lib().ptsbe_workspace_size(plan.handle, ts.handle, C.byref(o), C.byref(n)))
     return n.value
@@ -283,12 +299,16 @@ def _stream(torch, stream):
 
 
 def ptsbe_run_batch(plan, ts, mode="shots", seed=0, cfg=0, sort_chunk=0, max_batch=0, uniforms=None,
-                    params=None, observable=None, workspace=None, out=None, stream=None, timing=None):
+                    params=None, observable=None, workspace=None, out=None, stream=None, timing=None,
+                    prefix_sharing=True, capture=False):
     """Batched execution (Sec. 3).  Returns a dict of device tensors:
     shots: bits (int32 or int64 basis indices), traj (int32 trajectory ids), mr_bits;
     states: states (n_traj x 2^n complex); expectation: expval (n_traj float64).
-    ``timing``: optional float64 numpy array of 8 entries filled by the library's
-    HIP-event stage timer (the call then waits for the stream)."""
+    ``timing``: optional float64 numpy array of 10 entries filled by the library's
+    HIP-event stage timer (the call then waits for the stream).
+    ``prefix_sharing``: False runs every pass for every trajectory (same results).
+    ``capture``: record the run as a HIP graph on ``stream`` (a created stream)
+    instead of running it; the result's "graph" replays it (``graph.launch()``)."""
     import torch
     dev = torch.device("cuda")
     n = plan.info["n_qubits"]
@@ -308,7 +328,7 @@ def ptsbe_run_batch(plan, ts, mode="shots", seed=0, cfg=0, sort_chunk=0, max_bat
             expval = torch.empty(B, dtype=torch.float64, device=dev)
         res["expval"] = expval
     o, keep = _run_opts(mcode, seed, cfg, sort_chunk, max_batch, uniforms, params, state_out, expval,
-                        observable, timing)
+                        observable, timing, prefix_sharing)
     need = C.c_size_t()
     check(lib().ptsbe_workspace_size(plan.handle, ts.handle, C.byref(o), C.byref(need)))
     ws = workspace
@@ -332,14 +352,38 @@ def ptsbe_run_batch(plan, ts, mode="shots", seed=0, cfg=0, sort_chunk=0, max_bat
             mr = torch.empty((B, nm), dtype=torch.uint8, device=dev)
         res["mr_bits"] = mr
     cap = bits.numel() if bits is not None else 0
-    check(lib().ptsbe_run_batch(plan.handle, ts.handle, C.byref(o), C.c_void_p(ws.data_ptr()),
-                                ws.numel(), C.c_void_p(bits.data_ptr()) if bits is not None else None,
-                                C.c_void_p(traj.data_ptr()) if traj is not None else None, cap,
-                                C.c_void_p(mr.data_ptr()) if mr is not None else None,
-                                _stream(torch, stream)))
+    args = (plan.handle, ts.handle, C.byref(o), C.c_void_p(ws.data_ptr()), ws.numel(),
+            C.c_void_p(bits.data_ptr()) if bits is not None else None,
+            C.c_void_p(traj.data_ptr()) if traj is not None else None, cap,
+            C.c_void_p(mr.data_ptr()) if mr is not None else None, _stream(torch, stream))
     res["workspace"] = ws
     res["_keep"] = keep
+    if capture:
+        h = C.c_void_p()
+        check(lib().ptsbe_graph_create(*args, C.byref(h)))
+        res["graph"] = RunGraph(h, plan, ts, res)
+        return res
+    check(lib().ptsbe_run_batch(*args))
     return res
+
+
+class RunGraph:
+    """A captured ptsbe_run_batch (HIP graph): launch() replays the whole run on
+    a stream with the same inputs and outputs."""
+
+    def __init__(self, handle, plan, ts, buffers):
+        self.handle = handle
+        self._refs = (plan, ts, buffers)
+
+    def launch(self, stream=None):
+        import torch
+        check(lib().ptsbe_graph_launch(self.handle, _stream(torch, stream)))
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            lib().ptsbe_graph_destroy(h)
+            self.handle = None
 
 
 def ptsbe_run_status(plan, workspace, stream=None):

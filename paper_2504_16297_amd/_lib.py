@@ -22,6 +22,8 @@ C64, C128 = 0, 1
 PTS_MODES = {"proportional": 0, "alg2_literal": 1, "most_likely": 2, "per_shot": 3}
 ALLOCS = {"multiplicity": 0, "reweight": 1, "uniform": 2}
 RUN_SHOTS, RUN_STATES, RUN_EXPECTATION, RUN_ADJOINT = range(4)
+RUN_NO_PREFIX_SHARING = 1
+PLAN_NO_COMPILE = 8
 
 
 class Op(C.Structure):
@@ -72,7 +74,7 @@ class RunOpts(C.Structure):
                 ("d_uniforms", C.c_void_p), ("params", C.POINTER(C.c_double)),
                 ("d_state_out", C.c_void_p), ("d_expval", C.c_void_p),
                 ("obs_coef", C.POINTER(C.c_double)), ("obs_zmask", C.POINTER(C.c_uint64)),
-                ("n_terms", C.c_uint32), ("reserved", C.c_uint32),
+                ("n_terms", C.c_uint32), ("flags", C.c_uint32),
                 ("timing", C.POINTER(C.c_double))]
 
 
@@ -101,8 +103,15 @@ _SIGS = {
                                   C.c_size_t, C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p,
                                   C.c_void_p]),
     "ptsbe_run_status": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ptsbe_graph_create": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(RunOpts), C.c_void_p,
+                                     C.c_size_t, C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p,
+                                     C.c_void_p, C.POINTER(C.c_void_p)]),
+    "ptsbe_graph_launch": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "ptsbe_graph_destroy": (None, [C.c_void_p]),
     "ptsbe_trajset_tables": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_uint32, C.c_void_p,
                                        C.POINTER(C.c_size_t), C.c_void_p]),
+    "ptsbe_plan_compile": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint32), C.POINTER(C.c_double)]),
+    "ptsbe_plan_pass_source": (C.c_int, [C.c_void_p, C.c_uint32, C.c_char_p, C.POINTER(C.c_size_t)]),
     "ptsbe_trajset_adjoint_tables": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_void_p,
                                                C.POINTER(C.c_size_t), C.c_void_p, C.c_void_p, C.c_void_p]),
     "ptsbe_adjoint_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_double),

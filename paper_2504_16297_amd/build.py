@@ -20,7 +20,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libptsbe.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-HOST_SRCS = ["plan.cpp", "pts.cpp", "run.cpp", "abi.cpp", "adjoint.cpp"]
+HOST_SRCS = ["plan.cpp", "pts.cpp", "run.cpp", "abi.cpp", "adjoint.cpp", "jit.cpp"]
 DEVICE_SRCS = ["kernels.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-I" + os.path.join(ROOT, "include")]
@@ -56,7 +56,8 @@ def build(jobs=8, verbose=False):
             if o.strip():
                 sys.stdout.write(o)
     tmp = LIB + ".tmp"
-    _run([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs)
+    _run([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs +
+         ["-L/opt/rocm/lib", "-lhiprtc", "-Wl,-rpath,/opt/rocm/lib"])
     os.replace(tmp, LIB)
     return LIB
 

@@ -6,6 +6,7 @@
 #include <string>
 
 #include "host.hpp"
+#include "jit.hpp"
 
 namespace ptsbe {
 const char* last_error_cstr();
@@ -16,7 +17,8 @@ ptsbe_status trajset_from_records(const std::shared_ptr<Plan>& plan, uint32_t n,
 ptsbe_status trajset_slice(const TrajSet& ts, uint32_t b, uint32_t e, ptsbe_trajset_t* out);
 ptsbe_status workspace_size(const Plan& P, TrajSet& ts, const ptsbe_run_opts* o, size_t* bytes);
 ptsbe_status run_batch(const Plan& P, TrajSet& ts, const ptsbe_run_opts* o, void* d_ws, size_t ws_bytes,
-                       void* d_bits, uint32_t* d_traj, uint64_t capacity, uint8_t* d_mr_bits, void* stream);
+                       void* d_bits, uint32_t* d_traj, uint64_t capacity, uint8_t* d_mr_bits, void* stream,
+                       hipGraphExec_t* graph_out = nullptr);
 ptsbe_status run_status(const void* d_ws, void* stream);
 ptsbe_status adjoint_grad(const Plan& P, TrajSet& ts, const double* params, const double* coef,
                           const uint64_t* zmask, uint32_t n_terms, void* d_ws, size_t ws_bytes, double* d_expval,
@@ -55,6 +57,32 @@ ptsbe_status ptsbe_plan(const ptsbe_circuit* circuit, const ptsbe_noise_model* n
     auto* h = new ptsbe_plan_s;
     h->plan = p;
     *out = h;
+    return PTSBE_OK;
+  })
+}
+
+ptsbe_status ptsbe_plan_compile(ptsbe_plan_t plan, uint32_t* n_kernels, double* seconds) {
+  FENCE({
+    if (!plan) return fail(PTSBE_E_ARG, "null plan");
+    const Plan& P = *plan->plan;
+    ptsbe_status st = jit_build(P);
+    if (n_kernels) *n_kernels = (uint32_t)P.jit->names.size();
+    if (seconds) *seconds = P.jit->compile_seconds;
+    return st;
+  })
+}
+
+ptsbe_status ptsbe_plan_pass_source(ptsbe_plan_t plan, uint32_t pass, char* out, size_t* len) {
+  FENCE({
+    if (!plan || !len) return fail(PTSBE_E_ARG, "null argument");
+    const Plan& P = *plan->plan;
+    if (pass >= P.passes.size()) return fail(PTSBE_E_ARG, "pass index out of range");
+    const std::string src = jit_pass_source(P.passes[pass], P.n, P.precision, "ptsbe_pass");
+    if (out) {
+      if (*len < src.size() + 1) return fail(PTSBE_E_ARG, "output buffer too small");
+      std::memcpy(out, src.c_str(), src.size() + 1);
+    }
+    *len = src.size() + 1;
     return PTSBE_OK;
   })
 }
@@ -158,6 +186,38 @@ ptsbe_status ptsbe_run_batch(ptsbe_plan_t plan, ptsbe_trajset_t ts, const ptsbe_
     if (ts->ts->plan.get() != plan->plan.get()) return fail(PTSBE_E_ARG, "trajectory set belongs to another plan");
     return run_batch(*plan->plan, *ts->ts, opts, d_ws, ws_bytes, d_bits, d_traj, capacity, d_mr_bits, stream);
   })
+}
+
+ptsbe_status ptsbe_graph_create(ptsbe_plan_t plan, ptsbe_trajset_t ts, const ptsbe_run_opts* opts, void* d_ws,
+                                size_t ws_bytes, void* d_bits, uint32_t* d_traj, uint64_t capacity,
+                                uint8_t* d_mr_bits, void* stream, ptsbe_graph_t* out) {
+  FENCE({
+    if (!plan || !ts || !out) return fail(PTSBE_E_ARG, "null argument");
+    if (ts->ts->plan.get() != plan->plan.get()) return fail(PTSBE_E_ARG, "trajectory set belongs to another plan");
+    hipGraphExec_t exec = nullptr;
+    ptsbe_status st =
+        run_batch(*plan->plan, *ts->ts, opts, d_ws, ws_bytes, d_bits, d_traj, capacity, d_mr_bits, stream, &exec);
+    if (st != PTSBE_OK) return st;
+    ptsbe_graph_s* g = new ptsbe_graph_s;
+    g->plan = plan->plan;
+    g->ts = ts->ts;
+    g->exec = exec;
+    *out = g;
+    return PTSBE_OK;
+  })
+}
+
+ptsbe_status ptsbe_graph_launch(ptsbe_graph_t g, void* stream) {
+  if (!g || !g->exec) return fail(PTSBE_E_ARG, "null graph");
+  hipError_t e = hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(PTSBE_E_DEVICE, std::string("graph launch: ") + hipGetErrorString(e));
+  return PTSBE_OK;
+}
+
+void ptsbe_graph_destroy(ptsbe_graph_t g) {
+  if (!g) return;
+  if (g->exec) hipGraphExecDestroy(g->exec);
+  delete g;
 }
 
 ptsbe_status ptsbe_trajset_tables(ptsbe_trajset_t h, const double* params, uint32_t sort_chunk, void* out,

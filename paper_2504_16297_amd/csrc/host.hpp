@@ -10,10 +10,14 @@
 #include <string>
 #include <vector>
 
+#include <hip/hip_runtime.h>
+
 #include "../../include/ptsbe.h"
 #include "tables.hpp"
 
 namespace ptsbe {
+
+struct JitProgram;
 
 using cd = std::complex<double>;
 using Mat = std::vector<cd>;  // row-major d x d
@@ -115,6 +119,9 @@ struct Plan {
   // reverse-sweep program of the adjoint gradient (unitary circuits with parameters)
   bool has_adjoint = false;
   Program adj;
+  // per-pass compiled kernels (built on first use unless disabled)
+  bool use_jit = true;
+  std::shared_ptr<JitProgram> jit;
 };
 
 struct TrajSet {
@@ -143,6 +150,8 @@ struct TrajSet {
   TableLayout adj_layout{};
   bool adj_valid = false;
   std::vector<uint8_t> adj_aux;    // host staging of weights and the dot -> parameter map
+  std::vector<uint32_t> route_host; // host staging of prefix-sharing launch routes (src, dst pairs)
+  std::vector<uint32_t> route_off;
 };
 
 // Matrix helpers
@@ -172,4 +181,9 @@ struct ptsbe_plan_s {
 };
 struct ptsbe_trajset_s {
   std::shared_ptr<ptsbe::TrajSet> ts;
+};
+struct ptsbe_graph_s {
+  std::shared_ptr<const ptsbe::Plan> plan;
+  std::shared_ptr<ptsbe::TrajSet> ts;
+  hipGraphExec_t exec = nullptr;
 };

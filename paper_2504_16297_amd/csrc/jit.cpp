@@ -1,0 +1,646 @@
+// Pass compiler (see jit.hpp).  The generated kernel is the register-layout
+// tile pass with the pass's operation list unrolled: 256 threads hold 16
+// amplitudes each over 4 register bits of a 2^k-amplitude tile; 2x2 matrices
+// on register bits are applied in registers, the register set is changed by
+// an LDS transpose, and everything known per pass (tile qubits, which bits are
+// register bits, which group positions are idle, which amplitudes a CZ-type
+// sign touches, whether a block-uniform phase is pending) is resolved while
+// generating, so the kernel executes only the arithmetic of its operations.
+#include "jit.hpp"
+
+#include <hip/hiprtc.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <functional>
+#include <sstream>
+#include <thread>
+
+#include "host.hpp"
+
+namespace ptsbe {
+
+namespace {
+
+#define PTSBE_STR2(...) #__VA_ARGS__
+#define PTSBE_STR(...) PTSBE_STR2(__VA_ARGS__)
+const char* kArgsFields = PTSBE_STR(PTSBE_PASS_ARGS_FIELDS(V, void, void, DOverride, uint2));
+
+// A Boolean runtime variable of the sign algebra: a thread bit of the local
+// index or a tile (global) bit, as a C expression.
+using Mono = std::vector<std::string>;  // product of variables, sorted; empty = 1
+
+struct Gen {
+  std::ostringstream o;
+  int k = 0, n = 0;
+  bool c64 = true;
+  std::vector<int> tq, oq;
+  int R[4] = {0, 0, 0, 0};
+  bool pending = false;      // `cs` holds a block-uniform scalar not yet applied
+  bool cs_neg = false;       // the pending scalar must also be negated
+  bool tile_read = false;    // the LDS tile was read since the last barrier
+  // accumulated +-1 diagonal: amplitude r is negated where bit r of
+  // XOR over monomials m of (value of m) * mask[m] is set
+  std::map<Mono, uint32_t> signs;
+  bool ok = true;
+  std::string why;
+
+  void fail(const std::string& w) {
+    if (ok) why = w;
+    ok = false;
+  }
+  int reg_pos(int l) const {
+    for (int j = 0; j < 4; ++j)
+      if (R[j] == l) return j;
+    return -1;
+  }
+  // thread-index bit that holds local bit l (l not a register bit)
+  int thread_bit(int l) const {
+    int i = 0;
+    for (int p = 0; p < l; ++p)
+      if (reg_pos(p) < 0) ++i;
+    return i;
+  }
+  std::string tvar(int l) const { return "((tid >> " + std::to_string(thread_bit(l)) + ") & 1u)"; }
+  static std::string gvar(int g) { return "((uint32_t)(base >> " + std::to_string(g) + ") & 1u)"; }
+  // Lt: the thread's local-index part (register bits zero) for the current R
+  std::string lt_expr() const {
+    std::vector<int> P;
+    for (int p = 0; p < k; ++p)
+      if (reg_pos(p) < 0) P.push_back(p);
+    std::string e;
+    size_t i = 0;
+    while (i < P.size()) {
+      size_t j = i;
+      while (j + 1 < P.size() && P[j + 1] == P[j] + 1) ++j;
+      const uint32_t len = (uint32_t)(j - i + 1);
+      // tid bits i..j land on local positions P[i]..P[j]
+      std::string term = "((tid >> " + std::to_string(i) + ") & " + std::to_string((1u << len) - 1) + "u)";
+      if (P[i] > 0) term = "(" + term + " << " + std::to_string(P[i]) + ")";
+      e += (e.empty() ? "" : " | ") + term;
+      i = j + 1;
+    }
+    return e.empty() ? "0u" : e;
+  }
+  uint32_t reg_const(int r) const {
+    uint32_t c = 0;
+    for (int j = 0; j < 4; ++j)
+      if ((r >> j) & 1) c |= 1u << R[j];
+    return c;
+  }
+  static uint32_t swz(uint32_t L) { return L ^ ((L >> 4) & 15u); }
+
+  std::string S(int r) const { return "s" + std::to_string(r); }
+
+  void barrier_before_tile_write() {
+    if (tile_read) {
+      o << "  __syncthreads();\n";
+      tile_read = false;
+    }
+  }
+
+  // ---- block-uniform scalar
+  void apply_pending_to(const char* m0, const char* m1, const char* m2, const char* m3) {
+    if (!pending) return;
+    if (cs_neg) o << "    cs.x = -cs.x; cs.y = -cs.y;\n";
+    o << "    " << m0 << " = cm(cs, " << m0 << "); " << m1 << " = cm(cs, " << m1 << "); " << m2 << " = cm(cs, "
+      << m2 << "); " << m3 << " = cm(cs, " << m3 << ");\n";
+    pending = false;
+    cs_neg = false;
+  }
+  void pend(const std::string& ph) {
+    if (pending) o << "  cs = cm(cs, " << ph << ");\n";
+    else o << "  cs = " << ph << ";\n";
+    pending = true;
+  }
+
+  // ---- 2x2 matrix on register position j, matrix in mats[4 * slot ..]
+  void gate(int j, int slot) {
+    o << "  {\n    V m0 = mats[" << 4 * slot << "], m1 = mats[" << 4 * slot + 1 << "], m2 = mats[" << 4 * slot + 2
+      << "], m3 = mats[" << 4 * slot + 3 << "];\n";
+    apply_pending_to("m0", "m1", "m2", "m3");
+    for (int r = 0; r < 16; ++r) {
+      if ((r >> j) & 1) continue;
+      const int r1 = r | (1 << j);
+      o << "    { const V x0 = " << S(r) << ", x1 = " << S(r1) << "; " << S(r) << " = cf(m0, x0, m1, x1); " << S(r1)
+        << " = cf(m2, x0, m3, x1); }\n";
+    }
+    o << "  }\n";
+  }
+
+  // ---- signs
+  void add_term(const Mono& m, uint32_t mask) {
+    if (!mask) return;
+    uint32_t& v = signs[m];
+    v ^= mask;
+  }
+  // value of local bit / tile bit as (is_register, register pattern, variable)
+  struct Bit {
+    bool reg;
+    uint32_t pat;       // register: 16-bit pattern over r
+    std::string var;    // runtime variable otherwise
+  };
+  Bit bit_of_local(int l) const {
+    const int j = reg_pos(l);
+    if (j >= 0) {
+      uint32_t p = 0;
+      for (int r = 0; r < 16; ++r)
+        if ((r >> j) & 1) p |= 1u << r;
+      return {true, p, ""};
+    }
+    return {false, 0, tvar(l)};
+  }
+  void dsign(const DOp& op) {
+    const Bit x = op.a == 255 ? Bit{false, 0, gvar(op.ga)} : bit_of_local(op.a);
+    const bool one = op.b == 254;
+    const Bit y = one ? Bit{true, 0, ""} : (op.b == 255 ? Bit{false, 0, gvar(op.gb)} : bit_of_local(op.b));
+    const uint32_t mk = op.slot[0] & 15u;
+    auto mkb = [&](int i) { return (mk >> i) & 1u; };
+    // sign(r) = mk[x(r) + 2 y(r)] as a GF(2) polynomial in the runtime bits
+    if (x.reg && y.reg) {
+      uint32_t c = 0;
+      for (int r = 0; r < 16; ++r)
+        if (mkb(((x.pat >> r) & 1) + 2 * ((y.pat >> r) & 1))) c |= 1u << r;
+      add_term({}, c);
+    } else if (x.reg || y.reg) {
+      const Bit& R_ = x.reg ? x : y;
+      const std::string v = x.reg ? y.var : x.var;
+      uint32_t a0 = 0, a1 = 0;
+      for (int r = 0; r < 16; ++r) {
+        const int rb = (R_.pat >> r) & 1;
+        const int i0 = x.reg ? rb : 2 * rb;          // runtime bit = 0
+        const int i1 = x.reg ? rb + 2 : 2 * rb + 1;  // runtime bit = 1
+        if (mkb(i0)) a0 |= 1u << r;
+        if (mkb(i1)) a1 |= 1u << r;
+      }
+      add_term({}, a0);
+      add_term({v}, a0 ^ a1);
+    } else {
+      const uint32_t F = 0xFFFFu;
+      add_term({}, mkb(0) ? F : 0u);
+      add_term({x.var}, (mkb(0) ^ mkb(1)) ? F : 0u);
+      add_term({y.var}, (mkb(0) ^ mkb(2)) ? F : 0u);
+      Mono uv = {x.var, y.var};
+      std::sort(uv.begin(), uv.end());
+      if (uv[0] == uv[1]) add_term({x.var}, (mkb(0) ^ mkb(1) ^ mkb(2) ^ mkb(3)) ? F : 0u);
+      else add_term(uv, (mkb(0) ^ mkb(1) ^ mkb(2) ^ mkb(3)) ? F : 0u);
+    }
+  }
+  void flush_signs() {
+    uint32_t c = 0;
+    std::vector<std::pair<std::string, uint32_t>> rt;
+    for (auto& kv : signs) {
+      if (!kv.second) continue;
+      if (kv.first.empty()) {
+        c ^= kv.second;
+      } else {
+        std::string cond = kv.first[0];
+        for (size_t i = 1; i < kv.first.size(); ++i) cond += " & " + kv.first[i];
+        rt.push_back({cond, kv.second});
+      }
+    }
+    signs.clear();
+    if (c == 0xFFFFu && rt.empty()) {  // a sign common to the tile joins the scalar
+      if (pending) cs_neg = !cs_neg;
+      else {
+        o << "  cs.x = -1; cs.y = 0;\n";
+        pending = true;
+      }
+      return;
+    }
+    for (int r = 0; r < 16; ++r)
+      if ((c >> r) & 1) o << "  " << S(r) << ".x = -" << S(r) << ".x; " << S(r) << ".y = -" << S(r) << ".y;\n";
+    if (rt.empty()) return;
+    uint32_t any = 0;
+    o << "  {\n    uint32_t ng = 0u";
+    for (auto& t : rt) {
+      o << " ^ ((" << t.first << ") ? " << t.second << "u : 0u)";
+      any |= t.second;
+    }
+    o << ";\n";
+    for (int r = 0; r < 16; ++r) {
+      if (!((any >> r) & 1)) continue;
+      if (c64)
+        o << "    { const uint32_t sg = (ng << " << 31 - r << ") & 0x80000000u; " << S(r)
+          << ".x = __uint_as_float(__float_as_uint(" << S(r) << ".x) ^ sg); " << S(r)
+          << ".y = __uint_as_float(__float_as_uint(" << S(r) << ".y) ^ sg); }\n";
+      else
+        o << "    { const uint64_t sg = (uint64_t)((ng >> " << r << ") & 1u) << 63; " << S(r)
+          << ".x = __longlong_as_double(__double_as_longlong(" << S(r) << ".x) ^ sg); " << S(r)
+          << ".y = __longlong_as_double(__double_as_longlong(" << S(r) << ".y) ^ sg); }\n";
+    }
+    o << "  }\n";
+  }
+
+  // ---- diagonals
+  void diag(const DOp& op) {
+    const bool two = op.type == DOP_D2;
+    if (op.a == 255 && (!two || op.b == 255)) {
+      if (!two) {
+        o << "  { const V* mp = mats + " << 4 * op.slot[0] << "; const V ph = " << gvar(op.ga)
+          << " ? mp[3] : mp[0];\n  ";
+        pend("ph");
+        o << "  }\n";
+      } else {
+        o << "  { const uint32_t i = " << gvar(op.ga) << " + 2u * " << gvar(op.gb)
+          << "; const V ph = a.pool[slot_off[" << op.slot[0] << "] + 5u * i];\n  ";
+        pend("ph");
+        o << "  }\n";
+      }
+      return;
+    }
+    o << "  {\n";
+    if (!two) {
+      o << "    const V d0 = mats[" << 4 * op.slot[0] << "], d1 = mats[" << 4 * op.slot[0] + 3
+        << "], d2 = d0, d3 = d1;\n";
+    } else {
+      o << "    const V* mp = a.pool + slot_off[" << op.slot[0]
+        << "]; const V d0 = mp[0], d1 = mp[5], d2 = mp[10], d3 = mp[15];\n";
+    }
+    auto bitexpr = [&](int local, int g, int r) -> std::string {
+      if (local == 255) return gvar(g);
+      const int j = reg_pos(local);
+      if (j >= 0) return ((r >> j) & 1) ? "1u" : "0u";
+      return tvar(local);
+    };
+    for (int r = 0; r < 16; ++r) {
+      const std::string ba = bitexpr(op.a, op.ga, r);
+      const std::string bb = two ? bitexpr(op.b, op.gb, r) : "0u";
+      std::string e;
+      auto pick = [&](const std::string& b, const std::string& lo, const std::string& hi) {
+        if (b == "0u") return lo;
+        if (b == "1u") return hi;
+        return "(" + b + " ? " + hi + " : " + lo + ")";
+      };
+      const std::string lo = pick(ba, "d0", "d1"), hi = pick(ba, "d2", "d3");
+      e = pick(bb, lo, hi);
+      o << "    " << S(r) << " = cm(" << e << ", " << S(r) << ");\n";
+    }
+    o << "  }\n";
+  }
+
+  // ---- 4x4 matrix
+  void m2(const DOp& op) {
+    const int ja = reg_pos(op.a), jb = reg_pos(op.b);
+    o << "  {\n    const V* m = a.pool + slot_off[" << op.slot[0] << "];\n";
+    if (ja >= 0 && jb >= 0) {
+      o << "    V M[16];\n    for (int i = 0; i < 16; ++i) M[i] = m[i];\n";
+      for (int r = 0; r < 16; ++r) {
+        if ((r >> ja) & 1 || (r >> jb) & 1) continue;
+        const int i0 = r, i1 = r | (1 << ja), i2 = r | (1 << jb), i3 = r | (1 << ja) | (1 << jb);
+        o << "    { const V x0 = " << S(i0) << ", x1 = " << S(i1) << ", x2 = " << S(i2) << ", x3 = " << S(i3) << ";\n";
+        const int idx[4] = {i0, i1, i2, i3};
+        for (int q = 0; q < 4; ++q)
+          o << "      " << S(idx[q]) << " = cd4(M + " << 4 * q << ", x0, x1, x2, x3);\n";
+        o << "    }\n";
+      }
+      o << "  }\n";
+      return;
+    }
+    // through the LDS tile: any two local bits
+    barrier_before_tile_write();
+    o << "    const uint32_t Lt = " << lt_expr() << ", Lw = Lt ^ ((Lt >> 4) & 15u);\n";
+    for (int r = 0; r < 16; ++r) o << "    tile[Lw ^ " << swz(reg_const(r)) << "u] = " << S(r) << ";\n";
+    o << "    __syncthreads();\n";
+    const uint32_t A = 1u << op.a, B = 1u << op.b;
+    const uint32_t l1 = std::min(A, B) - 1, l2 = std::max(A, B) - 1;
+    o << "    for (uint32_t qd = tid; qd < " << (1u << (k - 2)) << "u; qd += blockDim.x) {\n"
+      << "      uint32_t i = ((qd & ~" << l1 << "u) << 1) | (qd & " << l1 << "u);\n"
+      << "      i = ((i & ~" << l2 << "u) << 1) | (i & " << l2 << "u);\n"
+      << "      const uint32_t i0 = sw(i), i1 = sw(i | " << A << "u), i2 = sw(i | " << B << "u), i3 = sw(i | "
+      << (A | B) << "u);\n"
+      << "      const V x0 = tile[i0], x1 = tile[i1], x2 = tile[i2], x3 = tile[i3];\n"
+      << "      tile[i0] = cd4(m, x0, x1, x2, x3); tile[i1] = cd4(m + 4, x0, x1, x2, x3);\n"
+      << "      tile[i2] = cd4(m + 8, x0, x1, x2, x3); tile[i3] = cd4(m + 12, x0, x1, x2, x3);\n    }\n"
+      << "    __syncthreads();\n";
+    for (int r = 0; r < 16; ++r) o << "    " << S(r) << " = tile[Lw ^ " << swz(reg_const(r)) << "u];\n";
+    o << "  }\n";
+    tile_read = true;
+  }
+
+  void mr(const DOp& op) {
+    const int j = reg_pos(op.a);
+    if (j < 0) {
+      fail("measure-reset on a non-register bit");
+      return;
+    }
+    o << "  {\n    const uint64_t ri = (uint64_t)t * a.n_measure + " << op.slot[0]
+      << "u;\n    const uint32_t b = a.mr_bits[ri];\n    const T sc = (T)a.mr_norm[ri];\n";
+    for (int r = 0; r < 16; ++r) {
+      if ((r >> j) & 1) continue;
+      const int r1 = r | (1 << j);
+      o << "    { V x = b ? " << S(r1) << " : " << S(r) << "; x.x *= sc; x.y *= sc; " << S(r) << " = x; " << S(r1)
+        << ".x = 0; " << S(r1) << ".y = 0; }\n";
+    }
+    o << "  }\n";
+  }
+
+  void phase(const DOp& op) {
+    if (!signs.empty()) {
+      bool live = false;
+      for (auto& kv : signs) live |= kv.second != 0;
+      if (live) fail("signs pending across a register change");
+    }
+    barrier_before_tile_write();
+    o << "  {\n    const uint32_t Lt = " << lt_expr() << ", Lw = Lt ^ ((Lt >> 4) & 15u);\n";
+    for (int r = 0; r < 16; ++r) o << "    tile[Lw ^ " << swz(reg_const(r)) << "u] = " << S(r) << ";\n";
+    o << "  }\n  __syncthreads();\n";
+    int nr[4] = {op.a, op.b, op.ga, op.gb};
+    for (int j = 0; j < 4; ++j) R[j] = nr[j];
+    for (int j = 0; j < 3; ++j)
+      if (!(R[j] < R[j + 1]) || R[3] >= k) fail("register bits not ascending");
+    o << "  {\n    const uint32_t Lt = " << lt_expr() << ", Lw = Lt ^ ((Lt >> 4) & 15u);\n";
+    for (int r = 0; r < 16; ++r) o << "    " << S(r) << " = tile[Lw ^ " << swz(reg_const(r)) << "u];\n";
+    o << "  }\n";
+    tile_read = true;
+  }
+};
+
+const char* kPrelude = R"(typedef __UINT8_TYPE__ uint8_t;
+typedef __UINT32_TYPE__ uint32_t;
+typedef __UINT64_TYPE__ uint64_t;
+struct DOverride { uint32_t slot, off; };
+)";
+
+const char* kHelpers = R"(
+__device__ __forceinline__ V cm(V a, V b) { V r; r.x = a.x * b.x - a.y * b.y; r.y = a.x * b.y + a.y * b.x; return r; }
+__device__ __forceinline__ V cf(V m0, V x0, V m1, V x1) {
+  V r;
+  r.x = m0.x * x0.x - m0.y * x0.y + m1.x * x1.x - m1.y * x1.y;
+  r.y = m0.x * x0.y + m0.y * x0.x + m1.x * x1.y + m1.y * x1.x;
+  return r;
+}
+__device__ __forceinline__ V cd4(const V* m, V x0, V x1, V x2, V x3) {
+  V r = cf(m[0], x0, m[1], x1), q = cf(m[2], x2, m[3], x3);
+  r.x += q.x; r.y += q.y;
+  return r;
+}
+__device__ __forceinline__ uint32_t sw(uint32_t L) { return L ^ ((L >> 4) & 15u); }
+)";
+
+std::string bit_gather(const char* src, const std::vector<int>& dst_pos, int first_src_bit) {
+  // sum over i of ((src >> (first + i)) & 1) << dst_pos[i], as shifted runs (64-bit)
+  std::string e;
+  size_t i = 0;
+  while (i < dst_pos.size()) {
+    size_t j = i;
+    while (j + 1 < dst_pos.size() && dst_pos[j + 1] == dst_pos[j] + 1) ++j;
+    const int len = (int)(j - i + 1);
+    const int sb = first_src_bit + (int)i;
+    std::string term = "(((uint64_t)" + std::string(src) + " >> " + std::to_string(sb) + ") & " +
+                       std::to_string((1ull << len) - 1) + "ull)";
+    term = "(" + term + " << " + std::to_string(dst_pos[i]) + ")";
+    e += (e.empty() ? "" : " | ") + term;
+    i = j + 1;
+  }
+  return e.empty() ? "0ull" : e;
+}
+
+}  // namespace
+
+std::string jit_pass_source(const Pass& ps, int n, int precision, const std::string& name) {
+  const int k = ps.k;
+  if (k < (int)kMinRegTile || k > 12) return "";
+  Gen g;
+  g.k = k;
+  g.n = n;
+  g.c64 = precision == PTSBE_C64;
+  g.tq = ps.tq;
+  g.oq = ps.oq;
+  for (int j = 0; j < 4; ++j) g.R[j] = k - 4 + j;
+  const int n_slots = (int)ps.slots.size();
+  std::ostringstream& o = g.o;
+  o << kPrelude << (g.c64 ? "typedef float T;\ntypedef float2 V;\n" : "typedef double T;\ntypedef double2 V;\n")
+    << "struct PassArgs { " << kArgsFields << " };\n"
+    << "static_assert(sizeof(PassArgs) == " << sizeof(PassArgs<float2>) << ", \"PassArgs layout\");\n"
+    << kHelpers;
+  o << "extern \"C\" __global__ __launch_bounds__(256) void " << name << "(PassArgs a) {\n"
+    << "  extern __shared__ __align__(16) unsigned char smem[];\n"
+    << "  V* tile = reinterpret_cast<V*>(smem);\n"
+    << "  V* mats = tile + " << (1 << k) << ";\n"
+    << "  uint32_t* slot_off = reinterpret_cast<uint32_t*>(mats + " << 4 * n_slots << ");\n"
+    << "  const uint32_t tid = threadIdx.x;\n"
+    << "  uint32_t src = blockIdx.y, dst = blockIdx.y;\n"
+    << "  if (a.route) { const uint2 e = a.route[blockIdx.y]; src = e.x; dst = e.y; }\n"
+    << "  const bool carrier = a.route != nullptr && dst >= a.carrier0;\n"
+    << "  const uint32_t t = a.t0 + dst;\n"
+    << "  const uint64_t tile_id = blockIdx.x;\n"
+    << "  const uint64_t base = " << bit_gather("tile_id", g.oq, 0) << ";\n"
+    << "  for (uint32_t i = tid; i < " << n_slots << "u; i += blockDim.x) slot_off[i] = a.slot_default[i];\n"
+    << "  __syncthreads();\n"
+    << "  if (!carrier) {\n"
+    << "    const uint32_t ob = a.ov_off[(uint64_t)t * a.n_passes + a.pass];\n"
+    << "    const uint32_t oe = a.ov_off[(uint64_t)t * a.n_passes + a.pass + 1];\n"
+    << "    for (uint32_t i = ob + tid; i < oe; i += blockDim.x) slot_off[a.ov[i].slot] = a.ov[i].off;\n"
+    << "  }\n"
+    << "  __syncthreads();\n"
+    << "  for (uint32_t i = tid; i < " << 4 * n_slots << "u; i += blockDim.x) mats[i] = a.pool[slot_off[i >> 2] + (i & 3u)];\n"
+    << "  __syncthreads();\n"
+    << "  V cs; cs.x = 1; cs.y = 0;\n";
+  // global offsets: thread part from tid, register parts constant
+  std::vector<int> tpos(g.tq.begin(), g.tq.begin() + (k - 4));
+  o << "  const uint64_t ot = " << bit_gather("tid", tpos, 0) << ";\n";
+  uint64_t og[16];
+  for (int r = 0; r < 16; ++r) {
+    og[r] = 0;
+    for (int j = 0; j < 4; ++j)
+      if ((r >> j) & 1) og[r] |= 1ull << g.tq[k - 4 + j];
+  }
+  const bool init = (ps.flags & PASS_INIT_ZERO) != 0;
+  if (init) {
+    o << "  V s0; s0.x = (base == 0 && tid == 0) ? (T)1 : (T)0; s0.y = 0;\n";
+    for (int r = 1; r < 16; ++r) o << "  V " << g.S(r) << "; " << g.S(r) << ".x = 0; " << g.S(r) << ".y = 0;\n";
+  } else {
+    o << "  const V* sst = a.states + (uint64_t)src * a.N + base + ot;\n";
+    for (int r = 0; r < 16; ++r) o << "  V " << g.S(r) << " = sst[" << og[r] << "ull];\n";
+  }
+  for (const DOp& op : ps.ops) {
+    switch (op.type) {
+      case DOP_M1G:
+        for (int j = 0; j < 4; ++j)
+          if ((op.mask >> j) & 1) g.gate(j, op.slot[j]);
+        break;
+      case DOP_M1: {
+        const int j = g.reg_pos(op.a);
+        if (j < 0) g.fail("2x2 matrix on a non-register bit");
+        else g.gate(j, op.slot[0]);
+        break;
+      }
+      case DOP_DSIGN: g.dsign(op); break;
+      case DOP_SFLIP: g.flush_signs(); break;
+      case DOP_D1:
+      case DOP_D2: g.diag(op); break;
+      case DOP_M2: g.m2(op); break;
+      case DOP_MR: g.mr(op); break;
+      case DOP_PHASE: g.phase(op); break;
+      default: g.fail("unknown operation type " + std::to_string(op.type));
+    }
+    if (!g.ok) return "";
+  }
+  g.flush_signs();
+  for (int j = 0; j < 4; ++j)
+    if (g.R[j] != k - 4 + j) g.fail("pass does not end in the load layout");
+  if (!g.ok) return "";
+  if (g.pending) {
+    if (g.cs_neg) o << "  cs.x = -cs.x; cs.y = -cs.y;\n";
+    for (int r = 0; r < 16; ++r) o << "  " << g.S(r) << " = cm(cs, " << g.S(r) << ");\n";
+  }
+  o << "  V* dstp = a.states + (uint64_t)dst * a.N + base + ot;\n";
+  for (int r = 0; r < 16; ++r) o << "  dstp[" << og[r] << "ull] = " << g.S(r) << ";\n";
+  o << "}\n";
+  return o.str();
+}
+
+namespace {
+
+ptsbe_status compile_one(const std::string& src, const std::string& name, std::vector<char>& code, std::string& err) {
+  hiprtcProgram prog;
+  if (hiprtcCreateProgram(&prog, src.c_str(), (name + ".hip").c_str(), 0, nullptr, nullptr) != HIPRTC_SUCCESS) {
+    err = "hiprtcCreateProgram failed";
+    return PTSBE_E_DEVICE;
+  }
+  const char* opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
+                        "-packed-fp32-ops"};
+  hiprtcResult r = hiprtcCompileProgram(prog, (int)(sizeof(opts) / sizeof(opts[0])), opts);
+  if (r != HIPRTC_SUCCESS) {
+    size_t ls = 0;
+    hiprtcGetProgramLogSize(prog, &ls);
+    std::string log(ls, '\0');
+    if (ls) hiprtcGetProgramLog(prog, &log[0]);
+    err = std::string("pass compiler: ") + hiprtcGetErrorString(r) + ": " + log.substr(0, 2000);
+    hiprtcDestroyProgram(&prog);
+    return PTSBE_E_DEVICE;
+  }
+  size_t cs = 0;
+  hiprtcGetCodeSize(prog, &cs);
+  code.resize(cs);
+  hiprtcGetCode(prog, code.data());
+  hiprtcDestroyProgram(&prog);
+  return PTSBE_OK;
+}
+
+}  // namespace
+
+ptsbe_status jit_build(const Plan& P) {
+  JitProgram& J = *P.jit;
+  std::lock_guard<std::mutex> lk(J.mu);
+  if (J.built) return J.build_status == PTSBE_OK ? PTSBE_OK : fail(J.build_status, J.build_error);
+  const auto t0 = std::chrono::steady_clock::now();
+  J.pass_kernel.assign(P.passes.size(), -1);
+  std::map<std::string, int> by_body;
+  for (size_t p = 0; p < P.passes.size(); ++p) {
+    const std::string body = jit_pass_source(P.passes[p], P.n, P.precision, "KERNEL_NAME");
+    if (body.empty()) continue;
+    auto it = by_body.find(body);
+    if (it != by_body.end()) {
+      J.pass_kernel[p] = it->second;
+      continue;
+    }
+    const int id = (int)J.names.size();
+    const std::string name = "ptsbe_pass_" + std::to_string(id);
+    std::string src = body;
+    src.replace(src.find("KERNEL_NAME"), 11, name);
+    by_body[body] = id;
+    J.pass_kernel[p] = id;
+    J.names.push_back(name);
+    J.sources.push_back(src);
+  }
+  const size_t K = J.names.size();
+  if (const char* dir = std::getenv("PTSBE_PASS_SOURCE_DIR")) {  // inspection: keep the generated sources
+    for (size_t i = 0; i < K; ++i) {
+      FILE* f = std::fopen((std::string(dir) + "/" + J.names[i] + ".hip").c_str(), "w");
+      if (f) {
+        std::fwrite(J.sources[i].data(), 1, J.sources[i].size(), f);
+        std::fclose(f);
+      }
+    }
+  }
+  J.code.assign(K, {});
+  std::vector<ptsbe_status> st(K, PTSBE_OK);
+  std::vector<std::string> err(K);
+  std::atomic<size_t> next{0};
+  const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<std::thread> pool;
+  auto work = [&]() {
+    for (size_t i = next++; i < K; i = next++) st[i] = compile_one(J.sources[i], J.names[i], J.code[i], err[i]);
+  };
+  for (unsigned w = 0; w < std::min<size_t>(hw, K); ++w) pool.emplace_back(work);
+  for (auto& th : pool) th.join();
+  J.compile_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  J.built = true;
+  for (size_t i = 0; i < K; ++i)
+    if (st[i] != PTSBE_OK) {
+      J.build_status = st[i];
+      J.build_error = err[i];
+      return fail(st[i], err[i]);
+    }
+  return PTSBE_OK;
+}
+
+bool jit_has(const Plan& P, uint32_t pass) {
+  return P.jit && P.jit->built && P.jit->build_status == PTSBE_OK && pass < P.jit->pass_kernel.size() &&
+         P.jit->pass_kernel[pass] >= 0;
+}
+
+namespace {
+
+// Kernel handles of the plan's compiled passes on the current device, loading
+// the code objects there at first use.
+hipError_t jit_functions(const Plan& P, const std::vector<hipFunction_t>** out) {
+  JitProgram& J = *P.jit;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(J.mu);
+  auto it = J.functions.find(dev);
+  if (it == J.functions.end()) {
+    std::vector<hipModule_t> mods(J.code.size());
+    std::vector<hipFunction_t> fns(J.code.size());
+    for (size_t i = 0; i < J.code.size(); ++i) {
+      e = hipModuleLoadData(&mods[i], J.code[i].data());
+      if (e != hipSuccess) return e;
+      e = hipModuleGetFunction(&fns[i], mods[i], J.names[i].c_str());
+      if (e != hipSuccess) return e;
+    }
+    J.modules[dev] = mods;
+    it = J.functions.emplace(dev, fns).first;
+  }
+  *out = &it->second;
+  return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t jit_load(const Plan& P) {
+  if (!P.jit || !P.jit->built || P.jit->build_status != PTSBE_OK) return hipSuccess;
+  const std::vector<hipFunction_t>* fns = nullptr;
+  return jit_functions(P, &fns);
+}
+
+template <typename V>
+hipError_t jit_launch(const Plan& P, uint32_t pass, const PassArgs<V>& a, uint32_t rows, hipStream_t s) {
+  const std::vector<hipFunction_t>* fns = nullptr;
+  hipError_t e = jit_functions(P, &fns);
+  if (e != hipSuccess) return e;
+  hipFunction_t f = (*fns)[P.jit->pass_kernel[pass]];
+  const Pass& ps = P.passes[pass];
+  const uint32_t k = (uint32_t)ps.k, n_slots = (uint32_t)ps.slots.size();
+  const size_t lds = sizeof(V) * ((size_t(1) << k) + 4 * (size_t)n_slots) + 4 * (size_t)n_slots;
+  if (lds > 65536) return hipErrorInvalidConfiguration;
+  PassArgs<V> la = a;
+  uint32_t slot_begin = 0;
+  for (uint32_t p = 0; p < pass; ++p) slot_begin += (uint32_t)P.passes[p].slots.size();
+  la.slot_default = a.slot_default + slot_begin;
+  void* args[] = {&la};
+  return hipModuleLaunchKernel(f, 1u << (P.n - k), rows, 1, 1u << (k - kRegBits), 1, 1, (unsigned)lds, s, args,
+                               nullptr);
+}
+
+template hipError_t jit_launch<float2>(const Plan&, uint32_t, const PassArgs<float2>&, uint32_t, hipStream_t);
+template hipError_t jit_launch<double2>(const Plan&, uint32_t, const PassArgs<double2>&, uint32_t, hipStream_t);
+
+}  // namespace ptsbe

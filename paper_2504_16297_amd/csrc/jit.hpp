@@ -1,0 +1,59 @@
+// Pass compiler: each register-layout tile pass of a plan becomes its own
+// gfx950 kernel, generated as HIP source from the pass's fixed operation list
+// and compiled with hiprtc once per plan.  The trajectory-dependent part of a
+// pass (which matrix each slot holds) stays in the device tables, so one
+// compiled kernel serves every trajectory of every set run on the plan.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/ptsbe.h"
+#include "kernels.hpp"
+
+namespace ptsbe {
+
+struct Pass;
+struct Plan;
+
+struct JitProgram {
+  std::mutex mu;
+  bool built = false;
+  ptsbe_status build_status = PTSBE_OK;
+  std::string build_error;
+  std::vector<int> pass_kernel;            // pass -> compiled kernel index, -1 = interpreter kernel
+  std::vector<std::string> names;          // kernel index -> symbol
+  std::vector<std::string> sources;        // kernel index -> HIP source
+  std::vector<std::vector<char>> code;     // kernel index -> code object
+  double compile_seconds = 0.0;
+  // per device: loaded modules and kernel handles
+  std::map<int, std::vector<hipModule_t>> modules;
+  std::map<int, std::vector<hipFunction_t>> functions;
+};
+
+// HIP source of a register-layout pass kernel named `name`, or "" if the pass
+// is outside what the compiler handles (then the interpreter kernel runs it).
+std::string jit_pass_source(const Pass& ps, int n, int precision, const std::string& name);
+
+// Generate and compile every pass kernel of the plan (host only, no device
+// needed).  Idempotent; thread-safe.
+ptsbe_status jit_build(const Plan& P);
+
+// Launch pass `pass` of the plan through its compiled kernel on `stream`
+// (loads the code objects on the current device at first use).  `a` carries
+// the plan-wide tables; the pass-local slot defaults are selected here.
+template <typename V>
+hipError_t jit_launch(const Plan& P, uint32_t pass, const PassArgs<V>& a, uint32_t rows, hipStream_t s);
+
+// Load the compiled kernels on the current device now (before stream capture).
+hipError_t jit_load(const Plan& P);
+
+// True if pass `pass` runs through a compiled kernel.
+bool jit_has(const Plan& P, uint32_t pass);
+
+}  // namespace ptsbe

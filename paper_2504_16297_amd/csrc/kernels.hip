@@ -59,6 +59,25 @@ __device__ __forceinline__ uint64_t tile_offset(uint32_t L, const uint8_t* tq, u
   return off;
 }
 
+// Source / destination state slots of this block row, and whose overrides apply.
+struct Route {
+  uint32_t src, dst, t;
+  bool carrier;
+};
+template <typename V>
+__device__ __forceinline__ Route route_of(const PassArgs<V>& a) {
+  Route r;
+  r.src = r.dst = blockIdx.y;
+  if (a.route) {
+    const uint2 e = a.route[blockIdx.y];
+    r.src = e.x;
+    r.dst = e.y;
+  }
+  r.carrier = a.route != nullptr && r.dst >= a.carrier0;
+  r.t = a.t0 + r.dst;
+  return r;
+}
+
 template <typename V>
 __global__ __launch_bounds__(256) void k_pass(PassArgs<V> a) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -69,16 +88,18 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs<V> a) {
   uint32_t* slot_off = reinterpret_cast<uint32_t*>(smem + sizeof(V) * nt);
   __shared__ uint8_t tq[16];
   const uint32_t tid = threadIdx.x;
-  const uint32_t t = a.t0 + blockIdx.y;               // trajectory (set-local index)
+  const Route rt = route_of(a);
+  const uint32_t t = rt.t;                            // trajectory (set-local index)
   const uint64_t tile_id = blockIdx.x;
   if (tid < 16) tq[tid] = P.tq[tid];
   uint64_t base = 0;
   for (uint32_t i = 0; i < a.n - k; ++i)
     if ((tile_id >> i) & 1) base |= 1ull << P.oq[i];
-  V* st = a.states + (uint64_t)blockIdx.y * a.N;
+  const V* sst = a.states + (uint64_t)rt.src * a.N;
+  V* st = a.states + (uint64_t)rt.dst * a.N;
   for (uint32_t s = tid; s < P.n_slots; s += blockDim.x) slot_off[s] = a.slot_default[P.slot_begin + s];
   __syncthreads();
-  {
+  if (!rt.carrier) {
     const uint32_t ob = a.ov_off[(uint64_t)t * a.n_passes + a.pass];
     const uint32_t oe = a.ov_off[(uint64_t)t * a.n_passes + a.pass + 1];
     for (uint32_t i = ob + tid; i < oe; i += blockDim.x) slot_off[a.ov[i].slot] = a.ov[i].off;
@@ -90,7 +111,7 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs<V> a) {
       v.x = (base == 0 && L == 0) ? 1 : 0;
       v.y = 0;
     } else {
-      v = st[base + tile_offset(L, tq, k)];
+      v = sst[base + tile_offset(L, tq, k)];
     }
     tile[L] = v;
   }
@@ -289,12 +310,14 @@ __global__ __launch_bounds__(256) void k_pass_reg(PassArgs<V> a) {
   DOp* opl = reinterpret_cast<DOp*>(mats + 4 * (size_t)n_slots);
   uint32_t* slot_off = reinterpret_cast<uint32_t*>(opl + n_ops);
   const uint32_t tid = threadIdx.x;
-  const uint32_t t = a.t0 + blockIdx.y;
+  const Route rt = route_of(a);
+  const uint32_t t = rt.t;
   const uint64_t tile_id = blockIdx.x;
   uint64_t base = 0;
   for (uint32_t i = 0; i < a.n - k; ++i)
     if ((tile_id >> i) & 1) base |= 1ull << P.oq[i];
-  V* st = a.states + (uint64_t)blockIdx.y * a.N;
+  const V* sst = a.states + (uint64_t)rt.src * a.N;
+  V* st = a.states + (uint64_t)rt.dst * a.N;
   for (uint32_t s = tid; s < n_slots; s += blockDim.x) slot_off[s] = a.slot_default[P.slot_begin + s];
   {
     const uint32_t* src = reinterpret_cast<const uint32_t*>(a.ops + P.op_begin);
@@ -302,7 +325,7 @@ __global__ __launch_bounds__(256) void k_pass_reg(PassArgs<V> a) {
     for (uint32_t i = tid; i < 4 * n_ops; i += blockDim.x) dst[i] = src[i];
   }
   __syncthreads();
-  {
+  if (!rt.carrier) {
     const uint32_t ob = a.ov_off[(uint64_t)t * a.n_passes + a.pass];
     const uint32_t oe = a.ov_off[(uint64_t)t * a.n_passes + a.pass + 1];
     for (uint32_t i = ob + tid; i < oe; i += blockDim.x) slot_off[a.ov[i].slot] = a.ov[i].off;
@@ -330,7 +353,7 @@ __global__ __launch_bounds__(256) void k_pass_reg(PassArgs<V> a) {
       s.v[r].x = (base == 0 && Lt == 0 && r == 0) ? 1 : 0;
       s.v[r].y = 0;
     } else {
-      s.v[r] = st[base + off];
+      s.v[r] = sst[base + off];
     }
   }
 
@@ -410,13 +433,8 @@ __global__ __launch_bounds__(256) void k_pass_reg(PassArgs<V> a) {
       neg ^= ((mk & 1) ? (A0 & B0) : 0u) | ((mk & 2) ? (A1 & B0) : 0u) | ((mk & 4) ? (A0 & B1) : 0u) |
              ((mk & 8) ? (A1 & B1) : 0u);
     } else if (type == DOP_SFLIP) {
-      if (neg == 0xFFFFu) {
-        // a sign common to the whole tile joins the pending scalar
-        cs.x = -cs.x;
-        cs.y = -cs.y;
-        pending = true;
-        neg = 0;
-      }
+      // neg may differ between threads (signs on thread bits), so it is applied
+      // here and never folded into the block-uniform pending scalar
       reg_flip_signs(s, neg);
       neg = 0;
     } else if ((type == DOP_D1 && op.a == 255) || (type == DOP_D2 && op.a == 255 && op.b == 255)) {

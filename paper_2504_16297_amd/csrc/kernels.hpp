@@ -11,23 +11,39 @@ namespace ptsbe {
 constexpr int kMaxGroup = 16;   // measure-resets measured together
 constexpr uint32_t kScanBlock = 4096;
 
+// Arguments of one tile-pass launch.  The field list is a macro so that the
+// pass compiler can emit the identical structure into the kernels it builds:
+//   passes, ops, slot_default, pool, ov_off, ov   device tables (slot_default is
+//       pass-local for compiled pass kernels);
+//   mr_bits, mr_norm   measure-reset records and renormalisation factors;
+//   states             batch of states, state b at states + b * N;
+//   route, carrier0    optional routing of block row y: state slot route[y].x is
+//       read and slot route[y].y written; slots >= carrier0 hold error-free
+//       prefix states and use no overrides, any other slot b is trajectory
+//       t0 + b; route == nullptr means y -> y;
+//   N, n, pass, n_passes, t0, n_measure.
+#define PTSBE_PASS_ARGS_FIELDS(V, DPASS, DOP, DOV, U2)                                        \
+  const DPASS* passes;                                                                       \
+  const DOP* ops;                                                                            \
+  const uint32_t* slot_default;                                                              \
+  const V* pool;                                                                             \
+  const uint32_t* ov_off;                                                                    \
+  const DOV* ov;                                                                             \
+  const uint8_t* mr_bits;                                                                    \
+  const double* mr_norm;                                                                     \
+  V* states;                                                                                 \
+  const U2* route;                                                                           \
+  uint32_t carrier0;                                                                         \
+  uint64_t N;                                                                                \
+  uint32_t n;                                                                                \
+  uint32_t pass;                                                                             \
+  uint32_t n_passes;                                                                         \
+  uint32_t t0;                                                                               \
+  uint32_t n_measure;
+
 template <typename V>
 struct PassArgs {
-  const DPass* passes;
-  const DOp* ops;
-  const uint32_t* slot_default;
-  const V* pool;
-  const uint32_t* ov_off;
-  const DOverride* ov;
-  const uint8_t* mr_bits;
-  const double* mr_norm;
-  V* states;        // batch of states, state b at states + b * N
-  uint64_t N;
-  uint32_t n;
-  uint32_t pass;
-  uint32_t n_passes;
-  uint32_t t0;      // set-local index of the batch's first trajectory
-  uint32_t n_measure;
+  PTSBE_PASS_ARGS_FIELDS(V, DPass, DOp, DOverride, uint2)
 };
 
 template <typename V>

@@ -8,6 +8,7 @@
 #include <sstream>
 
 #include "host.hpp"
+#include "jit.hpp"
 
 namespace ptsbe {
 
@@ -708,6 +709,8 @@ ptsbe_status build_plan(const ptsbe_circuit* c, const ptsbe_noise_model* nm, con
   P.tile_bits = tb;
   // flags bits 0..2: phase-scheduler fill threshold (0 = default 3)
   if (o && (o->flags & 7u)) P.min_fill = (int)(o->flags & 7u);
+  P.use_jit = !(o && (o->flags & PTSBE_PLAN_NO_COMPILE));
+  P.jit = std::make_shared<JitProgram>();
   // channels
   uint32_t n_ch = nm ? nm->n_channels : 0;
   if (n_ch && !nm->channels) return fail(PTSBE_E_ARG, "null channel array");

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "host.hpp"
+#include "jit.hpp"
 #include "kernels.hpp"
 
 namespace ptsbe {
@@ -17,24 +18,40 @@ namespace {
 uint64_t a256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
 
 struct WsLayout {
-  uint64_t status, tables, states, cdf, partial, offs, total, mr_partial, mr_bits, mr_norm, end;
+  uint64_t status, tables, routes, states, cdf, partial, offs, total, mr_partial, mr_bits, mr_norm, end;
   uint32_t batch;
   uint32_t nblk, per_block, per_thread;
+  bool share;
 };
 
-WsLayout layout_for(const Plan& P, const TrajSet& ts, uint32_t mode, uint32_t batch, uint64_t table_bytes) {
+// Prefix sharing applies to plans without measure-resets whose first pass
+// starts from |0>, when at least two trajectories are run and it is not off.
+bool prefix_sharing(const Plan& P, const TrajSet& ts, const ptsbe_run_opts* o) {
+  if (o->flags & PTSBE_RUN_NO_PREFIX_SHARING) return false;
+  if (P.n_measure || ts.m.size() < 2 || P.exec.empty()) return false;
+  for (const ExecStep& ex : P.exec)
+    if (ex.pass < 0) return false;
+  return (P.passes[P.exec[0].pass].flags & PASS_INIT_ZERO) != 0;
+}
+
+WsLayout layout_for(const Plan& P, const TrajSet& ts, uint32_t mode, uint32_t batch, uint64_t table_bytes,
+                    bool share) {
   WsLayout L{};
   const uint64_t N = 1ull << P.n;
   const uint64_t esz = P.precision == PTSBE_C64 ? 8 : 16;
   const uint64_t Btot = ts.m.size();
+  const uint64_t n_batches = (Btot + batch - 1) / std::max<uint32_t>(batch, 1);
   L.batch = batch;
+  L.share = share;
   L.per_block = (uint32_t)std::min<uint64_t>(N, kScanBlock);
   L.nblk = (uint32_t)(N / L.per_block);
   L.per_thread = std::max<uint32_t>(1, L.per_block / 256);
   uint64_t o = 0;
   L.status = o; o = a256(o + 16);
   L.tables = o; o = a256(o + table_bytes);
-  L.states = o; o = a256(o + (uint64_t)batch * N * esz);
+  L.routes = o;
+  if (share) o = a256(o + P.exec.size() * (Btot + n_batches) * sizeof(uint2));
+  L.states = o; o = a256(o + (uint64_t)(batch + (share ? 2 : 0)) * N * esz);
   L.cdf = o;
   if (mode == PTSBE_RUN_SHOTS && P.precision == PTSBE_C128) o = a256(o + (uint64_t)batch * N * 8);
   L.partial = o; o = a256(o + (uint64_t)batch * L.nblk * 8);
@@ -58,6 +75,71 @@ ptsbe_status hip_check(hipError_t e, const char* what) {
     ptsbe_status _s = hip_check((expr), (what));        \
     if (_s != PTSBE_OK) return _s;                      \
   } while (0)
+
+// Useful FLOPs per amplitude of a pass: 14 per 2x2 matrix (two complex
+// products and a sum per output), 30 per 4x4, 6 per diagonal.
+double pass_flops_per_amp(const Pass& ps) {
+  double f = 0;
+  for (const DOp& op : ps.ops) {
+    switch (op.type) {
+      case DOP_M1: f += 14; break;
+      case DOP_M1G: f += 14 * __builtin_popcount(op.mask & 15u); break;
+      case DOP_M2: f += 30; break;
+      case DOP_D1: case DOP_D2: f += 6; break;
+      case DOP_MR: f += 2; break;
+      default: break;
+    }
+  }
+  return f;
+}
+
+// Launch routes of one batch under prefix sharing.  eff[b] is the first
+// execution step whose pass the trajectory's record changes (the last step if
+// none does); before it the trajectory's state equals the error-free state,
+// which is carried in slots bb and bb + 1 (read one, write the other, swap).
+// At step e: trajectories with eff == e read the carried state, those with
+// eff < e their own, and the carrier advances while some eff > e.
+void build_routes(const Plan& P, const TrajSet& ts, uint32_t b0, uint32_t bb, std::vector<uint32_t>& out,
+                  std::vector<uint32_t>& off) {
+  const TableLayout& T = ts.layout;
+  const uint32_t* ov_off = reinterpret_cast<const uint32_t*>(ts.table_blob.data() + T.ov_off);
+  const uint32_t NP = (uint32_t)P.passes.size();
+  const uint32_t E = (uint32_t)P.exec.size();
+  std::vector<uint32_t> eff(bb, E - 1);
+  for (uint32_t b = 0; b < bb; ++b) {
+    const uint64_t row = (uint64_t)(b0 + b) * NP;
+    for (uint32_t e = 0; e < E; ++e) {
+      const uint32_t p = (uint32_t)P.exec[e].pass;
+      if (ov_off[row + p + 1] > ov_off[row + p]) {
+        eff[b] = e;
+        break;
+      }
+    }
+  }
+  uint32_t cur = bb, nxt = bb + 1;
+  off.assign(E + 1, 0);
+  for (uint32_t e = 0; e < E; ++e) {
+    off[e] = (uint32_t)(out.size() / 2);
+    bool carry = false;
+    for (uint32_t b = 0; b < bb; ++b) {
+      if (eff[b] < e) {
+        out.push_back(b);
+        out.push_back(b);
+      } else if (eff[b] == e) {
+        out.push_back(e == 0 ? b : cur);
+        out.push_back(b);
+      } else {
+        carry = true;
+      }
+    }
+    if (carry) {
+      out.push_back(cur);
+      out.push_back(nxt);
+      std::swap(cur, nxt);
+    }
+  }
+  off[E] = (uint32_t)(out.size() / 2);
+}
 
 // Stage timer: HIP events recorded on the caller's stream between launches;
 // the time between two marks is charged to the stage named by the later mark.
@@ -95,16 +177,21 @@ struct StageTimer {
 };
 enum { T_PASS = 0, T_MEASURE = 2, T_SCAN = 3, T_SAMPLE = 4, T_OTHER = -1 };
 
+enum { PH_UPLOAD = 1, PH_LAUNCH = 2 };
+
+// PH_UPLOAD copies the tables and launch routes into the workspace; PH_LAUNCH
+// enqueues the kernels (device work only, so it can be captured in a graph).
 template <typename V, typename BitT>
 ptsbe_status run_typed(const Plan& P, TrajSet& ts, const ptsbe_run_opts& o, uint8_t* ws, const WsLayout& L,
-                       void* d_bits, uint32_t* d_traj, uint8_t* d_mr_bits, hipStream_t s) {
+                       void* d_bits, uint32_t* d_traj, uint8_t* d_mr_bits, hipStream_t s, int phase) {
   const uint32_t B = (uint32_t)ts.m.size();
   const uint64_t N = 1ull << P.n;
   const TableLayout& T = ts.layout;
   uint8_t* tb = ws + L.tables;
-  CK(hipMemcpyAsync(tb, ts.table_blob.data(), ts.table_blob.size(), hipMemcpyHostToDevice, s), "table upload");
+  if (phase & PH_UPLOAD)
+    CK(hipMemcpyAsync(tb, ts.table_blob.data(), ts.table_blob.size(), hipMemcpyHostToDevice, s), "table upload");
   uint32_t* status = reinterpret_cast<uint32_t*>(ws + L.status);
-  CK(launch_fill_u32(status, 0, 4, s), "status reset");
+  if (phase & PH_LAUNCH) CK(launch_fill_u32(status, 0, 4, s), "status reset");
   V* states = reinterpret_cast<V*>(ws + L.states);
   double* partial = reinterpret_cast<double*>(ws + L.partial);
   double* offs = reinterpret_cast<double*>(ws + L.offs);
@@ -112,9 +199,27 @@ ptsbe_status run_typed(const Plan& P, TrajSet& ts, const ptsbe_run_opts& o, uint
   uint8_t* mr_bits = ws + L.mr_bits;
   double* mr_norm = reinterpret_cast<double*>(ws + L.mr_norm);
   const uint32_t chunk = o.sort_chunk ? o.sort_chunk : 4096;
-  StageTimer tm(s, o.timing != nullptr);
-  if (o.timing)
-    for (int i = 0; i < 8; ++i) o.timing[i] = 0.0;
+  const bool timed = o.timing != nullptr && (phase & PH_LAUNCH);
+  StageTimer tm(s, timed);
+  if (timed)
+    for (int i = 0; i < 10; ++i) o.timing[i] = 0.0;
+  // routes of every batch, uploaded once
+  std::vector<uint32_t>& route_off = ts.route_off;
+  std::vector<uint32_t>& routes = ts.route_host;
+  routes.clear();
+  route_off.clear();
+  if (L.share) {
+    std::vector<uint32_t> off;
+    for (uint32_t b0 = 0; b0 < B; b0 += L.batch) {
+      build_routes(P, ts, b0, std::min<uint32_t>(L.batch, B - b0), routes, off);
+      route_off.insert(route_off.end(), off.begin(), off.end());
+    }
+    if (phase & PH_UPLOAD)
+      CK(hipMemcpyAsync(ws + L.routes, routes.data(), routes.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s),
+         "route upload");
+  }
+  if (!(phase & PH_LAUNCH)) return PTSBE_OK;
+  const uint2* d_routes = reinterpret_cast<const uint2*>(ws + L.routes);
   CK(tm.mark(T_OTHER), "timer");
 
   PassArgs<V> pa{};
@@ -132,19 +237,34 @@ ptsbe_status run_typed(const Plan& P, TrajSet& ts, const ptsbe_run_opts& o, uint
   pa.n_passes = (uint32_t)P.passes.size();
   pa.n_measure = (uint32_t)P.n_measure;
 
-  for (uint32_t b0 = 0; b0 < B; b0 += L.batch) {
+  const uint32_t E = (uint32_t)P.exec.size();
+  for (uint32_t b0 = 0, bi = 0; b0 < B; b0 += L.batch, ++bi) {
     const uint32_t bb = std::min<uint32_t>(L.batch, B - b0);
     pa.t0 = b0;
-    for (const ExecStep& ex : P.exec) {
+    pa.carrier0 = bb;
+    for (uint32_t e = 0; e < E; ++e) {
+      const ExecStep& ex = P.exec[e];
       if (ex.pass >= 0) {
         const Pass& ps = P.passes[ex.pass];
         pa.pass = (uint32_t)ex.pass;
-        CK(launch_pass<V>(pa, (uint32_t)ps.k, (uint32_t)ps.slots.size(), (uint32_t)ps.ops.size(), bb, s),
-           "tile pass");
+        uint32_t rows = bb;
+        pa.route = nullptr;
+        if (L.share) {
+          const uint32_t r0 = route_off[(size_t)bi * (E + 1) + e], r1 = route_off[(size_t)bi * (E + 1) + e + 1];
+          rows = r1 - r0;
+          pa.route = d_routes + r0;
+        }
+        if (rows && jit_has(P, (uint32_t)ex.pass))
+          CK(jit_launch<V>(P, (uint32_t)ex.pass, pa, rows, s), "compiled tile pass");
+        else if (rows)
+          CK(launch_pass<V>(pa, (uint32_t)ps.k, (uint32_t)ps.slots.size(), (uint32_t)ps.ops.size(), rows, s),
+             "tile pass");
         CK(tm.mark(T_PASS), "timer");
-        if (o.timing) {
+        if (timed) {
           o.timing[1] += 1;
-          o.timing[6] += (double)bb * (double)N * sizeof(V) * ((ps.flags & PASS_INIT_ZERO) ? 1.0 : 2.0);
+          o.timing[6] += (double)rows * (double)N * sizeof(V) * ((ps.flags & PASS_INIT_ZERO) ? 1.0 : 2.0);
+          o.timing[8] += (double)rows * (double)N * pass_flops_per_amp(ps);
+          o.timing[9] += rows;
         }
       } else {
         for (size_t g0 = 0; g0 < ex.mr_qubits.size(); g0 += kMaxGroup) {
@@ -208,7 +328,7 @@ ptsbe_status run_typed(const Plan& P, TrajSet& ts, const ptsbe_run_opts& o, uint
       if (items) {
         CK(launch_sample<BitT>(sm, items, s), "sampler");
         CK(tm.mark(T_SAMPLE), "timer");
-        if (o.timing) o.timing[7] += 1;
+        if (timed) o.timing[7] += 1;
       }
     } else if (o.mode == PTSBE_RUN_STATES) {
       CK(launch_norm<V>(sa, bb, total, s), "norm");
@@ -233,7 +353,7 @@ ptsbe_status run_typed(const Plan& P, TrajSet& ts, const ptsbe_run_opts& o, uint
   if (d_mr_bits && P.n_measure)
     CK(hipMemcpyAsync(d_mr_bits, mr_bits, (size_t)B * P.n_measure, hipMemcpyDeviceToDevice, s), "record copy");
   CK(tm.mark(T_OTHER), "timer");
-  if (o.timing) CK(tm.collect(o.timing), "timer");
+  if (timed) CK(tm.collect(o.timing), "timer");
   return PTSBE_OK;
 }
 
@@ -266,13 +386,14 @@ ptsbe_status workspace_size(const Plan& P, TrajSet& ts, const ptsbe_run_opts* o,
   }
   uint32_t B = (uint32_t)ts.m.size();
   uint32_t batch = o->max_batch ? std::min<uint32_t>(o->max_batch, std::max<uint32_t>(B, 1)) : std::max<uint32_t>(B, 1);
-  batch = std::min<uint32_t>(batch, 65535);
-  *bytes = layout_for(P, ts, o->mode, batch, ts.table_blob.size()).end;
+  batch = std::min<uint32_t>(batch, 65534);
+  *bytes = layout_for(P, ts, o->mode, batch, ts.table_blob.size(), prefix_sharing(P, ts, o)).end;
   return PTSBE_OK;
 }
 
 ptsbe_status run_batch(const Plan& P, TrajSet& ts, const ptsbe_run_opts* o, void* d_ws, size_t ws_bytes,
-                       void* d_bits, uint32_t* d_traj, uint64_t capacity, uint8_t* d_mr_bits, void* stream) {
+                       void* d_bits, uint32_t* d_traj, uint64_t capacity, uint8_t* d_mr_bits, void* stream,
+                       hipGraphExec_t* graph_out) {
   ptsbe_status st = check_opts(P, ts, o);
   if (st != PTSBE_OK) return st;
   if (!d_ws) return fail(PTSBE_E_ARG, "null workspace");
@@ -291,23 +412,51 @@ ptsbe_status run_batch(const Plan& P, TrajSet& ts, const ptsbe_run_opts* o, void
   const uint32_t B = (uint32_t)ts.m.size();
   if (B == 0) return PTSBE_OK;
   uint32_t batch = o->max_batch ? std::min(o->max_batch, B) : B;
-  batch = std::min<uint32_t>(batch, 65535);  // grid.y limit of the per-state launches
-  WsLayout L = layout_for(P, ts, o->mode, batch, ts.table_blob.size());
+  batch = std::min<uint32_t>(batch, 65534);  // grid.y limit of the per-state launches (+1 carrier row)
+  const bool share = prefix_sharing(P, ts, o);
+  WsLayout L = layout_for(P, ts, o->mode, batch, ts.table_blob.size(), share);
   while (L.end > ws_bytes && batch > 1) {
     batch = std::max<uint32_t>(1, batch / 2);
-    L = layout_for(P, ts, o->mode, batch, ts.table_blob.size());
+    L = layout_for(P, ts, o->mode, batch, ts.table_blob.size(), share);
   }
   if (L.end > ws_bytes)
     return fail(PTSBE_E_OOM, "workspace of " + std::to_string(ws_bytes) + " bytes is below the " +
                                  std::to_string(L.end) + " bytes needed for one trajectory");
+  if (P.use_jit) {
+    st = jit_build(P);
+    if (st != PTSBE_OK) return st;
+  }
   uint8_t* ws = static_cast<uint8_t*>(d_ws);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (P.precision == PTSBE_C64) {
-    if (P.n <= 32) return run_typed<float2, uint32_t>(P, ts, *o, ws, L, d_bits, d_traj, d_mr_bits, s);
-    return run_typed<float2, uint64_t>(P, ts, *o, ws, L, d_bits, d_traj, d_mr_bits, s);
+  auto dispatch = [&](int phase) -> ptsbe_status {
+    if (P.precision == PTSBE_C64) {
+      if (P.n <= 32) return run_typed<float2, uint32_t>(P, ts, *o, ws, L, d_bits, d_traj, d_mr_bits, s, phase);
+      return run_typed<float2, uint64_t>(P, ts, *o, ws, L, d_bits, d_traj, d_mr_bits, s, phase);
+    }
+    if (P.n <= 32) return run_typed<double2, uint32_t>(P, ts, *o, ws, L, d_bits, d_traj, d_mr_bits, s, phase);
+    return run_typed<double2, uint64_t>(P, ts, *o, ws, L, d_bits, d_traj, d_mr_bits, s, phase);
+  };
+  if (!graph_out) return dispatch(PH_UPLOAD | PH_LAUNCH);
+  // graph: upload now, load the compiled kernels, then capture the device work
+  if (!s) return fail(PTSBE_E_ARG, "graph capture needs a created stream, not the default stream");
+  if (o->timing) return fail(PTSBE_E_ARG, "timing is not available for captured runs");
+  st = dispatch(PH_UPLOAD);
+  if (st != PTSBE_OK) return st;
+  CK(hipStreamSynchronize(s), "table upload");
+  CK(jit_load(P), "compiled pass load");
+  CK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
+  st = dispatch(PH_LAUNCH);
+  hipGraph_t g = nullptr;
+  hipError_t ce = hipStreamEndCapture(s, &g);
+  if (st != PTSBE_OK) {
+    if (g) hipGraphDestroy(g);
+    return st;
   }
-  if (P.n <= 32) return run_typed<double2, uint32_t>(P, ts, *o, ws, L, d_bits, d_traj, d_mr_bits, s);
-  return run_typed<double2, uint64_t>(P, ts, *o, ws, L, d_bits, d_traj, d_mr_bits, s);
+  CK(ce, "end capture");
+  hipError_t ie = hipGraphInstantiate(graph_out, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  CK(ie, "graph instantiate");
+  return PTSBE_OK;
 }
 
 ptsbe_status run_status(const void* d_ws, void* stream) {

@@ -1,0 +1,124 @@
+"""Turn rocprofv3 CSV output into the short text summaries kept with the
+project, and read those summaries back.
+
+    python -m paper_2504_16297_amd.profile_summary stats KERNEL_STATS_CSV --cmd "..." [--top 12]
+    python -m paper_2504_16297_amd.profile_summary traffic --kernel k_pass_reg \\
+        --fetch F.csv --write W.csv --copy-fetch CF.csv --copy-write CW.csv --copy-bytes B --cmd "..."
+
+`traffic` averages FETCH_SIZE and WRITE_SIZE (KiB per dispatch) over the
+dispatches of the named kernel and scales each by what the same counter reads
+for a plain device copy of known size (the copy's bytes divided by its
+counter), giving HBM bytes per dispatch.  The summary records the SHA-256 of
+the kernel source the counters were taken with, so a reader can tell when the
+kernel has changed since.
+"""
+
+import argparse
+import csv
+import hashlib
+import os
+import re
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCE = os.path.join(HERE, "csrc", "kernels.hip")
+
+
+def kernel_source_sha():
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def _short(name):
+    m = re.search(r"(\w+)(<[^(]*>)?\(", name)
+    base = m.group(1) if m else name[:60]
+    if "float, 2u" in name:
+        base += "<c64>"
+    elif "double, 2u" in name:
+        base += "<c128>"
+    return base
+
+
+def stats(path, top=12):
+    rows = list(csv.DictReader(open(path)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    out = ["| kernel | calls | total ms | avg us | min us | max us | % |", "|---|---|---|---|---|---|---|"]
+    for r in rows[:top]:
+        out.append(f"| {_short(r['Name'])} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+                   f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
+                   f"{float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
+    return "\n".join(out)
+
+
+def counter_per_dispatch(path, counter, kernel_regex):
+    """Mean counter value (KiB) over the dispatches whose name matches."""
+    vals = {}
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] != counter or not re.search(kernel_regex, r["Kernel_Name"]):
+            continue
+        d = r["Dispatch_Id"]
+        vals[d] = vals.get(d, 0.0) + float(r["Counter_Value"])
+    if not vals:
+        raise SystemExit(f"no {counter} rows for /{kernel_regex}/ in {path}")
+    return sum(vals.values()) / len(vals), len(vals)
+
+
+def traffic(a):
+    copy_re = r"copyBuffer|copy_kernel|elementwise_kernel.*copy"
+    cf, _ = counter_per_dispatch(a.copy_fetch, "FETCH_SIZE", copy_re)
+    cw, _ = counter_per_dispatch(a.copy_write, "WRITE_SIZE", copy_re)
+    fscale = a.copy_bytes / (cf * 1024.0)
+    wscale = a.copy_bytes / (cw * 1024.0)
+    f, nf = counter_per_dispatch(a.fetch, "FETCH_SIZE", a.kernel)
+    w, nw = counter_per_dispatch(a.write, "WRITE_SIZE", a.kernel)
+    fb = f * 1024.0 * fscale
+    wb = w * 1024.0 * wscale
+    lines = [
+        f"kernel: {a.kernel}",
+        f"dispatches: fetch run {nf}, write run {nw}",
+        f"FETCH_SIZE raw KiB/dispatch: {f:.1f}",
+        f"WRITE_SIZE raw KiB/dispatch: {w:.1f}",
+        f"copy calibration: {a.copy_bytes} bytes copied, FETCH_SIZE {cf:.1f} KiB -> scale {fscale:.4f}, "
+        f"WRITE_SIZE {cw:.1f} KiB -> scale {wscale:.4f}",
+        f"read_bytes_per_dispatch: {fb:.6g}",
+        f"write_bytes_per_dispatch: {wb:.6g}",
+        f"traffic_bytes_per_dispatch: {fb + wb:.6g}",
+        f"kernel_source_sha256: {kernel_source_sha()}",
+    ]
+    return "\n".join(lines)
+
+
+def read_traffic(path):
+    """(bytes per dispatch, kernel source hash) from a traffic summary, or None."""
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        m = re.match(r"\s*(traffic_bytes_per_dispatch|kernel_source_sha256):\s*(\S+)", line)
+        if m:
+            vals[m.group(1)] = m.group(2)
+    if len(vals) != 2:
+        return None
+    return float(vals["traffic_bytes_per_dispatch"]), vals["kernel_source_sha256"]
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="what", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("csv")
+    s.add_argument("--top", type=int, default=12)
+    s.add_argument("--cmd", required=True)
+    t = sub.add_parser("traffic")
+    for k in ("fetch", "write", "copy_fetch", "copy_write"):
+        t.add_argument("--" + k.replace("_", "-"), dest=k, required=True)
+    t.add_argument("--copy-bytes", type=float, required=True)
+    t.add_argument("--kernel", required=True)
+    t.add_argument("--cmd", required=True)
+    a = ap.parse_args(argv)
+    body = stats(a.csv, a.top) if a.what == "stats" else traffic(a)
+    sys.stdout.write(f"command: {a.cmd}\n\n{body}\n")
+
+
+if __name__ == "__main__":
+    main()

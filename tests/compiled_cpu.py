@@ -1,0 +1,186 @@
+"""Run the generated pass kernels on the CPU (test helper).
+
+Each pass's generated HIP source (ptsbe_plan_pass_source) is compiled with g++
+against a small shim: one OS thread per GPU thread of a block, __syncthreads as
+a std::barrier, the block's LDS as a static buffer, HIP's bit-cast intrinsics
+as memcpy.  The shim runs the kernel over the whole grid on the exported
+device tables, so the pass compiler's output can be checked against the oracle
+without a GPU.  Measure-reset steps between passes follow the same rule as the
+table emulator.
+"""
+
+import ctypes as C
+import hashlib
+import os
+import subprocess
+import tempfile
+
+import numpy as np
+
+import paper_2504_16297_amd as P
+from paper_2504_16297_amd import _lib as L
+from paper_2504_16297_amd.tables import export_tables
+
+SHIM = r"""
+#include <cstdint>
+#include <cstring>
+#include <barrier>
+#include <thread>
+#include <vector>
+struct float2 { float x, y; };
+struct double2 { double x, y; };
+struct uint2 { unsigned x, y; };
+struct Dim3 { unsigned x = 0, y = 0, z = 0; };
+thread_local Dim3 threadIdx, blockIdx;
+Dim3 blockDim, gridDim;
+static std::barrier<>* g_bar = nullptr;
+static inline void __syncthreads() { g_bar->arrive_and_wait(); }
+alignas(16) unsigned char smem[1 << 17];
+static inline float __uint_as_float(uint32_t u) { float f; std::memcpy(&f, &u, 4); return f; }
+static inline uint32_t __float_as_uint(float f) { uint32_t u; std::memcpy(&u, &f, 4); return u; }
+static inline double __longlong_as_double(long long u) { double f; std::memcpy(&f, &u, 8); return f; }
+static inline long long __double_as_longlong(double f) { long long u; std::memcpy(&u, &f, 8); return u; }
+#define __global__
+#define __device__
+#define __forceinline__ inline
+#define __launch_bounds__(x)
+#define __shared__
+#define __align__(x)
+"""
+
+RUNNER = r"""
+extern "C" int run_pass(const unsigned char* blob, const uint64_t* offs, unsigned pass, unsigned slot_begin,
+                        void* states, uint64_t N, unsigned n, unsigned k, unsigned n_passes, unsigned rows,
+                        const uint8_t* mr_bits, const double* mr_norm, unsigned n_measure) {
+  PassArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.passes = blob + offs[0];
+  a.ops = blob + offs[1];
+  a.slot_default = reinterpret_cast<const uint32_t*>(blob + offs[2]) + slot_begin;
+  a.pool = reinterpret_cast<const V*>(blob + offs[3]);
+  a.ov_off = reinterpret_cast<const uint32_t*>(blob + offs[4]);
+  a.ov = reinterpret_cast<const DOverride*>(blob + offs[5]);
+  a.mr_bits = mr_bits;
+  a.mr_norm = mr_norm;
+  a.states = reinterpret_cast<V*>(states);
+  a.route = nullptr;
+  a.carrier0 = 0;
+  a.N = N;
+  a.n = n;
+  a.pass = pass;
+  a.n_passes = n_passes;
+  a.t0 = 0;
+  a.n_measure = n_measure;
+  const unsigned bx = 1u << (k - 4), gx = 1u << (n - k);
+  blockDim.x = bx;
+  gridDim.x = gx;
+  gridDim.y = rows;
+  for (unsigned y = 0; y < rows; ++y)
+    for (unsigned x = 0; x < gx; ++x) {
+      std::barrier<> bar(bx);
+      g_bar = &bar;
+      std::vector<std::thread> th;
+      for (unsigned t = 0; t < bx; ++t)
+        th.emplace_back([&, t]() {
+          threadIdx.x = t;
+          blockIdx.x = x;
+          blockIdx.y = y;
+          ptsbe_pass(a);
+        });
+      for (auto& h : th) h.join();
+    }
+  return 0;
+}
+"""
+
+_CACHE = os.path.join(tempfile.gettempdir(), "ptsbe_compiled_cpu")
+
+
+def pass_source(plan, p):
+    n = C.c_size_t()
+    P.check(L.lib().ptsbe_plan_pass_source(plan.handle, p, None, C.byref(n)))
+    buf = C.create_string_buffer(n.value)
+    P.check(L.lib().ptsbe_plan_pass_source(plan.handle, p, buf, C.byref(n)))
+    return buf.value.decode()
+
+
+def _build(src):
+    os.makedirs(_CACHE, exist_ok=True)
+    h = hashlib.sha256(src.encode()).hexdigest()[:20]
+    so = os.path.join(_CACHE, h + ".so")
+    if not os.path.exists(so):
+        cpp = os.path.join(_CACHE, h + ".cpp")
+        with open(cpp, "w") as f:
+            f.write(SHIM + src + RUNNER)
+        tmp = so + f".{os.getpid()}.tmp"
+        r = subprocess.run(["g++", "-std=c++20", "-O1", "-fPIC", "-shared", "-pthread", "-w", cpp, "-o", tmp],
+                           stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+        if r.returncode:
+            raise RuntimeError("g++ failed on generated pass source:\n" + r.stdout[:4000])
+        os.replace(tmp, so)
+    lib = C.CDLL(so)
+    lib.run_pass.restype = C.c_int
+    lib.run_pass.argtypes = [C.c_void_p, C.c_void_p, C.c_uint, C.c_uint, C.c_void_p, C.c_uint64, C.c_uint,
+                             C.c_uint, C.c_uint, C.c_uint, C.c_void_p, C.c_void_p, C.c_uint]
+    return lib
+
+
+def _raw_tables(ts, params):
+    pa = None
+    if params is not None and len(params):
+        pa = np.ascontiguousarray(params, dtype=np.float64)
+    pp = C.cast(pa.ctypes.data, C.POINTER(C.c_double)) if pa is not None else None
+    n = C.c_size_t()
+    offs = np.zeros(16, dtype=np.uint64)
+    P.check(L.lib().ptsbe_trajset_tables(ts.handle, pp, 0, None, C.byref(n), offs.ctypes.data))
+    buf = np.zeros(n.value, dtype=np.uint8)
+    P.check(L.lib().ptsbe_trajset_tables(ts.handle, pp, 0, buf.ctypes.data, C.byref(n), offs.ctypes.data))
+    return buf, offs
+
+
+def run_compiled(plan, ts, params=None, mr_tol=1e-6):
+    """States [B, 2^n] (normalised) after running every pass through its
+    generated kernel on the CPU."""
+    info = plan.info
+    n = info["n_qubits"]
+    N = 1 << n
+    B = ts.n_traj
+    t = export_tables(ts, params)
+    blob, offs = _raw_tables(ts, params)
+    passes = t["passes"]
+    NP = len(passes)
+    c64 = info["precision"] == L.C64
+    states = np.zeros((B, N), dtype=np.complex64 if c64 else np.complex128)
+    nm = info["n_measure"]
+    mr_bits = np.zeros(max(1, B * nm), dtype=np.uint8)
+    mr_norm = np.zeros(max(1, B * nm), dtype=np.float64)
+    slot_begin = [int(ps["slot_begin"]) for ps in passes]
+    libs = {}
+    x = np.arange(N, dtype=np.int64)
+    for ex in t["exec"]:
+        if ex["pass"] != 0xFFFFFFFF:
+            p = int(ex["pass"])
+            src = pass_source(plan, p)
+            if not src:
+                raise RuntimeError(f"pass {p} has no compiled kernel")
+            if src not in libs:
+                libs[src] = _build(src)
+            k = int(passes[p]["k"])
+            libs[src].run_pass(blob.ctypes.data, offs.ctypes.data, p, slot_begin[p], states.ctypes.data, N, n, k,
+                               NP, B, mr_bits.ctypes.data, mr_norm.ctypes.data, nm)
+        else:
+            for b in range(B):
+                w = np.abs(states[b].astype(np.complex128)) ** 2
+                tot = w.sum()
+                for j in range(int(ex["nq"])):
+                    q = int(ex["q"][j])
+                    p1 = w[((x >> q) & 1) == 1].sum() / tot
+                    if min(p1, 1 - p1) > mr_tol:
+                        raise RuntimeError(f"non-deterministic measure-reset on qubit {q}")
+                    bit = 1 if p1 > 0.5 else 0
+                    r = int(ex["idx"][j])
+                    pb = p1 if bit else 1 - p1
+                    mr_bits[b * nm + r] = bit
+                    mr_norm[b * nm + r] = 1.0 / np.sqrt(pb * tot) if j == 0 else 1.0 / np.sqrt(pb)
+    out = states.astype(np.complex128)
+    return out / np.linalg.norm(out, axis=1, keepdims=True)

@@ -199,3 +199,121 @@ def test_expectation_mode_matches_oracle():
         od += c * s
     for a, psi in enumerate(ref):
         assert abs(e[a] - float(np.sum(np.abs(psi) ** 2 * od))) < 1e-5
+
+
+def _expected_state_passes(ts, B_batch):
+    """Rows launched under prefix sharing: per batch and execution step, the
+    trajectories that have diverged by then, plus one carrier row while some
+    have not (a trajectory diverges at the first pass its overrides touch, or
+    at the last pass)."""
+    from paper_2504_16297_amd.tables import export_tables
+    t = export_tables(ts)
+    NP = len(t["passes"])
+    ex = [int(e["pass"]) for e in t["exec"]]
+    ov = t["ov_off"].astype(np.int64)
+    B = ts.n_traj
+    eff = []
+    for b in range(B):
+        f = len(ex) - 1
+        for e, p in enumerate(ex):
+            if ov[b * NP + p + 1] > ov[b * NP + p]:
+                f = e
+                break
+        eff.append(f)
+    rows = 0
+    for b0 in range(0, B, B_batch):
+        sub = eff[b0:b0 + B_batch]
+        for e in range(len(ex)):
+            rows += sum(1 for f in sub if f <= e) + (1 if any(f > e for f in sub) else 0)
+    return rows
+
+
+@pytest.mark.parametrize("max_batch", [0, 7])
+def test_prefix_sharing_is_bit_identical(max_batch):
+    """Sharing the error-free prefix changes which passes run, never a value:
+    states and shots equal the unshared run bit for bit; the launched
+    state-passes match the count the records imply."""
+    log(f"[prefix sharing] max_batch={max_batch}")
+    circ = random_small_circuit(12, 120, np.random.default_rng(21), p1=0.02, p2=0.03)
+    plan = P.ptsbe_plan(circ, tile_qubits=8)
+    ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=60, total_shots=20000, seed=5, cfg=2)
+    outs = []
+    for share in (True, False):
+        tm = np.zeros(10)
+        r = P.ptsbe_run_batch(plan, ts, mode="states", max_batch=max_batch, prefix_sharing=share, timing=tm)
+        s = P.ptsbe_run_batch(plan, ts, mode="shots", seed=5, cfg=2, max_batch=max_batch, prefix_sharing=share)
+        torch.cuda.synchronize()
+        outs.append((r["states"].cpu().numpy(), s["bits"].cpu().numpy(), s["traj"].cpu().numpy(), tm))
+    (s1, b1, t1, tm1), (s0, b0, t0, tm0) = outs
+    assert np.array_equal(s1, s0)
+    assert np.array_equal(b1, b0) and np.array_equal(t1, t0)
+    B = ts.n_traj
+    n_pass = plan.info["n_passes"]
+    assert tm0[9] == B * n_pass
+    assert tm1[9] == _expected_state_passes(ts, max_batch or B)
+    log(f"  state-passes shared {tm1[9]:.0f} vs {tm0[9]:.0f}")
+    assert tm1[9] < tm0[9]
+    ref, _ = oracle_states(circ, ts.get()["records"])
+    err = max(float(np.max(np.abs(s1[a] - ref[a]))) for a in range(len(ref)))
+    assert err <= 1e-5
+
+
+@pytest.mark.parametrize("n,prec,tile", [(12, "c64", 0), (14, "c64", 9), (12, "c128", 0), (13, "c128", 8)])
+def test_compiled_passes_match_generic_kernels(n, prec, tile):
+    """Per-pass compiled kernels against the generic tile kernels and the oracle,
+    on circuits with every operation kind (4x4 gates, diagonals on and off the
+    tile, CZ-type signs, Pauli and U3-mixture noise)."""
+    log(f"[compiled passes] n={n} {prec} tile={tile}")
+    rng = np.random.default_rng(700 + n + tile)
+    circ = random_small_circuit(n, 90, rng, p1=0.1, p2=0.15, with_params=True)
+    params = np.asarray(circ["params"])
+    pc = P.ptsbe_plan(circ, precision=prec, tile_qubits=tile)
+    pg = P.ptsbe_plan(circ, precision=prec, tile_qubits=tile, compile=False)
+    nk, sec = P.ptsbe_plan_compile(pc)
+    log(f"  {nk} kernels compiled in {sec:.1f} s for {pc.info['n_passes']} passes")
+    ts_c = P.ptsbe_sample_kraus(pc, "proportional", n_draws=12, total_shots=12, seed=2, cfg=1)
+    ts_g = P.ptsbe_sample_kraus(pg, "proportional", n_draws=12, total_shots=12, seed=2, cfg=1)
+    a = _states(pc, ts_c, params=params)
+    b = _states(pg, ts_g, params=params)
+    tol = 1e-5 if prec == "c64" else 1e-12
+    assert float(np.max(np.abs(a - b))) <= tol
+    ref, _ = oracle_states(circ, ts_c.get()["records"], params=params)
+    err = max(float(np.max(np.abs(a[i] - ref[i]))) for i in range(len(ref)))
+    log(f"  max|compiled - oracle| = {err:.2e}")
+    assert err <= tol
+
+
+@pytest.mark.parametrize("wl_name", ["c1", "random12"])
+def test_graph_replays_match_eager(wl_name):
+    """A captured run replayed several times, with eager work and synchronisation
+    between replays, reproduces the eager run's shots bit for bit each time."""
+    log(f"[graph] {wl_name}")
+    if wl_name == "c1":
+        wl = c1_workload()
+        circ, prec = wl["circuit"], "c128"
+        pts = wl["pts"]
+        plan = P.ptsbe_plan(circ, precision=prec)
+        ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=pts["n_draws"], total_shots=pts["total_shots"],
+                                  seed=wl["seed"], cfg=wl["cfg"])
+        seed, cfg = wl["seed"], wl["cfg"]
+    else:
+        circ = random_small_circuit(12, 80, np.random.default_rng(44), p1=0.05, p2=0.08)
+        plan = P.ptsbe_plan(circ)
+        ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=40, total_shots=30000, seed=3, cfg=2)
+        seed, cfg = 3, 2
+    eager = P.ptsbe_run_batch(plan, ts, seed=seed, cfg=cfg)
+    torch.cuda.synchronize()
+    eb, et = eager["bits"].cpu().numpy().copy(), eager["traj"].cpu().numpy().copy()
+    s = torch.cuda.Stream()
+    cap = P.ptsbe_run_batch(plan, ts, seed=seed, cfg=cfg, stream=s, capture=True)
+    g = cap["graph"]
+    for rep in range(4):
+        cap["bits"].fill_(-1)
+        cap["traj"].fill_(-1)
+        torch.cuda.synchronize()
+        g.launch(stream=s)
+        s.synchronize()
+        assert np.array_equal(cap["bits"].cpu().numpy(), eb), rep
+        assert np.array_equal(cap["traj"].cpu().numpy(), et), rep
+        x = torch.randn(1 << 16, device="cuda")       # unrelated eager work between replays
+        float((x * x).sum())
