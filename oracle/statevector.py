@@ -108,3 +108,44 @@ def run_record(circuit, record, params=None, steps_sites=None, chans=None,
         else:
             raise ValueError(kind)
     return psi, bits
+
+
+def product_factors(circuit, record, params=None):
+    """One-qubit factors of psi_alpha when every operation and noise site acts on
+    a single qubit: then psi = (x)_q v_q with v_q = (product of the operators on
+    q, in circuit order) |0>, so amplitude x is prod_q v_q[x_q].  Returns an
+    (n, 2) complex128 array; raises ValueError on any multi-qubit step.  This is
+    the plain definition of the state for such circuits, usable at any n."""
+    n = circuit["n_qubits"]
+    steps, sites = expand(circuit)
+    chans = site_channels(circuit)
+    if params is None:
+        params = circuit.get("params", [])
+    ks = dict(record)
+    v = np.zeros((n, 2), dtype=np.complex128)
+    v[:, 0] = 1.0
+    for st in steps:
+        kind = st[0]
+        if kind == "gate":
+            U = gate_matrix(st[1], st[3])
+        elif kind == "param":
+            U = rot(st[1], params[st[3]])
+        elif kind == "site":
+            _, us = chans[sites[st[1]]["channel"]]
+            U = us[ks.get(st[1], 0)]
+        else:
+            raise ValueError(f"{kind} is not a one-qubit unitary step")
+        qs = st[2]
+        if len(qs) != 1:
+            raise ValueError("product_factors needs one-qubit operations only")
+        v[qs[0]] = U @ v[qs[0]]
+    return v
+
+
+def product_amplitudes(factors, xs):
+    """Amplitudes <x|psi> = prod_q factors[q, x_q] for basis indices xs."""
+    xs = np.asarray(xs, dtype=np.int64)
+    out = np.ones(xs.shape, dtype=np.complex128)
+    for q in range(factors.shape[0]):
+        out *= factors[q, (xs >> q) & 1]
+    return out

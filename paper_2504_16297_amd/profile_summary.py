@@ -1,15 +1,16 @@
 """Turn rocprofv3 CSV output into the short text summaries kept with the
 project, and read those summaries back.
 
-    python -m paper_2504_16297_amd.profile_summary stats KERNEL_STATS_CSV --cmd "..." [--top 12]
-    python -m paper_2504_16297_amd.profile_summary traffic --kernel k_pass_reg \\
+    python -m paper_2504_16297_amd.profile_summary stats KERNEL_STATS_CSV --cmd "..." [--top 12] [--group RE]
+    python -m paper_2504_16297_amd.profile_summary traffic --kernel ptsbe_pass_ \\
         --fetch F.csv --write W.csv --copy-fetch CF.csv --copy-write CW.csv --copy-bytes B --cmd "..."
 
 `traffic` averages FETCH_SIZE and WRITE_SIZE (KiB per dispatch) over the
 dispatches of the named kernel and scales each by what the same counter reads
 for a plain device copy of known size (the copy's bytes divided by its
 counter), giving HBM bytes per dispatch.  The summary records the SHA-256 of
-the kernel source the counters were taken with, so a reader can tell when the
+the kernel sources (generic kernels and pass generator) the counters were
+taken with, so a reader can tell when the
 kernel has changed since.
 """
 
@@ -21,12 +22,16 @@ import re
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCE = os.path.join(HERE, "csrc", "kernels.hip")
+# the tile-pass kernels: the generic kernels and the generator of the compiled ones
+KERNEL_SOURCES = [os.path.join(HERE, "csrc", "kernels.hip"), os.path.join(HERE, "csrc", "jit.cpp")]
 
 
 def kernel_source_sha():
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def _short(name):
@@ -39,7 +44,7 @@ def _short(name):
     return base
 
 
-def stats(path, top=12):
+def stats(path, top=12, group=None):
     rows = list(csv.DictReader(open(path)))
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
     out = ["| kernel | calls | total ms | avg us | min us | max us | % |", "|---|---|---|---|---|---|---|"]
@@ -47,6 +52,13 @@ def stats(path, top=12):
         out.append(f"| {_short(r['Name'])} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
                    f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
                    f"{float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
+    if group:
+        g = [r for r in rows if re.search(group, r["Name"])]
+        calls = sum(int(r["Calls"]) for r in g)
+        tot = sum(float(r["TotalDurationNs"]) for r in g)
+        out.append("")
+        out.append(f"group /{group}/: {len(g)} kernels, {calls} launches, {tot / 1e6:.3f} ms, "
+                   f"average launch {tot / max(calls, 1) / 1e6:.4f} ms")
     return "\n".join(out)
 
 
@@ -108,6 +120,7 @@ def main(argv=None):
     s = sub.add_parser("stats")
     s.add_argument("csv")
     s.add_argument("--top", type=int, default=12)
+    s.add_argument("--group", default=None, help="regex: also report the combined average launch")
     s.add_argument("--cmd", required=True)
     t = sub.add_parser("traffic")
     for k in ("fetch", "write", "copy_fetch", "copy_write"):
@@ -116,7 +129,7 @@ def main(argv=None):
     t.add_argument("--kernel", required=True)
     t.add_argument("--cmd", required=True)
     a = ap.parse_args(argv)
-    body = stats(a.csv, a.top) if a.what == "stats" else traffic(a)
+    body = stats(a.csv, a.top, a.group) if a.what == "stats" else traffic(a)
     sys.stdout.write(f"command: {a.cmd}\n\n{body}\n")
 
 

@@ -113,3 +113,25 @@ def test_ghz_closed_form(n):
     ref = np.zeros(1 << n, dtype=complex)
     ref[0] = ref[-1] = 1 / math.sqrt(2)
     assert np.max(np.abs(psi - ref)) < 1e-15
+
+
+@pytest.mark.parametrize("n", [3, 7, 10])
+def test_product_factors_equal_full_simulation(n):
+    """product_factors / product_amplitudes against the full state vector for
+    circuits of one-qubit gates, parameterised rotations and Pauli records."""
+    from oracle.noise import expand
+    from oracle.statevector import product_amplitudes, product_factors, run_record
+    from workloads import product_circuit
+    rng = np.random.default_rng(40 + n)
+    circ = product_circuit(n, 3, rng, 0.1)
+    circ["ops"].append({"kind": "param", "gen": "Y", "qubits": (n - 1,), "index": 0, "tag": "RY"})
+    circ["params"] = [0.7]
+    _, sites = expand(circ)
+    rec = tuple(sorted((int(s), int(rng.integers(1, 4))) for s in rng.choice(len(sites), 4, replace=False)))
+    psi, _ = run_record(circ, rec)
+    f = product_factors(circ, rec)
+    x = np.arange(1 << n)
+    assert np.max(np.abs(product_amplitudes(f, x) - psi)) < 1e-13
+    circ["ops"].append({"kind": "gate", "name": "CZ", "qubits": (0, 1), "params": (), "tag": "CZ"})
+    with pytest.raises(ValueError):
+        product_factors(circ, rec)

@@ -17,6 +17,7 @@ from .circuits import (  # noqa: F401
     c3_workload,
     c4_workload,
     c5_workload,
+    product_circuit,
     random_small_circuit,
     surface_code_d3,
     hea_circuit,

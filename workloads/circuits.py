@@ -177,6 +177,21 @@ def hea_circuit(n, layers, rng, p2):
             "params": [float(x) for x in params]}
 
 
+def product_circuit(n, layers, rng, p1):
+    """Layers of U3 (angles U[0, 2pi)) on every qubit, each followed by 1-qubit
+    depolarizing p1; no entangling gates, so every trajectory is a product
+    state (large-n cases with amplitudes computable one by one)."""
+    ops = []
+    for layer in range(layers):
+        angles = rng.uniform(0.0, 2.0 * math.pi, size=(n, 3))
+        for q in range(n):
+            ops.append({"kind": "gate", "name": "U3", "qubits": (q,),
+                        "params": tuple(float(a) for a in angles[q]), "tag": "U3"})
+    channels = [{"name": "depolarizing", "nq": 1, "p": float(p1)}] if p1 > 0 else []
+    rules = [{"when": "after_tag", "tag": "U3", "channel": 0}] if p1 > 0 else []
+    return {"n_qubits": n, "ops": ops, "channels": channels, "rules": rules, "params": []}
+
+
 def zz_ring(n):
     """Observable sum_i Z_i Z_{(i+1) mod n} as (coefficient, qubits) Z-strings."""
     return [(1.0, (i, (i + 1) % n)) for i in range(n)]
