@@ -85,6 +85,9 @@ def main():
     ap.add_argument("--baseline-shots", type=int, default=512)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 2 GiB device copy (calibrates FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c4"],
+                    help="c2: the 20-qubit headline workload; c4: the 24/26/28-qubit mixed batch and the "
+                         "33-qubit trajectory")
     args = ap.parse_args()
     if args.copy_probe:
         import torch
@@ -101,6 +104,9 @@ def main():
               f"sharding is a partition of the trajectory set, not built); --gpus {args.gpus} is "
               f"not supported", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "c4":
+        return bench_c4(args)
 
     import numpy as np
     import torch
@@ -202,6 +208,119 @@ def main():
     if not args.no_cpu:
         log("[bench] timing the oracle on the host ...")
         result["cpu_baseline"] = cpu_baseline(wl, g)
+    print(json.dumps(result))
+
+
+def bench_c4(args):
+    """The mixed-size batch: brick circuits of 24, 26 and 28 qubits (30 layers,
+    p2 = 1e-2) with 256 / 64 / 16 proportional draws x 10^5 shots, run back to
+    back as one step; the per-shot baseline at 28 qubits; then one 33-qubit
+    trajectory x 10^6 shots (64 GiB state) timed on its own."""
+    import numpy as np
+    import torch
+
+    import paper_2504_16297_amd as P
+    from workloads import c4_workload
+
+    torch.cuda.set_device(0)
+    runs = []
+    for n in (24, 26, 28):
+        wl = c4_workload(n)
+        pts = wl["pts"]
+        plan = P.ptsbe_plan(wl["circuit"], precision="c64")
+        ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=pts["n_draws"], total_shots=pts["total_shots"],
+                                  seed=wl["seed"], cfg=wl["cfg"])
+        nk, csec = P.ptsbe_plan_compile(plan)
+        S = int(ts.get()["total_shots"])
+        ws = torch.empty(P.ptsbe_workspace_size(plan, ts, mode="shots"), dtype=torch.uint8, device="cuda")
+        out = {"bits": torch.empty(S, dtype=torch.int32, device="cuda"),
+               "traj": torch.empty(S, dtype=torch.int32, device="cuda")}
+        runs.append({"n": n, "wl": wl, "plan": plan, "ts": ts, "ws": ws, "out": out, "S": S})
+        log(f"[bench c4] {n} qubits: {ts.n_traj} trajectories, {plan.info['n_passes']} passes, {nk} kernels "
+            f"({csec:.1f} s), workspace {ws.numel() / 2**30:.1f} GiB")
+
+    def step(timings=None):
+        for i, r in enumerate(runs):
+            tm = np.zeros(10) if timings is not None else None
+            P.ptsbe_run_batch(r["plan"], r["ts"], seed=r["wl"]["seed"], cfg=r["wl"]["cfg"], workspace=r["ws"],
+                              out=r["out"], timing=tm)
+            if timings is not None:
+                timings.append(tm)
+
+    for i in range(args.warmup):
+        step()
+        log(f"[bench c4] warmup {i + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+    timings = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(timings)
+        log(f"[bench c4] step {i + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    S = sum(r["S"] for r in runs)
+    value = S * args.steps / dt
+    T = np.sum(timings, axis=0)
+    per28 = np.sum(timings[2::3], axis=0)
+    rate28 = runs[2]["S"] * args.steps / (per28[5] * 1e-3)
+    pass_ms = T[0] / T[1]
+    tflops = T[8] / T[1] / (pass_ms * 1e-3) / 1e12
+    gbs = T[6] / T[1] / (pass_ms * 1e-3) / 1e9
+    result = {"metric": METRIC, "value": value, "unit": "shots/s", "n_gpus": 1, "steps": args.steps,
+              "warmup": args.warmup, "ms_per_step": dt * 1e3 / args.steps, "higher_is_better": True,
+              "scaling": "weak", "vs_baseline": None, "dtype": "c64 (fp32 state, fp64 norm/CDF)",
+              "data": "synthetic",
+              "config": {"workload": "C4 mixed batch: 24/26/28 qubits x 30 brick layers, 256/64/16 draws "
+                                     "x 1e5 shots", "total_shots": S,
+                         "trajectories": [r["ts"].n_traj for r in runs], "parallelism": "single GPU, batched"},
+              "roofline": {"bound": "alu", "achieved": tflops, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                           "frac": tflops / FP32_PEAK_TFLOPS, "traffic": None,
+                           "kernel": "ptsbe_pass_* (compiled fused tile passes)", "avg_launch_ms": pass_ms,
+                           "hbm": {"achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                   "frac": gbs / HBM_PEAK_GBS}},
+              "q28_batched_shots_per_s": rate28}
+    if not args.no_baseline:
+        r = runs[2]
+        nb = 8
+        tb = P.ptsbe_sample_kraus(r["plan"], "per_shot", n_draws=nb, seed=r["wl"]["seed"], cfg=r["wl"]["cfg"])
+        for x in runs:
+            del x["ws"]
+        torch.cuda.empty_cache()
+        bws = torch.empty(P.ptsbe_workspace_size(r["plan"], tb, mode="shots"), dtype=torch.uint8, device="cuda")
+        bout = {"bits": torch.empty(nb, dtype=torch.int32, device="cuda"),
+                "traj": torch.empty(nb, dtype=torch.int32, device="cuda")}
+        P.ptsbe_run_batch(r["plan"], tb, workspace=bws, out=bout)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P.ptsbe_run_batch(r["plan"], tb, workspace=bws, out=bout)
+        torch.cuda.synchronize()
+        base = nb / (time.perf_counter() - t0)
+        result["q28_per_shot_baseline_shots_per_s"] = base
+        result["q28_speedup_vs_per_shot"] = rate28 / base
+        log(f"[bench c4] 28 qubits: batched {rate28:.4g} shots/s, per-shot {base:.4g} shots/s, "
+            f"speedup {rate28 / base:.1f}x")
+        del bws
+    runs.clear()
+    torch.cuda.empty_cache()
+    wl = c4_workload(33)
+    plan = P.ptsbe_plan(wl["circuit"], precision="c64")
+    ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=1, total_shots=10**6, seed=wl["seed"], cfg=wl["cfg"])
+    P.ptsbe_plan_compile(plan)
+    ws = torch.empty(P.ptsbe_workspace_size(plan, ts, mode="shots"), dtype=torch.uint8, device="cuda")
+    out = {"bits": torch.empty(10**6, dtype=torch.int64, device="cuda"),
+           "traj": torch.empty(10**6, dtype=torch.int32, device="cuda")}
+    P.ptsbe_run_batch(plan, ts, seed=wl["seed"], cfg=wl["cfg"], workspace=ws, out=out)
+    torch.cuda.synchronize()
+    tm = np.zeros(10)
+    t0 = time.perf_counter()
+    P.ptsbe_run_batch(plan, ts, seed=wl["seed"], cfg=wl["cfg"], workspace=ws, out=out, timing=tm)
+    torch.cuda.synchronize()
+    d33 = time.perf_counter() - t0
+    result["q33"] = {"shots": 10**6, "seconds": d33, "shots_per_s": 10**6 / d33, "passes": plan.info["n_passes"],
+                     "pass_ms": tm[0], "state_gib": (1 << 33) * 8 / 2**30,
+                     "pass_hbm_gbs": tm[6] / (tm[0] * 1e-3) / 1e9}
+    log(f"[bench c4] 33 qubits: {d33:.2f} s for 1e6 shots ({plan.info['n_passes']} passes, "
+        f"{tm[6] / (tm[0] * 1e-3) / 1e9:.0f} GB/s in the passes)")
     print(json.dumps(result))
 
 

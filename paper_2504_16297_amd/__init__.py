@@ -89,7 +89,10 @@ class Plan:
     def __del__(self):
         h = getattr(self, "handle", None)
         if h:
-            lib().ptsbe_plan_destroy(h)
+            try:
+                lib().ptsbe_plan_destroy(h)
+            except Exception:  # interpreter shutdown
+                pass
             self.handle = None
 
 
@@ -102,10 +105,11 @@ def ptsbe_plan_compile(plan):
     return nk.value, sec.value
 
 
-def ptsbe_plan(circuit, precision="c64", tile_qubits=0, compile=True):
+def ptsbe_plan(circuit, precision="c64", tile_qubits=0, compile=True, min_fill=0):
     """Build the execution plan of a circuit dictionary (ops, channels, rules).
     ``compile=False`` runs the passes through the generic tile kernels instead of
-    per-pass compiled kernels."""
+    per-pass compiled kernels; ``min_fill`` (1..7, 0 = 3) is the fewest 2x2
+    matrices a partial register group must hold."""
     ops = circuit["ops"]
     arr = (L.Op * max(1, len(ops)))()
     keep = []
@@ -166,8 +170,10 @@ def ptsbe_plan(circuit, precision="c64", tile_qubits=0, compile=True):
             raise ValueError(w)
     c = L.Circuit(circuit["n_qubits"], len(ops), arr)
     nm = L.NoiseModel(len(chans), carr, len(rules), rarr)
+    if not 0 <= int(min_fill) <= 7:
+        raise ValueError("min_fill must be in 0..7")
     po = L.PlanOpts({"c64": L.C64, "c128": L.C128}[precision], int(tile_qubits),
-                    0 if compile else L.PLAN_NO_COMPILE, 0)
+                    int(min_fill) | (0 if compile else L.PLAN_NO_COMPILE), 0)
     h = C.c_void_p()
     check(lib().ptsbe_plan(C.byref(c), C.byref(nm), C.byref(po), C.byref(h)))
     return Plan(h, None)
@@ -215,7 +221,10 @@ class TrajSet:
     def __del__(self):
         h = getattr(self, "handle", None)
         if h:
-            lib().ptsbe_trajset_destroy(h)
+            try:
+                lib().ptsbe_trajset_destroy(h)
+            except Exception:  # interpreter shutdown
+                pass
             self.handle = None
 
 
@@ -382,7 +391,10 @@ class RunGraph:
     def __del__(self):
         h = getattr(self, "handle", None)
         if h:
-            lib().ptsbe_graph_destroy(h)
+            try:
+                lib().ptsbe_graph_destroy(h)
+            except Exception:  # interpreter shutdown
+                pass
             self.handle = None
 
 

@@ -1,0 +1,124 @@
+"""Large-state parity (24-33 qubits), where the full oracle state is out of
+reach: product-state circuits whose amplitudes the oracle computes one by one
+(oracle.statevector.product_factors), shot marginals against the closed form,
+expectation values of Z strings against the closed form, and, for the
+entangling 24/26/28-qubit brick workloads, compiled against generic kernels
+and the bookkeeping of shots and trajectory tags."""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2504_16297_amd as P
+from gpu_helpers import log
+from oracle.statevector import product_amplitudes, product_factors
+from workloads import c4_workload, product_circuit
+
+pytestmark = pytest.mark.gpu
+
+
+def _marginal_check(bits, f, n, m):
+    p1 = np.abs(f[:, 1]) ** 2 / (np.abs(f[:, 0]) ** 2 + np.abs(f[:, 1]) ** 2)
+    worst = 0.0
+    for q in range(n):
+        freq = float(np.mean((bits >> q) & 1))
+        sd = math.sqrt(max(p1[q] * (1 - p1[q]), 1e-12) / m)
+        worst = max(worst, abs(freq - p1[q]) / sd)
+    return worst
+
+
+def test_product_28q_amplitudes_and_shots():
+    n = 28
+    circ = product_circuit(n, 4, np.random.default_rng(28), 0.02)
+    plan = P.ptsbe_plan(circ)
+    ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=4, total_shots=4 * 100000, seed=7, cfg=4)
+    g = ts.get()
+    log(f"[28q product] trajectories={ts.n_traj} passes={plan.info['n_passes']}")
+    r = P.ptsbe_run_batch(plan, ts, mode="states")
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(1)
+    xs = rng.integers(0, 1 << n, size=4096)
+    xs[:2] = [0, (1 << n) - 1]
+    for a in range(ts.n_traj):
+        f = product_factors(circ, g["records"][a])
+        ref = product_amplitudes(f, xs)
+        got = r["states"][a][torch.as_tensor(xs, device="cuda")].cpu().numpy().astype(np.complex128)
+        err = float(np.max(np.abs(got - ref)))
+        rel = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+        log(f"  trajectory {a}: max|d| = {err:.2e}, relative to the largest sampled amplitude {rel:.2e}")
+        assert err <= 1e-5 and rel <= 1e-4
+    del r
+    torch.cuda.empty_cache()
+    s = P.ptsbe_run_batch(plan, ts, mode="shots", seed=7, cfg=4)
+    torch.cuda.synchronize()
+    bits = s["bits"].cpu().numpy().astype(np.int64)
+    traj = s["traj"].cpu().numpy()
+    off = np.concatenate([[0], np.cumsum(g["m"].astype(np.int64))])
+    for a in range(ts.n_traj):
+        seg = slice(off[a], off[a + 1])
+        assert np.all(traj[seg] == a)
+        z = _marginal_check(bits[seg] & ((1 << n) - 1), product_factors(circ, g["records"][a]), n, int(g["m"][a]))
+        log(f"  trajectory {a}: worst single-qubit marginal deviation {z:.2f} sigma")
+        assert z < 5.5
+
+
+def test_product_33q_expectations_and_shots():
+    """One 33-qubit trajectory (64 GiB complex64 state): Z and ZZ expectation
+    values and single-qubit shot marginals against the product closed form."""
+    n = 33
+    circ = product_circuit(n, 2, np.random.default_rng(33), 0.0)
+    plan = P.ptsbe_plan(circ)
+    ts = P.ptsbe_trajset_from_records(plan, [()], [1000000])
+    f = product_factors(circ, ())
+    z = (np.abs(f[:, 0]) ** 2 - np.abs(f[:, 1]) ** 2)
+    obs = [(1.0, (0,)), (0.5, (17, 32)), (0.25, (31,))]
+    ref = 1.0 * z[0] + 0.5 * z[17] * z[32] + 0.25 * z[31]
+    r = P.ptsbe_run_batch(plan, ts, mode="expectation", observable=obs)
+    torch.cuda.synchronize()
+    got = float(r["expval"].cpu().numpy()[0])
+    log(f"[33q product] passes={plan.info['n_passes']} <O> = {got:.8f}, closed form {ref:.8f}")
+    assert abs(got - ref) <= 1e-5
+    del r
+    torch.cuda.empty_cache()
+    s = P.ptsbe_run_batch(plan, ts, mode="shots", seed=1, cfg=4)
+    torch.cuda.synchronize()
+    bits = s["bits"].cpu().numpy()
+    assert s["bits"].dtype == torch.int64 and np.all(bits >= 0) and np.all(bits < (1 << n))
+    zs = _marginal_check(bits.astype(np.int64), f, n, 1000000)
+    log(f"  worst single-qubit marginal deviation {zs:.2f} sigma")
+    assert zs < 5.5
+
+
+@pytest.mark.parametrize("n", [24, 28])
+def test_brick_compiled_vs_generic_and_tags(n):
+    """The entangling brick workload: compiled and generic kernels agree on
+    the states of two trajectories; every shot carries its trajectory's tag,
+    in the trajectory's own m_alpha range."""
+    wl = c4_workload(n)
+    circ = wl["circuit"]
+    pc = P.ptsbe_plan(circ)
+    pg = P.ptsbe_plan(circ, compile=False)
+    ts = P.ptsbe_sample_kraus(pc, "proportional", n_draws=wl["pts"]["n_draws"],
+                              total_shots=wl["pts"]["total_shots"], seed=wl["seed"], cfg=wl["cfg"])
+    g = ts.get()
+    sub_c = ts.slice(0, 2)
+    sub_g = P.ptsbe_trajset_from_records(pg, g["records"][:2], g["m"][:2])
+    a = P.ptsbe_run_batch(pc, sub_c, mode="states")["states"]
+    b = P.ptsbe_run_batch(pg, sub_g, mode="states")["states"]
+    torch.cuda.synchronize()
+    d = float((a - b).abs().max())
+    nrm = float((a.abs() ** 2).sum(dim=1).max())
+    log(f"[{n}q brick] compiled vs generic max|d| = {d:.2e}, max norm^2 = {nrm:.8f}")
+    assert d <= 1e-6 and abs(nrm - 1) <= 1e-4
+    del a, b
+    torch.cuda.empty_cache()
+    s = P.ptsbe_run_batch(pc, ts, mode="shots", seed=wl["seed"], cfg=wl["cfg"])
+    torch.cuda.synchronize()
+    traj = s["traj"].cpu().numpy()
+    bits = s["bits"].cpu().numpy()
+    assert np.all(bits >= 0) and np.all(bits < (1 << n))
+    counts = np.bincount(traj, minlength=ts.n_traj)
+    assert np.array_equal(counts, g["m"].astype(np.int64))
+    assert np.all(np.diff(traj) >= 0)
