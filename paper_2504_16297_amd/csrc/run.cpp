@@ -357,15 +357,17 @@ ptsbe_status run_typed(const Plan& P, TrajSet& ts, const ptsbe_run_opts& o, uint
   return PTSBE_OK;
 }
 
-ptsbe_status check_opts(const Plan& P, const TrajSet& ts, const ptsbe_run_opts* o) {
+// `outputs`: also check the output pointers (not needed for a size query)
+ptsbe_status check_opts(const Plan& P, const TrajSet& ts, const ptsbe_run_opts* o, bool outputs) {
   if (!o) return fail(PTSBE_E_ARG, "null run options");
   if (o->mode > PTSBE_RUN_EXPECTATION) return fail(PTSBE_E_ARG, "bad run mode");
   uint32_t c = o->sort_chunk ? o->sort_chunk : 4096;
   if (c < 256 || c > 4096 || (c & (c - 1))) return fail(PTSBE_E_ARG, "sort_chunk must be a power of two in 256..4096");
   if (P.n_params && !o->params) return fail(PTSBE_E_ARG, "the circuit has parameters: params required");
-  if (o->mode == PTSBE_RUN_STATES && !o->d_state_out) return fail(PTSBE_E_ARG, "STATES mode needs d_state_out");
+  if (outputs && o->mode == PTSBE_RUN_STATES && !o->d_state_out)
+    return fail(PTSBE_E_ARG, "STATES mode needs d_state_out");
   if (o->mode == PTSBE_RUN_EXPECTATION) {
-    if (!o->d_expval) return fail(PTSBE_E_ARG, "EXPECTATION mode needs d_expval");
+    if (outputs && !o->d_expval) return fail(PTSBE_E_ARG, "EXPECTATION mode needs d_expval");
     if (o->n_terms > 64 || (o->n_terms && (!o->obs_coef || !o->obs_zmask)))
       return fail(PTSBE_E_ARG, "observable: at most 64 Z-string terms with coefficients and masks");
   }
@@ -376,7 +378,7 @@ ptsbe_status check_opts(const Plan& P, const TrajSet& ts, const ptsbe_run_opts* 
 }  // namespace
 
 ptsbe_status workspace_size(const Plan& P, TrajSet& ts, const ptsbe_run_opts* o, size_t* bytes) {
-  ptsbe_status st = check_opts(P, ts, o);
+  ptsbe_status st = check_opts(P, ts, o, false);
   if (st != PTSBE_OK) return st;
   uint32_t chunk = o->sort_chunk ? o->sort_chunk : 4096;
   {
@@ -394,7 +396,7 @@ ptsbe_status workspace_size(const Plan& P, TrajSet& ts, const ptsbe_run_opts* o,
 ptsbe_status run_batch(const Plan& P, TrajSet& ts, const ptsbe_run_opts* o, void* d_ws, size_t ws_bytes,
                        void* d_bits, uint32_t* d_traj, uint64_t capacity, uint8_t* d_mr_bits, void* stream,
                        hipGraphExec_t* graph_out) {
-  ptsbe_status st = check_opts(P, ts, o);
+  ptsbe_status st = check_opts(P, ts, o, true);
   if (st != PTSBE_OK) return st;
   if (!d_ws) return fail(PTSBE_E_ARG, "null workspace");
   if (reinterpret_cast<uintptr_t>(d_ws) % 256) return fail(PTSBE_E_ARG, "workspace must be 256-byte aligned");

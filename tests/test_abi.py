@@ -115,3 +115,11 @@ def test_adjoint_workspace_query_runs_on_host():
     state = (1 << 10) * 8
     assert full >= one + 2 * (ts.n_traj - 1) * state
     assert one >= 2 * state
+
+
+def test_workspace_query_needs_no_outputs():
+    circ = hea_circuit(6, 2, np.random.default_rng(0), 0.02)
+    plan = P.ptsbe_plan(circ)
+    ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=5, total_shots=5, seed=1, cfg=5)
+    for mode in ("shots", "states", "expectation"):
+        assert P.ptsbe_workspace_size(plan, ts, mode, params=circ["params"]) > 5 * (1 << 6) * 8

@@ -122,3 +122,42 @@ def test_brick_compiled_vs_generic_and_tags(n):
     counts = np.bincount(traj, minlength=ts.n_traj)
     assert np.array_equal(counts, g["m"].astype(np.int64))
     assert np.all(np.diff(traj) >= 0)
+
+
+def test_surface_code_billion_shots():
+    """The d=3 surface-code workload at full size: top-4096 most-likely records
+    sharing 10^9 shots.  Every shot's tag and count, the support of sampled
+    trajectories (noiseless support XOR the trajectory's Pauli frame), and exact
+    shots of a small trajectory against the oracle."""
+    from gpu_helpers import compare_shots, oracle_states
+    from oracle.stabilizer import frame_run
+    from workloads import c3_workload
+    wl = c3_workload()
+    circ = wl["circuit"]
+    plan = P.ptsbe_plan(circ)
+    ts = P.ptsbe_sample_kraus(plan, "most_likely", k_max=4096, total_shots=10**9, seed=0, cfg=3)
+    g = ts.get()
+    m = g["m"].astype(np.int64)
+    assert int(m.sum()) == 10**9
+    r = P.ptsbe_run_batch(plan, ts, seed=0, cfg=3)
+    P.ptsbe_run_status(plan, r["workspace"])
+    torch.cuda.synchronize()
+    bits, traj = r["bits"], r["traj"]
+    counts = torch.bincount(traj.long(), minlength=ts.n_traj).cpu().numpy()
+    assert np.array_equal(counts, m)
+    assert bool((traj[1:] >= traj[:-1]).all())
+    log(f"[C3 1e9] trajectories={ts.n_traj} largest m={m.max()}")
+    psi0, _ = oracle_states(circ, [()])
+    support0 = np.flatnonzero(np.abs(psi0[0]) ** 2 > 1e-12)
+    off = np.concatenate([[0], np.cumsum(m)])
+    for a in (0, 1, 100, 2000, 4095):
+        _, xf = frame_run(circ, g["records"][a])
+        allowed = set(int(s) ^ int(xf) for s in support0)
+        seen = set(torch.unique(bits[off[a]:off[a + 1]]).cpu().numpy().tolist())
+        assert seen <= allowed, f"trajectory {a}"
+    small = int(np.argmin(np.where(m > 1000, m, np.iinfo(np.int64).max)))
+    ref, _ = oracle_states(circ, [g["records"][small]])
+    seg = bits[off[small]:off[small + 1]].cpu().numpy()
+    bad, exc = compare_shots(ref[0], seg, int(m[small]), 0, 3, small)
+    log(f"  trajectory {small}: {m[small]} shots, {bad} mismatches, {exc} excused")
+    assert bad == 0
