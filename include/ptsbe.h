@@ -128,13 +128,18 @@ typedef struct {
     uint32_t precision;         /* PTSBE_C64 (FP32 state) or PTSBE_C128 (FP64 state) */
     uint32_t tile_qubits;       /* 0 = automatic; else qubits per LDS tile (4..13) */
     uint32_t flags;             /* bits 0..2: fewest 2x2 matrices per register group worth a
-                                   partial group (0 = 3); PTSBE_PLAN_NO_COMPILE */
+                                   partial group (0 = 3); PTSBE_PLAN_NO_COMPILE,
+                                   PTSBE_PLAN_HALF_TILE_LDS */
     uint32_t reserved;
 } ptsbe_plan_opts;
 
 /* Run every pass through the generic (interpreting) tile kernels instead of
  * the per-pass kernels the plan compiles for itself (see ptsbe_plan_compile). */
 #define PTSBE_PLAN_NO_COMPILE 8u
+/* Compiled passes move amplitudes between register sets through half a tile
+ * of LDS in two rounds (more resident workgroups per CU, two more barriers
+ * per register change). */
+#define PTSBE_PLAN_HALF_TILE_LDS 16u
 
 typedef struct ptsbe_plan_s* ptsbe_plan_t;
 typedef struct ptsbe_trajset_s* ptsbe_trajset_t;

@@ -24,6 +24,7 @@ ALLOCS = {"multiplicity": 0, "reweight": 1, "uniform": 2}
 RUN_SHOTS, RUN_STATES, RUN_EXPECTATION, RUN_ADJOINT = range(4)
 RUN_NO_PREFIX_SHARING = 1
 PLAN_NO_COMPILE = 8
+PLAN_HALF_TILE_LDS = 16
 
 
 class Op(C.Structure):

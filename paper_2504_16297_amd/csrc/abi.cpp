@@ -77,7 +77,7 @@ ptsbe_status ptsbe_plan_pass_source(ptsbe_plan_t plan, uint32_t pass, char* out,
     if (!plan || !len) return fail(PTSBE_E_ARG, "null argument");
     const Plan& P = *plan->plan;
     if (pass >= P.passes.size()) return fail(PTSBE_E_ARG, "pass index out of range");
-    const std::string src = jit_pass_source(P.passes[pass], P.n, P.precision, "ptsbe_pass");
+    const std::string src = jit_pass_source(P.passes[pass], P.n, P.precision, "ptsbe_pass", P.half_tile_lds, nullptr);
     if (out) {
       if (*len < src.size() + 1) return fail(PTSBE_E_ARG, "output buffer too small");
       std::memcpy(out, src.c_str(), src.size() + 1);

@@ -121,6 +121,7 @@ struct Plan {
   Program adj;
   // per-pass compiled kernels (built on first use unless disabled)
   bool use_jit = true;
+  bool half_tile_lds = false;  // compiled passes change registers through half a tile of LDS
   std::shared_ptr<JitProgram> jit;
 };
 

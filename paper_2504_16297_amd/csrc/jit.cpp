@@ -43,6 +43,8 @@ struct Gen {
   bool pending = false;      // `cs` holds a block-uniform scalar not yet applied
   bool cs_neg = false;       // the pending scalar must also be negated
   bool tile_read = false;    // the LDS tile was read since the last barrier
+  bool split = false;        // register changes go through half a tile of LDS, in two rounds
+  bool needs_full = false;   // an operation needs the whole tile in LDS
   // accumulated +-1 diagonal: amplitude r is negated where bit r of
   // XOR over monomials m of (value of m) * mask[m] is set
   std::map<Mono, uint32_t> signs;
@@ -302,6 +304,7 @@ struct Gen {
       return;
     }
     // through the LDS tile: any two local bits
+    needs_full = true;
     barrier_before_tile_write();
     o << "    const uint32_t Lt = " << lt_expr() << ", Lw = Lt ^ ((Lt >> 4) & 15u);\n";
     for (int r = 0; r < 16; ++r) o << "    tile[Lw ^ " << swz(reg_const(r)) << "u] = " << S(r) << ";\n";
@@ -346,15 +349,95 @@ struct Gen {
       if (live) fail("signs pending across a register change");
     }
     barrier_before_tile_write();
+    int nr[4] = {op.a, op.b, op.ga, op.gb};
+    if (split) {
+      phase_split(nr);
+      return;
+    }
     o << "  {\n    const uint32_t Lt = " << lt_expr() << ", Lw = Lt ^ ((Lt >> 4) & 15u);\n";
     for (int r = 0; r < 16; ++r) o << "    tile[Lw ^ " << swz(reg_const(r)) << "u] = " << S(r) << ";\n";
     o << "  }\n  __syncthreads();\n";
-    int nr[4] = {op.a, op.b, op.ga, op.gb};
     for (int j = 0; j < 4; ++j) R[j] = nr[j];
     for (int j = 0; j < 3; ++j)
       if (!(R[j] < R[j + 1]) || R[3] >= k) fail("register bits not ascending");
     o << "  {\n    const uint32_t Lt = " << lt_expr() << ", Lw = Lt ^ ((Lt >> 4) & 15u);\n";
     for (int r = 0; r < 16; ++r) o << "    " << S(r) << " = tile[Lw ^ " << swz(reg_const(r)) << "u];\n";
+    o << "  }\n";
+    tile_read = true;
+  }
+
+  // local index with bit p removed
+  static uint32_t compress(uint32_t L, int p) { return ((L >> (p + 1)) << p) | (L & ((1u << p) - 1u)); }
+  std::string compress_expr(const std::string& L, int p) const {
+    return "(((" + L + ") >> " + std::to_string(p + 1) + ") << " + std::to_string(p) + ") | ((" + L + ") & " +
+           std::to_string((1u << p) - 1u) + "u)";
+  }
+  // One side (write: old layout, read: new layout) of a half-tile round h:
+  // the amplitudes whose local bit p equals h move through tile[0 .. 2^(k-1)).
+  // Reads of amplitude r go to u<r> instead of s<r> where defer[r] is set.
+  void half_side(bool write, int p, int h, const bool* defer) {
+    const int j = reg_pos(p);
+    const std::string lt = lt_expr();
+    o << "  {\n    const uint32_t Lt = " << lt << ";\n    const uint32_t Lc = " << compress_expr("Lt", p)
+      << ", Lw = Lc ^ ((Lc >> 4) & 15u);\n";
+    std::string indent = "    ";
+    if (j < 0) {  // p is a thread bit: this thread moves all or none of its amplitudes
+      o << "    if (((tid >> " << thread_bit(p) << ") & 1u) == " << h << "u) {\n";
+      indent = "      ";
+    }
+    for (int r = 0; r < 16; ++r) {
+      if (j >= 0 && ((r >> j) & 1) != h) continue;
+      const uint32_t c = swz(compress(reg_const(r), p));
+      if (write) o << indent << "tile[Lw ^ " << c << "u] = " << S(r) << ";\n";
+      else o << indent << (defer && defer[r] ? "u" + std::to_string(r) : S(r)) << " = tile[Lw ^ " << c << "u];\n";
+    }
+    if (j < 0) o << "    }\n";
+    o << "  }\n";
+  }
+  void phase_split(const int* nr) {
+    int newR[4] = {nr[0], nr[1], nr[2], nr[3]};
+    for (int j = 0; j < 3; ++j)
+      if (!(newR[j] < newR[j + 1]) || newR[3] >= k) fail("register bits not ascending");
+    // partition bit: a register bit in both layouts if any, else one in either
+    int p = -1;
+    for (int j = 0; j < 4 && p < 0; ++j)
+      for (int i = 0; i < 4; ++i)
+        if (R[j] == newR[i]) p = R[j];
+    if (p < 0) p = R[3];
+    int oldR[4] = {R[0], R[1], R[2], R[3]};
+    const int jo = reg_pos(p);
+    for (int j = 0; j < 4; ++j) R[j] = newR[j];
+    const int jn = reg_pos(p);
+    // a round-0 read must not overwrite a register that round 1 still writes
+    bool defer[16];
+    bool any = false;
+    for (int r = 0; r < 16; ++r) {
+      const bool read0 = jn < 0 || ((r >> jn) & 1) == 0;
+      const bool write1 = jo < 0 || ((r >> jo) & 1) == 1;
+      defer[r] = read0 && write1;
+      any |= defer[r];
+    }
+    o << "  {\n";
+    for (int r = 0; r < 16; ++r)
+      if (defer[r]) o << "  V u" << r << ";\n";
+    for (int h = 0; h < 2; ++h) {
+      if (h) o << "  __syncthreads();\n";
+      for (int j = 0; j < 4; ++j) R[j] = oldR[j];
+      half_side(true, p, h, nullptr);
+      o << "  __syncthreads();\n";
+      for (int j = 0; j < 4; ++j) R[j] = newR[j];
+      half_side(false, p, h, h == 0 ? defer : nullptr);
+    }
+    if (any) {
+      std::string indent = "  ";
+      if (jn < 0) {  // only the threads that read in round 0 hold deferred values
+        o << "  if (((tid >> " << thread_bit(p) << ") & 1u) == 0u) {\n";
+        indent = "    ";
+      }
+      for (int r = 0; r < 16; ++r)
+        if (defer[r]) o << indent << S(r) << " = u" << r << ";\n";
+      if (jn < 0) o << "  }\n";
+    }
     o << "  }\n";
     tile_read = true;
   }
@@ -402,10 +485,13 @@ std::string bit_gather(const char* src, const std::vector<int>& dst_pos, int fir
 
 }  // namespace
 
-std::string jit_pass_source(const Pass& ps, int n, int precision, const std::string& name) {
+namespace {
+
+std::string gen_pass(const Pass& ps, int n, int precision, const std::string& name, bool split, bool* needs_full) {
   const int k = ps.k;
   if (k < (int)kMinRegTile || k > 12) return "";
   Gen g;
+  g.split = split;
   g.k = k;
   g.n = n;
   g.c64 = precision == PTSBE_C64;
@@ -421,7 +507,7 @@ std::string jit_pass_source(const Pass& ps, int n, int precision, const std::str
   o << "extern \"C\" __global__ __launch_bounds__(256) void " << name << "(PassArgs a) {\n"
     << "  extern __shared__ __align__(16) unsigned char smem[];\n"
     << "  V* tile = reinterpret_cast<V*>(smem);\n"
-    << "  V* mats = tile + " << (1 << k) << ";\n"
+    << "  V* mats = tile + " << (split ? (1 << (k - 1)) : (1 << k)) << ";\n"
     << "  uint32_t* slot_off = reinterpret_cast<uint32_t*>(mats + " << 4 * n_slots << ");\n"
     << "  const uint32_t tid = threadIdx.x;\n"
     << "  uint32_t src = blockIdx.y, dst = blockIdx.y;\n"
@@ -492,7 +578,22 @@ std::string jit_pass_source(const Pass& ps, int n, int precision, const std::str
   o << "  V* dstp = a.states + (uint64_t)dst * a.N + base + ot;\n";
   for (int r = 0; r < 16; ++r) o << "  dstp[" << og[r] << "ull] = " << g.S(r) << ";\n";
   o << "}\n";
+  *needs_full = g.needs_full;
   return o.str();
+}
+
+}  // namespace
+
+std::string jit_pass_source(const Pass& ps, int n, int precision, const std::string& name, bool split,
+                            uint32_t* tile_elems) {
+  bool full = false;
+  std::string src = gen_pass(ps, n, precision, name, split, &full);
+  if (split && full) {  // a 4x4 matrix off the register bits needs the whole tile
+    split = false;
+    src = gen_pass(ps, n, precision, name, false, &full);
+  }
+  if (tile_elems) *tile_elems = src.empty() ? 0u : (1u << (ps.k - (split ? 1 : 0)));
+  return src;
 }
 
 namespace {
@@ -533,7 +634,8 @@ ptsbe_status jit_build(const Plan& P) {
   J.pass_kernel.assign(P.passes.size(), -1);
   std::map<std::string, int> by_body;
   for (size_t p = 0; p < P.passes.size(); ++p) {
-    const std::string body = jit_pass_source(P.passes[p], P.n, P.precision, "KERNEL_NAME");
+    uint32_t te = 0;
+    const std::string body = jit_pass_source(P.passes[p], P.n, P.precision, "KERNEL_NAME", P.half_tile_lds, &te);
     if (body.empty()) continue;
     auto it = by_body.find(body);
     if (it != by_body.end()) {
@@ -548,6 +650,7 @@ ptsbe_status jit_build(const Plan& P) {
     J.pass_kernel[p] = id;
     J.names.push_back(name);
     J.sources.push_back(src);
+    J.tile_elems.push_back(te);
   }
   const size_t K = J.names.size();
   if (const char* dir = std::getenv("PTSBE_PASS_SOURCE_DIR")) {  // inspection: keep the generated sources
@@ -629,7 +732,8 @@ hipError_t jit_launch(const Plan& P, uint32_t pass, const PassArgs<V>& a, uint32
   hipFunction_t f = (*fns)[P.jit->pass_kernel[pass]];
   const Pass& ps = P.passes[pass];
   const uint32_t k = (uint32_t)ps.k, n_slots = (uint32_t)ps.slots.size();
-  const size_t lds = sizeof(V) * ((size_t(1) << k) + 4 * (size_t)n_slots) + 4 * (size_t)n_slots;
+  const size_t te = P.jit->tile_elems[P.jit->pass_kernel[pass]];
+  const size_t lds = sizeof(V) * (te + 4 * (size_t)n_slots) + 4 * (size_t)n_slots;
   if (lds > 65536) return hipErrorInvalidConfiguration;
   PassArgs<V> la = a;
   uint32_t slot_begin = 0;

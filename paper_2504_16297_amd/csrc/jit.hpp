@@ -29,6 +29,7 @@ struct JitProgram {
   std::vector<int> pass_kernel;            // pass -> compiled kernel index, -1 = interpreter kernel
   std::vector<std::string> names;          // kernel index -> symbol
   std::vector<std::string> sources;        // kernel index -> HIP source
+  std::vector<uint32_t> tile_elems;        // kernel index -> amplitudes of LDS tile space
   std::vector<std::vector<char>> code;     // kernel index -> code object
   double compile_seconds = 0.0;
   // per device: loaded modules and kernel handles
@@ -38,7 +39,12 @@ struct JitProgram {
 
 // HIP source of a register-layout pass kernel named `name`, or "" if the pass
 // is outside what the compiler handles (then the interpreter kernel runs it).
-std::string jit_pass_source(const Pass& ps, int n, int precision, const std::string& name);
+// `split`: register changes move through half a tile of LDS in two rounds
+// (less LDS per workgroup, more resident workgroups), unless a 4x4 matrix off
+// the register bits needs the whole tile.  *tile_elems receives the LDS tile
+// size in amplitudes.
+std::string jit_pass_source(const Pass& ps, int n, int precision, const std::string& name, bool split,
+                            uint32_t* tile_elems);
 
 // Generate and compile every pass kernel of the plan (host only, no device
 // needed).  Idempotent; thread-safe.

@@ -18,11 +18,12 @@ CASES = [(6, 30, "c128", 0, 1), (8, 60, "c64", 0, 2), (10, 80, "c64", 0, 1070), 
          (12, 70, "c64", 8, 9), (13, 60, "c128", 9, 13)]
 
 
+@pytest.mark.parametrize("half", [False, True])
 @pytest.mark.parametrize("n,gates,prec,tile,seed", CASES)
-def test_random_circuits(n, gates, prec, tile, seed):
+def test_random_circuits(n, gates, prec, tile, seed, half):
     circ = random_small_circuit(n, gates, np.random.default_rng(seed), p1=0.2, p2=0.3, with_params=True)
     params = np.asarray(circ["params"])
-    plan = P.ptsbe_plan(circ, precision=prec, tile_qubits=tile)
+    plan = P.ptsbe_plan(circ, precision=prec, tile_qubits=tile, half_tile=half)
     ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=3, total_shots=3, seed=3, cfg=1)
     st = run_compiled(plan, ts, params)
     ref, _ = oracle_states(circ, ts.get()["records"], params=params)
@@ -30,9 +31,10 @@ def test_random_circuits(n, gates, prec, tile, seed):
     assert max(float(np.max(np.abs(st[a] - ref[a]))) for a in range(len(ref))) <= tol
 
 
-def test_c1_slice():
+@pytest.mark.parametrize("half", [False, True])
+def test_c1_slice(half):
     wl = c1_workload()
-    plan = P.ptsbe_plan(wl["circuit"], precision="c128")
+    plan = P.ptsbe_plan(wl["circuit"], precision="c128", half_tile=half)
     ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=64, total_shots=64000, seed=0, cfg=1).slice(0, 4)
     st = run_compiled(plan, ts)
     ref, _ = oracle_states(wl["circuit"], ts.get()["records"])
@@ -55,4 +57,19 @@ def test_hea_with_parameters():
     ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=4, total_shots=4, seed=1, cfg=5)
     st = run_compiled(plan, ts, params)
     ref, _ = oracle_states(circ, ts.get()["records"], params=params)
+    assert max(float(np.max(np.abs(st[a] - ref[a]))) for a in range(len(ref))) <= 1e-5
+
+
+def test_brick_half_tile_transposes():
+    """A 14-qubit brick circuit with coherent over-rotations on 4096-amplitude
+    tiles, register changes through half the tile: every pass is split."""
+    from compiled_cpu import pass_source
+    from workloads import brick_circuit
+    circ = brick_circuit(14, 6, np.random.default_rng(3), 0.05, 0.08, eps_sigma=0.05)
+    plan = P.ptsbe_plan(circ, half_tile=True)
+    srcs = [pass_source(plan, p) for p in range(plan.info["n_passes"])]
+    assert all("tile + 2048;" in s for s in srcs if s)
+    ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=3, total_shots=3, seed=5, cfg=2)
+    st = run_compiled(plan, ts)
+    ref, _ = oracle_states(circ, ts.get()["records"])
     assert max(float(np.max(np.abs(st[a] - ref[a]))) for a in range(len(ref))) <= 1e-5

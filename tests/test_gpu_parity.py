@@ -317,3 +317,18 @@ def test_graph_replays_match_eager(wl_name):
         assert np.array_equal(cap["traj"].cpu().numpy(), et), rep
         x = torch.randn(1 << 16, device="cuda")       # unrelated eager work between replays
         float((x * x).sum())
+
+
+@pytest.mark.parametrize("n,prec", [(14, "c64"), (13, "c128")])
+def test_half_tile_register_changes(n, prec):
+    """Compiled passes that change register sets through half a tile of LDS."""
+    from workloads import brick_circuit
+    log(f"[half tile] n={n} {prec}")
+    circ = brick_circuit(n, 8, np.random.default_rng(60 + n), 0.03, 0.05, eps_sigma=0.05)
+    plan = P.ptsbe_plan(circ, precision=prec, half_tile=True)
+    ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=16, total_shots=16, seed=4, cfg=2)
+    gpu = _states(plan, ts)
+    ref, _ = oracle_states(circ, ts.get()["records"])
+    err = max(float(np.max(np.abs(gpu[a] - ref[a]))) for a in range(len(ref)))
+    log(f"  max|d| = {err:.2e}")
+    assert err <= (1e-5 if prec == "c64" else 1e-12)
