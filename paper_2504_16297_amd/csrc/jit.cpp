@@ -514,8 +514,6 @@ std::string gen_pass(const Pass& ps, int n, int precision, const std::string& na
     << "  if (a.route) { const uint2 e = a.route[blockIdx.y]; src = e.x; dst = e.y; }\n"
     << "  const bool carrier = a.route != nullptr && dst >= a.carrier0;\n"
     << "  const uint32_t t = a.t0 + dst;\n"
-    << "  const uint64_t tile_id = blockIdx.x;\n"
-    << "  const uint64_t base = " << bit_gather("tile_id", g.oq, 0) << ";\n"
     << "  for (uint32_t i = tid; i < " << n_slots << "u; i += blockDim.x) slot_off[i] = a.slot_default[i];\n"
     << "  __syncthreads();\n"
     << "  if (!carrier) {\n"
@@ -525,11 +523,15 @@ std::string gen_pass(const Pass& ps, int n, int precision, const std::string& na
     << "  }\n"
     << "  __syncthreads();\n"
     << "  for (uint32_t i = tid; i < " << 4 * n_slots << "u; i += blockDim.x) mats[i] = a.pool[slot_off[i >> 2] + (i & 3u)];\n"
-    << "  __syncthreads();\n"
-    << "  V cs; cs.x = 1; cs.y = 0;\n";
+    << "  __syncthreads();\n";
   // global offsets: thread part from tid, register parts constant
   std::vector<int> tpos(g.tq.begin(), g.tq.begin() + (k - 4));
   o << "  const uint64_t ot = " << bit_gather("tid", tpos, 0) << ";\n";
+  // the block's tiles of this state: grid-stride over the 2^(n-k) tiles, so a
+  // block reuses its slot table and matrices for several tiles
+  o << "  for (uint64_t tile_id = blockIdx.x; tile_id < " << (1ull << (n - k)) << "ull; tile_id += gridDim.x) {\n"
+    << "  const uint64_t base = " << bit_gather("tile_id", g.oq, 0) << ";\n"
+    << "  V cs; cs.x = 1; cs.y = 0;\n";
   uint64_t og[16];
   for (int r = 0; r < 16; ++r) {
     og[r] = 0;
@@ -577,7 +579,8 @@ std::string gen_pass(const Pass& ps, int n, int precision, const std::string& na
   }
   o << "  V* dstp = a.states + (uint64_t)dst * a.N + base + ot;\n";
   for (int r = 0; r < 16; ++r) o << "  dstp[" << og[r] << "ull] = " << g.S(r) << ";\n";
-  o << "}\n";
+  if (g.tile_read) o << "  __syncthreads();  // the next tile's first register change reuses the LDS tile\n";
+  o << "  }\n}\n";
   *needs_full = g.needs_full;
   return o.str();
 }
@@ -668,8 +671,25 @@ ptsbe_status jit_build(const Plan& P) {
   std::atomic<size_t> next{0};
   const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
   std::vector<std::thread> pool;
+  // code objects are shared between plans with identical pass sources (process-wide cache)
+  static std::mutex cache_mu;
+  static std::map<std::string, std::vector<char>> cache;
   auto work = [&]() {
-    for (size_t i = next++; i < K; i = next++) st[i] = compile_one(J.sources[i], J.names[i], J.code[i], err[i]);
+    for (size_t i = next++; i < K; i = next++) {
+      {
+        std::lock_guard<std::mutex> lk(cache_mu);
+        auto it = cache.find(J.sources[i]);
+        if (it != cache.end()) {
+          J.code[i] = it->second;
+          continue;
+        }
+      }
+      st[i] = compile_one(J.sources[i], J.names[i], J.code[i], err[i]);
+      if (st[i] == PTSBE_OK) {
+        std::lock_guard<std::mutex> lk(cache_mu);
+        cache.emplace(J.sources[i], J.code[i]);
+      }
+    }
   };
   for (unsigned w = 0; w < std::min<size_t>(hw, K); ++w) pool.emplace_back(work);
   for (auto& th : pool) th.join();
@@ -740,8 +760,9 @@ hipError_t jit_launch(const Plan& P, uint32_t pass, const PassArgs<V>& a, uint32
   for (uint32_t p = 0; p < pass; ++p) slot_begin += (uint32_t)P.passes[p].slots.size();
   la.slot_default = a.slot_default + slot_begin;
   void* args[] = {&la};
-  return hipModuleLaunchKernel(f, 1u << (P.n - k), rows, 1, 1u << (k - kRegBits), 1, 1, (unsigned)lds, s, args,
-                               nullptr);
+  const uint32_t n_tiles = 1u << (P.n - k);
+  const uint32_t gx = std::max<uint32_t>(1u, n_tiles / std::min<uint32_t>(n_tiles, P.tiles_per_block));
+  return hipModuleLaunchKernel(f, gx, rows, 1, 1u << (k - kRegBits), 1, 1, (unsigned)lds, s, args, nullptr);
 }
 
 template hipError_t jit_launch<float2>(const Plan&, uint32_t, const PassArgs<float2>&, uint32_t, hipStream_t);

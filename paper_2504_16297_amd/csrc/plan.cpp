@@ -711,6 +711,7 @@ ptsbe_status build_plan(const ptsbe_circuit* c, const ptsbe_noise_model* nm, con
   if (o && (o->flags & 7u)) P.min_fill = (int)(o->flags & 7u);
   P.use_jit = !(o && (o->flags & PTSBE_PLAN_NO_COMPILE));
   P.half_tile_lds = o && (o->flags & PTSBE_PLAN_HALF_TILE_LDS);
+  P.tiles_per_block = 1u << (o ? ((o->flags >> PTSBE_PLAN_TILES_PER_BLOCK_SHIFT) & 3u) : 0u);
   P.jit = std::make_shared<JitProgram>();
   // channels
   uint32_t n_ch = nm ? nm->n_channels : 0;

@@ -18,14 +18,16 @@ CASES = [(6, 30, "c128", 0, 1), (8, 60, "c64", 0, 2), (10, 80, "c64", 0, 1070), 
          (12, 70, "c64", 8, 9), (13, 60, "c128", 9, 13)]
 
 
-@pytest.mark.parametrize("half", [False, True])
-@pytest.mark.parametrize("n,gates,prec,tile,seed", CASES)
+RUNS = [c + (False,) for c in CASES] + [CASES[i] + (True,) for i in (1, 3, 4)]
+
+
+@pytest.mark.parametrize("n,gates,prec,tile,seed,half", RUNS)
 def test_random_circuits(n, gates, prec, tile, seed, half):
     circ = random_small_circuit(n, gates, np.random.default_rng(seed), p1=0.2, p2=0.3, with_params=True)
     params = np.asarray(circ["params"])
     plan = P.ptsbe_plan(circ, precision=prec, tile_qubits=tile, half_tile=half)
     ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=3, total_shots=3, seed=3, cfg=1)
-    st = run_compiled(plan, ts, params)
+    st = run_compiled(plan, ts, params, tiles_per_block=4 if half else 1)
     ref, _ = oracle_states(circ, ts.get()["records"], params=params)
     tol = 1e-5 if prec == "c64" else 1e-12
     assert max(float(np.max(np.abs(st[a] - ref[a]))) for a in range(len(ref))) <= tol
@@ -66,10 +68,10 @@ def test_brick_half_tile_transposes():
     from compiled_cpu import pass_source
     from workloads import brick_circuit
     circ = brick_circuit(14, 6, np.random.default_rng(3), 0.05, 0.08, eps_sigma=0.05)
-    plan = P.ptsbe_plan(circ, half_tile=True)
+    plan = P.ptsbe_plan(circ, half_tile=True, tiles_per_block=2)
     srcs = [pass_source(plan, p) for p in range(plan.info["n_passes"])]
     assert all("tile + 2048;" in s for s in srcs if s)
     ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=3, total_shots=3, seed=5, cfg=2)
-    st = run_compiled(plan, ts)
+    st = run_compiled(plan, ts, tiles_per_block=2)
     ref, _ = oracle_states(circ, ts.get()["records"])
     assert max(float(np.max(np.abs(st[a] - ref[a]))) for a in range(len(ref))) <= 1e-5
