@@ -85,9 +85,9 @@ def main():
     ap.add_argument("--baseline-shots", type=int, default=512)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 2 GiB device copy (calibrates FETCH_SIZE / WRITE_SIZE counters)")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c4"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c4", "c5"],
                     help="c2: the 20-qubit headline workload; c4: the 24/26/28-qubit mixed batch and the "
-                         "33-qubit trajectory")
+                         "33-qubit trajectory; c5: the adjoint gradient of the 16-qubit ansatz")
     args = ap.parse_args()
     if args.copy_probe:
         import torch
@@ -107,6 +107,8 @@ def main():
 
     if args.workload == "c4":
         return bench_c4(args)
+    if args.workload == "c5":
+        return bench_c5(args)
 
     import numpy as np
     import torch
@@ -321,6 +323,61 @@ def bench_c4(args):
                      "pass_hbm_gbs": tm[6] / (tm[0] * 1e-3) / 1e9}
     log(f"[bench c4] 33 qubits: {d33:.2f} s for 1e6 shots ({plan.info['n_passes']} passes, "
         f"{tm[6] / (tm[0] * 1e-3) / 1e9:.0f} GB/s in the passes)")
+    print(json.dumps(result))
+
+
+def bench_c5(args):
+    """Adjoint gradient of sum_i Z_i Z_(i+1) over the 16-qubit, 8-layer ansatz
+    (256 parameters) with 1024 proportional draws: one step = E and all 256
+    derivatives (forward preparation, lambda = O psi, reverse sweep, FP64
+    reductions) for every trajectory; against that, the parameter-shift rule on
+    the same GPU (2 expectation runs per parameter, timed on 8 parameters)."""
+    import numpy as np
+    import torch
+
+    import paper_2504_16297_amd as P
+    from workloads import c5_workload
+
+    torch.cuda.set_device(0)
+    wl = c5_workload()
+    circ, obs = wl["circuit"], wl["observable"]
+    params = np.asarray(circ["params"])
+    pts = wl["pts"]
+    plan = P.ptsbe_plan(circ, precision=wl["precision"])
+    ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=pts["n_draws"], total_shots=pts["total_shots"],
+                              seed=wl["seed"], cfg=wl["cfg"])
+    P.ptsbe_plan_compile(plan)
+    ws = torch.empty(P.ptsbe_workspace_size(plan, ts, "adjoint", params=params), dtype=torch.uint8, device="cuda")
+    for _ in range(args.warmup):
+        P.ptsbe_adjoint_grad(plan, ts, params, obs, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        E, G = P.ptsbe_adjoint_grad(plan, ts, params, obs, workspace=ws)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    ews = torch.empty(P.ptsbe_workspace_size(plan, ts, "expectation", params=params), dtype=torch.uint8,
+                      device="cuda")
+    out = {"expval": torch.empty(ts.n_traj, dtype=torch.float64, device="cuda")}
+    P.ptsbe_run_batch(plan, ts, mode="expectation", params=params, observable=obs, workspace=ews, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(8):
+        for sgn in (1.0, -1.0):
+            pv = params.copy()
+            pv[i] += sgn * np.pi / 2
+            P.ptsbe_run_batch(plan, ts, mode="expectation", params=pv, observable=obs, workspace=ews, out=out)
+    torch.cuda.synchronize()
+    shift = (time.perf_counter() - t0) / 8 * params.size
+    result = {"metric": "adjoint gradient evaluations/s (E and all derivatives over the trajectory set)",
+              "value": 1.0 / dt, "unit": "gradients/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+              "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+              "dtype": "c64 (fp32 state, fp64 dots)", "data": "synthetic",
+              "config": {"workload": wl["name"], "parameters": int(params.size), "trajectories": ts.n_traj},
+              "E": float(E.cpu()[0]), "parameter_shift_seconds_estimate": shift,
+              "speedup_vs_parameter_shift": shift / dt}
+    log(f"[bench c5] {dt * 1e3:.1f} ms per gradient ({ts.n_traj} trajectories, {params.size} parameters); "
+        f"parameter shift would take {shift:.2f} s")
     print(json.dumps(result))
 
 

@@ -128,7 +128,7 @@ typedef struct {
     uint32_t precision;         /* PTSBE_C64 (FP32 state) or PTSBE_C128 (FP64 state) */
     uint32_t tile_qubits;       /* 0 = automatic; else qubits per LDS tile (4..13) */
     uint32_t flags;             /* bits 0..2: fewest 2x2 matrices per register group worth a
-                                   partial group (0 = 3); PTSBE_PLAN_NO_COMPILE,
+                                   partial group (0 = 2); PTSBE_PLAN_NO_COMPILE,
                                    PTSBE_PLAN_HALF_TILE_LDS; bits 5..6: tiles per
                                    workgroup (PTSBE_PLAN_TILES_PER_BLOCK_SHIFT) */
     uint32_t reserved;

@@ -109,7 +109,7 @@ def ptsbe_plan(circuit, precision="c64", tile_qubits=0, compile=True, min_fill=0
                tiles_per_block=1):
     """Build the execution plan of a circuit dictionary (ops, channels, rules).
     ``compile=False`` runs the passes through the generic tile kernels instead of
-    per-pass compiled kernels; ``min_fill`` (1..7, 0 = 3) is the fewest 2x2
+    per-pass compiled kernels; ``min_fill`` (1..7, 0 = 2) is the fewest 2x2
     matrices a partial register group must hold; ``half_tile`` moves amplitudes
     between register sets through half a tile of LDS; ``tiles_per_block`` (1, 2,
     4, 8) tiles of a state per workgroup of a compiled pass."""

@@ -104,7 +104,7 @@ struct Plan {
   int n = 0;
   int precision = PTSBE_C64;
   int tile_bits = 12;
-  int min_fill = 3;            // phase scheduler: fewest 2x2 matrices worth a partial wave
+  int min_fill = 2;            // phase scheduler: fewest 2x2 matrices worth a partial wave
   int n_params = 0;
   int n_measure = 0;
   std::vector<Channel> channels;

@@ -707,7 +707,7 @@ ptsbe_status build_plan(const ptsbe_circuit* c, const ptsbe_noise_model* nm, con
     if (P.precision == PTSBE_C128 && tb > 12) return fail(PTSBE_E_ARG, "tile_qubits <= 12 for complex128");
   }
   P.tile_bits = tb;
-  // flags bits 0..2: phase-scheduler fill threshold (0 = default 3)
+  // flags bits 0..2: phase-scheduler fill threshold (0 = default 2)
   if (o && (o->flags & 7u)) P.min_fill = (int)(o->flags & 7u);
   P.use_jit = !(o && (o->flags & PTSBE_PLAN_NO_COMPILE));
   P.half_tile_lds = o && (o->flags & PTSBE_PLAN_HALF_TILE_LDS);
