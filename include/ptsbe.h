@@ -129,8 +129,7 @@ typedef struct {
     uint32_t tile_qubits;       /* 0 = automatic; else qubits per LDS tile (4..13) */
     uint32_t flags;             /* bits 0..2: fewest 2x2 matrices per register group worth a
                                    partial group (0 = 2); PTSBE_PLAN_NO_COMPILE,
-                                   PTSBE_PLAN_HALF_TILE_LDS; bits 5..6: tiles per
-                                   workgroup (PTSBE_PLAN_TILES_PER_BLOCK_SHIFT) */
+                                   PTSBE_PLAN_HALF_TILE_LDS */
     uint32_t reserved;
 } ptsbe_plan_opts;
 
@@ -141,10 +140,6 @@ typedef struct {
  * of LDS in two rounds (more resident workgroups per CU, two more barriers
  * per register change). */
 #define PTSBE_PLAN_HALF_TILE_LDS 16u
-/* Bits 5..6 of flags: log2 of the tiles of one state each workgroup of a
- * compiled pass handles (1, 2, 4 or 8; its slot table and matrices are set up
- * once for all of them). */
-#define PTSBE_PLAN_TILES_PER_BLOCK_SHIFT 5
 
 typedef struct ptsbe_plan_s* ptsbe_plan_t;
 typedef struct ptsbe_trajset_s* ptsbe_trajset_t;

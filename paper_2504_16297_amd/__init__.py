@@ -105,14 +105,12 @@ def ptsbe_plan_compile(plan):
     return nk.value, sec.value
 
 
-def ptsbe_plan(circuit, precision="c64", tile_qubits=0, compile=True, min_fill=0, half_tile=False,
-               tiles_per_block=1):
+def ptsbe_plan(circuit, precision="c64", tile_qubits=0, compile=True, min_fill=0, half_tile=False):
     """Build the execution plan of a circuit dictionary (ops, channels, rules).
     ``compile=False`` runs the passes through the generic tile kernels instead of
     per-pass compiled kernels; ``min_fill`` (1..7, 0 = 2) is the fewest 2x2
     matrices a partial register group must hold; ``half_tile`` moves amplitudes
-    between register sets through half a tile of LDS; ``tiles_per_block`` (1, 2,
-    4, 8) tiles of a state per workgroup of a compiled pass."""
+    between register sets through half a tile of LDS."""
     ops = circuit["ops"]
     arr = (L.Op * max(1, len(ops)))()
     keep = []
@@ -177,8 +175,7 @@ def ptsbe_plan(circuit, precision="c64", tile_qubits=0, compile=True, min_fill=0
         raise ValueError("min_fill must be in 0..7")
     po = L.PlanOpts({"c64": L.C64, "c128": L.C128}[precision], int(tile_qubits),
                     int(min_fill) | (0 if compile else L.PLAN_NO_COMPILE) |
-                    (L.PLAN_HALF_TILE_LDS if half_tile else 0) |
-                    ({1: 0, 2: 1, 4: 2, 8: 3}[int(tiles_per_block)] << 5), 0)
+                    (L.PLAN_HALF_TILE_LDS if half_tile else 0), 0)
     h = C.c_void_p()
     check(lib().ptsbe_plan(C.byref(c), C.byref(nm), C.byref(po), C.byref(h)))
     return Plan(h, None)

@@ -122,7 +122,6 @@ struct Plan {
   // per-pass compiled kernels (built on first use unless disabled)
   bool use_jit = true;
   bool half_tile_lds = false;  // compiled passes change registers through half a tile of LDS
-  uint32_t tiles_per_block = 1;  // compiled passes: tiles of one state handled by each workgroup
   std::shared_ptr<JitProgram> jit;
 };
 

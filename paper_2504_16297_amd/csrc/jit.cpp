@@ -527,9 +527,7 @@ std::string gen_pass(const Pass& ps, int n, int precision, const std::string& na
   // global offsets: thread part from tid, register parts constant
   std::vector<int> tpos(g.tq.begin(), g.tq.begin() + (k - 4));
   o << "  const uint64_t ot = " << bit_gather("tid", tpos, 0) << ";\n";
-  // the block's tiles of this state: grid-stride over the 2^(n-k) tiles, so a
-  // block reuses its slot table and matrices for several tiles
-  o << "  for (uint64_t tile_id = blockIdx.x; tile_id < " << (1ull << (n - k)) << "ull; tile_id += gridDim.x) {\n"
+  o << "  const uint64_t tile_id = blockIdx.x;\n"
     << "  const uint64_t base = " << bit_gather("tile_id", g.oq, 0) << ";\n"
     << "  V cs; cs.x = 1; cs.y = 0;\n";
   uint64_t og[16];
@@ -579,8 +577,7 @@ std::string gen_pass(const Pass& ps, int n, int precision, const std::string& na
   }
   o << "  V* dstp = a.states + (uint64_t)dst * a.N + base + ot;\n";
   for (int r = 0; r < 16; ++r) o << "  dstp[" << og[r] << "ull] = " << g.S(r) << ";\n";
-  if (g.tile_read) o << "  __syncthreads();  // the next tile's first register change reuses the LDS tile\n";
-  o << "  }\n}\n";
+  o << "}\n";
   *needs_full = g.needs_full;
   return o.str();
 }
@@ -760,9 +757,8 @@ hipError_t jit_launch(const Plan& P, uint32_t pass, const PassArgs<V>& a, uint32
   for (uint32_t p = 0; p < pass; ++p) slot_begin += (uint32_t)P.passes[p].slots.size();
   la.slot_default = a.slot_default + slot_begin;
   void* args[] = {&la};
-  const uint32_t n_tiles = 1u << (P.n - k);
-  const uint32_t gx = std::max<uint32_t>(1u, n_tiles / std::min<uint32_t>(n_tiles, P.tiles_per_block));
-  return hipModuleLaunchKernel(f, gx, rows, 1, 1u << (k - kRegBits), 1, 1, (unsigned)lds, s, args, nullptr);
+  return hipModuleLaunchKernel(f, 1u << (P.n - k), rows, 1, 1u << (k - kRegBits), 1, 1, (unsigned)lds, s, args,
+                               nullptr);
 }
 
 template hipError_t jit_launch<float2>(const Plan&, uint32_t, const PassArgs<float2>&, uint32_t, hipStream_t);

@@ -704,8 +704,33 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs<V> a) {
   }
   __syncthreads();
   const DOp* ops = pa.ops + P.op_begin;
+  // register-phase ops of a phased program act on the LDS tiles directly:
+  // PHASE only renames the 4 register bits, M1G is up to 4 2x2 matrices on them,
+  // signs are applied as they come (SFLIP has nothing left to do)
+  uint32_t R[4] = {k - 4, k - 3, k - 2, k - 1};
   for (uint32_t o = 0; o < P.n_ops; ++o) {
     const DOp op = ops[o];
+    if (op.type == DOP_PHASE) {
+      R[0] = op.a;
+      R[1] = op.b;
+      R[2] = op.ga;
+      R[3] = op.gb;
+      continue;
+    }
+    if (op.type == DOP_SFLIP) continue;
+    if (op.type == DOP_M1G) {
+      for (uint32_t j = 0; j < 4; ++j) {
+        if (!((op.mask >> j) & 1u)) continue;
+        DOp m1{};
+        m1.type = DOP_M1;
+        m1.a = (uint8_t)R[j];
+        const V* m = pa.pool + slot_off[op.slot[j]];
+        tile_apply(tp, m1, m, base, nt, tid, bd);
+        tile_apply(tl, m1, m, base, nt, tid, bd);
+        __syncthreads();
+      }
+      continue;
+    }
     if (op.type == DOP_DOT) {
       // Im<lambda|P_q|psi> restricted to this tile (pairs along local bit a)
       const uint32_t bit = 1u << op.a, lo = bit - 1;

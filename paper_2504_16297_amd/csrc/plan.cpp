@@ -372,6 +372,7 @@ static int op_qubits(const Pass& ps, const DOp& op, int* q) {
   switch (op.type) {
     case DOP_M1:
     case DOP_MR:
+    case DOP_DOT:
       q[0] = ps.tq[op.a];
       return 1;
     case DOP_M2:
@@ -441,7 +442,7 @@ static void schedule_phases(Pass& ps, int min_fill) {
   };
   // register bits an operation needs (4x4 matrices go through LDS and need none)
   auto local_bits = [&](const DOp& op, int* b) -> int {
-    if (op.type == DOP_M1 || op.type == DOP_MR) {
+    if (op.type == DOP_M1 || op.type == DOP_MR || op.type == DOP_DOT) {
       b[0] = op.a;
       return 1;
     }
@@ -711,7 +712,6 @@ ptsbe_status build_plan(const ptsbe_circuit* c, const ptsbe_noise_model* nm, con
   if (o && (o->flags & 7u)) P.min_fill = (int)(o->flags & 7u);
   P.use_jit = !(o && (o->flags & PTSBE_PLAN_NO_COMPILE));
   P.half_tile_lds = o && (o->flags & PTSBE_PLAN_HALF_TILE_LDS);
-  P.tiles_per_block = 1u << (o ? ((o->flags >> PTSBE_PLAN_TILES_PER_BLOCK_SHIFT) & 3u) : 0u);
   P.jit = std::make_shared<JitProgram>();
   // channels
   uint32_t n_ch = nm ? nm->n_channels : 0;
@@ -870,7 +870,7 @@ ptsbe_status build_plan(const ptsbe_circuit* c, const ptsbe_noise_model* nm, con
       A.steps.push_back(r);
     }
     // two tiles (psi and lambda) share the LDS: one tile bit less
-    st = schedule(P, A.steps, A.passes, A.exec, A.site_slots, false, false, std::max(4, P.tile_bits - 1));
+    st = schedule(P, A.steps, A.passes, A.exec, A.site_slots, false, true, std::max(4, P.tile_bits - 1));
     if (st != PTSBE_OK) return st;
     P.has_adjoint = true;
   }

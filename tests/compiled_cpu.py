@@ -51,7 +51,7 @@ static inline long long __double_as_longlong(double f) { long long u; std::memcp
 RUNNER = r"""
 extern "C" int run_pass(const unsigned char* blob, const uint64_t* offs, unsigned pass, unsigned slot_begin,
                         void* states, uint64_t N, unsigned n, unsigned k, unsigned n_passes, unsigned rows,
-                        const uint8_t* mr_bits, const double* mr_norm, unsigned n_measure, unsigned tpb) {
+                        const uint8_t* mr_bits, const double* mr_norm, unsigned n_measure) {
   PassArgs a;
   std::memset(&a, 0, sizeof(a));
   a.passes = blob + offs[0];
@@ -71,8 +71,7 @@ extern "C" int run_pass(const unsigned char* blob, const uint64_t* offs, unsigne
   a.n_passes = n_passes;
   a.t0 = 0;
   a.n_measure = n_measure;
-  const unsigned n_tiles = 1u << (n - k);
-  const unsigned bx = 1u << (k - 4), gx = n_tiles / (tpb < n_tiles ? tpb : n_tiles);
+  const unsigned bx = 1u << (k - 4), gx = 1u << (n - k);
   blockDim.x = bx;
   gridDim.x = gx;
   gridDim.y = rows;
@@ -122,7 +121,7 @@ def _build(src):
     lib = C.CDLL(so)
     lib.run_pass.restype = C.c_int
     lib.run_pass.argtypes = [C.c_void_p, C.c_void_p, C.c_uint, C.c_uint, C.c_void_p, C.c_uint64, C.c_uint,
-                             C.c_uint, C.c_uint, C.c_uint, C.c_void_p, C.c_void_p, C.c_uint, C.c_uint]
+                             C.c_uint, C.c_uint, C.c_uint, C.c_void_p, C.c_void_p, C.c_uint]
     return lib
 
 
@@ -139,9 +138,9 @@ def _raw_tables(ts, params):
     return buf, offs
 
 
-def run_compiled(plan, ts, params=None, mr_tol=1e-6, tiles_per_block=1):
+def run_compiled(plan, ts, params=None, mr_tol=1e-6):
     """States [B, 2^n] (normalised) after running every pass through its
-    generated kernel on the CPU (grid of 2^(n-k) / tiles_per_block blocks)."""
+    generated kernel on the CPU."""
     info = plan.info
     n = info["n_qubits"]
     N = 1 << n
@@ -168,7 +167,7 @@ def run_compiled(plan, ts, params=None, mr_tol=1e-6, tiles_per_block=1):
                 libs[src] = _build(src)
             k = int(passes[p]["k"])
             libs[src].run_pass(blob.ctypes.data, offs.ctypes.data, p, slot_begin[p], states.ctypes.data, N, n, k,
-                               NP, B, mr_bits.ctypes.data, mr_norm.ctypes.data, nm, tiles_per_block)
+                               NP, B, mr_bits.ctypes.data, mr_norm.ctypes.data, nm)
         else:
             for b in range(B):
                 w = np.abs(states[b].astype(np.complex128)) ** 2

@@ -165,8 +165,11 @@ def run_adjoint(fwd, adj, dot_param, n, B, n_params, odiag, weights, back_tol=1e
             ps, k, idx, slot = _geometry(adj, p, t, n)
             assert not ps["flags"] & 1
             Tp, Tl = psi[idx].copy(), lam[idx].copy()
+            reg = set(range(k - 4, k)) if k >= 6 else None
             for op in adj["ops"][ps["op_begin"]:ps["op_begin"] + ps["n_ops"]]:
                 if int(op["type"]) == DOT:
+                    if reg is not None:
+                        assert int(op["a"]) in reg, "gradient term outside the register bits"
                     a, gen = int(op["a"]), int(op["b"])
                     d = int(op["slots"][0]) | (int(op["slots"][1]) << 16)
                     vp = Tp.reshape(Tp.shape[0], -1, 2, 1 << a)
@@ -180,8 +183,9 @@ def run_adjoint(fwd, adj, dot_param, n, B, n_params, odiag, weights, back_tol=1e
                         z = -1j * np.vdot(l0, p1) + 1j * np.vdot(l1, p0)
                     grad[int(dot_param[d])] += weights[t] * z.imag
                 else:
-                    _apply_op(Tp, op, slot, adj["pool"], idx, k, None, {}, {})
-                    _apply_op(Tl, op, slot, adj["pool"], idx, k, None, {}, {})
+                    r0 = reg
+                    reg = _apply_op(Tp, op, slot, adj["pool"], idx, k, r0, {}, {})
+                    _apply_op(Tl, op, slot, adj["pool"], idx, k, r0, {}, {})
             psi[idx] = Tp
             lam[idx] = Tl
         # the sweep un-applies the whole circuit: psi is back at |0>

@@ -27,7 +27,7 @@ def test_random_circuits(n, gates, prec, tile, seed, half):
     params = np.asarray(circ["params"])
     plan = P.ptsbe_plan(circ, precision=prec, tile_qubits=tile, half_tile=half)
     ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=3, total_shots=3, seed=3, cfg=1)
-    st = run_compiled(plan, ts, params, tiles_per_block=4 if half else 1)
+    st = run_compiled(plan, ts, params)
     ref, _ = oracle_states(circ, ts.get()["records"], params=params)
     tol = 1e-5 if prec == "c64" else 1e-12
     assert max(float(np.max(np.abs(st[a] - ref[a]))) for a in range(len(ref))) <= tol
@@ -68,10 +68,10 @@ def test_brick_half_tile_transposes():
     from compiled_cpu import pass_source
     from workloads import brick_circuit
     circ = brick_circuit(14, 6, np.random.default_rng(3), 0.05, 0.08, eps_sigma=0.05)
-    plan = P.ptsbe_plan(circ, half_tile=True, tiles_per_block=2)
+    plan = P.ptsbe_plan(circ, half_tile=True)
     srcs = [pass_source(plan, p) for p in range(plan.info["n_passes"])]
     assert all("tile + 2048;" in s for s in srcs if s)
     ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=3, total_shots=3, seed=5, cfg=2)
-    st = run_compiled(plan, ts, tiles_per_block=2)
+    st = run_compiled(plan, ts)
     ref, _ = oracle_states(circ, ts.get()["records"])
     assert max(float(np.max(np.abs(st[a] - ref[a]))) for a in range(len(ref))) <= 1e-5
