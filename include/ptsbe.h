@@ -173,9 +173,12 @@ ptsbe_status ptsbe_plan_get_info(ptsbe_plan_t plan, ptsbe_plan_info* out);
  * PTSBE_E_DEVICE carries the compiler log if compilation fails. */
 ptsbe_status ptsbe_plan_compile(ptsbe_plan_t plan, uint32_t* n_kernels, double* seconds);
 /* Inspection: the generated HIP source of pass `pass` (kernel symbol
- * "ptsbe_pass"), NUL-terminated; an empty string if that pass runs through the
- * generic kernels.  With out == NULL only *len (bytes including the NUL) is set. */
-ptsbe_status ptsbe_plan_pass_source(ptsbe_plan_t plan, uint32_t pass, char* out, size_t* len);
+ * "ptsbe_pass") of the forward program, or with adjoint != 0 of the adjoint
+ * gradient's reverse sweep (signature (args, lambda, partial, n_dot)),
+ * NUL-terminated; an empty string if that pass runs through the generic
+ * kernels.  With out == NULL only *len (bytes including the NUL) is set. */
+ptsbe_status ptsbe_plan_pass_source(ptsbe_plan_t plan, uint32_t pass, uint32_t adjoint, char* out,
+                                    size_t* len);
 /* Per-site probabilities p_{s,k}: offsets[n_sites+1] into probs[total_kraus];
  * qubits[2*n_sites] (second entry 0xffffffff for 1-qubit sites); either may be NULL. */
 ptsbe_status ptsbe_plan_get_sites(ptsbe_plan_t plan, uint32_t* offsets, double* probs,

@@ -112,7 +112,8 @@ _SIGS = {
     "ptsbe_trajset_tables": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_uint32, C.c_void_p,
                                        C.POINTER(C.c_size_t), C.c_void_p]),
     "ptsbe_plan_compile": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint32), C.POINTER(C.c_double)]),
-    "ptsbe_plan_pass_source": (C.c_int, [C.c_void_p, C.c_uint32, C.c_char_p, C.POINTER(C.c_size_t)]),
+    "ptsbe_plan_pass_source": (C.c_int, [C.c_void_p, C.c_uint32, C.c_uint32, C.c_char_p,
+                                         C.POINTER(C.c_size_t)]),
     "ptsbe_trajset_adjoint_tables": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_void_p,
                                                C.POINTER(C.c_size_t), C.c_void_p, C.c_void_p, C.c_void_p]),
     "ptsbe_adjoint_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_double),

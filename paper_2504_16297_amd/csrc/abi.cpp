@@ -72,12 +72,14 @@ ptsbe_status ptsbe_plan_compile(ptsbe_plan_t plan, uint32_t* n_kernels, double* 
   })
 }
 
-ptsbe_status ptsbe_plan_pass_source(ptsbe_plan_t plan, uint32_t pass, char* out, size_t* len) {
+ptsbe_status ptsbe_plan_pass_source(ptsbe_plan_t plan, uint32_t pass, uint32_t adjoint, char* out, size_t* len) {
   FENCE({
     if (!plan || !len) return fail(PTSBE_E_ARG, "null argument");
     const Plan& P = *plan->plan;
-    if (pass >= P.passes.size()) return fail(PTSBE_E_ARG, "pass index out of range");
-    const std::string src = jit_pass_source(P.passes[pass], P.n, P.precision, "ptsbe_pass", P.half_tile_lds, nullptr);
+    const std::vector<Pass>& passes = adjoint ? P.adj.passes : P.passes;
+    if (pass >= passes.size()) return fail(PTSBE_E_ARG, "pass index out of range");
+    const std::string src =
+        jit_pass_source(passes[pass], P.n, P.precision, "ptsbe_pass", P.half_tile_lds, nullptr, adjoint != 0);
     if (out) {
       if (*len < src.size() + 1) return fail(PTSBE_E_ARG, "output buffer too small");
       std::memcpy(out, src.c_str(), src.size() + 1);

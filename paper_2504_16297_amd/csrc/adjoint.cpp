@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "host.hpp"
+#include "jit.hpp"
 #include "kernels.hpp"
 
 namespace ptsbe {
@@ -36,7 +37,8 @@ AdjLayout adj_layout(const Plan& P, const TrajSet& ts, uint32_t batch) {
   const uint32_t k_adj = P.adj.passes.empty() ? (uint32_t)P.n : (uint32_t)P.adj.passes[0].k;
   const uint64_t n_dot = P.adj.dot_param.size();
   L.batch = batch;
-  L.n_tiles = 1u << (P.n - k_adj);
+  // compiled sweeps write one partial per wavefront; room for that either way
+  L.n_tiles = (1u << (P.n - k_adj)) * (k_adj >= kMinRegTile ? jit_adjoint_waves(k_adj) : 1u);
   L.per_block = (uint32_t)std::min<uint64_t>(N, kScanBlock);
   L.nblk = (uint32_t)(N / L.per_block);
   L.per_thread = std::max<uint32_t>(1, L.per_block / 256);
@@ -88,6 +90,9 @@ PassArgs<V> pass_args(const Plan& P, uint8_t* tb, const TableLayout& T, uint32_t
 template <typename V>
 ptsbe_status adjoint_typed(const Plan& P, TrajSet& ts, const double* coef, const uint64_t* zmask, uint32_t n_terms,
                            uint8_t* ws, const AdjLayout& L, double* d_expval, double* d_grad, hipStream_t s) {
+  // every reverse-sweep pass compiled, or none (the partial layouts differ)
+  bool compiled = P.use_jit && !P.adj.passes.empty();
+  for (uint32_t p = 0; compiled && p < P.adj.passes.size(); ++p) compiled = jit_has_adjoint(P, p);
   const uint32_t B = (uint32_t)ts.m.size();
   const uint64_t N = 1ull << P.n;
   const uint32_t n_dot = (uint32_t)P.adj.dot_param.size();
@@ -127,7 +132,11 @@ ptsbe_status adjoint_typed(const Plan& P, TrajSet& ts, const double* coef, const
       if (ex.pass < 0) return fail(PTSBE_E_UNSUPPORTED, "adjoint: measurement steps are not supported");
       const Pass& ps = P.passes[ex.pass];
       fa.pass = (uint32_t)ex.pass;
-      CK(launch_pass<V>(fa, (uint32_t)ps.k, (uint32_t)ps.slots.size(), (uint32_t)ps.ops.size(), bb, s), "forward");
+      if (jit_has(P, (uint32_t)ex.pass))
+        CK(jit_launch<V>(P, (uint32_t)ex.pass, fa, bb, s), "compiled forward");
+      else
+        CK(launch_pass<V>(fa, (uint32_t)ps.k, (uint32_t)ps.slots.size(), (uint32_t)ps.ops.size(), bb, s),
+           "forward");
     }
     ScanArgs<V> sa{};
     sa.states = psi;
@@ -160,10 +169,15 @@ ptsbe_status adjoint_typed(const Plan& P, TrajSet& ts, const double* coef, const
     for (const ExecStep& ex : P.adj.exec) {
       const Pass& ps = P.adj.passes[ex.pass];
       aa.p.pass = (uint32_t)ex.pass;
-      CK(launch_adjoint_pass<V>(aa, (uint32_t)ps.k, (uint32_t)ps.slots.size(), bb, s), "reverse sweep");
+      if (compiled)
+        CK(jit_adjoint_launch<V>(P, (uint32_t)ex.pass, aa, bb, s), "compiled reverse sweep");
+      else
+        CK(launch_adjoint_pass<V>(aa, (uint32_t)ps.k, (uint32_t)ps.slots.size(), bb, s), "reverse sweep");
     }
   }
-  CK(launch_grad_reduce(partial, w, B, L.n_tiles, n_dot, reinterpret_cast<double*>(ws + L.gdot), dot_param,
+  const uint32_t k_adj = P.adj.passes.empty() ? (uint32_t)P.n : (uint32_t)P.adj.passes[0].k;
+  const uint32_t tiles_eff = compiled ? L.n_tiles : (1u << (P.n - k_adj));
+  CK(launch_grad_reduce(partial, w, B, tiles_eff, n_dot, reinterpret_cast<double*>(ws + L.gdot), dot_param,
                         (uint32_t)P.n_params, d_grad, ev, d_expval, s),
      "gradient reduction");
   return PTSBE_OK;
@@ -211,6 +225,10 @@ ptsbe_status adjoint_grad(const Plan& P, TrajSet& ts, const double* params, cons
   if (st != PTSBE_OK) return st;
   if (!d_ws || !d_expval || !d_grad) return fail(PTSBE_E_ARG, "null device pointer");
   if (reinterpret_cast<uintptr_t>(d_ws) % 256) return fail(PTSBE_E_ARG, "workspace must be 256-byte aligned");
+  if (P.use_jit) {
+    st = jit_build(P);
+    if (st != PTSBE_OK) return st;
+  }
   std::lock_guard<std::mutex> lk(ts.mu);
   st = build_tables(ts, params, 4096);
   if (st != PTSBE_OK) return st;

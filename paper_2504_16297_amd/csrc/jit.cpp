@@ -44,6 +44,8 @@ struct Gen {
   bool cs_neg = false;       // the pending scalar must also be negated
   bool tile_read = false;    // the LDS tile was read since the last barrier
   bool split = false;        // register changes go through half a tile of LDS, in two rounds
+  bool dual = false;         // adjoint sweep: every operation acts on psi (s*) and lambda (l*)
+  std::string pre = "s";     // register set the emitters write (s = psi, l = lambda)
   bool needs_full = false;   // an operation needs the whole tile in LDS
   // accumulated +-1 diagonal: amplitude r is negated where bit r of
   // XOR over monomials m of (value of m) * mask[m] is set
@@ -96,7 +98,11 @@ struct Gen {
   }
   static uint32_t swz(uint32_t L) { return L ^ ((L >> 4) & 15u); }
 
-  std::string S(int r) const { return "s" + std::to_string(r); }
+  std::string S(int r) const { return pre + std::to_string(r); }
+  std::vector<std::string> sets() const {
+    if (dual) return {"s", "l"};
+    return {"s"};
+  }
 
   void barrier_before_tile_write() {
     if (tile_read) {
@@ -125,12 +131,16 @@ struct Gen {
     o << "  {\n    V m0 = mats[" << 4 * slot << "], m1 = mats[" << 4 * slot + 1 << "], m2 = mats[" << 4 * slot + 2
       << "], m3 = mats[" << 4 * slot + 3 << "];\n";
     apply_pending_to("m0", "m1", "m2", "m3");
-    for (int r = 0; r < 16; ++r) {
-      if ((r >> j) & 1) continue;
-      const int r1 = r | (1 << j);
-      o << "    { const V x0 = " << S(r) << ", x1 = " << S(r1) << "; " << S(r) << " = cf(m0, x0, m1, x1); " << S(r1)
-        << " = cf(m2, x0, m3, x1); }\n";
+    for (const std::string& st : sets()) {
+      pre = st;
+      for (int r = 0; r < 16; ++r) {
+        if ((r >> j) & 1) continue;
+        const int r1 = r | (1 << j);
+        o << "    { const V x0 = " << S(r) << ", x1 = " << S(r1) << "; " << S(r) << " = cf(m0, x0, m1, x1); " << S(r1)
+          << " = cf(m2, x0, m3, x1); }\n";
+      }
     }
+    pre = "s";
     o << "  }\n";
   }
 
@@ -214,8 +224,12 @@ struct Gen {
       }
       return;
     }
-    for (int r = 0; r < 16; ++r)
-      if ((c >> r) & 1) o << "  " << S(r) << ".x = -" << S(r) << ".x; " << S(r) << ".y = -" << S(r) << ".y;\n";
+    for (const std::string& st : sets()) {
+      pre = st;
+      for (int r = 0; r < 16; ++r)
+        if ((c >> r) & 1) o << "  " << S(r) << ".x = -" << S(r) << ".x; " << S(r) << ".y = -" << S(r) << ".y;\n";
+    }
+    pre = "s";
     if (rt.empty()) return;
     uint32_t any = 0;
     o << "  {\n    uint32_t ng = 0u";
@@ -224,7 +238,9 @@ struct Gen {
       any |= t.second;
     }
     o << ";\n";
+    for (const std::string& st : sets())
     for (int r = 0; r < 16; ++r) {
+      pre = st;
       if (!((any >> r) & 1)) continue;
       if (c64)
         o << "    { const uint32_t sg = (ng << " << 31 - r << ") & 0x80000000u; " << S(r)
@@ -235,6 +251,7 @@ struct Gen {
           << ".x = __longlong_as_double(__double_as_longlong(" << S(r) << ".x) ^ sg); " << S(r)
           << ".y = __longlong_as_double(__double_as_longlong(" << S(r) << ".y) ^ sg); }\n";
     }
+    pre = "s";
     o << "  }\n";
   }
 
@@ -280,7 +297,11 @@ struct Gen {
       };
       const std::string lo = pick(ba, "d0", "d1"), hi = pick(ba, "d2", "d3");
       e = pick(bb, lo, hi);
-      o << "    " << S(r) << " = cm(" << e << ", " << S(r) << ");\n";
+      for (const std::string& st : sets()) {
+        pre = st;
+        o << "    " << S(r) << " = cm(" << e << ", " << S(r) << ");\n";
+      }
+      pre = "s";
     }
     o << "  }\n";
   }
@@ -291,7 +312,9 @@ struct Gen {
     o << "  {\n    const V* m = a.pool + slot_off[" << op.slot[0] << "];\n";
     if (ja >= 0 && jb >= 0) {
       o << "    V M[16];\n    for (int i = 0; i < 16; ++i) M[i] = m[i];\n";
+      for (const std::string& st : sets())
       for (int r = 0; r < 16; ++r) {
+        pre = st;
         if ((r >> ja) & 1 || (r >> jb) & 1) continue;
         const int i0 = r, i1 = r | (1 << ja), i2 = r | (1 << jb), i3 = r | (1 << ja) | (1 << jb);
         o << "    { const V x0 = " << S(i0) << ", x1 = " << S(i1) << ", x2 = " << S(i2) << ", x3 = " << S(i3) << ";\n";
@@ -300,13 +323,16 @@ struct Gen {
           o << "      " << S(idx[q]) << " = cd4(M + " << 4 * q << ", x0, x1, x2, x3);\n";
         o << "    }\n";
       }
+      pre = "s";
       o << "  }\n";
       return;
     }
     // through the LDS tile: any two local bits
     needs_full = true;
-    barrier_before_tile_write();
     o << "    const uint32_t Lt = " << lt_expr() << ", Lw = Lt ^ ((Lt >> 4) & 15u);\n";
+    for (const std::string& st : sets()) {
+    pre = st;
+    barrier_before_tile_write();
     for (int r = 0; r < 16; ++r) o << "    tile[Lw ^ " << swz(reg_const(r)) << "u] = " << S(r) << ";\n";
     o << "    __syncthreads();\n";
     const uint32_t A = 1u << op.a, B = 1u << op.b;
@@ -321,14 +347,16 @@ struct Gen {
       << "      tile[i2] = cd4(m + 8, x0, x1, x2, x3); tile[i3] = cd4(m + 12, x0, x1, x2, x3);\n    }\n"
       << "    __syncthreads();\n";
     for (int r = 0; r < 16; ++r) o << "    " << S(r) << " = tile[Lw ^ " << swz(reg_const(r)) << "u];\n";
-    o << "  }\n";
     tile_read = true;
+    }
+    pre = "s";
+    o << "  }\n";
   }
 
   void mr(const DOp& op) {
     const int j = reg_pos(op.a);
-    if (j < 0) {
-      fail("measure-reset on a non-register bit");
+    if (j < 0 || dual) {
+      fail("measure-reset on a non-register bit or in an adjoint sweep");
       return;
     }
     o << "  {\n    const uint64_t ri = (uint64_t)t * a.n_measure + " << op.slot[0]
@@ -354,16 +382,52 @@ struct Gen {
       phase_split(nr);
       return;
     }
-    o << "  {\n    const uint32_t Lt = " << lt_expr() << ", Lw = Lt ^ ((Lt >> 4) & 15u);\n";
-    for (int r = 0; r < 16; ++r) o << "    tile[Lw ^ " << swz(reg_const(r)) << "u] = " << S(r) << ";\n";
-    o << "  }\n  __syncthreads();\n";
-    for (int j = 0; j < 4; ++j) R[j] = nr[j];
-    for (int j = 0; j < 3; ++j)
-      if (!(R[j] < R[j + 1]) || R[3] >= k) fail("register bits not ascending");
-    o << "  {\n    const uint32_t Lt = " << lt_expr() << ", Lw = Lt ^ ((Lt >> 4) & 15u);\n";
-    for (int r = 0; r < 16; ++r) o << "    " << S(r) << " = tile[Lw ^ " << swz(reg_const(r)) << "u];\n";
-    o << "  }\n";
-    tile_read = true;
+    int oldR[4] = {R[0], R[1], R[2], R[3]};
+    for (const std::string& st : sets()) {
+      pre = st;
+      barrier_before_tile_write();
+      for (int j = 0; j < 4; ++j) R[j] = oldR[j];
+      o << "  {\n    const uint32_t Lt = " << lt_expr() << ", Lw = Lt ^ ((Lt >> 4) & 15u);\n";
+      for (int r = 0; r < 16; ++r) o << "    tile[Lw ^ " << swz(reg_const(r)) << "u] = " << S(r) << ";\n";
+      o << "  }\n  __syncthreads();\n";
+      for (int j = 0; j < 4; ++j) R[j] = nr[j];
+      for (int j = 0; j < 3; ++j)
+        if (!(R[j] < R[j + 1]) || R[3] >= k) fail("register bits not ascending");
+      o << "  {\n    const uint32_t Lt = " << lt_expr() << ", Lw = Lt ^ ((Lt >> 4) & 15u);\n";
+      for (int r = 0; r < 16; ++r) o << "    " << S(r) << " = tile[Lw ^ " << swz(reg_const(r)) << "u];\n";
+      o << "  }\n";
+      tile_read = true;
+    }
+    pre = "s";
+  }
+
+  // ---- adjoint gradient term: Im<lambda|P|psi> over this tile, P = X/Y/Z on a
+  // register bit; each wavefront sums its lanes and writes one FP64 partial
+  void dot(const DOp& op) {
+    const int j = reg_pos(op.a);
+    if (j < 0 || !dual) {
+      fail("gradient term on a non-register bit");
+      return;
+    }
+    const uint32_t d = (uint32_t)op.slot[0] | ((uint32_t)op.slot[1] << 16);
+    o << "  {\n    double acc = 0.0;\n";
+    for (int r = 0; r < 16; ++r) {
+      if ((r >> j) & 1) continue;
+      const int r1 = r | (1 << j);
+      const std::string p0 = "s" + std::to_string(r), p1 = "s" + std::to_string(r1);
+      const std::string l0 = "l" + std::to_string(r), l1 = "l" + std::to_string(r1);
+      if (op.b == 3)
+        o << "    acc += imc(" << l0 << ", " << p0 << ") - imc(" << l1 << ", " << p1 << ");\n";
+      else if (op.b == 1)
+        o << "    acc += imc(" << l0 << ", " << p1 << ") + imc(" << l1 << ", " << p0 << ");\n";
+      else  // Y: (Y psi)_0 = -i psi_1, (Y psi)_1 = i psi_0
+        o << "    acc += rec(" << l1 << ", " << p0 << ") - rec(" << l0 << ", " << p1 << ");\n";
+    }
+    const uint32_t bd = 1u << (k - 4), wl = std::min<uint32_t>(64, bd);
+    for (uint32_t off = 1; off < wl; off <<= 1) o << "    acc += __shfl_xor(acc, " << off << ", " << wl << ");\n";
+    const uint32_t W = bd / wl;
+    o << "    if ((tid & " << wl - 1 << "u) == 0u) partial[((uint64_t)t * " << (1ull << (n - k)) * W
+      << "ull + tile_id * " << W << "ull + (tid / " << wl << "u)) * n_dot + " << d << "u] = acc;\n  }\n";
   }
 
   // local index with bit p removed
@@ -463,6 +527,8 @@ __device__ __forceinline__ V cd4(const V* m, V x0, V x1, V x2, V x3) {
   return r;
 }
 __device__ __forceinline__ uint32_t sw(uint32_t L) { return L ^ ((L >> 4) & 15u); }
+__device__ __forceinline__ double imc(V a, V b) { return (double)a.x * (double)b.y - (double)a.y * (double)b.x; }
+__device__ __forceinline__ double rec(V a, V b) { return (double)a.x * (double)b.x + (double)a.y * (double)b.y; }
 )";
 
 std::string bit_gather(const char* src, const std::vector<int>& dst_pos, int first_src_bit) {
@@ -487,11 +553,15 @@ std::string bit_gather(const char* src, const std::vector<int>& dst_pos, int fir
 
 namespace {
 
-std::string gen_pass(const Pass& ps, int n, int precision, const std::string& name, bool split, bool* needs_full) {
+std::string gen_pass(const Pass& ps, int n, int precision, const std::string& name, bool split, bool dual,
+                     bool* needs_full) {
   const int k = ps.k;
   if (k < (int)kMinRegTile || k > 12) return "";
+  if (dual && (ps.flags & PASS_INIT_ZERO)) return "";
   Gen g;
-  g.split = split;
+  g.split = split && !dual;
+  g.dual = dual;
+  split = g.split;
   g.k = k;
   g.n = n;
   g.c64 = precision == PTSBE_C64;
@@ -504,7 +574,8 @@ std::string gen_pass(const Pass& ps, int n, int precision, const std::string& na
     << "struct PassArgs { " << kArgsFields << " };\n"
     << "static_assert(sizeof(PassArgs) == " << sizeof(PassArgs<float2>) << ", \"PassArgs layout\");\n"
     << kHelpers;
-  o << "extern \"C\" __global__ __launch_bounds__(256) void " << name << "(PassArgs a) {\n"
+  o << "extern \"C\" __global__ __launch_bounds__(256) void " << name << "(PassArgs a"
+    << (dual ? ", V* lam, double* partial, uint32_t n_dot" : "") << ") {\n"
     << "  extern __shared__ __align__(16) unsigned char smem[];\n"
     << "  V* tile = reinterpret_cast<V*>(smem);\n"
     << "  V* mats = tile + " << (split ? (1 << (k - 1)) : (1 << k)) << ";\n"
@@ -543,6 +614,10 @@ std::string gen_pass(const Pass& ps, int n, int precision, const std::string& na
   } else {
     o << "  const V* sst = a.states + (uint64_t)src * a.N + base + ot;\n";
     for (int r = 0; r < 16; ++r) o << "  V " << g.S(r) << " = sst[" << og[r] << "ull];\n";
+    if (dual) {
+      o << "  const V* lst = lam + (uint64_t)src * a.N + base + ot;\n";
+      for (int r = 0; r < 16; ++r) o << "  V l" << r << " = lst[" << og[r] << "ull];\n";
+    }
   }
   for (const DOp& op : ps.ops) {
     switch (op.type) {
@@ -563,6 +638,7 @@ std::string gen_pass(const Pass& ps, int n, int precision, const std::string& na
       case DOP_M2: g.m2(op); break;
       case DOP_MR: g.mr(op); break;
       case DOP_PHASE: g.phase(op); break;
+      case DOP_DOT: g.dot(op); break;
       default: g.fail("unknown operation type " + std::to_string(op.type));
     }
     if (!g.ok) return "";
@@ -573,10 +649,15 @@ std::string gen_pass(const Pass& ps, int n, int precision, const std::string& na
   if (!g.ok) return "";
   if (g.pending) {
     if (g.cs_neg) o << "  cs.x = -cs.x; cs.y = -cs.y;\n";
-    for (int r = 0; r < 16; ++r) o << "  " << g.S(r) << " = cm(cs, " << g.S(r) << ");\n";
+    for (const std::string& st : g.sets())
+      for (int r = 0; r < 16; ++r) o << "  " << st << r << " = cm(cs, " << st << r << ");\n";
   }
   o << "  V* dstp = a.states + (uint64_t)dst * a.N + base + ot;\n";
   for (int r = 0; r < 16; ++r) o << "  dstp[" << og[r] << "ull] = " << g.S(r) << ";\n";
+  if (dual) {
+    o << "  V* ldst = lam + (uint64_t)dst * a.N + base + ot;\n";
+    for (int r = 0; r < 16; ++r) o << "  ldst[" << og[r] << "ull] = l" << r << ";\n";
+  }
   o << "}\n";
   *needs_full = g.needs_full;
   return o.str();
@@ -585,12 +666,13 @@ std::string gen_pass(const Pass& ps, int n, int precision, const std::string& na
 }  // namespace
 
 std::string jit_pass_source(const Pass& ps, int n, int precision, const std::string& name, bool split,
-                            uint32_t* tile_elems) {
+                            uint32_t* tile_elems, bool dual) {
   bool full = false;
-  std::string src = gen_pass(ps, n, precision, name, split, &full);
+  split = split && !dual;
+  std::string src = gen_pass(ps, n, precision, name, split, dual, &full);
   if (split && full) {  // a 4x4 matrix off the register bits needs the whole tile
     split = false;
-    src = gen_pass(ps, n, precision, name, false, &full);
+    src = gen_pass(ps, n, precision, name, false, dual, &full);
   }
   if (tile_elems) *tile_elems = src.empty() ? 0u : (1u << (ps.k - (split ? 1 : 0)));
   return src;
@@ -631,27 +713,33 @@ ptsbe_status jit_build(const Plan& P) {
   std::lock_guard<std::mutex> lk(J.mu);
   if (J.built) return J.build_status == PTSBE_OK ? PTSBE_OK : fail(J.build_status, J.build_error);
   const auto t0 = std::chrono::steady_clock::now();
-  J.pass_kernel.assign(P.passes.size(), -1);
   std::map<std::string, int> by_body;
-  for (size_t p = 0; p < P.passes.size(); ++p) {
-    uint32_t te = 0;
-    const std::string body = jit_pass_source(P.passes[p], P.n, P.precision, "KERNEL_NAME", P.half_tile_lds, &te);
-    if (body.empty()) continue;
-    auto it = by_body.find(body);
-    if (it != by_body.end()) {
-      J.pass_kernel[p] = it->second;
-      continue;
+  auto add_program = [&](const std::vector<Pass>& passes, bool dual, std::vector<int>& kernel_of,
+                         const char* stem) {
+    kernel_of.assign(passes.size(), -1);
+    for (size_t p = 0; p < passes.size(); ++p) {
+      uint32_t te = 0;
+      const std::string body =
+          jit_pass_source(passes[p], P.n, P.precision, "KERNEL_NAME", P.half_tile_lds, &te, dual);
+      if (body.empty()) continue;
+      auto it = by_body.find(body);
+      if (it != by_body.end()) {
+        kernel_of[p] = it->second;
+        continue;
+      }
+      const int id = (int)J.names.size();
+      const std::string name = stem + std::to_string(id);
+      std::string src = body;
+      src.replace(src.find("KERNEL_NAME"), 11, name);
+      by_body[body] = id;
+      kernel_of[p] = id;
+      J.names.push_back(name);
+      J.sources.push_back(src);
+      J.tile_elems.push_back(te);
     }
-    const int id = (int)J.names.size();
-    const std::string name = "ptsbe_pass_" + std::to_string(id);
-    std::string src = body;
-    src.replace(src.find("KERNEL_NAME"), 11, name);
-    by_body[body] = id;
-    J.pass_kernel[p] = id;
-    J.names.push_back(name);
-    J.sources.push_back(src);
-    J.tile_elems.push_back(te);
-  }
+  };
+  add_program(P.passes, false, J.pass_kernel, "ptsbe_pass_");
+  if (P.has_adjoint) add_program(P.adj.passes, true, J.adj_pass_kernel, "ptsbe_adjoint_pass_");
   const size_t K = J.names.size();
   if (const char* dir = std::getenv("PTSBE_PASS_SOURCE_DIR")) {  // inspection: keep the generated sources
     for (size_t i = 0; i < K; ++i) {
@@ -761,6 +849,43 @@ hipError_t jit_launch(const Plan& P, uint32_t pass, const PassArgs<V>& a, uint32
                                nullptr);
 }
 
+bool jit_has_adjoint(const Plan& P, uint32_t pass) {
+  return P.jit && P.jit->built && P.jit->build_status == PTSBE_OK && pass < P.jit->adj_pass_kernel.size() &&
+         P.jit->adj_pass_kernel[pass] >= 0;
+}
+
+template <typename V>
+hipError_t jit_adjoint_launch(const Plan& P, uint32_t pass, const AdjArgs<V>& a, uint32_t rows, hipStream_t s) {
+  const std::vector<hipFunction_t>* fns = nullptr;
+  hipError_t e = jit_functions(P, &fns);
+  if (e != hipSuccess) return e;
+  const int kid = P.jit->adj_pass_kernel[pass];
+  hipFunction_t f = (*fns)[kid];
+  const Pass& ps = P.adj.passes[pass];
+  const uint32_t k = (uint32_t)ps.k, n_slots = (uint32_t)ps.slots.size();
+  const size_t te = P.jit->tile_elems[kid];
+  const size_t lds = sizeof(V) * (te + 4 * (size_t)n_slots) + 4 * (size_t)n_slots;
+  if (lds > 65536) return hipErrorInvalidConfiguration;
+  PassArgs<V> la = a.p;
+  uint32_t slot_begin = 0;
+  for (uint32_t p = 0; p < pass; ++p) slot_begin += (uint32_t)P.adj.passes[p].slots.size();
+  la.slot_default = a.p.slot_default + slot_begin;
+  V* lam = a.lam;
+  double* partial = a.partial;
+  uint32_t n_dot = a.n_dot;
+  void* args[] = {&la, &lam, &partial, &n_dot};
+  return hipModuleLaunchKernel(f, 1u << (P.n - k), rows, 1, 1u << (k - kRegBits), 1, 1, (unsigned)lds, s, args,
+                               nullptr);
+}
+
+uint32_t jit_adjoint_waves(uint32_t k) {
+  const uint32_t bd = 1u << (k - kRegBits);
+  return bd > 64 ? bd / 64 : 1u;
+}
+
+template hipError_t jit_adjoint_launch<float2>(const Plan&, uint32_t, const AdjArgs<float2>&, uint32_t, hipStream_t);
+template hipError_t jit_adjoint_launch<double2>(const Plan&, uint32_t, const AdjArgs<double2>&, uint32_t,
+                                                hipStream_t);
 template hipError_t jit_launch<float2>(const Plan&, uint32_t, const PassArgs<float2>&, uint32_t, hipStream_t);
 template hipError_t jit_launch<double2>(const Plan&, uint32_t, const PassArgs<double2>&, uint32_t, hipStream_t);
 

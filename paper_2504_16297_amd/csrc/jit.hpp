@@ -27,6 +27,7 @@ struct JitProgram {
   ptsbe_status build_status = PTSBE_OK;
   std::string build_error;
   std::vector<int> pass_kernel;            // pass -> compiled kernel index, -1 = interpreter kernel
+  std::vector<int> adj_pass_kernel;        // reverse-sweep pass -> compiled kernel index, -1 = generic
   std::vector<std::string> names;          // kernel index -> symbol
   std::vector<std::string> sources;        // kernel index -> HIP source
   std::vector<uint32_t> tile_elems;        // kernel index -> amplitudes of LDS tile space
@@ -43,8 +44,11 @@ struct JitProgram {
 // (less LDS per workgroup, more resident workgroups), unless a 4x4 matrix off
 // the register bits needs the whole tile.  *tile_elems receives the LDS tile
 // size in amplitudes.
+// `dual`: the adjoint sweep's kernel (signature (PassArgs, V* lam, double*
+// partial, uint32_t n_dot)): every operation acts on psi and lambda, DOT ops
+// write one FP64 partial per (trajectory, tile, wavefront, gradient term).
 std::string jit_pass_source(const Pass& ps, int n, int precision, const std::string& name, bool split,
-                            uint32_t* tile_elems);
+                            uint32_t* tile_elems, bool dual = false);
 
 // Generate and compile every pass kernel of the plan (host only, no device
 // needed).  Idempotent; thread-safe.
@@ -61,5 +65,14 @@ hipError_t jit_load(const Plan& P);
 
 // True if pass `pass` runs through a compiled kernel.
 bool jit_has(const Plan& P, uint32_t pass);
+
+// The reverse-sweep (adjoint) pass `pass` through its compiled kernel: psi in
+// a.p.states, lambda in a.lam; gradient partials at
+// [(trajectory * tiles * W + tile * W + wavefront) * n_dot + term], W =
+// jit_adjoint_waves(k) wavefronts per workgroup.
+bool jit_has_adjoint(const Plan& P, uint32_t pass);
+template <typename V>
+hipError_t jit_adjoint_launch(const Plan& P, uint32_t pass, const AdjArgs<V>& a, uint32_t rows, hipStream_t s);
+uint32_t jit_adjoint_waves(uint32_t k);
 
 }  // namespace ptsbe

@@ -39,6 +39,17 @@ alignas(16) unsigned char smem[1 << 17];
 static inline float __uint_as_float(uint32_t u) { float f; std::memcpy(&f, &u, 4); return f; }
 static inline uint32_t __float_as_uint(float f) { uint32_t u; std::memcpy(&u, &f, 4); return u; }
 static inline double __longlong_as_double(long long u) { double f; std::memcpy(&f, &u, 8); return f; }
+static double g_shfl[1024];
+// lane exchange within `width` lanes, by way of a block-wide buffer: every
+// thread of the block calls it at the same point, as the kernels do
+static inline double __shfl_xor(double v, int mask, int width) {
+  g_shfl[threadIdx.x] = v;
+  __syncthreads();
+  const unsigned src = (threadIdx.x & ~(unsigned)(width - 1)) | ((threadIdx.x ^ mask) & (width - 1));
+  const double r = g_shfl[src];
+  __syncthreads();
+  return r;
+}
 static inline long long __double_as_longlong(double f) { long long u; std::memcpy(&u, &f, 8); return u; }
 #define __global__
 #define __device__
@@ -51,7 +62,9 @@ static inline long long __double_as_longlong(double f) { long long u; std::memcp
 RUNNER = r"""
 extern "C" int run_pass(const unsigned char* blob, const uint64_t* offs, unsigned pass, unsigned slot_begin,
                         void* states, uint64_t N, unsigned n, unsigned k, unsigned n_passes, unsigned rows,
-                        const uint8_t* mr_bits, const double* mr_norm, unsigned n_measure) {
+                        const uint8_t* mr_bits, const double* mr_norm, unsigned n_measure, void* lam,
+                        double* partial, unsigned n_dot) {
+  (void)lam; (void)partial; (void)n_dot;
   PassArgs a;
   std::memset(&a, 0, sizeof(a));
   a.passes = blob + offs[0];
@@ -85,7 +98,7 @@ extern "C" int run_pass(const unsigned char* blob, const uint64_t* offs, unsigne
           threadIdx.x = t;
           blockIdx.x = x;
           blockIdx.y = y;
-          ptsbe_pass(a);
+          ptsbe_pass(a PASS_EXTRA);
         });
       for (auto& h : th) h.join();
     }
@@ -96,11 +109,11 @@ extern "C" int run_pass(const unsigned char* blob, const uint64_t* offs, unsigne
 _CACHE = os.path.join(tempfile.gettempdir(), "ptsbe_compiled_cpu")
 
 
-def pass_source(plan, p):
+def pass_source(plan, p, adjoint=False):
     n = C.c_size_t()
-    P.check(L.lib().ptsbe_plan_pass_source(plan.handle, p, None, C.byref(n)))
+    P.check(L.lib().ptsbe_plan_pass_source(plan.handle, p, int(adjoint), None, C.byref(n)))
     buf = C.create_string_buffer(n.value)
-    P.check(L.lib().ptsbe_plan_pass_source(plan.handle, p, buf, C.byref(n)))
+    P.check(L.lib().ptsbe_plan_pass_source(plan.handle, p, int(adjoint), buf, C.byref(n)))
     return buf.value.decode()
 
 
@@ -110,8 +123,10 @@ def _build(src):
     so = os.path.join(_CACHE, h + ".so")
     if not os.path.exists(so):
         cpp = os.path.join(_CACHE, h + ".cpp")
+        extra = "#define PASS_EXTRA , reinterpret_cast<V*>(lam), partial, n_dot\n" if "double* partial" in src \
+            else "#define PASS_EXTRA\n"
         with open(cpp, "w") as f:
-            f.write(SHIM + src + RUNNER)
+            f.write(SHIM + src + extra + RUNNER)
         tmp = so + f".{os.getpid()}.tmp"
         r = subprocess.run(["g++", "-std=c++20", "-O1", "-fPIC", "-shared", "-pthread", "-w", cpp, "-o", tmp],
                            stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
@@ -121,7 +136,8 @@ def _build(src):
     lib = C.CDLL(so)
     lib.run_pass.restype = C.c_int
     lib.run_pass.argtypes = [C.c_void_p, C.c_void_p, C.c_uint, C.c_uint, C.c_void_p, C.c_uint64, C.c_uint,
-                             C.c_uint, C.c_uint, C.c_uint, C.c_void_p, C.c_void_p, C.c_uint]
+                             C.c_uint, C.c_uint, C.c_uint, C.c_void_p, C.c_void_p, C.c_uint, C.c_void_p,
+                             C.c_void_p, C.c_uint]
     return lib
 
 
@@ -167,7 +183,7 @@ def run_compiled(plan, ts, params=None, mr_tol=1e-6):
                 libs[src] = _build(src)
             k = int(passes[p]["k"])
             libs[src].run_pass(blob.ctypes.data, offs.ctypes.data, p, slot_begin[p], states.ctypes.data, N, n, k,
-                               NP, B, mr_bits.ctypes.data, mr_norm.ctypes.data, nm)
+                               NP, B, mr_bits.ctypes.data, mr_norm.ctypes.data, nm, None, None, 0)
         else:
             for b in range(B):
                 w = np.abs(states[b].astype(np.complex128)) ** 2
@@ -184,3 +200,53 @@ def run_compiled(plan, ts, params=None, mr_tol=1e-6):
                     mr_norm[b * nm + r] = 1.0 / np.sqrt(pb * tot) if j == 0 else 1.0 / np.sqrt(pb)
     out = states.astype(np.complex128)
     return out / np.linalg.norm(out, axis=1, keepdims=True)
+
+
+def run_compiled_adjoint(plan, ts, params, odiag):
+    """(E, grad) of the trajectory set with the forward and reverse-sweep
+    passes run through their generated kernels on the CPU: psi by the forward
+    kernels, lambda = O psi, the dual-state sweep kernels writing one FP64
+    partial per (trajectory, tile, wavefront, term), reduced with weights
+    count / sum count."""
+    from paper_2504_16297_amd.tables import export_adjoint_tables
+    info = plan.info
+    n, N, B = info["n_qubits"], 1 << info["n_qubits"], ts.n_traj
+    c64 = info["precision"] == L.C64
+    cdt = np.complex64 if c64 else np.complex128
+    psi = run_compiled(plan, ts, params).astype(cdt)   # normalised: unitary circuits keep the norm
+    lam = (psi.astype(np.complex128) * odiag[None, :]).astype(cdt)
+    adj, dot_param = export_adjoint_tables(ts, params)
+    n_raw = C.c_size_t()
+    offs = np.zeros(16, dtype=np.uint64)
+    pa = np.ascontiguousarray(params, dtype=np.float64)
+    pp = C.cast(pa.ctypes.data, C.POINTER(C.c_double))
+    P.check(L.lib().ptsbe_trajset_adjoint_tables(ts.handle, pp, None, C.byref(n_raw), offs.ctypes.data, None, None))
+    blob = np.zeros(n_raw.value, dtype=np.uint8)
+    P.check(L.lib().ptsbe_trajset_adjoint_tables(ts.handle, pp, blob.ctypes.data, C.byref(n_raw), offs.ctypes.data,
+                                                 None, None))
+    passes = adj["passes"]
+    NP = len(passes)
+    n_dot = len(dot_param)
+    k = int(passes[0]["k"])
+    W = max(1, (1 << (k - 4)) // 64)
+    tiles = (1 << (n - k)) * W
+    partial = np.zeros(B * tiles * max(1, n_dot), dtype=np.float64)
+    libs = {}
+    for ex in adj["exec"]:
+        p = int(ex["pass"])
+        src = pass_source(plan, p, adjoint=True)
+        if not src:
+            raise RuntimeError(f"reverse-sweep pass {p} has no compiled kernel")
+        if src not in libs:
+            libs[src] = _build(src)
+        libs[src].run_pass(blob.ctypes.data, offs.ctypes.data, p, int(passes[p]["slot_begin"]), psi.ctypes.data, N,
+                           n, int(passes[p]["k"]), NP, B, None, None, 0, lam.ctypes.data, partial.ctypes.data, n_dot)
+    g = ts.get()
+    w = g["count"].astype(np.float64) / g["count"].sum()
+    part = partial.reshape(B, tiles, max(1, n_dot))[:, :, :n_dot].sum(axis=1)
+    grad = np.zeros(info["n_params"])
+    for d in range(n_dot):
+        grad[int(dot_param[d])] += float(np.dot(w, part[:, d]))
+    fwd = run_compiled(plan, ts, params)
+    E = float(np.dot(w, (np.abs(fwd) ** 2 * odiag[None, :]).sum(axis=1)))
+    return E, grad

@@ -75,3 +75,24 @@ def test_brick_half_tile_transposes():
     st = run_compiled(plan, ts)
     ref, _ = oracle_states(circ, ts.get()["records"])
     assert max(float(np.max(np.abs(st[a] - ref[a]))) for a in range(len(ref))) <= 1e-5
+
+
+@pytest.mark.parametrize("n,prec,seed", [(7, "c128", 11), (9, "c64", 12)])
+def test_adjoint_sweep_kernels(n, prec, seed):
+    """The compiled reverse sweep (psi and lambda in registers, gradient terms
+    as per-wavefront FP64 partials) against the oracle's adjoint gradient, on
+    circuits with X, Y and Z generators, 2-qubit gates and noise."""
+    from compiled_cpu import run_compiled_adjoint
+    from oracle.adjoint import ensemble_value_and_grad, observable_diag
+    circ = random_small_circuit(n, 50, np.random.default_rng(seed), p1=0.1, p2=0.15, with_params=True)
+    params = np.asarray(circ["params"])
+    obs = [(0.7, (0,)), (-1.3, (1, n - 1)), (0.4, tuple(range(n)))]
+    plan = P.ptsbe_plan(circ, precision=prec)
+    ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=3, total_shots=3, seed=3, cfg=7)
+    E, G = run_compiled_adjoint(plan, ts, params, observable_diag(n, obs))
+    g = ts.get()
+    w = g["count"].astype(np.float64) / g["count"].sum()
+    Er, Gr = ensemble_value_and_grad(circ, g["records"], w, params, obs)
+    tol = 1e-5 if prec == "c64" else 1e-11
+    assert abs(E - Er) <= tol
+    assert float(np.max(np.abs(G - Gr))) <= tol * max(1.0, float(np.max(np.abs(Gr))))
