@@ -465,6 +465,7 @@ static void schedule_phases(Pass& ps, int min_fill) {
     return op;
   };
   std::vector<DOp> out;
+  bool force_wave = false;  // the last register change brought nothing new: run the waves there are
   while (ndone < nops) {
     // Waves: every operation ready at the start of a wave is independent of the
     // others in it.  The wave's 2x2 matrices (at most one per register position)
@@ -477,10 +478,13 @@ static void schedule_phases(Pass& ps, int min_fill) {
       // A wave with few 2x2 matrices leaves register positions idle; when other
       // tile bits hold at least min_fill ready ones, emit only its diagonal ops
       // and switch registers instead.
-      int m1_here = 0, m1_other = 0;
+      int m1_here = 0, m1_other = 0, reg_others = 0;
       for (int i = 0; i < nops; ++i)
         if (!done[i] && ready(i) && ps.ops[i].type == DOP_M1) (fits(ps.ops[i]) ? m1_here : m1_other) += 1;
-      if (m1_here > 0 && m1_here < min_fill && std::min(m1_other, (int)kRegBits) >= min_fill) {
+      for (int i : wave)  // measure-resets and gradient terms in registers: never put off
+        if (ps.ops[i].type == DOP_MR || ps.ops[i].type == DOP_DOT) ++reg_others;
+      if (!force_wave && reg_others == 0 && m1_here > 0 && m1_here < min_fill &&
+          std::min(m1_other, (int)kRegBits) >= min_fill) {
         std::vector<int> diag;
         bool any_sign = false;
         for (int i : wave)
@@ -553,6 +557,11 @@ static void schedule_phases(Pass& ps, int min_fill) {
     for (int j = k - 1; j >= 0 && (int)nr.size() < (int)kRegBits; --j)
       if (std::find(nr.begin(), nr.end(), j) == nr.end()) nr.push_back(j);
     std::sort(nr.begin(), nr.end());
+    if (nr == R) {
+      force_wave = true;
+      continue;
+    }
+    force_wave = false;
     out.push_back(phase_op(nr));
     R = nr;
   }

@@ -117,3 +117,16 @@ def test_plan_site_order_matches_expansion():
             assert row[1] == s["qubits"][1]
         else:
             assert row[1] == 0xFFFFFFFF
+
+
+def test_adjoint_register_schedule_terminates():
+    """Gradient terms take register bits like 2x2 matrices; a register change
+    that brings no new bits must not be repeated (this circuit once made the
+    scheduler cycle forever)."""
+    import time
+    from workloads import random_small_circuit
+    circ = random_small_circuit(11, 70, np.random.default_rng(311), p1=0.1, p2=0.15, with_params=True)
+    t0 = time.perf_counter()
+    plan = P.ptsbe_plan(circ, precision="c64")
+    assert time.perf_counter() - t0 < 10
+    assert plan.info["n_params"] > 0
