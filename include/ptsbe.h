@@ -129,7 +129,8 @@ typedef struct {
     uint32_t tile_qubits;       /* 0 = automatic; else qubits per LDS tile (4..13) */
     uint32_t flags;             /* bits 0..2: fewest 2x2 matrices per register group worth a
                                    partial group (0 = 2); PTSBE_PLAN_NO_COMPILE,
-                                   PTSBE_PLAN_HALF_TILE_LDS */
+                                   PTSBE_PLAN_HALF_TILE_LDS, PTSBE_PLAN_NO_PHASE_FRAMES;
+                                   bits 8..11: waves per SIMD (PTSBE_PLAN_WAVES_SHIFT) */
     uint32_t reserved;
 } ptsbe_plan_opts;
 
@@ -140,6 +141,19 @@ typedef struct {
  * of LDS in two rounds (more resident workgroups per CU, two more barriers
  * per register change). */
 #define PTSBE_PLAN_HALF_TILE_LDS 16u
+/* Keep every slot matrix as it is.  By default the planner rewrites the
+ * forward program in phase frames: a unit-modulus diagonal may stay pending
+ * on a qubit between two of its matrices (it commutes with every diagonal
+ * operation in between), so that a 2x2 matrix is stored with a real diagonal
+ * (cheaper in the compiled passes) and diagonal gates between two matrices are
+ * merged away.  The states between passes and at the end are unchanged. */
+#define PTSBE_PLAN_NO_PHASE_FRAMES 32u
+/* flags bits 8..11: the number of waves per SIMD (1..8) the compiled passes'
+ * register budget is set for (512 / waves VGPRs, the compiler spills beyond
+ * it); 0 leaves the budget to the compiler.  Each pass kernel holds its
+ * 4096-amplitude tile (32 KiB in complex64) in LDS, so up to 5 workgroups fit
+ * a compute unit. */
+#define PTSBE_PLAN_WAVES_SHIFT 8u
 
 typedef struct ptsbe_plan_s* ptsbe_plan_t;
 typedef struct ptsbe_trajset_s* ptsbe_trajset_t;

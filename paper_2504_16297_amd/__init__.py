@@ -105,12 +105,16 @@ def ptsbe_plan_compile(plan):
     return nk.value, sec.value
 
 
-def ptsbe_plan(circuit, precision="c64", tile_qubits=0, compile=True, min_fill=0, half_tile=False):
+def ptsbe_plan(circuit, precision="c64", tile_qubits=0, compile=True, min_fill=0, half_tile=False,
+               phase_frames=True, waves=0):
     """Build the execution plan of a circuit dictionary (ops, channels, rules).
     ``compile=False`` runs the passes through the generic tile kernels instead of
     per-pass compiled kernels; ``min_fill`` (1..7, 0 = 2) is the fewest 2x2
     matrices a partial register group must hold; ``half_tile`` moves amplitudes
-    between register sets through half a tile of LDS."""
+    between register sets through half a tile of LDS; ``phase_frames=False``
+    keeps every slot matrix as it is (no pending diagonals between matrices);
+    ``waves`` (1..8, 0 = compiler's choice) sets the compiled passes' register
+    budget to 512 / waves VGPRs."""
     ops = circuit["ops"]
     arr = (L.Op * max(1, len(ops)))()
     keep = []
@@ -173,9 +177,12 @@ def ptsbe_plan(circuit, precision="c64", tile_qubits=0, compile=True, min_fill=0
     nm = L.NoiseModel(len(chans), carr, len(rules), rarr)
     if not 0 <= int(min_fill) <= 7:
         raise ValueError("min_fill must be in 0..7")
+    if not 0 <= int(waves) <= 8:
+        raise ValueError("waves must be in 0..8")
     po = L.PlanOpts({"c64": L.C64, "c128": L.C128}[precision], int(tile_qubits),
                     int(min_fill) | (0 if compile else L.PLAN_NO_COMPILE) |
-                    (L.PLAN_HALF_TILE_LDS if half_tile else 0), 0)
+                    (L.PLAN_HALF_TILE_LDS if half_tile else 0) |
+                    (0 if phase_frames else L.PLAN_NO_PHASE_FRAMES) | (int(waves) << L.PLAN_WAVES_SHIFT), 0)
     h = C.c_void_p()
     check(lib().ptsbe_plan(C.byref(c), C.byref(nm), C.byref(po), C.byref(h)))
     return Plan(h, None)

@@ -25,6 +25,8 @@ RUN_SHOTS, RUN_STATES, RUN_EXPECTATION, RUN_ADJOINT = range(4)
 RUN_NO_PREFIX_SHARING = 1
 PLAN_NO_COMPILE = 8
 PLAN_HALF_TILE_LDS = 16
+PLAN_NO_PHASE_FRAMES = 32
+PLAN_WAVES_SHIFT = 8
 
 
 class Op(C.Structure):

@@ -79,7 +79,8 @@ ptsbe_status ptsbe_plan_pass_source(ptsbe_plan_t plan, uint32_t pass, uint32_t a
     const std::vector<Pass>& passes = adjoint ? P.adj.passes : P.passes;
     if (pass >= passes.size()) return fail(PTSBE_E_ARG, "pass index out of range");
     const std::string src =
-        jit_pass_source(passes[pass], P.n, P.precision, "ptsbe_pass", P.half_tile_lds, nullptr, adjoint != 0);
+        jit_pass_source(passes[pass], P.n, P.precision, "ptsbe_pass", P.half_tile_lds, nullptr, adjoint != 0,
+                        P.waves);
     if (out) {
       if (*len < src.size() + 1) return fail(PTSBE_E_ARG, "output buffer too small");
       std::memcpy(out, src.c_str(), src.size() + 1);

@@ -65,8 +65,28 @@ struct Part {
   int half;                    // -1: whole step; 0 / 1: factor on the site's first / second qubit
 };
 
+// Phase frames of the forward program.  A diagonal of unit-modulus phases
+// commutes with every diagonal operation, so the tables may leave one pending
+// on a qubit and let the next matrix on that qubit take it in: a 2x2 slot M
+// then runs as V = D^-1 M F, with F the diagonal pending before it and D the
+// phases of the diagonal of M F, chosen so that V has a real diagonal (cheaper
+// to apply); D stays pending.  A diagonal gate slot between two matrices is
+// taken into the pending diagonal and not applied at all.  The chain of every
+// qubit ends without a pending diagonal (the last matrix before a measurement,
+// a measure-reset or the end of the program absorbs it as a plain 2x2), so
+// the states between passes and at the end are the exact ones.
+enum FrameRole : uint8_t {
+  FRAME_NONE = 0,           // matrix applied as is (a 2x2 or 4x4 slot still absorbs the pending diagonal)
+  FRAME_REAL_DIAG = 1,      // 2x2 slot stored as V with a real diagonal; D stays pending
+  FRAME_ABSORB = 2,         // unitary diagonal slot with no noise site, merged into the pending
+                            // diagonal; the tables hold the identity and the kernels skip it
+  FRAME_OVERRIDE_ONLY = 3,  // unitary diagonal 2x2 slot with noise sites: its default becomes the
+                            // identity (skipped), a trajectory's override still runs as a 2x2
+};
+
 struct Slot {
   uint8_t type;                // DOP_M1 / DOP_M2 / DOP_D1 / DOP_D2
+  uint8_t frame = FRAME_NONE;  // FrameRole (forward program only)
   int q[2];                    // global qubits (matrix bit 0, bit 1)
   std::vector<Part> parts;     // applied in order
   std::vector<int> sites;      // sites whose choice changes this slot
@@ -122,6 +142,7 @@ struct Plan {
   // per-pass compiled kernels (built on first use unless disabled)
   bool use_jit = true;
   bool half_tile_lds = false;  // compiled passes change registers through half a tile of LDS
+  int waves = 0;               // waves per SIMD the compiled passes' register budget is set for (0 = default)
   std::shared_ptr<JitProgram> jit;
 };
 
@@ -165,6 +186,19 @@ Mat rot_matrix(int gen, double theta);
 // the step list of the program the slot belongs to.
 Mat slot_matrix(const Plan& plan, const std::vector<Step>& steps, const Slot& s, const double* params,
                 const std::map<int, int>& choice);
+
+// Phase frames: per slot of a program, the pending diagonal it takes in
+// (`in[j]` for its matrix qubit j) and, for FRAME_REAL_DIAG, the diagonal it
+// leaves pending (`out`).  Computed from the slots' default matrices.
+struct SlotFrame {
+  cd in[2][2] = {{cd(1, 0), cd(1, 0)}, {cd(1, 0), cd(1, 0)}};
+  cd out[2] = {cd(1, 0), cd(1, 0)};
+};
+std::vector<std::vector<SlotFrame>> slot_frames(int n, const std::vector<Pass>& passes,
+                                                const std::vector<ExecStep>& exec,
+                                                const std::vector<std::vector<Mat>>& defaults);
+// The matrix a slot's table entry holds for true matrix M (default or override).
+Mat frame_matrix(const Slot& s, const SlotFrame& f, const Mat& M);
 
 // Planner
 ptsbe_status build_plan(const ptsbe_circuit* c, const ptsbe_noise_model* nm,

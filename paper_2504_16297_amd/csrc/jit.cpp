@@ -17,6 +17,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <functional>
+#include <set>
 #include <sstream>
 #include <thread>
 
@@ -52,6 +53,18 @@ struct Gen {
   std::map<Mono, uint32_t> signs;
   bool ok = true;
   std::string why;
+  const uint8_t* frame = nullptr;  // FrameRole per slot
+
+  // bit of `slot` in the block's override set (wave-uniform words)
+  std::string ovbit(int slot) const {
+    return "(ovw" + std::to_string(slot >> 5) + " & " + std::to_string(1u << (slot & 31)) + "u)";
+  }
+  // branch condition of an override path: rare, laid out away from the hot code
+  std::string ovcond(int slot) const { return "(__builtin_expect(" + ovbit(slot) + " != 0u, 0))"; }
+  void load2x2(int slot) {
+    o << "    V m0 = mats[" << 4 * slot << "], m1 = mats[" << 4 * slot + 1 << "], m2 = mats[" << 4 * slot + 2
+      << "], m3 = mats[" << 4 * slot + 3 << "];\n";
+  }
 
   void fail(const std::string& w) {
     if (ok) why = w;
@@ -126,21 +139,45 @@ struct Gen {
     pending = true;
   }
 
-  // ---- 2x2 matrix on register position j, matrix in mats[4 * slot ..]
-  void gate(int j, int slot) {
-    o << "  {\n    V m0 = mats[" << 4 * slot << "], m1 = mats[" << 4 * slot + 1 << "], m2 = mats[" << 4 * slot + 2
-      << "], m3 = mats[" << 4 * slot + 3 << "];\n";
-    apply_pending_to("m0", "m1", "m2", "m3");
+  // ---- 2x2 matrix on register position j
+  void gate_body(int j, bool real_diag) {
     for (const std::string& st : sets()) {
       pre = st;
       for (int r = 0; r < 16; ++r) {
         if ((r >> j) & 1) continue;
         const int r1 = r | (1 << j);
-        o << "    { const V x0 = " << S(r) << ", x1 = " << S(r1) << "; " << S(r) << " = cf(m0, x0, m1, x1); " << S(r1)
-          << " = cf(m2, x0, m3, x1); }\n";
+        if (real_diag)
+          o << "    { const V x0 = " << S(r) << ", x1 = " << S(r1) << "; " << S(r) << " = cr(m0.x, x0, m1, x1); "
+            << S(r1) << " = cr(m3.x, x1, m2, x0); }\n";
+        else
+          o << "    { const V x0 = " << S(r) << ", x1 = " << S(r1) << "; " << S(r) << " = cf(m0, x0, m1, x1); "
+            << S(r1) << " = cf(m2, x0, m3, x1); }\n";
       }
     }
     pre = "s";
+  }
+  // A slot stored with a real diagonal (phase frame) runs the cheaper form
+  // unless this block's trajectory overrides it with a general matrix; the
+  // block-uniform scalar then stays pending instead of being folded in.
+  void gate(int j, int slot) {
+    const uint8_t role = frame ? frame[slot] : (uint8_t)FRAME_NONE;
+    if (role == FRAME_ABSORB) return;  // merged into a pending phase frame
+    o << "  {\n";
+    load2x2(slot);
+    if (role == FRAME_REAL_DIAG || role == FRAME_OVERRIDE_ONLY) {
+      o << "  if " << ovcond(slot) << " {\n";
+      gate_body(j, false);
+      o << "  }";
+      if (role == FRAME_REAL_DIAG) {
+        o << " else {\n";
+        gate_body(j, true);
+        o << "  }";
+      }
+      o << "\n  }\n";
+      return;
+    }
+    apply_pending_to("m0", "m1", "m2", "m3");
+    gate_body(j, false);
     o << "  }\n";
   }
 
@@ -521,6 +558,13 @@ __device__ __forceinline__ V cf(V m0, V x0, V m1, V x1) {
   r.y = m0.x * x0.y + m0.y * x0.x + m1.x * x1.y + m1.y * x1.x;
   return r;
 }
+// d * xd + m * xo for a real d: the diagonal entry of a phase-frame matrix
+__device__ __forceinline__ V cr(T d, V xd, V m, V xo) {
+  V r;
+  r.x = d * xd.x + m.x * xo.x - m.y * xo.y;
+  r.y = d * xd.y + m.x * xo.y + m.y * xo.x;
+  return r;
+}
 __device__ __forceinline__ V cd4(const V* m, V x0, V x1, V x2, V x3) {
   V r = cf(m[0], x0, m[1], x1), q = cf(m[2], x2, m[3], x3);
   r.x += q.x; r.y += q.y;
@@ -554,7 +598,7 @@ std::string bit_gather(const char* src, const std::vector<int>& dst_pos, int fir
 namespace {
 
 std::string gen_pass(const Pass& ps, int n, int precision, const std::string& name, bool split, bool dual,
-                     bool* needs_full) {
+                     int waves, bool* needs_full) {
   const int k = ps.k;
   if (k < (int)kMinRegTile || k > 12) return "";
   if (dual && (ps.flags & PASS_INIT_ZERO)) return "";
@@ -569,12 +613,22 @@ std::string gen_pass(const Pass& ps, int n, int precision, const std::string& na
   g.oq = ps.oq;
   for (int j = 0; j < 4; ++j) g.R[j] = k - 4 + j;
   const int n_slots = (int)ps.slots.size();
+  std::vector<uint8_t> frame(n_slots);
+  std::set<int> ovw_words;  // words of the override bit set that hold a rewritten 2x2 slot
+  for (int i = 0; i < n_slots; ++i) {
+    frame[i] = ps.slots[i].frame;
+    if (frame[i] == FRAME_REAL_DIAG || frame[i] == FRAME_OVERRIDE_ONLY) ovw_words.insert(i >> 5);
+  }
+  g.frame = frame.data();
+  const int n_ovw = (n_slots + 31) / 32;
   std::ostringstream& o = g.o;
   o << kPrelude << (g.c64 ? "typedef float T;\ntypedef float2 V;\n" : "typedef double T;\ntypedef double2 V;\n")
     << "struct PassArgs { " << kArgsFields << " };\n"
     << "static_assert(sizeof(PassArgs) == " << sizeof(PassArgs<float2>) << ", \"PassArgs layout\");\n"
     << kHelpers;
-  o << "extern \"C\" __global__ __launch_bounds__(256) void " << name << "(PassArgs a"
+  o << "extern \"C\" __global__ __launch_bounds__(256) ";
+  if (waves > 0) o << "__attribute__((amdgpu_waves_per_eu(" << waves << "))) ";
+  o << "void " << name << "(PassArgs a"
     << (dual ? ", V* lam, double* partial, uint32_t n_dot" : "") << ") {\n"
     << "  extern __shared__ __align__(16) unsigned char smem[];\n"
     << "  V* tile = reinterpret_cast<V*>(smem);\n"
@@ -584,18 +638,9 @@ std::string gen_pass(const Pass& ps, int n, int precision, const std::string& na
     << "  uint32_t src = blockIdx.y, dst = blockIdx.y;\n"
     << "  if (a.route) { const uint2 e = a.route[blockIdx.y]; src = e.x; dst = e.y; }\n"
     << "  const bool carrier = a.route != nullptr && dst >= a.carrier0;\n"
-    << "  const uint32_t t = a.t0 + dst;\n"
-    << "  for (uint32_t i = tid; i < " << n_slots << "u; i += blockDim.x) slot_off[i] = a.slot_default[i];\n"
-    << "  __syncthreads();\n"
-    << "  if (!carrier) {\n"
-    << "    const uint32_t ob = a.ov_off[(uint64_t)t * a.n_passes + a.pass];\n"
-    << "    const uint32_t oe = a.ov_off[(uint64_t)t * a.n_passes + a.pass + 1];\n"
-    << "    for (uint32_t i = ob + tid; i < oe; i += blockDim.x) slot_off[a.ov[i].slot] = a.ov[i].off;\n"
-    << "  }\n"
-    << "  __syncthreads();\n"
-    << "  for (uint32_t i = tid; i < " << 4 * n_slots << "u; i += blockDim.x) mats[i] = a.pool[slot_off[i >> 2] + (i & 3u)];\n"
-    << "  __syncthreads();\n";
-  // global offsets: thread part from tid, register parts constant
+    << "  const uint32_t t = a.t0 + dst;\n";
+  // The state loads come first: their latency overlaps the matrix set-up.
+  // Global offsets: thread part from tid, register parts constant.
   std::vector<int> tpos(g.tq.begin(), g.tq.begin() + (k - 4));
   o << "  const uint64_t ot = " << bit_gather("tid", tpos, 0) << ";\n";
   o << "  const uint64_t tile_id = blockIdx.x;\n"
@@ -619,6 +664,32 @@ std::string gen_pass(const Pass& ps, int n, int precision, const std::string& na
       for (int r = 0; r < 16; ++r) o << "  V l" << r << " = lst[" << og[r] << "ull];\n";
     }
   }
+  // Matrix set-up in LDS: every block gathers the defaults (one dependent
+  // pair of loads, overlapping the state loads); only a block whose trajectory
+  // overrides slots of this pass patches them after a barrier.
+  o << "  uint32_t* ovw = slot_off + " << n_slots << ";\n"
+    << "  uint32_t ob = 0u, oe = 0u;\n"
+    << "  if (!carrier) {\n"
+    << "    ob = a.ov_off[(uint64_t)t * a.n_passes + a.pass];\n"
+    << "    oe = a.ov_off[(uint64_t)t * a.n_passes + a.pass + 1];\n"
+    << "  }\n"
+    << "  for (uint32_t i = tid; i < " << n_slots << "u; i += blockDim.x) slot_off[i] = a.slot_default[i];\n"
+    << "  for (uint32_t i = tid; i < " << 4 * n_slots
+    << "u; i += blockDim.x) mats[i] = a.pool[a.slot_default[i >> 2] + (i & 3u)];\n"
+    << "  for (uint32_t i = tid; i < " << n_ovw << "u; i += blockDim.x) ovw[i] = 0u;\n"
+    << "  __syncthreads();\n"
+    << "  if (ob != oe) {\n"
+    << "    for (uint32_t i = ob + tid; i < oe; i += blockDim.x) {\n"
+    << "      const uint32_t sl = a.ov[i].slot, off = a.ov[i].off;\n"
+    << "      slot_off[sl] = off;\n"
+    << "      for (uint32_t e = 0; e < 4u; ++e) mats[4u * sl + e] = a.pool[off + e];\n"
+    << "      atomicOr(ovw + (sl >> 5), 1u << (sl & 31u));\n"
+    << "    }\n"
+    << "    __syncthreads();\n"
+    << "  }\n";
+  // which rewritten slots this block's trajectory overrides, as wave-uniform words
+  for (int w : ovw_words)
+    o << "  const uint32_t ovw" << w << " = __builtin_amdgcn_readfirstlane(ovw[" << w << "]);\n";
   for (const DOp& op : ps.ops) {
     switch (op.type) {
       case DOP_M1G:
@@ -634,6 +705,8 @@ std::string gen_pass(const Pass& ps, int n, int precision, const std::string& na
       case DOP_DSIGN: g.dsign(op); break;
       case DOP_SFLIP: g.flush_signs(); break;
       case DOP_D1:
+        if (frame[op.slot[0]] != FRAME_ABSORB) g.diag(op);  // else merged into a pending phase frame
+        break;
       case DOP_D2: g.diag(op); break;
       case DOP_M2: g.m2(op); break;
       case DOP_MR: g.mr(op); break;
@@ -666,13 +739,13 @@ std::string gen_pass(const Pass& ps, int n, int precision, const std::string& na
 }  // namespace
 
 std::string jit_pass_source(const Pass& ps, int n, int precision, const std::string& name, bool split,
-                            uint32_t* tile_elems, bool dual) {
+                            uint32_t* tile_elems, bool dual, int waves) {
   bool full = false;
   split = split && !dual;
-  std::string src = gen_pass(ps, n, precision, name, split, dual, &full);
+  std::string src = gen_pass(ps, n, precision, name, split, dual, waves, &full);
   if (split && full) {  // a 4x4 matrix off the register bits needs the whole tile
     split = false;
-    src = gen_pass(ps, n, precision, name, false, dual, &full);
+    src = gen_pass(ps, n, precision, name, false, dual, waves, &full);
   }
   if (tile_elems) *tile_elems = src.empty() ? 0u : (1u << (ps.k - (split ? 1 : 0)));
   return src;
@@ -720,7 +793,7 @@ ptsbe_status jit_build(const Plan& P) {
     for (size_t p = 0; p < passes.size(); ++p) {
       uint32_t te = 0;
       const std::string body =
-          jit_pass_source(passes[p], P.n, P.precision, "KERNEL_NAME", P.half_tile_lds, &te, dual);
+          jit_pass_source(passes[p], P.n, P.precision, "KERNEL_NAME", P.half_tile_lds, &te, dual, P.waves);
       if (body.empty()) continue;
       auto it = by_body.find(body);
       if (it != by_body.end()) {
@@ -838,7 +911,7 @@ hipError_t jit_launch(const Plan& P, uint32_t pass, const PassArgs<V>& a, uint32
   const Pass& ps = P.passes[pass];
   const uint32_t k = (uint32_t)ps.k, n_slots = (uint32_t)ps.slots.size();
   const size_t te = P.jit->tile_elems[P.jit->pass_kernel[pass]];
-  const size_t lds = sizeof(V) * (te + 4 * (size_t)n_slots) + 4 * (size_t)n_slots;
+  const size_t lds = sizeof(V) * (te + 4 * (size_t)n_slots) + 4 * ((size_t)n_slots + (n_slots + 31) / 32);
   if (lds > 65536) return hipErrorInvalidConfiguration;
   PassArgs<V> la = a;
   uint32_t slot_begin = 0;
@@ -864,7 +937,7 @@ hipError_t jit_adjoint_launch(const Plan& P, uint32_t pass, const AdjArgs<V>& a,
   const Pass& ps = P.adj.passes[pass];
   const uint32_t k = (uint32_t)ps.k, n_slots = (uint32_t)ps.slots.size();
   const size_t te = P.jit->tile_elems[kid];
-  const size_t lds = sizeof(V) * (te + 4 * (size_t)n_slots) + 4 * (size_t)n_slots;
+  const size_t lds = sizeof(V) * (te + 4 * (size_t)n_slots) + 4 * ((size_t)n_slots + (n_slots + 31) / 32);
   if (lds > 65536) return hipErrorInvalidConfiguration;
   PassArgs<V> la = a.p;
   uint32_t slot_begin = 0;

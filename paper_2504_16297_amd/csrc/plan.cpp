@@ -2,6 +2,7 @@
 // of every channel (Sec. 2.2), expansion into noise sites (the NoisyCircuit of
 // Algorithm 2), and fusion of the operations into LDS tile passes.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <set>
@@ -697,6 +698,137 @@ static ptsbe_status schedule(Plan& plan, const std::vector<Step>& steps, std::ve
   return PTSBE_OK;
 }
 
+// ------------------------------------------------------------ phase frames
+
+namespace {
+
+enum FrameEventKind { FE_M1, FE_M2, FE_DIAG, FE_BREAK };
+
+struct FrameEvent {
+  int kind, pass, slot, j;  // j: matrix qubit of an M2 slot
+};
+
+// Calls f(q, event) for every event of qubit q's chain, in program order: a
+// 2x2 or 4x4 slot, a diagonal slot (D1), or a break (measure-reset, gradient
+// dot, measurement step, end of program).  Diagonal ops that the tables do not
+// hold as slots (signs, D2) commute with any pending diagonal and are skipped.
+template <class F>
+void walk_frames(int n, const std::vector<Pass>& passes, const std::vector<ExecStep>& exec, F&& f) {
+  for (const ExecStep& ex : exec) {
+    if (ex.pass < 0) {
+      for (int q : ex.mr_qubits) f(q, FrameEvent{FE_BREAK, -1, -1, 0});
+      continue;
+    }
+    const Pass& ps = passes[ex.pass];
+    for (const DOp& op : ps.ops) {
+      switch (op.type) {
+        case DOP_M1G:
+          for (int j = 0; j < 4; ++j)
+            if ((op.mask >> j) & 1) f(ps.slots[op.slot[j]].q[0], FrameEvent{FE_M1, ex.pass, op.slot[j], 0});
+          break;
+        case DOP_M1: f(ps.slots[op.slot[0]].q[0], FrameEvent{FE_M1, ex.pass, op.slot[0], 0}); break;
+        case DOP_M2:
+          f(ps.slots[op.slot[0]].q[0], FrameEvent{FE_M2, ex.pass, op.slot[0], 0});
+          f(ps.slots[op.slot[0]].q[1], FrameEvent{FE_M2, ex.pass, op.slot[0], 1});
+          break;
+        case DOP_D1: f(ps.slots[op.slot[0]].q[0], FrameEvent{FE_DIAG, ex.pass, op.slot[0], 0}); break;
+        case DOP_MR:
+        case DOP_DOT: f(ps.tq[op.a], FrameEvent{FE_BREAK, ex.pass, -1, 0}); break;
+        default: break;
+      }
+    }
+  }
+  for (int q = 0; q < n; ++q) f(q, FrameEvent{FE_BREAK, -1, -1, 0});
+}
+
+// Roles: a 2x2 slot runs with a real diagonal when the next non-diagonal event
+// of its qubit is another matrix (which takes the pending diagonal in); under
+// the same condition a slot that is a unitary diagonal for every choice of its
+// sites (projections excluded) is merged into the pending diagonal, or, when
+// noise sites can override it, keeps only the override.
+void assign_frames(int n, const std::vector<Step>& steps, std::vector<Pass>& passes,
+                   const std::vector<ExecStep>& exec) {
+  std::vector<std::vector<FrameEvent>> chain(n);
+  walk_frames(n, passes, exec, [&](int q, const FrameEvent& e) { chain[q].push_back(e); });
+  auto unitary_diag = [&](const Slot& s) {
+    for (const Part& pt : s.parts)
+      if (!steps[pt.step].diag || steps[pt.step].kind == ST_P0) return false;
+    return true;
+  };
+  for (int q = 0; q < n; ++q) {
+    const auto& c = chain[q];
+    for (size_t i = 0; i < c.size(); ++i) {
+      if (c[i].kind != FE_M1 && c[i].kind != FE_DIAG) continue;
+      size_t j = i + 1;
+      while (j < c.size() && c[j].kind == FE_DIAG) ++j;
+      const bool absorbed = j < c.size() && (c[j].kind == FE_M1 || c[j].kind == FE_M2);
+      Slot& s = passes[c[i].pass].slots[c[i].slot];
+      s.frame = FRAME_NONE;
+      if (!absorbed) continue;
+      if (unitary_diag(s)) s.frame = s.sites.empty() ? FRAME_ABSORB : (c[i].kind == FE_M1 ? FRAME_OVERRIDE_ONLY
+                                                                                          : FRAME_NONE);
+      else if (c[i].kind == FE_M1) s.frame = FRAME_REAL_DIAG;
+    }
+  }
+}
+
+cd unit_phase(cd z) {
+  const double a = std::abs(z);
+  return a > 0 ? z / a : cd(1, 0);
+}
+
+}  // namespace
+
+std::vector<std::vector<SlotFrame>> slot_frames(int n, const std::vector<Pass>& passes,
+                                                const std::vector<ExecStep>& exec,
+                                                const std::vector<std::vector<Mat>>& defaults) {
+  std::vector<std::vector<SlotFrame>> fr(passes.size());
+  for (size_t p = 0; p < passes.size(); ++p) fr[p].resize(passes[p].slots.size());
+  std::vector<std::array<cd, 2>> pend(n, {cd(1, 0), cd(1, 0)});
+  walk_frames(n, passes, exec, [&](int q, const FrameEvent& e) {
+    if (e.kind == FE_BREAK) return;  // every chain is flushed before a break (assign_frames)
+    const Slot& s = passes[e.pass].slots[e.slot];
+    SlotFrame& f = fr[e.pass][e.slot];
+
+    if (e.kind == FE_M2 || (e.kind == FE_M1 && s.frame == FRAME_NONE)) {
+      f.in[e.j][0] = pend[q][0];
+      f.in[e.j][1] = pend[q][1];
+      pend[q] = {cd(1, 0), cd(1, 0)};
+    } else if (e.kind == FE_M1 && s.frame != FRAME_ABSORB) {
+      f.in[0][0] = pend[q][0];
+      f.in[0][1] = pend[q][1];
+      const Mat& M = defaults[e.pass][e.slot];
+      f.out[0] = unit_phase(M[0] * pend[q][0]);
+      f.out[1] = unit_phase(M[3] * pend[q][1]);
+      pend[q] = {f.out[0], f.out[1]};
+    } else if (s.frame == FRAME_ABSORB) {
+      const Mat& M = defaults[e.pass][e.slot];
+      pend[q] = {unit_phase(pend[q][0] * M[0]), unit_phase(pend[q][1] * M[3])};
+    }
+  });
+  return fr;
+}
+
+Mat frame_matrix(const Slot& s, const SlotFrame& f, const Mat& M) {
+  Mat V = M;
+  if (s.frame == FRAME_ABSORB) {
+    V = mat_identity(2);
+  } else if (s.type == DOP_M1) {
+    for (int r = 0; r < 2; ++r)
+      for (int c = 0; c < 2; ++c) V[r * 2 + c] *= f.in[0][c];
+    if (s.frame == FRAME_REAL_DIAG || s.frame == FRAME_OVERRIDE_ONLY) {
+      for (int r = 0; r < 2; ++r)
+        for (int c = 0; c < 2; ++c) V[r * 2 + c] *= std::conj(f.out[r]);
+      // the default matrix now has a real diagonal (up to rounding, which the
+      // kernels' real-diagonal form drops); an override's is general
+    }
+  } else if (s.type == DOP_M2) {
+    for (int r = 0; r < 4; ++r)
+      for (int c = 0; c < 4; ++c) V[r * 4 + c] *= f.in[0][c & 1] * f.in[1][c >> 1];
+  }
+  return V;
+}
+
 ptsbe_status build_plan(const ptsbe_circuit* c, const ptsbe_noise_model* nm, const ptsbe_plan_opts* o,
                         std::shared_ptr<Plan>* out) {
   if (!c || !out) return fail(PTSBE_E_ARG, "null circuit or output handle");
@@ -721,6 +853,8 @@ ptsbe_status build_plan(const ptsbe_circuit* c, const ptsbe_noise_model* nm, con
   if (o && (o->flags & 7u)) P.min_fill = (int)(o->flags & 7u);
   P.use_jit = !(o && (o->flags & PTSBE_PLAN_NO_COMPILE));
   P.half_tile_lds = o && (o->flags & PTSBE_PLAN_HALF_TILE_LDS);
+  P.waves = o ? (int)((o->flags >> PTSBE_PLAN_WAVES_SHIFT) & 15u) : 0;
+  if (P.waves > 8) return fail(PTSBE_E_ARG, "waves per SIMD must be 0 (default) or 1..8");
   P.jit = std::make_shared<JitProgram>();
   // channels
   uint32_t n_ch = nm ? nm->n_channels : 0;
@@ -851,6 +985,7 @@ ptsbe_status build_plan(const ptsbe_circuit* c, const ptsbe_noise_model* nm, con
   }
   ptsbe_status st = schedule(P, P.steps, P.passes, P.exec, P.site_slots, true, true, P.tile_bits);
   if (st != PTSBE_OK) return st;
+  if (!(o && (o->flags & PTSBE_PLAN_NO_PHASE_FRAMES))) assign_frames(P.n, P.steps, P.passes, P.exec);
   // Reverse-sweep program of the adjoint gradient: the steps in reverse order,
   // each applied as its adjoint, with a DOT marker (Im<lambda|P|psi>) just before
   // un-applying every parametrised rotation.  Only for circuits without

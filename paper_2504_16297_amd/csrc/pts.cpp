@@ -367,6 +367,11 @@ static void program_tables(const Plan& P, const std::vector<Step>& steps, const 
   std::vector<cd> pool;
   std::vector<uint32_t> slot_base(NP);
   std::map<int, int> empty;
+  std::vector<std::vector<Mat>> defaults(NP);
+  for (uint32_t p = 0; p < NP; ++p)
+    for (const Slot& s : prog_passes[p].slots)
+      defaults[p].push_back(slot_matrix(P, steps, s, pv.empty() ? nullptr : pv.data(), empty));
+  const std::vector<std::vector<SlotFrame>> frames = slot_frames(P.n, prog_passes, prog_exec, defaults);
   for (uint32_t p = 0; p < NP; ++p) {
     const Pass& ps = prog_passes[p];
     DPass& d = passes[p];
@@ -381,8 +386,8 @@ static void program_tables(const Plan& P, const std::vector<Step>& steps, const 
     for (size_t j = 0; j < ps.oq.size(); ++j) d.oq[j] = (uint8_t)ps.oq[j];
     ops.insert(ops.end(), ps.ops.begin(), ps.ops.end());
     slot_base[p] = (uint32_t)slot_default.size();
-    for (const Slot& s : ps.slots) {
-      Mat M = slot_matrix(P, steps, s, pv.empty() ? nullptr : pv.data(), empty);
+    for (size_t si = 0; si < ps.slots.size(); ++si) {
+      const Mat M = frame_matrix(ps.slots[si], frames[p][si], defaults[p][si]);
       slot_default.push_back((uint32_t)pool.size());
       pool.insert(pool.end(), M.begin(), M.end());
     }
@@ -407,7 +412,9 @@ static void program_tables(const Plan& P, const std::vector<Step>& steps, const 
       if (it != dedupe.end()) {
         off = it->second;
       } else {
-        Mat M = slot_matrix(P, steps,prog_passes[p].slots[s], pv.empty() ? nullptr : pv.data(), kv.second);
+        const Slot& sl = prog_passes[p].slots[s];
+        const Mat M = frame_matrix(sl, frames[p][s], slot_matrix(P, steps, sl, pv.empty() ? nullptr : pv.data(),
+                                                                  kv.second));
         off = (uint32_t)pool.size();
         pool.insert(pool.end(), M.begin(), M.end());
         dedupe.emplace(dk, off);

@@ -78,14 +78,32 @@ ptsbe_status hip_check(hipError_t e, const char* what) {
 
 // Useful FLOPs per amplitude of a pass: 14 per 2x2 matrix (two complex
 // products and a sum per output), 30 per 4x4, 6 per diagonal.
+// Useful real floating-point operations per amplitude of a pass, on the path
+// a block without overrides takes: a 2x2 complex matrix makes each output from
+// two complex products and a sum (14); with a real diagonal (phase frame) one
+// product is real times complex (10); a 4x4 costs 30, a diagonal 6, a
+// measure-reset 2; slots merged into a phase frame, signs and relabellings 0.
+static double m1_flops(const Pass& ps, int slot) {
+  switch (ps.slots[slot].frame) {
+    case FRAME_REAL_DIAG: return 10;
+    case FRAME_ABSORB:
+    case FRAME_OVERRIDE_ONLY: return 0;
+    default: return 14;
+  }
+}
+
 double pass_flops_per_amp(const Pass& ps) {
   double f = 0;
   for (const DOp& op : ps.ops) {
     switch (op.type) {
-      case DOP_M1: f += 14; break;
-      case DOP_M1G: f += 14 * __builtin_popcount(op.mask & 15u); break;
+      case DOP_M1: f += m1_flops(ps, op.slot[0]); break;
+      case DOP_M1G:
+        for (int j = 0; j < 4; ++j)
+          if ((op.mask >> j) & 1) f += m1_flops(ps, op.slot[j]);
+        break;
       case DOP_M2: f += 30; break;
-      case DOP_D1: case DOP_D2: f += 6; break;
+      case DOP_D1: f += ps.slots[op.slot[0]].frame == FRAME_ABSORB ? 0 : 6; break;
+      case DOP_D2: f += 6; break;
       case DOP_MR: f += 2; break;
       default: break;
     }

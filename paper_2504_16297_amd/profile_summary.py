@@ -9,7 +9,7 @@ project, and read those summaries back.
 dispatches of the named kernel and scales each by what the same counter reads
 for a plain device copy of known size (the copy's bytes divided by its
 counter), giving HBM bytes per dispatch.  The summary records the SHA-256 of
-the kernel sources (generic kernels and pass generator) the counters were
+the kernel sources (generic kernels, pass generator, planner) the counters were
 taken with, so a reader can tell when the
 kernel has changed since.
 """
@@ -22,8 +22,9 @@ import re
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-# the tile-pass kernels: the generic kernels and the generator of the compiled ones
-KERNEL_SOURCES = [os.path.join(HERE, "csrc", "kernels.hip"), os.path.join(HERE, "csrc", "jit.cpp")]
+# the tile-pass kernels: the generic kernels, the generator of the compiled
+# ones and the planner whose programs (and phase frames) it compiles
+KERNEL_SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "jit.cpp", "plan.cpp")]
 
 
 def kernel_source_sha():

@@ -19,14 +19,6 @@ OV_DT = np.dtype([("slot", "<u4"), ("off", "<u4")])
 EXEC_DT = np.dtype([("pass", "<u4"), ("nq", "<u4"), ("q", "<u4", 16), ("idx", "<u4", 16)])
 M1, M2, D1, D2, MR, DSIGN, PHASE, M1G, SFLIP, DOT = 1, 2, 3, 4, 5, 6, 7, 8, 9, 10
 
-# Useful real floating-point operations per state amplitude of each op type:
-# a 2x2 complex matrix on a pair makes each output from two complex products
-# and one complex sum (2 x 6 + 2 = 14); a 4x4 from four products and three sums
-# (4 x 6 + 3 x 2 = 30); a diagonal is one complex product (6).  Sign flips,
-# relabellings (PHASE) and identity positions of grouped ops count zero.
-FLOPS_PER_AMP = {M1: 14, M2: 30, D1: 6, D2: 6, MR: 2}
-
-
 def _ptr(params):
     if params is None or not len(params):
         return None, None
@@ -78,26 +70,3 @@ def export_adjoint_tables(ts, params):
                                                C.byref(nd), dp.ctypes.data))
     del keep
     return decode(ts, buf, offs), dp[:nd.value]
-
-
-def pass_flops_per_amp(tables):
-    """Useful FLOPs per state amplitude of every pass (the same for every
-    trajectory: overrides swap matrices, never op types)."""
-    out = np.zeros(len(tables["passes"]), dtype=np.float64)
-    for p, ps in enumerate(tables["passes"]):
-        f = 0
-        for op in tables["ops"][ps["op_begin"]:ps["op_begin"] + ps["n_ops"]]:
-            ty = int(op["type"])
-            if ty == M1G:
-                f += FLOPS_PER_AMP[M1] * bin(int(op["mask"]) & 15).count("1")
-            else:
-                f += FLOPS_PER_AMP.get(ty, 0)
-        out[p] = f
-    return out
-
-
-def step_pass_flops(tables, n, n_traj):
-    """Useful FLOPs of all tile passes of one run over n_traj trajectories."""
-    per_amp = pass_flops_per_amp(tables)
-    used = [int(e["pass"]) for e in tables["exec"] if int(e["pass"]) != 0xFFFFFFFF]
-    return float(np.sum(per_amp[used])) * float(1 << n) * n_traj

@@ -51,6 +51,9 @@ static inline double __shfl_xor(double v, int mask, int width) {
   return r;
 }
 static inline long long __double_as_longlong(double f) { long long u; std::memcpy(&u, &f, 8); return u; }
+static inline uint32_t atomicOr(uint32_t* p, uint32_t v) { return __atomic_fetch_or(p, v, __ATOMIC_SEQ_CST); }
+// every lane of a wave reads the same LDS word after a barrier where the kernels call it
+static inline uint32_t __builtin_amdgcn_readfirstlane(uint32_t v) { return v; }
 #define __global__
 #define __device__
 #define __forceinline__ inline

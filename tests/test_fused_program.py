@@ -104,3 +104,86 @@ def test_adjoint_program_hea():
     Er, Gr = ensemble_value_and_grad(circ, g["records"], w, params, zz_ring(7))
     assert abs(E - Er) <= 1e-10
     assert np.max(np.abs(G - Gr)) <= 1e-10 * max(1.0, np.max(np.abs(Gr)))
+
+
+def _slot_diag_imag(t):
+    """Largest |Im| of the diagonal of each 2x2 default slot matrix, per pass."""
+    out = []
+    for ps in t["passes"]:
+        ops = t["ops"][ps["op_begin"]:ps["op_begin"] + ps["n_ops"]]
+        for op in ops:
+            ty = int(op["type"])
+            js = [j for j in range(4) if (int(op["mask"]) >> j) & 1] if ty == 8 else ([0] if ty == 1 else [])
+            for j in js:
+                off = int(t["slot_default"][int(ps["slot_begin"]) + int(op["slots"][j])])
+                m = t["pool"][off:off + 4]
+                out.append(max(abs(m[0].imag), abs(m[3].imag)))
+    return np.asarray(out)
+
+
+def test_phase_frames_keep_states_and_make_real_diagonals():
+    """Phase frames (Sec. 3's trajectories are fixed circuits, so a diagonal
+    can be carried between two matrices of a qubit): the rewritten tables give
+    the same states as the plain ones and as the oracle, for trajectories with
+    overrides on rewritten slots, and most 2x2 slots of a brick circuit (every
+    U3 followed by another matrix on its qubit) end up with a real diagonal."""
+    from workloads.circuits import brick_circuit
+    import math
+    circ = brick_circuit(8, 6, np.random.default_rng(5), 0.05, 0.08, eps_sigma=0.02)
+    framed = P.ptsbe_plan(circ, precision="c128", tile_qubits=6)
+    plain = P.ptsbe_plan(circ, precision="c128", tile_qubits=6, phase_frames=False)
+    ts_f = P.ptsbe_sample_kraus(framed, "proportional", n_draws=16, total_shots=16, seed=4, cfg=2)
+    ts_p = P.ptsbe_sample_kraus(plain, "proportional", n_draws=16, total_shots=16, seed=4, cfg=2)
+    tf, tp = export_tables(ts_f), export_tables(ts_p)
+    imf, imp = _slot_diag_imag(tf), _slot_diag_imag(tp)
+    assert len(imf) == len(imp)
+    # 8 qubits x 6 layers of U3: all but the last matrix of each qubit are rewritten
+    assert np.sum(imf < 1e-12) >= 8 * 5
+    assert np.sum(imp < 1e-12) < np.sum(imf < 1e-12)
+    g = ts_f.get()
+    assert any(len(r) for r in g["records"])
+    sf, _ = run_program(tf, 8, len(g["m"]))
+    sp, _ = run_program(tp, 8, len(g["m"]))
+    assert max(float(np.max(np.abs(a - b))) for a, b in zip(sf, sp)) < 1e-12
+    _check(circ, framed, ts_f)
+
+
+def test_phase_frames_absorb_diagonals_and_flush_before_measure_reset():
+    """A diagonal gate between two matrices of its qubit is merged away (its
+    slot holds the identity), and no diagonal stays pending across a
+    measure-reset: the surface-code program (measure-resets between rounds)
+    still matches the oracle record by record."""
+    circ = {"n_qubits": 3, "channels": [{"name": "depolarizing", "nq": 1, "p": 0.2}], "rules": [],
+            "params": [], "ops": [
+                {"kind": "gate", "name": "H", "qubits": (0,), "params": ()},
+                {"kind": "gate", "name": "CNOT", "qubits": (0, 1), "params": ()},
+                {"kind": "gate", "name": "RZ", "qubits": (2,), "params": (0.3,)},
+                {"kind": "gate", "name": "CZ", "qubits": (1, 2), "params": ()},
+                {"kind": "gate", "name": "RZ", "qubits": (2,), "params": (0.7,)},
+                {"kind": "gate", "name": "CZ", "qubits": (0, 2), "params": ()},
+                {"kind": "gate", "name": "H", "qubits": (2,), "params": ()},
+                {"kind": "noise", "channel": 0, "qubits": (2,)},
+                {"kind": "gate", "name": "U3", "qubits": (1,), "params": (0.4, 0.1, 0.9)},
+                {"kind": "gate", "name": "RX", "qubits": (2,), "params": (0.5,)},
+            ]}
+    plan = P.ptsbe_plan(circ, precision="c128")
+    ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=8, total_shots=8, seed=1, cfg=1)
+    _check(circ, plan, ts)
+
+    def identity_slots(t):
+        ops = t["ops"]
+        n_id = 0
+        for op in ops:
+            if int(op["type"]) != 1:
+                continue
+            off = int(t["slot_default"][int(op["slots"][0])])
+            n_id += int(np.allclose(t["pool"][off:off + 4], [1, 0, 0, 1], atol=1e-15))
+        return n_id
+    plain = P.ptsbe_plan(circ, precision="c128", phase_frames=False)
+    ts_p = P.ptsbe_sample_kraus(plain, "proportional", n_draws=8, total_shots=8, seed=1, cfg=1)
+    # the two RZ slots on qubit 2 sit between matrices of that qubit
+    assert identity_slots(export_tables(ts)) == identity_slots(export_tables(ts_p)) + 2
+    wl = c3_workload(rounds=1)
+    plan3 = P.ptsbe_plan(wl["circuit"], precision="c128")
+    ts3 = P.ptsbe_sample_kraus(plan3, "most_likely", k_max=12, total_shots=12, seed=0, cfg=3)
+    _check(wl["circuit"], plan3, ts3)

@@ -332,3 +332,25 @@ def test_half_tile_register_changes(n, prec):
     err = max(float(np.max(np.abs(gpu[a] - ref[a]))) for a in range(len(ref)))
     log(f"  max|d| = {err:.2e}")
     assert err <= (1e-5 if prec == "c64" else 1e-12)
+
+
+@pytest.mark.parametrize("n,prec", [(14, "c64"), (12, "c128")])
+def test_phase_frames_match_plain_plan(n, prec):
+    """Brick circuit with coherent over-rotations: the plan in phase frames
+    (real-diagonal 2x2 form, override branch for trajectories with errors on
+    rewritten slots) and the plain plan give the oracle's states."""
+    from workloads import brick_circuit
+    log(f"[phase frames] n={n} {prec}")
+    circ = brick_circuit(n, 8, np.random.default_rng(90 + n), 0.02, 0.05, eps_sigma=0.05)
+    framed = P.ptsbe_plan(circ, precision=prec)
+    plain = P.ptsbe_plan(circ, precision=prec, phase_frames=False)
+    ts_f = P.ptsbe_sample_kraus(framed, "proportional", n_draws=20, total_shots=20, seed=7, cfg=2)
+    ts_p = P.ptsbe_sample_kraus(plain, "proportional", n_draws=20, total_shots=20, seed=7, cfg=2)
+    a = _states(framed, ts_f)
+    b = _states(plain, ts_p)
+    tol = 1e-5 if prec == "c64" else 1e-12
+    ref, _ = oracle_states(circ, ts_f.get()["records"])
+    err_f = max(float(np.max(np.abs(a[i] - ref[i]))) for i in range(len(ref)))
+    err_p = max(float(np.max(np.abs(b[i] - ref[i]))) for i in range(len(ref)))
+    log(f"  max|framed - oracle| = {err_f:.2e}, max|plain - oracle| = {err_p:.2e}")
+    assert err_f <= tol and err_p <= tol
