@@ -216,8 +216,9 @@ def main():
 def bench_c4(args):
     """The mixed-size batch: brick circuits of 24, 26 and 28 qubits (30 layers,
     p2 = 1e-2) with 256 / 64 / 16 proportional draws x 10^5 shots, run back to
-    back as one step; the per-shot baseline at 28 qubits; then one 33-qubit
-    trajectory x 10^6 shots (64 GiB state) timed on its own."""
+    back as one step; the per-shot baseline at 28 qubits; then one 33-qubit and
+    one 35-qubit trajectory x 10^6 shots (64 and 256 GiB states), each timed on
+    its own (the 35-qubit one only where the device has the memory)."""
     import numpy as np
     import torch
 
@@ -304,25 +305,34 @@ def bench_c4(args):
         del bws
     runs.clear()
     torch.cuda.empty_cache()
-    wl = c4_workload(33)
-    plan = P.ptsbe_plan(wl["circuit"], precision="c64")
-    ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=1, total_shots=10**6, seed=wl["seed"], cfg=wl["cfg"])
-    P.ptsbe_plan_compile(plan)
-    ws = torch.empty(P.ptsbe_workspace_size(plan, ts, mode="shots"), dtype=torch.uint8, device="cuda")
-    out = {"bits": torch.empty(10**6, dtype=torch.int64, device="cuda"),
-           "traj": torch.empty(10**6, dtype=torch.int32, device="cuda")}
-    P.ptsbe_run_batch(plan, ts, seed=wl["seed"], cfg=wl["cfg"], workspace=ws, out=out)
-    torch.cuda.synchronize()
-    tm = np.zeros(10)
-    t0 = time.perf_counter()
-    P.ptsbe_run_batch(plan, ts, seed=wl["seed"], cfg=wl["cfg"], workspace=ws, out=out, timing=tm)
-    torch.cuda.synchronize()
-    d33 = time.perf_counter() - t0
-    result["q33"] = {"shots": 10**6, "seconds": d33, "shots_per_s": 10**6 / d33, "passes": plan.info["n_passes"],
-                     "pass_ms": tm[0], "state_gib": (1 << 33) * 8 / 2**30,
-                     "pass_hbm_gbs": tm[6] / (tm[0] * 1e-3) / 1e9}
-    log(f"[bench c4] 33 qubits: {d33:.2f} s for 1e6 shots ({plan.info['n_passes']} passes, "
-        f"{tm[6] / (tm[0] * 1e-3) / 1e9:.0f} GB/s in the passes)")
+    for nq in (33, 35):
+        wl = c4_workload(nq)
+        plan = P.ptsbe_plan(wl["circuit"], precision="c64")
+        ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=1, total_shots=10**6, seed=wl["seed"],
+                                  cfg=wl["cfg"])
+        need = P.ptsbe_workspace_size(plan, ts, mode="shots")
+        if torch.cuda.mem_get_info()[0] < need + (1 << 30):
+            log(f"[bench c4] {nq} qubits: not enough device memory ({need / 2**30:.1f} GiB needed), skipped")
+            continue
+        P.ptsbe_plan_compile(plan)
+        ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+        out = {"bits": torch.empty(10**6, dtype=torch.int64, device="cuda"),
+               "traj": torch.empty(10**6, dtype=torch.int32, device="cuda")}
+        P.ptsbe_run_batch(plan, ts, seed=wl["seed"], cfg=wl["cfg"], workspace=ws, out=out)
+        torch.cuda.synchronize()
+        log(f"[bench c4] {nq} qubits: warm-up run done")
+        tm = np.zeros(10)
+        t0 = time.perf_counter()
+        P.ptsbe_run_batch(plan, ts, seed=wl["seed"], cfg=wl["cfg"], workspace=ws, out=out, timing=tm)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        result[f"q{nq}"] = {"shots": 10**6, "seconds": dt, "shots_per_s": 10**6 / dt,
+                            "passes": plan.info["n_passes"], "pass_ms": tm[0], "state_gib": (1 << nq) * 8 / 2**30,
+                            "pass_hbm_gbs": tm[6] / (tm[0] * 1e-3) / 1e9}
+        log(f"[bench c4] {nq} qubits: {dt:.2f} s for 1e6 shots ({plan.info['n_passes']} passes, "
+            f"{tm[6] / (tm[0] * 1e-3) / 1e9:.0f} GB/s in the passes)")
+        del ws, out
+        torch.cuda.empty_cache()
     print(json.dumps(result))
 
 

@@ -40,7 +40,7 @@ typedef enum {
     PTSBE_OK = 0,
     PTSBE_E_ARG = 1,            /* invalid argument: null pointer, bad qubit, size mismatch */
     PTSBE_E_NOT_CPTP = 2,       /* a channel violates sum_k K_k^dagger K_k = I (Sec. 2.2) beyond 1e-12 */
-    PTSBE_E_UNSUPPORTED = 3,    /* valid but not implemented (a non-unitary-mixture noise channel, n > 34) */
+    PTSBE_E_UNSUPPORTED = 3,    /* valid but not implemented (a non-unitary-mixture noise channel, n > 35) */
     PTSBE_E_CAPACITY = 4,       /* output capacity below the total shot count */
     PTSBE_E_OOM = 5,            /* workspace smaller than ptsbe_workspace_size() */
     PTSBE_E_DEVICE = 6,         /* a HIP call failed */
@@ -75,7 +75,7 @@ typedef struct {
 } ptsbe_op;
 
 typedef struct {
-    uint32_t n_qubits;          /* 1..34 */
+    uint32_t n_qubits;          /* 1..35 (35: a 256 GiB complex64 state) */
     uint32_t n_ops;
     const ptsbe_op* ops;
 } ptsbe_circuit;

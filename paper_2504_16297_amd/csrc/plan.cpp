@@ -834,7 +834,7 @@ ptsbe_status build_plan(const ptsbe_circuit* c, const ptsbe_noise_model* nm, con
   if (!c || !out) return fail(PTSBE_E_ARG, "null circuit or output handle");
   if (c->n_qubits < 1 || c->n_qubits > (uint32_t)kMaxQubits)
     return fail(c->n_qubits > (uint32_t)kMaxQubits ? PTSBE_E_UNSUPPORTED : PTSBE_E_ARG,
-                "n_qubits must be in 1..34");
+                "n_qubits must be in 1..35");
   if (c->n_ops && !c->ops) return fail(PTSBE_E_ARG, "null op array");
   auto plan = std::make_shared<Plan>();
   Plan& P = *plan;

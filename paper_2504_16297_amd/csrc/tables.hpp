@@ -9,7 +9,7 @@
 namespace ptsbe {
 
 constexpr int kMaxTileBits = 13;
-constexpr int kMaxQubits = 34;
+constexpr int kMaxQubits = 35;  // 2^35 complex64 = 256 GiB: one trajectory on one 288 GB GPU
 
 // Fused operation types inside a tile pass.
 enum DOpType : uint8_t {

@@ -60,6 +60,13 @@ def test_channel_checks():
     assert _status(P.ptsbe_plan, _one_gate(bad)) == E_NOT_CPTP
     # CPTP but not a unitary mixture: outside batched pre-trajectory sampling
     assert _status(P.ptsbe_plan, _one_gate({"name": "amplitude_damping", "gamma": 0.2})) == E_UNSUPPORTED
+    # up to 35 qubits (a 2^35 complex64 state is 256 GiB)
+    big = {"n_qubits": 35, "ops": [{"kind": "gate", "name": "H", "qubits": (34,), "params": ()}], "channels": [],
+           "rules": [], "params": []}
+    plan35 = P.ptsbe_plan(big)
+    ts35 = P.ptsbe_trajset_from_records(plan35, [()], [10])
+    assert P.ptsbe_workspace_size(plan35, ts35, mode="shots") >= 8 << 35
+    assert _status(P.ptsbe_plan, dict(big, n_qubits=36)) == E_UNSUPPORTED
     # a custom unitary mixture given as explicit Kraus operators is accepted
     X = np.array([[0, 1], [1, 0]])
     ok = {"kraus": [np.sqrt(0.9) * np.eye(2), np.sqrt(0.1) * X]}

@@ -1,4 +1,4 @@
-"""Large-state parity (24-33 qubits), where the full oracle state is out of
+"""Large-state parity (24-35 qubits), where the full oracle state is out of
 reach: product-state circuits whose amplitudes the oracle computes one by one
 (oracle.statevector.product_factors), shot marginals against the closed form,
 expectation values of Z strings against the closed form, and, for the
@@ -89,6 +89,39 @@ def test_product_33q_expectations_and_shots():
     zs = _marginal_check(bits.astype(np.int64), f, n, 1000000)
     log(f"  worst single-qubit marginal deviation {zs:.2f} sigma")
     assert zs < 5.5
+
+
+def test_product_35q_on_one_gpu():
+    """One 35-qubit trajectory: a 256 GiB complex64 state on one GPU (the
+    paper's statevector scale, which took four 80 GB GPUs), the FP64 CDF
+    written in place over it; 10^6 shots whose single-qubit marginals, and
+    the <Z Z> value, match the product closed form."""
+    n = 35
+    circ = product_circuit(n, 2, np.random.default_rng(35), 0.0)
+    plan = P.ptsbe_plan(circ)
+    ts = P.ptsbe_trajset_from_records(plan, [()], [1000000])
+    need = P.ptsbe_workspace_size(plan, ts, mode="shots") + 16 * 1000000
+    free, _ = torch.cuda.mem_get_info()
+    log(f"[35q product] workspace {need / 2**30:.1f} GiB, device free {free / 2**30:.1f} GiB")
+    if free < need + (1 << 30):
+        pytest.skip("not enough device memory for a 2^35 complex64 state")
+    f = product_factors(circ, ())
+    s = P.ptsbe_run_batch(plan, ts, mode="shots", seed=2, cfg=4)
+    torch.cuda.synchronize()
+    bits = s["bits"].cpu().numpy()
+    del s
+    torch.cuda.empty_cache()
+    assert np.all(bits >= 0) and np.all(bits < (1 << n))
+    zs = _marginal_check(bits.astype(np.int64), f, n, 1000000)
+    log(f"  passes={plan.info['n_passes']} worst single-qubit marginal deviation {zs:.2f} sigma")
+    assert zs < 5.5
+    z = (np.abs(f[:, 0]) ** 2 - np.abs(f[:, 1]) ** 2)
+    obs = [(1.0, (3, 34))]
+    r = P.ptsbe_run_batch(plan, ts, mode="expectation", observable=obs)
+    torch.cuda.synchronize()
+    got = float(r["expval"].cpu().numpy()[0])
+    log(f"  <Z3 Z34> = {got:.8f}, closed form {z[3] * z[34]:.8f}")
+    assert abs(got - z[3] * z[34]) <= 1e-5
 
 
 @pytest.mark.parametrize("n", [24, 28])

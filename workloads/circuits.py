@@ -232,9 +232,9 @@ def c3_workload(seed=0, k_max=4096, total_shots=10**9, rounds=5):
 
 def c4_workload(n, seed=0, shots_per_draw=10**5):
     """Brick circuit at n in {24, 26, 28} (30 layers, p2=1e-2, p1=0) with
-    256/64/16 draws x 1e5 shots; n = 33 is one draw x 1e6 shots."""
-    draws = {24: 256, 26: 64, 28: 16, 33: 1}.get(n, 16)
-    if n == 33:
+    256/64/16 draws x 1e5 shots; n = 33 and 35 are one draw x 1e6 shots."""
+    draws = {24: 256, 26: 64, 28: 16, 33: 1, 35: 1}.get(n, 16)
+    if n in (33, 35):
         shots_per_draw = 10**6
     circ = brick_circuit(n, 30, _rng(seed, 4), 0.0, 1e-2)
     return {"name": f"C4 {n}q x 30 brick layers, {draws} draws x {shots_per_draw} shots, complex64",
