@@ -184,6 +184,23 @@ def main():
               "plan_ms": t_plan * 1e3, "pts_ms": t_pts * 1e3, "compile_s": t_compile,
               "compiled_kernels": n_kernels}
 
+    # distinct shots of the last step (Fig. 4's unique fraction), outside the timed steps
+    uws = torch.empty(P.ptsbe_unique_workspace_size(ts), dtype=torch.uint8, device="cuda")
+    P.ptsbe_unique_shots(ts, out["bits"], workspace=uws, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u = P.ptsbe_unique_shots(ts, out["bits"], workspace=uws, pairs=True, stream=stream)
+    torch.cuda.synchronize()
+    dt_u = time.perf_counter() - t0
+    uniq = u["unique"].cpu().numpy().astype(np.float64)
+    mm = np.asarray(g["m"], dtype=np.float64)
+    result["distinct_shots"] = {"unique_fraction_of_all_shots": float(uniq.sum() / max(mm.sum(), 1.0)),
+                                "mean_unique_fraction_per_trajectory": float(np.mean(uniq[mm > 0] / mm[mm > 0])),
+                                "ms": dt_u * 1e3, "with_pairs": True}
+    log(f"[bench] distinct shots: {uniq.sum() / mm.sum():.3f} of all shots are distinct within their "
+        f"trajectory ({dt_u * 1e3:.2f} ms with (index, count) pairs)")
+    del uws, u
+
     if not args.no_baseline:
         nb = args.baseline_shots
         tb = P.ptsbe_sample_kraus(plan, "per_shot", n_draws=nb, seed=wl["seed"], cfg=wl["cfg"])

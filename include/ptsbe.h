@@ -351,6 +351,28 @@ ptsbe_status ptsbe_trajset_adjoint_tables(ptsbe_trajset_t ts, const double* para
  * by ptsbe_run_batch: PTSBE_OK or PTSBE_E_NONDET_MEASURE. */
 ptsbe_status ptsbe_run_status(ptsbe_plan_t plan, const void* d_ws, void* stream);
 
+/* Distinct shots (Sec. 4, Fig. 4: the fraction of a trajectory's shots that
+ * are distinct; its expectation is sum_x 1 - (1 - p_x)^m).  For the shots of
+ * ts as ptsbe_run_batch wrote them (d_bits: device, total_shots entries, uint32
+ * for n <= 32 qubits, else uint64, trajectory alpha's m_alpha shots contiguous
+ * in trajectory order): d_unique (device, n_traj uint64) receives each
+ * trajectory's number of distinct basis indices; optionally d_pair_index (same
+ * width and length as d_bits) and d_pair_count (device, total_shots uint32)
+ * receive, from trajectory alpha's first shot position on, its distinct
+ * indices in order of first appearance in its shots with their shot counts
+ * (entries past d_unique[alpha] within its range are left untouched).  One
+ * open-addressing hash table per trajectory lives in the caller's workspace
+ * (256-byte aligned, size from ptsbe_unique_workspace_size: max_batch
+ * consecutive trajectories at once, 0 = all); trajectories are processed in the
+ * largest batches that fit.  Results do not depend on thread scheduling.
+ * Errors: PTSBE_E_ARG (null outputs, misaligned or too small workspace),
+ * PTSBE_E_UNSUPPORTED (2^32 or more shots in one trajectory).  The call only
+ * enqueues work on `stream`; host staging lives in ts until its next call, so
+ * calls on one trajectory set must not overlap. */
+ptsbe_status ptsbe_unique_workspace_size(ptsbe_trajset_t ts, uint32_t max_batch, size_t* bytes);
+ptsbe_status ptsbe_unique_shots(ptsbe_trajset_t ts, const void* d_bits, void* d_ws, size_t ws_bytes,
+                                uint64_t* d_unique, void* d_pair_index, uint32_t* d_pair_count, void* stream);
+
 /* Adjoint gradient of E(theta) = sum_alpha w_alpha <psi_alpha|O|psi_alpha>,
  * w_alpha = count_alpha / sum count (for unitary-mixture noise w does not depend
  * on theta): forward preparation, lambda = O psi, then a reverse sweep that

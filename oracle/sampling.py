@@ -8,6 +8,8 @@ u_j = (word_j >> 11) 2^-53 from the stream [seed, key1(SAMPLER, cfg, alpha)]
 u_j * CDF[-1], side='right'), N - 1): the inverse-CDF reading of
 index(r, {p}) in Algorithm 1, which never selects a zero-probability x.
 Shots come out chunk by chunk, ascending in u within a chunk.
+`distinct` lists a trajectory's distinct shot values with their counts and
+`expected_distinct` gives the closed-form expectation of their number.
 """
 
 import math
@@ -58,3 +60,30 @@ def boundary_distance(c, u):
     lo = np.where(pos > 0, cn[np.maximum(pos - 1, 0)], 0.0)
     hi = np.where(pos < cn.size, cn[np.minimum(pos, cn.size - 1)], 1.0)
     return np.minimum(np.abs(u - lo), np.abs(hi - u))
+
+
+def distinct(shots):
+    """Distinct values of one trajectory's shots (Sec. 4, Fig. 4: the unique
+    fraction is len(values) / len(shots)), in order of first appearance, with
+    how often each occurs: written out as a loop over the shots."""
+    first = {}
+    values, counts = [], []
+    for x in np.asarray(shots).tolist():
+        j = first.get(x)
+        if j is None:
+            first[x] = len(values)
+            values.append(x)
+            counts.append(1)
+        else:
+            counts[j] += 1
+    return np.asarray(values, dtype=np.int64), np.asarray(counts, dtype=np.int64)
+
+
+def expected_distinct(p, m):
+    """E[#distinct values among m iid draws from p] = sum_x 1 - (1 - p_x)^m
+    (each x is missed by all m draws with probability (1 - p_x)^m)."""
+    p = np.asarray(p, dtype=np.float64)
+    if m == 0:
+        return 0.0
+    with np.errstate(divide="ignore"):
+        return float(np.sum(-np.expm1(m * np.log1p(-p))))

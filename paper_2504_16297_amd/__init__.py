@@ -16,7 +16,8 @@ from . import _lib as L
 from ._lib import PtsbeError, lib, check
 
 __all__ = ["ptsbe_plan", "ptsbe_plan_compile", "ptsbe_sample_kraus", "ptsbe_trajset_from_records",
-           "ptsbe_workspace_size", "ptsbe_run_batch", "ptsbe_run_status", "ptsbe_adjoint_grad", "std_gate",
+           "ptsbe_workspace_size", "ptsbe_run_batch", "ptsbe_run_status", "ptsbe_unique_workspace_size",
+           "ptsbe_unique_shots", "ptsbe_adjoint_grad", "std_gate",
            "std_channel", "Plan", "TrajSet", "RunGraph", "PtsbeError", "tag_id"]
 
 
@@ -410,6 +411,37 @@ class RunGraph:
 def ptsbe_run_status(plan, workspace, stream=None):
     import torch
     check(lib().ptsbe_run_status(plan.handle, C.c_void_p(workspace.data_ptr()), _stream(torch, stream)))
+
+
+def ptsbe_unique_workspace_size(ts, max_batch=0):
+    n = C.c_size_t()
+    check(lib().ptsbe_unique_workspace_size(ts.handle, int(max_batch), C.byref(n)))
+    return n.value
+
+
+def ptsbe_unique_shots(ts, bits, workspace=None, max_batch=0, pairs=False, stream=None):
+    """Distinct basis indices among each trajectory's shots (``bits``: the device
+    shot buffer of a run of ``ts``).  Returns {"unique": int64 tensor [n_traj]}
+    and with ``pairs`` also "index" (dtype of ``bits``) and "count" (int32),
+    indexed like the shots: trajectory a's distinct indices in order of first
+    appearance, with their counts, from its first shot position on."""
+    import torch
+    dev = bits.device
+    B = ts.n_traj
+    ws = workspace
+    if ws is None:
+        ws = torch.empty(max(1, ptsbe_unique_workspace_size(ts, max_batch)), dtype=torch.uint8, device=dev)
+    uniq = torch.empty(max(1, B), dtype=torch.int64, device=dev)
+    out = {"unique": uniq[:B]}
+    pi = pc = None
+    if pairs:
+        pi = torch.zeros_like(bits)
+        pc = torch.zeros(bits.numel(), dtype=torch.int32, device=dev)
+        out["index"], out["count"] = pi, pc
+    check(lib().ptsbe_unique_shots(ts.handle, C.c_void_p(bits.data_ptr()), C.c_void_p(ws.data_ptr()), ws.numel(),
+                                   C.c_void_p(uniq.data_ptr()), C.c_void_p(pi.data_ptr() if pi is not None else 0),
+                                   C.c_void_p(pc.data_ptr() if pc is not None else 0), _stream(torch, stream)))
+    return out
 
 
 def ptsbe_adjoint_grad(plan, ts, params, observable, workspace=None, max_batch=0, stream=None):

@@ -106,6 +106,9 @@ _SIGS = {
                                   C.c_size_t, C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p,
                                   C.c_void_p]),
     "ptsbe_run_status": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ptsbe_unique_workspace_size": (C.c_int, [C.c_void_p, C.c_uint32, C.POINTER(C.c_size_t)]),
+    "ptsbe_unique_shots": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_void_p]),
     "ptsbe_graph_create": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(RunOpts), C.c_void_p,
                                      C.c_size_t, C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p,
                                      C.c_void_p, C.POINTER(C.c_void_p)]),

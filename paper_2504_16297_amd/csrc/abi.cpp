@@ -287,6 +287,23 @@ ptsbe_status ptsbe_run_status(ptsbe_plan_t plan, const void* d_ws, void* stream)
   })
 }
 
+ptsbe_status ptsbe_unique_workspace_size(ptsbe_trajset_t ts, uint32_t max_batch, size_t* bytes) {
+  FENCE({
+    if (!ts || !bytes) return fail(PTSBE_E_ARG, "null argument");
+    return unique_workspace_size(*ts->ts, max_batch, bytes);
+  })
+}
+
+ptsbe_status ptsbe_unique_shots(ptsbe_trajset_t ts, const void* d_bits, void* d_ws, size_t ws_bytes,
+                                uint64_t* d_unique, void* d_pair_index, uint32_t* d_pair_count, void* stream) {
+  FENCE({
+    if (!ts) return fail(PTSBE_E_ARG, "null trajectory set");
+    std::lock_guard<std::mutex> lk(ts->ts->mu);
+    return unique_shots(*ts->ts, d_bits, d_ws, ws_bytes, d_unique, d_pair_index, d_pair_count,
+                        reinterpret_cast<hipStream_t>(stream));
+  })
+}
+
 ptsbe_status ptsbe_adjoint_grad(ptsbe_plan_t plan, ptsbe_trajset_t ts, const double* params, const double* obs_coef,
                                 const uint64_t* obs_zmask, uint32_t n_terms, void* d_ws, size_t ws_bytes,
                                 double* d_expval, double* d_grad, void* stream) {

@@ -174,6 +174,7 @@ struct TrajSet {
   std::vector<uint8_t> adj_aux;    // host staging of weights and the dot -> parameter map
   std::vector<uint32_t> route_host; // host staging of prefix-sharing launch routes (src, dst pairs)
   std::vector<uint32_t> route_off;
+  std::vector<uint64_t> uq_host;    // host staging of the distinct-shot pass's offset arrays
 };
 
 // Matrix helpers
@@ -208,6 +209,11 @@ ptsbe_status build_plan(const ptsbe_circuit* c, const ptsbe_noise_model* nm,
 ptsbe_status build_tables(TrajSet& ts, const double* params, uint32_t chunk);
 // Device tables of the adjoint (reverse-sweep) program, cached in ts.
 ptsbe_status build_adj_tables(TrajSet& ts, const double* params);
+
+// Distinct shots per trajectory and (basis index, count) pairs (unique.hip).
+ptsbe_status unique_workspace_size(const TrajSet& ts, uint32_t max_batch, size_t* bytes);
+ptsbe_status unique_shots(TrajSet& ts, const void* d_bits, void* d_ws, size_t ws_bytes, uint64_t* d_unique,
+                          void* d_pair_index, uint32_t* d_pair_count, hipStream_t s);
 
 }  // namespace ptsbe
 

@@ -124,6 +124,23 @@ def test_adjoint_workspace_query_runs_on_host():
     assert one >= 2 * state
 
 
+def test_distinct_shot_queries_and_checks():
+    plan = P.ptsbe_plan({"n_qubits": 12, "ops": [], "channels": [], "rules": [], "params": []})
+    ts = P.ptsbe_trajset_from_records(plan, [(), (), ()], [10, 0, 5000])
+    whole = P.ptsbe_unique_workspace_size(ts)
+    one = P.ptsbe_unique_workspace_size(ts, max_batch=1)
+    assert whole > one > 0
+    # tables: a power of two >= 2 min(m, 2^n) slots of 16 bytes per trajectory
+    assert whole >= (32 + 2 + 8192) * 16      # 5000 shots of a 2^12 state: at most 4096 distinct
+    lib = P.lib()
+    null = C.c_void_p(0)
+    # no distinct-count output
+    assert lib.ptsbe_unique_shots(ts.handle, C.c_void_p(256), null, 0, null, null, null, null) == E_ARG
+    # workspace too small: rejected before any device work
+    assert lib.ptsbe_unique_shots(ts.handle, C.c_void_p(256), null, 0, C.c_void_p(256), null, null, null) == E_ARG
+    assert b"workspace" in lib.ptsbe_last_error()
+
+
 def test_workspace_query_needs_no_outputs():
     circ = hea_circuit(6, 2, np.random.default_rng(0), 0.02)
     plan = P.ptsbe_plan(circ)
