@@ -65,12 +65,12 @@ def cpu_baseline(wl, g, budget_s=12.0):
                       f"extrapolated linearly to the whole job"}
 
 
-def measured_traffic():
+def measured_traffic(plan):
     """HBM bytes per tile-pass dispatch from the committed counter summary, or
-    None when the kernel source has changed since the counters were taken."""
-    from paper_2504_16297_amd.profile_summary import kernel_source_sha, read_traffic
+    None when the plan's kernels have changed since the counters were taken."""
+    from paper_2504_16297_amd.profile_summary import kernel_fingerprint, read_traffic
     r = read_traffic(TRAFFIC_SUMMARY)
-    if r is None or r[1] != kernel_source_sha():
+    if r is None or r[1] != kernel_fingerprint(plan):
         return None
     return r[0]
 
@@ -83,12 +83,21 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-baseline", action="store_true", help="skip the per-shot GPU baseline")
     ap.add_argument("--baseline-shots", type=int, default=512)
+    ap.add_argument("--fingerprint", action="store_true",
+                    help="only print the kernel fingerprint of the 20-qubit workload's plan (host only)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 2 GiB device copy (calibrates FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--workload", default="c2", choices=["c2", "c4", "c5"],
                     help="c2: the 20-qubit headline workload; c4: the 24/26/28-qubit mixed batch and the "
-                         "33-qubit trajectory; c5: the adjoint gradient of the 16-qubit ansatz")
+                         "33- and 35-qubit trajectories; c5: the adjoint gradient of the 16-qubit ansatz")
     args = ap.parse_args()
+    if args.fingerprint:
+        import paper_2504_16297_amd as P
+        from paper_2504_16297_amd.profile_summary import kernel_fingerprint
+        from workloads import c2_workload
+        wl = c2_workload()
+        print(kernel_fingerprint(P.ptsbe_plan(wl["circuit"], precision=wl["precision"])))
+        return
     if args.copy_probe:
         import torch
         n = 1 << 28                      # 2^28 float64 = 2 GiB read + 2 GiB written per copy
@@ -173,7 +182,7 @@ def main():
               "config": {"workload": wl["name"], "n_qubits": 20, "layers": 40, "draws": pts["n_draws"],
                          "unique_trajectories": B, "total_shots": S, "parallelism": "single GPU, batched"},
               "roofline": {"bound": "alu", "achieved": tflops, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                           "frac": tflops / FP32_PEAK_TFLOPS, "traffic": measured_traffic(),
+                           "frac": tflops / FP32_PEAK_TFLOPS, "traffic": measured_traffic(plan),
                            "kernel": "ptsbe_pass_* (compiled fused tile passes)", "avg_launch_ms": pass_ms,
                            "flops_per_launch": pass_flops, "bytes_per_launch": pass_bytes,
                            "hbm": {"achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -154,6 +154,11 @@ typedef struct {
  * 4096-amplitude tile (32 KiB in complex64) in LDS, so up to 5 workgroups fit
  * a compute unit. */
 #define PTSBE_PLAN_WAVES_SHIFT 8u
+/* Replace every channel that is not a unitary mixture (amplitude damping, ...)
+ * by its Pauli twirl (see ptsbe_pauli_twirl), which is: Pauli-twirled noise
+ * models, one of the tailored error models Sec. 1 names.  Without the flag such
+ * channels are rejected (PTSBE_E_UNSUPPORTED). */
+#define PTSBE_PLAN_TWIRL 64u
 
 typedef struct ptsbe_plan_s* ptsbe_plan_t;
 typedef struct ptsbe_trajset_s* ptsbe_trajset_t;
@@ -197,6 +202,13 @@ ptsbe_status ptsbe_plan_pass_source(ptsbe_plan_t plan, uint32_t pass, uint32_t a
  * qubits[2*n_sites] (second entry 0xffffffff for 1-qubit sites); either may be NULL. */
 ptsbe_status ptsbe_plan_get_sites(ptsbe_plan_t plan, uint32_t* offsets, double* probs,
                                   uint32_t* qubits);
+/* Where each noise site comes from: op_index[s] = the circuit op it follows
+ * (AFTER_TAG), precedes (BEFORE_MEASURE) or is (an explicit NOISE op), or
+ * 0xffffffff for BEFORE_READOUT sites; tag[s] = that op's tag (0 otherwise);
+ * origin[s] = PTSBE_SITE_*.  Each array has n_sites entries; any may be NULL. */
+enum { PTSBE_SITE_NOISE_OP = 0, PTSBE_SITE_AFTER_TAG = 1, PTSBE_SITE_BEFORE_MEASURE = 2,
+       PTSBE_SITE_BEFORE_READOUT = 3 };
+ptsbe_status ptsbe_plan_get_site_ops(ptsbe_plan_t plan, uint32_t* op_index, uint32_t* tag, uint32_t* origin);
 void ptsbe_plan_destroy(ptsbe_plan_t plan);
 
 /* ---------------------------------------------------- pre-trajectory sampling */
@@ -224,7 +236,22 @@ typedef struct {
     uint32_t cfg;               /* workload id, bits 48..55 of the second key word */
     uint32_t stream;            /* 0: default (1 = PTS, 3 = PER_SHOT); bits 56..63 of the key */
     double p_min, p_max;        /* probability band on p_alpha; both 0 = no band (Sec. 3.1) */
+    /* Selection criteria (Sec. 3.1: criteria on gate type, parity, location added
+     * to the choice of each operator in Algorithm 2).  kraus_allow: NULL, or one
+     * flag per (site, Kraus index) in the order of ptsbe_plan_get_sites; an
+     * operator k >= 1 whose flag is 0 is never chosen (its site keeps operator
+     * 0: in PROPORTIONAL / PER_SHOT a draw of it counts as operator 0, in
+     * ALG2_LITERAL its test is skipped, MOST_LIKELY never enumerates it).  Build
+     * the flags from ptsbe_plan_get_site_ops (the op and tag a site belongs
+     * to, i.e. gate type and location) and the Kraus index (error type). */
+    const uint8_t* kraus_allow;
+    uint32_t min_errors;        /* records with fewer operators k >= 1 are dropped */
+    uint32_t max_errors;        /* records with more are dropped; 0 = no limit */
+    uint32_t error_parity;      /* PTSBE_PARITY_*: keep records with any / an even / an odd number */
+    uint32_t reserved;
 } ptsbe_pts_opts;
+
+enum { PTSBE_PARITY_ANY = 0, PTSBE_PARITY_EVEN = 1, PTSBE_PARITY_ODD = 2 };
 
 /* Run a PTS algorithm (Sec. 3.1).  Draw t of PROPORTIONAL uses the Philox4x64-10
  * stream keyed [seed, stream<<56 | cfg<<48 | t]; its word s (NumPy's raw order:
@@ -391,6 +418,14 @@ ptsbe_status ptsbe_adjoint_grad(ptsbe_plan_t plan, ptsbe_trajset_t ts, const dou
                                 void* stream);
 
 /* ---------------------------------------------------------- gate library */
+
+/* Pauli twirl of a channel (nq 1 or 2; n_kraus operators, complex128 row-major
+ * interleaved, basis index bit j = the site's j-th qubit): averaging over
+ * conjugation by the 4^nq Pauli strings leaves the Pauli channel with
+ * probs[P] = sum_k |Tr(P^dag K_k)|^2 / 4^nq (the diagonal of the Pauli transfer
+ * matrix); string P has base-4 digit j (0 I, 1 X, 2 Y, 3 Z) on qubit j.  probs
+ * holds 4^nq doubles.  Errors: PTSBE_E_ARG (bad sizes), PTSBE_E_NOT_CPTP. */
+ptsbe_status ptsbe_pauli_twirl(uint32_t nq, const double* kraus, uint32_t n_kraus, double* probs);
 
 /* Standard gate matrices (complex128, row-major interleaved) for building
  * circuits: name in {U3, RX, RY, RZ, H, X, Y, Z, S, T, CZ, CNOT, SWAP};

@@ -16,7 +16,14 @@ Conventions (the paper names none):
 * pauli(px, py, pz): {sqrt(1-px-py-pz) I, sqrt(px) X, sqrt(py) Y, sqrt(pz) Z};
 * u3_mixture(p, angles): {sqrt(1-p) I, sqrt(p) U3(angles)};
 * amplitude_damping(gamma): {[[1,0],[0,sqrt(1-gamma)]], [[0,sqrt(gamma)],[0,0]]}.
-Index 0 is the no-error operator of every channel above.
+Index 0 is the no-error operator of every channel above.  A channel may also be
+given as {"kraus": [K_0, K_1, ...]}.
+
+Pauli twirl (Sec. 1 names Pauli-twirled noise among the tailored error
+models): averaging E over rho -> P^dag E(P rho P^dag) P for every Pauli string P
+leaves a Pauli channel whose probabilities are p_P = sum_k |Tr(P^dag K_k)|^2 /
+d^2.  Strings are indexed by base-4 digits (0 I, 1 X, 2 Y, 3 Z), digit j on the
+site's qubit j (matrix bit j, the least significant factor of np.kron).
 """
 
 import math
@@ -27,6 +34,8 @@ from .gates import PAULIS, u3, I2
 
 
 def kraus_ops(ch):
+    if "kraus" in ch:
+        return [np.asarray(k, dtype=np.complex128) for k in ch["kraus"]]
     name = ch["name"]
     if name == "depolarizing":
         p = ch["p"]
@@ -96,3 +105,43 @@ def unitary_mixture(kraus, tol=1e-12):
         probs.append(p)
         unitaries.append(K / math.sqrt(p) if p > 0 else np.eye(d, dtype=np.complex128))
     return probs, unitaries
+
+
+def pauli_string(index, nq):
+    """The Pauli string with base-4 digit j (0 I, 1 X, 2 Y, 3 Z) on matrix bit j."""
+    m = np.ones((1, 1), dtype=np.complex128)
+    for j in reversed(range(nq)):
+        m = np.kron(m, PAULIS[(index >> (2 * j)) & 3])
+    return m
+
+
+def pauli_twirl(kraus):
+    """p_P = sum_k |Tr(P^dag K_k)|^2 / d^2 for every Pauli string P (the definition)."""
+    d = kraus[0].shape[0]
+    nq = d.bit_length() - 1
+    out = np.zeros(4 ** nq)
+    for i in range(4 ** nq):
+        P = pauli_string(i, nq)
+        out[i] = sum(abs(np.trace(P.conj().T @ K)) ** 2 for K in kraus) / d ** 2
+    return out
+
+
+def twirled(ch):
+    """The channel dict of ch's Pauli twirl: sqrt(p_P) P for p_P > 0, in string order."""
+    K = kraus_ops(ch)
+    nq = K[0].shape[0].bit_length() - 1
+    p = pauli_twirl(K)
+    return {"kraus": [math.sqrt(p[i]) * pauli_string(i, nq) for i in range(p.size) if p[i] > 0],
+            "nq": nq}
+
+
+def pauli_transfer_diagonal(kraus):
+    """R_PP = Tr(P^dag E(P)) / d for every Pauli string P."""
+    d = kraus[0].shape[0]
+    nq = d.bit_length() - 1
+    out = np.zeros(4 ** nq)
+    for i in range(4 ** nq):
+        P = pauli_string(i, nq)
+        EP = sum(K @ P @ K.conj().T for K in kraus)
+        out[i] = np.trace(P.conj().T @ EP).real / d
+    return out

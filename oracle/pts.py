@@ -16,6 +16,12 @@ Samplers:
 * ``most_likely``    -- the records of highest joint probability ("error
   combinations whose joint probability falls above a given cutoff").
 
+Selection criteria (the checks Sec. 3.1 suggests adding where Algorithm 2
+chooses each operator: gate type, parity, location): ``allow`` is a set of
+(site, k) pairs; an operator outside it is never chosen (its site keeps
+operator 0).  ``keep_record`` drops records by their number of errors (a
+window and a parity); dropped draws do not count towards n_draws.
+
 Allocations:
 * ``multiplicity``   -- m_alpha = count_alpha * S / T, largest remainder.
 * ``reweight``       -- m_alpha proportional to p'_alpha = p_alpha / sum over the
@@ -40,10 +46,11 @@ def _categorical(u, probs):
     return min(k, len(probs) - 1)
 
 
-def proportional(site_probs, seed, cfg, n_draws, stream=STREAM_PTS, merge=True):
+def proportional(site_probs, seed, cfg, n_draws, stream=STREAM_PTS, merge=True, allow=None):
     """Return (records, counts) for ``n_draws`` proportional draws.
 
-    Draw t uses the stream [seed, key1(stream, cfg, t)]; word s is site s."""
+    Draw t uses the stream [seed, key1(stream, cfg, t)]; word s is site s.  A
+    drawn operator outside ``allow`` leaves its site at operator 0."""
     S = len(site_probs)
     index = {}
     records = []
@@ -53,7 +60,7 @@ def proportional(site_probs, seed, cfg, n_draws, stream=STREAM_PTS, merge=True):
         rec = []
         for s in range(S):
             k = _categorical(u[s], site_probs[s])
-            if k != 0:
+            if k != 0 and (allow is None or (s, k) in allow):
                 rec.append((s, k))
         rec = tuple(rec)
         if merge and rec in index:
@@ -65,10 +72,11 @@ def proportional(site_probs, seed, cfg, n_draws, stream=STREAM_PTS, merge=True):
     return records, counts
 
 
-def alg2_draw(site_probs, seed, cfg, t, stream=STREAM_PTS):
+def alg2_draw(site_probs, seed, cfg, t, stream=STREAM_PTS, allow=None):
     """One sample of Algorithm 2 as printed.  Words of stream t are consumed one
     per (s, k >= 1) pair in circuit order; r <= p_{s,k} keeps K_{s,k} if it is
-    compatible, i.e. site s has no operator yet (the first one kept wins)."""
+    compatible, i.e. site s has no operator yet (the first one kept wins), and
+    it passes the selection (in ``allow``)."""
     n_pairs = sum(len(p) - 1 for p in site_probs)
     u = uniforms(seed, key1(stream, cfg, t), n_pairs) if n_pairs else np.zeros(0)
     j = 0
@@ -78,19 +86,19 @@ def alg2_draw(site_probs, seed, cfg, t, stream=STREAM_PTS):
         for k in range(1, len(probs)):
             r = u[j]
             j += 1
-            if r <= probs[k] and not chosen:
+            if r <= probs[k] and not chosen and (allow is None or (s, k) in allow):
                 rec.append((s, k))
                 chosen = True
     return tuple(rec)
 
 
-def alg2_literal(site_probs, seed, cfg, n_draws, nshots, stream=STREAM_PTS):
+def alg2_literal(site_probs, seed, cfg, n_draws, nshots, stream=STREAM_PTS, allow=None):
     """Algorithm 2: ``n_draws`` samples, duplicates dropped (uniqueKraus), each kept
     record given ``nshots`` shots."""
     index = {}
     records = []
     for t in range(n_draws):
-        rec = alg2_draw(site_probs, seed, cfg, t, stream)
+        rec = alg2_draw(site_probs, seed, cfg, t, stream, allow)
         if rec not in index:
             index[rec] = len(records)
             records.append(rec)
@@ -169,34 +177,59 @@ def _pairs_numpy(items, bound, keep):
     return [(((int(sa[o]), int(ka[o])), (int(sb[o]), int(kb[o]))), float(tot[o])) for o in order]
 
 
-def most_likely(site_probs, k_max):
+def keep_record(n_errors, min_errors=0, max_errors=0, parity=None):
+    """Record-level selection: at least min_errors and (max_errors > 0) at most
+    max_errors operators k >= 1, and their number even / odd if asked."""
+    if n_errors < min_errors or (max_errors and n_errors > max_errors):
+        return False
+    if parity == "even" and n_errors % 2:
+        return False
+    if parity == "odd" and n_errors % 2 == 0:
+        return False
+    return True
+
+
+def select_records(records, counts, **crit):
+    """Drop the records (with their counts) that keep_record rejects."""
+    kept = [(r, c) for r, c in zip(records, counts) if keep_record(len(r), **crit)]
+    return [r for r, _ in kept], [c for _, c in kept]
+
+
+def most_likely(site_probs, k_max, allow=None, **crit):
     """The ``k_max`` records of highest joint probability.
 
     Ranking: ascending score (= descending p_alpha / p_none), ties broken by the
     record's (s, k) list in lexicographic order.  Enumeration by number of
     errors e = 0, 1, 2, ...: each round adds every e-error record whose score
     does not exceed the current k_max-th score, and the search stops once the
-    cheapest possible record with e errors scores above it.  Returns (records, scores)."""
+    cheapest possible record with e errors scores above it.  With selection
+    criteria only operators in ``allow`` are enumerated and only records that
+    keep_record(**crit) accepts are ranked.  Returns (records, scores)."""
     cost = costs(site_probs)
+    if allow is not None:
+        cost = {sk: c for sk, c in cost.items() if sk in allow}
+    max_e = crit.get("max_errors", 0)
     items = sorted((c, s, k) for (s, k), c in cost.items())
     per_site = {}
     for c, s, _ in items:
         per_site.setdefault(s, c)              # items ascending: first is the site's minimum
     site_min = sorted(per_site.values())
-    cands = [((), 0.0)]
+    cands = [((), 0.0)] if keep_record(0, **crit) else []
     e = 0
     while True:
         e += 1
         cands.sort(key=lambda rc: (rc[1], rc[0]))
         cands = cands[:k_max]
         bound = cands[-1][1] if len(cands) >= k_max else math.inf
-        if e > len(site_min):
+        if e > len(site_min) or (max_e and e > max_e):
             break
         cheapest = 0.0
         for v in site_min[:e]:
             cheapest += v
         if cheapest > bound:
             break
+        if not keep_record(e, **crit):
+            continue
         if e == 2:
             cands.extend(_pairs_numpy(items, bound, k_max))
         else:
@@ -206,14 +239,15 @@ def most_likely(site_probs, k_max):
     return [r for r, _ in top], [sc for _, sc in top]
 
 
-def most_likely_bruteforce(site_probs, k_max):
+def most_likely_bruteforce(site_probs, k_max, allow=None, **crit):
     """Every record of the full product space, sorted by (score, record); tiny cases only."""
     cost = costs(site_probs)
     choices = [range(len(p)) for p in site_probs]
     allrec = []
     for ks in itertools.product(*choices):
         rec = tuple((s, k) for s, k in enumerate(ks) if k != 0)
-        if all(sk in cost for sk in rec):
+        if (all(sk in cost for sk in rec) and (allow is None or all(sk in allow for sk in rec))
+                and keep_record(len(rec), **crit)):
             allrec.append((rec, score(rec, cost)))
     allrec.sort(key=lambda rc: (rc[1], rc[0]))
     top = allrec[:k_max]

@@ -17,7 +17,7 @@ from ._lib import PtsbeError, lib, check
 
 __all__ = ["ptsbe_plan", "ptsbe_plan_compile", "ptsbe_sample_kraus", "ptsbe_trajset_from_records",
            "ptsbe_workspace_size", "ptsbe_run_batch", "ptsbe_run_status", "ptsbe_unique_workspace_size",
-           "ptsbe_unique_shots", "ptsbe_adjoint_grad", "std_gate",
+           "ptsbe_unique_shots", "ptsbe_adjoint_grad", "site_selection", "pauli_twirl", "std_gate",
            "std_channel", "Plan", "TrajSet", "RunGraph", "PtsbeError", "tag_id"]
 
 
@@ -107,7 +107,7 @@ def ptsbe_plan_compile(plan):
 
 
 def ptsbe_plan(circuit, precision="c64", tile_qubits=0, compile=True, min_fill=0, half_tile=False,
-               phase_frames=True, waves=0):
+               phase_frames=True, waves=0, twirl=False):
     """Build the execution plan of a circuit dictionary (ops, channels, rules).
     ``compile=False`` runs the passes through the generic tile kernels instead of
     per-pass compiled kernels; ``min_fill`` (1..7, 0 = 2) is the fewest 2x2
@@ -115,7 +115,8 @@ def ptsbe_plan(circuit, precision="c64", tile_qubits=0, compile=True, min_fill=0
     between register sets through half a tile of LDS; ``phase_frames=False``
     keeps every slot matrix as it is (no pending diagonals between matrices);
     ``waves`` (1..8, 0 = compiler's choice) sets the compiled passes' register
-    budget to 512 / waves VGPRs."""
+    budget to 512 / waves VGPRs; ``twirl`` replaces channels that are not unitary
+    mixtures by their Pauli twirl (else they are rejected)."""
     ops = circuit["ops"]
     arr = (L.Op * max(1, len(ops)))()
     keep = []
@@ -183,7 +184,8 @@ def ptsbe_plan(circuit, precision="c64", tile_qubits=0, compile=True, min_fill=0
     po = L.PlanOpts({"c64": L.C64, "c128": L.C128}[precision], int(tile_qubits),
                     int(min_fill) | (0 if compile else L.PLAN_NO_COMPILE) |
                     (L.PLAN_HALF_TILE_LDS if half_tile else 0) |
-                    (0 if phase_frames else L.PLAN_NO_PHASE_FRAMES) | (int(waves) << L.PLAN_WAVES_SHIFT), 0)
+                    (0 if phase_frames else L.PLAN_NO_PHASE_FRAMES) | (int(waves) << L.PLAN_WAVES_SHIFT) |
+                    (L.PLAN_TWIRL if twirl else 0), 0)
     h = C.c_void_p()
     check(lib().ptsbe_plan(C.byref(c), C.byref(nm), C.byref(po), C.byref(h)))
     return Plan(h, None)
@@ -239,17 +241,67 @@ class TrajSet:
 
 
 def ptsbe_sample_kraus(plan, mode="proportional", n_draws=0, k_max=0, total_shots=0, nshots=0, seed=0,
-                       cfg=0, alloc=None, stream=0, p_band=None):
-    """Pre-trajectory sampling (Sec. 3.1) with the library's samplers."""
+                       cfg=0, alloc=None, stream=0, p_band=None, kraus_allow=None, min_errors=0, max_errors=0,
+                       parity=None):
+    """Pre-trajectory sampling (Sec. 3.1) with the library's samplers.  Selection
+    criteria: ``kraus_allow`` (one flag per (site, Kraus index) in the order of
+    plan.site_probs(); see site_selection), ``min_errors`` / ``max_errors``
+    (0 = no limit) on the number of non-identity operators of a record, and
+    ``parity`` ("even" / "odd") of that number."""
     if alloc is None:
         alloc = {"proportional": "multiplicity", "alg2_literal": "uniform", "most_likely": "reweight",
                  "per_shot": "multiplicity"}[mode]
+    allow = None
+    if kraus_allow is not None:
+        allow = np.ascontiguousarray(kraus_allow, dtype=np.uint8)
+        if allow.size != plan.info["total_kraus"]:
+            raise ValueError("kraus_allow needs one flag per (site, Kraus index)")
     o = L.PtsOpts(L.PTS_MODES[mode], L.ALLOCS[alloc], int(n_draws), int(k_max), int(total_shots),
                   int(nshots), int(seed), int(cfg), int(stream),
-                  float(p_band[0]) if p_band else 0.0, float(p_band[1]) if p_band else 0.0)
+                  float(p_band[0]) if p_band else 0.0, float(p_band[1]) if p_band else 0.0,
+                  C.c_void_p(allow.ctypes.data) if allow is not None else None, int(min_errors), int(max_errors),
+                  L.PARITY[parity], 0)
     h = C.c_void_p()
     check(lib().ptsbe_sample_kraus(plan.handle, C.byref(o), C.byref(h)))
     return TrajSet(h, plan)
+
+
+def pauli_twirl(channel):
+    """Pauli-twirl probabilities of a channel dict (as in circuit["channels"]):
+    4^nq values, string index digit j (0 I, 1 X, 2 Y, 3 Z) on the site's qubit j."""
+    k, nq, nk = std_channel(channel)
+    out = np.zeros(4 ** nq, dtype=np.float64)
+    check(lib().ptsbe_pauli_twirl(nq, C.c_void_p(k.ctypes.data), nk, C.c_void_p(out.ctypes.data)))
+    return out
+
+
+def site_selection(plan, tags=None, qubits=None, ops=None, origins=None, kraus=None):
+    """Flags for ptsbe_sample_kraus(kraus_allow=...): operator k >= 1 of site s is
+    allowed when the site's op tag is in ``tags`` (gate type), every qubit of
+    the site is in ``qubits`` and its op index in ``ops`` (location), its origin
+    in ``origins`` ("noise_op", "after_tag", "before_measure",
+    "before_readout") and k in ``kraus`` (error type); None accepts anything."""
+    n = plan.info["n_sites"]
+    probs, site_q = plan.site_probs()
+    off = np.concatenate([[0], np.cumsum([len(p) for p in probs])]).astype(np.int64)
+    op = np.zeros(max(1, n), dtype=np.uint32)
+    tg = np.zeros(max(1, n), dtype=np.uint32)
+    org = np.zeros(max(1, n), dtype=np.uint32)
+    check(lib().ptsbe_plan_get_site_ops(plan.handle, C.c_void_p(op.ctypes.data), C.c_void_p(tg.ctypes.data),
+                                        C.c_void_p(org.ctypes.data)))
+    tagset = None if tags is None else {tag_id(t) for t in tags}
+    qset = None if qubits is None else set(int(q) for q in qubits)
+    oset = None if ops is None else set(int(i) for i in ops)
+    orset = None if origins is None else {L.SITE_ORIGINS.index(x) for x in origins}
+    kset = None if kraus is None else set(int(k) for k in kraus)
+    flags = np.ones(plan.info["total_kraus"], dtype=np.uint8)
+    for s in range(n):
+        q = [int(x) for x in site_q[s] if x != 0xFFFFFFFF]
+        ok = ((tagset is None or int(tg[s]) in tagset) and (qset is None or all(x in qset for x in q)) and
+              (oset is None or int(op[s]) in oset) and (orset is None or int(org[s]) in orset))
+        for k in range(1, int(off[s + 1] - off[s])):
+            flags[off[s] + k] = 1 if ok and (kset is None or k in kset) else 0
+    return flags
 
 
 def ptsbe_trajset_from_records(plan, records, m, alpha0=0):

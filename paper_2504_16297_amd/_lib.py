@@ -27,6 +27,7 @@ PLAN_NO_COMPILE = 8
 PLAN_HALF_TILE_LDS = 16
 PLAN_NO_PHASE_FRAMES = 32
 PLAN_WAVES_SHIFT = 8
+PLAN_TWIRL = 64
 
 
 class Op(C.Structure):
@@ -68,7 +69,13 @@ class PtsOpts(C.Structure):
     _fields_ = [("mode", C.c_uint32), ("alloc", C.c_uint32), ("n_draws", C.c_uint64),
                 ("k_max", C.c_uint64), ("total_shots", C.c_uint64), ("nshots", C.c_uint64),
                 ("seed", C.c_uint64), ("cfg", C.c_uint32), ("stream", C.c_uint32),
-                ("p_min", C.c_double), ("p_max", C.c_double)]
+                ("p_min", C.c_double), ("p_max", C.c_double),
+                ("kraus_allow", C.c_void_p), ("min_errors", C.c_uint32), ("max_errors", C.c_uint32),
+                ("error_parity", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+PARITY = {None: 0, "any": 0, "even": 1, "odd": 2}
+SITE_ORIGINS = ("noise_op", "after_tag", "before_measure", "before_readout")
 
 
 class RunOpts(C.Structure):
@@ -106,6 +113,8 @@ _SIGS = {
                                   C.c_size_t, C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p,
                                   C.c_void_p]),
     "ptsbe_run_status": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ptsbe_pauli_twirl": (C.c_int, [C.c_uint32, C.c_void_p, C.c_uint32, C.c_void_p]),
+    "ptsbe_plan_get_site_ops": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "ptsbe_unique_workspace_size": (C.c_int, [C.c_void_p, C.c_uint32, C.POINTER(C.c_size_t)]),
     "ptsbe_unique_shots": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p,
                                      C.c_void_p, C.c_void_p]),

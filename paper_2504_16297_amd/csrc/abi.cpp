@@ -122,6 +122,17 @@ ptsbe_status ptsbe_plan_get_sites(ptsbe_plan_t plan, uint32_t* offsets, double* 
   return PTSBE_OK;
 }
 
+ptsbe_status ptsbe_plan_get_site_ops(ptsbe_plan_t plan, uint32_t* op_index, uint32_t* tag, uint32_t* origin) {
+  if (!plan) return fail(PTSBE_E_ARG, "null plan");
+  const Plan& P = *plan->plan;
+  for (size_t s = 0; s < P.sites.size(); ++s) {
+    if (op_index) op_index[s] = P.sites[s].op;
+    if (tag) tag[s] = P.sites[s].tag;
+    if (origin) origin[s] = P.sites[s].origin;
+  }
+  return PTSBE_OK;
+}
+
 void ptsbe_plan_destroy(ptsbe_plan_t plan) { delete plan; }
 
 ptsbe_status ptsbe_sample_kraus(ptsbe_plan_t plan, const ptsbe_pts_opts* opts, ptsbe_trajset_t* out) {
@@ -372,6 +383,10 @@ ptsbe_status ptsbe_std_gate(const char* name, const double* params, double* out,
   put(out, m);
   *nq = q;
   return PTSBE_OK;
+}
+
+ptsbe_status ptsbe_pauli_twirl(uint32_t nq, const double* kraus, uint32_t n_kraus, double* probs) {
+  FENCE({ return pauli_twirl_channel(nq, kraus, n_kraus, probs); })
 }
 
 ptsbe_status ptsbe_std_channel(const char* name, uint32_t nq, const double* params, double* out, uint32_t* n_kraus) {

@@ -57,6 +57,9 @@ struct Site {
   int nq;
   int q[2];
   int step;
+  uint32_t op = 0xffffffffu;  // circuit op the site belongs to (none for readout sites)
+  uint32_t tag = 0;           // that op's tag
+  uint32_t origin = 0;        // PTSBE_SITE_*
 };
 
 // One factor of a fused slot: a step, or one half of a product 2-qubit site.
@@ -200,6 +203,11 @@ std::vector<std::vector<SlotFrame>> slot_frames(int n, const std::vector<Pass>& 
                                                 const std::vector<std::vector<Mat>>& defaults);
 // The matrix a slot's table entry holds for true matrix M (default or override).
 Mat frame_matrix(const Slot& s, const SlotFrame& f, const Mat& M);
+
+// Pauli twirl of a channel: probabilities of the 4^nq Pauli strings (digit j of
+// the string index, 0 I / 1 X / 2 Y / 3 Z, on matrix bit j).
+std::vector<double> pauli_twirl_probs(const std::vector<Mat>& K, int nq);
+ptsbe_status pauli_twirl_channel(uint32_t nq, const double* kraus, uint32_t n_kraus, double* probs);
 
 // Planner
 ptsbe_status build_plan(const ptsbe_circuit* c, const ptsbe_noise_model* nm,

@@ -102,7 +102,61 @@ static bool split_product(const Mat& U, Mat* a, Mat* b) {
   return true;
 }
 
-static ptsbe_status analyse_channel(const ptsbe_channel& ch, int idx, Channel* out) {
+// ------------------------------------------------------------ Pauli twirl
+
+// Pauli string `index` on nq qubits: base-4 digit j (0 I, 1 X, 2 Y, 3 Z) acts
+// on matrix bit j.
+static Mat pauli_matrix(uint32_t index, int nq) {
+  static const cd s[4][4] = {{1, 0, 0, 1}, {0, 1, 1, 0}, {0, cd(0, -1), cd(0, 1), 0}, {1, 0, 0, -1}};
+  const int d = 1 << nq;
+  Mat M(d * d);
+  for (int r = 0; r < d; ++r)
+    for (int c = 0; c < d; ++c) {
+      cd v(1, 0);
+      for (int j = 0; j < nq; ++j) v *= s[(index >> (2 * j)) & 3][((r >> j) & 1) * 2 + ((c >> j) & 1)];
+      M[r * d + c] = v;
+    }
+  return M;
+}
+
+// Averaging a channel over conjugation by every Pauli string keeps the diagonal
+// of its Pauli transfer matrix: the Pauli channel with p_P = sum_k |Tr(P^dag K_k)|^2 / d^2.
+std::vector<double> pauli_twirl_probs(const std::vector<Mat>& K, int nq) {
+  const int d = 1 << nq;
+  std::vector<double> p(d * d, 0.0);
+  for (uint32_t i = 0; i < (uint32_t)(d * d); ++i) {
+    const Mat P = pauli_matrix(i, nq);
+    for (const Mat& m : K) {
+      cd tr(0, 0);
+      for (int r = 0; r < d; ++r)
+        for (int c = 0; c < d; ++c) tr += std::conj(P[r * d + c]) * m[r * d + c];
+      p[i] += std::norm(tr) / (double)(d * d);
+    }
+  }
+  return p;
+}
+
+ptsbe_status pauli_twirl_channel(uint32_t nq, const double* kraus, uint32_t n_kraus, double* probs) {
+  if (nq < 1 || nq > 2 || n_kraus < 1 || n_kraus > 64 || !kraus || !probs)
+    return fail(PTSBE_E_ARG, "Pauli twirl: nq 1 or 2, 1..64 Kraus operators, non-null arrays");
+  const int d = 1 << nq;
+  std::vector<Mat> K;
+  for (uint32_t k = 0; k < n_kraus; ++k) K.push_back(read_mat(kraus + 2 * k * d * d, d));
+  double err = 0;
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j) {
+      cd v(0, 0);
+      for (auto& m : K)
+        for (int l = 0; l < d; ++l) v += std::conj(m[l * d + i]) * m[l * d + j];
+      err = std::max(err, std::abs(v - (i == j ? 1.0 : 0.0)));
+    }
+  if (err > 1e-12) return fail(PTSBE_E_NOT_CPTP, "Pauli twirl: the channel is not CPTP");
+  const std::vector<double> p = pauli_twirl_probs(K, (int)nq);
+  std::copy(p.begin(), p.end(), probs);
+  return PTSBE_OK;
+}
+
+static ptsbe_status analyse_channel(const ptsbe_channel& ch, int idx, Channel* out, bool twirl = false) {
   if (ch.nq < 1 || ch.nq > 2) return fail(PTSBE_E_ARG, "channel " + std::to_string(idx) + ": nq must be 1 or 2");
   if (ch.n_kraus < 1 || ch.n_kraus > 16 || !ch.kraus)
     return fail(PTSBE_E_ARG, "channel " + std::to_string(idx) + ": 1..16 Kraus operators required");
@@ -134,10 +188,29 @@ static ptsbe_status analyse_channel(const ptsbe_channel& ch, int idx, Channel* o
       for (int j = 0; j < d; ++j) {
         cd v(0, 0);
         for (int l = 0; l < d; ++l) v += std::conj(K[k][l * d + i]) * K[k][l * d + j];
-        if (std::abs(v - (i == j ? p : 0.0)) > 1e-12)
-          return fail(PTSBE_E_UNSUPPORTED, "channel " + std::to_string(idx) +
-                                               " is not a unitary mixture; state-dependent channels are not "
-                                               "pre-samplable");
+        if (std::abs(v - (i == j ? p : 0.0)) > 1e-12) {
+          if (!twirl)
+            return fail(PTSBE_E_UNSUPPORTED, "channel " + std::to_string(idx) +
+                                                 " is not a unitary mixture; state-dependent channels are not "
+                                                 "pre-samplable (PTSBE_PLAN_TWIRL replaces them by their Pauli twirl)");
+          // its Pauli twirl: sqrt(p_P) P for the strings with p_P > 0, in string order
+          const std::vector<double> pt = pauli_twirl_probs(K, ch.nq);
+          std::vector<double> flat;
+          uint32_t nk = 0;
+          for (uint32_t s = 0; s < pt.size(); ++s) {
+            if (pt[s] <= 0.0) continue;
+            const Mat P = pauli_matrix(s, ch.nq);
+            for (const cd& x : P) {
+              flat.push_back(x.real() * std::sqrt(pt[s]));
+              flat.push_back(x.imag() * std::sqrt(pt[s]));
+            }
+            ++nk;
+          }
+          ptsbe_channel tw = ch;
+          tw.n_kraus = nk;
+          tw.kraus = flat.data();
+          return analyse_channel(tw, idx, out, false);
+        }
       }
     Mat U = K[k];
     if (p > 0) {
@@ -861,7 +934,7 @@ ptsbe_status build_plan(const ptsbe_circuit* c, const ptsbe_noise_model* nm, con
   if (n_ch && !nm->channels) return fail(PTSBE_E_ARG, "null channel array");
   for (uint32_t i = 0; i < n_ch; ++i) {
     Channel ch;
-    ptsbe_status st = analyse_channel(nm->channels[i], (int)i, &ch);
+    ptsbe_status st = analyse_channel(nm->channels[i], (int)i, &ch, o && (o->flags & PTSBE_PLAN_TWIRL));
     if (st != PTSBE_OK) return st;
     P.channels.push_back(std::move(ch));
   }
@@ -876,7 +949,8 @@ ptsbe_status build_plan(const ptsbe_circuit* c, const ptsbe_noise_model* nm, con
     if (a.when == PTSBE_ATTACH_BEFORE_READOUT && P.n < 64 && (a.qmask >> P.n))
       return fail(PTSBE_E_ARG, "rule " + std::to_string(r) + ": readout mask names a qubit >= n");
   }
-  auto add_site = [&](int ch, int nq, const int* q) -> ptsbe_status {
+  auto add_site = [&](int ch, int nq, const int* q, uint32_t op_index, uint32_t tag,
+                      uint32_t origin) -> ptsbe_status {
     if (P.channels[ch].nq != nq) return fail(PTSBE_E_ARG, "channel arity does not match the site's qubits");
     Site s;
     s.channel = ch;
@@ -884,6 +958,9 @@ ptsbe_status build_plan(const ptsbe_circuit* c, const ptsbe_noise_model* nm, con
     s.q[0] = q[0];
     s.q[1] = nq > 1 ? q[1] : -1;
     s.step = (int)P.steps.size();
+    s.op = op_index;
+    s.tag = tag;
+    s.origin = origin;
     P.sites.push_back(s);
     Step st;
     st.kind = ST_SITE;
@@ -934,13 +1011,14 @@ ptsbe_status build_plan(const ptsbe_circuit* c, const ptsbe_noise_model* nm, con
     } else if (op.kind == PTSBE_OP_NOISE) {
       if (op.index < 0 || (uint32_t)op.index >= n_ch) return fail(PTSBE_E_ARG, where + "bad channel index");
       if (op.nq > 2) return fail(PTSBE_E_ARG, where + "noise ops act on 1 or 2 qubits");
-      ptsbe_status s2 = add_site(op.index, (int)op.nq, q);
+      ptsbe_status s2 = add_site(op.index, (int)op.nq, q, i, op.tag, PTSBE_SITE_NOISE_OP);
       if (s2 != PTSBE_OK) return fail(s2, where + last_error_cstr());
       continue;
     } else if (op.kind == PTSBE_OP_MEASURE_RESET) {
       if (op.nq != 1) return fail(PTSBE_E_ARG, where + "measure-reset acts on one qubit");
       for (uint32_t r = 0; r < n_rules; ++r)
-        if (nm->rules[r].when == PTSBE_ATTACH_BEFORE_MEASURE) add_site((int)nm->rules[r].channel, 1, q);
+        if (nm->rules[r].when == PTSBE_ATTACH_BEFORE_MEASURE)
+          add_site((int)nm->rules[r].channel, 1, q, i, op.tag, PTSBE_SITE_BEFORE_MEASURE);
       Step st;
       st.kind = ST_MR;
       st.nq = 1;
@@ -964,7 +1042,7 @@ ptsbe_status build_plan(const ptsbe_circuit* c, const ptsbe_noise_model* nm, con
     for (uint32_t r = 0; r < n_rules; ++r) {
       const ptsbe_attach& a = nm->rules[r];
       if (a.when == PTSBE_ATTACH_AFTER_TAG && a.tag == op.tag) {
-        ptsbe_status s2 = add_site((int)a.channel, (int)op.nq, q);
+        ptsbe_status s2 = add_site((int)a.channel, (int)op.nq, q, i, op.tag, PTSBE_SITE_AFTER_TAG);
         if (s2 != PTSBE_OK) return fail(s2, where + "rule " + std::to_string(r) + ": " + last_error_cstr());
       }
     }
@@ -973,7 +1051,7 @@ ptsbe_status build_plan(const ptsbe_circuit* c, const ptsbe_noise_model* nm, con
     const ptsbe_attach& a = nm->rules[r];
     if (a.when != PTSBE_ATTACH_BEFORE_READOUT) continue;
     for (int qq = 0; qq < P.n; ++qq)
-      if ((a.qmask >> qq) & 1) add_site((int)a.channel, 1, &qq);
+      if ((a.qmask >> qq) & 1) add_site((int)a.channel, 1, &qq, 0xffffffffu, 0u, PTSBE_SITE_BEFORE_READOUT);
   }
   if (P.n_measure > 65535) return fail(PTSBE_E_UNSUPPORTED, "too many measure-reset ops");
   P.n_params = max_param + 1;

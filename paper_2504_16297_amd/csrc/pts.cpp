@@ -95,18 +95,37 @@ struct Item {
   uint8_t k;
 };
 
+// Selection criteria of a PTS run (operator flags and record-level filters).
+struct Criteria {
+  const uint8_t* allow = nullptr;  // per (site, k) flags, k >= 1 consulted
+  uint32_t min_errors = 0, max_errors = 0, parity = PTSBE_PARITY_ANY;
+  const Plan* P = nullptr;
+  bool allowed(size_t s, int k) const { return !allow || k == 0 || allow[P->site_off[s] + k]; }
+  bool keep(size_t n_err) const {
+    if (n_err < min_errors) return false;
+    if (max_errors && n_err > max_errors) return false;
+    if (parity == PTSBE_PARITY_EVEN && (n_err & 1)) return false;
+    if (parity == PTSBE_PARITY_ODD && !(n_err & 1)) return false;
+    return true;
+  }
+  bool any_filter() const { return min_errors || max_errors || parity != PTSBE_PARITY_ANY; }
+};
+
 // Most-likely-first selection: records ranked by ascending score
 // sum_{(s,k)} -ln(p_{s,k}/p_{s,0}) (summed in ascending (c, s, k) order), ties by
 // the record's (s, k) list.  A depth-first walk over the items sorted by cost
 // finds every record with score <= tau; tau is bisected until at least k_max
 // records qualify, then the qualifying records are sorted and cut.
-std::vector<Record> most_likely(const Plan& P, uint64_t k_max) {
+// Selection criteria restrict the items to allowed operators; only records the
+// record-level filters keep are counted (and collected), and no record grows
+// past max_errors.
+std::vector<Record> most_likely(const Plan& P, uint64_t k_max, const Criteria& crit) {
   std::vector<Item> items;
   for (size_t s = 0; s < P.sites.size(); ++s) {
     const double* p = &P.site_p[P.site_off[s]];
     int K = (int)(P.site_off[s + 1] - P.site_off[s]);
     for (int k = 1; k < K; ++k)
-      if (p[k] > 0) items.push_back({-std::log(p[k] / p[0]), (uint32_t)s, (uint8_t)k});
+      if (p[k] > 0 && crit.allowed(s, k)) items.push_back({-std::log(p[k] / p[0]), (uint32_t)s, (uint8_t)k});
   }
   std::sort(items.begin(), items.end(), [](const Item& a, const Item& b) {
     if (a.c != b.c) return a.c < b.c;
@@ -120,13 +139,16 @@ std::vector<Record> most_likely(const Plan& P, uint64_t k_max) {
     uint64_t count = 0;
     std::function<void(size_t, double)> rec_fn = [&](size_t start, double partial) {
       if (count >= cap) return;
-      ++count;
-      if (sink) {
-        Record r;
-        for (uint32_t it : stack_item) r.push_back({items[it].s, items[it].k});
-        std::sort(r.begin(), r.end());
-        sink->push_back({partial, r});
+      if (crit.keep(stack_item.size())) {
+        ++count;
+        if (sink) {
+          Record r;
+          for (uint32_t it : stack_item) r.push_back({items[it].s, items[it].k});
+          std::sort(r.begin(), r.end());
+          sink->push_back({partial, r});
+        }
       }
+      if (crit.max_errors && stack_item.size() >= crit.max_errors) return;
       for (size_t j = start; j < items.size(); ++j) {
         if (partial + items[j].c > tau) break;
         if (used[items[j].s]) continue;
@@ -209,6 +231,14 @@ ptsbe_status sample_kraus(const std::shared_ptr<Plan>& plan, const ptsbe_pts_opt
   std::vector<Record> recs;
   std::vector<uint64_t> counts;
   uint64_t T = 0;
+  Criteria crit;
+  crit.P = &P;
+  crit.allow = o->kraus_allow;
+  crit.min_errors = o->min_errors;
+  crit.max_errors = o->max_errors;
+  crit.parity = o->error_parity;
+  if (crit.parity > PTSBE_PARITY_ODD) return fail(PTSBE_E_ARG, "bad error parity");
+  if (crit.max_errors && crit.min_errors > crit.max_errors) return fail(PTSBE_E_ARG, "min_errors > max_errors");
   if (o->mode == PTSBE_PTS_PROPORTIONAL || o->mode == PTSBE_PTS_PER_SHOT) {
     if (o->n_draws == 0 || o->n_draws > (1ull << 32)) return fail(PTSBE_E_ARG, "n_draws must be in 1..2^32");
     bool merge = o->mode == PTSBE_PTS_PROPORTIONAL;
@@ -222,7 +252,7 @@ ptsbe_status sample_kraus(const std::shared_ptr<Plan>& plan, const ptsbe_pts_opt
         double u = word_to_uniform(philox_word(o->seed, k1, s));
         int K = (int)(P.site_off[s + 1] - P.site_off[s]);
         int k = categorical(u, &P.site_p[P.site_off[s]], K);
-        if (k) rec.push_back({(uint32_t)s, (uint8_t)k});
+        if (k && crit.allowed(s, k)) rec.push_back({(uint32_t)s, (uint8_t)k});
       }
       if (merge) {
         auto it = index.find(rec);
@@ -249,7 +279,8 @@ ptsbe_status sample_kraus(const std::shared_ptr<Plan>& plan, const ptsbe_pts_opt
         bool chosen = false;
         for (int k = 1; k < K; ++k) {
           double r = word_to_uniform(philox_word(o->seed, k1, j++));
-          if (r <= P.site_p[P.site_off[s] + k] && !chosen) {  // compatible(): one per site
+          // compatible(): one per site; selection criteria: allowed operators only
+          if (r <= P.site_p[P.site_off[s] + k] && !chosen && crit.allowed(s, k)) {
             rec.push_back({(uint32_t)s, (uint8_t)k});
             chosen = true;
           }
@@ -266,12 +297,28 @@ ptsbe_status sample_kraus(const std::shared_ptr<Plan>& plan, const ptsbe_pts_opt
     }
   } else if (o->mode == PTSBE_PTS_MOST_LIKELY) {
     if (o->k_max == 0 || o->k_max > (1ull << 26)) return fail(PTSBE_E_ARG, "k_max must be in 1..2^26");
-    recs = most_likely(P, o->k_max);
+    recs = most_likely(P, o->k_max, crit);
     counts.assign(recs.size(), 1);
     T = recs.size();
   } else {
     return fail(PTSBE_E_ARG, "unknown PTS mode");
   }
+  // record-level selection criteria: drop the records (and their draws) that fail
+  if (crit.any_filter() && o->mode != PTSBE_PTS_MOST_LIKELY) {
+    std::vector<Record> r2;
+    std::vector<uint64_t> c2;
+    uint64_t T2 = 0;
+    for (size_t a = 0; a < recs.size(); ++a)
+      if (crit.keep(recs[a].size())) {
+        r2.push_back(recs[a]);
+        c2.push_back(counts[a]);
+        T2 += counts[a];
+      }
+    recs.swap(r2);
+    counts.swap(c2);
+    T = T2;
+  }
+  if (recs.empty()) return fail(PTSBE_E_ARG, "no record meets the selection criteria");
   // probability band (Sec. 3.1): keep records with p_alpha in [p_min, p_max]
   if (o->p_min != 0.0 || o->p_max != 0.0) {
     if (!(o->p_min >= 0.0 && o->p_max >= o->p_min)) return fail(PTSBE_E_ARG, "bad probability band");

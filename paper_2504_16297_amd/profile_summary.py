@@ -8,10 +8,10 @@ project, and read those summaries back.
 `traffic` averages FETCH_SIZE and WRITE_SIZE (KiB per dispatch) over the
 dispatches of the named kernel and scales each by what the same counter reads
 for a plain device copy of known size (the copy's bytes divided by its
-counter), giving HBM bytes per dispatch.  The summary records the SHA-256 of
-the kernel sources (generic kernels, pass generator, planner) the counters were
-taken with, so a reader can tell when the
-kernel has changed since.
+counter), giving HBM bytes per dispatch.  The summary records the fingerprint
+of the kernels the counters were taken with (`kernel_fingerprint`: the generic
+kernels' source and the generated source of every pass of the workload's plan),
+so a reader can tell when the kernels have changed since.
 """
 
 import argparse
@@ -22,16 +22,20 @@ import re
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-# the tile-pass kernels: the generic kernels, the generator of the compiled
-# ones and the planner whose programs (and phase frames) it compiles
-KERNEL_SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "jit.cpp", "plan.cpp")]
-
-
-def kernel_source_sha():
+def kernel_fingerprint(plan):
+    """SHA-256 prefix over the generic tile kernels' source and the generated
+    source of every pass of `plan` (what runs on the device for it)."""
+    import ctypes as C
+    from . import _lib as L
     h = hashlib.sha256()
-    for path in KERNEL_SOURCES:
-        with open(path, "rb") as f:
-            h.update(f.read())
+    with open(os.path.join(HERE, "csrc", "kernels.hip"), "rb") as f:
+        h.update(f.read())
+    for p in range(plan.info["n_passes"]):
+        n = C.c_size_t()
+        L.check(L.lib().ptsbe_plan_pass_source(plan.handle, p, 0, None, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        L.check(L.lib().ptsbe_plan_pass_source(plan.handle, p, 0, buf, C.byref(n)))
+        h.update(buf.value)
     return h.hexdigest()[:16]
 
 
@@ -96,23 +100,23 @@ def traffic(a):
         f"read_bytes_per_dispatch: {fb:.6g}",
         f"write_bytes_per_dispatch: {wb:.6g}",
         f"traffic_bytes_per_dispatch: {fb + wb:.6g}",
-        f"kernel_source_sha256: {kernel_source_sha()}",
+        f"kernel_fingerprint: {a.fingerprint}",
     ]
     return "\n".join(lines)
 
 
 def read_traffic(path):
-    """(bytes per dispatch, kernel source hash) from a traffic summary, or None."""
+    """(bytes per dispatch, kernel fingerprint) from a traffic summary, or None."""
     if not os.path.exists(path):
         return None
     vals = {}
     for line in open(path):
-        m = re.match(r"\s*(traffic_bytes_per_dispatch|kernel_source_sha256):\s*(\S+)", line)
+        m = re.match(r"\s*(traffic_bytes_per_dispatch|kernel_fingerprint):\s*(\S+)", line)
         if m:
             vals[m.group(1)] = m.group(2)
     if len(vals) != 2:
         return None
-    return float(vals["traffic_bytes_per_dispatch"]), vals["kernel_source_sha256"]
+    return float(vals["traffic_bytes_per_dispatch"]), vals["kernel_fingerprint"]
 
 
 def main(argv=None):
@@ -128,6 +132,8 @@ def main(argv=None):
         t.add_argument("--" + k.replace("_", "-"), dest=k, required=True)
     t.add_argument("--copy-bytes", type=float, required=True)
     t.add_argument("--kernel", required=True)
+    t.add_argument("--fingerprint", required=True, help="kernel_fingerprint of the profiled plan "
+                   "(python bench.py --fingerprint)")
     t.add_argument("--cmd", required=True)
     a = ap.parse_args(argv)
     body = stats(a.csv, a.top, a.group) if a.what == "stats" else traffic(a)

@@ -354,3 +354,28 @@ def test_phase_frames_match_plain_plan(n, prec):
     err_p = max(float(np.max(np.abs(b[i] - ref[i]))) for i in range(len(ref)))
     log(f"  max|framed - oracle| = {err_f:.2e}, max|plain - oracle| = {err_p:.2e}")
     assert err_f <= tol and err_p <= tol
+
+
+def test_twirled_amplitude_damping_states():
+    """A circuit with amplitude damping, planned with its Pauli twirl
+    (PTSBE_PLAN_TWIRL): trajectory states equal the oracle's for the twirled
+    channel, and proportional selection with a location criterion (errors on
+    qubits 0..3 only) keeps every error there."""
+    from oracle.channels import twirled
+    log("[twirl] amplitude damping")
+    rng = np.random.default_rng(8)
+    circ = random_small_circuit(7, 40, rng, p1=0.0, p2=0.0)
+    ad = {"name": "amplitude_damping", "gamma": 0.2, "nq": 1}
+    circ = dict(circ, ops=[op for op in circ["ops"] if op["kind"] != "noise"], channels=[ad],
+                rules=[{"when": "after_tag", "tag": "U3", "channel": 0}, {"when": "after_tag", "tag": "RX", "channel": 0}])
+    plan = P.ptsbe_plan(circ, twirl=True)
+    flags = P.site_selection(plan, qubits=range(4))
+    ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=30, total_shots=30, seed=2, cfg=1, kraus_allow=flags)
+    g = ts.get()
+    _, q = plan.site_probs()
+    assert all(int(q[s][0]) < 4 for r in g["records"] for s, _ in r)
+    gpu = _states(plan, ts)
+    ref, _ = oracle_states(dict(circ, channels=[twirled(ad)]), g["records"])
+    err = max(float(np.max(np.abs(gpu[a] - ref[a]))) for a in range(len(ref)))
+    log(f"  {len(ref)} trajectories, max|d| = {err:.2e}")
+    assert err <= 1e-5

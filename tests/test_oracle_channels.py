@@ -96,3 +96,51 @@ def test_site_expansion_order_rules():
     kinds = [s[0] for s in steps]
     assert kinds == ["gate", "site", "gate", "site", "site", "mr", "site", "site", "site"]
     assert [s["qubits"] for s in sites] == [(0,), (0, 1), (1,), (1,), (0,), (1,)]
+
+
+# ---------------------------------------------------------------- Pauli twirl
+
+def _random_cptp(nq, n_kraus, rng):
+    d = 2 ** nq
+    a = rng.normal(size=(n_kraus * d, d)) + 1j * rng.normal(size=(n_kraus * d, d))
+    q, _ = np.linalg.qr(a)                                 # isometry: sum K^dag K = I
+    return [q[k * d:(k + 1) * d, :] for k in range(n_kraus)]
+
+
+def test_twirl_of_amplitude_damping_closed_form():
+    from oracle.channels import pauli_twirl
+    for g in (0.0, 0.1, 0.37, 1.0):
+        s = math.sqrt(1 - g)
+        p = pauli_twirl(kraus_ops({"name": "amplitude_damping", "gamma": g}))
+        assert np.allclose(p, [(1 + s) ** 2 / 4, g / 4, g / 4, (1 - s) ** 2 / 4], atol=1e-15)
+
+
+def test_twirl_fixed_points_and_unitaries():
+    from oracle.channels import pauli_twirl
+    p = pauli_twirl(kraus_ops({"name": "pauli", "probs": (0.03, 0.02, 0.05)}))
+    assert np.allclose(p, [0.9, 0.03, 0.02, 0.05], atol=1e-15)
+    p = pauli_twirl(kraus_ops({"name": "depolarizing", "nq": 2, "p": 0.3}))
+    assert np.allclose(p, [0.7] + [0.02] * 15, atol=1e-15)
+    th = 0.8
+    rz = np.diag([np.exp(-0.5j * th), np.exp(0.5j * th)])
+    assert np.allclose(pauli_twirl([rz]), [math.cos(th / 2) ** 2, 0, 0, math.sin(th / 2) ** 2], atol=1e-15)
+
+
+def test_twirl_keeps_the_transfer_diagonal_and_sums_to_one():
+    from oracle.channels import pauli_transfer_diagonal, pauli_twirl, twirled
+    rng = np.random.default_rng(9)
+    for nq, nk in ((1, 2), (1, 3), (2, 2), (2, 5)):
+        K = _random_cptp(nq, nk, rng)
+        p = pauli_twirl(K)
+        assert abs(p.sum() - 1) < 1e-12 and np.all(p >= 0)
+        Kt = twirled({"kraus": K})["kraus"]
+        assert np.allclose(pauli_transfer_diagonal(K), pauli_transfer_diagonal(Kt), atol=1e-12)
+
+
+def test_twirl_string_index_puts_digit_j_on_matrix_bit_j():
+    from oracle.channels import pauli_twirl
+    ad = kraus_ops({"name": "amplitude_damping", "gamma": 0.5})
+    on_bit0 = [np.kron(np.eye(2), A) for A in ad]          # acts on the site's first qubit only
+    p = pauli_twirl(on_bit0)
+    assert np.all(p.reshape(4, 4)[1:, :] == 0)             # digit 1 (second qubit) is always I
+    assert np.allclose(p[:4], pauli_twirl(ad), atol=1e-15)

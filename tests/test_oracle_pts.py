@@ -132,3 +132,45 @@ def test_score_is_order_canonical():
     c = costs(sp)
     assert score(((0, 1), (2, 1)), c) == score(((1, 1), (2, 1)), c)
     assert math.isclose(score(((0, 1),), c), -math.log(0.1 / 0.9))
+
+
+def _small_probs(seed, S=7):
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(S):
+        K = int(rng.integers(2, 5))
+        p = rng.dirichlet(np.full(K, 0.6))
+        p = np.sort(p)[::-1]
+        out.append(p)
+    return out
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_most_likely_with_criteria_matches_exhaustive_sort(seed):
+    from oracle.pts import most_likely_bruteforce
+    sp = _small_probs(100 + seed)
+    allow = {(s, k) for s in range(len(sp)) for k in range(1, len(sp[s])) if (s + k + seed) % 3}
+    for crit in ({}, {"min_errors": 2}, {"max_errors": 2}, {"parity": "odd"}, {"parity": "even", "min_errors": 1}):
+        for a in (None, allow):
+            r1, s1 = most_likely(sp, 9, allow=a, **crit)
+            r2, s2 = most_likely_bruteforce(sp, 9, allow=a, **crit)
+            assert r1 == r2 and s1 == s2, (crit, a is None)
+
+
+def test_selection_special_cases():
+    from oracle.pts import select_records
+    sp = _small_probs(7)
+    every = {(s, k) for s in range(len(sp)) for k in range(1, len(sp[s]))}
+    base = proportional(sp, 3, 1, 200)
+    assert proportional(sp, 3, 1, 200, allow=every) == base        # allowing all changes nothing
+    recs, counts = proportional(sp, 3, 1, 200, allow=set())
+    assert recs == [()] and counts == [200]                        # allowing none: the error-free record
+    # an operator outside `allow` maps to operator 0, draw by draw
+    drop = {(0, 1), (3, 1)}
+    r_all, _ = proportional(sp, 3, 1, 200, merge=False)
+    r_sel, _ = proportional(sp, 3, 1, 200, merge=False, allow=every - drop)
+    assert r_sel == [tuple(x for x in r if x not in drop) for r in r_all]
+    # record filters drop whole records with their draws
+    kept, kc = select_records(base[0], base[1], parity="odd", max_errors=3)
+    assert all(len(r) % 2 == 1 and len(r) <= 3 for r in kept)
+    assert sum(kc) == sum(c for r, c in zip(*base) if len(r) % 2 == 1 and len(r) <= 3)

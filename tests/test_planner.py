@@ -130,3 +130,78 @@ def test_adjoint_register_schedule_terminates():
     plan = P.ptsbe_plan(circ, precision="c64")
     assert time.perf_counter() - t0 < 10
     assert plan.info["n_params"] > 0
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_selection_criteria_match_oracle(seed):
+    """Selection criteria (gate type, location, error type, error count and its
+    parity) give the oracle's records, counts, shots and p_alpha in every mode."""
+    from oracle.pts import select_records
+    rng = np.random.default_rng(50 + seed)
+    circ = random_small_circuit(6, 50, rng, p1=0.15, p2=0.2)
+    plan = P.ptsbe_plan(circ)
+    sp = site_probs(circ)
+    flags = P.site_selection(plan, qubits=range(1, 6), ops=range(0, 2 * len(circ["ops"]) // 3), kraus=(1, 2, 5, 7))
+    off = np.concatenate([[0], np.cumsum([len(p) for p in sp])])
+    allow = {(s, k) for s in range(len(sp)) for k in range(1, len(sp[s])) if flags[off[s] + k]}
+    assert 0 < len(allow) < sum(len(p) - 1 for p in sp)
+    for crit in ({}, {"max_errors": 2}, {"min_errors": 1, "parity": "odd"}, {"parity": "even"}):
+        kw = dict(kraus_allow=flags, **crit)
+        ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=400, total_shots=9999, seed=seed, cfg=3, **kw)
+        g = ts.get()
+        recs, counts = select_records(*proportional(sp, seed, 3, 400, allow=allow), **crit)
+        assert g["records"] == recs and list(g["count"]) == counts
+        assert list(g["m"]) == allocate_multiplicity(counts, sum(counts), 9999)
+        assert list(g["p"]) == [joint_prob(r, sp) for r in recs]
+        ts = P.ptsbe_sample_kraus(plan, "alg2_literal", n_draws=150, nshots=5, seed=seed, cfg=3, **kw)
+        recs, _ = alg2_literal(sp, seed, 3, 150, 5, allow=allow)
+        recs, _ = select_records(recs, [1] * len(recs), **crit)
+        assert ts.get()["records"] == recs
+        ts = P.ptsbe_sample_kraus(plan, "most_likely", k_max=40, total_shots=10**5, **kw)
+        recs, _ = most_likely(sp, 40, allow=allow, **crit)
+        assert ts.get()["records"] == recs
+
+
+def test_selection_by_gate_type_on_tagged_rules():
+    """Errors only after CZ gates (gate type) of the brick circuit whose noise
+    comes from tag rules; most-likely and proportional records carry no error
+    after a U3."""
+    from workloads.circuits import brick_circuit
+    circ = brick_circuit(6, 4, np.random.default_rng(2), 0.05, 0.1)
+    plan = P.ptsbe_plan(circ)
+    sp = site_probs(circ)
+    flags = P.site_selection(plan, tags=["CZ"], origins=["after_tag"])
+    off = np.concatenate([[0], np.cumsum([len(p) for p in sp])])
+    allow = {(s, k) for s in range(len(sp)) for k in range(1, len(sp[s])) if flags[off[s] + k]}
+    two_q = {s for s in range(len(sp)) if len(sp[s]) == 16}
+    assert {s for s, _ in allow} == two_q           # CZ sites are the 2-qubit depolarizing ones
+    ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=300, total_shots=3000, seed=4, cfg=2, kraus_allow=flags)
+    recs, counts = proportional(sp, 4, 2, 300, allow=allow)
+    assert ts.get()["records"] == recs and all(s in two_q for r in recs for s, _ in r)
+    ts = P.ptsbe_sample_kraus(plan, "most_likely", k_max=25, total_shots=10**4, kraus_allow=flags)
+    assert ts.get()["records"] == most_likely(sp, 25, allow=allow)[0]
+
+
+def test_pauli_twirl_matches_oracle_and_plans_twirled_channels():
+    """ptsbe_pauli_twirl against the oracle's definition on random CPTP channels,
+    and a plan with PTSBE_PLAN_TWIRL: its sites carry the twirled channel's
+    probabilities (the plain plan rejects the channel)."""
+    from oracle.channels import pauli_twirl, twirled
+    rng = np.random.default_rng(21)
+    for nq, nk in ((1, 2), (1, 4), (2, 3)):
+        d = 2 ** nq
+        a = rng.normal(size=(nk * d, d)) + 1j * rng.normal(size=(nk * d, d))
+        q, _ = np.linalg.qr(a)
+        K = [q[k * d:(k + 1) * d, :] for k in range(nk)]
+        got = P.pauli_twirl({"kraus": K})
+        assert np.allclose(got, pauli_twirl(K), rtol=0, atol=1e-14)
+    ad = {"name": "amplitude_damping", "gamma": 0.3, "nq": 1}
+    circ = {"n_qubits": 3, "channels": [ad], "rules": [{"when": "after_tag", "tag": "H", "channel": 0}],
+            "params": [], "ops": [{"kind": "gate", "name": "H", "qubits": (q,), "params": (), "tag": "H"}
+                                  for q in range(3)]}
+    with pytest.raises(P.PtsbeError):
+        P.ptsbe_plan(circ)
+    plan = P.ptsbe_plan(circ, twirl=True)
+    ref = site_probs(dict(circ, channels=[twirled(ad)]))
+    got, _ = plan.site_probs()
+    assert len(got) == 3 and all(np.allclose(a, b, rtol=0, atol=1e-15) for a, b in zip(got, ref))
