@@ -1,5 +1,8 @@
+import gc
 import os
 import sys
+
+import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
@@ -9,3 +12,16 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: CPU test that takes more than a few seconds")
+
+
+@pytest.fixture(autouse=True)
+def _release_device_memory(request):
+    """After each GPU test, drop its buffers and return torch's cached device
+    blocks, so that the large-state tests find the memory free."""
+    yield
+    if request.node.get_closest_marker("gpu") is None:
+        return
+    torch = sys.modules.get("torch")
+    if torch is not None and torch.cuda.is_available():
+        gc.collect()
+        torch.cuda.empty_cache()

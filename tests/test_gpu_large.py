@@ -5,6 +5,7 @@ expectation values of Z strings against the closed form, and, for the
 entangling 24/26/28-qubit brick workloads, compiled against generic kernels
 and the bookkeeping of shots and trajectory tags."""
 
+import gc
 import math
 
 import numpy as np
@@ -101,6 +102,8 @@ def test_product_35q_on_one_gpu():
     plan = P.ptsbe_plan(circ)
     ts = P.ptsbe_trajset_from_records(plan, [()], [1000000])
     need = P.ptsbe_workspace_size(plan, ts, mode="shots") + 16 * 1000000
+    gc.collect()                  # earlier tests' buffers: free them and return torch's cached blocks
+    torch.cuda.empty_cache()
     free, _ = torch.cuda.mem_get_info()
     log(f"[35q product] workspace {need / 2**30:.1f} GiB, device free {free / 2**30:.1f} GiB")
     if free < need + (1 << 30):
