@@ -552,7 +552,17 @@ __device__ __forceinline__ void block_prob_scan(const ScanArgs<V>& a) {
   V* st = a.states + (uint64_t)blockIdx.y * a.N;
   const uint64_t e0 = (uint64_t)b * a.per_block;
   const uint32_t E = a.per_block, per = a.per_thread, tid = threadIdx.x;
-  for (uint32_t e = tid; e < E; e += blockDim.x) sh[scan_pad(e)] = norm2(st[e0 + e]);
+  if (E == kScanBlock) {
+    // full block: all 16 loads of a thread in flight before the first use
+    constexpr uint32_t kPer = kScanBlock / 256;
+    double w[kPer];
+#pragma unroll
+    for (uint32_t i = 0; i < kPer; ++i) w[i] = norm2(st[e0 + tid + 256u * i]);
+#pragma unroll
+    for (uint32_t i = 0; i < kPer; ++i) sh[scan_pad(tid + 256u * i)] = w[i];
+  } else {
+    for (uint32_t e = tid; e < E; e += blockDim.x) sh[scan_pad(e)] = norm2(st[e0 + e]);
+  }
   __syncthreads();
   const bool active = tid * per < E;
   double v[16];
@@ -573,7 +583,12 @@ __device__ __forceinline__ void block_prob_scan(const ScanArgs<V>& a) {
     for (uint32_t i = 0; i < per; ++i) sh[scan_pad(tid * per + i)] = off + (ex + v[i]);
   __syncthreads();
   double* out = a.cdf ? a.cdf + (uint64_t)blockIdx.y * a.N : reinterpret_cast<double*>(st);
-  for (uint32_t e = tid; e < E; e += blockDim.x) out[e0 + e] = sh[scan_pad(e)];
+  if (E == kScanBlock) {
+#pragma unroll
+    for (uint32_t i = 0; i < kScanBlock / 256; ++i) out[e0 + tid + 256u * i] = sh[scan_pad(tid + 256u * i)];
+  } else {
+    for (uint32_t e = tid; e < E; e += blockDim.x) out[e0 + e] = sh[scan_pad(e)];
+  }
 }
 
 // partial[t * nblk + b] = sum over block b of |psi|^2 (FP64).
