@@ -87,8 +87,9 @@ def main():
                     help="only print the kernel fingerprint of the 20-qubit workload's plan (host only)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 2 GiB device copy (calibrates FETCH_SIZE / WRITE_SIZE counters)")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c4", "c5"],
-                    help="c2: the 20-qubit headline workload; c4: the 24/26/28-qubit mixed batch and the "
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"],
+                    help="c2: the 20-qubit headline workload; c3: the surface-code job (10^9 shots); "
+                         "c4: the 24/26/28-qubit mixed batch and the "
                          "33- and 35-qubit trajectories; c5: the adjoint gradient of the 16-qubit ansatz")
     args = ap.parse_args()
     if args.fingerprint:
@@ -118,6 +119,8 @@ def main():
         return bench_c4(args)
     if args.workload == "c5":
         return bench_c5(args)
+    if args.workload == "c3":
+        return bench_c3(args)
 
     import numpy as np
     import torch
@@ -359,6 +362,72 @@ def bench_c4(args):
             f"{tm[6] / (tm[0] * 1e-3) / 1e9:.0f} GB/s in the passes)")
         del ws, out
         torch.cuda.empty_cache()
+    print(json.dumps(result))
+
+
+def bench_c3(args):
+    """The surface-code memory experiment: 17 qubits (9 data + 8 ancilla), 5
+    rounds with measure-resets, the 4096 most likely Kraus combinations sharing
+    10^9 shots (reweighted allocation), every shot tagged with its trajectory;
+    one step = plan tables uploaded, all trajectories prepared (measure-reset
+    records decided on the device) and all 10^9 shots drawn into device buffers."""
+    import numpy as np
+    import torch
+
+    import paper_2504_16297_amd as P
+    from workloads import c3_workload
+
+    torch.cuda.set_device(0)
+    wl = c3_workload()
+    pts = wl["pts"]
+    plan = P.ptsbe_plan(wl["circuit"], precision=wl["precision"])
+    t0 = time.perf_counter()
+    ts = P.ptsbe_sample_kraus(plan, "most_likely", k_max=pts["k_max"], total_shots=pts["total_shots"],
+                              seed=wl["seed"], cfg=wl["cfg"])
+    t_pts = time.perf_counter() - t0
+    g = ts.get()
+    S = int(g["total_shots"])
+    B = len(g["m"])
+    n_kernels, t_compile = P.ptsbe_plan_compile(plan)
+    ws = torch.empty(P.ptsbe_workspace_size(plan, ts, mode="shots"), dtype=torch.uint8, device="cuda")
+    out = {"bits": torch.empty(S, dtype=torch.int32, device="cuda"),
+           "traj": torch.empty(S, dtype=torch.int32, device="cuda"),
+           "mr_bits": torch.empty(max(1, B * plan.info["n_measure"]), dtype=torch.uint8, device="cuda")}
+    stream = torch.cuda.current_stream()
+    log(f"[bench c3] {B} trajectories, {S} shots, {plan.info['n_passes']} passes, covered probability "
+        f"{float(np.sum(g['p'])):.4f}, PTS {t_pts:.2f} s")
+
+    def step(timing=None):
+        P.ptsbe_run_batch(plan, ts, mode="shots", seed=wl["seed"], cfg=wl["cfg"], workspace=ws, out=out,
+                          stream=stream, timing=timing)
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"[bench c3] warmup {i + 1}/{args.warmup} done")
+    timings = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        tm = np.zeros(10)
+        step(tm)
+        timings.append(tm)
+        log(f"[bench c3] step {i + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    T = np.sum(timings, axis=0)
+    value = S * args.steps / dt
+    sampler_gbs = S * 8 * args.steps / (T[4] * 1e-3) / 1e9
+    result = {"metric": "shots/s of the surface-code job (10^9 shots with trajectory tags)", "value": value,
+              "unit": "shots/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+              "ms_per_step": dt * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
+              "vs_baseline": None, "dtype": "c64 (fp32 state, fp64 CDF)", "data": "synthetic",
+              "config": {"workload": wl["name"], "trajectories": B, "total_shots": S},
+              "stages_ms_per_step": {"passes": T[0] / args.steps, "measure_reset": T[2] / args.steps,
+                                     "scan": T[3] / args.steps, "sampler": T[4] / args.steps},
+              "sampler_output_gbs": sampler_gbs, "pts_s": t_pts, "compile_s": t_compile,
+              "compiled_kernels": n_kernels}
+    log(f"[bench c3] {dt * 1e3 / args.steps:.1f} ms/step, {value:.4g} shots/s; sampler "
+        f"{T[4] / args.steps:.1f} ms ({sampler_gbs:.0f} GB/s of shot words and tags)")
     print(json.dumps(result))
 
 

@@ -830,19 +830,34 @@ template <typename V>
 __global__ __launch_bounds__(256) void k_marginal(MarginalArgs<V> a) {
   const V* st = a.states + (uint64_t)blockIdx.y * a.N;
   const uint64_t e0 = (uint64_t)blockIdx.x * a.per_block;
+  // sums in registers: every index into s is a compile-time constant
   double s[kMaxGroup + 1];
+#pragma unroll
   for (int j = 0; j <= kMaxGroup; ++j) s[j] = 0.0;
-  for (uint32_t i = threadIdx.x; i < a.per_block; i += blockDim.x) {
-    const uint64_t x = e0 + i;
-    const double w = norm2(st[x]);
+  auto add = [&](uint64_t x, double w) {
     s[0] += w;
-    for (uint32_t j = 0; j < a.nq; ++j)
-      if ((x >> a.q[j]) & 1) s[j + 1] += w;
+#pragma unroll
+    for (int j = 0; j < kMaxGroup; ++j)
+      if (j < (int)a.nq && ((x >> a.q[j]) & 1)) s[j + 1] += w;
+  };
+  if (a.per_block == kScanBlock) {
+    // full block: a thread's 16 loads in flight before the first use (same order of sums)
+    constexpr uint32_t kPer = kScanBlock / 256;
+    double w[kPer];
+#pragma unroll
+    for (uint32_t i = 0; i < kPer; ++i) w[i] = norm2(st[e0 + threadIdx.x + 256u * i]);
+#pragma unroll
+    for (uint32_t i = 0; i < kPer; ++i) add(e0 + threadIdx.x + 256u * i, w[i]);
+  } else {
+    for (uint32_t i = threadIdx.x; i < a.per_block; i += blockDim.x) add(e0 + i, norm2(st[e0 + i]));
   }
-  for (uint32_t j = 0; j <= a.nq; ++j) {
-    double ex, tot;
-    block_excl_scan(s[j], &ex, &tot);
-    if (threadIdx.x == 0) a.partial[((uint64_t)blockIdx.y * a.nblk + blockIdx.x) * (kMaxGroup + 1) + j] = tot;
+#pragma unroll
+  for (int j = 0; j <= kMaxGroup; ++j) {
+    if (j <= (int)a.nq) {  // uniform over the block
+      double ex, tot;
+      block_excl_scan(s[j], &ex, &tot);
+      if (threadIdx.x == 0) a.partial[((uint64_t)blockIdx.y * a.nblk + blockIdx.x) * (kMaxGroup + 1) + j] = tot;
+    }
   }
 }
 
