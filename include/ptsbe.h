@@ -209,6 +209,18 @@ ptsbe_status ptsbe_plan_get_sites(ptsbe_plan_t plan, uint32_t* offsets, double* 
 enum { PTSBE_SITE_NOISE_OP = 0, PTSBE_SITE_AFTER_TAG = 1, PTSBE_SITE_BEFORE_MEASURE = 2,
        PTSBE_SITE_BEFORE_READOUT = 3 };
 ptsbe_status ptsbe_plan_get_site_ops(ptsbe_plan_t plan, uint32_t* op_index, uint32_t* tag, uint32_t* origin);
+/* The record entries of a trajectory (n_measure of them, in circuit order):
+ * measure-resets (outcome bit) and state-dependent channel steps (chosen Kraus
+ * index).  channel[r] = the entry's channel index, or 0xffffffff for a
+ * measure-reset; gidx[r] = the word of the channel decision's uniform in the
+ * stream [seed, 4 << 56 | cfg << 48 | alpha] (0 for measure-resets).  A
+ * state-dependent channel is a 1-qubit channel that is not a unitary mixture
+ * but has diagonal K_k^dagger K_k (amplitude damping): it is resolved when the
+ * trajectory's state reaches it (Algorithm 1's state-dependent branch), with
+ * p_k = (K_k^dagger K_k)_00 P(q = 0) + (K_k^dagger K_k)_11 P(q = 1) and k the
+ * smallest index with u < p_0 + ... + p_k (the last with p_k > 0 past the end),
+ * then K_k / sqrt(p_k).  Arrays have n_measure entries; either may be NULL. */
+ptsbe_status ptsbe_plan_get_record_info(ptsbe_plan_t plan, uint32_t* channel, uint32_t* gidx);
 void ptsbe_plan_destroy(ptsbe_plan_t plan);
 
 /* ---------------------------------------------------- pre-trajectory sampling */

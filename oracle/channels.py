@@ -145,3 +145,20 @@ def pauli_transfer_diagonal(kraus):
         EP = sum(K @ P @ K.conj().T for K in kraus)
         out[i] = np.trace(P.conj().T @ EP).real / d
     return out
+
+
+def general_channel(kraus, tol=1e-12):
+    """A channel that is not a unitary mixture but acts on one qubit with every
+    K_k^dagger K_k diagonal is resolved when the trajectory's state reaches it
+    (Algorithm 1's state-dependent branch): p_k = d0[k] P(q=0) + d1[k] P(q=1).
+    Returns (d0, d1), or None for any other channel."""
+    if unitary_mixture(kraus, tol) is not None or kraus[0].shape != (2, 2):
+        return None
+    d0, d1 = [], []
+    for K in kraus:
+        m = K.conj().T @ K
+        if abs(m[0, 1]) > tol or abs(m[1, 0]) > tol:
+            return None
+        d0.append(float(m[0, 0].real))
+        d1.append(float(m[1, 1].real))
+    return d0, d1

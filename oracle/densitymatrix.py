@@ -1,7 +1,7 @@
 """Exact density-matrix evolution for small circuits (Sec. 2.1: 2^n x 2^n).
 
 rho <- G rho G^dagger for a gate; rho <- sum_k K_k rho K_k^dagger at a noise
-site; measure-reset on q is the channel {|0><0|, |0><1|} on q; PROJECT0 is
+site (pre-sampled or state-dependent alike); measure-reset on q is the channel {|0><0|, |0><1|} on q; PROJECT0 is
 |0><0| followed by division by the trace.  Operators are lifted to the full
 space with the brute-force builder of ``gates`` (n <= 8).
 """
@@ -32,6 +32,12 @@ def evolve(circuit, params=None):
             acc = np.zeros_like(rho)
             for K in kraus_ops(ch):
                 F = full_unitary(n, K, st[2])
+                acc += F @ rho @ F.conj().T
+            rho = acc
+        elif kind == "gch":
+            acc = np.zeros_like(rho)
+            for K in kraus_ops(circuit["channels"][st[3]]):
+                F = full_unitary(n, K, st[1])
                 acc += F @ rho @ F.conj().T
             rho = acc
         elif kind == "mr":

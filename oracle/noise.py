@@ -11,9 +11,15 @@ Before a measure-reset op, one site per ``before_measure`` rule (rule order).
 An explicit ``noise`` op is a site at its own position.  After a gate or
 parametrised gate, one site per ``after_tag`` rule whose tag matches.  At the
 end, for each ``before_readout`` rule, one site per listed qubit, ascending.
+
+A channel that is not a unitary mixture but a 1-qubit channel with diagonal
+K^dagger K (amplitude damping) is not pre-sampled: at each of its positions
+the step list holds a ("gch", qubits, record index, channel, gch index) step,
+decided when the state reaches it; its record index shares the counter of the
+measure-resets.
 """
 
-from .channels import kraus_ops, cptp_error, unitary_mixture
+from .channels import general_channel, kraus_ops, cptp_error, unitary_mixture
 
 
 class NotCPTP(ValueError):
@@ -36,10 +42,18 @@ def expand(circuit):
     steps = []
     sites = []
     n_mr = 0
+    n_g = 0
+    general = [general_channel(kraus_ops(ch)) is not None for ch in circuit.get("channels", [])]
 
     def add_site(ch, qubits):
+        nonlocal n_mr, n_g
         if circuit["channels"][ch]["nq"] != len(qubits):
             raise ValueError("channel arity does not match the site's qubits")
+        if general[ch]:
+            steps.append(("gch", tuple(qubits), n_mr, ch, n_g))
+            n_mr += 1
+            n_g += 1
+            return
         sites.append({"channel": ch, "qubits": tuple(qubits)})
         steps.append(("site", len(sites) - 1, tuple(qubits)))
 
@@ -78,10 +92,13 @@ def site_channels(circuit):
     for ch in circuit["channels"]:
         K = kraus_ops(ch)
         if cptp_error(K) > 1e-12:
-            raise NotCPTP(ch["name"])
+            raise NotCPTP(ch.get("name", "kraus"))
         um = unitary_mixture(K)
         if um is None:
-            raise Unsupported(f"{ch['name']} is not a unitary mixture")
+            if general_channel(K) is None:
+                raise Unsupported(f"{ch.get('name', 'kraus')} is not a unitary mixture")
+            out.append(None)        # state-dependent: no pre-sampled probabilities
+            continue
         out.append(um)
     return out
 

@@ -21,8 +21,12 @@ import math
 
 import numpy as np
 
+from .channels import general_channel, kraus_ops
 from .gates import gate_matrix, rot
 from .noise import expand, site_channels
+from .rng import key1, uniforms
+
+STREAM_CHANNEL = 4   # uniforms of the state-dependent channel decisions
 
 
 class NonDeterministicMeasure(RuntimeError):
@@ -57,9 +61,30 @@ def zero_state(n):
     return psi
 
 
+def _categorical_positive(u, probs):
+    """Smallest k with u < p_0 + ... + p_k (running sum in order, p_k > 0);
+    past the end (rounding), the last k with p_k > 0."""
+    c = 0.0
+    last = 0
+    for k, p in enumerate(probs):
+        c += p
+        if p > 0.0:
+            last = k
+            if u < c:
+                return k
+    return last
+
+
 def run_record(circuit, record, params=None, steps_sites=None, chans=None,
-               kraus_unnormalised=False, mr_tol=1e-6):
+               kraus_unnormalised=False, mr_tol=1e-6, be_key=None):
     """Prepare psi_alpha for one record.  Returns (psi, mr_bits).
+
+    State-dependent channel steps ("gch") are decided here (Algorithm 1's
+    state-dependent branch): p_k = d0[k] P(q=0) + d1[k] P(q=1) from the state,
+    u = word gidx of the stream [seed, key1(4, cfg, alpha)] for ``be_key`` =
+    (seed, cfg, alpha), k by the running sum, then K_k / sqrt(p_k); the chosen k
+    joins the returned record entries (in record index order with the
+    measure-reset bits).
 
     With ``kraus_unnormalised`` the site operators are K_k = sqrt(p_k) U_k, so
     that ||psi||^2 ends as p_alpha (used as an invariant check)."""
@@ -105,6 +130,19 @@ def run_record(circuit, record, params=None, steps_sites=None, chans=None,
             proj = np.array([[1, 0], [0, 0]], dtype=np.complex128)
             psi = apply(psi, n, proj, (q,))
             psi = psi / math.sqrt(math.fsum(psi.real ** 2 + psi.imag ** 2))
+        elif kind == "gch":
+            q = st[1][0]
+            K = kraus_ops(circuit["channels"][st[3]])
+            d0, d1 = general_channel(K)
+            one, tot = marginal_one(psi, n, q)
+            p1 = one / tot
+            probs = [d0[k] * (1.0 - p1) + d1[k] * p1 for k in range(len(K))]
+            seed, cfg, alpha = be_key
+            u = uniforms(seed, key1(STREAM_CHANNEL, cfg, alpha), st[4] + 1)[st[4]]
+            k = _categorical_positive(u, probs)
+            psi = apply(psi, n, K[k] / math.sqrt(probs[k]), (q,))
+            psi = psi / math.sqrt(math.fsum(psi.real ** 2 + psi.imag ** 2))
+            bits.append(k)
         else:
             raise ValueError(kind)
     return psi, bits

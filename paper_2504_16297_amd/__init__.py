@@ -87,6 +87,14 @@ class Plan:
         check(lib().ptsbe_plan_get_sites(self.handle, off.ctypes.data, p.ctypes.data, q.ctypes.data))
         return [p[off[s]:off[s + 1]].copy() for s in range(ns)], q[:2 * ns].reshape(-1, 2)
 
+    def record_info(self):
+        """Per record entry: (channel index or -1 for a measure-reset, uniform word)."""
+        nm = self.info["n_measure"]
+        ch = np.zeros(max(1, nm), dtype=np.uint32)
+        gi = np.zeros(max(1, nm), dtype=np.uint32)
+        check(lib().ptsbe_plan_get_record_info(self.handle, C.c_void_p(ch.ctypes.data), C.c_void_p(gi.ctypes.data)))
+        return [(-1 if c == 0xFFFFFFFF else int(c), int(g)) for c, g in zip(ch[:nm], gi[:nm])]
+
     def __del__(self):
         h = getattr(self, "handle", None)
         if h:

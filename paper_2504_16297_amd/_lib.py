@@ -114,6 +114,7 @@ _SIGS = {
                                   C.c_void_p]),
     "ptsbe_run_status": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "ptsbe_pauli_twirl": (C.c_int, [C.c_uint32, C.c_void_p, C.c_uint32, C.c_void_p]),
+    "ptsbe_plan_get_record_info": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "ptsbe_plan_get_site_ops": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "ptsbe_unique_workspace_size": (C.c_int, [C.c_void_p, C.c_uint32, C.POINTER(C.c_size_t)]),
     "ptsbe_unique_shots": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p,

@@ -133,6 +133,20 @@ ptsbe_status ptsbe_plan_get_site_ops(ptsbe_plan_t plan, uint32_t* op_index, uint
   return PTSBE_OK;
 }
 
+ptsbe_status ptsbe_plan_get_record_info(ptsbe_plan_t plan, uint32_t* channel, uint32_t* gidx) {
+  if (!plan) return fail(PTSBE_E_ARG, "null plan");
+  const Plan& P = *plan->plan;
+  std::vector<uint32_t> ch(P.n_measure, 0xffffffffu), gi(P.n_measure, 0u);
+  for (const Step& st : P.steps)
+    if (st.kind == ST_GCH) {
+      ch[st.mr] = (uint32_t)st.chan;
+      gi[st.mr] = (uint32_t)st.gidx;
+    }
+  if (channel) std::copy(ch.begin(), ch.end(), channel);
+  if (gidx) std::copy(gi.begin(), gi.end(), gidx);
+  return PTSBE_OK;
+}
+
 void ptsbe_plan_destroy(ptsbe_plan_t plan) { delete plan; }
 
 ptsbe_status ptsbe_sample_kraus(ptsbe_plan_t plan, const ptsbe_pts_opts* opts, ptsbe_trajset_t* out) {

@@ -35,9 +35,14 @@ struct Channel {
   // 2-qubit channels whose every U_k is a product A_k (x) B_k (B on matrix bit 0):
   bool product = false;
   std::vector<Mat> f0, f1;     // factors on matrix bit 0 / bit 1 (2x2 each)
+  // State-dependent 1-qubit channel (not a unitary mixture) whose K_k^dagger K_k
+  // are diagonal: p_k = d0[k] P(q = 0) + d1[k] P(q = 1), resolved when the
+  // trajectory's state reaches it; U holds the raw Kraus operators.
+  bool general = false;
+  std::vector<double> d0, d1;
 };
 
-enum StepKind { ST_GATE, ST_PARAM, ST_SITE, ST_MR, ST_P0, ST_DOT };
+enum StepKind { ST_GATE, ST_PARAM, ST_SITE, ST_MR, ST_P0, ST_DOT, ST_GCH };
 
 struct Step {
   StepKind kind;
@@ -48,7 +53,9 @@ struct Step {
   bool dagger = false;         // apply the adjoint of the operation (reverse sweep)
   int param = -1, gen = 0;     // PARAM, DOT
   int site = -1;               // SITE
-  int mr = -1;                 // MR record index
+  int mr = -1;                 // MR, GCH: record index
+  int chan = -1;               // GCH: channel
+  int gidx = -1;               // GCH: index among the state-dependent channel steps
   int dot = -1;                // DOT: index of the gradient contribution
 };
 
@@ -112,6 +119,15 @@ struct ExecStep {
   std::vector<int> mr_index;   // measurement: record indices
 };
 
+// Decision data of the record entries (measure-resets and state-dependent
+// channels), uploaded with every run: rec_chan[r] = offset into chan_param of
+// entry r's channel, or 0xffffffff for a measure-reset; rec_gidx[r] = its
+// uniform's word; chan_param per channel: K, then d0[0..K), d1[0..K).
+struct RecordInfo {
+  std::vector<uint32_t> rec_chan, rec_gidx;
+  std::vector<double> chan_param;
+};
+
 // A fused device program: steps, the tile passes and execution steps built
 // from them, and the slots each noise site touches.
 struct Program {
@@ -129,7 +145,9 @@ struct Plan {
   int tile_bits = 12;
   int min_fill = 2;            // phase scheduler: fewest 2x2 matrices worth a partial wave
   int n_params = 0;
-  int n_measure = 0;
+  int n_measure = 0;           // record entries: measure-resets and state-dependent channel steps
+  int n_general = 0;           // state-dependent channel steps
+  RecordInfo rec_info;
   std::vector<Channel> channels;
   std::vector<Step> steps;
   std::vector<Site> sites;

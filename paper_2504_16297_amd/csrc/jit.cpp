@@ -407,6 +407,24 @@ struct Gen {
     o << "  }\n";
   }
 
+  // state-dependent channel: K_k / sqrt(p_k) on register position j, k and the
+  // factor from the trajectory's record entry, K_0.. at the slot's pool offset
+  void kr(const DOp& op) {
+    const int j = reg_pos(op.a);
+    if (j < 0 || dual) {
+      fail("state-dependent channel on a non-register bit or in an adjoint sweep");
+      return;
+    }
+    o << "  {\n    const uint64_t ri = (uint64_t)t * a.n_measure + " << op.slot[0] << "u;\n"
+      << "    const T sc = (T)a.mr_norm[ri];\n"
+      << "    const V* kp = a.pool + slot_off[" << op.slot[1] << "] + 4u * a.mr_bits[ri];\n"
+      << "    V m0 = kp[0], m1 = kp[1], m2 = kp[2], m3 = kp[3];\n"
+      << "    m0.x *= sc; m0.y *= sc; m1.x *= sc; m1.y *= sc; m2.x *= sc; m2.y *= sc; m3.x *= sc; m3.y *= sc;\n";
+    apply_pending_to("m0", "m1", "m2", "m3");
+    gate_body(j, false);
+    o << "  }\n";
+  }
+
   void phase(const DOp& op) {
     if (!signs.empty()) {
       bool live = false;
@@ -710,6 +728,7 @@ std::string gen_pass(const Pass& ps, int n, int precision, const std::string& na
       case DOP_D2: g.diag(op); break;
       case DOP_M2: g.m2(op); break;
       case DOP_MR: g.mr(op); break;
+      case DOP_KR: g.kr(op); break;
       case DOP_PHASE: g.phase(op); break;
       case DOP_DOT: g.dot(op); break;
       default: g.fail("unknown operation type " + std::to_string(op.type));

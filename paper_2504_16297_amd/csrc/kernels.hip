@@ -175,6 +175,25 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs<V> a) {
           tile[L] = v;
         }
       }
+    } else if (op.type == DOP_KR) {
+      // state-dependent channel: K_k / sqrt(p_k), k and the factor from the record
+      const uint64_t ri = (uint64_t)t * a.n_measure + op.slot[0];
+      const typename Real<V>::T sc = (typename Real<V>::T)a.mr_norm[ri];
+      const V* m = a.pool + slot_off[op.slot[1]] + 4u * a.mr_bits[ri];
+      V mm[4];
+      for (int e = 0; e < 4; ++e) {
+        mm[e] = m[e];
+        mm[e].x *= sc;
+        mm[e].y *= sc;
+      }
+      const uint32_t bit = 1u << op.a, lo = bit - 1;
+      for (uint32_t pr = tid; pr < nt / 2; pr += blockDim.x) {
+        const uint32_t i0 = ((pr & ~lo) << 1) | (pr & lo);
+        const uint32_t i1 = i0 | bit;
+        const V x0 = tile[i0], x1 = tile[i1];
+        tile[i0] = cfma2(mm[0], x0, mm[1], x1);
+        tile[i1] = cfma2(mm[2], x0, mm[3], x1);
+      }
     } else if (op.type == DOP_MR) {
       const uint64_t ri = (uint64_t)t * a.n_measure + op.slot[0];
       const uint32_t b = a.mr_bits[ri];
@@ -474,6 +493,22 @@ __global__ __launch_bounds__(256) void k_pass_reg(PassArgs<V> a) {
       else if (la == R[1]) reg_mr<1>(s, b, sc);
       else if (la == R[2]) reg_mr<2>(s, b, sc);
       else reg_mr<3>(s, b, sc);
+    } else if (type == DOP_KR) {
+      const uint64_t ri = (uint64_t)t * a.n_measure + op.slot[0];
+      const typename Real<V>::T sc = (typename Real<V>::T)a.mr_norm[ri];
+      const V* m = a.pool + slot_off[op.slot[1]] + 4u * a.mr_bits[ri];
+      V mm[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        mm[e] = m[e];
+        mm[e].x *= sc;
+        mm[e].y *= sc;
+      }
+      const uint32_t la = op.a;
+      if (la == R[0]) reg_1q<0>(s, mm[0], mm[1], mm[2], mm[3]);
+      else if (la == R[1]) reg_1q<1>(s, mm[0], mm[1], mm[2], mm[3]);
+      else if (la == R[2]) reg_1q<2>(s, mm[0], mm[1], mm[2], mm[3]);
+      else reg_1q<3>(s, mm[0], mm[1], mm[2], mm[3]);
     } else if (type == DOP_PHASE) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) tile[lds_swz(reg_local(Lt, rb, r))] = s.v[r];
@@ -872,6 +907,43 @@ __global__ void k_mr_decide(MrDecideArgs a) {
     one += p[j + 1];
   }
   const double p1 = one / tot;
+  const uint32_t r = a.idx[j];
+  const uint32_t co = a.rec_chan ? a.rec_chan[r] : 0xffffffffu;
+  if (co != 0xffffffffu) {
+    // state-dependent channel: p_k = d0[k] P(q=0) + d1[k] P(q=1); the uniform is
+    // word rec_gidx[r] of the stream [seed, key1(4, cfg, alpha)]
+    const double* cp = a.chan_param + co;
+    const uint32_t K = (uint32_t)cp[0];
+    const uint64_t alpha = a.alpha0 + a.t0 + tb;
+    const uint64_t g = a.rec_gidx[r];
+    const U64x4 w = philox4x64_10(g / 4 + 1, 0, 0, 0, a.seed, stream_key1(4, a.cfg, alpha));
+    const double u = word_to_uniform(w.v[g % 4]);
+    // smallest k with u < p_0 + ... + p_k; past the end (rounding), the last k with p_k > 0
+    uint32_t k = 0, k_last = 0;
+    double c = 0.0, pk = 0.0, p_last = 0.0;
+    bool found = false;
+    for (uint32_t kk = 0; kk < K; ++kk) {
+      const double p = cp[1 + kk] * (1.0 - p1) + cp[1 + K + kk] * p1;
+      c += p;
+      if (p > 0.0) {
+        k_last = kk;
+        p_last = p;
+      }
+      if (!found && u < c && p > 0.0) {
+        k = kk;
+        pk = p;
+        found = true;
+      }
+    }
+    if (!found) {
+      k = k_last;
+      pk = p_last;
+    }
+    const uint64_t ri = (uint64_t)(a.t0 + tb) * a.n_measure + r;
+    a.mr_bits[ri] = (uint8_t)k;
+    a.mr_norm[ri] = j == 0 ? 1.0 / sqrt(pk * tot) : 1.0 / sqrt(pk);
+    return;
+  }
   const uint32_t bit = p1 > 0.5 ? 1u : 0u;
   const double pb = bit ? p1 : 1.0 - p1;
   if (fmin(p1, 1.0 - p1) > a.tol) atomicOr(a.status, 1u);

@@ -80,6 +80,12 @@ struct MrDecideArgs {
   uint32_t t0;
   uint32_t n_measure;
   uint32_t idx[kMaxGroup];
+  // state-dependent channels among the record entries (null if the plan has none)
+  const uint32_t* rec_chan;   // per record entry: offset into chan_param, or 0xffffffff (measure-reset)
+  const uint32_t* rec_gidx;   // per record entry: word of its uniform
+  const double* chan_param;   // per channel: K, d0[0..K), d1[0..K)
+  uint64_t seed, alpha0;
+  uint32_t cfg;
 };
 
 template <typename BitT>

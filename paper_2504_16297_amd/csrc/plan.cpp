@@ -189,10 +189,34 @@ static ptsbe_status analyse_channel(const ptsbe_channel& ch, int idx, Channel* o
         cd v(0, 0);
         for (int l = 0; l < d; ++l) v += std::conj(K[k][l * d + i]) * K[k][l * d + j];
         if (std::abs(v - (i == j ? p : 0.0)) > 1e-12) {
-          if (!twirl)
-            return fail(PTSBE_E_UNSUPPORTED, "channel " + std::to_string(idx) +
-                                                 " is not a unitary mixture; state-dependent channels are not "
-                                                 "pre-samplable (PTSBE_PLAN_TWIRL replaces them by their Pauli twirl)");
+          if (!twirl) {
+            // A state-dependent 1-qubit channel with diagonal K_k^dagger K_k is
+            // resolved when the trajectory's state reaches it (from the qubit's
+            // populations); anything else is not supported.
+            Channel g;
+            g.nq = 1;
+            g.K = ch.n_kraus;
+            g.general = ch.nq == 1;
+            for (int kk = 0; kk < g.K && g.general; ++kk) {
+              cd m[4] = {0, 0, 0, 0};
+              for (int r = 0; r < 2; ++r)
+                for (int c2 = 0; c2 < 2; ++c2)
+                  for (int l = 0; l < 2; ++l) m[r * 2 + c2] += std::conj(K[kk][l * 2 + r]) * K[kk][l * 2 + c2];
+              if (std::abs(m[1]) > 1e-12 || std::abs(m[2]) > 1e-12) g.general = false;
+              g.d0.push_back(m[0].real());
+              g.d1.push_back(m[3].real());
+              g.U.push_back(K[kk]);
+              g.p.push_back(kraus_weight(K[kk], 2));
+              g.diag.push_back(mat_is_diag(K[kk], 2));
+            }
+            if (!g.general)
+              return fail(PTSBE_E_UNSUPPORTED, "channel " + std::to_string(idx) +
+                                                   " is not a unitary mixture and not a 1-qubit channel with "
+                                                   "diagonal K^dagger K (PTSBE_PLAN_TWIRL replaces it by its "
+                                                   "Pauli twirl)");
+            *out = std::move(g);
+            return PTSBE_OK;
+          }
           // its Pauli twirl: sqrt(p_P) P for the strings with p_P > 0, in string order
           const std::vector<double> pt = pauli_twirl_probs(K, ch.nq);
           std::vector<double> flat;
@@ -286,6 +310,12 @@ static Mat part_matrix(const Plan& plan, const std::vector<Step>& steps, const P
 
 Mat slot_matrix(const Plan& plan, const std::vector<Step>& steps, const Slot& s, const double* params,
                 const std::map<int, int>& choice) {
+  if (s.type == DOP_KR) {  // the channel's Kraus operators, 4 entries each
+    const Channel& c = plan.channels[steps[s.parts[0].step].chan];
+    Mat M;
+    for (const Mat& k : c.U) M.insert(M.end(), k.begin(), k.end());
+    return M;
+  }
   int d = (s.type == DOP_M2 || s.type == DOP_D2) ? 4 : 2;
   Mat M = mat_identity(d);
   for (const Part& pt : s.parts) M = mat_mul(part_matrix(plan, steps, pt, params, choice), M, d);
@@ -382,6 +412,19 @@ struct Fuser {
       pass.ops.push_back(op);
       return;
     }
+    if (st.kind == ST_GCH) {
+      // K_k / sqrt(p_k) with k decided on the device; the slot holds K_0..K_{K-1}
+      flush(st.q[0]);
+      const int s = new_slot(DOP_KR, st.q[0], -1);
+      add_part(s, Part{si, -1});
+      DOp op{};
+      op.type = DOP_KR;
+      op.a = (uint8_t)local[st.q[0]];
+      op.slot[0] = (uint16_t)st.mr;
+      op.slot[1] = (uint16_t)s;
+      pass.ops.push_back(op);
+      return;
+    }
     if (st.nq == 1) {
       one_qubit(st.q[0], Part{si, -1});
       return;
@@ -446,6 +489,7 @@ static int op_qubits(const Pass& ps, const DOp& op, int* q) {
   switch (op.type) {
     case DOP_M1:
     case DOP_MR:
+    case DOP_KR:
     case DOP_DOT:
       q[0] = ps.tq[op.a];
       return 1;
@@ -516,7 +560,7 @@ static void schedule_phases(Pass& ps, int min_fill) {
   };
   // register bits an operation needs (4x4 matrices go through LDS and need none)
   auto local_bits = [&](const DOp& op, int* b) -> int {
-    if (op.type == DOP_M1 || op.type == DOP_MR || op.type == DOP_DOT) {
+    if (op.type == DOP_M1 || op.type == DOP_MR || op.type == DOP_KR || op.type == DOP_DOT) {
       b[0] = op.a;
       return 1;
     }
@@ -556,7 +600,7 @@ static void schedule_phases(Pass& ps, int min_fill) {
       for (int i = 0; i < nops; ++i)
         if (!done[i] && ready(i) && ps.ops[i].type == DOP_M1) (fits(ps.ops[i]) ? m1_here : m1_other) += 1;
       for (int i : wave)  // measure-resets and gradient terms in registers: never put off
-        if (ps.ops[i].type == DOP_MR || ps.ops[i].type == DOP_DOT) ++reg_others;
+        if (ps.ops[i].type == DOP_MR || ps.ops[i].type == DOP_KR || ps.ops[i].type == DOP_DOT) ++reg_others;
       if (!force_wave && reg_others == 0 && m1_here > 0 && m1_here < min_fill &&
           std::min(m1_other, (int)kRegBits) >= min_fill) {
         std::vector<int> diag;
@@ -674,7 +718,7 @@ static ptsbe_status schedule(Plan& plan, const std::vector<Step>& steps, std::ve
       for (int j = 0; j < st.nq; ++j) blk = blk || blocked[st.q[j]];
       bool can = false;
       if (!blk) {
-        if (st.kind == ST_MR && !measured[si]) {
+        if ((st.kind == ST_MR || st.kind == ST_GCH) && !measured[si]) {
           can = false;
         } else if (st.diag && st.kind != ST_MR) {
           can = true;
@@ -699,18 +743,27 @@ static ptsbe_status schedule(Plan& plan, const std::vector<Step>& steps, std::ve
       }
     }
     if (taken.empty()) {
-      // every frontier operation is an unmeasured measure-reset: measure them together
+      // every frontier operation is an undecided record entry: measure-resets are
+      // decided together (their outcomes are deterministic, so they do not
+      // change each other's marginals); a state-dependent channel only alone
+      // among channels and only once no channel step before it is pending, so
+      // that its probabilities come from the state in circuit order
       ExecStep ex;
       std::vector<char> blk(n, 0);
+      bool channel_pending = false, channel_taken = false;
       for (int si : rem) {
         const Step& st = steps[si];
         bool b = false;
         for (int j = 0; j < st.nq; ++j) b = b || blk[st.q[j]];
-        if (!b && st.kind == ST_MR && !measured[si]) {
+        const bool mr_ok = st.kind == ST_MR;
+        const bool ch_ok = st.kind == ST_GCH && !channel_pending && !channel_taken;
+        if (!b && (mr_ok || ch_ok) && !measured[si]) {
           ex.mr_qubits.push_back(st.q[0]);
           ex.mr_index.push_back(st.mr);
           measured[si] = 1;
+          channel_taken = channel_taken || st.kind == ST_GCH;
         }
+        if (st.kind == ST_GCH) channel_pending = true;
         for (int j = 0; j < st.nq; ++j) blk[st.q[j]] = 1;
       }
       if (ex.mr_qubits.empty()) return fail(PTSBE_E_UNSUPPORTED, "an operation does not fit in a tile");
@@ -806,6 +859,7 @@ void walk_frames(int n, const std::vector<Pass>& passes, const std::vector<ExecS
           break;
         case DOP_D1: f(ps.slots[op.slot[0]].q[0], FrameEvent{FE_DIAG, ex.pass, op.slot[0], 0}); break;
         case DOP_MR:
+        case DOP_KR:
         case DOP_DOT: f(ps.tq[op.a], FrameEvent{FE_BREAK, ex.pass, -1, 0}); break;
         default: break;
       }
@@ -952,6 +1006,18 @@ ptsbe_status build_plan(const ptsbe_circuit* c, const ptsbe_noise_model* nm, con
   auto add_site = [&](int ch, int nq, const int* q, uint32_t op_index, uint32_t tag,
                       uint32_t origin) -> ptsbe_status {
     if (P.channels[ch].nq != nq) return fail(PTSBE_E_ARG, "channel arity does not match the site's qubits");
+    if (P.channels[ch].general) {
+      // not pre-sampled: a record entry decided on the device (like a measure-reset)
+      Step st;
+      st.kind = ST_GCH;
+      st.nq = 1;
+      st.q[0] = q[0];
+      st.chan = ch;
+      st.gidx = P.n_general++;
+      st.mr = P.n_measure++;
+      P.steps.push_back(st);
+      return PTSBE_OK;
+    }
     Site s;
     s.channel = ch;
     s.nq = nq;
@@ -1053,7 +1119,31 @@ ptsbe_status build_plan(const ptsbe_circuit* c, const ptsbe_noise_model* nm, con
     for (int qq = 0; qq < P.n; ++qq)
       if ((a.qmask >> qq) & 1) add_site((int)a.channel, 1, &qq, 0xffffffffu, 0u, PTSBE_SITE_BEFORE_READOUT);
   }
-  if (P.n_measure > 65535) return fail(PTSBE_E_UNSUPPORTED, "too many measure-reset ops");
+  if (P.n_measure > 65535) return fail(PTSBE_E_UNSUPPORTED, "too many measure-reset and state-dependent ops");
+  if (P.n_general) {
+    for (const Step& st : P.steps)
+      if (st.kind == ST_P0)
+        return fail(PTSBE_E_UNSUPPORTED, "projections together with state-dependent channels are not supported");
+  }
+  {
+    // decision data of the record entries
+    RecordInfo& R = P.rec_info;
+    R.rec_chan.assign(P.n_measure, 0xffffffffu);
+    R.rec_gidx.assign(P.n_measure, 0u);
+    std::vector<int> chan_off(P.channels.size(), -1);
+    for (const Step& st : P.steps) {
+      if (st.kind != ST_GCH) continue;
+      if (chan_off[st.chan] < 0) {
+        const Channel& c = P.channels[st.chan];
+        chan_off[st.chan] = (int)R.chan_param.size();
+        R.chan_param.push_back((double)c.K);
+        for (int k = 0; k < c.K; ++k) R.chan_param.push_back(c.d0[k]);
+        for (int k = 0; k < c.K; ++k) R.chan_param.push_back(c.d1[k]);
+      }
+      R.rec_chan[st.mr] = (uint32_t)chan_off[st.chan];
+      R.rec_gidx[st.mr] = (uint32_t)st.gidx;
+    }
+  }
   P.n_params = max_param + 1;
   P.site_off.push_back(0);
   for (auto& s : P.sites) {
@@ -1069,7 +1159,7 @@ ptsbe_status build_plan(const ptsbe_circuit* c, const ptsbe_noise_model* nm, con
   // un-applying every parametrised rotation.  Only for circuits without
   // measure-reset / projection (state-independent unitary trajectories).
   bool unitary = true;
-  for (const Step& s : P.steps) unitary = unitary && s.kind != ST_MR && s.kind != ST_P0;
+  for (const Step& s : P.steps) unitary = unitary && s.kind != ST_MR && s.kind != ST_P0 && s.kind != ST_GCH;
   if (P.n_params > 0 && unitary) {
     Program& A = P.adj;
     int ndot = 0;

@@ -18,7 +18,7 @@ namespace {
 uint64_t a256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
 
 struct WsLayout {
-  uint64_t status, tables, routes, states, cdf, partial, offs, total, mr_partial, mr_bits, mr_norm, end;
+  uint64_t status, tables, routes, states, cdf, partial, offs, total, mr_partial, mr_bits, mr_norm, rec_info, end;
   uint32_t batch;
   uint32_t nblk, per_block, per_thread;
   bool share;
@@ -61,6 +61,8 @@ WsLayout layout_for(const Plan& P, const TrajSet& ts, uint32_t mode, uint32_t ba
   if (P.n_measure) o = a256(o + (uint64_t)batch * L.nblk * (kMaxGroup + 1) * 8);
   L.mr_bits = o; o = a256(o + std::max<uint64_t>(1, Btot * P.n_measure));
   L.mr_norm = o; o = a256(o + std::max<uint64_t>(1, Btot * P.n_measure) * 8);
+  L.rec_info = o;
+  if (P.n_general) o = a256(o + (uint64_t)P.n_measure * 8 + P.rec_info.chan_param.size() * 8);
   L.end = o;
   return L;
 }
@@ -105,6 +107,7 @@ double pass_flops_per_amp(const Pass& ps) {
       case DOP_D1: f += ps.slots[op.slot[0]].frame == FRAME_ABSORB ? 0 : 6; break;
       case DOP_D2: f += 6; break;
       case DOP_MR: f += 2; break;
+      case DOP_KR: f += 14; break;
       default: break;
     }
   }
@@ -208,6 +211,23 @@ ptsbe_status run_typed(const Plan& P, TrajSet& ts, const ptsbe_run_opts& o, uint
   uint8_t* tb = ws + L.tables;
   if (phase & PH_UPLOAD)
     CK(hipMemcpyAsync(tb, ts.table_blob.data(), ts.table_blob.size(), hipMemcpyHostToDevice, s), "table upload");
+  // decision data of state-dependent channels (plan-owned host arrays)
+  const uint32_t* d_rec_chan = nullptr;
+  const uint32_t* d_rec_gidx = nullptr;
+  const double* d_chan_param = nullptr;
+  if (P.n_general) {
+    uint8_t* ri = ws + L.rec_info;
+    const size_t nm = (size_t)P.n_measure;
+    if (phase & PH_UPLOAD) {
+      CK(hipMemcpyAsync(ri, P.rec_info.rec_chan.data(), nm * 4, hipMemcpyHostToDevice, s), "record upload");
+      CK(hipMemcpyAsync(ri + nm * 4, P.rec_info.rec_gidx.data(), nm * 4, hipMemcpyHostToDevice, s), "record upload");
+      CK(hipMemcpyAsync(ri + nm * 8, P.rec_info.chan_param.data(), P.rec_info.chan_param.size() * 8,
+                        hipMemcpyHostToDevice, s), "record upload");
+    }
+    d_rec_chan = reinterpret_cast<const uint32_t*>(ri);
+    d_rec_gidx = reinterpret_cast<const uint32_t*>(ri + nm * 4);
+    d_chan_param = reinterpret_cast<const double*>(ri + nm * 8);
+  }
   uint32_t* status = reinterpret_cast<uint32_t*>(ws + L.status);
   if (phase & PH_LAUNCH) CK(launch_fill_u32(status, 0, 4, s), "status reset");
   V* states = reinterpret_cast<V*>(ws + L.states);
@@ -304,6 +324,12 @@ ptsbe_status run_typed(const Plan& P, TrajSet& ts, const ptsbe_run_opts& o, uint
           da.nq = ma.nq;
           da.t0 = b0;
           da.n_measure = (uint32_t)P.n_measure;
+          da.rec_chan = d_rec_chan;
+          da.rec_gidx = d_rec_gidx;
+          da.chan_param = d_chan_param;
+          da.seed = o.seed;
+          da.cfg = o.cfg;
+          da.alpha0 = ts.alpha0;
           for (size_t j = g0; j < g1; ++j) {
             ma.q[j - g0] = (uint32_t)ex.mr_qubits[j];
             da.idx[j - g0] = (uint32_t)ex.mr_index[j];

@@ -24,6 +24,8 @@ enum DOpType : uint8_t {
   DOP_M1G = 8,    // register kernel: 2x2 matrix slot[j] on register position j = 0..3 (the
                   // ascending register bits); `mask` marks the non-identity positions
   DOP_SFLIP = 9,  // register kernel: apply the signs accumulated by the preceding DOP_DSIGNs
+  DOP_KR = 11,    // state-dependent channel on local bit a: K_k / sqrt(p_k) with k and the factor from
+                  // the device record entry slot[0]; the Kraus operators (4 entries each) at slot slot[1]
   DOP_DOT = 10,   // adjoint kernel: partial Im<lambda|P_a|psi> of gradient term slot[0] | slot[1] << 16,
                   // P = X/Y/Z by b = 1/2/3 on local bit a
 };

@@ -157,9 +157,29 @@ def _raw_tables(ts, params):
     return buf, offs
 
 
-def run_compiled(plan, ts, params=None, mr_tol=1e-6):
+def _channel_decision(circuit, chan, gidx, p1, be, alpha):
+    """The device's decision for a state-dependent channel entry (test side:
+    the oracle's uniforms and channel definition)."""
+    from oracle.channels import general_channel, kraus_ops
+    from oracle.rng import key1, uniforms
+    d0, d1 = general_channel(kraus_ops(circuit["channels"][chan]))
+    probs = [d0[k] * (1.0 - p1) + d1[k] * p1 for k in range(len(d0))]
+    u = uniforms(be[0], key1(4, be[1], alpha), gidx + 1)[gidx]
+    c, last, k = 0.0, 0, None
+    for kk, pp in enumerate(probs):
+        c += pp
+        if pp > 0.0:
+            last = kk
+            if k is None and u < c:
+                k = kk
+    k = last if k is None else k
+    return k, probs[k]
+
+
+def run_compiled(plan, ts, params=None, mr_tol=1e-6, circuit=None, be=(0, 0)):
     """States [B, 2^n] (normalised) after running every pass through its
-    generated kernel on the CPU."""
+    generated kernel on the CPU.  State-dependent channel entries are decided
+    as the device does, with ``circuit``'s channels and ``be`` = (seed, cfg)."""
     info = plan.info
     n = info["n_qubits"]
     N = 1 << n
@@ -188,16 +208,23 @@ def run_compiled(plan, ts, params=None, mr_tol=1e-6):
             libs[src].run_pass(blob.ctypes.data, offs.ctypes.data, p, slot_begin[p], states.ctypes.data, N, n, k,
                                NP, B, mr_bits.ctypes.data, mr_norm.ctypes.data, nm, None, None, 0)
         else:
+            rinfo = plan.record_info()
             for b in range(B):
                 w = np.abs(states[b].astype(np.complex128)) ** 2
                 tot = w.sum()
                 for j in range(int(ex["nq"])):
                     q = int(ex["q"][j])
                     p1 = w[((x >> q) & 1) == 1].sum() / tot
+                    r = int(ex["idx"][j])
+                    chan, gidx = rinfo[r]
+                    if chan >= 0:
+                        k, pk = _channel_decision(circuit, chan, gidx, p1, be, b)
+                        mr_bits[b * nm + r] = k
+                        mr_norm[b * nm + r] = 1.0 / np.sqrt(pk * tot) if j == 0 else 1.0 / np.sqrt(pk)
+                        continue
                     if min(p1, 1 - p1) > mr_tol:
                         raise RuntimeError(f"non-deterministic measure-reset on qubit {q}")
                     bit = 1 if p1 > 0.5 else 0
-                    r = int(ex["idx"][j])
                     pb = p1 if bit else 1 - p1
                     mr_bits[b * nm + r] = bit
                     mr_norm[b * nm + r] = 1.0 / np.sqrt(pb * tot) if j == 0 else 1.0 / np.sqrt(pb)

@@ -58,8 +58,14 @@ def test_channel_checks():
     # sum K^dagger K != I
     bad = {"kraus": [1.05 * np.eye(2)]}
     assert _status(P.ptsbe_plan, _one_gate(bad)) == E_NOT_CPTP
-    # CPTP but not a unitary mixture: outside batched pre-trajectory sampling
-    assert _status(P.ptsbe_plan, _one_gate({"name": "amplitude_damping", "gamma": 0.2})) == E_UNSUPPORTED
+    # CPTP, not a unitary mixture, K^dagger K not diagonal (measure X, write Z):
+    # neither pre-samplable nor resolvable from the qubit's populations
+    plus, minus = np.array([1, 1]) / np.sqrt(2), np.array([1, -1]) / np.sqrt(2)
+    xmeas = {"kraus": [np.outer([1, 0], plus), np.outer([0, 1], minus)]}
+    assert _status(P.ptsbe_plan, _one_gate(xmeas)) == E_UNSUPPORTED
+    # amplitude damping: resolved when the state reaches it (a record entry, no site)
+    plan_ad = P.ptsbe_plan(_one_gate({"name": "amplitude_damping", "gamma": 0.2}))
+    assert plan_ad.info["n_sites"] == 0 and plan_ad.info["n_measure"] == 1
     # up to 35 qubits (a 2^35 complex64 state is 256 GiB)
     big = {"n_qubits": 35, "ops": [{"kind": "gate", "name": "H", "qubits": (34,), "params": ()}], "channels": [],
            "rules": [], "params": []}

@@ -119,3 +119,26 @@ def test_brick_phase_frames(frames):
     st = run_compiled(plan, ts)
     ref, _ = oracle_states(circ, g["records"])
     assert max(float(np.max(np.abs(st[a] - ref[a]))) for a in range(len(ref))) <= 1e-5
+
+
+@pytest.mark.parametrize("tile", [0, 6])
+def test_state_dependent_channels(tile):
+    """Amplitude damping resolved when the state reaches it: the generated
+    kernels apply K_k / sqrt(p_k) from the record entry, the decisions made
+    between passes as the device makes them; states and entries equal the
+    oracle's for every trajectory (alpha = its index)."""
+    rng = np.random.default_rng(4)
+    circ = random_small_circuit(8, 40, rng, p1=0.0, p2=0.0)
+    circ = dict(circ, ops=[op for op in circ["ops"] if op["kind"] != "noise"],
+                channels=[{"name": "amplitude_damping", "gamma": 0.25, "nq": 1},
+                          {"name": "depolarizing", "nq": 1, "p": 0.05}],
+                rules=[{"when": "after_tag", "tag": "U3", "channel": 0}, {"when": "after_tag", "tag": "RX", "channel": 1}])
+    plan = P.ptsbe_plan(circ, tile_qubits=tile)
+    assert any(c >= 0 for c, _ in plan.record_info())
+    ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=6, total_shots=6, seed=3, cfg=1)
+    st = run_compiled(plan, ts, circuit=circ, be=(9, 2))
+    from oracle.statevector import run_record
+    for a, rec in enumerate(ts.get()["records"]):
+        psi, entries = run_record(circ, rec, be_key=(9, 2, a))
+        psi = psi / np.linalg.norm(psi)
+        assert float(np.max(np.abs(st[a] - psi))) <= 1e-5, f"trajectory {a}"
