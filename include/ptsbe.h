@@ -418,6 +418,14 @@ ptsbe_status ptsbe_unique_shots(ptsbe_trajset_t ts, const void* d_bits, void* d_
  * un-applies each operation on psi and lambda and accumulates
  * 2 Re <lambda| dG/dtheta |psi> in FP64 per (trajectory, tile), reduced in a
  * fixed order (deterministic).  O = sum_t coef_t Z-string(zmask_t), 1..64 terms.
+ * State-dependent channels (Algorithm 1's state-dependent branch) are decided
+ * in the forward preparation exactly as ptsbe_run_batch decides them with the
+ * same seed and cfg (Philox stream 4); the state at each decision is
+ * checkpointed in the workspace and restored by the reverse sweep, which holds
+ * the chosen K_k / sqrt(p_k) fixed: the per-trajectory derivative is then
+ * d<phi|O|phi> / <phi|phi> of the unnormalised path state, whose average over
+ * paths drawn with their probabilities is the exact derivative (pathwise and
+ * score-function terms together).
  * params: host FP64 array of n_params values; d_expval: device, 1 FP64 (E);
  * d_grad: device, n_params FP64.  The workspace (256-byte aligned, size from
  * ptsbe_workspace_size with mode PTSBE_RUN_ADJOINT) is split into batches of
@@ -426,8 +434,8 @@ ptsbe_status ptsbe_unique_shots(ptsbe_trajset_t ts, const void* d_bits, void* d_
  * one trajectory fits the workspace.  The call only enqueues work on `stream`. */
 ptsbe_status ptsbe_adjoint_grad(ptsbe_plan_t plan, ptsbe_trajset_t ts, const double* params,
                                 const double* obs_coef, const uint64_t* obs_zmask, uint32_t n_terms,
-                                void* d_ws, size_t ws_bytes, double* d_expval, double* d_grad,
-                                void* stream);
+                                uint64_t seed, uint32_t cfg, void* d_ws, size_t ws_bytes,
+                                double* d_expval, double* d_grad, void* stream);
 
 /* ---------------------------------------------------------- gate library */
 

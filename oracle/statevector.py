@@ -76,7 +76,7 @@ def _categorical_positive(u, probs):
 
 
 def run_record(circuit, record, params=None, steps_sites=None, chans=None,
-               kraus_unnormalised=False, mr_tol=1e-6, be_key=None):
+               kraus_unnormalised=False, mr_tol=1e-6, be_key=None, forced=None, trace=None):
     """Prepare psi_alpha for one record.  Returns (psi, mr_bits).
 
     State-dependent channel steps ("gch") are decided here (Algorithm 1's
@@ -84,7 +84,9 @@ def run_record(circuit, record, params=None, steps_sites=None, chans=None,
     u = word gidx of the stream [seed, key1(4, cfg, alpha)] for ``be_key`` =
     (seed, cfg, alpha), k by the running sum, then K_k / sqrt(p_k); the chosen k
     joins the returned record entries (in record index order with the
-    measure-reset bits).
+    measure-reset bits).  ``forced`` (a list indexed by gidx) fixes the
+    decisions instead; if ``trace`` is a list, each decision appends a dict with
+    the state before it ("psi"), the qubit, k, p_k and the Kraus operator.
 
     With ``kraus_unnormalised`` the site operators are K_k = sqrt(p_k) U_k, so
     that ||psi||^2 ends as p_alpha (used as an invariant check)."""
@@ -137,9 +139,14 @@ def run_record(circuit, record, params=None, steps_sites=None, chans=None,
             one, tot = marginal_one(psi, n, q)
             p1 = one / tot
             probs = [d0[k] * (1.0 - p1) + d1[k] * p1 for k in range(len(K))]
-            seed, cfg, alpha = be_key
-            u = uniforms(seed, key1(STREAM_CHANNEL, cfg, alpha), st[4] + 1)[st[4]]
-            k = _categorical_positive(u, probs)
+            if forced is not None:
+                k = forced[st[4]]
+            else:
+                seed, cfg, alpha = be_key
+                u = uniforms(seed, key1(STREAM_CHANNEL, cfg, alpha), st[4] + 1)[st[4]]
+                k = _categorical_positive(u, probs)
+            if trace is not None:
+                trace.append({"psi": psi.copy(), "q": q, "k": k, "p": probs[k], "K": K[k]})
             psi = apply(psi, n, K[k] / math.sqrt(probs[k]), (q,))
             psi = psi / math.sqrt(math.fsum(psi.real ** 2 + psi.imag ** 2))
             bits.append(k)

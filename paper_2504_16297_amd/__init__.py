@@ -504,10 +504,12 @@ def ptsbe_unique_shots(ts, bits, workspace=None, max_batch=0, pairs=False, strea
     return out
 
 
-def ptsbe_adjoint_grad(plan, ts, params, observable, workspace=None, max_batch=0, stream=None):
+def ptsbe_adjoint_grad(plan, ts, params, observable, workspace=None, max_batch=0, stream=None, seed=0, cfg=0):
     """Adjoint gradient of E(theta) = sum_a w_a <psi_a|O|psi_a> over the trajectory
     set (w_a = count_a / sum count).  ``observable``: list of (coef, qubits) Z-strings.
-    Returns (E, grad) as FP64 device tensors of shapes (1,) and (n_params,)."""
+    State-dependent channels are decided as ptsbe_run_batch decides them with the
+    same ``seed`` and ``cfg``.  Returns (E, grad) as FP64 device tensors of shapes
+    (1,) and (n_params,)."""
     import torch
     dev = torch.device("cuda")
     pa = np.ascontiguousarray(params, dtype=np.float64)
@@ -521,6 +523,7 @@ def ptsbe_adjoint_grad(plan, ts, params, observable, workspace=None, max_batch=0
     G = torch.zeros(max(1, pa.size), dtype=torch.float64, device=dev)
     check(lib().ptsbe_adjoint_grad(plan.handle, ts.handle, _dptr(pa), _dptr(coef),
                                    C.cast(zm.ctypes.data, C.POINTER(C.c_uint64)), len(observable),
+                                   int(seed), int(cfg),
                                    C.c_void_p(ws.data_ptr()), ws.numel(), C.c_void_p(E.data_ptr()),
                                    C.c_void_p(G.data_ptr()), _stream(torch, stream)))
     return E, G[:pa.size]

@@ -133,6 +133,7 @@ _SIGS = {
                                                C.POINTER(C.c_size_t), C.c_void_p, C.c_void_p, C.c_void_p]),
     "ptsbe_adjoint_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_double),
                                      C.POINTER(C.c_double), C.POINTER(C.c_uint64), C.c_uint32,
+                                     C.c_uint64, C.c_uint32,
                                      C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p]),
     "ptsbe_std_gate": (C.c_int, [C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                  C.POINTER(C.c_uint32)]),

@@ -21,8 +21,8 @@ ptsbe_status run_batch(const Plan& P, TrajSet& ts, const ptsbe_run_opts* o, void
                        hipGraphExec_t* graph_out = nullptr);
 ptsbe_status run_status(const void* d_ws, void* stream);
 ptsbe_status adjoint_grad(const Plan& P, TrajSet& ts, const double* params, const double* coef,
-                          const uint64_t* zmask, uint32_t n_terms, void* d_ws, size_t ws_bytes, double* d_expval,
-                          double* d_grad, void* stream);
+                          const uint64_t* zmask, uint32_t n_terms, uint64_t seed, uint32_t cfg, void* d_ws,
+                          size_t ws_bytes, double* d_expval, double* d_grad, void* stream);
 ptsbe_status adjoint_workspace_size(const Plan& P, TrajSet& ts, const double* params, uint32_t max_batch,
                                     size_t* bytes);
 }  // namespace ptsbe
@@ -330,13 +330,13 @@ ptsbe_status ptsbe_unique_shots(ptsbe_trajset_t ts, const void* d_bits, void* d_
 }
 
 ptsbe_status ptsbe_adjoint_grad(ptsbe_plan_t plan, ptsbe_trajset_t ts, const double* params, const double* obs_coef,
-                                const uint64_t* obs_zmask, uint32_t n_terms, void* d_ws, size_t ws_bytes,
-                                double* d_expval, double* d_grad, void* stream) {
+                                const uint64_t* obs_zmask, uint32_t n_terms, uint64_t seed, uint32_t cfg,
+                                void* d_ws, size_t ws_bytes, double* d_expval, double* d_grad, void* stream) {
   FENCE({
     if (!plan || !ts) return fail(PTSBE_E_ARG, "null argument");
     if (ts->ts->plan.get() != plan->plan.get()) return fail(PTSBE_E_ARG, "trajectory set belongs to another plan");
-    return adjoint_grad(*plan->plan, *ts->ts, params, obs_coef, obs_zmask, n_terms, d_ws, ws_bytes, d_expval, d_grad,
-                        stream);
+    return adjoint_grad(*plan->plan, *ts->ts, params, obs_coef, obs_zmask, n_terms, seed, cfg, d_ws, ws_bytes,
+                        d_expval, d_grad, stream);
   })
 }
 

@@ -7,6 +7,16 @@
 // (forward program), lambda = O psi, then the reverse-sweep program un-applies
 // every operation on psi and lambda and, just before un-applying a rotation
 // exp(-i theta P / 2), adds Im<lambda|P|psi> = 2 Re<lambda|dG/dtheta|psi_prev>.
+//
+// A state-dependent channel (Algorithm 1's state-dependent branch) is decided
+// in the forward preparation as in a batched run, and the state at its decision
+// is checkpointed.  With the chosen operator G = K_k / sqrt(p_k) held fixed,
+// 2 Re<lambda|dpsi> is d<phi|O|phi> / <phi|phi> for the unnormalised path state
+// phi (raw K_k): averaged over paths drawn with their probabilities <phi|phi>
+// this is the derivative of sum_paths <phi|O|phi>, the pathwise and the
+// score-function term together.  The reverse sweep cannot un-apply a singular
+// K_k: at the channel it restores psi from the checkpoint and applies G^dagger
+// to lambda alone.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -25,7 +35,8 @@ namespace {
 uint64_t a256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
 
 struct AdjLayout {
-  uint64_t status, fwd, adj, aux, psi, lam, partial, ev, scan_part, scan_offs, scan_total, gdot, end;
+  uint64_t status, fwd, adj, aux, psi, lam, partial, ev, scan_part, scan_offs, scan_total, gdot;
+  uint64_t mr_partial, mr_bits, mr_norm, rec_info, ckpt, end;
   uint32_t batch, n_tiles, nblk, per_block, per_thread;
 };
 
@@ -55,6 +66,14 @@ AdjLayout adj_layout(const Plan& P, const TrajSet& ts, uint32_t batch) {
   L.scan_offs = o; o = a256(o + (uint64_t)batch * L.nblk * 8);
   L.scan_total = o; o = a256(o + (uint64_t)batch * 8);
   L.gdot = o; o = a256(o + std::max<uint64_t>(1, n_dot) * 8);
+  // state-dependent channels: decision partials, record entries, their data,
+  // and one checkpointed state per channel step and resident trajectory
+  const uint64_t nm = (uint64_t)P.n_measure, ng = (uint64_t)P.n_general;
+  L.mr_partial = o; if (nm) o = a256(o + (uint64_t)batch * L.nblk * (kMaxGroup + 1) * 8);
+  L.mr_bits = o; if (nm) o = a256(o + B * nm);
+  L.mr_norm = o; if (nm) o = a256(o + B * nm * 8);
+  L.rec_info = o; if (ng) o = a256(o + nm * 8 + P.rec_info.chan_param.size() * 8);
+  L.ckpt = o; o = a256(o + ng * (uint64_t)batch * N * esz);
   L.end = o;
   return L;
 }
@@ -89,7 +108,8 @@ PassArgs<V> pass_args(const Plan& P, uint8_t* tb, const TableLayout& T, uint32_t
 
 template <typename V>
 ptsbe_status adjoint_typed(const Plan& P, TrajSet& ts, const double* coef, const uint64_t* zmask, uint32_t n_terms,
-                           uint8_t* ws, const AdjLayout& L, double* d_expval, double* d_grad, hipStream_t s) {
+                           uint64_t seed, uint32_t cfg, uint8_t* ws, const AdjLayout& L, double* d_expval,
+                           double* d_grad, hipStream_t s) {
   // every reverse-sweep pass compiled, or none (the partial layouts differ)
   bool compiled = P.use_jit && !P.adj.passes.empty();
   for (uint32_t p = 0; compiled && p < P.adj.passes.size(); ++p) compiled = jit_has_adjoint(P, p);
@@ -112,6 +132,28 @@ ptsbe_status adjoint_typed(const Plan& P, TrajSet& ts, const double* coef, const
     std::memcpy(aux.data() + B * 8 + 4 * d, &p, 4);
   }
   CK(hipMemcpyAsync(ws + L.aux, aux.data(), aux.size(), hipMemcpyHostToDevice, s), "weights upload");
+  const uint32_t nm = (uint32_t)P.n_measure;
+  const uint32_t* d_rec_chan = nullptr;
+  const uint32_t* d_rec_gidx = nullptr;
+  const double* d_chan_param = nullptr;
+  if (P.n_general) {
+    uint8_t* ri = ws + L.rec_info;
+    CK(hipMemcpyAsync(ri, P.rec_info.rec_chan.data(), (size_t)nm * 4, hipMemcpyHostToDevice, s), "record upload");
+    CK(hipMemcpyAsync(ri + (size_t)nm * 4, P.rec_info.rec_gidx.data(), (size_t)nm * 4, hipMemcpyHostToDevice, s),
+       "record upload");
+    CK(hipMemcpyAsync(ri + (size_t)nm * 8, P.rec_info.chan_param.data(), P.rec_info.chan_param.size() * 8,
+                      hipMemcpyHostToDevice, s),
+       "record upload");
+    d_rec_chan = reinterpret_cast<const uint32_t*>(ri);
+    d_rec_gidx = reinterpret_cast<const uint32_t*>(ri + (size_t)nm * 4);
+    d_chan_param = reinterpret_cast<const double*>(ri + (size_t)nm * 8);
+  }
+  uint32_t* status = reinterpret_cast<uint32_t*>(ws + L.status);
+  CK(launch_fill_u32(status, 0, 4, s), "status reset");
+  uint8_t* mr_bits = ws + L.mr_bits;
+  double* mr_norm = reinterpret_cast<double*>(ws + L.mr_norm);
+  V* ckpt = reinterpret_cast<V*>(ws + L.ckpt);
+  const uint64_t state_bytes = N * sizeof(V);
   const double* w = reinterpret_cast<const double*>(ws + L.aux);
   const uint32_t* dot_param = reinterpret_cast<const uint32_t*>(ws + L.aux + B * 8);
   V* psi = reinterpret_cast<V*>(ws + L.psi);
@@ -119,6 +161,9 @@ ptsbe_status adjoint_typed(const Plan& P, TrajSet& ts, const double* coef, const
   double* ev = reinterpret_cast<double*>(ws + L.ev);
   double* partial = reinterpret_cast<double*>(ws + L.partial);
   PassArgs<V> fa = pass_args<V>(P, ws + L.fwd, ts.layout, (uint32_t)P.passes.size(), psi);
+  fa.mr_bits = mr_bits;
+  fa.mr_norm = mr_norm;
+  fa.n_measure = nm;
   AdjArgs<V> aa{};
   aa.p = pass_args<V>(P, ws + L.adj, ts.adj_layout, (uint32_t)P.adj.passes.size(), psi);
   aa.lam = lam;
@@ -129,7 +174,42 @@ ptsbe_status adjoint_typed(const Plan& P, TrajSet& ts, const double* coef, const
     fa.t0 = b0;
     aa.p.t0 = b0;
     for (const ExecStep& ex : P.exec) {
-      if (ex.pass < 0) return fail(PTSBE_E_UNSUPPORTED, "adjoint: measurement steps are not supported");
+      if (ex.pass < 0) {
+        // one state-dependent channel: checkpoint the state, then decide
+        if (ex.mr_index.size() != 1 || !d_rec_chan || P.rec_info.rec_chan[ex.mr_index[0]] == 0xffffffffu)
+          return fail(PTSBE_E_UNSUPPORTED, "adjoint: measure-reset steps are not supported");
+        const uint32_t g = P.rec_info.rec_gidx[ex.mr_index[0]];
+        CK(hipMemcpyAsync(ckpt + ((uint64_t)g * L.batch) * N, psi, (size_t)bb * state_bytes, hipMemcpyDeviceToDevice,
+                          s),
+           "checkpoint");
+        MarginalArgs<V> ma{};
+        ma.states = psi;
+        ma.partial = reinterpret_cast<double*>(ws + L.mr_partial);
+        ma.N = N;
+        ma.nblk = L.nblk;
+        ma.per_block = L.per_block;
+        ma.nq = 1;
+        ma.q[0] = (uint32_t)ex.mr_qubits[0];
+        MrDecideArgs da{};
+        da.partial = ma.partial;
+        da.mr_bits = mr_bits;
+        da.mr_norm = mr_norm;
+        da.status = status;
+        da.tol = 1e-6;
+        da.nblk = L.nblk;
+        da.nq = 1;
+        da.t0 = b0;
+        da.n_measure = nm;
+        da.rec_chan = d_rec_chan;
+        da.rec_gidx = d_rec_gidx;
+        da.chan_param = d_chan_param;
+        da.seed = seed;
+        da.cfg = cfg;
+        da.alpha0 = ts.alpha0;
+        da.idx[0] = (uint32_t)ex.mr_index[0];
+        CK(launch_marginal<V>(ma, da, bb, s), "state-dependent channel");
+        continue;
+      }
       const Pass& ps = P.passes[ex.pass];
       fa.pass = (uint32_t)ex.pass;
       if (jit_has(P, (uint32_t)ex.pass))
@@ -167,6 +247,25 @@ ptsbe_status adjoint_typed(const Plan& P, TrajSet& ts, const double* coef, const
     CK(launch_expval<V>(ea, total, ev, bb, b0, s), "expectation");
     CK(launch_obs_apply<V>(oa, bb, s), "lambda");
     for (const ExecStep& ex : P.adj.exec) {
+      if (ex.pass < 0) {
+        // state-dependent channel: psi from its checkpoint, lambda <- G^dagger lambda
+        const uint32_t r = (uint32_t)ex.mr_index[0];
+        CK(hipMemcpyAsync(psi, ckpt + ((uint64_t)ex.restore * L.batch) * N, (size_t)bb * state_bytes,
+                          hipMemcpyDeviceToDevice, s),
+           "checkpoint restore");
+        GchAdjArgs<V> ga{};
+        ga.lam = lam;
+        ga.mr_bits = mr_bits;
+        ga.mr_norm = mr_norm;
+        ga.chan = d_chan_param + P.rec_info.rec_chan[r];
+        ga.N = N;
+        ga.q = (uint32_t)ex.mr_qubits[0];
+        ga.rec = r;
+        ga.n_measure = nm;
+        ga.t0 = b0;
+        CK(launch_gch_lam_adjoint<V>(ga, bb, s), "state-dependent channel adjoint");
+        continue;
+      }
       const Pass& ps = P.adj.passes[ex.pass];
       aa.p.pass = (uint32_t)ex.pass;
       if (compiled)
@@ -219,8 +318,8 @@ ptsbe_status adjoint_workspace_size(const Plan& P, TrajSet& ts, const double* pa
 }
 
 ptsbe_status adjoint_grad(const Plan& P, TrajSet& ts, const double* params, const double* coef,
-                          const uint64_t* zmask, uint32_t n_terms, void* d_ws, size_t ws_bytes, double* d_expval,
-                          double* d_grad, void* stream) {
+                          const uint64_t* zmask, uint32_t n_terms, uint64_t seed, uint32_t cfg, void* d_ws,
+                          size_t ws_bytes, double* d_expval, double* d_grad, void* stream) {
   ptsbe_status st = check_adjoint(P, ts, params, coef, zmask, n_terms);
   if (st != PTSBE_OK) return st;
   if (!d_ws || !d_expval || !d_grad) return fail(PTSBE_E_ARG, "null device pointer");
@@ -247,8 +346,8 @@ ptsbe_status adjoint_grad(const Plan& P, TrajSet& ts, const double* params, cons
   uint8_t* ws = static_cast<uint8_t*>(d_ws);
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (P.precision == PTSBE_C64)
-    return adjoint_typed<float2>(P, ts, coef, zmask, n_terms, ws, L, d_expval, d_grad, s);
-  return adjoint_typed<double2>(P, ts, coef, zmask, n_terms, ws, L, d_expval, d_grad, s);
+    return adjoint_typed<float2>(P, ts, coef, zmask, n_terms, seed, cfg, ws, L, d_expval, d_grad, s);
+  return adjoint_typed<double2>(P, ts, coef, zmask, n_terms, seed, cfg, ws, L, d_expval, d_grad, s);
 }
 
 }  // namespace ptsbe

@@ -112,17 +112,22 @@ struct Pass {
   uint32_t flags = 0;
 };
 
-// Execution step: a tile pass, or a measurement of a group of measure-resets.
+// Execution step: a tile pass, or a decision of a group of record entries
+// (measure-resets, or one state-dependent channel), or in the reverse sweep the
+// restore of the state checkpointed at a state-dependent channel.
 struct ExecStep {
   int pass = -1;               // >= 0: tile pass index
-  std::vector<int> mr_qubits;  // measurement: qubits
-  std::vector<int> mr_index;   // measurement: record indices
+  std::vector<int> mr_qubits;  // decision / restore: qubits
+  std::vector<int> mr_index;   // decision / restore: record indices
+  bool wall = false;           // a state-dependent channel: every qubit's phase frame ends here
+  int restore = -1;            // reverse sweep: checkpoint (state-dependent channel index) to restore
 };
 
 // Decision data of the record entries (measure-resets and state-dependent
 // channels), uploaded with every run: rec_chan[r] = offset into chan_param of
 // entry r's channel, or 0xffffffff for a measure-reset; rec_gidx[r] = its
-// uniform's word; chan_param per channel: K, then d0[0..K), d1[0..K).
+// uniform's word; chan_param per channel: K, then d0[0..K), d1[0..K), then the
+// K raw Kraus operators (2x2 row-major, re/im interleaved: 8 doubles each).
 struct RecordInfo {
   std::vector<uint32_t> rec_chan, rec_gidx;
   std::vector<double> chan_param;

@@ -814,6 +814,36 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs<V> a) {
   }
 }
 
+// lambda <- (s K_k)^dagger lambda on qubit q (FP64 matrix): the adjoint of the
+// operator a state-dependent channel applied in the forward sweep, held fixed.
+template <typename V>
+__global__ __launch_bounds__(256) void k_gch_lam_adjoint(GchAdjArgs<V> a) {
+  const uint64_t ri = (uint64_t)(a.t0 + blockIdx.y) * a.n_measure + a.rec;
+  const uint32_t kk = a.mr_bits[ri];
+  const double sc = a.mr_norm[ri];
+  const double* K = a.chan + 1 + 2 * (uint32_t)a.chan[0] + 8 * kk;  // K_k row-major, re/im
+  // (K^dagger)_{ij} = conj(K_{ji})
+  const double h00r = sc * K[0], h00i = -sc * K[1];
+  const double h01r = sc * K[4], h01i = -sc * K[5];
+  const double h10r = sc * K[2], h10i = -sc * K[3];
+  const double h11r = sc * K[6], h11i = -sc * K[7];
+  V* l = a.lam + (uint64_t)blockIdx.y * a.N;
+  const uint64_t bit = 1ull << a.q, lo = bit - 1;
+  for (uint64_t pr = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; pr < a.N / 2;
+       pr += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t i0 = ((pr & ~lo) << 1) | (pr & lo), i1 = i0 | bit;
+    const V x0 = l[i0], x1 = l[i1];
+    const double ar = x0.x, ai = x0.y, br = x1.x, bi = x1.y;
+    V y0, y1;
+    y0.x = (typename Real<V>::T)(h00r * ar - h00i * ai + h01r * br - h01i * bi);
+    y0.y = (typename Real<V>::T)(h00r * ai + h00i * ar + h01r * bi + h01i * br);
+    y1.x = (typename Real<V>::T)(h10r * ar - h10i * ai + h11r * br - h11i * bi);
+    y1.y = (typename Real<V>::T)(h10r * ai + h10i * ar + h11r * bi + h11i * br);
+    l[i0] = y0;
+    l[i1] = y1;
+  }
+}
+
 // lambda = O psi for a diagonal O = sum_t coef_t Z-string(zmask_t)
 template <typename V>
 __global__ __launch_bounds__(256) void k_obs_apply(ObsArgs<V> a) {
@@ -1153,6 +1183,14 @@ hipError_t launch_obs_apply(const ObsArgs<V>& a, uint32_t batch, hipStream_t s) 
   return hipGetLastError();
 }
 
+template <typename V>
+hipError_t launch_gch_lam_adjoint(const GchAdjArgs<V>& a, uint32_t batch, hipStream_t s) {
+  const uint64_t pairs = a.N / 2;
+  const uint32_t gx = (uint32_t)((pairs + 255) / 256 < 4096 ? (pairs + 255) / 256 : 4096);
+  hipLaunchKernelGGL(k_gch_lam_adjoint<V>, dim3(gx, batch), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_grad_reduce(const double* partial, const double* w, uint32_t n_traj, uint32_t n_tiles,
                               uint32_t n_dot, double* gdot, const uint32_t* dot_param, uint32_t n_params,
                               double* grad, const double* ev, double* E, hipStream_t s) {
@@ -1181,6 +1219,8 @@ PTSBE_INST(float2)
 PTSBE_INST(double2)
 template hipError_t launch_adjoint_pass<float2>(const AdjArgs<float2>&, uint32_t, uint32_t, uint32_t, hipStream_t);
 template hipError_t launch_adjoint_pass<double2>(const AdjArgs<double2>&, uint32_t, uint32_t, uint32_t, hipStream_t);
+template hipError_t launch_gch_lam_adjoint<float2>(const GchAdjArgs<float2>&, uint32_t, hipStream_t);
+template hipError_t launch_gch_lam_adjoint<double2>(const GchAdjArgs<double2>&, uint32_t, hipStream_t);
 template hipError_t launch_obs_apply<float2>(const ObsArgs<float2>&, uint32_t, hipStream_t);
 template hipError_t launch_obs_apply<double2>(const ObsArgs<double2>&, uint32_t, hipStream_t);
 template hipError_t launch_sample<uint32_t>(const SampleArgs<uint32_t>&, uint64_t, hipStream_t);

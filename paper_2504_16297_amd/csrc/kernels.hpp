@@ -139,8 +139,26 @@ struct ObsArgs {
   uint64_t zmask[64];
 };
 
+// Reverse sweep at a state-dependent channel on qubit q: lambda <- G^dagger
+// lambda for the operator G = s K_k the forward sweep applied (k and s from
+// record entry `rec` of each trajectory, K_k from the channel's parameters).
+template <typename V>
+struct GchAdjArgs {
+  V* lam;
+  const uint8_t* mr_bits;
+  const double* mr_norm;
+  const double* chan;   // the channel's block of the record data: K, d0[K], d1[K], K x 8 operator doubles
+  uint64_t N;
+  uint32_t q;
+  uint32_t rec;
+  uint32_t n_measure;
+  uint32_t t0;
+};
+
 template <typename V>
 hipError_t launch_adjoint_pass(const AdjArgs<V>& a, uint32_t k, uint32_t n_slots, uint32_t batch, hipStream_t s);
+template <typename V>
+hipError_t launch_gch_lam_adjoint(const GchAdjArgs<V>& a, uint32_t batch, hipStream_t s);
 template <typename V>
 hipError_t launch_obs_apply(const ObsArgs<V>& a, uint32_t batch, hipStream_t s);
 // gdot[d] = sum_t w[t] sum_tile partial[t][tile][d]; grad[p] = sum over dots of p; E = sum_t w[t] ev[t]

@@ -712,10 +712,16 @@ static ptsbe_status schedule(Plan& plan, const std::vector<Step>& steps, std::ve
       ++qcount;
     }
     std::vector<int> taken, keep;
+    // A state-dependent channel not yet decided (forward) or restored (reverse
+    // sweep) is a wall: nothing after it runs before it, so that the state at
+    // its decision is the state at its place in the circuit (the checkpoint
+    // the reverse sweep restores).
+    bool wall = false;
     for (int si : rem) {
       const Step& st = steps[si];
-      bool blk = false;
+      bool blk = wall;
       for (int j = 0; j < st.nq; ++j) blk = blk || blocked[st.q[j]];
+      if (st.kind == ST_GCH && !measured[si]) wall = true;
       bool can = false;
       if (!blk) {
         if ((st.kind == ST_MR || st.kind == ST_GCH) && !measured[si]) {
@@ -742,26 +748,44 @@ static ptsbe_status schedule(Plan& plan, const std::vector<Step>& steps, std::ve
         keep.push_back(si);
       }
     }
+    if (taken.empty() && steps[rem[0]].kind == ST_GCH && steps[rem[0]].dagger) {
+      // reverse sweep at a state-dependent channel: restore the state
+      // checkpointed at its decision, apply its adjoint to lambda alone
+      const Step& st = steps[rem[0]];
+      ExecStep ex;
+      ex.mr_qubits.push_back(st.q[0]);
+      ex.mr_index.push_back(st.mr);
+      ex.wall = true;
+      ex.restore = st.gidx;
+      exec.push_back(ex);
+      rem.erase(rem.begin());
+      first = false;
+      continue;
+    }
     if (taken.empty()) {
       // every frontier operation is an undecided record entry: measure-resets are
       // decided together (their outcomes are deterministic, so they do not
       // change each other's marginals); a state-dependent channel only alone
-      // among channels and only once no channel step before it is pending, so
-      // that its probabilities come from the state in circuit order
+      // among channels and only once every step before it is an entry decided
+      // in this same step, so that its probabilities come from the state at its
+      // place in the circuit
       ExecStep ex;
       std::vector<char> blk(n, 0);
-      bool channel_pending = false, channel_taken = false;
+      bool channel_pending = false, channel_taken = false, others_before = false;
       for (int si : rem) {
         const Step& st = steps[si];
         bool b = false;
         for (int j = 0; j < st.nq; ++j) b = b || blk[st.q[j]];
         const bool mr_ok = st.kind == ST_MR;
-        const bool ch_ok = st.kind == ST_GCH && !channel_pending && !channel_taken;
+        const bool ch_ok = st.kind == ST_GCH && !channel_pending && !channel_taken && !others_before;
         if (!b && (mr_ok || ch_ok) && !measured[si]) {
           ex.mr_qubits.push_back(st.q[0]);
           ex.mr_index.push_back(st.mr);
           measured[si] = 1;
           channel_taken = channel_taken || st.kind == ST_GCH;
+          ex.wall = ex.wall || st.kind == ST_GCH;
+        } else {
+          others_before = true;
         }
         if (st.kind == ST_GCH) channel_pending = true;
         for (int j = 0; j < st.nq; ++j) blk[st.q[j]] = 1;
@@ -842,7 +866,10 @@ template <class F>
 void walk_frames(int n, const std::vector<Pass>& passes, const std::vector<ExecStep>& exec, F&& f) {
   for (const ExecStep& ex : exec) {
     if (ex.pass < 0) {
-      for (int q : ex.mr_qubits) f(q, FrameEvent{FE_BREAK, -1, -1, 0});
+      if (ex.wall)
+        for (int q = 0; q < n; ++q) f(q, FrameEvent{FE_BREAK, -1, -1, 0});
+      else
+        for (int q : ex.mr_qubits) f(q, FrameEvent{FE_BREAK, -1, -1, 0});
       continue;
     }
     const Pass& ps = passes[ex.pass];
@@ -1139,6 +1166,11 @@ ptsbe_status build_plan(const ptsbe_circuit* c, const ptsbe_noise_model* nm, con
         R.chan_param.push_back((double)c.K);
         for (int k = 0; k < c.K; ++k) R.chan_param.push_back(c.d0[k]);
         for (int k = 0; k < c.K; ++k) R.chan_param.push_back(c.d1[k]);
+        for (int k = 0; k < c.K; ++k)
+          for (int e = 0; e < 4; ++e) {
+            R.chan_param.push_back(c.U[k][e].real());
+            R.chan_param.push_back(c.U[k][e].imag());
+          }
       }
       R.rec_chan[st.mr] = (uint32_t)chan_off[st.chan];
       R.rec_gidx[st.mr] = (uint32_t)st.gidx;
@@ -1156,10 +1188,12 @@ ptsbe_status build_plan(const ptsbe_circuit* c, const ptsbe_noise_model* nm, con
   if (!(o && (o->flags & PTSBE_PLAN_NO_PHASE_FRAMES))) assign_frames(P.n, P.steps, P.passes, P.exec);
   // Reverse-sweep program of the adjoint gradient: the steps in reverse order,
   // each applied as its adjoint, with a DOT marker (Im<lambda|P|psi>) just before
-  // un-applying every parametrised rotation.  Only for circuits without
-  // measure-reset / projection (state-independent unitary trajectories).
+  // un-applying every parametrised rotation.  Not for circuits with
+  // measure-reset / projection; a state-dependent channel becomes a restore
+  // step (its checkpointed state back into psi, its fixed operator's adjoint
+  // on lambda), scheduled as a wall.
   bool unitary = true;
-  for (const Step& s : P.steps) unitary = unitary && s.kind != ST_MR && s.kind != ST_P0 && s.kind != ST_GCH;
+  for (const Step& s : P.steps) unitary = unitary && s.kind != ST_MR && s.kind != ST_P0;
   if (P.n_params > 0 && unitary) {
     Program& A = P.adj;
     int ndot = 0;

@@ -98,7 +98,7 @@ def _adjoint_status(plan, ts, params, obs, ws=None, nbytes=0):
     pa = np.ascontiguousarray(params, dtype=np.float64) if params is not None else None
     return P.lib().ptsbe_adjoint_grad(plan.handle, ts.handle, P._dptr(pa) if pa is not None else None,
                                       P._dptr(coef), C.cast(zm.ctypes.data, C.POINTER(C.c_uint64)), len(obs),
-                                      ws, nbytes, None, None, None)
+                                      0, 0, ws, nbytes, None, None, None)
 
 
 def test_adjoint_argument_checks():
@@ -128,6 +128,16 @@ def test_adjoint_workspace_query_runs_on_host():
     state = (1 << 10) * 8
     assert full >= one + 2 * (ts.n_traj - 1) * state
     assert one >= 2 * state
+    # amplitude damping after every RY: one checkpointed state per channel step
+    # and resident trajectory on top of psi and lambda
+    circ["channels"].append({"name": "amplitude_damping", "gamma": 0.2, "nq": 1})
+    circ["rules"].append({"when": "after_tag", "tag": "RY", "channel": 1})
+    plan = P.ptsbe_plan(circ)
+    ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=20, total_shots=20, seed=1, cfg=5)
+    one_g = P.ptsbe_workspace_size(plan, ts, "adjoint", max_batch=1, params=circ["params"])
+    full_g = P.ptsbe_workspace_size(plan, ts, "adjoint", params=circ["params"])
+    assert one_g >= one + 20 * state
+    assert full_g >= full + 20 * ts.n_traj * state
 
 
 def test_distinct_shot_queries_and_checks():

@@ -170,3 +170,32 @@ def test_autograd_function_and_central_differences():
     err = float(np.max(np.abs(fd - g)))
     log(f"  autograd vs central FD (c128, h=1e-4): max|d| = {err:.2e}")
     assert err <= 1e-6
+
+
+@pytest.mark.parametrize("n,prec,tile,max_batch", [(5, "c64", 0, 0), (7, "c128", 0, 0), (9, "c64", 5, 0),
+                                                   (8, "c64", 0, 5)])
+def test_gradient_through_state_dependent_channels(n, prec, tile, max_batch):
+    """Amplitude damping after every RY, decided on the device as a batched run
+    decides it (key (seed, cfg, trajectory)), the state at each decision
+    checkpointed and restored by the reverse sweep with the chosen operator
+    held fixed; depolarizing after every CZ from the trajectory records.  E and
+    the gradient equal the oracle's (same decisions, same fixed operators)."""
+    log(f"[adjoint state-dependent] n={n} {prec} tile={tile} max_batch={max_batch}")
+    circ = hea_circuit(n, 2, np.random.default_rng(70 + n), 2e-2)
+    circ["channels"].append({"name": "amplitude_damping", "gamma": 0.2, "nq": 1})
+    circ["rules"].append({"when": "after_tag", "tag": "RY", "channel": 1})
+    params = np.asarray(circ["params"])
+    plan = P.ptsbe_plan(circ, precision=prec, tile_qubits=tile)
+    assert plan.info["n_measure"] == 2 * n
+    ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=24, total_shots=24, seed=9, cfg=5)
+    g = ts.get()
+    obs = zz_ring(n)
+    E, G = P.ptsbe_adjoint_grad(plan, ts, params, obs, max_batch=max_batch, seed=13, cfg=3)
+    torch.cuda.synchronize()
+    E, G = float(E.cpu().numpy()[0]), G.cpu().numpy()
+    Er, Gr = ensemble_value_and_grad(circ, g["records"], _weights(g), params, obs, be_seed=(13, 3))
+    scale = max(1.0, float(np.max(np.abs(Gr))))
+    err = float(np.max(np.abs(G - Gr))) / scale
+    log(f"  E={E:.6f} ref={Er:.6f} |dE|={abs(E - Er):.2e} grad rel err={err:.2e}")
+    assert abs(E - Er) <= (1e-5 if prec == "c64" else 1e-10)
+    assert err <= (1e-4 if prec == "c64" else 1e-10)

@@ -78,3 +78,100 @@ def test_channel_diagonals_closed_form():
     off = [math.sqrt(0.5) * np.eye(2), math.sqrt(0.5) * h @ np.diag([1.0, 0.0]) @ h,
            math.sqrt(0.5) * h @ np.diag([0.0, 1.0]) @ h]
     assert general_channel(off) is None
+
+
+def _ad_hea(gamma=0.25):
+    """3-qubit, 2-layer RY/RZ ansatz with CZ ring; amplitude damping after every RY."""
+    ops = []
+    for layer in range(2):
+        for q in range(3):
+            b = layer * 6 + 2 * q
+            ops.append({"kind": "param", "gen": "Y", "qubits": (q,), "index": b, "tag": "RY"})
+            ops.append({"kind": "param", "gen": "Z", "qubits": (q,), "index": b + 1, "tag": "RZ"})
+        for i in range(3):
+            ops.append({"kind": "gate", "name": "CZ", "qubits": (i, (i + 1) % 3), "params": (), "tag": "CZ"})
+    params = np.random.default_rng(21).uniform(0.0, 2.0 * math.pi, size=12)
+    return {"n_qubits": 3, "ops": ops, "params": [float(x) for x in params],
+            "channels": [{"name": "amplitude_damping", "gamma": gamma, "nq": 1}],
+            "rules": [{"when": "after_tag", "tag": "RY", "channel": 0}]}
+
+
+def _paths(circ, params, terms):
+    """Every decision path with its probability (product of the p_k met),
+    value and fixed-operator adjoint gradient."""
+    import itertools
+    from oracle.adjoint import observable_diag, trajectory_grad
+    n_gch = sum(1 for s in expand(circ)[0] if s[0] == "gch")
+    od = observable_diag(circ["n_qubits"], terms)
+    out = []
+    for path in itertools.product(range(2), repeat=n_gch):
+        tr = []
+        run_record(circ, (), params=params, forced=list(path), trace=tr)
+        prob = math.prod(d["p"] for d in tr)
+        e, g = trajectory_grad(circ, (), params, od, forced=list(path))
+        out.append((path, prob, e, g))
+    return out
+
+
+def test_gradient_through_channels_sums_to_density_matrix_derivative():
+    """sum over all decision paths of p(path) * (fixed-operator adjoint gradient)
+    equals the derivative of Tr(O rho(theta)) under the full channel (parameter
+    shift of the density-matrix evolution); a gradient without the score-function
+    part (each path's derivative of its normalised expectation) does not."""
+    circ = _ad_hea()
+    p = np.asarray(circ["params"])
+    terms = [(1.0, (0, 1)), (0.6, (2,)), (-0.4, (0,))]
+    from oracle.adjoint import observable_diag
+    od = observable_diag(3, terms)
+
+    def exact(pp):
+        return float(np.real(np.sum(np.diag(evolve(circ, pp)) * od)))
+
+    paths = _paths(circ, p, terms)
+    assert abs(sum(pr for _, pr, _, _ in paths) - 1.0) < 1e-12
+    assert abs(sum(pr * e for _, pr, e, _ in paths) - exact(p)) < 1e-12
+    G = sum(pr * g for _, pr, _, g in paths)
+    shift = np.zeros(p.size)
+    for i in range(p.size):
+        pp = p.copy(); pp[i] += math.pi / 2
+        pm = p.copy(); pm[i] -= math.pi / 2
+        shift[i] = 0.5 * (exact(pp) - exact(pm))
+    assert float(np.max(np.abs(G - shift))) < 1e-11
+    # the pathwise part alone (derivative of <O> along each fixed path) misses the
+    # score-function term, and the sum then differs from the exact derivative
+    h = 1e-5
+    pathwise = np.zeros(p.size)
+    for path, pr, _, _ in paths:
+        for i in range(p.size):
+            pp = p.copy(); pp[i] += h
+            pm = p.copy(); pm[i] -= h
+            ep = float(np.sum(np.abs(run_record(circ, (), params=pp, forced=list(path))[0]) ** 2 * od))
+            em = float(np.sum(np.abs(run_record(circ, (), params=pm, forced=list(path))[0]) ** 2 * od))
+            pathwise[i] += pr * (ep - em) / (2 * h)
+    assert float(np.max(np.abs(pathwise - shift))) > 1e-3
+
+
+def test_path_gradient_is_derivative_of_unnormalised_value():
+    """For one fixed path, the adjoint gradient equals d<phi|O|phi>/dtheta divided
+    by <phi|phi> (phi: the path state under the raw Kraus operators; <phi|phi>
+    = p(path), <phi|O|phi> = p(path) <O>), by central differences."""
+    circ = _ad_hea(0.4)
+    p = np.asarray(circ["params"])
+    terms = [(1.0, (1, 2)), (0.3, (0,))]
+    from oracle.adjoint import observable_diag, trajectory_grad
+    od = observable_diag(3, terms)
+    path = [1, 0, 1, 0, 0, 1]
+
+    def f(pp):
+        tr = []
+        psi, _ = run_record(circ, (), params=pp, forced=path, trace=tr)
+        return math.prod(d["p"] for d in tr) * float(np.sum(np.abs(psi) ** 2 * od)), math.prod(d["p"] for d in tr)
+
+    _, g = trajectory_grad(circ, (), p, od, forced=path)
+    _, prob = f(p)
+    h = 1e-5
+    for i in range(p.size):
+        pp = p.copy(); pp[i] += h
+        pm = p.copy(); pm[i] -= h
+        fd = (f(pp)[0] - f(pm)[0]) / (2 * h) / prob
+        assert abs(fd - g[i]) < 1e-7, (i, fd, g[i])

@@ -205,3 +205,28 @@ def test_pauli_twirl_matches_oracle_and_plans_twirled_channels():
     ref = site_probs(dict(circ, channels=[twirled(ad)]))
     got, _ = plan.site_probs()
     assert len(got) == 3 and all(np.allclose(a, b, rtol=0, atol=1e-15) for a, b in zip(got, ref))
+
+
+def test_state_dependent_channels_in_forward_and_reverse_programs():
+    """Amplitude damping after every RY of a parametrised ansatz: the forward
+    program decides each such channel alone (one record entry per decision
+    step), and the reverse-sweep program restores them in the opposite order
+    (one restore step per channel), so the plan has an adjoint program."""
+    from paper_2504_16297_amd.tables import export_adjoint_tables, export_tables
+    from workloads.circuits import hea_circuit
+    circ = hea_circuit(6, 2, np.random.default_rng(3), 2e-2)
+    circ["channels"].append({"name": "amplitude_damping", "gamma": 0.2, "nq": 1})
+    circ["rules"].append({"when": "after_tag", "tag": "RY", "channel": 1})
+    params = np.asarray(circ["params"])
+    for tile in (0, 5):
+        plan = P.ptsbe_plan(circ, tile_qubits=tile)
+        info = plan.record_info()
+        gch = [r for r, (c, _) in enumerate(info) if c >= 0]
+        assert len(gch) == 12 and plan.info["n_measure"] == 12
+        ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=8, total_shots=8, seed=1, cfg=1)
+        fwd = export_tables(ts, params)
+        dec = [list(e["idx"][:e["nq"]]) for e in fwd["exec"] if e["pass"] == 0xFFFFFFFF]
+        assert dec == [[r] for r in gch]
+        adj, _ = export_adjoint_tables(ts, params)
+        res = [list(e["idx"][:e["nq"]]) for e in adj["exec"] if e["pass"] == 0xFFFFFFFF]
+        assert res == [[r] for r in reversed(gch)]
