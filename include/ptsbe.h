@@ -159,6 +159,12 @@ typedef struct {
  * models, one of the tailored error models Sec. 1 names.  Without the flag such
  * channels are rejected (PTSBE_E_UNSUPPORTED). */
 #define PTSBE_PLAN_TWIRL 64u
+/* Plan flag: no pair fusion.  By default a diagonal 2-qubit gate (CZ, ...)
+ * whose two qubits both carry a pending run of 1-qubit operations merges with
+ * them into one 4x4 slot, which also takes the following 1-qubit operations on
+ * either qubit until another operation needs one of them (in a brick circuit one
+ * 4x4 then replaces four 2x2 matrices and a sign flip). */
+#define PTSBE_PLAN_NO_PAIR_FUSION 128u
 
 typedef struct ptsbe_plan_s* ptsbe_plan_t;
 typedef struct ptsbe_trajset_s* ptsbe_trajset_t;

@@ -115,7 +115,7 @@ def ptsbe_plan_compile(plan):
 
 
 def ptsbe_plan(circuit, precision="c64", tile_qubits=0, compile=True, min_fill=0, half_tile=False,
-               phase_frames=True, waves=0, twirl=False):
+               phase_frames=True, waves=0, twirl=False, pair_fusion=True):
     """Build the execution plan of a circuit dictionary (ops, channels, rules).
     ``compile=False`` runs the passes through the generic tile kernels instead of
     per-pass compiled kernels; ``min_fill`` (1..7, 0 = 2) is the fewest 2x2
@@ -124,7 +124,8 @@ def ptsbe_plan(circuit, precision="c64", tile_qubits=0, compile=True, min_fill=0
     keeps every slot matrix as it is (no pending diagonals between matrices);
     ``waves`` (1..8, 0 = compiler's choice) sets the compiled passes' register
     budget to 512 / waves VGPRs; ``twirl`` replaces channels that are not unitary
-    mixtures by their Pauli twirl (else they are rejected)."""
+    mixtures by their Pauli twirl (else they are rejected); ``pair_fusion=False``
+    keeps diagonal 2-qubit gates apart from the 2x2 runs on their qubits."""
     ops = circuit["ops"]
     arr = (L.Op * max(1, len(ops)))()
     keep = []
@@ -193,7 +194,7 @@ def ptsbe_plan(circuit, precision="c64", tile_qubits=0, compile=True, min_fill=0
                     int(min_fill) | (0 if compile else L.PLAN_NO_COMPILE) |
                     (L.PLAN_HALF_TILE_LDS if half_tile else 0) |
                     (0 if phase_frames else L.PLAN_NO_PHASE_FRAMES) | (int(waves) << L.PLAN_WAVES_SHIFT) |
-                    (L.PLAN_TWIRL if twirl else 0), 0)
+                    (L.PLAN_TWIRL if twirl else 0) | (0 if pair_fusion else L.PLAN_NO_PAIR_FUSION), 0)
     h = C.c_void_p()
     check(lib().ptsbe_plan(C.byref(c), C.byref(nm), C.byref(po), C.byref(h)))
     return Plan(h, None)

@@ -28,6 +28,7 @@ PLAN_HALF_TILE_LDS = 16
 PLAN_NO_PHASE_FRAMES = 32
 PLAN_WAVES_SHIFT = 8
 PLAN_TWIRL = 64
+PLAN_NO_PAIR_FUSION = 128
 
 
 class Op(C.Structure):

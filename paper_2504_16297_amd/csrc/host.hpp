@@ -73,6 +73,8 @@ struct Site {
 struct Part {
   int step;
   int half;                    // -1: whole step; 0 / 1: factor on the site's first / second qubit
+  int emb = -1;                // in a 4x4 slot: 0 / 1 = a 2x2 on the slot's first / second qubit,
+                               // 2 = a 4x4 whose qubits are the slot's in swapped order
 };
 
 // Phase frames of the forward program.  A diagonal of unit-modulus phases
@@ -169,6 +171,7 @@ struct Plan {
   bool use_jit = true;
   bool half_tile_lds = false;  // compiled passes change registers through half a tile of LDS
   int waves = 0;               // waves per SIMD the compiled passes' register budget is set for (0 = default)
+  bool pair_fusion = true;     // diagonal 2-qubit gates merge with the 2x2 runs around them into 4x4 slots
   std::shared_ptr<JitProgram> jit;
 };
 

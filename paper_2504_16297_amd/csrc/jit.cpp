@@ -35,6 +35,15 @@ const char* kArgsFields = PTSBE_STR(PTSBE_PASS_ARGS_FIELDS(V, void, void, DOverr
 // index or a tile (global) bit, as a C expression.
 using Mono = std::vector<std::string>;  // product of variables, sorted; empty = 1
 
+// LDS matrix entries of a pass: 4 per slot (the 2x2 view every slot has),
+// then 16 per 4x4 slot, in slot order.
+uint32_t lds_mat_entries(const Pass& ps) {
+  uint32_t e = 4u * (uint32_t)ps.slots.size();
+  for (const Slot& sl : ps.slots)
+    if (sl.type == DOP_M2) e += 16u;
+  return e;
+}
+
 struct Gen {
   std::ostringstream o;
   int k = 0, n = 0;
@@ -46,6 +55,7 @@ struct Gen {
   bool tile_read = false;    // the LDS tile was read since the last barrier
   bool split = false;        // register changes go through half a tile of LDS, in two rounds
   bool dual = false;         // adjoint sweep: every operation acts on psi (s*) and lambda (l*)
+  std::vector<int> m2_off;   // slot -> offset of its 16 LDS entries (4x4 slots), else -1
   std::string pre = "s";     // register set the emitters write (s = psi, l = lambda)
   bool needs_full = false;   // an operation needs the whole tile in LDS
   // accumulated +-1 diagonal: amplitude r is negated where bit r of
@@ -346,6 +356,23 @@ struct Gen {
   // ---- 4x4 matrix
   void m2(const DOp& op) {
     const int ja = reg_pos(op.a), jb = reg_pos(op.b);
+    if (ja >= 0 && jb >= 0 && op.slot[0] < m2_off.size() && m2_off[op.slot[0]] >= 0) {
+      o << "  {\n    const V* M = mats + " << m2_off[op.slot[0]] << ";\n";
+      for (const std::string& st : sets())
+      for (int r = 0; r < 16; ++r) {
+        pre = st;
+        if ((r >> ja) & 1 || (r >> jb) & 1) continue;
+        const int i0 = r, i1 = r | (1 << ja), i2 = r | (1 << jb), i3 = r | (1 << ja) | (1 << jb);
+        o << "    { const V x0 = " << S(i0) << ", x1 = " << S(i1) << ", x2 = " << S(i2) << ", x3 = " << S(i3) << ";\n";
+        const int idx[4] = {i0, i1, i2, i3};
+        for (int q = 0; q < 4; ++q)
+          o << "      " << S(idx[q]) << " = cd4(M + " << 4 * q << ", x0, x1, x2, x3);\n";
+        o << "    }\n";
+      }
+      pre = "s";
+      o << "  }\n";
+      return;
+    }
     o << "  {\n    const V* m = a.pool + slot_off[" << op.slot[0] << "];\n";
     if (ja >= 0 && jb >= 0) {
       o << "    V M[16];\n    for (int i = 0; i < 16; ++i) M[i] = m[i];\n";
@@ -631,6 +658,18 @@ std::string gen_pass(const Pass& ps, int n, int precision, const std::string& na
   g.oq = ps.oq;
   for (int j = 0; j < 4; ++j) g.R[j] = k - 4 + j;
   const int n_slots = (int)ps.slots.size();
+  // 4x4 slots also keep all 16 entries in LDS, after the 2x2 views
+  g.m2_off.assign(n_slots, -1);
+  std::vector<std::pair<int, int>> m2_blocks;  // (slot, LDS offset)
+  {
+    int off = 4 * n_slots;
+    for (int i = 0; i < n_slots; ++i)
+      if (ps.slots[i].type == DOP_M2) {
+        g.m2_off[i] = off;
+        m2_blocks.push_back({i, off});
+        off += 16;
+      }
+  }
   std::vector<uint8_t> frame(n_slots);
   std::set<int> ovw_words;  // words of the override bit set that hold a rewritten 2x2 slot
   for (int i = 0; i < n_slots; ++i) {
@@ -651,7 +690,7 @@ std::string gen_pass(const Pass& ps, int n, int precision, const std::string& na
     << "  extern __shared__ __align__(16) unsigned char smem[];\n"
     << "  V* tile = reinterpret_cast<V*>(smem);\n"
     << "  V* mats = tile + " << (split ? (1 << (k - 1)) : (1 << k)) << ";\n"
-    << "  uint32_t* slot_off = reinterpret_cast<uint32_t*>(mats + " << 4 * n_slots << ");\n"
+    << "  uint32_t* slot_off = reinterpret_cast<uint32_t*>(mats + " << lds_mat_entries(ps) << ");\n"
     << "  const uint32_t tid = threadIdx.x;\n"
     << "  uint32_t src = blockIdx.y, dst = blockIdx.y;\n"
     << "  if (a.route) { const uint2 e = a.route[blockIdx.y]; src = e.x; dst = e.y; }\n"
@@ -693,14 +732,25 @@ std::string gen_pass(const Pass& ps, int n, int precision, const std::string& na
     << "  }\n"
     << "  for (uint32_t i = tid; i < " << n_slots << "u; i += blockDim.x) slot_off[i] = a.slot_default[i];\n"
     << "  for (uint32_t i = tid; i < " << 4 * n_slots
-    << "u; i += blockDim.x) mats[i] = a.pool[a.slot_default[i >> 2] + (i & 3u)];\n"
-    << "  for (uint32_t i = tid; i < " << n_ovw << "u; i += blockDim.x) ovw[i] = 0u;\n"
+    << "u; i += blockDim.x) mats[i] = a.pool[a.slot_default[i >> 2] + (i & 3u)];\n";
+  for (const auto& b : m2_blocks)
+    o << "  for (uint32_t i = tid; i < 16u; i += blockDim.x) mats[" << b.second << "u + i] = a.pool[a.slot_default["
+      << b.first << "] + i];\n";
+  o << "  for (uint32_t i = tid; i < " << n_ovw << "u; i += blockDim.x) ovw[i] = 0u;\n"
     << "  __syncthreads();\n"
     << "  if (ob != oe) {\n"
     << "    for (uint32_t i = ob + tid; i < oe; i += blockDim.x) {\n"
     << "      const uint32_t sl = a.ov[i].slot, off = a.ov[i].off;\n"
     << "      slot_off[sl] = off;\n"
-    << "      for (uint32_t e = 0; e < 4u; ++e) mats[4u * sl + e] = a.pool[off + e];\n"
+    << "      for (uint32_t e = 0; e < 4u; ++e) mats[4u * sl + e] = a.pool[off + e];\n";
+  if (!m2_blocks.empty()) {
+    o << "      switch (sl) {\n";
+    for (const auto& b : m2_blocks)
+      o << "        case " << b.first << "u: for (uint32_t e = 0; e < 16u; ++e) mats[" << b.second
+        << "u + e] = a.pool[off + e]; break;\n";
+    o << "        default: break;\n      }\n";
+  }
+  o
     << "      atomicOr(ovw + (sl >> 5), 1u << (sl & 31u));\n"
     << "    }\n"
     << "    __syncthreads();\n"
@@ -930,7 +980,7 @@ hipError_t jit_launch(const Plan& P, uint32_t pass, const PassArgs<V>& a, uint32
   const Pass& ps = P.passes[pass];
   const uint32_t k = (uint32_t)ps.k, n_slots = (uint32_t)ps.slots.size();
   const size_t te = P.jit->tile_elems[P.jit->pass_kernel[pass]];
-  const size_t lds = sizeof(V) * (te + 4 * (size_t)n_slots) + 4 * ((size_t)n_slots + (n_slots + 31) / 32);
+  const size_t lds = sizeof(V) * (te + lds_mat_entries(ps)) + 4 * ((size_t)n_slots + (n_slots + 31) / 32);
   if (lds > 65536) return hipErrorInvalidConfiguration;
   PassArgs<V> la = a;
   uint32_t slot_begin = 0;
@@ -956,7 +1006,7 @@ hipError_t jit_adjoint_launch(const Plan& P, uint32_t pass, const AdjArgs<V>& a,
   const Pass& ps = P.adj.passes[pass];
   const uint32_t k = (uint32_t)ps.k, n_slots = (uint32_t)ps.slots.size();
   const size_t te = P.jit->tile_elems[kid];
-  const size_t lds = sizeof(V) * (te + 4 * (size_t)n_slots) + 4 * ((size_t)n_slots + (n_slots + 31) / 32);
+  const size_t lds = sizeof(V) * (te + lds_mat_entries(ps)) + 4 * ((size_t)n_slots + (n_slots + 31) / 32);
   if (lds > 65536) return hipErrorInvalidConfiguration;
   PassArgs<V> la = a.p;
   uint32_t slot_begin = 0;

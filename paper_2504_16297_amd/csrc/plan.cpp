@@ -318,7 +318,28 @@ Mat slot_matrix(const Plan& plan, const std::vector<Step>& steps, const Slot& s,
   }
   int d = (s.type == DOP_M2 || s.type == DOP_D2) ? 4 : 2;
   Mat M = mat_identity(d);
-  for (const Part& pt : s.parts) M = mat_mul(part_matrix(plan, steps, pt, params, choice), M, d);
+  for (const Part& pt : s.parts) {
+    Mat m = part_matrix(plan, steps, pt, params, choice);
+    if (pt.emb == 0 || pt.emb == 1) {
+      // 2x2 on matrix bit emb of the 4x4: index bit 0 is the slot's first qubit
+      Mat e(16, cd(0, 0));
+      for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+          const int ib = (i >> pt.emb) & 1, jb = (j >> pt.emb) & 1;
+          const int io = (i >> (1 - pt.emb)) & 1, jo = (j >> (1 - pt.emb)) & 1;
+          if (io == jo) e[i * 4 + j] = m[ib * 2 + jb];
+        }
+      m = e;
+    } else if (pt.emb == 2) {
+      // swap the two matrix bits: index (b1 b0) -> (b0 b1)
+      auto sw = [](int x) { return ((x & 1) << 1) | ((x >> 1) & 1); };
+      Mat e(16);
+      for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) e[sw(i) * 4 + sw(j)] = m[i * 4 + j];
+      m = e;
+    }
+    M = mat_mul(m, M, d);
+  }
   return M;
 }
 
@@ -378,15 +399,46 @@ struct Fuser {
   }
 
   void flush(int q) {
-    if (run[q] >= 0) {
-      emit(run[q]);
+    const int s = run[q];
+    if (s >= 0) {
+      emit(s);
       run[q] = -1;
+      if (pass.slots[s].type == DOP_M2) run[pass.slots[s].q[0] == q ? pass.slots[s].q[1] : pass.slots[s].q[0]] = -1;
     }
   }
 
-  void one_qubit(int q, const Part& pt) {
+  void one_qubit(int q, Part pt) {
     if (run[q] < 0) run[q] = new_slot(local[q] >= 0 ? DOP_M1 : DOP_D1, q, -1);
+    const Slot& s = pass.slots[run[q]];
+    if (s.type == DOP_M2) pt.emb = s.q[0] == q ? 0 : 1;
     add_part(run[q], pt);
+  }
+
+  // Pair fusion: a diagonal 2-qubit operation whose qubits both hold an open
+  // 2x2 run (in the tile) turns the run of its first qubit into a 4x4 slot that
+  // takes the other run, the operation, and the following 1-qubit operations
+  // on either qubit; the other run's slot is left empty and dropped at finish.
+  bool fuse_pair(int si) {
+    const Step& st = steps[si];
+    const int a = st.q[0], b = st.q[1];
+    if (!plan.pair_fusion || !st.diag || local[a] < 0 || local[b] < 0) return false;
+    if (run[a] < 0 || run[b] < 0 || run[a] == run[b]) return false;
+    Slot& sa = pass.slots[run[a]];
+    Slot& sb = pass.slots[run[b]];
+    if (sa.type != DOP_M1 || sb.type != DOP_M1) return false;
+    sa.type = DOP_M2;
+    sa.q[1] = b;
+    for (Part& pt : sa.parts) pt.emb = 0;
+    for (Part pt : sb.parts) {
+      pt.emb = 1;
+      add_part(run[a], pt);
+    }
+    sb.parts.clear();
+    sb.sites.clear();
+    sb.uses_params = false;
+    add_part(run[a], Part{si, -1});
+    run[b] = run[a];
+    return true;
   }
 
   void take(int si) {
@@ -437,7 +489,14 @@ struct Fuser {
         return;
       }
     }
-    // 2-qubit operation
+    // 2-qubit operation: into the open 4x4 slot of exactly its two qubits, or
+    // merged with the 2x2 runs on them, or a slot of its own
+    if (run[st.q[0]] >= 0 && run[st.q[0]] == run[st.q[1]]) {
+      const Slot& sl = pass.slots[run[st.q[0]]];
+      add_part(run[st.q[0]], Part{si, -1, sl.q[0] == st.q[0] ? -1 : 2});
+      return;
+    }
+    if (fuse_pair(si)) return;
     flush(st.q[0]);
     flush(st.q[1]);
     int s = new_slot(st.diag ? DOP_D2 : DOP_M2, st.q[0], st.q[1]);
@@ -447,6 +506,30 @@ struct Fuser {
 
   void finish() {
     for (int q = 0; q < plan.n; ++q) flush(q);
+    // drop slots no operation refers to (runs taken over by pair fusion)
+    std::vector<int> remap(pass.slots.size(), -1);
+    auto slot_ref = [](DOp& op) -> uint16_t* {
+      switch (op.type) {
+        case DOP_M1:
+        case DOP_M2:
+        case DOP_D1:
+        case DOP_D2: return &op.slot[0];
+        case DOP_KR: return &op.slot[1];
+        default: return nullptr;
+      }
+    };
+    for (DOp& op : pass.ops)
+      if (uint16_t* r = slot_ref(op)) remap[*r] = 0;
+    std::vector<Slot> kept;
+    for (size_t i = 0; i < pass.slots.size(); ++i)
+      if (remap[i] == 0) {
+        remap[i] = (int)kept.size();
+        kept.push_back(pass.slots[i]);
+      }
+    if (kept.size() == pass.slots.size()) return;
+    pass.slots.swap(kept);
+    for (DOp& op : pass.ops)
+      if (uint16_t* r = slot_ref(op)) *r = (uint16_t)remap[*r];
   }
 };
 
@@ -558,11 +641,17 @@ static void schedule_phases(Pass& ps, int min_fill) {
       if (!done[p]) return false;
     return true;
   };
-  // register bits an operation needs (4x4 matrices go through LDS and need none)
+  // register bits an operation needs (a 4x4 matrix both of its bits: the
+  // compiled kernels then apply it in registers)
   auto local_bits = [&](const DOp& op, int* b) -> int {
     if (op.type == DOP_M1 || op.type == DOP_MR || op.type == DOP_KR || op.type == DOP_DOT) {
       b[0] = op.a;
       return 1;
+    }
+    if (op.type == DOP_M2) {
+      b[0] = op.a;
+      b[1] = op.b;
+      return 2;
     }
     return 0;
   };
@@ -598,7 +687,8 @@ static void schedule_phases(Pass& ps, int min_fill) {
       // and switch registers instead.
       int m1_here = 0, m1_other = 0, reg_others = 0;
       for (int i = 0; i < nops; ++i)
-        if (!done[i] && ready(i) && ps.ops[i].type == DOP_M1) (fits(ps.ops[i]) ? m1_here : m1_other) += 1;
+        if (!done[i] && ready(i) && (ps.ops[i].type == DOP_M1 || ps.ops[i].type == DOP_M2))
+          (fits(ps.ops[i]) ? m1_here : m1_other) += ps.ops[i].type == DOP_M2 ? 2 : 1;
       for (int i : wave)  // measure-resets and gradient terms in registers: never put off
         if (ps.ops[i].type == DOP_MR || ps.ops[i].type == DOP_KR || ps.ops[i].type == DOP_DOT) ++reg_others;
       if (!force_wave && reg_others == 0 && m1_here > 0 && m1_here < min_fill &&
@@ -1008,6 +1098,7 @@ ptsbe_status build_plan(const ptsbe_circuit* c, const ptsbe_noise_model* nm, con
   P.use_jit = !(o && (o->flags & PTSBE_PLAN_NO_COMPILE));
   P.half_tile_lds = o && (o->flags & PTSBE_PLAN_HALF_TILE_LDS);
   P.waves = o ? (int)((o->flags >> PTSBE_PLAN_WAVES_SHIFT) & 15u) : 0;
+  P.pair_fusion = !(o && (o->flags & PTSBE_PLAN_NO_PAIR_FUSION));
   if (P.waves > 8) return fail(PTSBE_E_ARG, "waves per SIMD must be 0 (default) or 1..8");
   P.jit = std::make_shared<JitProgram>();
   // channels

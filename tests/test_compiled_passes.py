@@ -109,13 +109,41 @@ def test_brick_phase_frames(frames):
     from compiled_cpu import pass_source
     from workloads import brick_circuit
     circ = brick_circuit(12, 5, np.random.default_rng(8), 0.08, 0.1, eps_sigma=0.05)
-    plan = P.ptsbe_plan(circ, phase_frames=frames)
+    plan = P.ptsbe_plan(circ, phase_frames=frames, pair_fusion=False)
     srcs = "".join(pass_source(plan, p) for p in range(plan.info["n_passes"]))
     assert ("= cr(m0.x" in srcs) == frames
     assert ("  if (__builtin_expect((ovw" in srcs) == frames   # override branch of a rewritten slot
     ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=6, total_shots=6, seed=6, cfg=2)
     g = ts.get()
     assert sum(1 for r in g["records"] if len(r)) >= 2
+    st = run_compiled(plan, ts)
+    ref, _ = oracle_states(circ, g["records"])
+    assert max(float(np.max(np.abs(st[a] - ref[a]))) for a in range(len(ref))) <= 1e-5
+
+
+def test_brick_pair_fusion():
+    """Pair fusion on a brick circuit: each even-layer CZ merges with the 2x2
+    runs on its qubits into a 4x4 slot that also takes the next layer's gates on
+    them, applied in registers (both bits register bits, no pass through the
+    LDS tile for it); noise overrides of the 4x4 slots included, the states
+    match the oracle, and the plan has fewer 2x2 register groups than without."""
+    from collections import Counter
+    from compiled_cpu import pass_source
+    from paper_2504_16297_amd.tables import export_tables
+    from workloads import brick_circuit
+    circ = brick_circuit(12, 6, np.random.default_rng(9), 0.06, 0.1, eps_sigma=0.05)
+    plan = P.ptsbe_plan(circ)
+    srcs = [pass_source(plan, p) for p in range(plan.info["n_passes"])]
+    assert any("cd4(M + " in s for s in srcs)                 # 4x4 in registers
+    assert not any("cd4(m, x0" in s for s in srcs)            # never through the tile
+    ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=6, total_shots=6, seed=7, cfg=2)
+    g = ts.get()
+    assert sum(1 for r in g["records"] if len(r)) >= 3
+    ops = Counter(int(o["type"]) for o in export_tables(ts, None)["ops"])
+    plain = P.ptsbe_plan(circ, pair_fusion=False)
+    ts0 = P.ptsbe_sample_kraus(plain, "proportional", n_draws=6, total_shots=6, seed=7, cfg=2)
+    ops0 = Counter(int(o["type"]) for o in export_tables(ts0, None)["ops"])
+    assert ops[2] > 0 and ops0[2] == 0 and ops[8] < ops0[8]   # M2 slots, fewer M1G groups
     st = run_compiled(plan, ts)
     ref, _ = oracle_states(circ, g["records"])
     assert max(float(np.max(np.abs(st[a] - ref[a]))) for a in range(len(ref))) <= 1e-5

@@ -130,8 +130,8 @@ def test_phase_frames_keep_states_and_make_real_diagonals():
     from workloads.circuits import brick_circuit
     import math
     circ = brick_circuit(8, 6, np.random.default_rng(5), 0.05, 0.08, eps_sigma=0.02)
-    framed = P.ptsbe_plan(circ, precision="c128", tile_qubits=6)
-    plain = P.ptsbe_plan(circ, precision="c128", tile_qubits=6, phase_frames=False)
+    framed = P.ptsbe_plan(circ, precision="c128", tile_qubits=6, pair_fusion=False)
+    plain = P.ptsbe_plan(circ, precision="c128", tile_qubits=6, phase_frames=False, pair_fusion=False)
     ts_f = P.ptsbe_sample_kraus(framed, "proportional", n_draws=16, total_shots=16, seed=4, cfg=2)
     ts_p = P.ptsbe_sample_kraus(plain, "proportional", n_draws=16, total_shots=16, seed=4, cfg=2)
     tf, tp = export_tables(ts_f), export_tables(ts_p)
