@@ -356,6 +356,32 @@ def test_phase_frames_match_plain_plan(n, prec):
     assert err_f <= tol and err_p <= tol
 
 
+@pytest.mark.parametrize("n,prec,kw", [(14, "c64", {}), (12, "c128", {}), (13, "c64", {"compile": False}),
+                                       (12, "c64", {"tile_qubits": 8})])
+def test_pair_fusion_matches_unfused_plan(n, prec, kw):
+    """Brick circuit with 1- and 2-qubit noise and over-rotations: the plan with
+    pair fusion (4x4 slots over two layers of a pair, with per-trajectory 4x4
+    overrides) and without it give the oracle's states, through the compiled
+    kernels, the generic register kernel and smaller tiles."""
+    from workloads import brick_circuit
+    log(f"[pair fusion] n={n} {prec} {kw}")
+    circ = brick_circuit(n, 8, np.random.default_rng(110 + n), 0.03, 0.06, eps_sigma=0.05)
+    fused = P.ptsbe_plan(circ, precision=prec, **kw)
+    plain = P.ptsbe_plan(circ, precision=prec, pair_fusion=False, **kw)
+    ts_f = P.ptsbe_sample_kraus(fused, "proportional", n_draws=20, total_shots=20, seed=5, cfg=2)
+    ts_p = P.ptsbe_sample_kraus(plain, "proportional", n_draws=20, total_shots=20, seed=5, cfg=2)
+    recs = ts_f.get()["records"]
+    assert recs == ts_p.get()["records"] and sum(1 for r in recs if len(r)) >= 5
+    a = _states(fused, ts_f)
+    b = _states(plain, ts_p)
+    tol = 1e-5 if prec == "c64" else 1e-12
+    ref, _ = oracle_states(circ, recs)
+    err_f = max(float(np.max(np.abs(a[i] - ref[i]))) for i in range(len(ref)))
+    err_p = max(float(np.max(np.abs(b[i] - ref[i]))) for i in range(len(ref)))
+    log(f"  max|fused - oracle| = {err_f:.2e}, max|unfused - oracle| = {err_p:.2e}")
+    assert err_f <= tol and err_p <= tol
+
+
 def test_twirled_amplitude_damping_states():
     """A circuit with amplitude damping, planned with its Pauli twirl
     (PTSBE_PLAN_TWIRL): trajectory states equal the oracle's for the twirled
