@@ -14,9 +14,12 @@
 //              FP64 norm and inclusive prefix sum of |psi|^2 per state:
 //              per-thread sequential sums, wavefront shuffles, an LDS tree,
 //              then block offsets (reduce-then-scan, no inter-block waiting).
-//  k_sample    per (trajectory, chunk of shots): Philox4x64-10 uniforms, an
-//              LDS bitonic sort, and an upper-bound search of u * total in the
-//              CDF; writes the basis index and the trajectory id of each shot.
+//  k_sample    per (trajectory, chunk of shots): Philox4x64-10 uniforms, a
+//              bitonic sort (strides below 16 in registers, 16 elements per
+//              thread), and an upper-bound search of u * total in the CDF,
+//              each thread's next sorted element searched from its previous
+//              result on; writes the basis index and the trajectory id of
+//              each shot.
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -986,6 +989,24 @@ __global__ void k_mr_decide(MrDecideArgs a) {
 
 // ------------------------------------------------------------------ sampler
 
+// One register stage of the bitonic network on a thread's 16 elements
+// 16c .. 16c + 15: pairs (r, r + stride) for (r & stride) == 0, ascending where
+// ((16c + r) & size) == 0.  Called with constant stride (unrolled) so x stays
+// in registers.
+__device__ __forceinline__ void sort_stage_regs(double (&x)[16], uint32_t size, uint32_t stride, uint32_t c) {
+#pragma unroll
+  for (uint32_t r = 0; r < 16; ++r) {
+    if (r & stride) continue;
+    const uint32_t h = r | stride;
+    const bool up = (((16u * c + r) & size) == 0);
+    const double xa = x[r], xb = x[h];
+    if ((xa > xb) == up) {
+      x[r] = xb;
+      x[h] = xa;
+    }
+  }
+}
+
 template <typename BitT>
 __global__ __launch_bounds__(256) void k_sample(SampleArgs<BitT> a) {
   __shared__ double u[4096];
@@ -1008,46 +1029,106 @@ __global__ __launch_bounds__(256) void k_sample(SampleArgs<BitT> a) {
   const uint64_t alpha = a.alpha0 + t;
   const uint64_t k1 = stream_key1(2, a.cfg, alpha);
   const uint64_t out0 = a.shot_off[t] + j0;
+  // Element i of the chunk lives at LDS index (i & 15) * R + (i >> 4), R = C / 16
+  // columns: thread col < R holds elements 16 col .. 16 col + 15 of a row-major 16 x R
+  // view, so register loads, column-pair LDS stages and the uniforms' stores
+  // are bank-conflict free.
+  const uint32_t R = C >> 4;
   // uniforms: shot j uses word j of the trajectory's sampler stream
   for (uint32_t i = threadIdx.x * 4; i < C; i += blockDim.x * 4) {
     if (a.uniforms) {
-      for (int w = 0; w < 4; ++w) u[i + w] = (i + w < cnt) ? a.uniforms[out0 + i + w] : 2.0;
+      for (int w = 0; w < 4; ++w) u[((i + w) & 15u) * R + ((i + w) >> 4)] = (i + w < cnt) ? a.uniforms[out0 + i + w] : 2.0;
     } else {
       const uint64_t j = j0 + i;  // multiple of 4 because C and i are
       U64x4 r = philox4x64_10(j / 4 + 1, 0, 0, 0, a.seed, k1);
-      for (int w = 0; w < 4; ++w) u[i + w] = (i + w < cnt) ? word_to_uniform(r.v[w]) : 2.0;
+      for (int w = 0; w < 4; ++w)
+        u[((i + w) & 15u) * R + ((i + w) >> 4)] = (i + w < cnt) ? word_to_uniform(r.v[w]) : 2.0;
     }
   }
   __syncthreads();
-  // bitonic sort of C values in LDS (padding 2.0 sorts last)
-  for (uint32_t size = 2; size <= C; size <<= 1) {
-    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-      for (uint32_t i = threadIdx.x; i < C / 2; i += blockDim.x) {
-        const uint32_t lo_i = 2 * i - (i & (stride - 1));
-        const uint32_t hi_i = lo_i + stride;
-        const bool up = ((lo_i & size) == 0);
-        const double x = u[lo_i], y = u[hi_i];
-        if ((x > y) == up) {
-          u[lo_i] = y;
-          u[hi_i] = x;
+  // Bitonic sort of the C values (padding 2.0 sorts last): every stage compares
+  // elements i and i + stride for (i & stride) == 0, ascending where
+  // (i & size) == 0.  Strides below 16 pair elements of one thread and run in
+  // registers; larger strides pair columns of one row in LDS.
+  const uint32_t col = threadIdx.x;
+  const bool holder = col < R;
+  double x[16];
+  if (holder) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) x[r] = u[r * R + col];
+#pragma unroll
+    for (uint32_t size = 2; size <= 16; size <<= 1)
+#pragma unroll
+      for (uint32_t stride = size >> 1; stride > 0; stride >>= 1)
+        sort_stage_regs(x, size, stride, col);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) u[r * R + col] = x[r];
+  }
+  __syncthreads();
+  for (uint32_t size = 32; size <= C; size <<= 1) {
+    for (uint32_t stride = size >> 1; stride >= 16; stride >>= 1) {
+      const uint32_t sc = stride >> 4, half = R >> 1;
+      for (uint32_t q = threadIdx.x; q < C / 2; q += blockDim.x) {
+        const uint32_t row = q / half, pc = q - row * half;
+        const uint32_t lo_c = 2 * pc - (pc & (sc - 1)), hi_c = lo_c + sc;
+        const bool up = (((lo_c << 4) & size) == 0);
+        const double xa = u[row * R + lo_c], xb = u[row * R + hi_c];
+        if ((xa > xb) == up) {
+          u[row * R + lo_c] = xb;
+          u[row * R + hi_c] = xa;
         }
       }
       __syncthreads();
     }
+    if (holder) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) x[r] = u[r * R + col];
+#pragma unroll
+      for (uint32_t stride = 8; stride > 0; stride >>= 1) sort_stage_regs(x, size, stride, col);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) u[r * R + col] = x[r];
+    }
+    __syncthreads();
   }
+  // Each holder's 16 elements are consecutive in sorted order: the first is
+  // found by bisection, each next one from the previous result on (exponential
+  // probe, then bisection), since its answer can only be at or after it.  The
+  // index found is the first with cdf > u * total, as a bisection from 0 finds.
+  // Results go through LDS so the global stores stay coalesced.
   const double* cdf = a.cdf_base + (uint64_t)(t - a.b0) * a.cdf_stride;
   const double total = a.total[t - a.b0];
   const uint64_t N = a.N;
-  for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
-    const double v = u[i] * total;
-    uint64_t l = 0, h = N;  // first index with cdf > v
-    while (l < h) {
-      const uint64_t mid = (l + h) >> 1;
-      if (cdf[mid] > v)
-        h = mid;
-      else
-        l = mid + 1;
+  if (holder) {
+    uint64_t p = 0;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      if (16u * col + (uint32_t)r < cnt) {
+        const double v = x[r] * total;
+        uint64_t lo = r == 0 ? 0 : p, h = N;
+        if (r != 0) {
+          uint64_t probe = lo, step = 1;
+          while (probe < N && !(cdf[probe] > v)) {
+            lo = probe + 1;
+            probe = lo + step;
+            step <<= 1;
+          }
+          h = probe < N ? probe : N;
+        }
+        while (lo < h) {
+          const uint64_t mid = (lo + h) >> 1;
+          if (cdf[mid] > v)
+            h = mid;
+          else
+            lo = mid + 1;
+        }
+        p = lo;
+        u[r * R + col] = __longlong_as_double((long long)p);
+      }
     }
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
+    uint64_t l = (uint64_t)__double_as_longlong(u[(i & 15u) * R + (i >> 4)]);
     if (l > N - 1) l = N - 1;
     a.bits[out0 + i] = (BitT)l;
     a.traj[out0 + i] = (uint32_t)alpha;
