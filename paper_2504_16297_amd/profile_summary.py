@@ -9,9 +9,10 @@ project, and read those summaries back.
 dispatches of the named kernel and scales each by what the same counter reads
 for a plain device copy of known size (the copy's bytes divided by its
 counter), giving HBM bytes per dispatch.  The summary records the fingerprint
-of the kernels the counters were taken with (`kernel_fingerprint`: the generic
-kernels' source and the generated source of every pass of the workload's plan),
-so a reader can tell when the kernels have changed since.
+of the kernels the counters were taken with (`kernel_fingerprint`: the
+generated source of every pass of the workload's plan, and the generic kernels'
+source when a pass runs those), so a reader can tell when the kernels have
+changed since.
 """
 
 import argparse
@@ -22,20 +23,26 @@ import re
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
+
+
 def kernel_fingerprint(plan):
-    """SHA-256 prefix over the generic tile kernels' source and the generated
-    source of every pass of `plan` (what runs on the device for it)."""
+    """SHA-256 prefix over what runs on the device for the passes of `plan`:
+    the generated source of every pass, and the generic tile kernels' source
+    when some pass has no generated kernel (it then runs the generic ones)."""
     import ctypes as C
     from . import _lib as L
     h = hashlib.sha256()
-    with open(os.path.join(HERE, "csrc", "kernels.hip"), "rb") as f:
-        h.update(f.read())
+    generic = False
     for p in range(plan.info["n_passes"]):
         n = C.c_size_t()
         L.check(L.lib().ptsbe_plan_pass_source(plan.handle, p, 0, None, C.byref(n)))
         buf = C.create_string_buffer(n.value)
         L.check(L.lib().ptsbe_plan_pass_source(plan.handle, p, 0, buf, C.byref(n)))
+        generic = generic or not buf.value
         h.update(buf.value)
+    if generic:
+        with open(os.path.join(HERE, "csrc", "kernels.hip"), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
