@@ -108,6 +108,31 @@ def test_caller_uniforms_and_edges():
     assert bad == 0
 
 
+@pytest.mark.parametrize("chunk", [256, 512, 1024, 2048, 4096])
+def test_sampler_chunk_sizes(chunk):
+    """Every sort chunk size (the in-register / LDS split of the sort changes
+    with it): a peaked state (many repeated outcomes, so searches continue from
+    the previous result) and a spread one, with ragged last chunks and Philox
+    uniforms; shots equal the oracle's sampler."""
+    log(f"[sampler] chunk={chunk}")
+    peaked = {"n_qubits": 10, "params": [], "channels": [], "rules": [],
+              "ops": [{"kind": "gate", "name": "RY", "qubits": (q,), "params": (0.3 + 0.1 * q,), "tag": "RY"}
+                      for q in range(10)]}
+    spread = random_small_circuit(10, 60, np.random.default_rng(chunk), p1=0.0, p2=0.0)
+    for circ in (peaked, spread):
+        plan = P.ptsbe_plan(circ)
+        m = [3 * chunk + 17, chunk, 5, 0, chunk - 1]
+        ts = P.ptsbe_trajset_from_records(plan, [()] * len(m), m)
+        r = P.ptsbe_run_batch(plan, ts, mode="shots", seed=21, cfg=4, sort_chunk=chunk)
+        torch.cuda.synchronize()
+        bits = r["bits"].cpu().numpy()
+        ref, _ = oracle_states(circ, [()])
+        off = np.concatenate([[0], np.cumsum(m)])
+        for a in range(len(m)):
+            bad, _ = compare_shots(ref[0], bits[off[a]:off[a + 1]], m[a], 21, 4, a, chunk=chunk)
+            assert bad == 0, (chunk, a)
+
+
 def test_zero_shot_trajectories_and_capacity_error():
     circ = random_small_circuit(4, 20, np.random.default_rng(9))
     plan = P.ptsbe_plan(circ)
