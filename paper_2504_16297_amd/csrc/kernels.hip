@@ -1090,40 +1090,42 @@ __global__ __launch_bounds__(256) void k_sample(SampleArgs<BitT> a) {
     }
     __syncthreads();
   }
-  // Each holder's 16 elements are consecutive in sorted order: the first is
-  // found by bisection, each next one from the previous result on (exponential
-  // probe, then bisection), since its answer can only be at or after it.  The
-  // index found is the first with cdf > u * total, as a bisection from 0 finds.
-  // Results go through LDS so the global stores stay coalesced.
+  // Each thread takes g = ceil(cnt / blockDim) consecutive elements of the
+  // sorted chunk: the first is found by bisection, each next one from the
+  // previous result on (exponential probe, then bisection), since its answer
+  // can only be at or after it.  The index found is the first with
+  // cdf > u * total, as a bisection from 0 finds.  A thread reads and then
+  // overwrites only its own elements' LDS slots with the results, which go out
+  // after the barrier in coalesced stores.
   const double* cdf = a.cdf_base + (uint64_t)(t - a.b0) * a.cdf_stride;
   const double total = a.total[t - a.b0];
   const uint64_t N = a.N;
-  if (holder) {
+  {
+    const uint32_t g = (cnt + blockDim.x - 1) / blockDim.x;
+    const uint32_t e0 = threadIdx.x * g, e1 = min(cnt, e0 + g);
     uint64_t p = 0;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      if (16u * col + (uint32_t)r < cnt) {
-        const double v = x[r] * total;
-        uint64_t lo = r == 0 ? 0 : p, h = N;
-        if (r != 0) {
-          uint64_t probe = lo, step = 1;
-          while (probe < N && !(cdf[probe] > v)) {
-            lo = probe + 1;
-            probe = lo + step;
-            step <<= 1;
-          }
-          h = probe < N ? probe : N;
+    for (uint32_t e = e0; e < e1; ++e) {
+      const uint32_t li = (e & 15u) * R + (e >> 4);
+      const double v = u[li] * total;
+      uint64_t lo = e == e0 ? 0 : p, h = N;
+      if (e != e0) {
+        uint64_t probe = lo, step = 1;
+        while (probe < N && !(cdf[probe] > v)) {
+          lo = probe + 1;
+          probe = lo + step;
+          step <<= 1;
         }
-        while (lo < h) {
-          const uint64_t mid = (lo + h) >> 1;
-          if (cdf[mid] > v)
-            h = mid;
-          else
-            lo = mid + 1;
-        }
-        p = lo;
-        u[r * R + col] = __longlong_as_double((long long)p);
+        h = probe < N ? probe : N;
       }
+      while (lo < h) {
+        const uint64_t mid = (lo + h) >> 1;
+        if (cdf[mid] > v)
+          h = mid;
+        else
+          lo = mid + 1;
+      }
+      p = lo;
+      u[li] = __longlong_as_double((long long)p);
     }
   }
   __syncthreads();
