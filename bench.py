@@ -108,6 +108,27 @@ def measured_traffic(plan):
     return r[0]
 
 
+def pass_roofline(flops_per_launch, bytes_per_launch, launch_ms, traffic):
+    """Roofline entry of the tile-pass kernels.  Their arithmetic intensity
+    (useful FP32 flops per algorithmic HBM byte) against the machine balance
+    (FP32 peak / HBM peak) decides which roof bounds them; the other roof is
+    reported beside it."""
+    tflops = flops_per_launch / (launch_ms * 1e-3) / 1e12
+    gbs = bytes_per_launch / (launch_ms * 1e-3) / 1e9
+    ai = flops_per_launch / bytes_per_launch
+    balance = FP32_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
+    hbm = {"achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
+    alu = {"achieved": tflops, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": tflops / FP32_PEAK_TFLOPS}
+    main_roof, other = ("hbm", alu) if ai < balance else ("alu", hbm)
+    r = {"bound": main_roof}
+    r.update(hbm if main_roof == "hbm" else alu)
+    r.update({"traffic": traffic, "kernel": "ptsbe_pass_* (compiled fused tile passes)",
+              "avg_launch_ms": launch_ms, "flops_per_launch": flops_per_launch,
+              "bytes_per_launch": bytes_per_launch, "flops_per_byte": ai, "machine_balance": balance,
+              ("alu" if main_roof == "hbm" else "hbm"): other})
+    return r
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -214,9 +235,7 @@ def main():
     T = np.sum(timings, axis=0)
     pass_ms = T[0] / T[1]
     pass_bytes = T[6] / T[1]
-    gbs = pass_bytes / (pass_ms * 1e-3) / 1e9
     pass_flops = T[8] / T[1]
-    tflops = pass_flops / (pass_ms * 1e-3) / 1e12
     log(f"[bench] {ms_per_step:.2f} ms/step, {value:.4g} shots/s; passes {T[0]/args.steps:.2f} ms/step "
         f"({T[1]/args.steps:.0f} launches), scan {T[3]/args.steps:.2f} ms, sampler {T[4]/args.steps:.2f} ms")
 
@@ -225,12 +244,7 @@ def main():
               "vs_baseline": None, "dtype": "c64 (fp32 state, fp64 norm/CDF)", "data": "synthetic",
               "config": {"workload": wl["name"], "n_qubits": 20, "layers": 40, "draws": pts["n_draws"],
                          "unique_trajectories": B, "total_shots": S, "parallelism": "single GPU, batched"},
-              "roofline": {"bound": "alu", "achieved": tflops, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                           "frac": tflops / FP32_PEAK_TFLOPS, "traffic": measured_traffic(plan),
-                           "kernel": "ptsbe_pass_* (compiled fused tile passes)", "avg_launch_ms": pass_ms,
-                           "flops_per_launch": pass_flops, "bytes_per_launch": pass_bytes,
-                           "hbm": {"achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                   "frac": gbs / HBM_PEAK_GBS}},
+              "roofline": pass_roofline(pass_flops, pass_bytes, pass_ms, measured_traffic(plan)),
               "stages_ms_per_step": {"passes": T[0] / args.steps, "scan": T[3] / args.steps,
                                      "sampler": T[4] / args.steps, "total_events": T[5] / args.steps},
               "state_passes_per_step": T[9] / args.steps, "state_passes_unshared": B * plan.info["n_passes"],
@@ -336,8 +350,6 @@ def bench_c4(args):
     per28 = np.sum(timings[2::3], axis=0)
     rate28 = runs[2]["S"] * args.steps / (per28[5] * 1e-3)
     pass_ms = T[0] / T[1]
-    tflops = T[8] / T[1] / (pass_ms * 1e-3) / 1e12
-    gbs = T[6] / T[1] / (pass_ms * 1e-3) / 1e9
     result = {"metric": METRIC, "value": value, "unit": "shots/s", "n_gpus": 1, "steps": args.steps,
               "warmup": args.warmup, "ms_per_step": dt * 1e3 / args.steps, "higher_is_better": True,
               "scaling": "weak", "vs_baseline": None, "dtype": "c64 (fp32 state, fp64 norm/CDF)",
@@ -345,11 +357,7 @@ def bench_c4(args):
               "config": {"workload": "C4 mixed batch: 24/26/28 qubits x 30 brick layers, 256/64/16 draws "
                                      "x 1e5 shots", "total_shots": S,
                          "trajectories": [r["ts"].n_traj for r in runs], "parallelism": "single GPU, batched"},
-              "roofline": {"bound": "alu", "achieved": tflops, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                           "frac": tflops / FP32_PEAK_TFLOPS, "traffic": None,
-                           "kernel": "ptsbe_pass_* (compiled fused tile passes)", "avg_launch_ms": pass_ms,
-                           "hbm": {"achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                   "frac": gbs / HBM_PEAK_GBS}},
+              "roofline": pass_roofline(T[8] / T[1], T[6] / T[1], pass_ms, None),
               "q28_batched_shots_per_s": rate28}
     if not args.no_baseline:
         r = runs[2]
