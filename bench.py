@@ -61,8 +61,8 @@ def cpu_baseline(wl, g, budget_s=12.0, workers=16):
     sampling of the average shot count per trajectory, extrapolated linearly to
     whole-job shots/s: first on one thread for ``budget_s`` seconds (at least one
     trajectory), then trajectory-parallel over min(workers, host cores) processes
-    (one thread each) on as many trajectories per process as the single thread
-    finished.  Call it before the process touches the GPU: the pool forks."""
+    (one thread each), one trajectory per process.  Call it before the process
+    touches the GPU: the pool forks."""
     global _CPU_JOB
     import multiprocessing as mp
 
@@ -82,7 +82,7 @@ def cpu_baseline(wl, g, budget_s=12.0, workers=16):
         dt1 = time.perf_counter() - t0
     single = done * avg_m / dt1
     procs = max(1, min(workers, os.cpu_count() or 1))
-    n_par = min(B, procs * done)
+    n_par = min(B, procs)
     with mp.get_context("fork").Pool(procs, initializer=_oracle_worker_init) as pool:
         t0 = time.perf_counter()
         for _ in pool.imap_unordered(_oracle_trajectory, range(n_par)):
