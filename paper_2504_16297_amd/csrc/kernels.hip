@@ -919,13 +919,24 @@ __global__ __launch_bounds__(256) void k_marginal(MarginalArgs<V> a) {
   } else {
     for (uint32_t i = threadIdx.x; i < a.per_block; i += blockDim.x) add(e0 + i, norm2(st[e0 + i]));
   }
+  // block totals of the nq + 1 sums: a wavefront butterfly per sum, then one
+  // LDS exchange and one barrier for all of them
+  __shared__ double wtot[4][kMaxGroup + 1];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
   for (int j = 0; j <= kMaxGroup; ++j) {
     if (j <= (int)a.nq) {  // uniform over the block
-      double ex, tot;
-      block_excl_scan(s[j], &ex, &tot);
-      if (threadIdx.x == 0) a.partial[((uint64_t)blockIdx.y * a.nblk + blockIdx.x) * (kMaxGroup + 1) + j] = tot;
+      double v = s[j];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+      if (lane == 0) wtot[wv][j] = v;
     }
+  }
+  __syncthreads();
+  if (threadIdx.x <= a.nq) {
+    const uint32_t j = threadIdx.x;
+    a.partial[((uint64_t)blockIdx.y * a.nblk + blockIdx.x) * (kMaxGroup + 1) + j] =
+        ((wtot[0][j] + wtot[1][j]) + wtot[2][j]) + wtot[3][j];
   }
 }
 
