@@ -3,8 +3,10 @@
 The tile size k (tile qubits per pass: more qubits per tile means fewer passes
 but more LDS per workgroup and so fewer resident workgroups per CU), the
 register-group fill threshold (fewer, fuller 2x2 groups against more register
-changes) and the half-tile register changes (half the LDS, two more barriers
-per change) trade against each other differently for every circuit.  `autotune`
+changes), the half-tile register changes (half the LDS, two more barriers
+per change) and pair fusion (4x4 slots over the 2x2 runs around a diagonal
+2-qubit gate: fewer flops in brick circuits, more where a 4x4 takes in little)
+trade against each other differently for every circuit.  `autotune`
 builds the plan for each candidate, compiles its passes, runs a sample of the
 trajectory set through the library's stage timer on the device, and returns the
 candidate with the least tile-pass time on that sample.  Trajectory records are
@@ -21,18 +23,24 @@ from . import (ptsbe_plan, ptsbe_plan_compile, ptsbe_run_batch, ptsbe_trajset_fr
 
 
 def candidates_for(n, precision):
+    """(tile_qubits, min_fill, half_tile, pair_fusion) candidates: the two largest
+    register-kernel tiles that fit n qubits (0 = the planner's choice when none
+    does), fill 2 or 3, whole or half-tile register changes, pair fusion on or
+    off."""
     top = 12 if precision == "c64" else 11
     tiles = [t for t in (top, top - 1) if 6 <= t <= n] or [0]
-    return [(t, f, h) for t in tiles for f in (2, 3) for h in (False, True)]
+    return [(t, f, h, pf) for t in tiles for f in (2, 3) for h in (False, True) for pf in (True, False)]
 
 
 def autotune(circuit, precision="c64", records=None, sample=64, candidates=None, reps=2, params=None,
              stream=None, log=None):
-    """Pick (tile_qubits, min_fill, half_tile) for `circuit`.  `records`: trajectory
-    records (list of (site, k) tuples) to time on, e.g. from ts.get()["records"];
-    the first `sample` are used (an error-free record if none are given).
-    Returns {"tile_qubits", "min_fill", "half_tile", "results": [(tile, fill,
-    half, ms in the tile passes for the sample, compile s)], "seconds"}."""
+    """Pick (tile_qubits, min_fill, half_tile, pair_fusion) for `circuit`.
+    `records`: trajectory records (list of (site, k) tuples) to time on, e.g.
+    from ts.get()["records"]; the first `sample` are used (an error-free record
+    if none are given).  Returns {"tile_qubits", "min_fill", "half_tile",
+    "pair_fusion", "results": [(tile, fill, half, pair, ms in the tile passes for
+    the sample, compile s)], "seconds"}; the first four are ptsbe_plan's keyword
+    arguments."""
     import torch
     t_start = time.perf_counter()
     n = circuit["n_qubits"]
@@ -42,8 +50,9 @@ def autotune(circuit, precision="c64", records=None, sample=64, candidates=None,
     results = []
     best = None
     obs = [(1.0, (0,))]
-    for tile, fill, half in cands:
-        plan = ptsbe_plan(circuit, precision=precision, tile_qubits=tile, min_fill=fill, half_tile=half)
+    for tile, fill, half, pair in cands:
+        plan = ptsbe_plan(circuit, precision=precision, tile_qubits=tile, min_fill=fill, half_tile=half,
+                          pair_fusion=pair)
         _, csec = ptsbe_plan_compile(plan)
         ts = ptsbe_trajset_from_records(plan, recs, m)
         ws = torch.empty(ptsbe_workspace_size(plan, ts, "expectation", params=params), dtype=torch.uint8,
@@ -58,12 +67,12 @@ def autotune(circuit, precision="c64", records=None, sample=64, candidates=None,
                             out=out, stream=stream, timing=tm)
             tms.append(tm[0])
         ms = float(min(tms))
-        results.append((tile, fill, half, ms, csec))
+        results.append((tile, fill, half, pair, ms, csec))
         if log:
-            log(f"[tune] tile {tile} fill {fill} half-tile LDS {half}: {ms:.3f} ms in tile passes "
-                f"({plan.info['n_passes']} passes), compile {csec:.1f} s")
+            log(f"[tune] tile {tile} fill {fill} half-tile LDS {half} pair fusion {pair}: {ms:.3f} ms in "
+                f"tile passes ({plan.info['n_passes']} passes), compile {csec:.1f} s")
         if best is None or ms < best[0]:
-            best = (ms, tile, fill, half)
+            best = (ms, tile, fill, half, pair)
         del ws, out
-    return {"tile_qubits": best[1], "min_fill": best[2], "half_tile": best[3], "results": results,
-            "seconds": time.perf_counter() - t_start}
+    return {"tile_qubits": best[1], "min_fill": best[2], "half_tile": best[3], "pair_fusion": best[4],
+            "results": results, "seconds": time.perf_counter() - t_start}

@@ -407,6 +407,27 @@ def test_pair_fusion_matches_unfused_plan(n, prec, kw):
     assert err_f <= tol and err_p <= tol
 
 
+def test_autotune_picks_a_valid_plan():
+    """The launch-shape tuner times every candidate on a sample of records and
+    returns the fastest; the plan it names gives the oracle's states."""
+    from paper_2504_16297_amd.tune import autotune
+    from workloads import brick_circuit
+    circ = brick_circuit(12, 6, np.random.default_rng(31), 0.02, 0.05, eps_sigma=0.05)
+    plan0 = P.ptsbe_plan(circ)
+    recs = P.ptsbe_sample_kraus(plan0, "proportional", n_draws=16, total_shots=16, seed=2, cfg=2).get()["records"]
+    res = autotune(circ, records=recs, sample=8, reps=1, log=log)
+    assert len(res["results"]) == 16 and all(r[4] > 0 for r in res["results"])
+    assert min(r[4] for r in res["results"]) == next(
+        r[4] for r in res["results"] if r[:4] == (res["tile_qubits"], res["min_fill"], res["half_tile"],
+                                                 res["pair_fusion"]))
+    plan = P.ptsbe_plan(circ, tile_qubits=res["tile_qubits"], min_fill=res["min_fill"],
+                        half_tile=res["half_tile"], pair_fusion=res["pair_fusion"])
+    ts = P.ptsbe_trajset_from_records(plan, recs[:8], [1] * 8)
+    st = _states(plan, ts)
+    ref, _ = oracle_states(circ, recs[:8])
+    assert max(float(np.max(np.abs(st[i] - ref[i]))) for i in range(8)) <= 1e-5
+
+
 def test_twirled_amplitude_damping_states():
     """A circuit with amplitude damping, planned with its Pauli twirl
     (PTSBE_PLAN_TWIRL): trajectory states equal the oracle's for the twirled
