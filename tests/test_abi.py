@@ -163,3 +163,33 @@ def test_workspace_query_needs_no_outputs():
     ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=5, total_shots=5, seed=1, cfg=5)
     for mode in ("shots", "states", "expectation"):
         assert P.ptsbe_workspace_size(plan, ts, mode, params=circ["params"]) > 5 * (1 << 6) * 8
+
+
+def test_gate_and_channel_library_matches_oracle():
+    """The library's standard gates and channels (ptsbe_std_gate,
+    ptsbe_std_channel) equal the oracle's independently written matrices and
+    Kraus lists, operator by operator in the same order (the order is what a
+    trajectory record's Kraus index refers to)."""
+    from oracle.channels import kraus_ops
+    from oracle.gates import gate_matrix
+    rng = np.random.default_rng(17)
+    cases = [("U3", tuple(rng.uniform(0, 6.3, 3))), ("RX", (0.7,)), ("RY", (-1.3,)), ("RZ", (2.9,))]
+    cases += [(g, ()) for g in ("H", "X", "Y", "Z", "S", "T", "CZ", "CNOT", "SWAP")]
+    for name, params in cases:
+        flat, nq = P.std_gate(name, params)
+        d = 1 << nq
+        m = (flat[0::2] + 1j * flat[1::2]).reshape(d, d)
+        ref = gate_matrix(name, params)
+        assert ref.shape == (d, d) and np.allclose(m, ref, atol=1e-14), name
+    chans = [{"name": "depolarizing", "nq": 1, "p": 0.07}, {"name": "depolarizing", "nq": 2, "p": 0.11},
+             {"name": "xflip", "nq": 1, "p": 0.2}, {"name": "pauli", "nq": 1, "probs": [0.1, 0.05, 0.15]},
+             {"name": "u3_mixture", "nq": 1, "p": 0.3, "params": [0.4, 1.1, -0.6]},
+             {"name": "amplitude_damping", "nq": 1, "gamma": 0.35}]
+    for ch in chans:
+        flat, nq, nk = P.std_channel(ch)
+        d = 1 << nq
+        ks = (flat[0::2] + 1j * flat[1::2]).reshape(nk, d, d)
+        ref = kraus_ops(ch)
+        assert len(ref) == nk, ch["name"]
+        for k in range(nk):
+            assert np.allclose(ks[k], ref[k], atol=1e-14), (ch["name"], k)
