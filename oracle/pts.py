@@ -27,6 +27,11 @@ Allocations:
 * ``reweight``       -- m_alpha proportional to p'_alpha = p_alpha / sum over the
   selected set of p_beta (Sec. 3.1), largest remainder.
 * ``uniform``        -- every kept record gets ``nshots`` (Algorithm 2).
+
+Probability band (Sec. 3.1: a Kraus operator set is only chosen if its joint
+probability lies in [p_min, p_max]): applied to the records a sampler returns,
+after the record-level criteria and before the allocation, which then runs
+over the kept records and their kept draws.
 """
 
 import itertools
@@ -254,6 +259,19 @@ def most_likely_bruteforce(site_probs, k_max, allow=None, **crit):
     return [r for r, _ in top], [sc for _, sc in top]
 
 
+def probability_band(records, counts, site_probs, p_min, p_max):
+    """Keep the records whose joint probability p_alpha lies in [p_min, p_max]
+    (both ends included), with their draw counts, in their order.  Returns
+    (records, counts, T) with T the number of kept draws."""
+    kept_r, kept_c = [], []
+    for rec, c in zip(records, counts):
+        pa = joint_prob(rec, site_probs)
+        if p_min <= pa <= p_max:
+            kept_r.append(rec)
+            kept_c.append(c)
+    return kept_r, kept_c, sum(kept_c)
+
+
 def allocate_multiplicity(counts, n_draws, total_shots):
     """m_alpha = floor(count_alpha * S / T) plus one for the largest remainders
     (ties to the lower alpha), so that sum m_alpha = S exactly."""
@@ -281,24 +299,43 @@ def allocate_reweight(probs, total_shots):
     return base
 
 
+def _alg2_counts(site_probs, seed, cfg, n_draws, records):
+    """How many of Algorithm 2's ``n_draws`` samples produced each unique record."""
+    index = {r: a for a, r in enumerate(records)}
+    counts = [0] * len(records)
+    for t in range(n_draws):
+        counts[index[alg2_draw(site_probs, seed, cfg, t)]] += 1
+    return counts
+
+
 def sample_kraus(circuit_probs, pts, seed, cfg):
     """Run the PTS step described by a workload's ``pts`` options.
 
+    ``pts["p_band"] = (p_min, p_max)`` keeps only the records in that band; the
+    allocation then runs over the kept records (multiplicity: over their draws).
     Returns dict(records, m, p, counts)."""
     mode = pts["mode"]
     if mode == "proportional":
         recs, counts = proportional(circuit_probs, seed, cfg, pts["n_draws"])
+        T = pts["n_draws"]
     elif mode == "alg2_literal":
-        recs, counts = alg2_literal(circuit_probs, seed, cfg, pts["n_draws"], pts.get("nshots", 1))
+        recs, _ = alg2_literal(circuit_probs, seed, cfg, pts["n_draws"], pts.get("nshots", 1))
+        counts = _alg2_counts(circuit_probs, seed, cfg, pts["n_draws"], recs)
+        T = pts["n_draws"]
     elif mode == "most_likely":
         recs, _ = most_likely(circuit_probs, pts["k_max"])
         counts = [1] * len(recs)
+        T = len(recs)
     else:
         raise ValueError(mode)
+    if pts.get("p_band") is not None:
+        recs, counts, T = probability_band(recs, counts, circuit_probs, *pts["p_band"])
+        if not recs:
+            raise ValueError("no record falls in the probability band")
     p = [joint_prob(r, circuit_probs) for r in recs]
     alloc = pts.get("alloc", "multiplicity")
     if alloc == "multiplicity":
-        m = allocate_multiplicity(counts, pts["n_draws"], pts["total_shots"])
+        m = allocate_multiplicity(counts, T, pts["total_shots"])
     elif alloc == "reweight":
         m = allocate_reweight(p, pts["total_shots"])
     elif alloc == "uniform":

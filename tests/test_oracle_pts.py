@@ -174,3 +174,78 @@ def test_selection_special_cases():
     kept, kc = select_records(base[0], base[1], parity="odd", max_errors=3)
     assert all(len(r) % 2 == 1 and len(r) <= 3 for r in kept)
     assert sum(kc) == sum(c for r, c in zip(*base) if len(r) % 2 == 1 and len(r) <= 3)
+
+
+# --- probability band (Sec. 3.1: a Kraus operator set is chosen only if p_alpha lies in [p_min, p_max])
+
+_BAND_SP = [[0.9, 0.1], [0.8, 0.15, 0.05]]
+# every record of _BAND_SP with its joint probability, worked out by hand
+_BAND_ALL = [((), 0.72), (((0, 1),), 0.08), (((1, 1),), 0.135), (((1, 2),), 0.045),
+             (((0, 1), (1, 1)), 0.015), (((0, 1), (1, 2)), 0.005)]
+
+
+def test_probability_band_by_hand():
+    from oracle.pts import probability_band
+    recs = [r for r, _ in _BAND_ALL]
+    counts = [50, 9, 13, 5, 2, 1]
+    kr, kc, T = probability_band(recs, counts, _BAND_SP, 0.01, 0.1)
+    assert kr == [((0, 1),), ((1, 2),), ((0, 1), (1, 1))]
+    assert kc == [9, 5, 2] and T == 16
+    # multiplicity over the kept draws: 900/16, 500/16, 200/16 = 56.25, 31.25, 12.5;
+    # the one shot left goes to the largest remainder (200 mod 16 = 8)
+    assert allocate_multiplicity(kc, T, 100) == [56, 31, 13]
+    # reweight over the kept set: p' = (0.08, 0.045, 0.015) / 0.14 of 1000 shots
+    # = 571.43, 321.43, 107.14 -> 571, 321, 107 and the last shot to the first (ties to lower alpha)
+    assert allocate_reweight([joint_prob(r, _BAND_SP) for r in kr], 1000) == [572, 321, 107]
+
+
+def test_probability_band_edges():
+    from oracle.pts import probability_band
+    recs = [r for r, _ in _BAND_ALL]
+    ps = [joint_prob(r, _BAND_SP) for r in recs]
+    counts = [1] * len(recs)
+    # both ends are included: a band of one value keeps exactly the records of that probability
+    for r, p in zip(recs, ps):
+        kr, _, _ = probability_band(recs, counts, _BAND_SP, p, p)
+        assert kr == [x for x, q in zip(recs, ps) if q == p] and r in kr
+    # [0, 1] keeps everything; a band between the probabilities keeps nothing
+    assert probability_band(recs, counts, _BAND_SP, 0.0, 1.0)[0] == recs
+    assert probability_band(recs, counts, _BAND_SP, 0.2, 0.7)[0] == []
+
+
+def test_probability_band_draws_follow_the_conditional_distribution():
+    """Proportional draws restricted to a band: the kept records appear with
+    p_alpha / P(band), the channel's distribution conditioned on the band."""
+    from oracle.pts import probability_band
+    T = 20000
+    recs, counts = proportional(_BAND_SP, 11, 1, T)
+    kr, kc, Tk = probability_band(recs, counts, _BAND_SP, 0.01, 0.2)
+    inband = [(r, p) for r, p in _BAND_ALL if 0.01 <= p <= 0.2]
+    pb = sum(p for _, p in inband)
+    got = dict(zip(kr, kc))
+    obs = [got.get(r, 0) for r, _ in inband]
+    assert sum(obs) == Tk
+    assert _chi2_ok(obs, [p / pb for _, p in inband], Tk)
+    # and the kept fraction of the draws is P(band) = 0.08 + 0.135 + 0.045 + 0.015
+    assert abs(Tk / T - pb) < 4 * math.sqrt(pb * (1 - pb) / T)
+
+
+def test_sample_kraus_band_composes_sampler_band_and_allocation():
+    from oracle.pts import probability_band, sample_kraus
+    sp = _small_probs(3, S=6)
+    for pts in ({"mode": "proportional", "n_draws": 300, "total_shots": 5000, "alloc": "multiplicity"},
+                {"mode": "most_likely", "k_max": 40, "total_shots": 5000, "alloc": "reweight"},
+                {"mode": "alg2_literal", "n_draws": 300, "nshots": 7, "alloc": "uniform"}):
+        full = sample_kraus(sp, pts, 5, 2)
+        ps = sorted(full["p"])
+        band = (ps[len(ps) // 4], ps[3 * len(ps) // 4])
+        got = sample_kraus(sp, dict(pts, p_band=band), 5, 2)
+        kr, kc, T = probability_band(full["records"], full["counts"], sp, *band)
+        assert got["records"] == kr and got["counts"] == kc
+        assert all(band[0] <= p <= band[1] for p in got["p"])
+        if pts["alloc"] == "multiplicity":
+            assert got["m"] == allocate_multiplicity(kc, T, 5000) and sum(got["m"]) == 5000
+        elif pts["alloc"] == "reweight":
+            assert got["m"] == allocate_reweight(got["p"], 5000)
+        else:
+            assert got["m"] == [7] * len(kr)

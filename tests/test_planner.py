@@ -85,20 +85,36 @@ def test_most_likely_surface_code_top_4096():
     assert int(g["m"].sum()) == 10**9
 
 
-def test_probability_band_and_slices():
+@pytest.mark.parametrize("mode", ["proportional", "most_likely", "alg2_literal"])
+def test_probability_band_matches_oracle(mode):
+    """Band PTS (Sec. 3.1): records, draw counts, m_alpha and p_alpha of the
+    library equal the oracle's sampler + band filter + allocation, bit for bit."""
+    circ = random_small_circuit(4, 30, np.random.default_rng(3), p1=0.1, p2=0.2)
+    plan = P.ptsbe_plan(circ)
+    sp = site_probs(circ)
+    pts = {"proportional": {"mode": "proportional", "n_draws": 400, "total_shots": 4000, "alloc": "multiplicity"},
+           "most_likely": {"mode": "most_likely", "k_max": 300, "total_shots": 4000, "alloc": "reweight"},
+           "alg2_literal": {"mode": "alg2_literal", "n_draws": 400, "nshots": 9, "alloc": "uniform"}}[mode]
+    full = sample_kraus(sp, pts, 1, 2)
+    lo, hi = np.quantile(full["p"], [0.25, 0.75])
+    ref = sample_kraus(sp, dict(pts, p_band=(lo, hi)), 1, 2)
+    tb = P.ptsbe_sample_kraus(plan, mode, n_draws=pts.get("n_draws", 0), k_max=pts.get("k_max", 0),
+                              total_shots=pts.get("total_shots", 0), nshots=pts.get("nshots", 0), seed=1, cfg=2,
+                              alloc=pts["alloc"], p_band=(lo, hi))
+    gb = tb.get()
+    assert gb["records"] == ref["records"]
+    assert list(gb["count"]) == list(ref["counts"])
+    assert list(gb["m"]) == list(ref["m"])
+    assert list(gb["p"]) == list(ref["p"])
+    assert all(lo <= p <= hi for p in gb["p"])
+
+
+def test_trajset_slices_and_caller_records():
     circ = random_small_circuit(4, 30, np.random.default_rng(3), p1=0.1, p2=0.2)
     plan = P.ptsbe_plan(circ)
     sp = site_probs(circ)
     ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=400, total_shots=4000, seed=1, cfg=2)
     g = ts.get()
-    lo, hi = np.quantile(g["p"], [0.25, 0.75])
-    tb = P.ptsbe_sample_kraus(plan, "proportional", n_draws=400, total_shots=4000, seed=1, cfg=2,
-                              p_band=(lo, hi))
-    gb = tb.get()
-    assert all(lo <= p <= hi for p in gb["p"])
-    keep = [(r, c) for r, c, p in zip(g["records"], g["count"], g["p"]) if lo <= p <= hi]
-    assert gb["records"] == [r for r, _ in keep]
-    assert int(gb["m"].sum()) == 4000
     s = ts.slice(5, 9).get()
     assert s["alpha0"] == 5 and s["records"] == g["records"][5:9]
     fr = P.ptsbe_trajset_from_records(plan, g["records"][:3], [7, 8, 9], alpha0=11).get()
