@@ -20,7 +20,8 @@
  *    immutable after creation, shareable across threads, freed by their
  *    destroy call.  A handle must outlive the stream work enqueued with it.
  *  - Every device buffer (workspace, outputs, uniforms) is owned by the
- *    caller.  The library never allocates device memory.
+ *    caller.  The library never allocates device memory (the one fixed device
+ *    array of ptsbe_run_batch_noalloc is part of its code object).
  *  - Device launches are asynchronous on the caller's hipStream_t (passed as
  *    void*; NULL is the null stream).  Device-side conditions (a
  *    non-deterministic measure-reset) are written to a status word in the
@@ -355,6 +356,30 @@ ptsbe_status ptsbe_workspace_size(ptsbe_plan_t plan, ptsbe_trajset_t ts, const p
 ptsbe_status ptsbe_run_batch(ptsbe_plan_t plan, ptsbe_trajset_t ts, const ptsbe_run_opts* opts,
                              void* d_ws, size_t ws_bytes, void* d_bits, uint32_t* d_traj,
                              uint64_t capacity, uint8_t* d_mr_bits, void* stream);
+
+/* ptsbe_run_batch without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same plan, trajectory set, options and outputs as
+ * ptsbe_run_batch, but no workspace argument: the workspace is a fixed device
+ * array of PTSBE_NOALLOC_SCRATCH_BYTES inside this library (one per device,
+ * held from the first call on that device until the process ends).  The batch
+ * is split into the largest groups of trajectories that fit it; a plan whose
+ * single trajectory does not fit (about 2^22 amplitudes or more in complex64)
+ * fails with PTSBE_E_OOM before anything is enqueued.  The call allocates
+ * nothing (no hipMalloc / hipFree, no module load): the plan's compiled pass
+ * kernels run only if an earlier ptsbe_run_batch call loaded them on this
+ * device, otherwise the generic tile kernels run the same tables (same results).
+ * opts->timing must be NULL.  d_status (optional, device, one uint32) receives
+ * the run's status word: bit 0 set = a measure-reset outcome was not
+ * deterministic (what ptsbe_run_status reports as PTSBE_E_NONDET_MEASURE).
+ * Every call on a device shares that device's array and leaves its contents
+ * behind: calls that overlap on one device (other streams, other threads)
+ * race and must be serialised by the caller.  The call only enqueues work on
+ * `stream`. */
+#define PTSBE_NOALLOC_SCRATCH_BYTES (64ull << 20)
+ptsbe_status ptsbe_run_batch_noalloc(ptsbe_plan_t plan, ptsbe_trajset_t ts, const ptsbe_run_opts* opts,
+                                     void* d_bits, uint32_t* d_traj, uint64_t capacity, uint8_t* d_mr_bits,
+                                     uint32_t* d_status, void* stream);
 
 /* Captured execution (HIP graph): the same arguments as ptsbe_run_batch.  The
  * tables are uploaded into the workspace now (the call waits for `stream`),

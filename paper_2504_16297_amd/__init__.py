@@ -378,9 +378,23 @@ def _stream(torch, stream):
     return C.c_void_p(s.cuda_stream)
 
 
+def _outputs(plan, ts, mode, res, dev, torch):
+    """Shot, tag and measure-reset record buffers of a run (the caller's, or new)."""
+    n = plan.info["n_qubits"]
+    if mode == "shots":
+        total = ts.get()["total_shots"]
+        if res.get("bits") is None:
+            res["bits"] = torch.empty(max(1, total), dtype=torch.int32 if n <= 32 else torch.int64, device=dev)
+        if res.get("traj") is None:
+            res["traj"] = torch.empty(max(1, total), dtype=torch.int32, device=dev)
+    if plan.info["n_measure"] and res.get("mr_bits") is None:
+        res["mr_bits"] = torch.empty((ts.n_traj, plan.info["n_measure"]), dtype=torch.uint8, device=dev)
+    return res
+
+
 def ptsbe_run_batch(plan, ts, mode="shots", seed=0, cfg=0, sort_chunk=0, max_batch=0, uniforms=None,
                     params=None, observable=None, workspace=None, out=None, stream=None, timing=None,
-                    prefix_sharing=True, capture=False):
+                    prefix_sharing=True, capture=False, noalloc=False, status=None):
     """Batched execution (Sec. 3).  Returns a dict of device tensors:
     shots: bits (int32 or int64 basis indices), traj (int32 trajectory ids), mr_bits;
     states: states (n_traj x 2^n complex); expectation: expval (n_traj float64).
@@ -388,7 +402,11 @@ def ptsbe_run_batch(plan, ts, mode="shots", seed=0, cfg=0, sort_chunk=0, max_bat
     HIP-event stage timer (the call then waits for the stream).
     ``prefix_sharing``: False runs every pass for every trajectory (same results).
     ``capture``: record the run as a HIP graph on ``stream`` (a created stream)
-    instead of running it; the result's "graph" replays it (``graph.launch()``)."""
+    instead of running it; the result's "graph" replays it (``graph.launch()``).
+    ``noalloc``: run through ptsbe_run_batch_noalloc (the library's fixed device
+    scratch instead of a workspace; ``workspace`` and ``timing`` must be None);
+    ``status`` (optional int32 device tensor of one entry) then receives the
+    run's status word."""
     import torch
     dev = torch.device("cuda")
     n = plan.info["n_qubits"]
@@ -409,28 +427,25 @@ def ptsbe_run_batch(plan, ts, mode="shots", seed=0, cfg=0, sort_chunk=0, max_bat
         res["expval"] = expval
     o, keep = _run_opts(mcode, seed, cfg, sort_chunk, max_batch, uniforms, params, state_out, expval,
                         observable, timing, prefix_sharing)
+    if noalloc:
+        if workspace is not None or capture:
+            raise ValueError("noalloc runs take no workspace and are not captured here")
+        res = _outputs(plan, ts, mode, res, dev, torch)
+        bits, traj, mr = res.get("bits"), res.get("traj"), res.get("mr_bits")
+        check(lib().ptsbe_run_batch_noalloc(
+            plan.handle, ts.handle, C.byref(o), C.c_void_p(bits.data_ptr()) if bits is not None else None,
+            C.c_void_p(traj.data_ptr()) if traj is not None else None, bits.numel() if bits is not None else 0,
+            C.c_void_p(mr.data_ptr()) if mr is not None else None,
+            C.c_void_p(status.data_ptr()) if status is not None else None, _stream(torch, stream)))
+        res["_keep"] = keep
+        return res
     need = C.c_size_t()
     check(lib().ptsbe_workspace_size(plan.handle, ts.handle, C.byref(o), C.byref(need)))
     ws = workspace
     if ws is None:
         ws = torch.empty(need.value, dtype=torch.uint8, device=dev)
-    total = ts.get()["total_shots"] if mode == "shots" else 0
-    bits = traj = None
-    if mode == "shots":
-        bits = res.get("bits")
-        if bits is None:
-            bits = torch.empty(max(1, total), dtype=torch.int32 if n <= 32 else torch.int64, device=dev)
-        traj = res.get("traj")
-        if traj is None:
-            traj = torch.empty(max(1, total), dtype=torch.int32, device=dev)
-        res["bits"], res["traj"] = bits, traj
-    nm = plan.info["n_measure"]
-    mr = None
-    if nm:
-        mr = res.get("mr_bits")
-        if mr is None:
-            mr = torch.empty((B, nm), dtype=torch.uint8, device=dev)
-        res["mr_bits"] = mr
+    res = _outputs(plan, ts, mode, res, dev, torch)
+    bits, traj, mr = res.get("bits"), res.get("traj"), res.get("mr_bits")
     cap = bits.numel() if bits is not None else 0
     args = (plan.handle, ts.handle, C.byref(o), C.c_void_p(ws.data_ptr()), ws.numel(),
             C.c_void_p(bits.data_ptr()) if bits is not None else None,

@@ -29,6 +29,7 @@ PLAN_NO_PHASE_FRAMES = 32
 PLAN_WAVES_SHIFT = 8
 PLAN_TWIRL = 64
 PLAN_NO_PAIR_FUSION = 128
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class Op(C.Structure):
@@ -114,6 +115,8 @@ _SIGS = {
                                   C.c_size_t, C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p,
                                   C.c_void_p]),
     "ptsbe_run_status": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ptsbe_run_batch_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(RunOpts), C.c_void_p,
+                                          C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p, C.c_void_p]),
     "ptsbe_pauli_twirl": (C.c_int, [C.c_uint32, C.c_void_p, C.c_uint32, C.c_void_p]),
     "ptsbe_plan_get_record_info": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "ptsbe_plan_get_site_ops": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),

@@ -21,7 +21,7 @@ LIB = os.path.join(HERE, "libptsbe.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 HOST_SRCS = ["plan.cpp", "pts.cpp", "run.cpp", "abi.cpp", "adjoint.cpp", "jit.cpp"]
-DEVICE_SRCS = ["kernels.hip", "unique.hip"]
+DEVICE_SRCS = ["kernels.hip", "unique.hip", "noalloc.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-I" + os.path.join(ROOT, "include")]
 HOST_FLAGS = ["-x", "c++", "-ffp-contract=off", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include"]

@@ -18,7 +18,8 @@ ptsbe_status trajset_slice(const TrajSet& ts, uint32_t b, uint32_t e, ptsbe_traj
 ptsbe_status workspace_size(const Plan& P, TrajSet& ts, const ptsbe_run_opts* o, size_t* bytes);
 ptsbe_status run_batch(const Plan& P, TrajSet& ts, const ptsbe_run_opts* o, void* d_ws, size_t ws_bytes,
                        void* d_bits, uint32_t* d_traj, uint64_t capacity, uint8_t* d_mr_bits, void* stream,
-                       hipGraphExec_t* graph_out = nullptr);
+                       hipGraphExec_t* graph_out = nullptr, bool no_alloc = false,
+                       uint32_t* d_status = nullptr);
 ptsbe_status run_status(const void* d_ws, void* stream);
 ptsbe_status adjoint_grad(const Plan& P, TrajSet& ts, const double* params, const double* coef,
                           const uint64_t* zmask, uint32_t n_terms, uint64_t seed, uint32_t cfg, void* d_ws,

@@ -971,6 +971,14 @@ hipError_t jit_load(const Plan& P) {
   return jit_functions(P, &fns);
 }
 
+bool jit_loaded(const Plan& P) {
+  if (!P.jit || !P.jit->built || P.jit->build_status != PTSBE_OK) return false;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  std::lock_guard<std::mutex> lk(P.jit->mu);
+  return P.jit->functions.count(dev) != 0;
+}
+
 template <typename V>
 hipError_t jit_launch(const Plan& P, uint32_t pass, const PassArgs<V>& a, uint32_t rows, hipStream_t s) {
   const std::vector<hipFunction_t>* fns = nullptr;

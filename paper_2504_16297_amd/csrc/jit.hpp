@@ -65,6 +65,10 @@ hipError_t jit_launch(const Plan& P, uint32_t pass, const PassArgs<V>& a, uint32
 // Load the compiled kernels on the current device now (before stream capture).
 hipError_t jit_load(const Plan& P);
 
+// True if the compiled kernels are built and already loaded on the current
+// device (no loading, so no device allocation).
+bool jit_loaded(const Plan& P);
+
 // True if pass `pass` runs through a compiled kernel.
 bool jit_has(const Plan& P, uint32_t pass);
 

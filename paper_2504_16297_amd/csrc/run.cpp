@@ -204,7 +204,8 @@ enum { PH_UPLOAD = 1, PH_LAUNCH = 2 };
 // enqueues the kernels (device work only, so it can be captured in a graph).
 template <typename V, typename BitT>
 ptsbe_status run_typed(const Plan& P, TrajSet& ts, const ptsbe_run_opts& o, uint8_t* ws, const WsLayout& L,
-                       void* d_bits, uint32_t* d_traj, uint8_t* d_mr_bits, hipStream_t s, int phase) {
+                       void* d_bits, uint32_t* d_traj, uint8_t* d_mr_bits, hipStream_t s, int phase,
+                       bool use_jit, uint32_t* d_status) {
   const uint32_t B = (uint32_t)ts.m.size();
   const uint64_t N = 1ull << P.n;
   const TableLayout& T = ts.layout;
@@ -292,7 +293,7 @@ ptsbe_status run_typed(const Plan& P, TrajSet& ts, const ptsbe_run_opts& o, uint
           rows = r1 - r0;
           pa.route = d_routes + r0;
         }
-        if (rows && jit_has(P, (uint32_t)ex.pass))
+        if (rows && use_jit && jit_has(P, (uint32_t)ex.pass))
           CK(jit_launch<V>(P, (uint32_t)ex.pass, pa, rows, s), "compiled tile pass");
         else if (rows)
           CK(launch_pass<V>(pa, (uint32_t)ps.k, (uint32_t)ps.slots.size(), (uint32_t)ps.ops.size(), rows, s),
@@ -396,6 +397,7 @@ ptsbe_status run_typed(const Plan& P, TrajSet& ts, const ptsbe_run_opts& o, uint
   }
   if (d_mr_bits && P.n_measure)
     CK(hipMemcpyAsync(d_mr_bits, mr_bits, (size_t)B * P.n_measure, hipMemcpyDeviceToDevice, s), "record copy");
+  if (d_status) CK(hipMemcpyAsync(d_status, status, 4, hipMemcpyDeviceToDevice, s), "status copy");
   CK(tm.mark(T_OTHER), "timer");
   if (timed) CK(tm.collect(o.timing), "timer");
   return PTSBE_OK;
@@ -439,9 +441,10 @@ ptsbe_status workspace_size(const Plan& P, TrajSet& ts, const ptsbe_run_opts* o,
 
 ptsbe_status run_batch(const Plan& P, TrajSet& ts, const ptsbe_run_opts* o, void* d_ws, size_t ws_bytes,
                        void* d_bits, uint32_t* d_traj, uint64_t capacity, uint8_t* d_mr_bits, void* stream,
-                       hipGraphExec_t* graph_out) {
+                       hipGraphExec_t* graph_out, bool no_alloc, uint32_t* d_status) {
   ptsbe_status st = check_opts(P, ts, o, true);
   if (st != PTSBE_OK) return st;
+  if (no_alloc && o->timing) return fail(PTSBE_E_ARG, "timing is not available without allocation (it creates events)");
   if (!d_ws) return fail(PTSBE_E_ARG, "null workspace");
   if (reinterpret_cast<uintptr_t>(d_ws) % 256) return fail(PTSBE_E_ARG, "workspace must be 256-byte aligned");
   if (o->mode == PTSBE_RUN_SHOTS) {
@@ -468,19 +471,28 @@ ptsbe_status run_batch(const Plan& P, TrajSet& ts, const ptsbe_run_opts* o, void
   if (L.end > ws_bytes)
     return fail(PTSBE_E_OOM, "workspace of " + std::to_string(ws_bytes) + " bytes is below the " +
                                  std::to_string(L.end) + " bytes needed for one trajectory");
-  if (P.use_jit) {
+  // Without allocation the compiled passes run only if their code objects are
+  // already loaded on this device (loading a module allocates device memory);
+  // otherwise the generic tile kernels run the same tables.
+  bool use_jit = P.use_jit;
+  if (use_jit && !no_alloc) {
     st = jit_build(P);
     if (st != PTSBE_OK) return st;
   }
+  if (use_jit && no_alloc) use_jit = jit_loaded(P);
   uint8_t* ws = static_cast<uint8_t*>(d_ws);
   hipStream_t s = static_cast<hipStream_t>(stream);
   auto dispatch = [&](int phase) -> ptsbe_status {
     if (P.precision == PTSBE_C64) {
-      if (P.n <= 32) return run_typed<float2, uint32_t>(P, ts, *o, ws, L, d_bits, d_traj, d_mr_bits, s, phase);
-      return run_typed<float2, uint64_t>(P, ts, *o, ws, L, d_bits, d_traj, d_mr_bits, s, phase);
+      if (P.n <= 32) return run_typed<float2, uint32_t>(P, ts, *o, ws, L, d_bits, d_traj, d_mr_bits, s, phase,
+                                                        use_jit, d_status);
+      return run_typed<float2, uint64_t>(P, ts, *o, ws, L, d_bits, d_traj, d_mr_bits, s, phase,
+                                                        use_jit, d_status);
     }
-    if (P.n <= 32) return run_typed<double2, uint32_t>(P, ts, *o, ws, L, d_bits, d_traj, d_mr_bits, s, phase);
-    return run_typed<double2, uint64_t>(P, ts, *o, ws, L, d_bits, d_traj, d_mr_bits, s, phase);
+    if (P.n <= 32) return run_typed<double2, uint32_t>(P, ts, *o, ws, L, d_bits, d_traj, d_mr_bits, s, phase,
+                                                        use_jit, d_status);
+    return run_typed<double2, uint64_t>(P, ts, *o, ws, L, d_bits, d_traj, d_mr_bits, s, phase,
+                                                        use_jit, d_status);
   };
   if (!graph_out) return dispatch(PH_UPLOAD | PH_LAUNCH);
   // graph: upload now, load the compiled kernels, then capture the device work
