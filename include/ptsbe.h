@@ -41,7 +41,8 @@ typedef enum {
     PTSBE_OK = 0,
     PTSBE_E_ARG = 1,            /* invalid argument: null pointer, bad qubit, size mismatch */
     PTSBE_E_NOT_CPTP = 2,       /* a channel violates sum_k K_k^dagger K_k = I (Sec. 2.2) beyond 1e-12 */
-    PTSBE_E_UNSUPPORTED = 3,    /* valid but not implemented (a non-unitary-mixture noise channel, n > 35) */
+    PTSBE_E_UNSUPPORTED = 3,    /* valid but not implemented (a channel neither a unitary mixture nor
+                                   resolvable from one qubit's populations, n > 35) */
     PTSBE_E_CAPACITY = 4,       /* output capacity below the total shot count */
     PTSBE_E_OOM = 5,            /* workspace smaller than ptsbe_workspace_size() */
     PTSBE_E_DEVICE = 6,         /* a HIP call failed */
@@ -84,10 +85,14 @@ typedef struct {
 /* ------------------------------------------------------------- noise model */
 
 /* A channel {K_0 .. K_{n_kraus-1}} on nq (1 or 2) qubits: n_kraus consecutive
- * 2^nq x 2^nq complex128 matrices.  It must be CPTP (Sec. 2.2) and a unitary
+ * 2^nq x 2^nq complex128 matrices.  It must be CPTP (Sec. 2.2).  A unitary
  * mixture, K_k^dagger K_k = p_k I (Sec. 2.2 feature 2, read as
- * K_k = sqrt(p_k) U_k); then p_k is state independent and the site can be
- * pre-sampled.  K_0 is taken as the "no error" operator of the record.
+ * K_k = sqrt(p_k) U_k), has state-independent p_k: its sites are pre-sampled
+ * by PTS, and K_0 is taken as the "no error" operator of the record.  A
+ * 1-qubit channel whose K_k^dagger K_k are all diagonal (amplitude damping) is
+ * resolved from the state when a trajectory reaches it (Algorithm 1's
+ * state-dependent branch; see ptsbe_plan_get_record_info), or replaced by its
+ * Pauli twirl with PTSBE_PLAN_TWIRL.  Other channels: PTSBE_E_UNSUPPORTED.
  * At most 16 operators per channel. */
 typedef struct {
     uint32_t nq;
@@ -272,6 +277,23 @@ typedef struct {
 
 enum { PTSBE_PARITY_ANY = 0, PTSBE_PARITY_EVEN = 1, PTSBE_PARITY_ODD = 2 };
 
+/* Selection flags for ptsbe_pts_opts.kraus_allow from site properties (Sec. 3.1:
+ * criteria on gate type, location and error type added to the choice of each
+ * operator).  Operator k >= 1 of site s is allowed when the tag of the op the
+ * site belongs to is in tags (gate type), every qubit of the site is in qubits
+ * and its op index in ops (location), its origin (PTSBE_SITE_*) in origins, and
+ * k in kraus (error type); a NULL list accepts anything.  Operators k = 0 are
+ * always flagged 1.  flags: caller-owned host array of total_kraus bytes
+ * (ptsbe_plan_info), in the order of ptsbe_plan_get_sites. */
+typedef struct {
+    const uint32_t* tags;    uint32_t n_tags;
+    const uint32_t* qubits;  uint32_t n_qubits;
+    const uint32_t* ops;     uint32_t n_ops;
+    const uint32_t* origins; uint32_t n_origins;
+    const uint32_t* kraus;   uint32_t n_kraus;
+} ptsbe_site_filter;
+ptsbe_status ptsbe_site_selection(ptsbe_plan_t plan, const ptsbe_site_filter* filter, uint8_t* flags);
+
 /* Run a PTS algorithm (Sec. 3.1).  Draw t of PROPORTIONAL uses the Philox4x64-10
  * stream keyed [seed, stream<<56 | cfg<<48 | t]; its word s (NumPy's raw order:
  * counter block s/4 + 1, word s%4) gives site s the uniform (word >> 11) 2^-53
@@ -296,6 +318,15 @@ ptsbe_status ptsbe_trajset_get(ptsbe_trajset_t ts, uint32_t* n_traj, uint64_t* t
                                uint32_t* n_entries, uint64_t* alpha0, uint64_t* m, double* p,
                                uint64_t* count, uint32_t* rec_off, uint32_t* rec_site,
                                uint8_t* rec_kraus);
+/* Ensemble weights of a trajectory set: w[alpha] = b_alpha / sum_beta b_beta
+ * (n_traj FP64 values, caller-owned host array), with b_alpha the proportion its
+ * shots are allocated by -- the draw count for MULTIPLICITY (so E estimates
+ * the channel's expectation without bias), p_alpha for REWEIGHT (the
+ * probability-weighted expectation over the selected records, Sec. 3.1), 1 for
+ * UNIFORM and PER_SHOT, m_alpha for ptsbe_trajset_from_records; a slice keeps
+ * its trajectories' b.  The expectation mode's ensemble value and
+ * ptsbe_adjoint_grad use these weights. */
+ptsbe_status ptsbe_trajset_weights(ptsbe_trajset_t ts, double* w);
 void ptsbe_trajset_destroy(ptsbe_trajset_t ts);
 
 /* ------------------------------------------------------- batched execution */
@@ -329,6 +360,9 @@ typedef struct {
                                    state-pass, 1 x for the initialising pass), [7] sampler
                                    launches, [8] useful FLOPs of the passes (per amplitude: 14 per
                                    2x2 matrix, 30 per 4x4, 6 per diagonal), [9] state-passes run */
+    double* d_ensemble;         /* EXPECTATION: optional device FP64 scalar, receives the ensemble
+                                   value E = sum_alpha w_alpha <O>_alpha (w from ptsbe_trajset_weights),
+                                   summed on the device in trajectory order */
 } ptsbe_run_opts;
 
 /* Prefix sharing (default for plans without measure-resets): a trajectory's
@@ -337,6 +371,14 @@ typedef struct {
  * carried through those passes and each trajectory's first own pass reads it.
  * Results are bit-identical to running every pass for every trajectory. */
 #define PTSBE_RUN_NO_PREFIX_SHARING 1u
+/* Sampler support lists (default for states of at most 2^21 amplitudes): the
+ * CDF scan also lists, per state, the elements an upper-bound search can return
+ * (at most 1024 of them, else the list is not used); a chunk of such a
+ * trajectory's shots is then drawn by searching each uniform in that list and
+ * writing the per-element counts as ascending runs, which is the sorted
+ * chunk's result without the sort.  Shots are bit-identical either way; this
+ * flag turns the lists off. */
+#define PTSBE_RUN_NO_SUPPORT_LISTS 2u
 
 /* Device workspace in bytes needed by ptsbe_run_batch, or with
  * opts->mode == PTSBE_RUN_ADJOINT by ptsbe_adjoint_grad (max_batch bounds the
@@ -444,8 +486,8 @@ ptsbe_status ptsbe_unique_shots(ptsbe_trajset_t ts, const void* d_bits, void* d_
                                 uint64_t* d_unique, void* d_pair_index, uint32_t* d_pair_count, void* stream);
 
 /* Adjoint gradient of E(theta) = sum_alpha w_alpha <psi_alpha|O|psi_alpha>,
- * w_alpha = count_alpha / sum count (for unitary-mixture noise w does not depend
- * on theta): forward preparation, lambda = O psi, then a reverse sweep that
+ * w_alpha from ptsbe_trajset_weights (for unitary-mixture noise w does not
+ * depend on theta): forward preparation, lambda = O psi, then a reverse sweep that
  * un-applies each operation on psi and lambda and accumulates
  * 2 Re <lambda| dG/dtheta |psi> in FP64 per (trajectory, tile), reduced in a
  * fixed order (deterministic).  O = sum_t coef_t Z-string(zmask_t), 1..64 terms.

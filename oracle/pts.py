@@ -28,6 +28,13 @@ Allocations:
   selected set of p_beta (Sec. 3.1), largest remainder.
 * ``uniform``        -- every kept record gets ``nshots`` (Algorithm 2).
 
+Ensemble weights: the trajectories stand for the noisy channel in the
+proportions their shots are allocated by, so an expectation over the set is
+E = sum_alpha w_alpha <O>_alpha with w_alpha proportional to count_alpha
+(multiplicity: the draw frequencies, an unbiased estimate of the channel),
+p_alpha (reweight: the probability-weighted expectation over the selected
+records, Sec. 3.1) or 1 (uniform), normalised over the set.
+
 Probability band (Sec. 3.1: a Kraus operator set is only chosen if its joint
 probability lies in [p_min, p_max]): applied to the records a sampler returns,
 after the record-level criteria and before the allocation, which then runs
@@ -308,12 +315,29 @@ def _alg2_counts(site_probs, seed, cfg, n_draws, records):
     return counts
 
 
+def ensemble_weights(counts, probs, alloc):
+    """w_alpha = b_alpha / sum_beta b_beta with b = counts (multiplicity),
+    probs (reweight) or 1 (uniform), summed in trajectory order."""
+    if alloc == "multiplicity":
+        b = [float(c) for c in counts]
+    elif alloc == "reweight":
+        b = [float(p) for p in probs]
+    elif alloc == "uniform":
+        b = [1.0] * len(counts)
+    else:
+        raise ValueError(alloc)
+    tot = 0.0
+    for v in b:
+        tot += v
+    return [v / tot for v in b]
+
+
 def sample_kraus(circuit_probs, pts, seed, cfg):
     """Run the PTS step described by a workload's ``pts`` options.
 
     ``pts["p_band"] = (p_min, p_max)`` keeps only the records in that band; the
     allocation then runs over the kept records (multiplicity: over their draws).
-    Returns dict(records, m, p, counts)."""
+    Returns dict(records, m, p, counts, weights)."""
     mode = pts["mode"]
     if mode == "proportional":
         recs, counts = proportional(circuit_probs, seed, cfg, pts["n_draws"])
@@ -342,4 +366,5 @@ def sample_kraus(circuit_probs, pts, seed, cfg):
         m = [int(pts.get("nshots", 1))] * len(recs)
     else:
         raise ValueError(alloc)
-    return {"records": recs, "m": m, "p": p, "counts": counts}
+    return {"records": recs, "m": m, "p": p, "counts": counts,
+            "weights": ensemble_weights(counts, p, alloc)}

@@ -234,6 +234,13 @@ class TrajSet:
                                       None, None))
         return n.value
 
+    def weights(self):
+        """Ensemble weights w_alpha (ptsbe_trajset_weights), float64 [n_traj]."""
+        B = self.n_traj
+        w = np.zeros(max(1, B), dtype=np.float64)
+        check(lib().ptsbe_trajset_weights(self.handle, w.ctypes.data))
+        return w[:B]
+
     def slice(self, begin, end):
         h = C.c_void_p()
         check(lib().ptsbe_trajset_slice(self.handle, begin, end, C.byref(h)))
@@ -285,32 +292,33 @@ def pauli_twirl(channel):
 
 
 def site_selection(plan, tags=None, qubits=None, ops=None, origins=None, kraus=None):
-    """Flags for ptsbe_sample_kraus(kraus_allow=...): operator k >= 1 of site s is
-    allowed when the site's op tag is in ``tags`` (gate type), every qubit of
-    the site is in ``qubits`` and its op index in ``ops`` (location), its origin
-    in ``origins`` ("noise_op", "after_tag", "before_measure",
-    "before_readout") and k in ``kraus`` (error type); None accepts anything."""
-    n = plan.info["n_sites"]
-    probs, site_q = plan.site_probs()
-    off = np.concatenate([[0], np.cumsum([len(p) for p in probs])]).astype(np.int64)
-    op = np.zeros(max(1, n), dtype=np.uint32)
-    tg = np.zeros(max(1, n), dtype=np.uint32)
-    org = np.zeros(max(1, n), dtype=np.uint32)
-    check(lib().ptsbe_plan_get_site_ops(plan.handle, C.c_void_p(op.ctypes.data), C.c_void_p(tg.ctypes.data),
-                                        C.c_void_p(org.ctypes.data)))
-    tagset = None if tags is None else {tag_id(t) for t in tags}
-    qset = None if qubits is None else set(int(q) for q in qubits)
-    oset = None if ops is None else set(int(i) for i in ops)
-    orset = None if origins is None else {L.SITE_ORIGINS.index(x) for x in origins}
-    kset = None if kraus is None else set(int(k) for k in kraus)
-    flags = np.ones(plan.info["total_kraus"], dtype=np.uint8)
-    for s in range(n):
-        q = [int(x) for x in site_q[s] if x != 0xFFFFFFFF]
-        ok = ((tagset is None or int(tg[s]) in tagset) and (qset is None or all(x in qset for x in q)) and
-              (oset is None or int(op[s]) in oset) and (orset is None or int(org[s]) in orset))
-        for k in range(1, int(off[s + 1] - off[s])):
-            flags[off[s] + k] = 1 if ok and (kset is None or k in kset) else 0
-    return flags
+    """Flags for ptsbe_sample_kraus(kraus_allow=...) from ptsbe_site_selection:
+    operator k >= 1 of site s is allowed when the site's op tag is in ``tags``
+    (gate type), every qubit of the site is in ``qubits`` and its op index in
+    ``ops`` (location), its origin in ``origins`` ("noise_op", "after_tag",
+    "before_measure", "before_readout") and k in ``kraus`` (error type); None
+    accepts anything."""
+    keep = []
+
+    def arr(v):
+        if v is None:
+            return None, 0
+        a = np.ascontiguousarray(list(v), dtype=np.uint32)
+        n = a.size
+        if n == 0:                       # an empty list accepts nothing: non-null pointer, no entries
+            a = np.zeros(1, dtype=np.uint32)
+        keep.append(a)
+        return C.c_void_p(a.ctypes.data), n
+
+    f = L.SiteFilter()
+    f.tags, f.n_tags = arr(None if tags is None else [tag_id(t) for t in tags])
+    f.qubits, f.n_qubits = arr(qubits)
+    f.ops, f.n_ops = arr(ops)
+    f.origins, f.n_origins = arr(None if origins is None else [L.SITE_ORIGINS.index(x) for x in origins])
+    f.kraus, f.n_kraus = arr(kraus)
+    flags = np.ones(max(1, plan.info["total_kraus"]), dtype=np.uint8)
+    check(lib().ptsbe_site_selection(plan.handle, C.byref(f), C.c_void_p(flags.ctypes.data)))
+    return flags[:plan.info["total_kraus"]]
 
 
 def ptsbe_trajset_from_records(plan, records, m, alpha0=0):
@@ -332,14 +340,14 @@ def ptsbe_trajset_from_records(plan, records, m, alpha0=0):
 
 
 def _run_opts(mode, seed, cfg, sort_chunk, max_batch, uniforms, params, state_out, expval, observable,
-              timing=None, prefix_sharing=True):
+              timing=None, prefix_sharing=True, support_lists=True):
     o = L.RunOpts()
     if timing is not None:
         if timing.dtype != np.float64 or timing.size < 10:
             raise ValueError("timing must be a float64 array of at least 10 entries")
         o.timing = _dptr(timing)
     o.mode = mode
-    o.flags = 0 if prefix_sharing else L.RUN_NO_PREFIX_SHARING
+    o.flags = (0 if prefix_sharing else L.RUN_NO_PREFIX_SHARING) | (0 if support_lists else L.RUN_NO_SUPPORT_LISTS)
     o.seed = int(seed)
     o.cfg = int(cfg)
     o.sort_chunk = int(sort_chunk)
@@ -362,12 +370,13 @@ def _run_opts(mode, seed, cfg, sort_chunk, max_batch, uniforms, params, state_ou
     return o, keep
 
 
-def ptsbe_workspace_size(plan, ts, mode="shots", sort_chunk=0, max_batch=0, params=None, prefix_sharing=True):
+def ptsbe_workspace_size(plan, ts, mode="shots", sort_chunk=0, max_batch=0, params=None, prefix_sharing=True,
+                         support_lists=True):
     m = {"shots": L.RUN_SHOTS, "states": L.RUN_STATES, "expectation": L.RUN_EXPECTATION,
          "adjoint": L.RUN_ADJOINT}[mode]
     pa = None if params is None else np.ascontiguousarray(params, dtype=np.float64)
     o, keep = _run_opts(m, 0, 0, sort_chunk, max_batch, None, pa, None, None, None,
-                        prefix_sharing=prefix_sharing)
+                        prefix_sharing=prefix_sharing, support_lists=support_lists)
     n = C.c_size_t()
     check(lib().ptsbe_workspace_size(plan.handle, ts.handle, C.byref(o), C.byref(n)))
     return n.value
@@ -394,13 +403,16 @@ def _outputs(plan, ts, mode, res, dev, torch):
 
 def ptsbe_run_batch(plan, ts, mode="shots", seed=0, cfg=0, sort_chunk=0, max_batch=0, uniforms=None,
                     params=None, observable=None, workspace=None, out=None, stream=None, timing=None,
-                    prefix_sharing=True, capture=False, noalloc=False, status=None):
+                    prefix_sharing=True, capture=False, noalloc=False, status=None, support_lists=True):
     """Batched execution (Sec. 3).  Returns a dict of device tensors:
     shots: bits (int32 or int64 basis indices), traj (int32 trajectory ids), mr_bits;
-    states: states (n_traj x 2^n complex); expectation: expval (n_traj float64).
+    states: states (n_traj x 2^n complex); expectation: expval (n_traj float64) and
+    E (1 float64: the ensemble value sum_a w_a expval_a, w = ts.weights()).
     ``timing``: optional float64 numpy array of 10 entries filled by the library's
     HIP-event stage timer (the call then waits for the stream).
     ``prefix_sharing``: False runs every pass for every trajectory (same results).
+    ``support_lists``: False draws every chunk through the sort and the full-CDF
+    search (same shots).
     ``capture``: record the run as a HIP graph on ``stream`` (a created stream)
     instead of running it; the result's "graph" replays it (``graph.launch()``).
     ``noalloc``: run through ptsbe_run_batch_noalloc (the library's fixed device
@@ -420,13 +432,19 @@ def ptsbe_run_batch(plan, ts, mode="shots", seed=0, cfg=0, sort_chunk=0, max_bat
         if state_out is None:
             state_out = torch.empty((B, 1 << n), dtype=dt, device=dev)
         res["states"] = state_out
+    ensemble = None
     if mode == "expectation":
         expval = res.get("expval")
         if expval is None:
-            expval = torch.empty(B, dtype=torch.float64, device=dev)
-        res["expval"] = expval
+            expval = torch.empty(max(1, B), dtype=torch.float64, device=dev)
+        ensemble = res.get("E")
+        if ensemble is None:
+            ensemble = torch.empty(1, dtype=torch.float64, device=dev)
+        res["expval"], res["E"] = expval, ensemble
     o, keep = _run_opts(mcode, seed, cfg, sort_chunk, max_batch, uniforms, params, state_out, expval,
-                        observable, timing, prefix_sharing)
+                        observable, timing, prefix_sharing, support_lists)
+    if ensemble is not None:
+        o.d_ensemble = ensemble.data_ptr()
     if noalloc:
         if workspace is not None or capture:
             raise ValueError("noalloc runs take no workspace and are not captured here")
@@ -522,7 +540,7 @@ def ptsbe_unique_shots(ts, bits, workspace=None, max_batch=0, pairs=False, strea
 
 def ptsbe_adjoint_grad(plan, ts, params, observable, workspace=None, max_batch=0, stream=None, seed=0, cfg=0):
     """Adjoint gradient of E(theta) = sum_a w_a <psi_a|O|psi_a> over the trajectory
-    set (w_a = count_a / sum count).  ``observable``: list of (coef, qubits) Z-strings.
+    set (w = ts.weights()).  ``observable``: list of (coef, qubits) Z-strings.
     State-dependent channels are decided as ptsbe_run_batch decides them with the
     same ``seed`` and ``cfg``.  Returns (E, grad) as FP64 device tensors of shapes
     (1,) and (n_params,)."""

@@ -9,7 +9,9 @@ import ctypes as C
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libptsbe.so")
+# PTSBE_LIB selects another build of the same library (the host-sanitized one of
+# `python -m paper_2504_16297_amd.build --sanitize`, for CPU test runs)
+LIB_PATH = os.environ.get("PTSBE_LIB") or os.path.join(_HERE, "libptsbe.so")
 
 PTSBE_OK = 0
 STATUS_NAMES = {0: "PTSBE_OK", 1: "PTSBE_E_ARG", 2: "PTSBE_E_NOT_CPTP", 3: "PTSBE_E_UNSUPPORTED",
@@ -23,6 +25,7 @@ PTS_MODES = {"proportional": 0, "alg2_literal": 1, "most_likely": 2, "per_shot":
 ALLOCS = {"multiplicity": 0, "reweight": 1, "uniform": 2}
 RUN_SHOTS, RUN_STATES, RUN_EXPECTATION, RUN_ADJOINT = range(4)
 RUN_NO_PREFIX_SHARING = 1
+RUN_NO_SUPPORT_LISTS = 2
 PLAN_NO_COMPILE = 8
 PLAN_HALF_TILE_LDS = 16
 PLAN_NO_PHASE_FRAMES = 32
@@ -80,6 +83,12 @@ PARITY = {None: 0, "any": 0, "even": 1, "odd": 2}
 SITE_ORIGINS = ("noise_op", "after_tag", "before_measure", "before_readout")
 
 
+class SiteFilter(C.Structure):
+    _fields_ = [("tags", C.c_void_p), ("n_tags", C.c_uint32), ("qubits", C.c_void_p), ("n_qubits", C.c_uint32),
+                ("ops", C.c_void_p), ("n_ops", C.c_uint32), ("origins", C.c_void_p), ("n_origins", C.c_uint32),
+                ("kraus", C.c_void_p), ("n_kraus", C.c_uint32)]
+
+
 class RunOpts(C.Structure):
     _fields_ = [("mode", C.c_uint32), ("cfg", C.c_uint32), ("seed", C.c_uint64),
                 ("sort_chunk", C.c_uint32), ("max_batch", C.c_uint32),
@@ -87,7 +96,7 @@ class RunOpts(C.Structure):
                 ("d_state_out", C.c_void_p), ("d_expval", C.c_void_p),
                 ("obs_coef", C.POINTER(C.c_double)), ("obs_zmask", C.POINTER(C.c_uint64)),
                 ("n_terms", C.c_uint32), ("flags", C.c_uint32),
-                ("timing", C.POINTER(C.c_double))]
+                ("timing", C.POINTER(C.c_double)), ("d_ensemble", C.c_void_p)]
 
 
 _lib = None
@@ -109,6 +118,8 @@ _SIGS = {
                                     C.POINTER(C.c_uint32), C.POINTER(C.c_uint64), C.c_void_p,
                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "ptsbe_trajset_destroy": (None, [C.c_void_p]),
+    "ptsbe_trajset_weights": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "ptsbe_site_selection": (C.c_int, [C.c_void_p, C.POINTER(SiteFilter), C.c_void_p]),
     "ptsbe_workspace_size": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(RunOpts),
                                        C.POINTER(C.c_size_t)]),
     "ptsbe_run_batch": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(RunOpts), C.c_void_p,
@@ -151,6 +162,10 @@ EXPORTED = tuple(_SIGS)
 def lib():
     global _lib
     if _lib is None:
+        # torch first: its HIP runtime (SONAME libamdhip64.so.7) is then the one the
+        # library binds to, so streams and device pointers from torch are valid in
+        # it; loaded the other way round the process would hold two HIP runtimes
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "`python -m paper_2504_16297_amd.build` (hipcc, gfx950)")

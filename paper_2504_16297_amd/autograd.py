@@ -1,14 +1,14 @@
 """torch.autograd binding of the ensemble expectation and its adjoint gradient.
 
 Pre-trajectory sampling fixes each trajectory's Kraus operators before
-execution (Sec. 3), so E(theta) = sum_a w_a <psi_a(theta)|O|psi_a(theta)> with
-w_a = count_a / sum count is a smooth function of the circuit parameters.
-Forward runs the library's adjoint gradient call (one forward preparation and
-one reverse sweep of every trajectory) when the parameters require a gradient,
-else its expectation mode; backward scales the stored gradient.
+execution (Sec. 3), so E(theta) = sum_a w_a <psi_a(theta)|O|psi_a(theta)>, with
+the trajectory set's ensemble weights w_a, is a smooth function of the circuit
+parameters.  Forward runs the library's adjoint gradient call (one forward
+preparation and one reverse sweep of every trajectory) when the parameters
+require a gradient, else its expectation mode, which sums the weighted value on
+the device; backward scales the stored gradient.
 """
 
-import numpy as np
 import torch
 
 from . import ptsbe_adjoint_grad, ptsbe_run_batch
@@ -23,9 +23,7 @@ class PTSBEExpectation(torch.autograd.Function):
             ctx.save_for_backward(G.to(params.device, params.dtype))
             return E[0].to(params.device, params.dtype)
         r = ptsbe_run_batch(plan, ts, mode="expectation", params=pv, observable=observable)
-        g = ts.get()
-        w = torch.as_tensor(g["count"].astype(np.float64) / float(g["count"].sum()), device=r["expval"].device)
-        return torch.dot(w, r["expval"]).to(params.device, params.dtype)
+        return r["E"][0].to(params.device, params.dtype)
 
     @staticmethod
     def backward(ctx, grad_out):

@@ -62,9 +62,45 @@ def build(jobs=8, verbose=False):
     return LIB
 
 
+SAN_DIR = os.path.join(BUILD, "sanitize")
+SAN_FLAGS = ["-fsanitize=address,undefined", "-fno-omit-frame-pointer", "-fno-sanitize-recover=undefined"]
+
+
+def build_sanitized(jobs=8):
+    """A host-sanitized copy of the library for CPU test runs: the host sources
+    (planner, PTS, executor, ABI, pass compiler) built with g++ under
+    AddressSanitizer and UndefinedBehaviorSanitizer, the device sources built as
+    usual (no GPU sanitizer), into _build/sanitize/libptsbe.so.  Run the CPU
+    suite on it with
+
+        LD_PRELOAD="$(g++ -print-file-name=libasan.so) $(g++ -print-file-name=libubsan.so)" \
+        ASAN_OPTIONS=detect_leaks=0 PTSBE_LIB=_build/sanitize/libptsbe.so \
+        python -m pytest tests -m "not gpu"
+    """
+    os.makedirs(SAN_DIR, exist_ok=True)
+    cmds, objs = [], []
+    for s in HOST_SRCS:
+        o = os.path.join(SAN_DIR, s + ".o")
+        cmds.append(["g++", "-O1", "-g", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-ffp-contract=off",
+                     "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-I" + os.path.join(ROOT, "include")] +
+                    SAN_FLAGS + ["-c", os.path.join(CSRC, s), "-o", o])
+        objs.append(o)
+    for s in DEVICE_SRCS:
+        o = os.path.join(SAN_DIR, s + ".o")
+        cmds.append([HIPCC] + COMMON + DEVICE_FLAGS + ["-c", os.path.join(CSRC, s), "-o", o])
+        objs.append(o)
+    with ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
+        list(ex.map(_run, cmds))
+    lib = os.path.join(SAN_DIR, "libptsbe.so")
+    _run(["g++", "-shared", "-o", lib] + objs + SAN_FLAGS[:1] +
+         ["-L/opt/rocm/lib", "-lamdhip64", "-lhiprtc", "-Wl,-rpath,/opt/rocm/lib"])
+    return lib
+
+
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=8)
     ap.add_argument("-v", action="store_true")
+    ap.add_argument("--sanitize", action="store_true", help="build the host-sanitized copy for CPU test runs")
     a = ap.parse_args()
-    print(build(a.jobs, a.v))
+    print(build_sanitized(a.jobs) if a.sanitize else build(a.jobs, a.v))

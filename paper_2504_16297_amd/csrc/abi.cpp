@@ -1,5 +1,6 @@
 // extern "C" entry points of libptsbe: argument checks and exception fences
 // around the planner, the PTS samplers and the batched executor.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -114,7 +115,7 @@ ptsbe_status ptsbe_plan_get_sites(ptsbe_plan_t plan, uint32_t* offsets, double* 
   if (!plan) return fail(PTSBE_E_ARG, "null plan");
   const Plan& P = *plan->plan;
   if (offsets) std::memcpy(offsets, P.site_off.data(), P.site_off.size() * 4);
-  if (probs) std::memcpy(probs, P.site_p.data(), P.site_p.size() * 8);
+  if (probs && !P.site_p.empty()) std::memcpy(probs, P.site_p.data(), P.site_p.size() * 8);
   if (qubits)
     for (size_t s = 0; s < P.sites.size(); ++s) {
       qubits[2 * s] = (uint32_t)P.sites[s].q[0];
@@ -186,13 +187,49 @@ ptsbe_status ptsbe_trajset_get(ptsbe_trajset_t h, uint32_t* n_traj, uint64_t* to
   if (total_shots) *total_shots = ts.total_shots;
   if (n_entries) *n_entries = (uint32_t)ts.rec_site.size();
   if (alpha0) *alpha0 = ts.alpha0;
-  if (m) std::memcpy(m, ts.m.data(), B * 8);
-  if (p) std::memcpy(p, ts.p.data(), B * 8);
-  if (count) std::memcpy(count, ts.count.data(), B * 8);
-  if (rec_off) std::memcpy(rec_off, ts.rec_off.data(), (B + 1) * 4);
-  if (rec_site) std::memcpy(rec_site, ts.rec_site.data(), ts.rec_site.size() * 4);
-  if (rec_kraus) std::memcpy(rec_kraus, ts.rec_kraus.data(), ts.rec_kraus.size());
+  // copies skip empty arrays (an empty vector's data() may be null)
+  auto out = [](void* dst, const void* src, size_t bytes) {
+    if (dst && bytes) std::memcpy(dst, src, bytes);
+  };
+  out(m, ts.m.data(), B * 8);
+  out(p, ts.p.data(), B * 8);
+  out(count, ts.count.data(), B * 8);
+  out(rec_off, ts.rec_off.data(), (B + 1) * 4);
+  out(rec_site, ts.rec_site.data(), ts.rec_site.size() * 4);
+  out(rec_kraus, ts.rec_kraus.data(), ts.rec_kraus.size());
   return PTSBE_OK;
+}
+
+ptsbe_status ptsbe_site_selection(ptsbe_plan_t plan, const ptsbe_site_filter* f, uint8_t* flags) {
+  FENCE({
+    if (!plan || !f || !flags) return fail(PTSBE_E_ARG, "null argument");
+    const Plan& P = *plan->plan;
+    auto in = [](const uint32_t* v, uint32_t n, uint32_t x) {
+      if (!v) return true;
+      for (uint32_t i = 0; i < n; ++i)
+        if (v[i] == x) return true;
+      return false;
+    };
+    for (size_t s = 0; s < P.sites.size(); ++s) {
+      const Site& st = P.sites[s];
+      bool ok = in(f->tags, f->n_tags, st.tag) && in(f->ops, f->n_ops, st.op) &&
+                in(f->origins, f->n_origins, st.origin);
+      for (int j = 0; j < st.nq && ok; ++j) ok = in(f->qubits, f->n_qubits, (uint32_t)st.q[j]);
+      const uint32_t b = P.site_off[s], e = P.site_off[s + 1];
+      flags[b] = 1;
+      for (uint32_t k = 1; k < e - b; ++k) flags[b + k] = (ok && in(f->kraus, f->n_kraus, k)) ? 1 : 0;
+    }
+    return PTSBE_OK;
+  })
+}
+
+ptsbe_status ptsbe_trajset_weights(ptsbe_trajset_t h, double* w) {
+  FENCE({
+    if (!h || !w) return fail(PTSBE_E_ARG, "null argument");
+    const std::vector<double> v = ensemble_weights(*h->ts);
+    std::copy(v.begin(), v.end(), w);
+    return PTSBE_OK;
+  })
 }
 
 void ptsbe_trajset_destroy(ptsbe_trajset_t ts) { delete ts; }

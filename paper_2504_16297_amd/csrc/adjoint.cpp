@@ -121,12 +121,8 @@ ptsbe_status adjoint_typed(const Plan& P, TrajSet& ts, const double* coef, const
   // weights and the dot -> parameter map live with the plan's host data for the whole call
   std::vector<uint8_t>& aux = ts.adj_aux;
   aux.assign(B * 8 + std::max<uint32_t>(1, n_dot) * 4, 0);
-  double tot = 0.0;
-  for (uint64_t c : ts.count) tot += (double)c;
-  for (uint32_t t = 0; t < B; ++t) {
-    const double w = (double)ts.count[t] / tot;
-    std::memcpy(aux.data() + 8 * t, &w, 8);
-  }
+  const std::vector<double> wts = ensemble_weights(ts);
+  if (B) std::memcpy(aux.data(), wts.data(), 8 * (size_t)B);
   for (uint32_t d = 0; d < n_dot; ++d) {
     const uint32_t p = (uint32_t)P.adj.dot_param[d];
     std::memcpy(aux.data() + B * 8 + 4 * d, &p, 4);
@@ -206,6 +202,7 @@ ptsbe_status adjoint_typed(const Plan& P, TrajSet& ts, const double* coef, const
         da.seed = seed;
         da.cfg = cfg;
         da.alpha0 = ts.alpha0;
+        da.carries_norm = 1u;
         da.idx[0] = (uint32_t)ex.mr_index[0];
         CK(launch_marginal<V>(ma, da, bb, s), "state-dependent channel");
         continue;

@@ -186,6 +186,12 @@ struct TrajSet {
   std::vector<uint8_t> rec_kraus;
   uint64_t total_shots = 0;
   uint64_t total_count = 0;
+  // Unnormalised ensemble weight of each trajectory, the proportions its shots
+  // are allocated by: the draw count (multiplicity allocation), p_alpha
+  // (reweight), 1 (uniform and per-shot), m_alpha (caller records).  The
+  // expectation E = sum_alpha w_alpha <O>_alpha and its gradient use
+  // w_alpha = wbasis_alpha / sum over the set.
+  std::vector<double> wbasis;
   // Cached device tables (host copy), keyed by the parameter values they used.
   std::mutex mu;
   std::vector<double> cached_params;
@@ -202,9 +208,13 @@ struct TrajSet {
   bool adj_valid = false;
   std::vector<uint8_t> adj_aux;    // host staging of weights and the dot -> parameter map
   std::vector<uint32_t> route_host; // host staging of prefix-sharing launch routes (src, dst pairs)
+  std::vector<double> weights_host; // host staging of the ensemble weights (expectation mode)
   std::vector<uint32_t> route_off;
   std::vector<uint64_t> uq_host;    // host staging of the distinct-shot pass's offset arrays
 };
+
+// Normalised ensemble weights w_alpha = wbasis_alpha / sum (summed in trajectory order).
+std::vector<double> ensemble_weights(const TrajSet& ts);
 
 // Matrix helpers
 Mat mat_identity(int d);

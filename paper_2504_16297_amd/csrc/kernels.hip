@@ -553,6 +553,31 @@ __device__ __forceinline__ double wave_incl_scan(double v) {
   return v;
 }
 
+// Exclusive running maximum of `v` over the block's threads in thread order
+// (`lo` for thread 0) and the block maximum.
+__device__ __forceinline__ double block_excl_max(double v, double lo, double* total) {
+  __shared__ double wmax[4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double inc = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const double o = __shfl_up(inc, d, 64);
+    if (lane >= d) inc = fmax(inc, o);
+  }
+  double ex = __shfl_up(inc, 1, 64);
+  if (lane == 0) ex = lo;
+  if (lane == 63) wmax[w] = inc;
+  __syncthreads();
+  double before = lo, all = lo;
+  for (int i = 0; i < 4; ++i) {
+    if (i < w) before = fmax(before, wmax[i]);
+    all = fmax(all, wmax[i]);
+  }
+  __syncthreads();
+  *total = all;
+  return fmax(before, ex);
+}
+
 // Exclusive prefix of `v` over the block (256 threads, fixed order) and the
 // block total; identical arithmetic wherever it is called.
 __device__ __forceinline__ void block_excl_scan(double v, double* excl, double* total) {
@@ -612,13 +637,75 @@ __device__ __forceinline__ void block_prob_scan(const ScanArgs<V>& a) {
     }
   double ex, tot;
   block_excl_scan(s, &ex, &tot);   // ends with a barrier
+  const uint64_t yb = (uint64_t)blockIdx.y * a.nblk + b;
+  // Monotone CDF.  Element e = tid * per + i gets off + A_e with A_e = ex + v[i];
+  // A is non-decreasing within a thread but rounding can make it dip by an ulp
+  // where one thread's run meets the next, and off + A where one block meets the
+  // next.  With a.maxa set, each CDF entry is the running maximum of those
+  // values over all earlier entries (blocks: floor[b], the largest value of the
+  // blocks before b), so every upper-bound search on it returns the first entry
+  // above its argument.  The counting kernel writes each block's largest A.
+  const bool mono = a.maxa != nullptr;
+  double thr_floor = 0.0;
+  if (mono) {
+    const double top = active ? ex + v[per - 1] : 0.0;
+    double bmax;
+    if (!kWriteCdf) {
+      block_excl_max(top, 0.0, &bmax);
+      if (tid == 0) a.maxa[yb] = bmax;
+    } else {
+      const double off0 = a.offs[yb];
+      thr_floor = block_excl_max(active ? off0 + top : 0.0, a.floor[yb], &bmax);
+    }
+  }
+  // Support lists.  The CDF entry of element e = tid * per + i is off + A_e with
+  // A_e = ex + v[i]; since adding off is monotone, an upper-bound search can
+  // only return the block's first element or an element whose A exceeds the
+  // previous element's.  Those elements (a superset of the possible results)
+  // form the list; the counting and the writing kernels compute the same A.
+  const bool support = a.sup_part != nullptr;
+  uint32_t nz = 0;  // bit i: element tid * per + i is in the list
+  double sex = 0.0, stot = 0.0;
+  if (support) {
+    __shared__ double last_a[256];
+    if (active) last_a[tid] = ex + v[per - 1];
+    __syncthreads();
+    if (active) {
+      double prev = tid == 0 ? 0.0 : last_a[tid - 1];
+      for (uint32_t i = 0; i < per; ++i) {
+        const double A = ex + v[i];
+        if ((tid == 0 && i == 0) || A > prev) nz |= 1u << i;
+        prev = A;
+      }
+    }
+    block_excl_scan((double)__popc(nz), &sex, &stot);
+  }
   if (!kWriteCdf) {
-    if (tid == 0) a.partial[(uint64_t)blockIdx.y * a.nblk + b] = tot;
+    if (tid == 0) {
+      a.partial[yb] = tot;
+      if (support) a.sup_part[yb] = stot;
+    }
     return;
   }
-  const double off = a.offs[(uint64_t)blockIdx.y * a.nblk + b];
+  const double off = a.offs[yb];
   if (active)
-    for (uint32_t i = 0; i < per; ++i) sh[scan_pad(tid * per + i)] = off + (ex + v[i]);
+    for (uint32_t i = 0; i < per; ++i) {
+      const double c = off + (ex + v[i]);
+      v[i] = mono ? fmax(thr_floor, c) : c;
+      sh[scan_pad(tid * per + i)] = v[i];
+    }
+  if (support && active && a.sup_count[blockIdx.y] <= kSupportMax) {
+    // the state's support list: its nonzero entries with their CDF values, in index order
+    uint32_t pos = (uint32_t)(a.sup_offs[yb] + sex);
+    double* sc = a.sup_cdf + (uint64_t)blockIdx.y * kSupportMax;
+    uint64_t* si = a.sup_idx + (uint64_t)blockIdx.y * kSupportMax;
+    for (uint32_t i = 0; i < per; ++i)
+      if ((nz >> i) & 1u) {
+        sc[pos] = v[i];
+        si[pos] = e0 + tid * per + i;
+        ++pos;
+      }
+  }
   __syncthreads();
   double* out = a.cdf ? a.cdf + (uint64_t)blockIdx.y * a.N : reinterpret_cast<double*>(st);
   if (E == kScanBlock) {
@@ -636,9 +723,9 @@ __global__ __launch_bounds__(256) void k_blocksum(ScanArgs<V> a) {
 }
 
 // offs[t*nblk+b] = exclusive prefix of partial over blocks; total[t] = full sum.
-__global__ __launch_bounds__(256) void k_scan_partials(double* partial, double* offs, double* total, uint32_t nblk) {
-  const double* p = partial + (uint64_t)blockIdx.x * nblk;
-  double* o = offs + (uint64_t)blockIdx.x * nblk;
+// With support lists, the same for the blocks' nonzero counts (exact: integers
+// below 2^53) and count[t] = the state's number of nonzero entries.
+__device__ __forceinline__ double scan_blocks(const double* p, double* o, uint32_t nblk) {
   const uint32_t per = (nblk + 255) / 256;
   const uint32_t b0 = threadIdx.x * per;
   double s = 0.0;
@@ -652,7 +739,35 @@ __global__ __launch_bounds__(256) void k_scan_partials(double* partial, double* 
       o[b0 + i] = run;
       run += p[b0 + i];
     }
+  return run;
+}
+
+__global__ __launch_bounds__(256) void k_scan_partials(double* partial, double* offs, double* total, uint32_t nblk,
+                                                       double* sup_part, double* sup_offs, uint32_t* sup_count,
+                                                       const double* maxa, double* floor) {
+  const uint64_t r0 = (uint64_t)blockIdx.x * nblk;
+  const double run = scan_blocks(partial + r0, offs + r0, nblk);
   if (threadIdx.x == 255) total[blockIdx.x] = run;
+  if (maxa) {
+    // floor[b] = the largest CDF value of blocks 0 .. b-1: max over them of off + largest A
+    __syncthreads();  // offs of every block written
+    const uint32_t per = (nblk + 255) / 256;
+    const uint32_t b0 = threadIdx.x * per;
+    double m = 0.0;
+    for (uint32_t i = 0; i < per; ++i)
+      if (b0 + i < nblk) m = fmax(m, offs[r0 + b0 + i] + maxa[r0 + b0 + i]);
+    double all;
+    double run_max = block_excl_max(m, 0.0, &all);
+    for (uint32_t i = 0; i < per; ++i)
+      if (b0 + i < nblk) {
+        floor[r0 + b0 + i] = run_max;
+        run_max = fmax(run_max, offs[r0 + b0 + i] + maxa[r0 + b0 + i]);
+      }
+  }
+  if (sup_part) {
+    const double c = scan_blocks(sup_part + r0, sup_offs + r0, nblk);
+    if (threadIdx.x == 255) sup_count[blockIdx.x] = c > (double)kSupportMax ? 0xffffffffu : (uint32_t)c;
+  }
 }
 
 // Inclusive FP64 prefix sum of |psi|^2, written in place over each complex64
@@ -951,6 +1066,9 @@ __global__ void k_mr_decide(MrDecideArgs a) {
     one += p[j + 1];
   }
   const double p1 = one / tot;
+  // an empty or non-finite state leaves no valid decision: report it
+  if (!(tot > 0.0) || !isfinite(p1)) atomicOr(a.status, 2u);
+  const bool norm_here = j == 0 && a.carries_norm != 0;
   const uint32_t r = a.idx[j];
   const uint32_t co = a.rec_chan ? a.rec_chan[r] : 0xffffffffu;
   if (co != 0xffffffffu) {
@@ -985,7 +1103,7 @@ __global__ void k_mr_decide(MrDecideArgs a) {
     }
     const uint64_t ri = (uint64_t)(a.t0 + tb) * a.n_measure + r;
     a.mr_bits[ri] = (uint8_t)k;
-    a.mr_norm[ri] = j == 0 ? 1.0 / sqrt(pk * tot) : 1.0 / sqrt(pk);
+    a.mr_norm[ri] = norm_here ? 1.0 / sqrt(pk * tot) : 1.0 / sqrt(pk);
     return;
   }
   const uint32_t bit = p1 > 0.5 ? 1u : 0u;
@@ -993,9 +1111,9 @@ __global__ void k_mr_decide(MrDecideArgs a) {
   if (fmin(p1, 1.0 - p1) > a.tol) atomicOr(a.status, 1u);
   const uint64_t ri = (uint64_t)(a.t0 + tb) * a.n_measure + a.idx[j];
   a.mr_bits[ri] = (uint8_t)bit;
-  // Every measure-reset of the group scales the whole state once; the group's
+  // Every measure-reset of the step scales the whole state once; the step's
   // first one also carries the 1/||psi|| renormalisation.
-  a.mr_norm[ri] = j == 0 ? 1.0 / sqrt(pb * tot) : 1.0 / sqrt(pb);
+  a.mr_norm[ri] = norm_here ? 1.0 / sqrt(pb * tot) : 1.0 / sqrt(pb);
 }
 
 // ------------------------------------------------------------------ sampler
@@ -1015,6 +1133,85 @@ __device__ __forceinline__ void sort_stage_regs(double (&x)[16], uint32_t size, 
       x[r] = xb;
       x[h] = xa;
     }
+  }
+}
+
+// A chunk of a trajectory whose state has a short support list (at most
+// kSupportMax elements that an upper-bound search can return): the same
+// uniforms, each searched in the list held in LDS, counted per list element,
+// and written out as the counts' runs in ascending order -- the sorted chunk
+// of the full path, since the search result is monotone in u.  `sh` is the
+// block's 32 KiB of LDS.
+template <typename BitT>
+__device__ void sample_support(const SampleArgs<BitT>& a, double* sh, uint32_t t, uint64_t j0, uint32_t cnt,
+                               uint64_t alpha, uint64_t k1, uint64_t out0) {
+  const uint32_t tb = t - a.b0;
+  const uint32_t K = a.sup_count[tb];
+  double* scdf = sh;                                                      // K CDF values
+  uint64_t* sidx = reinterpret_cast<uint64_t*>(sh + kSupportMax);         // K basis indices
+  uint32_t* hist = reinterpret_cast<uint32_t*>(sh + 2 * kSupportMax);     // K + 1 counts
+  uint32_t* hoff = hist + kSupportMax + 4;                                // K + 2 run starts
+  const double* gsc = a.sup_cdf + (uint64_t)tb * kSupportMax;
+  const uint64_t* gsi = a.sup_idx + (uint64_t)tb * kSupportMax;
+  for (uint32_t i = threadIdx.x; i < K; i += blockDim.x) {
+    scdf[i] = gsc[i];
+    sidx[i] = gsi[i];
+  }
+  for (uint32_t i = threadIdx.x; i <= K; i += blockDim.x) hist[i] = 0u;
+  __syncthreads();
+  const double total = a.total[tb];
+  for (uint32_t i = threadIdx.x * 4; i < cnt; i += blockDim.x * 4) {
+    double uu[4];
+    if (a.uniforms) {
+      for (int w = 0; w < 4; ++w) uu[w] = (i + w < cnt) ? a.uniforms[out0 + i + w] : 0.0;
+    } else {
+      const U64x4 r = philox4x64_10((j0 + i) / 4 + 1, 0, 0, 0, a.seed, k1);
+      for (int w = 0; w < 4; ++w) uu[w] = word_to_uniform(r.v[w]);
+    }
+    for (int w = 0; w < 4; ++w) {
+      if (i + w >= cnt) break;
+      const double v = uu[w] * total;
+      uint32_t lo = 0, h = K;
+      while (lo < h) {
+        const uint32_t mid = (lo + h) >> 1;
+        if (scdf[mid] > v)
+          h = mid;
+        else
+          lo = mid + 1;
+      }
+      atomicAdd(hist + lo, 1u);   // lo == K: no element exceeds v (the full search clamps to N - 1)
+    }
+  }
+  __syncthreads();
+  // run starts: exclusive prefix of the K + 1 counts
+  const uint32_t nb = K + 1, per = (nb + blockDim.x - 1) / blockDim.x, c0 = threadIdx.x * per;
+  double sum = 0.0;
+  for (uint32_t q = 0; q < per; ++q)
+    if (c0 + q < nb) sum += (double)hist[c0 + q];
+  double ex, tot;
+  block_excl_scan(sum, &ex, &tot);
+  uint32_t run = (uint32_t)ex;
+  for (uint32_t q = 0; q < per; ++q)
+    if (c0 + q < nb) {
+      hoff[c0 + q] = run;
+      run += hist[c0 + q];
+    }
+  if (threadIdx.x == 0) hoff[nb] = cnt;
+  __syncthreads();
+  const uint64_t N = a.N;
+  for (uint32_t j = threadIdx.x; j < cnt; j += blockDim.x) {
+    // the last run starting at or before j (empty runs start where the next one does)
+    uint32_t lo = 0, h = nb;
+    while (h - lo > 1) {
+      const uint32_t mid = (lo + h) >> 1;
+      if (hoff[mid] <= j)
+        lo = mid;
+      else
+        h = mid;
+    }
+    const uint64_t l = lo < K ? sidx[lo] : N - 1;
+    a.bits[out0 + j] = (BitT)l;
+    a.traj[out0 + j] = (uint32_t)alpha;
   }
 }
 
@@ -1040,6 +1237,10 @@ __global__ __launch_bounds__(256) void k_sample(SampleArgs<BitT> a) {
   const uint64_t alpha = a.alpha0 + t;
   const uint64_t k1 = stream_key1(2, a.cfg, alpha);
   const uint64_t out0 = a.shot_off[t] + j0;
+  if (a.sup_count && a.sup_count[t - a.b0] <= kSupportMax) {
+    sample_support(a, u, t, j0, cnt, alpha, k1, out0);
+    return;
+  }
   // Element i of the chunk lives at LDS index (i & 15) * R + (i >> 4), R = C / 16
   // columns: thread col < R holds elements 16 col .. 16 col + 15 of a row-major 16 x R
   // view, so register loads, column-pair LDS stages and the uniforms' stores
@@ -1187,6 +1388,15 @@ __global__ void k_expval_finish(const double* partial, const double* total, doub
   out[t0 + blockIdx.x] = s / total[blockIdx.x];
 }
 
+// E = sum_t w[t] ev[t], summed in trajectory order (the order the adjoint
+// gradient's value uses).
+__global__ void k_weighted_sum(const double* w, const double* ev, uint32_t n, double* E) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  double e = 0.0;
+  for (uint32_t t = 0; t < n; ++t) e += w[t] * ev[t];
+  *E = e;
+}
+
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, uint64_t n) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
     p[i] = v;
@@ -1214,7 +1424,8 @@ template <typename V>
 hipError_t launch_scan(const ScanArgs<V>& a, uint32_t batch, double* total, hipStream_t s) {
   dim3 grid(a.nblk, batch);
   hipLaunchKernelGGL(k_blocksum<V>, grid, dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_scan_partials, dim3(batch), dim3(256), 0, s, a.partial, a.offs, total, a.nblk);
+  hipLaunchKernelGGL(k_scan_partials, dim3(batch), dim3(256), 0, s, a.partial, a.offs, total, a.nblk, a.sup_part,
+                     a.sup_offs, a.sup_count, a.maxa, a.floor);
   hipLaunchKernelGGL(k_cdf<V>, grid, dim3(256), 0, s, a);
   return hipGetLastError();
 }
@@ -1222,8 +1433,12 @@ hipError_t launch_scan(const ScanArgs<V>& a, uint32_t batch, double* total, hipS
 template <typename V>
 hipError_t launch_norm(const ScanArgs<V>& a, uint32_t batch, double* total, hipStream_t s) {
   dim3 grid(a.nblk, batch);
-  hipLaunchKernelGGL(k_blocksum<V>, grid, dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_scan_partials, dim3(batch), dim3(256), 0, s, a.partial, a.offs, total, a.nblk);
+  ScanArgs<V> b = a;
+  b.sup_part = nullptr;
+  b.maxa = nullptr;
+  hipLaunchKernelGGL(k_blocksum<V>, grid, dim3(256), 0, s, b);
+  hipLaunchKernelGGL(k_scan_partials, dim3(batch), dim3(256), 0, s, b.partial, b.offs, total, b.nblk, nullptr,
+                     nullptr, nullptr, nullptr, nullptr);
   return hipGetLastError();
 }
 
@@ -1292,6 +1507,11 @@ hipError_t launch_grad_reduce(const double* partial, const double* w, uint32_t n
   const uint32_t np = n_params ? n_params : 1;
   hipLaunchKernelGGL(k_grad_gather, dim3((np + 255) / 256), dim3(256), 0, s, gdot, dot_param, n_dot, n_params, grad, ev,
                      w, n_traj, E);
+  return hipGetLastError();
+}
+
+hipError_t launch_weighted_sum(const double* w, const double* ev, uint32_t n, double* E, hipStream_t s) {
+  hipLaunchKernelGGL(k_weighted_sum, dim3(1), dim3(64), 0, s, w, ev, n, E);
   return hipGetLastError();
 }
 

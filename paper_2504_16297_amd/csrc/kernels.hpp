@@ -46,6 +46,11 @@ struct PassArgs {
   PTSBE_PASS_ARGS_FIELDS(V, DPass, DOp, DOverride, uint2)
 };
 
+// Support lists: the basis indices of a state with |psi_x|^2 > 0 (a superset of
+// the indices an upper-bound search of the CDF can return) and their CDF
+// values, kept per trajectory when there are at most kSupportMax of them.
+constexpr uint32_t kSupportMax = 1024;
+
 template <typename V>
 struct ScanArgs {
   V* states;
@@ -56,6 +61,17 @@ struct ScanArgs {
   uint32_t nblk;
   uint32_t per_block;
   uint32_t per_thread;
+  // monotone CDF (nullptr: plain block scan): per (state, block) its largest
+  // in-block prefix and the largest CDF value of the blocks before it
+  double* maxa;         // batch x nblk
+  double* floor;        // batch x nblk
+  // optional support lists (nullptr: none): per (state, block) counts and their
+  // exclusive prefix, per state the count, then up to kSupportMax (CDF, index)
+  double* sup_part;     // batch x nblk
+  double* sup_offs;     // batch x nblk
+  uint32_t* sup_count;  // batch
+  double* sup_cdf;      // batch x kSupportMax
+  uint64_t* sup_idx;    // batch x kSupportMax
 };
 
 template <typename V>
@@ -86,6 +102,10 @@ struct MrDecideArgs {
   const double* chan_param;   // per channel: K, d0[0..K), d1[0..K)
   uint64_t seed, alpha0;
   uint32_t cfg;
+  // 1 for the first group of a decision step: its first entry also carries the
+  // 1/||psi|| renormalisation (a step with more than kMaxGroup entries is
+  // decided in several groups from the same state, which is rescaled once)
+  uint32_t carries_norm;
 };
 
 template <typename BitT>
@@ -105,6 +125,10 @@ struct SampleArgs {
   uint32_t b0, b1;          // trajectories of this batch (set-local)
   uint32_t chunk;
   uint32_t cfg;
+  // support lists of the batch's states (nullptr: search the full CDF)
+  const uint32_t* sup_count;
+  const double* sup_cdf;
+  const uint64_t* sup_idx;
 };
 
 template <typename V>
@@ -184,5 +208,6 @@ template <typename V>
 hipError_t launch_expval(const ExpArgs<V>& a, const double* total, double* out, uint32_t batch, uint32_t t0,
                          hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
+hipError_t launch_weighted_sum(const double* w, const double* ev, uint32_t n, double* E, hipStream_t s);
 
 }  // namespace ptsbe

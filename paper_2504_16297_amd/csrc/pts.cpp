@@ -199,9 +199,11 @@ std::vector<Record> most_likely(const Plan& P, uint64_t k_max, const Criteria& c
 
 }  // namespace
 
+// wbasis: the unnormalised ensemble weight of each record (see TrajSet::wbasis);
+// empty = the records' counts.
 static ptsbe_status make_trajset(std::shared_ptr<const Plan> plan, const std::vector<Record>& recs,
                                  std::vector<uint64_t> m, std::vector<uint64_t> counts, uint64_t alpha0,
-                                 ptsbe_trajset_t* out) {
+                                 ptsbe_trajset_t* out, std::vector<double> wbasis = {}) {
   auto ts = std::make_shared<TrajSet>();
   ts->plan = plan;
   ts->alpha0 = alpha0;
@@ -216,6 +218,9 @@ static ptsbe_status make_trajset(std::shared_ptr<const Plan> plan, const std::ve
   }
   ts->m = std::move(m);
   ts->count = std::move(counts);
+  if (wbasis.empty())
+    for (auto v : ts->count) wbasis.push_back((double)v);
+  ts->wbasis = std::move(wbasis);
   for (auto v : ts->m) ts->total_shots += v;
   for (auto v : ts->count) ts->total_count += v;
   auto* h = new (std::nothrow) ptsbe_trajset_s;
@@ -338,22 +343,27 @@ ptsbe_status sample_kraus(const std::shared_ptr<Plan>& plan, const ptsbe_pts_opt
     T = T2;
     if (recs.empty()) return fail(PTSBE_E_ARG, "no record falls in the probability band");
   }
+  // Shots and ensemble weights follow the allocation: draw counts (multiplicity),
+  // joint probabilities (reweight), equal (uniform, one shot per draw).
   std::vector<uint64_t> m;
+  std::vector<double> wb;
   if (o->mode == PTSBE_PTS_PER_SHOT) {
     m.assign(recs.size(), 1);
+    wb.assign(recs.size(), 1.0);
   } else if (o->alloc == PTSBE_ALLOC_MULTIPLICITY) {
     if (o->mode == PTSBE_PTS_MOST_LIKELY) return fail(PTSBE_E_ARG, "most-likely mode uses REWEIGHT or UNIFORM");
     m = alloc_multiplicity(counts, T, o->total_shots);
+    for (auto c : counts) wb.push_back((double)c);
   } else if (o->alloc == PTSBE_ALLOC_REWEIGHT) {
-    std::vector<double> p;
-    for (auto& r : recs) p.push_back(joint_prob(P, r));
-    m = alloc_reweight(p, o->total_shots);
+    for (auto& r : recs) wb.push_back(joint_prob(P, r));
+    m = alloc_reweight(wb, o->total_shots);
   } else if (o->alloc == PTSBE_ALLOC_UNIFORM) {
     m.assign(recs.size(), o->nshots);
+    wb.assign(recs.size(), 1.0);
   } else {
     return fail(PTSBE_E_ARG, "unknown allocation");
   }
-  return make_trajset(plan, recs, std::move(m), std::move(counts), 0, out);
+  return make_trajset(plan, recs, std::move(m), std::move(counts), 0, out, std::move(wb));
 }
 
 ptsbe_status trajset_from_records(const std::shared_ptr<Plan>& plan, uint32_t n, const uint32_t* off,
@@ -375,7 +385,9 @@ ptsbe_status trajset_from_records(const std::shared_ptr<Plan>& plan, uint32_t n,
     }
   }
   std::vector<uint64_t> mm(m, m + n), cnt(n, 1);
-  return make_trajset(plan, recs, std::move(mm), std::move(cnt), alpha0, out);
+  std::vector<double> wb;
+  for (uint32_t a = 0; a < n; ++a) wb.push_back((double)m[a]);
+  return make_trajset(plan, recs, std::move(mm), std::move(cnt), alpha0, out, std::move(wb));
 }
 
 ptsbe_status trajset_slice(const TrajSet& ts, uint32_t b, uint32_t e, ptsbe_trajset_t* out) {
@@ -388,7 +400,17 @@ ptsbe_status trajset_slice(const TrajSet& ts, uint32_t b, uint32_t e, ptsbe_traj
     recs.push_back(r);
   }
   std::vector<uint64_t> m(ts.m.begin() + b, ts.m.begin() + e), c(ts.count.begin() + b, ts.count.begin() + e);
-  return make_trajset(ts.plan, recs, std::move(m), std::move(c), ts.alpha0 + b, out);
+  std::vector<double> wb(ts.wbasis.begin() + b, ts.wbasis.begin() + e);
+  return make_trajset(ts.plan, recs, std::move(m), std::move(c), ts.alpha0 + b, out, std::move(wb));
+}
+
+std::vector<double> ensemble_weights(const TrajSet& ts) {
+  double tot = 0.0;
+  for (double v : ts.wbasis) tot += v;
+  std::vector<double> w(ts.wbasis.size(), 0.0);
+  if (tot > 0.0)
+    for (size_t a = 0; a < w.size(); ++a) w[a] = ts.wbasis[a] / tot;
+  return w;
 }
 
 // ----------------------------------------------------------- device tables

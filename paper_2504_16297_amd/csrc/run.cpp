@@ -18,7 +18,9 @@ namespace {
 uint64_t a256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
 
 struct WsLayout {
-  uint64_t status, tables, routes, states, cdf, partial, offs, total, mr_partial, mr_bits, mr_norm, rec_info, end;
+  uint64_t status, tables, routes, states, cdf, partial, offs, total, mr_partial, mr_bits, mr_norm, rec_info, weights,
+      sup_part, sup_offs, sup_count, sup_cdf, sup_idx, maxa, floor, end;
+  bool support;
   uint32_t batch;
   uint32_t nblk, per_block, per_thread;
   bool share;
@@ -35,7 +37,7 @@ bool prefix_sharing(const Plan& P, const TrajSet& ts, const ptsbe_run_opts* o) {
 }
 
 WsLayout layout_for(const Plan& P, const TrajSet& ts, uint32_t mode, uint32_t batch, uint64_t table_bytes,
-                    bool share) {
+                    bool share, bool support) {
   WsLayout L{};
   const uint64_t N = 1ull << P.n;
   const uint64_t esz = P.precision == PTSBE_C64 ? 8 : 16;
@@ -63,6 +65,26 @@ WsLayout layout_for(const Plan& P, const TrajSet& ts, uint32_t mode, uint32_t ba
   L.mr_norm = o; o = a256(o + std::max<uint64_t>(1, Btot * P.n_measure) * 8);
   L.rec_info = o;
   if (P.n_general) o = a256(o + (uint64_t)P.n_measure * 8 + P.rec_info.chan_param.size() * 8);
+  L.weights = o;
+  if (mode == PTSBE_RUN_EXPECTATION) o = a256(o + std::max<uint64_t>(1, Btot) * 8);
+  // support lists for the sampler: every block start is in a list, so they can
+  // only be short when the state has few blocks
+  L.support = support && mode == PTSBE_RUN_SHOTS && L.nblk <= kSupportMax / 2;
+  L.sup_part = o;
+  if (L.support) o = a256(o + (uint64_t)batch * L.nblk * 8);
+  L.sup_offs = o;
+  if (L.support) o = a256(o + (uint64_t)batch * L.nblk * 8);
+  L.sup_count = o;
+  if (L.support) o = a256(o + (uint64_t)batch * 4);
+  L.sup_cdf = o;
+  if (L.support) o = a256(o + (uint64_t)batch * kSupportMax * 8);
+  L.sup_idx = o;
+  if (L.support) o = a256(o + (uint64_t)batch * kSupportMax * 8);
+  // monotone CDF of the sampler: per (state, block) largest in-block prefix and floor
+  L.maxa = o;
+  if (mode == PTSBE_RUN_SHOTS) o = a256(o + (uint64_t)batch * L.nblk * 8);
+  L.floor = o;
+  if (mode == PTSBE_RUN_SHOTS) o = a256(o + (uint64_t)batch * L.nblk * 8);
   L.end = o;
   return L;
 }
@@ -229,6 +251,12 @@ ptsbe_status run_typed(const Plan& P, TrajSet& ts, const ptsbe_run_opts& o, uint
     d_rec_gidx = reinterpret_cast<const uint32_t*>(ri + nm * 4);
     d_chan_param = reinterpret_cast<const double*>(ri + nm * 8);
   }
+  if ((phase & PH_UPLOAD) && o.mode == PTSBE_RUN_EXPECTATION && o.d_ensemble) {
+    // the weights stay in the trajectory set until its next run (the copy is asynchronous)
+    ts.weights_host = ensemble_weights(ts);
+    CK(hipMemcpyAsync(ws + L.weights, ts.weights_host.data(), (size_t)B * 8, hipMemcpyHostToDevice, s),
+       "weights upload");
+  }
   uint32_t* status = reinterpret_cast<uint32_t*>(ws + L.status);
   if (phase & PH_LAUNCH) CK(launch_fill_u32(status, 0, 4, s), "status reset");
   V* states = reinterpret_cast<V*>(ws + L.states);
@@ -331,6 +359,7 @@ ptsbe_status run_typed(const Plan& P, TrajSet& ts, const ptsbe_run_opts& o, uint
           da.seed = o.seed;
           da.cfg = o.cfg;
           da.alpha0 = ts.alpha0;
+          da.carries_norm = g0 == 0 ? 1u : 0u;
           for (size_t j = g0; j < g1; ++j) {
             ma.q[j - g0] = (uint32_t)ex.mr_qubits[j];
             da.idx[j - g0] = (uint32_t)ex.mr_index[j];
@@ -350,6 +379,15 @@ ptsbe_status run_typed(const Plan& P, TrajSet& ts, const ptsbe_run_opts& o, uint
     sa.per_thread = L.per_thread;
     if (o.mode == PTSBE_RUN_SHOTS) {
       sa.cdf = P.precision == PTSBE_C128 ? reinterpret_cast<double*>(ws + L.cdf) : nullptr;
+      sa.maxa = reinterpret_cast<double*>(ws + L.maxa);
+      sa.floor = reinterpret_cast<double*>(ws + L.floor);
+      if (L.support) {
+        sa.sup_part = reinterpret_cast<double*>(ws + L.sup_part);
+        sa.sup_offs = reinterpret_cast<double*>(ws + L.sup_offs);
+        sa.sup_count = reinterpret_cast<uint32_t*>(ws + L.sup_count);
+        sa.sup_cdf = reinterpret_cast<double*>(ws + L.sup_cdf);
+        sa.sup_idx = reinterpret_cast<uint64_t*>(ws + L.sup_idx);
+      }
       CK(launch_scan<V>(sa, bb, total, s), "probability scan");
       CK(tm.mark(T_SCAN), "timer");
       SampleArgs<BitT> sm{};
@@ -369,6 +407,9 @@ ptsbe_status run_typed(const Plan& P, TrajSet& ts, const ptsbe_run_opts& o, uint
       sm.chunk = chunk;
       sm.cfg = o.cfg;
       sm.item0 = ts.chunk_off[b0];
+      sm.sup_count = sa.sup_count;
+      sm.sup_cdf = sa.sup_cdf;
+      sm.sup_idx = sa.sup_idx;
       const uint64_t items = ts.chunk_off[b0 + bb] - ts.chunk_off[b0];
       if (items) {
         CK(launch_sample<BitT>(sm, items, s), "sampler");
@@ -395,6 +436,9 @@ ptsbe_status run_typed(const Plan& P, TrajSet& ts, const ptsbe_run_opts& o, uint
       CK(launch_expval<V>(ea, total, o.d_expval, bb, b0, s), "expectation");
     }
   }
+  if (o.mode == PTSBE_RUN_EXPECTATION && o.d_ensemble)
+    CK(launch_weighted_sum(reinterpret_cast<const double*>(ws + L.weights), o.d_expval, B, o.d_ensemble, s),
+       "ensemble value");
   if (d_mr_bits && P.n_measure)
     CK(hipMemcpyAsync(d_mr_bits, mr_bits, (size_t)B * P.n_measure, hipMemcpyDeviceToDevice, s), "record copy");
   if (d_status) CK(hipMemcpyAsync(d_status, status, 4, hipMemcpyDeviceToDevice, s), "status copy");
@@ -435,7 +479,8 @@ ptsbe_status workspace_size(const Plan& P, TrajSet& ts, const ptsbe_run_opts* o,
   uint32_t B = (uint32_t)ts.m.size();
   uint32_t batch = o->max_batch ? std::min<uint32_t>(o->max_batch, std::max<uint32_t>(B, 1)) : std::max<uint32_t>(B, 1);
   batch = std::min<uint32_t>(batch, 65534);
-  *bytes = layout_for(P, ts, o->mode, batch, ts.table_blob.size(), prefix_sharing(P, ts, o)).end;
+  *bytes = layout_for(P, ts, o->mode, batch, ts.table_blob.size(), prefix_sharing(P, ts, o),
+                      !(o->flags & PTSBE_RUN_NO_SUPPORT_LISTS)).end;
   return PTSBE_OK;
 }
 
@@ -463,10 +508,11 @@ ptsbe_status run_batch(const Plan& P, TrajSet& ts, const ptsbe_run_opts* o, void
   uint32_t batch = o->max_batch ? std::min(o->max_batch, B) : B;
   batch = std::min<uint32_t>(batch, 65534);  // grid.y limit of the per-state launches (+1 carrier row)
   const bool share = prefix_sharing(P, ts, o);
-  WsLayout L = layout_for(P, ts, o->mode, batch, ts.table_blob.size(), share);
+  const bool support = !(o->flags & PTSBE_RUN_NO_SUPPORT_LISTS);
+  WsLayout L = layout_for(P, ts, o->mode, batch, ts.table_blob.size(), share, support);
   while (L.end > ws_bytes && batch > 1) {
     batch = std::max<uint32_t>(1, batch / 2);
-    L = layout_for(P, ts, o->mode, batch, ts.table_blob.size(), share);
+    L = layout_for(P, ts, o->mode, batch, ts.table_blob.size(), share, support);
   }
   if (L.end > ws_bytes)
     return fail(PTSBE_E_OOM, "workspace of " + std::to_string(ws_bytes) + " bytes is below the " +
@@ -524,6 +570,7 @@ ptsbe_status run_status(const void* d_ws, void* stream) {
   uint32_t v = 0;
   CK(hipMemcpy(&v, d_ws, 4, hipMemcpyDeviceToHost), "status read");
   if (v & 1u) return fail(PTSBE_E_NONDET_MEASURE, "a measure-reset outcome was not deterministic (min(p1, 1-p1) > 1e-6)");
+  if (v & 2u) return fail(PTSBE_E_DEVICE, "a decision step met a state of zero or non-finite norm");
   return PTSBE_OK;
 }
 

@@ -12,8 +12,17 @@ trajectory set through the library's stage timer on the device, and returns the
 candidate with the least tile-pass time on that sample.  Trajectory records are
 plan-independent (the noise sites depend only on the circuit), so one sample is
 carried across candidates with ptsbe_trajset_from_records.
+
+`tuned_plan_options` keeps the picks in a JSON cache keyed by a hash of the
+circuit description, the precision and the candidate set, so a workload is
+tuned once per machine (``python -m paper_2504_16297_amd.tune`` fills the
+cache for the benchmark workloads); the default cache is the package's
+``tune_cache.json``, or the file named by ``PTSBE_TUNE_CACHE``.
 """
 
+import hashlib
+import json
+import os
 import time
 
 import numpy as np
@@ -76,3 +85,88 @@ def autotune(circuit, precision="c64", records=None, sample=64, candidates=None,
         del ws, out
     return {"tile_qubits": best[1], "min_fill": best[2], "half_tile": best[3], "pair_fusion": best[4],
             "results": results, "seconds": time.perf_counter() - t_start}
+
+
+DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
+
+
+def circuit_key(circuit, precision, candidates):
+    """Cache key: SHA-256 of the circuit description (ops, channels, rules,
+    parameters), the precision and the candidate set."""
+    blob = json.dumps({"circuit": circuit, "precision": precision, "candidates": candidates}, sort_keys=True,
+                      default=lambda x: x.tolist() if hasattr(x, "tolist") else str(x))
+    return hashlib.sha256(blob.encode()).hexdigest()[:32]
+
+
+def _cache_path(path):
+    return path or os.environ.get("PTSBE_TUNE_CACHE") or DEFAULT_CACHE
+
+
+def load_cache(path=None):
+    path = _cache_path(path)
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        return json.load(f)
+
+
+def tuned_plan_options(circuit, precision="c64", cache=None, tune_if_missing=False, **kw):
+    """ptsbe_plan keyword arguments for `circuit` from the tuning cache, tuning
+    (and storing the pick) on a miss if `tune_if_missing`, else None on a miss.
+    Returns (options or None, cache entry or None)."""
+    cands = kw.get("candidates") or candidates_for(circuit["n_qubits"], precision)
+    key = circuit_key(circuit, precision, [list(c) for c in cands])
+    path = _cache_path(cache)
+    entries = load_cache(path)
+    e = entries.get(key)
+    if e is None and tune_if_missing:
+        r = autotune(circuit, precision=precision, **kw)
+        e = {"n_qubits": circuit["n_qubits"], "precision": precision,
+             "pick": {k: r[k] for k in ("tile_qubits", "min_fill", "half_tile", "pair_fusion")},
+             "results": [list(x) for x in r["results"]], "seconds": r["seconds"]}
+        entries[key] = e
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(entries, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    if e is None:
+        return None, None
+    return dict(e["pick"]), e
+
+
+def main(argv=None):
+    """Tune the benchmark workloads and store the picks in the cache."""
+    import argparse
+    import sys
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="c4", choices=["c2", "c4"])
+    ap.add_argument("--cache", default=None)
+    ap.add_argument("--sample", type=int, default=0, help="trajectories timed per candidate (0: by state size)")
+    a = ap.parse_args(argv)
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    if root not in sys.path:
+        sys.path.insert(0, root)
+    from workloads import c2_workload, c4_workload
+    from . import ptsbe_sample_kraus
+    wls = [c2_workload()] if a.workload == "c2" else [c4_workload(n) for n in (24, 26, 28)]
+
+    def log(msg):
+        sys.stderr.write(msg + "\n")
+        sys.stderr.flush()
+
+    for wl in wls:
+        circ = wl["circuit"]
+        n = circ["n_qubits"]
+        plan = ptsbe_plan(circ, precision=wl["precision"], compile=False)
+        pts = wl["pts"]
+        ts = ptsbe_sample_kraus(plan, "proportional", n_draws=pts["n_draws"], total_shots=pts["total_shots"],
+                                seed=wl["seed"], cfg=wl["cfg"])
+        state = (8 if wl["precision"] == "c64" else 16) << n
+        sample = a.sample or int(max(1, min(64, (8 << 30) // state)))
+        opts, e = tuned_plan_options(circ, wl["precision"], cache=a.cache, tune_if_missing=True,
+                                     records=ts.get()["records"], sample=sample, log=log)
+        log(f"[tune] {n} qubits: {opts} ({e['seconds']:.0f} s)")
+
+
+if __name__ == "__main__":
+    main()

@@ -133,6 +133,64 @@ def test_sampler_chunk_sizes(chunk):
             assert bad == 0, (chunk, a)
 
 
+def _support_cases():
+    peaked = {"n_qubits": 10, "params": [], "channels": [], "rules": [],
+              "ops": [{"kind": "gate", "name": "RY", "qubits": (q,), "params": (0.3 + 0.1 * q,), "tag": "RY"}
+                      for q in range(10)]}
+    # 18 qubits, 3 of them rotated: 8 nonzero amplitudes spread over 64 scan blocks
+    sparse = {"n_qubits": 18, "params": [], "channels": [], "rules": [],
+              "ops": [{"kind": "gate", "name": "RY", "qubits": (q,), "params": (0.7 + 0.2 * q,), "tag": "RY"}
+                      for q in (2, 9, 17)]}
+    spread = random_small_circuit(10, 60, np.random.default_rng(3), p1=0.0, p2=0.0)
+    dense = random_small_circuit(13, 80, np.random.default_rng(4), p1=0.0, p2=0.0)
+    return [("peaked", peaked, "c64"), ("sparse", sparse, "c64"), ("spread", spread, "c128"),
+            ("dense", dense, "c64")]
+
+
+@pytest.mark.parametrize("chunk", [256, 4096])
+def test_support_lists_give_the_sorted_shots(chunk):
+    """The sampler's support-list path (per-element counts of unsorted uniforms,
+    written as runs) gives exactly the shots of the sort-and-search path: on a
+    peaked, a sparse (8 nonzero amplitudes of 2^18), a spread complex128 and a
+    dense state (list too long: full path), with ragged chunks, zero-shot
+    trajectories and caller uniforms including 0 and 1 - 2^-53."""
+    for name, circ, prec in _support_cases():
+        plan = P.ptsbe_plan(circ, precision=prec)
+        m = [3 * chunk + 17, chunk, 5, 0, chunk - 1]
+        ts = P.ptsbe_trajset_from_records(plan, [()] * len(m), m)
+        a = P.ptsbe_run_batch(plan, ts, mode="shots", seed=21, cfg=4, sort_chunk=chunk)
+        b = P.ptsbe_run_batch(plan, ts, mode="shots", seed=21, cfg=4, sort_chunk=chunk, support_lists=False)
+        u = np.random.default_rng(chunk).random(sum(m))
+        u[0], u[1], u[chunk] = 0.0, 1.0 - 2.0 ** -53, 1.0 - 2.0 ** -53
+        ud = torch.tensor(u, dtype=torch.float64, device="cuda")
+        c = P.ptsbe_run_batch(plan, ts, mode="shots", uniforms=ud, sort_chunk=chunk)
+        d = P.ptsbe_run_batch(plan, ts, mode="shots", uniforms=ud, sort_chunk=chunk, support_lists=False)
+        torch.cuda.synchronize()
+        S = sum(m)
+        log(f"[support] {name} chunk={chunk}: {S} shots, {len(np.unique(a['bits'][:S].cpu().numpy()))} distinct")
+        assert torch.equal(a["bits"][:S], b["bits"][:S]) and torch.equal(a["traj"][:S], b["traj"][:S])
+        assert torch.equal(c["bits"][:S], d["bits"][:S])
+        if name == "sparse":
+            ref, _ = oracle_states(circ, [()])
+            bits = a["bits"][:S].cpu().numpy()
+            off = np.concatenate([[0], np.cumsum(m)])
+            for t in range(len(m)):
+                bad, _ = compare_shots(ref[0], bits[off[t]:off[t + 1]], m[t], 21, 4, t, chunk=chunk)
+                assert bad == 0
+
+
+def test_support_lists_surface_code():
+    """The surface-code trajectories (each spread over at most 16 outcomes):
+    support-list and sorted paths give the same 10^6 tagged shots."""
+    wl = c3_workload()
+    plan = P.ptsbe_plan(wl["circuit"])
+    ts = P.ptsbe_sample_kraus(plan, "most_likely", k_max=512, total_shots=10 ** 6)
+    a = P.ptsbe_run_batch(plan, ts, seed=0, cfg=3)
+    b = P.ptsbe_run_batch(plan, ts, seed=0, cfg=3, support_lists=False)
+    torch.cuda.synchronize()
+    assert torch.equal(a["bits"], b["bits"]) and torch.equal(a["traj"], b["traj"])
+
+
 def test_zero_shot_trajectories_and_capacity_error():
     circ = random_small_circuit(4, 20, np.random.default_rng(9))
     plan = P.ptsbe_plan(circ)
@@ -191,6 +249,40 @@ def test_surface_code_records_and_shots():
         assert rbits[j] == list(mr[a])
         bad, _ = compare_shots(ref[j], bits[off[a]:off[a + 1]], int(g["m"][a]), 0, 3, a)
         assert bad == 0
+
+
+def test_measure_reset_step_wider_than_one_group():
+    """18 measure-resets decided in one step (two groups of at most 16 from the
+    same state): records and states equal the oracle's, the state renormalised
+    once.  Before the step: X on every third qubit, an X-flip site on each
+    (records flip some outcomes), an entangled pair on qubits 18-19 that the
+    step leaves alone."""
+    n = 20
+    ops = []
+    for q in range(18):
+        if q % 3 == 0:
+            ops.append({"kind": "gate", "name": "X", "qubits": (q,), "params": (), "tag": "X"})
+        ops.append({"kind": "noise", "channel": 0, "qubits": (q,)})
+    ops += [{"kind": "gate", "name": "H", "qubits": (18,), "params": (), "tag": "H"},
+            {"kind": "gate", "name": "CNOT", "qubits": (18, 19), "params": (), "tag": "CNOT"}]
+    ops += [{"kind": "measure_reset", "qubits": (q,)} for q in range(18)]
+    ops += [{"kind": "gate", "name": "H", "qubits": (q,), "params": (), "tag": "H"} for q in (0, 7)]
+    circ = {"n_qubits": n, "ops": ops, "channels": [{"name": "xflip", "nq": 1, "p": 0.2}], "rules": [],
+            "params": []}
+    plan = P.ptsbe_plan(circ)
+    assert plan.info["n_measure"] == 18
+    ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=12, total_shots=12000, seed=5, cfg=2)
+    g = ts.get()
+    r = P.ptsbe_run_batch(plan, ts, mode="states")
+    P.ptsbe_run_status(plan, r["workspace"])
+    torch.cuda.synchronize()
+    gpu = r["states"].cpu().numpy()
+    mr = r["mr_bits"].cpu().numpy()
+    ref, rbits = oracle_states(circ, g["records"])
+    assert any(len(rec) > 0 for rec in g["records"])
+    for a in range(len(ref)):
+        assert list(mr[a]) == rbits[a], f"trajectory {a}"
+        assert float(np.max(np.abs(gpu[a] - ref[a]))) <= 1e-5
 
 
 def test_nondeterministic_measure_is_reported():

@@ -87,3 +87,33 @@ def test_most_likely_truncation_bound():
             dist += (pa / cover) * np.abs(psi) ** 2
         tvd = 0.5 * np.sum(np.abs(dist - exact))
         assert tvd <= (1 - cover) + 1e-12
+
+
+def test_ensemble_weights_reproduce_the_channel_expectation():
+    """sample_kraus's weights: most-likely-first over every record with reweight
+    weights (p_alpha / sum p) gives Tr(O rho) of the exact channel; with
+    multiplicity weights they are the draw frequencies count / T; uniform
+    weights are equal.  O = Z_0 Z_1 + 0.5 Z_2 (diagonal)."""
+    from oracle.pts import ensemble_weights, sample_kraus
+    circ = _tiny_circuit(1)
+    sp = site_probs(circ)
+    n_all = int(np.prod([len(p) for p in sp]))
+    ss = expand(circ)
+    ch = site_channels(circ)
+    rho = evolve(circ)
+    x = np.arange(1 << circ["n_qubits"])
+    z = lambda q: 1 - 2 * ((x >> q) & 1)
+    odiag = z(0) * z(1) + 0.5 * z(2)
+    exact = float(np.real(np.sum(np.diag(rho) * odiag)))
+    ref = sample_kraus(sp, {"mode": "most_likely", "k_max": n_all, "total_shots": 10 ** 6,
+                            "alloc": "reweight"}, 0, 1)
+    assert len(ref["records"]) == n_all
+    e = 0.0
+    for rec, w in zip(ref["records"], ref["weights"]):
+        psi, _ = run_record(circ, rec, steps_sites=ss, chans=ch)
+        e += w * float(np.sum(np.abs(psi) ** 2 * odiag))
+    assert abs(e - exact) < 1e-12
+    ref = sample_kraus(sp, {"mode": "proportional", "n_draws": 500, "total_shots": 999,
+                            "alloc": "multiplicity"}, 3, 1)
+    assert np.allclose(ref["weights"], np.asarray(ref["counts"]) / 500.0, rtol=0, atol=1e-15)
+    assert ensemble_weights([5, 1, 2], [0.1, 0.2, 0.3], "uniform") == [1 / 3] * 3

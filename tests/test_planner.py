@@ -161,6 +161,15 @@ def test_selection_criteria_match_oracle(seed):
     off = np.concatenate([[0], np.cumsum([len(p) for p in sp])])
     allow = {(s, k) for s in range(len(sp)) for k in range(1, len(sp[s])) if flags[off[s] + k]}
     assert 0 < len(allow) < sum(len(p) - 1 for p in sp)
+    # the same set from the circuit description: site s is the s-th explicit noise op
+    expect, s = set(), 0
+    for i, op in enumerate(circ["ops"]):
+        if op["kind"] != "noise":
+            continue
+        if all(1 <= q < 6 for q in op["qubits"]) and i < 2 * len(circ["ops"]) // 3:
+            expect |= {(s, k) for k in (1, 2, 5, 7) if k < len(sp[s])}
+        s += 1
+    assert allow == expect
     for crit in ({}, {"max_errors": 2}, {"min_errors": 1, "parity": "odd"}, {"parity": "even"}):
         kw = dict(kraus_allow=flags, **crit)
         ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=400, total_shots=9999, seed=seed, cfg=3, **kw)
@@ -261,3 +270,29 @@ def test_autotune_candidates():
     circ = random_small_circuit(8, 30, np.random.default_rng(2))
     for tile, fill, half, pf in candidates_for(8, "c64"):
         P.ptsbe_plan(circ, tile_qubits=tile, min_fill=fill, half_tile=half, pair_fusion=pf)
+
+
+def test_tuning_cache_keys_and_reuse(tmp_path, monkeypatch):
+    """The autotuner's cache: a miss tunes once and stores the pick under a key
+    of the circuit, precision and candidate set; a hit returns it without
+    tuning; another circuit or precision is another key."""
+    from paper_2504_16297_amd import tune
+    calls = []
+
+    def fake_autotune(circuit, precision="c64", **kw):
+        calls.append((circuit["n_qubits"], precision))
+        return {"tile_qubits": 11, "min_fill": 3, "half_tile": False, "pair_fusion": True,
+                "results": [(11, 3, False, True, 1.5, 0.1)], "seconds": 0.2}
+
+    monkeypatch.setattr(tune, "autotune", fake_autotune)
+    cache = str(tmp_path / "tune.json")
+    a = random_small_circuit(8, 30, np.random.default_rng(1))
+    b = random_small_circuit(8, 30, np.random.default_rng(2))
+    assert tune.tuned_plan_options(a, "c64", cache=cache) == (None, None)
+    opts, e = tune.tuned_plan_options(a, "c64", cache=cache, tune_if_missing=True)
+    assert opts == {"tile_qubits": 11, "min_fill": 3, "half_tile": False, "pair_fusion": True}
+    assert tune.tuned_plan_options(a, "c64", cache=cache)[0] == opts and len(calls) == 1
+    assert tune.tuned_plan_options(b, "c64", cache=cache)[0] is None
+    assert tune.tuned_plan_options(a, "c128", cache=cache)[0] is None
+    plan = P.ptsbe_plan(a, **opts)
+    assert plan.info["tile_qubits"] == 8      # tiles are capped at the qubit count
