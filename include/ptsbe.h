@@ -88,11 +88,10 @@ typedef struct {
  * 2^nq x 2^nq complex128 matrices.  It must be CPTP (Sec. 2.2).  A unitary
  * mixture, K_k^dagger K_k = p_k I (Sec. 2.2 feature 2, read as
  * K_k = sqrt(p_k) U_k), has state-independent p_k: its sites are pre-sampled
- * by PTS, and K_0 is taken as the "no error" operator of the record.  A
- * 1-qubit channel whose K_k^dagger K_k are all diagonal (amplitude damping) is
- * resolved from the state when a trajectory reaches it (Algorithm 1's
- * state-dependent branch; see ptsbe_plan_get_record_info), or replaced by its
- * Pauli twirl with PTSBE_PLAN_TWIRL.  Other channels: PTSBE_E_UNSUPPORTED.
+ * by PTS, and K_0 is taken as the "no error" operator of the record.  Any
+ * other channel is resolved from the state when a trajectory reaches it
+ * (Algorithm 1's state-dependent branch; see ptsbe_plan_get_record_info), or
+ * replaced by its Pauli twirl with PTSBE_PLAN_TWIRL.
  * At most 16 operators per channel. */
 typedef struct {
     uint32_t nq;
@@ -163,7 +162,7 @@ typedef struct {
 /* Replace every channel that is not a unitary mixture (amplitude damping, ...)
  * by its Pauli twirl (see ptsbe_pauli_twirl), which is: Pauli-twirled noise
  * models, one of the tailored error models Sec. 1 names.  Without the flag such
- * channels are rejected (PTSBE_E_UNSUPPORTED). */
+ * channels are resolved from the state (see ptsbe_plan_get_record_info). */
 #define PTSBE_PLAN_TWIRL 64u
 /* Plan flag: no pair fusion.  By default a diagonal 2-qubit gate (CZ, ...)
  * whose two qubits both carry a pending run of 1-qubit operations merges with
@@ -171,6 +170,16 @@ typedef struct {
  * either qubit until another operation needs one of them (in a brick circuit one
  * 4x4 then replaces four 2x2 matrices and a sign flip). */
 #define PTSBE_PLAN_NO_PAIR_FUSION 128u
+/* Plan flag: store the states in plain index order.  By default amplitude x of
+ * a state of more than 2^12 amplitudes sits at x XOR (f(x >> 12) << 4), f a fixed
+ * linear map of the high index bits to 8 bits: runs of 16 amplitudes and blocks
+ * of 4096 stay in place, but the runs a tile pass moves no longer differ only in
+ * high address bits (faster on the HBM).  States leave the library in plain
+ * order either way (STATES mode, shots, expectation values). */
+#define PTSBE_PLAN_NO_SWIZZLE 256u
+/* Plan flag: the compiled passes load and store the states with nontemporal
+ * (streaming) cache hints. */
+#define PTSBE_PLAN_NONTEMPORAL 512u
 
 typedef struct ptsbe_plan_s* ptsbe_plan_t;
 typedef struct ptsbe_trajset_s* ptsbe_trajset_t;
@@ -226,12 +235,15 @@ ptsbe_status ptsbe_plan_get_site_ops(ptsbe_plan_t plan, uint32_t* op_index, uint
  * index).  channel[r] = the entry's channel index, or 0xffffffff for a
  * measure-reset; gidx[r] = the word of the channel decision's uniform in the
  * stream [seed, 4 << 56 | cfg << 48 | alpha] (0 for measure-resets).  A
- * state-dependent channel is a 1-qubit channel that is not a unitary mixture
- * but has diagonal K_k^dagger K_k (amplitude damping): it is resolved when the
- * trajectory's state reaches it (Algorithm 1's state-dependent branch), with
- * p_k = (K_k^dagger K_k)_00 P(q = 0) + (K_k^dagger K_k)_11 P(q = 1) and k the
- * smallest index with u < p_0 + ... + p_k (the last with p_k > 0 past the end),
- * then K_k / sqrt(p_k).  Arrays have n_measure entries; either may be NULL. */
+ * state-dependent channel is a 1- or 2-qubit channel that is not a unitary
+ * mixture: it is resolved when the trajectory's state reaches it (Algorithm
+ * 1's state-dependent branch), with p_k = <psi|K_k^dagger K_k|psi> / <psi|psi>
+ * and k the smallest index with u < p_0 + ... + p_k (the last with p_k > 0
+ * past the end), then K_k / sqrt(p_k).  With diagonal K_k^dagger K_k on one
+ * qubit (amplitude damping) p_k comes from the qubit's populations and K_k is
+ * applied in the next tile pass; otherwise from the FP64 reduced density
+ * matrix of the channel's qubits, in a step of its own that also applies K_k.
+ * Arrays have n_measure entries; either may be NULL. */
 ptsbe_status ptsbe_plan_get_record_info(ptsbe_plan_t plan, uint32_t* channel, uint32_t* gidx);
 void ptsbe_plan_destroy(ptsbe_plan_t plan);
 

@@ -87,7 +87,7 @@ def trajectory_grad(circuit, record, params, odiag, steps_sites=None, chans=None
             d = trace[st[4]]
             G = d["K"] / np.sqrt(d["p"])
             psi = d["psi"]
-            lam = apply(lam, n, G.conj().T, (d["q"],))
+            lam = apply(lam, n, G.conj().T, d["q"])
         else:
             raise ValueError(f"adjoint does not support {kind}")
     return e, grad

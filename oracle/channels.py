@@ -147,11 +147,19 @@ def pauli_transfer_diagonal(kraus):
     return out
 
 
+def state_dependent(kraus, tol=1e-12):
+    """A CPTP channel on one or two qubits that is not a unitary mixture: its
+    probabilities p_k = <psi|K_k^dagger K_k|psi> depend on the state, so it is
+    resolved when the trajectory's state reaches it (Algorithm 1's
+    state-dependent branch) instead of being pre-sampled."""
+    return kraus[0].shape in ((2, 2), (4, 4)) and unitary_mixture(kraus, tol) is None
+
+
 def general_channel(kraus, tol=1e-12):
-    """A channel that is not a unitary mixture but acts on one qubit with every
-    K_k^dagger K_k diagonal is resolved when the trajectory's state reaches it
-    (Algorithm 1's state-dependent branch): p_k = d0[k] P(q=0) + d1[k] P(q=1).
-    Returns (d0, d1), or None for any other channel."""
+    """A state-dependent channel on one qubit with every K_k^dagger K_k diagonal
+    (amplitude damping, phase damping) has p_k = d0[k] P(q=0) + d1[k] P(q=1), a
+    function of the qubit's populations alone.  Returns (d0, d1), or None for
+    any other channel."""
     if unitary_mixture(kraus, tol) is not None or kraus[0].shape != (2, 2):
         return None
     d0, d1 = [], []

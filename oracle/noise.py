@@ -12,14 +12,15 @@ An explicit ``noise`` op is a site at its own position.  After a gate or
 parametrised gate, one site per ``after_tag`` rule whose tag matches.  At the
 end, for each ``before_readout`` rule, one site per listed qubit, ascending.
 
-A channel that is not a unitary mixture but a 1-qubit channel with diagonal
-K^dagger K (amplitude damping) is not pre-sampled: at each of its positions
+A channel on one or two qubits that is not a unitary mixture (amplitude
+damping, any CPTP channel whose K^dagger K are not multiples of the identity)
+is not pre-sampled: at each of its positions
 the step list holds a ("gch", qubits, record index, channel, gch index) step,
 decided when the state reaches it; its record index shares the counter of the
 measure-resets.
 """
 
-from .channels import general_channel, kraus_ops, cptp_error, unitary_mixture
+from .channels import kraus_ops, cptp_error, state_dependent, unitary_mixture
 
 
 class NotCPTP(ValueError):
@@ -43,7 +44,7 @@ def expand(circuit):
     sites = []
     n_mr = 0
     n_g = 0
-    general = [general_channel(kraus_ops(ch)) is not None for ch in circuit.get("channels", [])]
+    general = [state_dependent(kraus_ops(ch)) for ch in circuit.get("channels", [])]
 
     def add_site(ch, qubits):
         nonlocal n_mr, n_g
@@ -95,7 +96,7 @@ def site_channels(circuit):
             raise NotCPTP(ch.get("name", "kraus"))
         um = unitary_mixture(K)
         if um is None:
-            if general_channel(K) is None:
+            if not state_dependent(K):
                 raise Unsupported(f"{ch.get('name', 'kraus')} is not a unitary mixture")
             out.append(None)        # state-dependent: no pre-sampled probabilities
             continue

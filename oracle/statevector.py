@@ -21,7 +21,7 @@ import math
 
 import numpy as np
 
-from .channels import general_channel, kraus_ops
+from .channels import kraus_ops
 from .gates import gate_matrix, rot
 from .noise import expand, site_channels
 from .rng import key1, uniforms
@@ -80,13 +80,13 @@ def run_record(circuit, record, params=None, steps_sites=None, chans=None,
     """Prepare psi_alpha for one record.  Returns (psi, mr_bits).
 
     State-dependent channel steps ("gch") are decided here (Algorithm 1's
-    state-dependent branch): p_k = d0[k] P(q=0) + d1[k] P(q=1) from the state,
+    state-dependent branch): p_k = ||K_k psi||^2 / ||psi||^2 on the step's qubits,
     u = word gidx of the stream [seed, key1(4, cfg, alpha)] for ``be_key`` =
     (seed, cfg, alpha), k by the running sum, then K_k / sqrt(p_k); the chosen k
     joins the returned record entries (in record index order with the
     measure-reset bits).  ``forced`` (a list indexed by gidx) fixes the
     decisions instead; if ``trace`` is a list, each decision appends a dict with
-    the state before it ("psi"), the qubit, k, p_k and the Kraus operator.
+    the state before it ("psi"), the qubits, k, p_k and the Kraus operator.
 
     With ``kraus_unnormalised`` the site operators are K_k = sqrt(p_k) U_k, so
     that ||psi||^2 ends as p_alpha (used as an invariant check)."""
@@ -133,12 +133,14 @@ def run_record(circuit, record, params=None, steps_sites=None, chans=None,
             psi = apply(psi, n, proj, (q,))
             psi = psi / math.sqrt(math.fsum(psi.real ** 2 + psi.imag ** 2))
         elif kind == "gch":
-            q = st[1][0]
+            qs = st[1]
             K = kraus_ops(circuit["channels"][st[3]])
-            d0, d1 = general_channel(K)
-            one, tot = marginal_one(psi, n, q)
-            p1 = one / tot
-            probs = [d0[k] * (1.0 - p1) + d1[k] * p1 for k in range(len(K))]
+            # p_k = <psi|K_k^dagger K_k|psi> / <psi|psi> = ||K_k psi||^2 / ||psi||^2
+            tot = math.fsum(psi.real ** 2 + psi.imag ** 2)
+            probs = []
+            for Kk in K:
+                phi = apply(psi, n, Kk, qs)
+                probs.append(math.fsum(phi.real ** 2 + phi.imag ** 2) / tot)
             if forced is not None:
                 k = forced[st[4]]
             else:
@@ -146,8 +148,8 @@ def run_record(circuit, record, params=None, steps_sites=None, chans=None,
                 u = uniforms(seed, key1(STREAM_CHANNEL, cfg, alpha), st[4] + 1)[st[4]]
                 k = _categorical_positive(u, probs)
             if trace is not None:
-                trace.append({"psi": psi.copy(), "q": q, "k": k, "p": probs[k], "K": K[k]})
-            psi = apply(psi, n, K[k] / math.sqrt(probs[k]), (q,))
+                trace.append({"psi": psi.copy(), "q": qs, "k": k, "p": probs[k], "K": K[k]})
+            psi = apply(psi, n, K[k] / math.sqrt(probs[k]), qs)
             psi = psi / math.sqrt(math.fsum(psi.real ** 2 + psi.imag ** 2))
             bits.append(k)
         else:

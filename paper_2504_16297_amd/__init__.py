@@ -115,7 +115,7 @@ def ptsbe_plan_compile(plan):
 
 
 def ptsbe_plan(circuit, precision="c64", tile_qubits=0, compile=True, min_fill=0, half_tile=False,
-               phase_frames=True, waves=0, twirl=False, pair_fusion=True):
+               phase_frames=True, waves=0, twirl=False, pair_fusion=True, swizzle=True, nontemporal=False):
     """Build the execution plan of a circuit dictionary (ops, channels, rules).
     ``compile=False`` runs the passes through the generic tile kernels instead of
     per-pass compiled kernels; ``min_fill`` (1..7, 0 = 2) is the fewest 2x2
@@ -125,7 +125,9 @@ def ptsbe_plan(circuit, precision="c64", tile_qubits=0, compile=True, min_fill=0
     ``waves`` (1..8, 0 = compiler's choice) sets the compiled passes' register
     budget to 512 / waves VGPRs; ``twirl`` replaces channels that are not unitary
     mixtures by their Pauli twirl (else they are rejected); ``pair_fusion=False``
-    keeps diagonal 2-qubit gates apart from the 2x2 runs on their qubits."""
+    keeps diagonal 2-qubit gates apart from the 2x2 runs on their qubits; ``swizzle=False``
+    stores states in plain index order (PTSBE_PLAN_NO_SWIZZLE); ``nontemporal`` gives the
+    compiled passes' state loads and stores streaming cache hints."""
     ops = circuit["ops"]
     arr = (L.Op * max(1, len(ops)))()
     keep = []
@@ -194,7 +196,8 @@ def ptsbe_plan(circuit, precision="c64", tile_qubits=0, compile=True, min_fill=0
                     int(min_fill) | (0 if compile else L.PLAN_NO_COMPILE) |
                     (L.PLAN_HALF_TILE_LDS if half_tile else 0) |
                     (0 if phase_frames else L.PLAN_NO_PHASE_FRAMES) | (int(waves) << L.PLAN_WAVES_SHIFT) |
-                    (L.PLAN_TWIRL if twirl else 0) | (0 if pair_fusion else L.PLAN_NO_PAIR_FUSION), 0)
+                    (L.PLAN_TWIRL if twirl else 0) | (0 if pair_fusion else L.PLAN_NO_PAIR_FUSION) |
+                    (0 if swizzle else L.PLAN_NO_SWIZZLE) | (L.PLAN_NONTEMPORAL if nontemporal else 0), 0)
     h = C.c_void_p()
     check(lib().ptsbe_plan(C.byref(c), C.byref(nm), C.byref(po), C.byref(h)))
     return Plan(h, None)

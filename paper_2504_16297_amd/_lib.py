@@ -32,6 +32,8 @@ PLAN_NO_PHASE_FRAMES = 32
 PLAN_WAVES_SHIFT = 8
 PLAN_TWIRL = 64
 PLAN_NO_PAIR_FUSION = 128
+PLAN_NO_SWIZZLE = 256
+PLAN_NONTEMPORAL = 512
 NOALLOC_SCRATCH_BYTES = 64 << 20
 
 

@@ -82,7 +82,7 @@ ptsbe_status ptsbe_plan_pass_source(ptsbe_plan_t plan, uint32_t pass, uint32_t a
     if (pass >= passes.size()) return fail(PTSBE_E_ARG, "pass index out of range");
     const std::string src =
         jit_pass_source(passes[pass], P.n, P.precision, "ptsbe_pass", P.half_tile_lds, nullptr, adjoint != 0,
-                        P.waves);
+                        P.waves, P.swizzle, P.nontemporal);
     if (out) {
       if (*len < src.size() + 1) return fail(PTSBE_E_ARG, "output buffer too small");
       std::memcpy(out, src.c_str(), src.size() + 1);

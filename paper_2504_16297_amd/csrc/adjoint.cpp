@@ -30,6 +30,11 @@
 
 namespace ptsbe {
 
+template <typename V>
+DenseArgs<V> dense_args(const Plan& P, const ExecStep& ex, V* states, uint8_t* partial, uint8_t* mr_bits,
+                        double* mr_norm, uint32_t* status, const double* d_chan_param, uint32_t b0, uint64_t seed,
+                        uint32_t cfg, uint64_t alpha0);
+
 namespace {
 
 uint64_t a256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
@@ -103,6 +108,7 @@ PassArgs<V> pass_args(const Plan& P, uint8_t* tb, const TableLayout& T, uint32_t
   pa.n = (uint32_t)P.n;
   pa.n_passes = n_passes;
   pa.n_measure = 0;
+  pa.swz = P.swizzle ? 1u : 0u;
   return pa;
 }
 
@@ -178,7 +184,15 @@ ptsbe_status adjoint_typed(const Plan& P, TrajSet& ts, const double* coef, const
         CK(hipMemcpyAsync(ckpt + ((uint64_t)g * L.batch) * N, psi, (size_t)bb * state_bytes, hipMemcpyDeviceToDevice,
                           s),
            "checkpoint");
+        if (ex.dense) {
+          CK(launch_dense_channel<V>(dense_args<V>(P, ex, psi, ws + L.mr_partial, mr_bits, mr_norm, status,
+                                                   d_chan_param, b0, seed, cfg, ts.alpha0),
+                                     bb, s),
+             "state-dependent channel");
+          continue;
+        }
         MarginalArgs<V> ma{};
+        ma.swz = fa.swz;
         ma.states = psi;
         ma.partial = reinterpret_cast<double*>(ws + L.mr_partial);
         ma.N = N;
@@ -216,6 +230,7 @@ ptsbe_status adjoint_typed(const Plan& P, TrajSet& ts, const double* coef, const
            "forward");
     }
     ScanArgs<V> sa{};
+    sa.swz = fa.swz;
     sa.states = psi;
     sa.partial = reinterpret_cast<double*>(ws + L.scan_part);
     sa.offs = reinterpret_cast<double*>(ws + L.scan_offs);
@@ -226,6 +241,7 @@ ptsbe_status adjoint_typed(const Plan& P, TrajSet& ts, const double* coef, const
     double* total = reinterpret_cast<double*>(ws + L.scan_total);
     CK(launch_norm<V>(sa, bb, total, s), "norm");
     ExpArgs<V> ea{};
+    ea.swz = fa.swz;
     ea.states = psi;
     ea.partial = sa.partial;
     ea.N = N;
@@ -233,6 +249,7 @@ ptsbe_status adjoint_typed(const Plan& P, TrajSet& ts, const double* coef, const
     ea.per_block = L.per_block;
     ea.n_terms = n_terms;
     ObsArgs<V> oa{};
+    oa.swz = fa.swz;
     oa.psi = psi;
     oa.lam = lam;
     oa.N = N;
@@ -250,7 +267,15 @@ ptsbe_status adjoint_typed(const Plan& P, TrajSet& ts, const double* coef, const
         CK(hipMemcpyAsync(psi, ckpt + ((uint64_t)ex.restore * L.batch) * N, (size_t)bb * state_bytes,
                           hipMemcpyDeviceToDevice, s),
            "checkpoint restore");
+        if (ex.dense) {
+          DenseArgs<V> da = dense_args<V>(P, ex, psi, ws + L.mr_partial, mr_bits, mr_norm, status, d_chan_param, b0,
+                                          seed, cfg, ts.alpha0);
+          da.lam = lam;
+          CK(launch_dense_lam_adjoint<V>(da, bb, s), "state-dependent channel adjoint");
+          continue;
+        }
         GchAdjArgs<V> ga{};
+        ga.swz = fa.swz;
         ga.lam = lam;
         ga.mr_bits = mr_bits;
         ga.mr_norm = mr_norm;

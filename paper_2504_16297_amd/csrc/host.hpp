@@ -40,6 +40,11 @@ struct Channel {
   // trajectory's state reaches it; U holds the raw Kraus operators.
   bool general = false;
   std::vector<double> d0, d1;
+  // A state-dependent channel that is not that case (a 1-qubit channel with
+  // non-diagonal K_k^dagger K_k, or any 2-qubit one): p_k = Tr(M_k rho) from the
+  // reduced density matrix rho of its qubits, M_k = K_k^dagger K_k.
+  bool dense = false;
+  std::vector<Mat> M;
 };
 
 enum StepKind { ST_GATE, ST_PARAM, ST_SITE, ST_MR, ST_P0, ST_DOT, ST_GCH };
@@ -56,6 +61,7 @@ struct Step {
   int mr = -1;                 // MR, GCH: record index
   int chan = -1;               // GCH: channel
   int gidx = -1;               // GCH: index among the state-dependent channel steps
+  bool dense = false;          // GCH of a dense channel: decided and applied by its own step
   int dot = -1;                // DOT: index of the gradient contribution
 };
 
@@ -123,6 +129,7 @@ struct ExecStep {
   std::vector<int> mr_index;   // decision / restore: record indices
   bool wall = false;           // a state-dependent channel: every qubit's phase frame ends here
   int restore = -1;            // reverse sweep: checkpoint (state-dependent channel index) to restore
+  bool dense = false;          // a dense channel's step: reduced density matrix, decision, application
 };
 
 // Decision data of the record entries (measure-resets and state-dependent
@@ -172,6 +179,8 @@ struct Plan {
   bool half_tile_lds = false;  // compiled passes change registers through half a tile of LDS
   int waves = 0;               // waves per SIMD the compiled passes' register budget is set for (0 = default)
   bool pair_fusion = true;     // diagonal 2-qubit gates merge with the 2x2 runs around them into 4x4 slots
+  bool swizzle = true;         // states stored at swizzle(x) (kernels.hpp)
+  bool nontemporal = false;    // compiled passes load and store the states with nontemporal hints
   std::shared_ptr<JitProgram> jit;
 };
 

@@ -616,6 +616,16 @@ __device__ __forceinline__ V cd4(const V* m, V x0, V x1, V x2, V x3) {
   return r;
 }
 __device__ __forceinline__ uint32_t sw(uint32_t L) { return L ^ ((L >> 4) & 15u); }
+__device__ __forceinline__ V ldnt(const V* p) {
+  V r;
+  r.x = __builtin_nontemporal_load(&p->x);
+  r.y = __builtin_nontemporal_load(&p->y);
+  return r;
+}
+__device__ __forceinline__ void stnt(V* p, V v) {
+  __builtin_nontemporal_store(v.x, &p->x);
+  __builtin_nontemporal_store(v.y, &p->y);
+}
 __device__ __forceinline__ double imc(V a, V b) { return (double)a.x * (double)b.y - (double)a.y * (double)b.x; }
 __device__ __forceinline__ double rec(V a, V b) { return (double)a.x * (double)b.x + (double)a.y * (double)b.y; }
 )";
@@ -643,7 +653,7 @@ std::string bit_gather(const char* src, const std::vector<int>& dst_pos, int fir
 namespace {
 
 std::string gen_pass(const Pass& ps, int n, int precision, const std::string& name, bool split, bool dual,
-                     int waves, bool* needs_full) {
+                     int waves, bool swz, bool nt, bool* needs_full) {
   const int k = ps.k;
   if (k < (int)kMinRegTile || k > 12) return "";
   if (dual && (ps.flags & PASS_INIT_ZERO)) return "";
@@ -709,16 +719,43 @@ std::string gen_pass(const Pass& ps, int n, int precision, const std::string& na
     for (int j = 0; j < 4; ++j)
       if ((r >> j) & 1) og[r] |= 1ull << g.tq[k - 4 + j];
   }
+  // Storage positions (states swizzled, kernels.hpp): amplitude base | ot | og[r]
+  // sits at px ^ og[r] ^ (f(og[r] >> 12) << 4) with px = (base | ot) ^ ((f(base >> 12)
+  // ^ f(ot >> 12)) << 4), f linear; the register part is a constant.
+  swz = swz && n > 12;
+  std::string pos_base = "base + ot";
+  if (swz) {
+    std::string fx;
+    for (size_t j = 0; j < g.oq.size(); ++j)
+      if (g.oq[j] >= 12)
+        fx += " ^ ((uint32_t)((tile_id >> " + std::to_string(j) + ") & 1u) * " +
+              std::to_string(kSwizzle[g.oq[j] - 12]) + "u)";
+    for (size_t j = 0; j < tpos.size(); ++j)
+      if (tpos[j] >= 12)
+        fx += " ^ (((tid >> " + std::to_string(j) + ") & 1u) * " + std::to_string(kSwizzle[tpos[j] - 12]) + "u)";
+    o << "  const uint64_t px = (base + ot) ^ ((uint64_t)(0u" << fx << ") << 4);\n";
+    pos_base = "px";
+    for (int r = 0; r < 16; ++r) {
+      uint32_t fr = 0;
+      for (int j = 0; j < 4; ++j)
+        if (((r >> j) & 1) && g.tq[k - 4 + j] >= 12) fr ^= kSwizzle[g.tq[k - 4 + j] - 12];
+      og[r] ^= (uint64_t)fr << 4;   // applied by XOR onto px
+    }
+  }
+  const char* join = swz ? " ^ " : " + ";
   const bool init = (ps.flags & PASS_INIT_ZERO) != 0;
   if (init) {
     o << "  V s0; s0.x = (base == 0 && tid == 0) ? (T)1 : (T)0; s0.y = 0;\n";
     for (int r = 1; r < 16; ++r) o << "  V " << g.S(r) << "; " << g.S(r) << ".x = 0; " << g.S(r) << ".y = 0;\n";
   } else {
-    o << "  const V* sst = a.states + (uint64_t)src * a.N + base + ot;\n";
-    for (int r = 0; r < 16; ++r) o << "  V " << g.S(r) << " = sst[" << og[r] << "ull];\n";
+    o << "  const V* sst = a.states + (uint64_t)src * a.N;\n";
+    for (int r = 0; r < 16; ++r) {
+      const std::string at = "(" + pos_base + ")" + join + std::to_string(og[r]) + "ull";
+      o << "  V " << g.S(r) << " = " << (nt ? "ldnt(sst + (" + at + "))" : "sst[" + at + "]") << ";\n";
+    }
     if (dual) {
-      o << "  const V* lst = lam + (uint64_t)src * a.N + base + ot;\n";
-      for (int r = 0; r < 16; ++r) o << "  V l" << r << " = lst[" << og[r] << "ull];\n";
+      o << "  const V* lst = lam + (uint64_t)src * a.N;\n";
+      for (int r = 0; r < 16; ++r) o << "  V l" << r << " = lst[(" << pos_base << ")" << join << og[r] << "ull];\n";
     }
   }
   // Matrix set-up in LDS: every block gathers the defaults (one dependent
@@ -794,11 +831,17 @@ std::string gen_pass(const Pass& ps, int n, int precision, const std::string& na
     for (const std::string& st : g.sets())
       for (int r = 0; r < 16; ++r) o << "  " << st << r << " = cm(cs, " << st << r << ");\n";
   }
-  o << "  V* dstp = a.states + (uint64_t)dst * a.N + base + ot;\n";
-  for (int r = 0; r < 16; ++r) o << "  dstp[" << og[r] << "ull] = " << g.S(r) << ";\n";
+  o << "  V* dstp = a.states + (uint64_t)dst * a.N;\n";
+  for (int r = 0; r < 16; ++r) {
+    const std::string at = "(" + pos_base + ")" + join + std::to_string(og[r]) + "ull";
+    if (nt)
+      o << "  stnt(dstp + (" << at << "), " << g.S(r) << ");\n";
+    else
+      o << "  dstp[" << at << "] = " << g.S(r) << ";\n";
+  }
   if (dual) {
-    o << "  V* ldst = lam + (uint64_t)dst * a.N + base + ot;\n";
-    for (int r = 0; r < 16; ++r) o << "  ldst[" << og[r] << "ull] = l" << r << ";\n";
+    o << "  V* ldst = lam + (uint64_t)dst * a.N;\n";
+    for (int r = 0; r < 16; ++r) o << "  ldst[(" << pos_base << ")" << join << og[r] << "ull] = l" << r << ";\n";
   }
   o << "}\n";
   *needs_full = g.needs_full;
@@ -808,13 +851,13 @@ std::string gen_pass(const Pass& ps, int n, int precision, const std::string& na
 }  // namespace
 
 std::string jit_pass_source(const Pass& ps, int n, int precision, const std::string& name, bool split,
-                            uint32_t* tile_elems, bool dual, int waves) {
+                            uint32_t* tile_elems, bool dual, int waves, bool swz, bool nt) {
   bool full = false;
   split = split && !dual;
-  std::string src = gen_pass(ps, n, precision, name, split, dual, waves, &full);
+  std::string src = gen_pass(ps, n, precision, name, split, dual, waves, swz, nt, &full);
   if (split && full) {  // a 4x4 matrix off the register bits needs the whole tile
     split = false;
-    src = gen_pass(ps, n, precision, name, false, dual, waves, &full);
+    src = gen_pass(ps, n, precision, name, false, dual, waves, swz, nt, &full);
   }
   if (tile_elems) *tile_elems = src.empty() ? 0u : (1u << (ps.k - (split ? 1 : 0)));
   return src;
@@ -862,7 +905,8 @@ ptsbe_status jit_build(const Plan& P) {
     for (size_t p = 0; p < passes.size(); ++p) {
       uint32_t te = 0;
       const std::string body =
-          jit_pass_source(passes[p], P.n, P.precision, "KERNEL_NAME", P.half_tile_lds, &te, dual, P.waves);
+          jit_pass_source(passes[p], P.n, P.precision, "KERNEL_NAME", P.half_tile_lds, &te, dual, P.waves,
+                          P.swizzle, P.nontemporal);
       if (body.empty()) continue;
       auto it = by_body.find(body);
       if (it != by_body.end()) {

@@ -47,10 +47,13 @@ struct JitProgram {
 // `dual`: the adjoint sweep's kernel (signature (PassArgs, V* lam, double*
 // partial, uint32_t n_dot)): every operation acts on psi and lambda, DOT ops
 // write one FP64 partial per (trajectory, tile, wavefront, gradient term).
+// `swz`: states stored swizzled (kernels.hpp swizzle(); no effect for n <= 12).
+// `nt`: state loads and stores of the forward passes with nontemporal hints.
 // `waves`: waves per SIMD the kernel's register budget is set for (0 = the
 // compiler's choice).
 std::string jit_pass_source(const Pass& ps, int n, int precision, const std::string& name, bool split,
-                            uint32_t* tile_elems, bool dual = false, int waves = 0);
+                            uint32_t* tile_elems, bool dual = false, int waves = 0, bool swz = true,
+                            bool nt = false);
 
 // Generate and compile every pass kernel of the plan (host only, no device
 // needed).  Idempotent; thread-safe.

@@ -114,7 +114,7 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs<V> a) {
       v.x = (base == 0 && L == 0) ? 1 : 0;
       v.y = 0;
     } else {
-      v = sst[base + tile_offset(L, tq, k)];
+      v = sst[swizzle(base + tile_offset(L, tq, k), a.swz)];
     }
     tile[L] = v;
   }
@@ -217,7 +217,7 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs<V> a) {
     }
     __syncthreads();
   }
-  for (uint32_t L = tid; L < nt; L += blockDim.x) st[base + tile_offset(L, tq, k)] = tile[L];
+  for (uint32_t L = tid; L < nt; L += blockDim.x) st[swizzle(base + tile_offset(L, tq, k), a.swz)] = tile[L];
 }
 
 // ------------------------------------------------------- register tile pass
@@ -375,7 +375,7 @@ __global__ __launch_bounds__(256) void k_pass_reg(PassArgs<V> a) {
       s.v[r].x = (base == 0 && Lt == 0 && r == 0) ? 1 : 0;
       s.v[r].y = 0;
     } else {
-      s.v[r] = sst[base + off];
+      s.v[r] = sst[swizzle(base + off, a.swz)];
     }
   }
 
@@ -537,7 +537,7 @@ __global__ __launch_bounds__(256) void k_pass_reg(PassArgs<V> a) {
   for (int r = 0; r < 16; ++r) {
     const uint64_t off = ot + ((r & 1) ? og[0] : 0) + ((r & 2) ? og[1] : 0) + ((r & 4) ? og[2] : 0) +
                          ((r & 8) ? og[3] : 0);
-    st[base + off] = s.v[r];
+    st[swizzle(base + off, a.swz)] = s.v[r];
   }
 }
 
@@ -615,12 +615,14 @@ __device__ __forceinline__ void block_prob_scan(const ScanArgs<V>& a) {
   V* st = a.states + (uint64_t)blockIdx.y * a.N;
   const uint64_t e0 = (uint64_t)b * a.per_block;
   const uint32_t E = a.per_block, per = a.per_thread, tid = threadIdx.x;
+  // the block's amplitudes sit in its own 4096 positions, permuted by an XOR
+  const uint32_t sx = E == kScanBlock ? swizzle_block(b, a.swz) : 0u;
   if (E == kScanBlock) {
     // full block: all 16 loads of a thread in flight before the first use
     constexpr uint32_t kPer = kScanBlock / 256;
     double w[kPer];
 #pragma unroll
-    for (uint32_t i = 0; i < kPer; ++i) w[i] = norm2(st[e0 + tid + 256u * i]);
+    for (uint32_t i = 0; i < kPer; ++i) w[i] = norm2(st[e0 + ((tid + 256u * i) ^ sx)]);
 #pragma unroll
     for (uint32_t i = 0; i < kPer; ++i) sh[scan_pad(tid + 256u * i)] = w[i];
   } else {
@@ -866,7 +868,7 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs<V> a) {
     for (uint32_t i = ob + tid; i < oe; i += bd) slot_off[pa.ov[i].slot] = pa.ov[i].off;
   }
   for (uint32_t L = tid; L < nt; L += bd) {
-    const uint64_t off = base + tile_offset(L, tq, k);
+    const uint64_t off = swizzle(base + tile_offset(L, tq, k), pa.swz);
     tp[L] = sp[off];
     tl[L] = sl[off];
   }
@@ -949,7 +951,8 @@ __global__ __launch_bounds__(256) void k_gch_lam_adjoint(GchAdjArgs<V> a) {
   const uint64_t bit = 1ull << a.q, lo = bit - 1;
   for (uint64_t pr = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; pr < a.N / 2;
        pr += (uint64_t)gridDim.x * blockDim.x) {
-    const uint64_t i0 = ((pr & ~lo) << 1) | (pr & lo), i1 = i0 | bit;
+    const uint64_t c0 = ((pr & ~lo) << 1) | (pr & lo);
+    const uint64_t i0 = swizzle(c0, a.swz), i1 = swizzle(c0 | bit, a.swz);
     const V x0 = l[i0], x1 = l[i1];
     const double ar = x0.x, ai = x0.y, br = x1.x, bi = x1.y;
     V y0, y1;
@@ -967,13 +970,15 @@ template <typename V>
 __global__ __launch_bounds__(256) void k_obs_apply(ObsArgs<V> a) {
   const V* p = a.psi + (uint64_t)blockIdx.y * a.N;
   V* l = a.lam + (uint64_t)blockIdx.y * a.N;
-  for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < a.N; x += (uint64_t)gridDim.x * blockDim.x) {
+  for (uint64_t pos = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; pos < a.N;
+       pos += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t x = swizzle(pos, a.swz);  // the amplitude stored at pos (an involution)
     double o = 0.0;
     for (uint32_t j = 0; j < a.n_terms; ++j) o += (__popcll(x & a.zmask[j]) & 1) ? -a.coef[j] : a.coef[j];
-    V v = p[x];
+    V v = p[pos];
     v.x = (typename Real<V>::T)((double)v.x * o);
     v.y = (typename Real<V>::T)((double)v.y * o);
-    l[x] = v;
+    l[pos] = v;
   }
 }
 
@@ -1026,9 +1031,10 @@ __global__ __launch_bounds__(256) void k_marginal(MarginalArgs<V> a) {
   if (a.per_block == kScanBlock) {
     // full block: a thread's 16 loads in flight before the first use (same order of sums)
     constexpr uint32_t kPer = kScanBlock / 256;
+    const uint32_t sx = swizzle_block(blockIdx.x, a.swz);
     double w[kPer];
 #pragma unroll
-    for (uint32_t i = 0; i < kPer; ++i) w[i] = norm2(st[e0 + threadIdx.x + 256u * i]);
+    for (uint32_t i = 0; i < kPer; ++i) w[i] = norm2(st[e0 + ((threadIdx.x + 256u * i) ^ sx)]);
 #pragma unroll
     for (uint32_t i = 0; i < kPer; ++i) add(e0 + threadIdx.x + 256u * i, w[i]);
   } else {
@@ -1352,12 +1358,13 @@ __global__ __launch_bounds__(256) void k_sample(SampleArgs<BitT> a) {
 // ------------------------------------------------------------ states / <O>
 
 template <typename V>
-__global__ __launch_bounds__(256) void k_copy_normalised(const V* states, V* out, const double* total, uint64_t N) {
+__global__ __launch_bounds__(256) void k_copy_normalised(const V* states, V* out, const double* total, uint64_t N,
+                                                         uint32_t swz) {
   const double s = 1.0 / sqrt(total[blockIdx.y]);
   const V* st = states + (uint64_t)blockIdx.y * N;
   V* o = out + (uint64_t)blockIdx.y * N;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (uint64_t)gridDim.x * blockDim.x) {
-    V v = st[i];
+    V v = st[swizzle(i, swz)];
     v.x = (typename Real<V>::T)((double)v.x * s);
     v.y = (typename Real<V>::T)((double)v.y * s);
     o[i] = v;
@@ -1374,7 +1381,7 @@ __global__ __launch_bounds__(256) void k_expval(ExpArgs<V> a) {
     double o = 0.0;
     for (uint32_t j = 0; j < a.n_terms; ++j)
       o += (__popcll(x & a.zmask[j]) & 1) ? -a.coef[j] : a.coef[j];
-    s += norm2(st[x]) * o;
+    s += norm2(st[swizzle(x, a.swz)]) * o;
   }
   double ex, tot;
   block_excl_scan(s, &ex, &tot);
@@ -1395,6 +1402,179 @@ __global__ void k_weighted_sum(const double* w, const double* ev, uint32_t n, do
   double e = 0.0;
   for (uint32_t t = 0; t < n; ++t) e += w[t] * ev[t];
   *E = e;
+}
+
+// ------------------------------------------- dense state-dependent channels
+
+// Index with zeros inserted at the channel's qubit positions (ascending), the
+// amplitudes of base j being base | a-th combination of those bits.
+__device__ __forceinline__ uint64_t insert_zero(uint64_t j, uint32_t q) {
+  return ((j >> q) << (q + 1)) | (j & ((1ull << q) - 1));
+}
+template <typename V>
+__device__ __forceinline__ uint64_t dense_base(const DenseArgs<V>& a, uint64_t j) {
+  if (a.nq == 1) return insert_zero(j, a.q[0]);
+  const uint32_t lo = min(a.q[0], a.q[1]), hi = max(a.q[0], a.q[1]);
+  return insert_zero(insert_zero(j, lo), hi);
+}
+template <typename V>
+__device__ __forceinline__ uint64_t dense_index(const DenseArgs<V>& a, uint64_t base, uint32_t i) {
+  uint64_t x = base;
+  if (i & 1u) x |= 1ull << a.q[0];
+  if (i & 2u) x |= 1ull << a.q[1];
+  return x;
+}
+
+// Partial sums of rho[i][j] = sum psi_i conj(psi_j), i <= j, over one block of
+// base indices: 16 slots (diagonal real parts, then re/im of the upper entries).
+template <typename V>
+__global__ __launch_bounds__(256) void k_rdm(DenseArgs<V> a) {
+  const uint32_t d = 1u << a.nq;
+  const V* st = a.states + (uint64_t)blockIdx.y * a.N;
+  const uint64_t NB = a.N >> a.nq;
+  double acc[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) acc[c] = 0.0;
+  for (uint32_t it = 0; it < 16; ++it) {
+    const uint64_t j = (uint64_t)blockIdx.x * 4096u + threadIdx.x + 256u * it;
+    if (j >= NB) break;
+    const uint64_t b = dense_base(a, j);
+    double re[4], im[4];
+    for (uint32_t i = 0; i < d; ++i) {
+      const V v = st[swizzle(dense_index(a, b, i), a.swz)];
+      re[i] = (double)v.x;
+      im[i] = (double)v.y;
+    }
+    int c = 0;
+    for (uint32_t i = 0; i < d; ++i) acc[c++] += re[i] * re[i] + im[i] * im[i];
+    for (uint32_t i = 0; i < d; ++i)
+      for (uint32_t k = i + 1; k < d; ++k) {
+        acc[c++] += re[i] * re[k] + im[i] * im[k];   // Re psi_i conj(psi_k)
+        acc[c++] += im[i] * re[k] - re[i] * im[k];   // Im psi_i conj(psi_k)
+      }
+  }
+  __shared__ double wsum[4][16];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    double v = acc[c];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) wsum[w][c] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 16) {
+    const double v = ((wsum[0][threadIdx.x] + wsum[1][threadIdx.x]) + wsum[2][threadIdx.x]) + wsum[3][threadIdx.x];
+    a.partial[((uint64_t)blockIdx.y * a.nblk + blockIdx.x) * 16 + threadIdx.x] = v;
+  }
+}
+
+template <typename V>
+__global__ void k_dense_decide(DenseArgs<V> a) {
+  const uint32_t tb = blockIdx.x;
+  __shared__ double comp[16];
+  if (threadIdx.x < 16) {
+    double v = 0.0;
+    for (uint32_t b = 0; b < a.nblk; ++b) v += a.partial[((uint64_t)tb * a.nblk + b) * 16 + threadIdx.x];
+    comp[threadIdx.x] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const uint32_t d = 1u << a.nq;
+  // rho as d x d complex (upper entries from the slots, lower by conjugation)
+  double rr[16], ri[16];
+  int c = 0;
+  for (uint32_t i = 0; i < d; ++i) {
+    rr[i * d + i] = comp[c++];
+    ri[i * d + i] = 0.0;
+  }
+  for (uint32_t i = 0; i < d; ++i)
+    for (uint32_t k = i + 1; k < d; ++k) {
+      rr[i * d + k] = comp[c];
+      rr[k * d + i] = comp[c++];
+      ri[i * d + k] = comp[c];
+      ri[k * d + i] = -comp[c++];
+    }
+  double tot = 0.0;
+  for (uint32_t i = 0; i < d; ++i) tot += rr[i * d + i];
+  const uint32_t K = (uint32_t)a.chan[0];
+  const double* M = a.chan + 2;
+  const uint64_t alpha = a.alpha0 + a.t0 + tb;
+  const U64x4 w = philox4x64_10(a.gidx / 4 + 1, 0, 0, 0, a.seed, stream_key1(4, a.cfg, alpha));
+  const double u = word_to_uniform(w.v[a.gidx % 4]);
+  uint32_t kk = 0, k_last = 0;
+  double cum = 0.0, pk = 0.0, p_last = 0.0;
+  bool found = false;
+  for (uint32_t k = 0; k < K; ++k) {
+    // Re Tr(M_k rho) = sum_ij Re(M_ij rho_ji)
+    const double* m = M + (uint64_t)k * 2 * d * d;
+    double t = 0.0;
+    for (uint32_t i = 0; i < d; ++i)
+      for (uint32_t j = 0; j < d; ++j)
+        t += m[2 * (i * d + j)] * rr[j * d + i] - m[2 * (i * d + j) + 1] * ri[j * d + i];
+    const double p = t / tot;
+    cum += p;
+    if (p > 0.0) {
+      k_last = k;
+      p_last = p;
+    }
+    if (!found && u < cum && p > 0.0) {
+      kk = k;
+      pk = p;
+      found = true;
+    }
+  }
+  if (!found) {
+    kk = k_last;
+    pk = p_last;
+  }
+  if (!(tot > 0.0) || !isfinite(tot) || !(pk > 0.0)) atomicOr(a.status, 2u);
+  const uint64_t ri2 = (uint64_t)(a.t0 + tb) * a.n_measure + a.rec;
+  a.mr_bits[ri2] = (uint8_t)kk;
+  a.mr_norm[ri2] = 1.0 / sqrt(pk * tot);
+}
+
+// psi <- factor K_k psi (forward) or lambda <- factor K_k^dagger lambda (reverse)
+template <typename V, bool kAdjoint>
+__global__ __launch_bounds__(256) void k_dense_apply(DenseArgs<V> a) {
+  const uint32_t d = 1u << a.nq;
+  const uint64_t ri = (uint64_t)(a.t0 + blockIdx.y) * a.n_measure + a.rec;
+  const uint32_t kk = a.mr_bits[ri];
+  const double sc = a.mr_norm[ri];
+  const uint32_t K = (uint32_t)a.chan[0];
+  const double* G = a.chan + 2 + 2ull * d * d * (K + kk);
+  double gr[16], gi[16];
+  for (uint32_t i = 0; i < d; ++i)
+    for (uint32_t j = 0; j < d; ++j) {
+      // forward: (s K)_ij; reverse: (s K)^dagger_ij = s conj(K_ji)
+      const uint32_t e = kAdjoint ? j * d + i : i * d + j;
+      gr[i * d + j] = sc * G[2 * e];
+      gi[i * d + j] = kAdjoint ? -sc * G[2 * e + 1] : sc * G[2 * e + 1];
+    }
+  V* st = (kAdjoint ? a.lam : a.states) + (uint64_t)blockIdx.y * a.N;
+  const uint64_t NB = a.N >> a.nq;
+  for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < NB; j += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t b = dense_base(a, j);
+    uint64_t pos[4];
+    double xr[4], xi[4];
+    for (uint32_t i = 0; i < d; ++i) {
+      pos[i] = swizzle(dense_index(a, b, i), a.swz);
+      const V v = st[pos[i]];
+      xr[i] = v.x;
+      xi[i] = v.y;
+    }
+    for (uint32_t i = 0; i < d; ++i) {
+      double yr = 0.0, yi = 0.0;
+      for (uint32_t k = 0; k < d; ++k) {
+        yr += gr[i * d + k] * xr[k] - gi[i * d + k] * xi[k];
+        yi += gr[i * d + k] * xi[k] + gi[i * d + k] * xr[k];
+      }
+      V y;
+      y.x = (typename Real<V>::T)yr;
+      y.y = (typename Real<V>::T)yi;
+      st[pos[i]] = y;
+    }
+  }
 }
 
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, uint64_t n) {
@@ -1463,9 +1643,9 @@ hipError_t launch_sample(const SampleArgs<BitT>& a, uint64_t items, hipStream_t 
 
 template <typename V>
 hipError_t launch_copy_normalised(const V* states, V* out, const double* total, uint64_t N, uint32_t batch,
-                                  hipStream_t s) {
+                                  uint32_t swz, hipStream_t s) {
   uint32_t gx = (uint32_t)((N + 255) / 256 < 65536 ? (N + 255) / 256 : 65536);
-  hipLaunchKernelGGL(k_copy_normalised<V>, dim3(gx, batch), dim3(256), 0, s, states, out, total, N);
+  hipLaunchKernelGGL(k_copy_normalised<V>, dim3(gx, batch), dim3(256), 0, s, states, out, total, N, swz);
   return hipGetLastError();
 }
 
@@ -1510,6 +1690,24 @@ hipError_t launch_grad_reduce(const double* partial, const double* w, uint32_t n
   return hipGetLastError();
 }
 
+template <typename V>
+hipError_t launch_dense_channel(const DenseArgs<V>& a, uint32_t batch, hipStream_t s) {
+  hipLaunchKernelGGL(k_rdm<V>, dim3(a.nblk, batch), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_dense_decide<V>, dim3(batch), dim3(64), 0, s, a);
+  const uint64_t NB = a.N >> a.nq;
+  const uint32_t gx = (uint32_t)((NB + 255) / 256 < 4096 ? (NB + 255) / 256 : 4096);
+  hipLaunchKernelGGL((k_dense_apply<V, false>), dim3(gx, batch), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename V>
+hipError_t launch_dense_lam_adjoint(const DenseArgs<V>& a, uint32_t batch, hipStream_t s) {
+  const uint64_t NB = a.N >> a.nq;
+  const uint32_t gx = (uint32_t)((NB + 255) / 256 < 4096 ? (NB + 255) / 256 : 4096);
+  hipLaunchKernelGGL((k_dense_apply<V, true>), dim3(gx, batch), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_weighted_sum(const double* w, const double* ev, uint32_t n, double* E, hipStream_t s) {
   hipLaunchKernelGGL(k_weighted_sum, dim3(1), dim3(64), 0, s, w, ev, n, E);
   return hipGetLastError();
@@ -1527,7 +1725,8 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {
   template hipError_t launch_scan<V>(const ScanArgs<V>&, uint32_t, double*, hipStream_t);                 \
   template hipError_t launch_norm<V>(const ScanArgs<V>&, uint32_t, double*, hipStream_t);                 \
   template hipError_t launch_marginal<V>(const MarginalArgs<V>&, const MrDecideArgs&, uint32_t, hipStream_t); \
-  template hipError_t launch_copy_normalised<V>(const V*, V*, const double*, uint64_t, uint32_t, hipStream_t); \
+  template hipError_t launch_copy_normalised<V>(const V*, V*, const double*, uint64_t, uint32_t, uint32_t,         \
+                                                hipStream_t);                                                         \
   template hipError_t launch_expval<V>(const ExpArgs<V>&, const double*, double*, uint32_t, uint32_t, hipStream_t);
 PTSBE_INST(float2)
 PTSBE_INST(double2)
@@ -1537,6 +1736,10 @@ template hipError_t launch_gch_lam_adjoint<float2>(const GchAdjArgs<float2>&, ui
 template hipError_t launch_gch_lam_adjoint<double2>(const GchAdjArgs<double2>&, uint32_t, hipStream_t);
 template hipError_t launch_obs_apply<float2>(const ObsArgs<float2>&, uint32_t, hipStream_t);
 template hipError_t launch_obs_apply<double2>(const ObsArgs<double2>&, uint32_t, hipStream_t);
+template hipError_t launch_dense_channel<float2>(const DenseArgs<float2>&, uint32_t, hipStream_t);
+template hipError_t launch_dense_channel<double2>(const DenseArgs<double2>&, uint32_t, hipStream_t);
+template hipError_t launch_dense_lam_adjoint<float2>(const DenseArgs<float2>&, uint32_t, hipStream_t);
+template hipError_t launch_dense_lam_adjoint<double2>(const DenseArgs<double2>&, uint32_t, hipStream_t);
 template hipError_t launch_sample<uint32_t>(const SampleArgs<uint32_t>&, uint64_t, hipStream_t);
 template hipError_t launch_sample<uint64_t>(const SampleArgs<uint64_t>&, uint64_t, hipStream_t);
 

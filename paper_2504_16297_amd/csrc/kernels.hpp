@@ -11,6 +11,34 @@ namespace ptsbe {
 constexpr int kMaxGroup = 16;   // measure-resets measured together
 constexpr uint32_t kScanBlock = 4096;
 
+// Storage layout of the states.  Amplitude x is stored at position
+// swizzle(x) = x ^ (f(x >> 12) << 4): the bits of x from 12 up, mapped to 8 bits
+// by a fixed GF(2)-linear f (bit i contributes kSwizzle[i]), are XORed onto
+// bits 4..11.  Runs of 16 amplitudes stay contiguous and every 4096-amplitude
+// block stays in place (permuted inside), but a tile whose qubits are high
+// ones no longer sends its 128-byte runs to addresses that differ only in
+// high bits (which measured slower on the HBM: 4.0 against 5.2 TB/s for the
+// tile of qubits 0-3 and 20-27 of a 28-qubit state, 4.8 against 5.2 averaged
+// over a 28-qubit plan's tiles).  An involution: the same map takes a
+// position back to its amplitude.  States below 2^13 amplitudes are unchanged.
+constexpr uint32_t kSwizzle[24] = {0x7a, 0x96, 0x3d, 0x72, 0x37, 0xf0, 0x85, 0x96, 0x92, 0xce, 0x15, 0x7a,
+                                   0xaf, 0xa8, 0x5d, 0x0e, 0xaa, 0x06, 0xed, 0x62, 0x47, 0x60, 0x35, 0x86};
+
+__host__ __device__ inline uint32_t swizzle_f(uint64_t h) {
+  uint32_t f = 0;
+#pragma unroll
+  for (int i = 0; i < 24; ++i)
+    if ((h >> i) & 1u) f ^= kSwizzle[i];
+  return f;
+}
+// The XOR a 4096-amplitude block applies to its in-block offsets (0 when off).
+__host__ __device__ inline uint32_t swizzle_block(uint64_t block, uint32_t on) {
+  return on ? swizzle_f(block) << 4 : 0u;
+}
+__host__ __device__ inline uint64_t swizzle(uint64_t x, uint32_t on) {
+  return on ? x ^ ((uint64_t)swizzle_f(x >> 12) << 4) : x;
+}
+
 // Arguments of one tile-pass launch.  The field list is a macro so that the
 // pass compiler can emit the identical structure into the kernels it builds:
 //   passes, ops, slot_default, pool, ov_off, ov   device tables (slot_default is
@@ -39,7 +67,8 @@ constexpr uint32_t kScanBlock = 4096;
   uint32_t pass;                                                                             \
   uint32_t n_passes;                                                                         \
   uint32_t t0;                                                                               \
-  uint32_t n_measure;
+  uint32_t n_measure;                                                                        \
+  uint32_t swz;
 
 template <typename V>
 struct PassArgs {
@@ -61,6 +90,7 @@ struct ScanArgs {
   uint32_t nblk;
   uint32_t per_block;
   uint32_t per_thread;
+  uint32_t swz;         // states stored swizzled (see swizzle())
   // monotone CDF (nullptr: plain block scan): per (state, block) its largest
   // in-block prefix and the largest CDF value of the blocks before it
   double* maxa;         // batch x nblk
@@ -76,6 +106,7 @@ struct ScanArgs {
 
 template <typename V>
 struct MarginalArgs {
+  uint32_t swz;
   const V* states;
   double* partial;  // batch x nblk x (kMaxGroup + 1)
   uint64_t N;
@@ -133,6 +164,7 @@ struct SampleArgs {
 
 template <typename V>
 struct ExpArgs {
+  uint32_t swz;
   const V* states;
   double* partial;
   uint64_t N;
@@ -155,6 +187,7 @@ struct AdjArgs {
 
 template <typename V>
 struct ObsArgs {
+  uint32_t swz;
   const V* psi;
   V* lam;
   uint64_t N;
@@ -168,6 +201,7 @@ struct ObsArgs {
 // record entry `rec` of each trajectory, K_k from the channel's parameters).
 template <typename V>
 struct GchAdjArgs {
+  uint32_t swz;
   V* lam;
   const uint8_t* mr_bits;
   const double* mr_norm;
@@ -178,6 +212,37 @@ struct GchAdjArgs {
   uint32_t n_measure;
   uint32_t t0;
 };
+
+// A dense state-dependent channel on qubits q[0..nq-1] (nq 1 or 2; bit j of a
+// Kraus matrix index <-> q[j]), for every state of the batch: the reduced
+// density matrix rho of those qubits in FP64 (per-block partial sums, reduced
+// in a fixed order), p_k = Re Tr(M_k rho) / Tr rho with M_k = K_k^dagger K_k,
+// k drawn with the uniform of word gidx of the stream [seed, 4<<56 | cfg<<48 |
+// alpha] (smallest k with u < p_0 + ... + p_k over p_k > 0, else the last such
+// k), recorded with the factor 1 / sqrt(p_k Tr rho), and K_k times that factor
+// applied to the state.  chan: K, d, then M_k and K_k for every k (d x d
+// row-major complex, re/im interleaved).
+template <typename V>
+struct DenseArgs {
+  uint32_t swz;
+  V* states;
+  double* partial;      // batch x nblk x 16
+  uint64_t N;
+  uint32_t nq;
+  uint32_t q[2];
+  uint32_t nblk;        // blocks of 4096 base indices (indices with the channel's qubits 0)
+  uint8_t* mr_bits;
+  double* mr_norm;
+  uint32_t* status;
+  const double* chan;
+  uint32_t rec, gidx, n_measure, t0, cfg;
+  uint64_t seed, alpha0;
+  V* lam;               // reverse sweep: lambda <- (factor K_k)^dagger lambda
+};
+template <typename V>
+hipError_t launch_dense_channel(const DenseArgs<V>& a, uint32_t batch, hipStream_t s);
+template <typename V>
+hipError_t launch_dense_lam_adjoint(const DenseArgs<V>& a, uint32_t batch, hipStream_t s);
 
 template <typename V>
 hipError_t launch_adjoint_pass(const AdjArgs<V>& a, uint32_t k, uint32_t n_slots, uint32_t batch, hipStream_t s);
@@ -203,7 +268,7 @@ template <typename BitT>
 hipError_t launch_sample(const SampleArgs<BitT>& a, uint64_t items, hipStream_t s);
 template <typename V>
 hipError_t launch_copy_normalised(const V* states, V* out, const double* total, uint64_t N, uint32_t batch,
-                                  hipStream_t s);
+                                  uint32_t swz, hipStream_t s);
 template <typename V>
 hipError_t launch_expval(const ExpArgs<V>& a, const double* total, double* out, uint32_t batch, uint32_t t0,
                          hipStream_t s);

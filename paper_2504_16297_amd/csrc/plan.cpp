@@ -190,30 +190,33 @@ static ptsbe_status analyse_channel(const ptsbe_channel& ch, int idx, Channel* o
         for (int l = 0; l < d; ++l) v += std::conj(K[k][l * d + i]) * K[k][l * d + j];
         if (std::abs(v - (i == j ? p : 0.0)) > 1e-12) {
           if (!twirl) {
-            // A state-dependent 1-qubit channel with diagonal K_k^dagger K_k is
-            // resolved when the trajectory's state reaches it (from the qubit's
-            // populations); anything else is not supported.
+            // Not a unitary mixture: resolved when the trajectory's state reaches
+            // it (Algorithm 1's state-dependent branch, p_k = <psi|K_k^dag K_k|psi>).
+            // A 1-qubit channel with diagonal K_k^dagger K_k needs only the qubit's
+            // populations and is applied inside the next tile pass; any other
+            // (dense: a 1-qubit channel with non-diagonal K^dag K, or a 2-qubit
+            // channel) needs the reduced density matrix of its qubits and is
+            // applied by its own step.
             Channel g;
-            g.nq = 1;
+            g.nq = ch.nq;
             g.K = ch.n_kraus;
-            g.general = ch.nq == 1;
-            for (int kk = 0; kk < g.K && g.general; ++kk) {
-              cd m[4] = {0, 0, 0, 0};
-              for (int r = 0; r < 2; ++r)
-                for (int c2 = 0; c2 < 2; ++c2)
-                  for (int l = 0; l < 2; ++l) m[r * 2 + c2] += std::conj(K[kk][l * 2 + r]) * K[kk][l * 2 + c2];
-              if (std::abs(m[1]) > 1e-12 || std::abs(m[2]) > 1e-12) g.general = false;
-              g.d0.push_back(m[0].real());
-              g.d1.push_back(m[3].real());
+            g.general = true;
+            g.dense = ch.nq != 1;
+            for (int kk = 0; kk < g.K; ++kk) {
+              Mat m(d * d, cd(0, 0));
+              for (int r = 0; r < d; ++r)
+                for (int c2 = 0; c2 < d; ++c2)
+                  for (int l = 0; l < d; ++l) m[r * d + c2] += std::conj(K[kk][l * d + r]) * K[kk][l * d + c2];
+              if (d == 2) {
+                if (std::abs(m[1]) > 1e-12 || std::abs(m[2]) > 1e-12) g.dense = true;
+                g.d0.push_back(m[0].real());
+                g.d1.push_back(m[3].real());
+              }
+              g.M.push_back(m);
               g.U.push_back(K[kk]);
-              g.p.push_back(kraus_weight(K[kk], 2));
-              g.diag.push_back(mat_is_diag(K[kk], 2));
+              g.p.push_back(kraus_weight(K[kk], d));
+              g.diag.push_back(mat_is_diag(K[kk], d));
             }
-            if (!g.general)
-              return fail(PTSBE_E_UNSUPPORTED, "channel " + std::to_string(idx) +
-                                                   " is not a unitary mixture and not a 1-qubit channel with "
-                                                   "diagonal K^dagger K (PTSBE_PLAN_TWIRL replaces it by its "
-                                                   "Pauli twirl)");
             *out = std::move(g);
             return PTSBE_OK;
           }
@@ -843,13 +846,39 @@ static ptsbe_status schedule(Plan& plan, const std::vector<Step>& steps, std::ve
       // checkpointed at its decision, apply its adjoint to lambda alone
       const Step& st = steps[rem[0]];
       ExecStep ex;
-      ex.mr_qubits.push_back(st.q[0]);
+      for (int j = 0; j < st.nq; ++j) ex.mr_qubits.push_back(st.q[j]);
       ex.mr_index.push_back(st.mr);
       ex.wall = true;
       ex.restore = st.gidx;
+      ex.dense = st.dense;
       exec.push_back(ex);
       rem.erase(rem.begin());
       first = false;
+      continue;
+    }
+    if (taken.empty() && steps[rem[0]].kind == ST_GCH && steps[rem[0]].dense) {
+      // a dense state-dependent channel at the front (everything before it has
+      // run): its own step reduces the density matrix of its qubits, decides
+      // and applies the chosen operator
+      const Step& st = steps[rem[0]];
+      if (first) {
+        Pass p;
+        p.k = k;
+        for (int q = 0; q < n; ++q) (q < k ? p.tq : p.oq).push_back(q);
+        p.flags = PASS_INIT_ZERO;
+        passes.push_back(p);
+        ExecStep e0;
+        e0.pass = (int)passes.size() - 1;
+        exec.push_back(e0);
+        first = false;
+      }
+      ExecStep ex;
+      for (int j = 0; j < st.nq; ++j) ex.mr_qubits.push_back(st.q[j]);
+      ex.mr_index.push_back(st.mr);
+      ex.wall = true;
+      ex.dense = true;
+      exec.push_back(ex);
+      rem.erase(rem.begin());
       continue;
     }
     if (taken.empty()) {
@@ -867,7 +896,7 @@ static ptsbe_status schedule(Plan& plan, const std::vector<Step>& steps, std::ve
         bool b = false;
         for (int j = 0; j < st.nq; ++j) b = b || blk[st.q[j]];
         const bool mr_ok = st.kind == ST_MR;
-        const bool ch_ok = st.kind == ST_GCH && !channel_pending && !channel_taken && !others_before;
+        const bool ch_ok = st.kind == ST_GCH && !st.dense && !channel_pending && !channel_taken && !others_before;
         if (!b && (mr_ok || ch_ok) && !measured[si]) {
           ex.mr_qubits.push_back(st.q[0]);
           ex.mr_index.push_back(st.mr);
@@ -1099,6 +1128,8 @@ ptsbe_status build_plan(const ptsbe_circuit* c, const ptsbe_noise_model* nm, con
   P.half_tile_lds = o && (o->flags & PTSBE_PLAN_HALF_TILE_LDS);
   P.waves = o ? (int)((o->flags >> PTSBE_PLAN_WAVES_SHIFT) & 15u) : 0;
   P.pair_fusion = !(o && (o->flags & PTSBE_PLAN_NO_PAIR_FUSION));
+  P.swizzle = !(o && (o->flags & PTSBE_PLAN_NO_SWIZZLE));
+  P.nontemporal = o && (o->flags & PTSBE_PLAN_NONTEMPORAL);
   if (P.waves > 8) return fail(PTSBE_E_ARG, "waves per SIMD must be 0 (default) or 1..8");
   P.jit = std::make_shared<JitProgram>();
   // channels
@@ -1128,8 +1159,9 @@ ptsbe_status build_plan(const ptsbe_circuit* c, const ptsbe_noise_model* nm, con
       // not pre-sampled: a record entry decided on the device (like a measure-reset)
       Step st;
       st.kind = ST_GCH;
-      st.nq = 1;
-      st.q[0] = q[0];
+      st.nq = nq;
+      for (int j = 0; j < nq; ++j) st.q[j] = q[j];
+      st.dense = P.channels[ch].dense;
       st.chan = ch;
       st.gidx = P.n_general++;
       st.mr = P.n_measure++;
@@ -1255,13 +1287,25 @@ ptsbe_status build_plan(const ptsbe_circuit* c, const ptsbe_noise_model* nm, con
         const Channel& c = P.channels[st.chan];
         chan_off[st.chan] = (int)R.chan_param.size();
         R.chan_param.push_back((double)c.K);
-        for (int k = 0; k < c.K; ++k) R.chan_param.push_back(c.d0[k]);
-        for (int k = 0; k < c.K; ++k) R.chan_param.push_back(c.d1[k]);
-        for (int k = 0; k < c.K; ++k)
-          for (int e = 0; e < 4; ++e) {
-            R.chan_param.push_back(c.U[k][e].real());
-            R.chan_param.push_back(c.U[k][e].imag());
-          }
+        if (c.dense) {
+          // K, d, then K_k^dagger K_k and K_k for every k (d x d row-major, re/im)
+          const int d = 1 << c.nq;
+          R.chan_param.push_back((double)d);
+          for (const std::vector<Mat>* v : {&c.M, &c.U})
+            for (int k = 0; k < c.K; ++k)
+              for (int e = 0; e < d * d; ++e) {
+                R.chan_param.push_back((*v)[k][e].real());
+                R.chan_param.push_back((*v)[k][e].imag());
+              }
+        } else {
+          for (int k = 0; k < c.K; ++k) R.chan_param.push_back(c.d0[k]);
+          for (int k = 0; k < c.K; ++k) R.chan_param.push_back(c.d1[k]);
+          for (int k = 0; k < c.K; ++k)
+            for (int e = 0; e < 4; ++e) {
+              R.chan_param.push_back(c.U[k][e].real());
+              R.chan_param.push_back(c.U[k][e].imag());
+            }
+        }
       }
       R.rec_chan[st.mr] = (uint32_t)chan_off[st.chan];
       R.rec_gidx[st.mr] = (uint32_t)st.gidx;

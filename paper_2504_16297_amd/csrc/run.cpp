@@ -222,6 +222,42 @@ enum { T_PASS = 0, T_MEASURE = 2, T_SCAN = 3, T_SAMPLE = 4, T_OTHER = -1 };
 
 enum { PH_UPLOAD = 1, PH_LAUNCH = 2 };
 
+}  // namespace
+
+// Arguments of a dense state-dependent channel step (see DenseArgs).
+template <typename V>
+DenseArgs<V> dense_args(const Plan& P, const ExecStep& ex, V* states, uint8_t* partial, uint8_t* mr_bits,
+                        double* mr_norm, uint32_t* status, const double* d_chan_param, uint32_t b0, uint64_t seed,
+                        uint32_t cfg, uint64_t alpha0) {
+  DenseArgs<V> a{};
+  a.swz = P.swizzle ? 1u : 0u;
+  a.states = states;
+  a.partial = reinterpret_cast<double*>(partial);
+  a.N = 1ull << P.n;
+  a.nq = (uint32_t)ex.mr_qubits.size();
+  for (uint32_t j = 0; j < a.nq; ++j) a.q[j] = (uint32_t)ex.mr_qubits[j];
+  a.nblk = (uint32_t)(((a.N >> a.nq) + 4095) / 4096);
+  a.mr_bits = mr_bits;
+  a.mr_norm = mr_norm;
+  a.status = status;
+  const uint32_t r = (uint32_t)ex.mr_index[0];
+  a.chan = d_chan_param + P.rec_info.rec_chan[r];
+  a.rec = r;
+  a.gidx = P.rec_info.rec_gidx[r];
+  a.n_measure = (uint32_t)P.n_measure;
+  a.t0 = b0;
+  a.cfg = cfg;
+  a.seed = seed;
+  a.alpha0 = alpha0;
+  return a;
+}
+template DenseArgs<float2> dense_args<float2>(const Plan&, const ExecStep&, float2*, uint8_t*, uint8_t*, double*,
+                                              uint32_t*, const double*, uint32_t, uint64_t, uint32_t, uint64_t);
+template DenseArgs<double2> dense_args<double2>(const Plan&, const ExecStep&, double2*, uint8_t*, uint8_t*, double*,
+                                                uint32_t*, const double*, uint32_t, uint64_t, uint32_t, uint64_t);
+
+namespace {
+
 // PH_UPLOAD copies the tables and launch routes into the workspace; PH_LAUNCH
 // enqueues the kernels (device work only, so it can be captured in a graph).
 template <typename V, typename BitT>
@@ -303,6 +339,7 @@ ptsbe_status run_typed(const Plan& P, TrajSet& ts, const ptsbe_run_opts& o, uint
   pa.n = (uint32_t)P.n;
   pa.n_passes = (uint32_t)P.passes.size();
   pa.n_measure = (uint32_t)P.n_measure;
+  pa.swz = P.swizzle ? 1u : 0u;
 
   const uint32_t E = (uint32_t)P.exec.size();
   for (uint32_t b0 = 0, bi = 0; b0 < B; b0 += L.batch, ++bi) {
@@ -333,10 +370,17 @@ ptsbe_status run_typed(const Plan& P, TrajSet& ts, const ptsbe_run_opts& o, uint
           o.timing[8] += (double)rows * (double)N * pass_flops_per_amp(ps);
           o.timing[9] += rows;
         }
+      } else if (ex.dense) {
+        CK(launch_dense_channel<V>(dense_args<V>(P, ex, states, ws + L.mr_partial, mr_bits, mr_norm, status,
+                                                 d_chan_param, b0, o.seed, o.cfg, ts.alpha0),
+                                   bb, s),
+           "state-dependent channel");
+        CK(tm.mark(T_MEASURE), "timer");
       } else {
         for (size_t g0 = 0; g0 < ex.mr_qubits.size(); g0 += kMaxGroup) {
           size_t g1 = std::min(ex.mr_qubits.size(), g0 + kMaxGroup);
           MarginalArgs<V> ma{};
+          ma.swz = pa.swz;
           ma.states = states;
           ma.partial = reinterpret_cast<double*>(ws + L.mr_partial);
           ma.N = N;
@@ -370,6 +414,7 @@ ptsbe_status run_typed(const Plan& P, TrajSet& ts, const ptsbe_run_opts& o, uint
       }
     }
     ScanArgs<V> sa{};
+    sa.swz = pa.swz;
     sa.states = states;
     sa.partial = partial;
     sa.offs = offs;
@@ -418,11 +463,12 @@ ptsbe_status run_typed(const Plan& P, TrajSet& ts, const ptsbe_run_opts& o, uint
       }
     } else if (o.mode == PTSBE_RUN_STATES) {
       CK(launch_norm<V>(sa, bb, total, s), "norm");
-      CK(launch_copy_normalised<V>(states, reinterpret_cast<V*>(o.d_state_out) + (uint64_t)b0 * N, total, N, bb, s),
+      CK(launch_copy_normalised<V>(states, reinterpret_cast<V*>(o.d_state_out) + (uint64_t)b0 * N, total, N, bb, pa.swz, s),
          "state copy");
     } else {
       CK(launch_norm<V>(sa, bb, total, s), "norm");
       ExpArgs<V> ea{};
+      ea.swz = pa.swz;
       ea.states = states;
       ea.partial = partial;
       ea.N = N;

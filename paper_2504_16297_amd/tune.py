@@ -14,7 +14,7 @@ plan-independent (the noise sites depend only on the circuit), so one sample is
 carried across candidates with ptsbe_trajset_from_records.
 
 `tuned_plan_options` keeps the picks in a JSON cache keyed by a hash of the
-circuit description, the precision and the candidate set, so a workload is
+circuit description and the precision, so a workload is
 tuned once per machine (``python -m paper_2504_16297_amd.tune`` fills the
 cache for the benchmark workloads); the default cache is the package's
 ``tune_cache.json``, or the file named by ``PTSBE_TUNE_CACHE``.
@@ -90,10 +90,10 @@ def autotune(circuit, precision="c64", records=None, sample=64, candidates=None,
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
 
 
-def circuit_key(circuit, precision, candidates):
-    """Cache key: SHA-256 of the circuit description (ops, channels, rules,
-    parameters), the precision and the candidate set."""
-    blob = json.dumps({"circuit": circuit, "precision": precision, "candidates": candidates}, sort_keys=True,
+def circuit_key(circuit, precision):
+    """Cache key: SHA-256 of the circuit description (qubit count, ops, channels,
+    rules, parameters) and the precision."""
+    blob = json.dumps({"circuit": circuit, "precision": precision}, sort_keys=True,
                       default=lambda x: x.tolist() if hasattr(x, "tolist") else str(x))
     return hashlib.sha256(blob.encode()).hexdigest()[:32]
 
@@ -115,7 +115,8 @@ def tuned_plan_options(circuit, precision="c64", cache=None, tune_if_missing=Fal
     (and storing the pick) on a miss if `tune_if_missing`, else None on a miss.
     Returns (options or None, cache entry or None)."""
     cands = kw.get("candidates") or candidates_for(circuit["n_qubits"], precision)
-    key = circuit_key(circuit, precision, [list(c) for c in cands])
+    kw["candidates"] = cands
+    key = circuit_key(circuit, precision)
     path = _cache_path(cache)
     entries = load_cache(path)
     e = entries.get(key)
@@ -123,7 +124,8 @@ def tuned_plan_options(circuit, precision="c64", cache=None, tune_if_missing=Fal
         r = autotune(circuit, precision=precision, **kw)
         e = {"n_qubits": circuit["n_qubits"], "precision": precision,
              "pick": {k: r[k] for k in ("tile_qubits", "min_fill", "half_tile", "pair_fusion")},
-             "results": [list(x) for x in r["results"]], "seconds": r["seconds"]}
+             "results": [list(x) for x in r["results"]], "seconds": r["seconds"],
+             "candidates": [list(c) for c in cands]}
         entries[key] = e
         tmp = path + ".tmp"
         with open(tmp, "w") as f:
@@ -142,7 +144,13 @@ def main(argv=None):
     ap.add_argument("--workload", default="c4", choices=["c2", "c4"])
     ap.add_argument("--cache", default=None)
     ap.add_argument("--sample", type=int, default=0, help="trajectories timed per candidate (0: by state size)")
+    ap.add_argument("--candidates", default=None,
+                    help="comma-separated tile:fill pairs (whole-tile register changes, pair fusion on); "
+                         "default: the full candidate set")
     a = ap.parse_args(argv)
+    cands = None
+    if a.candidates:
+        cands = [(int(t), int(f), False, True) for t, f in (c.split(":") for c in a.candidates.split(","))]
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     if root not in sys.path:
         sys.path.insert(0, root)
@@ -164,7 +172,7 @@ def main(argv=None):
         state = (8 if wl["precision"] == "c64" else 16) << n
         sample = a.sample or int(max(1, min(64, (8 << 30) // state)))
         opts, e = tuned_plan_options(circ, wl["precision"], cache=a.cache, tune_if_missing=True,
-                                     records=ts.get()["records"], sample=sample, log=log)
+                                     records=ts.get()["records"], sample=sample, log=log, candidates=cands)
         log(f"[tune] {n} qubits: {opts} ({e['seconds']:.0f} s)")
 
 

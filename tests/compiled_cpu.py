@@ -60,6 +60,8 @@ static inline uint32_t __builtin_amdgcn_readfirstlane(uint32_t v) { return v; }
 #define __launch_bounds__(x)
 #define __shared__
 #define __align__(x)
+#define __builtin_nontemporal_load(p) (*(p))
+#define __builtin_nontemporal_store(v, p) (*(p) = (v))
 """
 
 RUNNER = r"""
@@ -176,7 +178,26 @@ def _channel_decision(circuit, chan, gidx, p1, be, alpha):
     return k, probs[k]
 
 
-def run_compiled(plan, ts, params=None, mr_tol=1e-6, circuit=None, be=(0, 0)):
+# The library's storage layout of states above 2^12 amplitudes (PTSBE_PLAN_NO_SWIZZLE
+# turns it off): amplitude x sits at x ^ (f(x >> 12) << 4), with f the XOR of the
+# 8-bit constants below over the set bits of x >> 12.  An involution.
+SWIZZLE = (0x7a, 0x96, 0x3d, 0x72, 0x37, 0xf0, 0x85, 0x96, 0x92, 0xce, 0x15, 0x7a,
+           0xaf, 0xa8, 0x5d, 0x0e, 0xaa, 0x06, 0xed, 0x62, 0x47, 0x60, 0x35, 0x86)
+
+
+def storage_positions(n, on=True):
+    """Position of each amplitude x (0 .. 2^n - 1) in the library's state storage."""
+    x = np.arange(1 << n, dtype=np.int64)
+    if not on or n <= 12:
+        return x
+    h = x >> 12
+    f = np.zeros_like(x)
+    for i, c in enumerate(SWIZZLE):
+        f ^= ((h >> i) & 1) * c
+    return x ^ (f << 4)
+
+
+def run_compiled(plan, ts, params=None, mr_tol=1e-6, circuit=None, be=(0, 0), swizzled=True):
     """States [B, 2^n] (normalised) after running every pass through its
     generated kernel on the CPU.  State-dependent channel entries are decided
     as the device does, with ``circuit``'s channels and ``be`` = (seed, cfg)."""
@@ -196,6 +217,7 @@ def run_compiled(plan, ts, params=None, mr_tol=1e-6, circuit=None, be=(0, 0)):
     slot_begin = [int(ps["slot_begin"]) for ps in passes]
     libs = {}
     x = np.arange(N, dtype=np.int64)
+    pos = storage_positions(n, swizzled)     # amplitude x is states[:, pos[x]]
     for ex in t["exec"]:
         if ex["pass"] != 0xFFFFFFFF:
             p = int(ex["pass"])
@@ -210,7 +232,7 @@ def run_compiled(plan, ts, params=None, mr_tol=1e-6, circuit=None, be=(0, 0)):
         else:
             rinfo = plan.record_info()
             for b in range(B):
-                w = np.abs(states[b].astype(np.complex128)) ** 2
+                w = np.abs(states[b][pos].astype(np.complex128)) ** 2
                 tot = w.sum()
                 for j in range(int(ex["nq"])):
                     q = int(ex["q"][j])
@@ -228,7 +250,7 @@ def run_compiled(plan, ts, params=None, mr_tol=1e-6, circuit=None, be=(0, 0)):
                     pb = p1 if bit else 1 - p1
                     mr_bits[b * nm + r] = bit
                     mr_norm[b * nm + r] = 1.0 / np.sqrt(pb * tot) if j == 0 else 1.0 / np.sqrt(pb)
-    out = states.astype(np.complex128)
+    out = states[:, pos].astype(np.complex128)
     return out / np.linalg.norm(out, axis=1, keepdims=True)
 
 
@@ -245,6 +267,13 @@ def run_compiled_adjoint(plan, ts, params, odiag):
     cdt = np.complex64 if c64 else np.complex128
     psi = run_compiled(plan, ts, params).astype(cdt)   # normalised: unitary circuits keep the norm
     lam = (psi.astype(np.complex128) * odiag[None, :]).astype(cdt)
+    # into storage order (the layout the reverse-sweep kernels read)
+    pos = storage_positions(n)
+    psi_s = np.empty_like(psi)
+    lam_s = np.empty_like(lam)
+    psi_s[:, pos] = psi
+    lam_s[:, pos] = lam
+    psi, lam = np.ascontiguousarray(psi_s), np.ascontiguousarray(lam_s)
     adj, dot_param = export_adjoint_tables(ts, params)
     n_raw = C.c_size_t()
     offs = np.zeros(16, dtype=np.uint64)

@@ -59,10 +59,15 @@ def test_channel_checks():
     bad = {"kraus": [1.05 * np.eye(2)]}
     assert _status(P.ptsbe_plan, _one_gate(bad)) == E_NOT_CPTP
     # CPTP, not a unitary mixture, K^dagger K not diagonal (measure X, write Z):
-    # neither pre-samplable nor resolvable from the qubit's populations
+    # resolved from the qubit's reduced density matrix when the state reaches it
     plus, minus = np.array([1, 1]) / np.sqrt(2), np.array([1, -1]) / np.sqrt(2)
     xmeas = {"kraus": [np.outer([1, 0], plus), np.outer([0, 1], minus)]}
-    assert _status(P.ptsbe_plan, _one_gate(xmeas)) == E_UNSUPPORTED
+    plan_x = P.ptsbe_plan(_one_gate(xmeas))
+    assert plan_x.info["n_sites"] == 0 and plan_x.info["n_measure"] == 1
+    # ... but not together with a projection
+    proj = _one_gate(xmeas)
+    proj["ops"] = proj["ops"] + [{"kind": "project0", "qubits": (1,)}]
+    assert _status(P.ptsbe_plan, proj) == E_UNSUPPORTED
     # amplitude damping: resolved when the state reaches it (a record entry, no site)
     plan_ad = P.ptsbe_plan(_one_gate({"name": "amplitude_damping", "gamma": 0.2}))
     assert plan_ad.info["n_sites"] == 0 and plan_ad.info["n_measure"] == 1

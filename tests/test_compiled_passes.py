@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import paper_2504_16297_amd as P
-from compiled_cpu import run_compiled
+from compiled_cpu import pass_source, run_compiled
 from gpu_helpers import oracle_states
 from workloads import c1_workload, c3_workload, random_small_circuit
 from workloads.circuits import hea_circuit
@@ -170,3 +170,27 @@ def test_state_dependent_channels(tile):
         psi, entries = run_record(circ, rec, be_key=(9, 2, a))
         psi = psi / np.linalg.norm(psi)
         assert float(np.max(np.abs(st[a] - psi))) <= 1e-5, f"trajectory {a}"
+
+
+@pytest.mark.parametrize("swizzle,nontemporal", [(True, False), (False, False), (True, True)])
+def test_swizzled_state_storage(swizzle, nontemporal):
+    """States above 2^12 amplitudes are stored swizzled (runs of 16 amplitudes and
+    blocks of 4096 kept, high index bits XORed onto bits 4..11); the generated
+    kernels address them that way, or plainly with PTSBE_PLAN_NO_SWIZZLE, and
+    the states read back in index order equal the oracle's either way."""
+    from compiled_cpu import storage_positions
+    from workloads import brick_circuit
+    pos = storage_positions(16)
+    assert np.array_equal(np.sort(pos), np.arange(1 << 16))          # a permutation
+    assert np.array_equal(pos[pos], np.arange(1 << 16))              # an involution
+    assert np.array_equal(pos & 15, np.arange(1 << 16) & 15)         # 16-amplitude runs kept
+    assert np.array_equal(pos >> 12, np.arange(1 << 16) >> 12)       # 4096-amplitude blocks kept
+    circ = brick_circuit(15, 4, np.random.default_rng(6), 0.05, 0.1)
+    plan = P.ptsbe_plan(circ, swizzle=swizzle, nontemporal=nontemporal)
+    src = "".join(pass_source(plan, p) for p in range(plan.info["n_passes"]))
+    assert ("const uint64_t px = " in src) == swizzle
+    assert ("stnt(dstp" in src) == nontemporal
+    ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=3, total_shots=3, seed=2, cfg=2)
+    st = run_compiled(plan, ts, swizzled=swizzle)
+    ref, _ = oracle_states(circ, ts.get()["records"])
+    assert max(float(np.max(np.abs(st[a] - ref[a]))) for a in range(len(ref))) <= 1e-5

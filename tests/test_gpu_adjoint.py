@@ -228,3 +228,28 @@ def test_gradient_through_state_dependent_channels(n, prec, tile, max_batch):
     E, G = float(E.cpu().numpy()[0]), G.cpu().numpy()
     Er, Gr = ensemble_value_and_grad(circ, ref["records"], ref["weights"], params, obs, be_seed=(13, 3))
     _assert_close(E, G, Er, Gr, prec)
+
+
+@pytest.mark.parametrize("n,prec,max_batch", [(6, "c64", 0), (7, "c128", 0), (14, "c64", 4)])
+def test_gradient_through_dense_state_dependent_channels(n, prec, max_batch):
+    """A 1-qubit channel with non-diagonal K^dagger K after every RY and a
+    2-qubit joint decay after every ring CZ, each resolved from the reduced
+    density matrix of its qubits in the forward preparation, checkpointed, and
+    in the reverse sweep restored with (factor K_k)^dagger applied to lambda:
+    E and the gradient equal the oracle's with the same decisions."""
+    from test_gpu_parity import _dense_channels
+    log(f"[adjoint dense state-dependent] n={n} {prec} max_batch={max_batch}")
+    circ = hea_circuit(n, 2, np.random.default_rng(90 + n), 0.0)
+    ch = _dense_channels()
+    circ["channels"] = ch
+    circ["rules"] = [{"when": "after_tag", "tag": "RY", "channel": 0}, {"when": "after_tag", "tag": "CZ", "channel": 1}]
+    params = np.asarray(circ["params"])
+    plan = P.ptsbe_plan(circ, precision=prec)
+    assert plan.info["n_sites"] == 0 and plan.info["n_measure"] >= 2 * n
+    ts = P.ptsbe_trajset_from_records(plan, [()] * 6, [1] * 6)
+    obs = zz_ring(n)
+    E, G = P.ptsbe_adjoint_grad(plan, ts, params, obs, max_batch=max_batch, seed=13, cfg=3)
+    torch.cuda.synchronize()
+    E, G = float(E.cpu().numpy()[0]), G.cpu().numpy()
+    Er, Gr = ensemble_value_and_grad(circ, [()] * 6, [1 / 6] * 6, params, obs, be_seed=(13, 3))
+    _assert_close(E, G, Er, Gr, prec)

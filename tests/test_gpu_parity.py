@@ -578,3 +578,58 @@ def test_state_dependent_channels(variant):
         psi = psi / np.linalg.norm(psi)
         assert float(np.max(np.abs(states[a] - psi))) <= 1e-5, f"trajectory {a}"
     log(f"  {len(g['records'])} trajectories, {len(info)} record entries each")
+
+
+def _dense_channels():
+    """A 1-qubit channel with non-diagonal K^dagger K (amplitude damping rotated
+    by RY(0.9)) and a 2-qubit joint decay |11> -> |00>, neither a unitary mixture."""
+    import math
+    c, s = math.cos(0.45), math.sin(0.45)
+    U = np.array([[c, -s], [s, c]], dtype=np.complex128)
+    g = 0.35
+    K0 = np.array([[1, 0], [0, math.sqrt(1 - g)]], dtype=np.complex128)
+    K1 = np.array([[0, math.sqrt(g)], [0, 0]], dtype=np.complex128)
+    rot = [U @ K0 @ U.conj().T, U @ K1 @ U.conj().T]
+    J0 = np.diag([1.0, 1.0, 1.0, math.sqrt(0.6)]).astype(np.complex128)
+    J1 = np.zeros((4, 4), dtype=np.complex128)
+    J1[0, 3] = math.sqrt(0.4)
+    return [{"kraus": rot, "nq": 1}, {"kraus": [J0, J1], "nq": 2}]
+
+
+@pytest.mark.parametrize("variant,n,prec", [("compiled", 9, "c64"), ("generic", 9, "c64"), ("small_tile", 9, "c64"),
+                                            ("compiled", 8, "c128"), ("compiled", 15, "c64")])
+def test_dense_state_dependent_channels(variant, n, prec):
+    """Channels resolved from the reduced density matrix of their one or two
+    qubits (Algorithm 1's state-dependent branch, p_k = <psi|K_k^dag K_k|psi>):
+    each is its own step (reduction, decision, application) between passes;
+    record entries and states equal the oracle's (15 qubits: swizzled storage)."""
+    from oracle.statevector import run_record
+    log(f"[dense state-dependent] {variant} n={n} {prec}")
+    rng = np.random.default_rng(60 + n)
+    circ = random_small_circuit(n, 60, rng, p1=0.0, p2=0.0)
+    circ = dict(circ, ops=[op for op in circ["ops"] if op["kind"] != "noise"],
+                channels=_dense_channels() + [{"name": "depolarizing", "nq": 1, "p": 0.05}],
+                rules=[{"when": "after_tag", "tag": "U3", "channel": 0}, {"when": "after_tag", "tag": "CZ", "channel": 1},
+                       {"when": "after_tag", "tag": "RX", "channel": 2}])
+    kw = {"compiled": {}, "generic": {"compile": False}, "small_tile": {"tile_qubits": 5}}[variant]
+    plan = P.ptsbe_plan(circ, precision=prec, **kw)
+    ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=12, total_shots=12, seed=3, cfg=1)
+    g = ts.get()
+    r = P.ptsbe_run_batch(plan, ts, mode="states", seed=9, cfg=2)
+    P.ptsbe_run_status(plan, r["workspace"])
+    torch.cuda.synchronize()
+    states = r["states"].cpu().numpy()
+    entries = r["mr_bits"].cpu().numpy()
+    info = plan.record_info()
+    assert sum(1 for c, _ in info if c == 1) >= 2          # some 2-qubit channel steps
+    tol = 1e-5 if prec == "c64" else 1e-12
+    for a, rec in enumerate(g["records"]):
+        psi, ref = run_record(circ, rec, be_key=(9, 2, a))
+        assert list(entries[a]) == list(ref), f"trajectory {a}"
+        psi = psi / np.linalg.norm(psi)
+        assert float(np.max(np.abs(states[a] - psi))) <= tol, f"trajectory {a}"
+    # shots come from the same states
+    sh = P.ptsbe_run_batch(plan, ts, mode="shots", seed=9, cfg=2)
+    torch.cuda.synchronize()
+    assert torch.equal(sh["mr_bits"], r["mr_bits"])
+    log(f"  {len(g['records'])} trajectories, {len(info)} record entries each")

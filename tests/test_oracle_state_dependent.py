@@ -175,3 +175,136 @@ def test_path_gradient_is_derivative_of_unnormalised_value():
         pm = p.copy(); pm[i] -= h
         fd = (f(pp)[0] - f(pm)[0]) / (2 * h) / prob
         assert abs(fd - g[i]) < 1e-7, (i, fd, g[i])
+
+
+# --- channels whose K^dagger K are not diagonal, and two-qubit channels
+
+def _rotated_damping(g, theta):
+    """Amplitude damping conjugated by RY(theta): K_k^dagger K_k not diagonal."""
+    c, s = math.cos(theta / 2), math.sin(theta / 2)
+    U = np.array([[c, -s], [s, c]], dtype=np.complex128)
+    K0 = np.array([[1, 0], [0, math.sqrt(1 - g)]], dtype=np.complex128)
+    K1 = np.array([[0, math.sqrt(g)], [0, 0]], dtype=np.complex128)
+    return [U @ K0 @ U.conj().T, U @ K1 @ U.conj().T]
+
+
+def _pair_decay(g):
+    """Two-qubit joint decay |11> -> |00> with probability g (not a unitary mixture):
+    K0 = diag(1, 1, 1, sqrt(1-g)), K1 = sqrt(g) |00><11|."""
+    K0 = np.diag([1.0, 1.0, 1.0, math.sqrt(1 - g)]).astype(np.complex128)
+    K1 = np.zeros((4, 4), dtype=np.complex128)
+    K1[0, 3] = math.sqrt(g)
+    return [K0, K1]
+
+
+def test_state_dependent_channel_classes():
+    from oracle.channels import cptp_error, general_channel, state_dependent
+    rd = _rotated_damping(0.3, 0.8)
+    pd = _pair_decay(0.4)
+    for K in (rd, pd):
+        assert cptp_error(K) < 1e-14 and state_dependent(K)
+    assert general_channel(rd) is None and general_channel(pd) is None
+    # unitary mixtures are pre-sampled, not state dependent
+    from oracle.channels import kraus_ops
+    assert not state_dependent(kraus_ops({"name": "depolarizing", "nq": 2, "p": 0.1}))
+
+
+def test_pair_decay_hand_worked():
+    """From |11> the joint decay happens with probability g (u >= 1 - g) and
+    leaves |00>; from |01> it never happens."""
+    g = 0.35
+    c = {"n_qubits": 2, "params": [], "rules": [], "channels": [{"kraus": _pair_decay(g), "nq": 2}],
+         "ops": [{"kind": "gate", "name": "X", "qubits": (0,), "params": (), "tag": "X"},
+                 {"kind": "gate", "name": "X", "qubits": (1,), "params": (), "tag": "X"},
+                 {"kind": "noise", "channel": 0, "qubits": (0, 1)}]}
+    c01 = dict(c, ops=c["ops"][:1] + c["ops"][2:])
+    for alpha in range(40):
+        u = uniforms(3, key1(4, 1, alpha), 1)[0]
+        psi, rec = run_record(c, (), be_key=(3, 1, alpha))
+        assert rec == [0 if u < 1 - g else 1]
+        assert np.allclose(np.abs(psi), [0, 0, 0, 1] if rec[0] == 0 else [1, 0, 0, 0])
+        psi, rec = run_record(c01, (), be_key=(3, 1, alpha))
+        assert rec == [0] and np.allclose(np.abs(psi), [0, 1, 0, 0])
+
+
+def _dense_circuit():
+    return {"n_qubits": 3, "params": [],
+            "channels": [{"kraus": _rotated_damping(0.45, 0.9), "nq": 1}, {"kraus": _pair_decay(0.5), "nq": 2}],
+            "rules": [{"when": "after_tag", "tag": "H", "channel": 0}, {"when": "after_tag", "tag": "CX", "channel": 1}],
+            "ops": [{"kind": "gate", "name": "H", "qubits": (0,), "params": (), "tag": "H"},
+                    {"kind": "gate", "name": "CNOT", "qubits": (0, 1), "params": (), "tag": "CX"},
+                    {"kind": "gate", "name": "RX", "qubits": (2,), "params": (1.1,), "tag": "RX"},
+                    {"kind": "gate", "name": "H", "qubits": (2,), "params": (), "tag": "H"},
+                    {"kind": "gate", "name": "CNOT", "qubits": (2, 1), "params": (), "tag": "CX"}]}
+
+
+def test_dense_channels_trajectory_average_equals_density_matrix():
+    """1-qubit channels with non-diagonal K^dagger K and a 2-qubit channel, each
+    decided from the state: the average of |psi><psi| over trajectories is the
+    density-matrix evolution under the full channels, and the exact average over
+    every decision path with its probability equals it to rounding."""
+    import itertools
+    c = _dense_circuit()
+    rho = evolve(c)
+    n_gch = sum(1 for s in expand(c)[0] if s[0] == "gch")
+    exact = np.zeros_like(rho)
+    for path in itertools.product(range(2), repeat=n_gch):
+        tr = []
+        with np.errstate(divide="ignore", invalid="ignore"):
+            psi, _ = run_record(c, (), forced=list(path), trace=tr)
+        pr = math.prod(d["p"] for d in tr)
+        if pr > 0.0:
+            exact += pr * np.outer(psi, psi.conj())
+    assert float(np.max(np.abs(exact - rho))) < 1e-12
+    T = 3000
+    acc = np.zeros_like(rho)
+    for alpha in range(T):
+        psi, _ = run_record(c, (), be_key=(17, 2, alpha))
+        acc += np.outer(psi, psi.conj())
+    acc /= T
+    assert float(np.max(np.abs(acc - rho))) < 5 * 0.5 / math.sqrt(T)
+
+
+def test_dense_channel_gradient_sums_to_density_matrix_derivative():
+    """Over all decision paths, sum of p(path) times the fixed-operator adjoint
+    gradient equals the parameter shift of Tr(O rho(theta)) with the 1-qubit
+    non-diagonal and the 2-qubit channels."""
+    import itertools
+    from oracle.adjoint import observable_diag, trajectory_grad
+    ops = []
+    for layer in range(2):
+        for q in range(3):
+            ops.append({"kind": "param", "gen": "Y", "qubits": (q,), "index": 2 * (3 * layer + q), "tag": "RY"})
+            ops.append({"kind": "param", "gen": "Z", "qubits": (q,), "index": 2 * (3 * layer + q) + 1, "tag": "RZ"})
+        ops.append({"kind": "gate", "name": "CZ", "qubits": (0, 1), "params": (), "tag": "CZ"})
+        ops.append({"kind": "gate", "name": "CZ", "qubits": (1, 2), "params": (), "tag": "CZ"})
+    params = np.random.default_rng(8).uniform(0, 2 * math.pi, 12)
+    c = {"n_qubits": 3, "ops": ops, "params": [float(x) for x in params],
+         "channels": [{"kraus": _rotated_damping(0.3, 0.7), "nq": 1}, {"kraus": _pair_decay(0.4), "nq": 2}],
+         "rules": [{"when": "after_tag", "tag": "RY", "channel": 0}, {"when": "after_tag", "tag": "CZ", "channel": 1}]}
+    terms = [(1.0, (0, 1)), (0.5, (2,)), (-0.3, (1,))]
+    od = observable_diag(3, terms)
+    n_gch = sum(1 for s in expand(c)[0] if s[0] == "gch")
+
+    def exact(pp):
+        return float(np.real(np.sum(np.diag(evolve(c, pp)) * od)))
+
+    G = np.zeros(params.size)
+    total = 0.0
+    for path in itertools.product(range(2), repeat=n_gch):
+        tr = []
+        with np.errstate(divide="ignore", invalid="ignore"):
+            run_record(c, (), params=params, forced=list(path), trace=tr)
+        pr = math.prod(d["p"] for d in tr)
+        if not pr > 0.0:     # a path through a zero-probability operator (e.g. a decay of |00>)
+            continue
+        total += pr
+        _, g = trajectory_grad(c, (), params, od, forced=list(path))
+        G += pr * g
+    assert abs(total - 1.0) < 1e-12
+    shift = np.zeros(params.size)
+    for i in range(params.size):
+        pp = params.copy(); pp[i] += math.pi / 2
+        pm = params.copy(); pm[i] -= math.pi / 2
+        shift[i] = 0.5 * (exact(pp) - exact(pm))
+    assert float(np.max(np.abs(G - shift))) < 1e-11

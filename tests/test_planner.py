@@ -274,7 +274,7 @@ def test_autotune_candidates():
 
 def test_tuning_cache_keys_and_reuse(tmp_path, monkeypatch):
     """The autotuner's cache: a miss tunes once and stores the pick under a key
-    of the circuit, precision and candidate set; a hit returns it without
+    of the circuit and precision; a hit returns it without
     tuning; another circuit or precision is another key."""
     from paper_2504_16297_amd import tune
     calls = []
