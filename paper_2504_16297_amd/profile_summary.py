@@ -4,6 +4,7 @@ project, and read those summaries back.
     python -m paper_2504_16297_amd.profile_summary stats KERNEL_STATS_CSV --cmd "..." [--top 12] [--group RE]
     python -m paper_2504_16297_amd.profile_summary traffic --kernel ptsbe_pass_ \\
         --fetch F.csv --write W.csv --copy-fetch CF.csv --copy-write CW.csv --copy-bytes B --cmd "..."
+    python -m paper_2504_16297_amd.profile_summary counters COUNTER_CSV --kernel RE --cmd "..."
 
 `traffic` averages FETCH_SIZE and WRITE_SIZE (KiB per dispatch) over the
 dispatches of the named kernel and scales each by what the same counter reads
@@ -112,6 +113,27 @@ def traffic(a):
     return "\n".join(lines)
 
 
+def counters(path, kernel_regex, note=""):
+    """Totals of every counter over the dispatches whose name matches, and per
+    wavefront when SQ_WAVES was collected."""
+    tot, disp = {}, set()
+    for r in csv.DictReader(open(path)):
+        if not re.search(kernel_regex, r["Kernel_Name"]):
+            continue
+        disp.add(r["Dispatch_Id"])
+        tot[r["Counter_Name"]] = tot.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    if not tot:
+        raise SystemExit(f"no counter rows for /{kernel_regex}/ in {path}")
+    waves = tot.get("SQ_WAVES")
+    out = [f"kernels: /{kernel_regex}/{' (' + note + ')' if note else ''}, {len(disp)} dispatches"
+           + (f", {waves:.4g} waves" if waves else ""), "",
+           "| counter | total | per dispatch | per wave |", "|---|---|---|---|"]
+    for c in sorted(tot):
+        pw = f"{tot[c] / waves:.1f}" if waves else "-"
+        out.append(f"| {c} | {tot[c]:.4g} | {tot[c] / len(disp):.4g} | {pw} |")
+    return "\n".join(out)
+
+
 def read_traffic(path):
     """(bytes per dispatch, kernel fingerprint) from a traffic summary, or None."""
     if not os.path.exists(path):
@@ -142,8 +164,18 @@ def main(argv=None):
     t.add_argument("--fingerprint", required=True, help="kernel_fingerprint of the profiled plan "
                    "(python bench.py --fingerprint)")
     t.add_argument("--cmd", required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("csv")
+    c.add_argument("--kernel", required=True, help="regex of the kernel names to sum over")
+    c.add_argument("--note", default="")
+    c.add_argument("--cmd", required=True)
     a = ap.parse_args(argv)
-    body = stats(a.csv, a.top, a.group) if a.what == "stats" else traffic(a)
+    if a.what == "stats":
+        body = stats(a.csv, a.top, a.group)
+    elif a.what == "traffic":
+        body = traffic(a)
+    else:
+        body = counters(a.csv, a.kernel, a.note)
     sys.stdout.write(f"command: {a.cmd}\n\n{body}\n")
 
 
