@@ -170,16 +170,26 @@ typedef struct {
  * either qubit until another operation needs one of them (in a brick circuit one
  * 4x4 then replaces four 2x2 matrices and a sign flip). */
 #define PTSBE_PLAN_NO_PAIR_FUSION 128u
-/* Plan flag: store the states in plain index order.  By default amplitude x of
- * a state of more than 2^12 amplitudes sits at x XOR (f(x >> 12) << 4), f a fixed
+/* Plan flags: state storage order.  Swizzled storage puts amplitude x of a
+ * state of more than 2^12 amplitudes at x XOR (f(x >> 12) << 4), f a fixed
  * linear map of the high index bits to 8 bits: runs of 16 amplitudes and blocks
  * of 4096 stay in place, but the runs a tile pass moves no longer differ only in
- * high address bits (faster on the HBM).  States leave the library in plain
- * order either way (STATES mode, shots, expectation values). */
-#define PTSBE_PLAN_NO_SWIZZLE 256u
+ * high address bits (faster on the HBM for large states, slower for small
+ * ones).  By default states of PTSBE_SWIZZLE_MIN_QUBITS qubits or more are
+ * swizzled; NO_SWIZZLE keeps every state in plain index order, SWIZZLE swizzles
+ * every state above 12 qubits.  States leave the library in plain order either
+ * way (STATES mode, shots, expectation values). */
+#define PTSBE_PLAN_NO_SWIZZLE 4096u
+#define PTSBE_PLAN_SWIZZLE 8192u
+#define PTSBE_SWIZZLE_MIN_QUBITS 22u
 /* Plan flag: the compiled passes load and store the states with nontemporal
  * (streaming) cache hints. */
-#define PTSBE_PLAN_NONTEMPORAL 512u
+#define PTSBE_PLAN_NONTEMPORAL 16384u
+/* Plan flag: each workgroup of a compiled forward pass runs two tiles of its
+ * state, one after the other, with the second tile's loads issued before the
+ * first tile's arithmetic (twice the state bytes in flight per workgroup, one
+ * matrix set-up for both). */
+#define PTSBE_PLAN_TWO_TILES 32768u
 
 typedef struct ptsbe_plan_s* ptsbe_plan_t;
 typedef struct ptsbe_trajset_s* ptsbe_trajset_t;
@@ -195,6 +205,7 @@ typedef struct {
     uint32_t tile_qubits;
     uint32_t max_kraus;         /* largest channel size */
     uint32_t total_kraus;       /* sum over sites of the channel size */
+    uint32_t swizzled;          /* 1: the plan's states are stored swizzled (PTSBE_PLAN_SWIZZLE) */
 } ptsbe_plan_info;
 
 /* Validate a circuit and noise model and build the execution plan: expand the

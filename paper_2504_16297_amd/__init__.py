@@ -115,7 +115,8 @@ def ptsbe_plan_compile(plan):
 
 
 def ptsbe_plan(circuit, precision="c64", tile_qubits=0, compile=True, min_fill=0, half_tile=False,
-               phase_frames=True, waves=0, twirl=False, pair_fusion=True, swizzle=True, nontemporal=False):
+               phase_frames=True, waves=0, twirl=False, pair_fusion=True, swizzle=None, nontemporal=False,
+               two_tiles=False):
     """Build the execution plan of a circuit dictionary (ops, channels, rules).
     ``compile=False`` runs the passes through the generic tile kernels instead of
     per-pass compiled kernels; ``min_fill`` (1..7, 0 = 2) is the fewest 2x2
@@ -125,9 +126,11 @@ def ptsbe_plan(circuit, precision="c64", tile_qubits=0, compile=True, min_fill=0
     ``waves`` (1..8, 0 = compiler's choice) sets the compiled passes' register
     budget to 512 / waves VGPRs; ``twirl`` replaces channels that are not unitary
     mixtures by their Pauli twirl (else they are rejected); ``pair_fusion=False``
-    keeps diagonal 2-qubit gates apart from the 2x2 runs on their qubits; ``swizzle=False``
-    stores states in plain index order (PTSBE_PLAN_NO_SWIZZLE); ``nontemporal`` gives the
-    compiled passes' state loads and stores streaming cache hints."""
+    keeps diagonal 2-qubit gates apart from the 2x2 runs on their qubits; ``swizzle``: None
+    stores states of PTSBE_SWIZZLE_MIN_QUBITS qubits or more swizzled, True every state above
+    12 qubits (PTSBE_PLAN_SWIZZLE), False none (PTSBE_PLAN_NO_SWIZZLE); ``nontemporal`` gives
+    the compiled passes' state loads and stores streaming cache hints; ``two_tiles`` has each
+    workgroup of a compiled forward pass run two tiles (PTSBE_PLAN_TWO_TILES)."""
     ops = circuit["ops"]
     arr = (L.Op * max(1, len(ops)))()
     keep = []
@@ -197,7 +200,8 @@ def ptsbe_plan(circuit, precision="c64", tile_qubits=0, compile=True, min_fill=0
                     (L.PLAN_HALF_TILE_LDS if half_tile else 0) |
                     (0 if phase_frames else L.PLAN_NO_PHASE_FRAMES) | (int(waves) << L.PLAN_WAVES_SHIFT) |
                     (L.PLAN_TWIRL if twirl else 0) | (0 if pair_fusion else L.PLAN_NO_PAIR_FUSION) |
-                    (0 if swizzle else L.PLAN_NO_SWIZZLE) | (L.PLAN_NONTEMPORAL if nontemporal else 0), 0)
+                    ({None: 0, True: L.PLAN_SWIZZLE, False: L.PLAN_NO_SWIZZLE}[swizzle]) |
+                    (L.PLAN_NONTEMPORAL if nontemporal else 0) | (L.PLAN_TWO_TILES if two_tiles else 0), 0)
     h = C.c_void_p()
     check(lib().ptsbe_plan(C.byref(c), C.byref(nm), C.byref(po), C.byref(h)))
     return Plan(h, None)

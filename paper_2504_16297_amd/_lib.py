@@ -32,8 +32,11 @@ PLAN_NO_PHASE_FRAMES = 32
 PLAN_WAVES_SHIFT = 8
 PLAN_TWIRL = 64
 PLAN_NO_PAIR_FUSION = 128
-PLAN_NO_SWIZZLE = 256
-PLAN_NONTEMPORAL = 512
+PLAN_NO_SWIZZLE = 4096
+PLAN_NONTEMPORAL = 16384
+PLAN_TWO_TILES = 32768
+PLAN_SWIZZLE = 8192
+SWIZZLE_MIN_QUBITS = 22
 NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
@@ -69,7 +72,7 @@ class PlanOpts(C.Structure):
 class PlanInfo(C.Structure):
     _fields_ = [(f, C.c_uint32) for f in ("n_qubits", "n_sites", "n_params", "n_measure", "n_passes",
                                           "n_steps", "precision", "tile_qubits", "max_kraus",
-                                          "total_kraus")]
+                                          "total_kraus", "swizzled")]
 
 
 class PtsOpts(C.Structure):

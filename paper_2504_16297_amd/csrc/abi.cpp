@@ -82,7 +82,7 @@ ptsbe_status ptsbe_plan_pass_source(ptsbe_plan_t plan, uint32_t pass, uint32_t a
     if (pass >= passes.size()) return fail(PTSBE_E_ARG, "pass index out of range");
     const std::string src =
         jit_pass_source(passes[pass], P.n, P.precision, "ptsbe_pass", P.half_tile_lds, nullptr, adjoint != 0,
-                        P.waves, P.swizzle, P.nontemporal);
+                        P.waves, P.swizzle, P.nontemporal, P.tiles_per_block);
     if (out) {
       if (*len < src.size() + 1) return fail(PTSBE_E_ARG, "output buffer too small");
       std::memcpy(out, src.c_str(), src.size() + 1);
@@ -108,6 +108,7 @@ ptsbe_status ptsbe_plan_get_info(ptsbe_plan_t plan, ptsbe_plan_info* out) {
   for (auto& c : P.channels) mk = std::max<uint32_t>(mk, (uint32_t)c.K);
   out->max_kraus = mk;
   out->total_kraus = (uint32_t)P.site_p.size();
+  out->swizzled = P.swizzle ? 1u : 0u;
   return PTSBE_OK;
 }
 

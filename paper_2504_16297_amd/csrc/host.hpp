@@ -181,6 +181,7 @@ struct Plan {
   bool pair_fusion = true;     // diagonal 2-qubit gates merge with the 2x2 runs around them into 4x4 slots
   bool swizzle = true;         // states stored at swizzle(x) (kernels.hpp)
   bool nontemporal = false;    // compiled passes load and store the states with nontemporal hints
+  int tiles_per_block = 1;     // tiles of a state one workgroup of a compiled forward pass runs
   std::shared_ptr<JitProgram> jit;
 };
 

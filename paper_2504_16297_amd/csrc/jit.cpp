@@ -492,19 +492,22 @@ struct Gen {
       return;
     }
     const uint32_t d = (uint32_t)op.slot[0] | ((uint32_t)op.slot[1] << 16);
-    o << "  {\n    double acc = 0.0;\n";
+    // the thread's 8 products are summed in the state's precision, the
+    // wavefront and everything above it in FP64
+    o << "  {\n    T acc_t = 0;\n";
     for (int r = 0; r < 16; ++r) {
       if ((r >> j) & 1) continue;
       const int r1 = r | (1 << j);
       const std::string p0 = "s" + std::to_string(r), p1 = "s" + std::to_string(r1);
       const std::string l0 = "l" + std::to_string(r), l1 = "l" + std::to_string(r1);
       if (op.b == 3)
-        o << "    acc += imc(" << l0 << ", " << p0 << ") - imc(" << l1 << ", " << p1 << ");\n";
+        o << "    acc_t += imc(" << l0 << ", " << p0 << ") - imc(" << l1 << ", " << p1 << ");\n";
       else if (op.b == 1)
-        o << "    acc += imc(" << l0 << ", " << p1 << ") + imc(" << l1 << ", " << p0 << ");\n";
+        o << "    acc_t += imc(" << l0 << ", " << p1 << ") + imc(" << l1 << ", " << p0 << ");\n";
       else  // Y: (Y psi)_0 = -i psi_1, (Y psi)_1 = i psi_0
-        o << "    acc += rec(" << l1 << ", " << p0 << ") - rec(" << l0 << ", " << p1 << ");\n";
+        o << "    acc_t += rec(" << l1 << ", " << p0 << ") - rec(" << l0 << ", " << p1 << ");\n";
     }
+    o << "    double acc = (double)acc_t;\n";
     const uint32_t bd = 1u << (k - 4), wl = std::min<uint32_t>(64, bd);
     for (uint32_t off = 1; off < wl; off <<= 1) o << "    acc += __shfl_xor(acc, " << off << ", " << wl << ");\n";
     const uint32_t W = bd / wl;
@@ -626,8 +629,12 @@ __device__ __forceinline__ void stnt(V* p, V v) {
   __builtin_nontemporal_store(v.x, &p->x);
   __builtin_nontemporal_store(v.y, &p->y);
 }
-__device__ __forceinline__ double imc(V a, V b) { return (double)a.x * (double)b.y - (double)a.y * (double)b.x; }
-__device__ __forceinline__ double rec(V a, V b) { return (double)a.x * (double)b.x + (double)a.y * (double)b.y; }
+)";
+
+// helpers of the adjoint sweep's gradient terms: Im(conj(a) b) and Re(conj(a) b)
+// in the state's precision
+const char* kDualHelpers = R"(__device__ __forceinline__ T imc(V a, V b) { return a.x * b.y - a.y * b.x; }
+__device__ __forceinline__ T rec(V a, V b) { return a.x * b.x + a.y * b.y; }
 )";
 
 std::string bit_gather(const char* src, const std::vector<int>& dst_pos, int first_src_bit) {
@@ -653,10 +660,13 @@ std::string bit_gather(const char* src, const std::vector<int>& dst_pos, int fir
 namespace {
 
 std::string gen_pass(const Pass& ps, int n, int precision, const std::string& name, bool split, bool dual,
-                     int waves, bool swz, bool nt, bool* needs_full) {
+                     int waves, bool swz, bool nt, int tpb, bool* needs_full) {
   const int k = ps.k;
   if (k < (int)kMinRegTile || k > 12) return "";
   if (dual && (ps.flags & PASS_INIT_ZERO)) return "";
+  // two tiles per workgroup: tiles 2b and 2b + 1 of the block's state (they
+  // differ in the lowest qubit outside the tile); forward passes only
+  const bool two = tpb == 2 && !dual && n > k;
   Gen g;
   g.split = split && !dual;
   g.dual = dual;
@@ -692,7 +702,7 @@ std::string gen_pass(const Pass& ps, int n, int precision, const std::string& na
   o << kPrelude << (g.c64 ? "typedef float T;\ntypedef float2 V;\n" : "typedef double T;\ntypedef double2 V;\n")
     << "struct PassArgs { " << kArgsFields << " };\n"
     << "static_assert(sizeof(PassArgs) == " << sizeof(PassArgs<float2>) << ", \"PassArgs layout\");\n"
-    << kHelpers;
+    << kHelpers << (dual ? kDualHelpers : "");
   o << "extern \"C\" __global__ __launch_bounds__(256) ";
   if (waves > 0) o << "__attribute__((amdgpu_waves_per_eu(" << waves << "))) ";
   o << "void " << name << "(PassArgs a"
@@ -710,9 +720,15 @@ std::string gen_pass(const Pass& ps, int n, int precision, const std::string& na
   // Global offsets: thread part from tid, register parts constant.
   std::vector<int> tpos(g.tq.begin(), g.tq.begin() + (k - 4));
   o << "  const uint64_t ot = " << bit_gather("tid", tpos, 0) << ";\n";
-  o << "  const uint64_t tile_id = blockIdx.x;\n"
-    << "  const uint64_t base = " << bit_gather("tile_id", g.oq, 0) << ";\n"
-    << "  V cs; cs.x = 1; cs.y = 0;\n";
+  if (two)
+    o << "  const uint64_t tile_id0 = 2ull * blockIdx.x;\n"
+      << "  const uint64_t base_a = " << bit_gather("tile_id0", g.oq, 0) << ";\n"
+      << "  const uint64_t base_b = base_a | " << (1ull << g.oq[0]) << "ull;\n"
+      << "  V cs; cs.x = 1; cs.y = 0;\n";
+  else
+    o << "  const uint64_t tile_id = blockIdx.x;\n"
+      << "  const uint64_t base = " << bit_gather("tile_id", g.oq, 0) << ";\n"
+      << "  V cs; cs.x = 1; cs.y = 0;\n";
   uint64_t og[16];
   for (int r = 0; r < 16; ++r) {
     og[r] = 0;
@@ -724,16 +740,25 @@ std::string gen_pass(const Pass& ps, int n, int precision, const std::string& na
   // ^ f(ot >> 12)) << 4), f linear; the register part is a constant.
   swz = swz && n > 12;
   std::string pos_base = "base + ot";
-  if (swz) {
+  // f(tile part) ^ f(thread part) of the swizzle, for the tile id in `tv`
+  auto fx_of = [&](const std::string& tv) {
     std::string fx;
     for (size_t j = 0; j < g.oq.size(); ++j)
       if (g.oq[j] >= 12)
-        fx += " ^ ((uint32_t)((tile_id >> " + std::to_string(j) + ") & 1u) * " +
+        fx += " ^ ((uint32_t)((" + tv + " >> " + std::to_string(j) + ") & 1u) * " +
               std::to_string(kSwizzle[g.oq[j] - 12]) + "u)";
     for (size_t j = 0; j < tpos.size(); ++j)
       if (tpos[j] >= 12)
         fx += " ^ (((tid >> " + std::to_string(j) + ") & 1u) * " + std::to_string(kSwizzle[tpos[j] - 12]) + "u)";
-    o << "  const uint64_t px = (base + ot) ^ ((uint64_t)(0u" << fx << ") << 4);\n";
+    return fx;
+  };
+  if (swz) {
+    if (two) {
+      o << "  const uint64_t px_a = (base_a + ot) ^ ((uint64_t)(0u" << fx_of("tile_id0") << ") << 4);\n"
+        << "  const uint64_t px_b = (base_b + ot) ^ ((uint64_t)(0u" << fx_of("(tile_id0 + 1ull)") << ") << 4);\n";
+    } else {
+      o << "  const uint64_t px = (base + ot) ^ ((uint64_t)(0u" << fx_of("tile_id") << ") << 4);\n";
+    }
     pos_base = "px";
     for (int r = 0; r < 16; ++r) {
       uint32_t fr = 0;
@@ -744,7 +769,28 @@ std::string gen_pass(const Pass& ps, int n, int precision, const std::string& na
   }
   const char* join = swz ? " ^ " : " + ";
   const bool init = (ps.flags & PASS_INIT_ZERO) != 0;
-  if (init) {
+  auto emit_init = [&]() {  // |0...0> on the loop's current tile (registers declared before the loop)
+    o << "  s0.x = (base == 0 && tid == 0) ? (T)1 : (T)0; s0.y = 0;\n";
+    for (int r = 1; r < 16; ++r) o << "  " << g.S(r) << ".x = 0; " << g.S(r) << ".y = 0;\n";
+  };
+  if (two) {
+    // the second tile's loads are issued with the first's; its registers
+    // become the working set after the first tile is stored
+    const std::string pa = swz ? "px_a" : "base_a + ot", pb = swz ? "px_b" : "base_b + ot";
+    if (init) {
+      o << "  V";
+      for (int r = 0; r < 16; ++r) o << (r ? ", " : " ") << g.S(r);
+      o << ";\n";
+    } else {
+      o << "  const V* sst = a.states + (uint64_t)src * a.N;\n";
+      for (int h = 0; h < 2; ++h)
+        for (int r = 0; r < 16; ++r) {
+          const std::string at = "(" + (h ? pb : pa) + ")" + join + std::to_string(og[r]) + "ull";
+          o << "  V " << (h ? "b" + std::to_string(r) : g.S(r)) << " = "
+            << (nt ? "ldnt(sst + (" + at + "))" : "sst[" + at + "]") << ";\n";
+        }
+    }
+  } else if (init) {
     o << "  V s0; s0.x = (base == 0 && tid == 0) ? (T)1 : (T)0; s0.y = 0;\n";
     for (int r = 1; r < 16; ++r) o << "  V " << g.S(r) << "; " << g.S(r) << ".x = 0; " << g.S(r) << ".y = 0;\n";
   } else {
@@ -795,6 +841,15 @@ std::string gen_pass(const Pass& ps, int n, int precision, const std::string& na
   // which rewritten slots this block's trajectory overrides, as wave-uniform words
   for (int w : ovw_words)
     o << "  const uint32_t ovw" << w << " = __builtin_amdgcn_readfirstlane(ovw[" << w << "]);\n";
+  if (two) {
+    o << "#pragma clang loop unroll(disable)\n"
+      << "  for (uint32_t it = 0; it < 2u; ++it) {\n"
+      << "  const uint64_t tile_id = tile_id0 + it;\n"
+      << "  const uint64_t base = it ? base_b : base_a;\n";
+    if (swz) o << "  const uint64_t px = it ? px_b : px_a;\n";
+    o << "  cs.x = 1; cs.y = 0;\n";
+    if (init) emit_init();
+  }
   for (const DOp& op : ps.ops) {
     switch (op.type) {
       case DOP_M1G:
@@ -839,6 +894,16 @@ std::string gen_pass(const Pass& ps, int n, int precision, const std::string& na
     else
       o << "  dstp[" << at << "] = " << g.S(r) << ";\n";
   }
+  if (two) {
+    if (!init) {
+      o << "  if (it == 0u) {\n";
+      for (int r = 0; r < 16; ++r) o << "    " << g.S(r) << " = b" << r << ";\n";
+      o << "  }\n";
+    }
+    // the next tile's first LDS write must wait for this tile's last reads
+    if (g.tile_read) o << "  __syncthreads();\n";
+    o << "  }\n";
+  }
   if (dual) {
     o << "  V* ldst = lam + (uint64_t)dst * a.N;\n";
     for (int r = 0; r < 16; ++r) o << "  ldst[(" << pos_base << ")" << join << og[r] << "ull] = l" << r << ";\n";
@@ -851,15 +916,18 @@ std::string gen_pass(const Pass& ps, int n, int precision, const std::string& na
 }  // namespace
 
 std::string jit_pass_source(const Pass& ps, int n, int precision, const std::string& name, bool split,
-                            uint32_t* tile_elems, bool dual, int waves, bool swz, bool nt) {
+                            uint32_t* tile_elems, bool dual, int waves, bool swz, bool nt, int tpb,
+                            uint32_t* tiles_per_block) {
   bool full = false;
   split = split && !dual;
-  std::string src = gen_pass(ps, n, precision, name, split, dual, waves, swz, nt, &full);
+  if (tpb != 2 || dual || n <= ps.k) tpb = 1;
+  std::string src = gen_pass(ps, n, precision, name, split, dual, waves, swz, nt, tpb, &full);
   if (split && full) {  // a 4x4 matrix off the register bits needs the whole tile
     split = false;
-    src = gen_pass(ps, n, precision, name, false, dual, waves, swz, nt, &full);
+    src = gen_pass(ps, n, precision, name, false, dual, waves, swz, nt, tpb, &full);
   }
   if (tile_elems) *tile_elems = src.empty() ? 0u : (1u << (ps.k - (split ? 1 : 0)));
+  if (tiles_per_block) *tiles_per_block = (uint32_t)tpb;
   return src;
 }
 
@@ -903,10 +971,10 @@ ptsbe_status jit_build(const Plan& P) {
                          const char* stem) {
     kernel_of.assign(passes.size(), -1);
     for (size_t p = 0; p < passes.size(); ++p) {
-      uint32_t te = 0;
+      uint32_t te = 0, tpb = 1;
       const std::string body =
           jit_pass_source(passes[p], P.n, P.precision, "KERNEL_NAME", P.half_tile_lds, &te, dual, P.waves,
-                          P.swizzle, P.nontemporal);
+                          P.swizzle, P.nontemporal, P.tiles_per_block, &tpb);
       if (body.empty()) continue;
       auto it = by_body.find(body);
       if (it != by_body.end()) {
@@ -922,6 +990,7 @@ ptsbe_status jit_build(const Plan& P) {
       J.names.push_back(name);
       J.sources.push_back(src);
       J.tile_elems.push_back(te);
+      J.tiles_per_block.push_back(tpb);
     }
   };
   add_program(P.passes, false, J.pass_kernel, "ptsbe_pass_");
@@ -1032,15 +1101,17 @@ hipError_t jit_launch(const Plan& P, uint32_t pass, const PassArgs<V>& a, uint32
   const Pass& ps = P.passes[pass];
   const uint32_t k = (uint32_t)ps.k, n_slots = (uint32_t)ps.slots.size();
   const size_t te = P.jit->tile_elems[P.jit->pass_kernel[pass]];
+  const uint32_t tpb = P.jit->tiles_per_block[P.jit->pass_kernel[pass]];
   const size_t lds = sizeof(V) * (te + lds_mat_entries(ps)) + 4 * ((size_t)n_slots + (n_slots + 31) / 32);
   if (lds > 65536) return hipErrorInvalidConfiguration;
+  if (tpb != 1 && (tpb != 2 || P.n <= (int)k)) return hipErrorInvalidConfiguration;
   PassArgs<V> la = a;
   uint32_t slot_begin = 0;
   for (uint32_t p = 0; p < pass; ++p) slot_begin += (uint32_t)P.passes[p].slots.size();
   la.slot_default = a.slot_default + slot_begin;
   void* args[] = {&la};
-  return hipModuleLaunchKernel(f, 1u << (P.n - k), rows, 1, 1u << (k - kRegBits), 1, 1, (unsigned)lds, s, args,
-                               nullptr);
+  return hipModuleLaunchKernel(f, (1u << (P.n - k)) / tpb, rows, 1, 1u << (k - kRegBits), 1, 1, (unsigned)lds, s,
+                               args, nullptr);
 }
 
 bool jit_has_adjoint(const Plan& P, uint32_t pass) {

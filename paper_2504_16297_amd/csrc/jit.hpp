@@ -31,6 +31,7 @@ struct JitProgram {
   std::vector<std::string> names;          // kernel index -> symbol
   std::vector<std::string> sources;        // kernel index -> HIP source
   std::vector<uint32_t> tile_elems;        // kernel index -> amplitudes of LDS tile space
+  std::vector<uint32_t> tiles_per_block;   // kernel index -> tiles of a state per workgroup (1 or 2)
   std::vector<std::vector<char>> code;     // kernel index -> code object
   double compile_seconds = 0.0;
   // per device: loaded modules and kernel handles
@@ -51,9 +52,12 @@ struct JitProgram {
 // `nt`: state loads and stores of the forward passes with nontemporal hints.
 // `waves`: waves per SIMD the kernel's register budget is set for (0 = the
 // compiler's choice).
+// `tpb`: tiles per workgroup (2: a forward pass of a state larger than one tile
+// runs tiles 2b and 2b + 1 in workgroup b, the second tile's loads issued up
+// front; the grid's x extent halves); *tiles_per_block receives what was used.
 std::string jit_pass_source(const Pass& ps, int n, int precision, const std::string& name, bool split,
                             uint32_t* tile_elems, bool dual = false, int waves = 0, bool swz = true,
-                            bool nt = false);
+                            bool nt = false, int tpb = 1, uint32_t* tiles_per_block = nullptr);
 
 // Generate and compile every pass kernel of the plan (host only, no device
 // needed).  Idempotent; thread-safe.

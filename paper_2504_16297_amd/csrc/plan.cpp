@@ -1128,8 +1128,13 @@ ptsbe_status build_plan(const ptsbe_circuit* c, const ptsbe_noise_model* nm, con
   P.half_tile_lds = o && (o->flags & PTSBE_PLAN_HALF_TILE_LDS);
   P.waves = o ? (int)((o->flags >> PTSBE_PLAN_WAVES_SHIFT) & 15u) : 0;
   P.pair_fusion = !(o && (o->flags & PTSBE_PLAN_NO_PAIR_FUSION));
-  P.swizzle = !(o && (o->flags & PTSBE_PLAN_NO_SWIZZLE));
+  if (o && (o->flags & PTSBE_PLAN_NO_SWIZZLE) && (o->flags & PTSBE_PLAN_SWIZZLE))
+    return fail(PTSBE_E_ARG, "PTSBE_PLAN_SWIZZLE and PTSBE_PLAN_NO_SWIZZLE together");
+  P.swizzle = (o && (o->flags & PTSBE_PLAN_NO_SWIZZLE))  ? false
+              : (o && (o->flags & PTSBE_PLAN_SWIZZLE)) ? P.n > 12
+                                                         : P.n >= (int)PTSBE_SWIZZLE_MIN_QUBITS;
   P.nontemporal = o && (o->flags & PTSBE_PLAN_NONTEMPORAL);
+  P.tiles_per_block = (o && (o->flags & PTSBE_PLAN_TWO_TILES)) ? 2 : 1;
   if (P.waves > 8) return fail(PTSBE_E_ARG, "waves per SIMD must be 0 (default) or 1..8");
   P.jit = std::make_shared<JitProgram>();
   // channels

@@ -89,7 +89,7 @@ extern "C" int run_pass(const unsigned char* blob, const uint64_t* offs, unsigne
   a.n_passes = n_passes;
   a.t0 = 0;
   a.n_measure = n_measure;
-  const unsigned bx = 1u << (k - 4), gx = 1u << (n - k);
+  const unsigned bx = 1u << (k - 4), gx = (1u << (n - k)) / PASS_TPB;
   blockDim.x = bx;
   gridDim.x = gx;
   gridDim.y = rows;
@@ -130,6 +130,8 @@ def _build(src):
         cpp = os.path.join(_CACHE, h + ".cpp")
         extra = "#define PASS_EXTRA , reinterpret_cast<V*>(lam), partial, n_dot\n" if "double* partial" in src \
             else "#define PASS_EXTRA\n"
+        # two tiles per workgroup: half the grid
+        extra += "#define PASS_TPB %du\n" % (2 if "tile_id0 = 2ull * blockIdx.x" in src else 1)
         with open(cpp, "w") as f:
             f.write(SHIM + src + extra + RUNNER)
         tmp = so + f".{os.getpid()}.tmp"
@@ -197,7 +199,7 @@ def storage_positions(n, on=True):
     return x ^ (f << 4)
 
 
-def run_compiled(plan, ts, params=None, mr_tol=1e-6, circuit=None, be=(0, 0), swizzled=True):
+def run_compiled(plan, ts, params=None, mr_tol=1e-6, circuit=None, be=(0, 0), swizzled=None):
     """States [B, 2^n] (normalised) after running every pass through its
     generated kernel on the CPU.  State-dependent channel entries are decided
     as the device does, with ``circuit``'s channels and ``be`` = (seed, cfg)."""
@@ -217,6 +219,8 @@ def run_compiled(plan, ts, params=None, mr_tol=1e-6, circuit=None, be=(0, 0), sw
     slot_begin = [int(ps["slot_begin"]) for ps in passes]
     libs = {}
     x = np.arange(N, dtype=np.int64)
+    if swizzled is None:
+        swizzled = bool(info["swizzled"])
     pos = storage_positions(n, swizzled)     # amplitude x is states[:, pos[x]]
     for ex in t["exec"]:
         if ex["pass"] != 0xFFFFFFFF:
@@ -268,7 +272,7 @@ def run_compiled_adjoint(plan, ts, params, odiag):
     psi = run_compiled(plan, ts, params).astype(cdt)   # normalised: unitary circuits keep the norm
     lam = (psi.astype(np.complex128) * odiag[None, :]).astype(cdt)
     # into storage order (the layout the reverse-sweep kernels read)
-    pos = storage_positions(n)
+    pos = storage_positions(n, bool(info["swizzled"]))
     psi_s = np.empty_like(psi)
     lam_s = np.empty_like(lam)
     psi_s[:, pos] = psi

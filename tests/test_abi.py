@@ -34,6 +34,24 @@ def test_every_declared_symbol_is_exported():
     assert set(names) == set(L.EXPORTED)
 
 
+def test_flag_constants_match_the_header():
+    """The binding's flag values are the header's, and the plan flags share no
+    bit with each other, the fill threshold (bits 0..2) or the waves field
+    (bits 8..11)."""
+    src = open(HEADER).read()
+    defs = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define PTSBE_(\w+) (\d+)u\b", src)}
+    for name in ("PLAN_NO_COMPILE", "PLAN_HALF_TILE_LDS", "PLAN_NO_PHASE_FRAMES", "PLAN_WAVES_SHIFT", "PLAN_TWIRL",
+                 "PLAN_NO_PAIR_FUSION", "PLAN_NO_SWIZZLE", "PLAN_SWIZZLE", "PLAN_NONTEMPORAL", "PLAN_TWO_TILES",
+                 "SWIZZLE_MIN_QUBITS", "RUN_NO_PREFIX_SHARING", "RUN_NO_SUPPORT_LISTS"):
+        assert getattr(L, name) == defs[name], name
+    flags = [v for k, v in defs.items() if k.startswith("PLAN_") and k != "PLAN_WAVES_SHIFT"]
+    used = 7 | (15 << defs["PLAN_WAVES_SHIFT"])
+    for f in flags:
+        assert f & (f - 1) == 0, f                  # one bit each
+        assert f & used == 0, f
+        used |= f
+
+
 def test_version_and_last_error():
     assert P.lib().ptsbe_version().decode().startswith("ptsbe")
     with pytest.raises(P.PtsbeError):

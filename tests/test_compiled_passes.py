@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 import paper_2504_16297_amd as P
+from paper_2504_16297_amd import _lib as L
 from compiled_cpu import pass_source, run_compiled
 from gpu_helpers import oracle_states
 from workloads import c1_workload, c3_workload, random_small_circuit
@@ -172,12 +173,13 @@ def test_state_dependent_channels(tile):
         assert float(np.max(np.abs(st[a] - psi))) <= 1e-5, f"trajectory {a}"
 
 
-@pytest.mark.parametrize("swizzle,nontemporal", [(True, False), (False, False), (True, True)])
+@pytest.mark.parametrize("swizzle,nontemporal", [(True, False), (False, False), (True, True), (None, False)])
 def test_swizzled_state_storage(swizzle, nontemporal):
-    """States above 2^12 amplitudes are stored swizzled (runs of 16 amplitudes and
-    blocks of 4096 kept, high index bits XORed onto bits 4..11); the generated
-    kernels address them that way, or plainly with PTSBE_PLAN_NO_SWIZZLE, and
-    the states read back in index order equal the oracle's either way."""
+    """States above 2^12 amplitudes stored swizzled (runs of 16 amplitudes and
+    blocks of 4096 kept, high index bits XORed onto bits 4..11; forced here with
+    PTSBE_PLAN_SWIZZLE, by default only from PTSBE_SWIZZLE_MIN_QUBITS qubits): the
+    generated kernels address them that way, or plainly, and the states read
+    back in index order equal the oracle's either way."""
     from compiled_cpu import storage_positions
     from workloads import brick_circuit
     pos = storage_positions(16)
@@ -187,6 +189,12 @@ def test_swizzled_state_storage(swizzle, nontemporal):
     assert np.array_equal(pos >> 12, np.arange(1 << 16) >> 12)       # 4096-amplitude blocks kept
     circ = brick_circuit(15, 4, np.random.default_rng(6), 0.05, 0.1)
     plan = P.ptsbe_plan(circ, swizzle=swizzle, nontemporal=nontemporal)
+    swizzle = bool(swizzle)                   # 15 qubits: plain order by default
+    assert plan.info["swizzled"] == swizzle
+    big = brick_circuit(L.SWIZZLE_MIN_QUBITS, 1, np.random.default_rng(1), 0.0, 0.0)
+    assert P.ptsbe_plan(big).info["swizzled"] == 1
+    below = brick_circuit(L.SWIZZLE_MIN_QUBITS - 1, 1, np.random.default_rng(1), 0.0, 0.0)
+    assert P.ptsbe_plan(below).info["swizzled"] == 0
     src = "".join(pass_source(plan, p) for p in range(plan.info["n_passes"]))
     assert ("const uint64_t px = " in src) == swizzle
     assert ("stnt(dstp" in src) == nontemporal
@@ -194,3 +202,33 @@ def test_swizzled_state_storage(swizzle, nontemporal):
     st = run_compiled(plan, ts, swizzled=swizzle)
     ref, _ = oracle_states(circ, ts.get()["records"])
     assert max(float(np.max(np.abs(st[a] - ref[a]))) for a in range(len(ref))) <= 1e-5
+
+
+@pytest.mark.parametrize("n,swizzle", [(14, True), (13, False), (17, True)])
+def test_two_tiles_per_workgroup(n, swizzle):
+    """PTSBE_PLAN_TWO_TILES: every forward pass kernel runs tiles 2b and 2b + 1
+    of its state in workgroup b (the second tile's loads issued first, the
+    registers swapped after the first tile's stores), including the
+    initialising pass and, at 17 qubits (the surface code), passes with
+    measure-resets; the states equal the oracle's and those of one tile per
+    workgroup."""
+    if n == 17:
+        circ = c3_workload()["circuit"]
+    else:
+        from workloads import brick_circuit
+        circ = brick_circuit(n, 4, np.random.default_rng(n), 0.05, 0.1)
+    plan2 = P.ptsbe_plan(circ, swizzle=swizzle, two_tiles=True)
+    plan1 = P.ptsbe_plan(circ, swizzle=swizzle)
+    srcs = [pass_source(plan2, p) for p in range(plan2.info["n_passes"])]
+    assert all("tile_id0 = 2ull * blockIdx.x" in s for s in srcs)
+    assert any("s0.x = (base == 0 && tid == 0)" in s for s in srcs)      # the initialising pass
+    if n == 17:
+        assert plan2.info["n_measure"] > 0
+        ts = P.ptsbe_sample_kraus(plan2, "most_likely", k_max=6, total_shots=60, seed=0, cfg=3).slice(0, 3)
+    else:
+        ts = P.ptsbe_sample_kraus(plan2, "proportional", n_draws=3, total_shots=3, seed=4, cfg=1)
+    st2 = run_compiled(plan2, ts)
+    st1 = run_compiled(plan1, ts)
+    assert np.array_equal(st1, st2)
+    ref, _ = oracle_states(circ, ts.get()["records"])
+    assert max(float(np.max(np.abs(st2[a] - ref[a]))) for a in range(len(ref))) <= 1e-5

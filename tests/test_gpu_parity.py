@@ -436,6 +436,51 @@ def test_graph_replays_match_eager(wl_name):
         float((x * x).sum())
 
 
+@pytest.mark.parametrize("n,prec,swizzle,two,tile", [(14, "c64", True, True, 0), (13, "c128", None, True, 0),
+                                                    (14, "c64", False, True, 9), (15, "c64", True, False, 0),
+                                                    (16, "c64", True, False, 10)])
+def test_storage_order_and_two_tiles(n, prec, swizzle, two, tile):
+    """Swizzled storage forced at sizes below its default threshold, plain
+    storage, and compiled forward passes running two tiles per workgroup: the
+    states equal the oracle's and the default plan's."""
+    log(f"[layout] n={n} {prec} swizzle={swizzle} two_tiles={two} tile={tile}")
+    rng = np.random.default_rng(900 + n + tile)
+    circ = random_small_circuit(n, 90, rng, p1=0.1, p2=0.15, with_params=True)
+    params = np.asarray(circ["params"])
+    plan = P.ptsbe_plan(circ, precision=prec, tile_qubits=tile, swizzle=swizzle, two_tiles=two)
+    base = P.ptsbe_plan(circ, precision=prec, tile_qubits=tile)
+    assert plan.info["swizzled"] == bool(swizzle)
+    ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=12, total_shots=12, seed=2, cfg=1)
+    tb = P.ptsbe_sample_kraus(base, "proportional", n_draws=12, total_shots=12, seed=2, cfg=1)
+    a = _states(plan, ts, params=params)
+    b = _states(base, tb, params=params)
+    tol = 1e-5 if prec == "c64" else 1e-12
+    assert float(np.max(np.abs(a - b))) <= tol
+    ref, _ = oracle_states(circ, ts.get()["records"], params=params)
+    err = max(float(np.max(np.abs(a[i] - ref[i]))) for i in range(len(ref)))
+    log(f"  max|d| = {err:.2e}")
+    assert err <= tol
+
+
+def test_two_tiles_surface_code():
+    """Two tiles per workgroup on the surface code's passes (measure-resets
+    decided on the device between them): records and states as with one."""
+    wl = c3_workload()
+    log("[two tiles] surface code")
+    p1 = P.ptsbe_plan(wl["circuit"])
+    p2 = P.ptsbe_plan(wl["circuit"], two_tiles=True)
+    t1 = P.ptsbe_sample_kraus(p1, "most_likely", k_max=64, total_shots=6400, seed=0, cfg=3)
+    t2 = P.ptsbe_sample_kraus(p2, "most_likely", k_max=64, total_shots=6400, seed=0, cfg=3)
+    r1 = P.ptsbe_run_batch(p1, t1, mode="states")
+    r2 = P.ptsbe_run_batch(p2, t2, mode="states")
+    torch.cuda.synchronize()
+    assert torch.equal(r1["mr_bits"], r2["mr_bits"])
+    assert float((r1["states"] - r2["states"]).abs().max()) <= 1e-5
+    ref, _ = oracle_states(wl["circuit"], t2.get()["records"][:4])
+    st = r2["states"].cpu().numpy()
+    assert max(float(np.max(np.abs(st[a] - ref[a]))) for a in range(4)) <= 1e-5
+
+
 @pytest.mark.parametrize("n,prec", [(14, "c64"), (13, "c128")])
 def test_half_tile_register_changes(n, prec):
     """Compiled passes that change register sets through half a tile of LDS."""
