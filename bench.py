@@ -404,6 +404,11 @@ def bench_c2(args):
               "plan_ms": t_plan * 1e3, "pts_ms": t_pts * 1e3, "compile_s": t_compile,
               "compiled_kernels": n_kernels}
 
+    cr = copy_rate(torch, gib=1)
+    result["roofline"]["copy_gbs"] = cr
+    result["roofline"]["frac_of_copy"] = result["roofline"]["achieved"] / cr if result["roofline"]["bound"] == "hbm" \
+        else result["roofline"]["hbm"]["achieved"] / cr
+
     # distinct shots of the last step (Fig. 4's unique fraction), outside the timed steps
     uws = torch.empty(P.ptsbe_unique_workspace_size(ts), dtype=torch.uint8, device="cuda")
     P.ptsbe_unique_shots(ts, out["bits"], workspace=uws, stream=stream)
@@ -498,6 +503,26 @@ def c4_plan(P, wl):
     from paper_2504_16297_amd.tune import tuned_plan_options
     opts, _ = tuned_plan_options(wl["circuit"], wl["precision"])
     return P.ptsbe_plan(wl["circuit"], precision=wl["precision"], **(opts or {})), opts
+
+
+def copy_rate(torch, gib=4, reps=5):
+    """GB/s (bytes read + written) of torch's device-to-device copy of `gib` GiB
+    on the current GPU: a plain streaming kernel that reads and writes every
+    byte once, the practical HBM ceiling beside the 8 TB/s peak."""
+    n = (gib << 30) // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del x, y
+    torch.cuda.empty_cache()
+    return 2.0 * n * 8 / (ms * 1e-3) / 1e9
 
 
 def bench_c4(args):
@@ -605,6 +630,10 @@ def bench_c4(args):
     for r in runs:
         del r["ws"], r["out"]
     torch.cuda.empty_cache()
+    cr = copy_rate(torch)
+    result["roofline"]["copy_gbs"] = cr
+    result["roofline"]["frac_of_copy"] = result["roofline"]["achieved"] / cr
+    log(f"[bench c4] device copy {cr:.0f} GB/s: the passes reach {result['roofline']['achieved'] / cr:.3f} of it")
     if not args.no_baseline:
         r = runs[-1]
         nb = 24

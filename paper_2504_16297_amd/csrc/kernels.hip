@@ -1029,14 +1029,34 @@ __global__ __launch_bounds__(256) void k_marginal(MarginalArgs<V> a) {
       if (j < (int)a.nq && ((x >> a.q[j]) & 1)) s[j + 1] += w;
   };
   if (a.per_block == kScanBlock) {
-    // full block: a thread's 16 loads in flight before the first use (same order of sums)
+    // full block: a thread's 16 loads in flight before the first use.  Its
+    // amplitudes x = e0 + tid + 256 i differ only in index bits 8..11 (the bits
+    // of i), so the thread forms its total and the four sums over i with bit b
+    // set, and a measured qubit takes one of them (bits 8..11) or the total or
+    // nothing (every other bit is fixed for the thread): the same sums, added
+    // in the same order, as accumulating amplitude by amplitude.
     constexpr uint32_t kPer = kScanBlock / 256;
     const uint32_t sx = swizzle_block(blockIdx.x, a.swz);
     double w[kPer];
 #pragma unroll
     for (uint32_t i = 0; i < kPer; ++i) w[i] = norm2(st[e0 + ((threadIdx.x + 256u * i) ^ sx)]);
+    double tot = 0.0, sb[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (uint32_t i = 0; i < kPer; ++i) add(e0 + threadIdx.x + 256u * i, w[i]);
+    for (uint32_t i = 0; i < kPer; ++i) {
+      tot += w[i];
+#pragma unroll
+      for (uint32_t b = 0; b < 4; ++b)
+        if ((i >> b) & 1u) sb[b] += w[i];
+    }
+    const uint64_t xt = e0 + threadIdx.x;
+    s[0] = tot;
+#pragma unroll
+    for (int j = 0; j < kMaxGroup; ++j)
+      if (j < (int)a.nq) {
+        const uint32_t q = a.q[j];
+        const double in_thread = q == 8u ? sb[0] : q == 9u ? sb[1] : q == 10u ? sb[2] : sb[3];  // no indexed registers
+        s[j + 1] = (q >= 8u && q < 12u) ? in_thread : (((xt >> q) & 1ull) ? tot : 0.0);
+      }
   } else {
     for (uint32_t i = threadIdx.x; i < a.per_block; i += blockDim.x) add(e0 + i, norm2(st[e0 + i]));
   }
@@ -1205,16 +1225,23 @@ __device__ void sample_support(const SampleArgs<BitT>& a, double* sh, uint32_t t
   if (threadIdx.x == 0) hoff[nb] = cnt;
   __syncthreads();
   const uint64_t N = a.N;
-  for (uint32_t j = threadIdx.x; j < cnt; j += blockDim.x) {
-    // the last run starting at or before j (empty runs start where the next one does)
-    uint32_t lo = 0, h = nb;
+  // each output position j takes the last run starting at or before j (empty
+  // runs start where the next one does): a bisection for the thread's first
+  // position, then a forward walk, since its positions only increase
+  // (hoff[nb] = cnt > j ends every walk)
+  uint32_t lo = 0;
+  if (threadIdx.x < cnt) {
+    uint32_t h = nb;
     while (h - lo > 1) {
       const uint32_t mid = (lo + h) >> 1;
-      if (hoff[mid] <= j)
+      if (hoff[mid] <= threadIdx.x)
         lo = mid;
       else
         h = mid;
     }
+  }
+  for (uint32_t j = threadIdx.x; j < cnt; j += blockDim.x) {
+    while (hoff[lo + 1] <= j) ++lo;
     const uint64_t l = lo < K ? sidx[lo] : N - 1;
     a.bits[out0 + j] = (BitT)l;
     a.traj[out0 + j] = (uint32_t)alpha;
