@@ -267,6 +267,121 @@ def pass_roofline(flops_per_launch, bytes_per_launch, launch_ms, traffic):
     return r
 
 
+RATE_PROBE_SRC = r"""
+typedef float float4_t __attribute__((ext_vector_type(4)));
+typedef float float16_t __attribute__((ext_vector_type(16)));
+// FP32 FMA on the vector ALU: 8 independent chains per thread
+extern "C" __global__ __launch_bounds__(256) void probe_valu_fma(float* out, int iters, float b, float c) {
+  float a[8];
+  for (int k = 0; k < 8; ++k) a[k] = (float)(threadIdx.x + k);
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a[k] = __builtin_fmaf(a[k], b, c);
+  }
+  float s = 0.f;
+  for (int k = 0; k < 8; ++k) s += a[k];
+  out[blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+// FP32 MFMA 16x16x4: 4 independent accumulators per wavefront
+extern "C" __global__ __launch_bounds__(256) void probe_mfma_16x16x4(float* out, int iters, float b, float c) {
+  float4_t acc[4];
+  for (int k = 0; k < 4; ++k) acc[k] = (float4_t){c, c, c, c};
+  const float x = (float)threadIdx.x * b;
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(x, b, acc[k], 0, 0, 0);
+  }
+  float s = 0.f;
+  for (int k = 0; k < 4; ++k) s += acc[k].x + acc[k].y + acc[k].z + acc[k].w;
+  out[blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+// FP32 MFMA 32x32x2: 2 independent accumulators per wavefront
+extern "C" __global__ __launch_bounds__(256) void probe_mfma_32x32x2(float* out, int iters, float b, float c) {
+  float16_t acc[2];
+  for (int k = 0; k < 2; ++k)
+    for (int e = 0; e < 16; ++e) acc[k][e] = c;
+  const float x = (float)threadIdx.x * b;
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) acc[k] = __builtin_amdgcn_mfma_f32_32x32x2f32(x, b, acc[k], 0, 0, 0);
+  }
+  float s = 0.f;
+  for (int k = 0; k < 2; ++k)
+    for (int e = 0; e < 16; ++e) s += acc[k][e];
+  out[blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+"""
+
+
+def rate_probe():
+    """FP32 issue rates of this GPU for the choice between the vector ALU and
+    the matrix cores (MFMA) in the gate kernels: a kernel of independent
+    v_fma_f32 chains and kernels of back-to-back FP32 MFMA (16x16x4, 32x32x2),
+    compiled here with hiprtc, each launched over 4096 workgroups of 256
+    threads and timed with events on torch's stream; prints one JSON line."""
+    import ctypes as C
+
+    import torch
+    torch.cuda.set_device(0)
+    rtc = C.CDLL("libhiprtc.so")
+    hip = C.CDLL("libamdhip64.so")
+    prog = C.c_void_p()
+    if rtc.hiprtcCreateProgram(C.byref(prog), RATE_PROBE_SRC.encode(), b"rate_probe.hip", 0, None, None) != 0:
+        raise SystemExit("hiprtcCreateProgram failed")
+    opts = [b"--offload-arch=gfx950", b"-O3", b"-std=c++17", b"-Xclang", b"-target-feature", b"-Xclang",
+            b"-packed-fp32-ops"]
+    if rtc.hiprtcCompileProgram(prog, len(opts), (C.c_char_p * len(opts))(*opts)) != 0:
+        n = C.c_size_t()
+        rtc.hiprtcGetProgramLogSize(prog, C.byref(n))
+        buf = C.create_string_buffer(n.value + 1)
+        rtc.hiprtcGetProgramLog(prog, buf)
+        raise SystemExit("rate probe does not compile:\n" + buf.value.decode(errors="replace"))
+    n = C.c_size_t()
+    rtc.hiprtcGetCodeSize(prog, C.byref(n))
+    code = C.create_string_buffer(n.value)
+    rtc.hiprtcGetCode(prog, code)
+    mod = C.c_void_p()
+    if hip.hipModuleLoadData(C.byref(mod), code) != 0:
+        raise SystemExit("hipModuleLoadData failed")
+    blocks, threads = 4096, 256
+    out = torch.empty(blocks * threads, dtype=torch.float32, device="cuda")
+    stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    # (iterations, flops per launch): 8 chains x 2 flops per lane and iteration;
+    # MFMA 2*M*N*K per wavefront instruction, 4 (16x16x4) or 2 (32x32x2) per
+    # iteration; each launch about 50 ms
+    waves = blocks * threads // 64
+    kernels = {"probe_valu_fma": (512, 2 * 8 * 512 * blocks * threads),
+               "probe_mfma_16x16x4": (64, 2 * 16 * 16 * 4 * 4 * 64 * waves),
+               "probe_mfma_32x32x2": (64, 2 * 32 * 32 * 2 * 2 * 64 * waves)}
+    res = {}
+    for name, (iters, flops) in kernels.items():
+        fn = C.c_void_p()
+        if hip.hipModuleGetFunction(C.byref(fn), mod, name.encode()) != 0:
+            raise SystemExit(f"no kernel {name}")
+        a_out = C.c_void_p(out.data_ptr())
+        a_it, a_b, a_c = C.c_int(iters), C.c_float(0.999), C.c_float(1e-3)
+        params = (C.c_void_p * 4)(C.cast(C.byref(a_out), C.c_void_p), C.cast(C.byref(a_it), C.c_void_p),
+                                  C.cast(C.byref(a_b), C.c_void_p), C.cast(C.byref(a_c), C.c_void_p))
+
+        def launch():
+            if hip.hipModuleLaunchKernel(fn, blocks, 1, 1, threads, 1, 1, 0, stream, params, None) != 0:
+                raise SystemExit(f"launch of {name} failed")
+
+        launch()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            launch()
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / 5
+        res[name] = {"ms": ms, "iterations": iters, "tflops": flops / (ms * 1e-3) / 1e12}
+        log(f"[rate probe] {name}: {res[name]['tflops']:.1f} TFLOP/s ({ms:.3f} ms)")
+    print(json.dumps({"rate_probe": res, "fp32_vector_peak_tflops": FP32_PEAK_TFLOPS,
+                      "launch": {"blocks": blocks, "threads": threads}}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -281,6 +396,8 @@ def main():
     ap.add_argument("--q35", action="store_true", help="also time one 35-qubit trajectory (c4)")
     ap.add_argument("--no-errors", action="store_true",
                     help="skip the 24-qubit trajectory's comparison with the stored oracle values (c4)")
+    ap.add_argument("--rate-probe", action="store_true",
+                    help="only measure the FP32 rates of the vector ALU and of FP32 MFMA on this GPU")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 2 GiB device copy (calibrates FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--workload", default="c4", choices=["c2", "c3", "c4", "c5"],
@@ -299,6 +416,8 @@ def main():
         else:
             raise SystemExit("--fingerprint: c2 or c4")
         return
+    if args.rate_probe:
+        return rate_probe()
     if args.copy_probe:
         import torch
         n = 1 << 28                      # 2^28 float64 = 2 GiB read + 2 GiB written per copy

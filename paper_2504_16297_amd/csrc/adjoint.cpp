@@ -223,11 +223,15 @@ ptsbe_status adjoint_typed(const Plan& P, TrajSet& ts, const double* coef, const
       }
       const Pass& ps = P.passes[ex.pass];
       fa.pass = (uint32_t)ex.pass;
-      if (jit_has(P, (uint32_t)ex.pass))
+      if (jit_has(P, (uint32_t)ex.pass)) {
         CK(jit_launch<V>(P, (uint32_t)ex.pass, fa, bb, s), "compiled forward");
-      else
+      } else {
+        if (ps.k > 12)  // the generic kernels hold at most 12-qubit tiles
+          return fail(PTSBE_E_UNSUPPORTED, "forward pass " + std::to_string(ex.pass) +
+                                               " has a 13-qubit tile and no compiled kernel");
         CK(launch_pass<V>(fa, (uint32_t)ps.k, (uint32_t)ps.slots.size(), (uint32_t)ps.ops.size(), bb, s),
            "forward");
+      }
     }
     ScanArgs<V> sa{};
     sa.swz = fa.swz;

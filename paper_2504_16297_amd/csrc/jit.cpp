@@ -662,7 +662,7 @@ namespace {
 std::string gen_pass(const Pass& ps, int n, int precision, const std::string& name, bool split, bool dual,
                      int waves, bool swz, bool nt, int tpb, bool* needs_full) {
   const int k = ps.k;
-  if (k < (int)kMinRegTile || k > 12) return "";
+  if (k < (int)kMinRegTile || k > 13 || (dual && k > 12)) return "";
   if (dual && (ps.flags & PASS_INIT_ZERO)) return "";
   // two tiles per workgroup: tiles 2b and 2b + 1 of the block's state (they
   // differ in the lowest qubit outside the tile); forward passes only
@@ -703,7 +703,7 @@ std::string gen_pass(const Pass& ps, int n, int precision, const std::string& na
     << "struct PassArgs { " << kArgsFields << " };\n"
     << "static_assert(sizeof(PassArgs) == " << sizeof(PassArgs<float2>) << ", \"PassArgs layout\");\n"
     << kHelpers << (dual ? kDualHelpers : "");
-  o << "extern \"C\" __global__ __launch_bounds__(256) ";
+  o << "extern \"C\" __global__ __launch_bounds__(" << std::max(256, 1 << (k - 4)) << ") ";
   if (waves > 0) o << "__attribute__((amdgpu_waves_per_eu(" << waves << "))) ";
   o << "void " << name << "(PassArgs a"
     << (dual ? ", V* lam, double* partial, uint32_t n_dot" : "") << ") {\n"
@@ -1092,6 +1092,23 @@ bool jit_loaded(const Plan& P) {
   return P.jit->functions.count(dev) != 0;
 }
 
+// Dynamic LDS a workgroup may hold on the current device (160 KiB on gfx950).
+size_t max_lds_per_block() {
+  static std::mutex mu;
+  static std::map<int, size_t> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 65536;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(dev);
+  if (it != cache.end()) return it->second;
+  int v = 0;
+  const size_t m = hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0
+                       ? (size_t)v
+                       : 65536;
+  cache[dev] = m;
+  return m;
+}
+
 template <typename V>
 hipError_t jit_launch(const Plan& P, uint32_t pass, const PassArgs<V>& a, uint32_t rows, hipStream_t s) {
   const std::vector<hipFunction_t>* fns = nullptr;
@@ -1103,7 +1120,7 @@ hipError_t jit_launch(const Plan& P, uint32_t pass, const PassArgs<V>& a, uint32
   const size_t te = P.jit->tile_elems[P.jit->pass_kernel[pass]];
   const uint32_t tpb = P.jit->tiles_per_block[P.jit->pass_kernel[pass]];
   const size_t lds = sizeof(V) * (te + lds_mat_entries(ps)) + 4 * ((size_t)n_slots + (n_slots + 31) / 32);
-  if (lds > 65536) return hipErrorInvalidConfiguration;
+  if (lds > max_lds_per_block()) return hipErrorInvalidConfiguration;
   if (tpb != 1 && (tpb != 2 || P.n <= (int)k)) return hipErrorInvalidConfiguration;
   PassArgs<V> la = a;
   uint32_t slot_begin = 0;

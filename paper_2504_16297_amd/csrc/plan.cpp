@@ -1116,10 +1116,13 @@ ptsbe_status build_plan(const ptsbe_circuit* c, const ptsbe_noise_model* nm, con
   if (P.precision != PTSBE_C64 && P.precision != PTSBE_C128) return fail(PTSBE_E_ARG, "bad precision");
   int tb = (P.precision == PTSBE_C64) ? 12 : 11;
   if (o && o->tile_qubits) {
-    if (o->tile_qubits < 4 || o->tile_qubits > 12)
-      return fail(PTSBE_E_ARG, "tile_qubits must be in 4..12");
+    if (o->tile_qubits < 4 || o->tile_qubits > 13)
+      return fail(PTSBE_E_ARG, "tile_qubits must be in 4..13");
     tb = (int)o->tile_qubits;
     if (P.precision == PTSBE_C128 && tb > 12) return fail(PTSBE_E_ARG, "tile_qubits <= 12 for complex128");
+    // 13-qubit tiles (512 threads, 64 KiB of LDS) exist only as compiled passes
+    if (tb > 12 && (o->flags & PTSBE_PLAN_NO_COMPILE))
+      return fail(PTSBE_E_ARG, "tile_qubits 13 needs the compiled passes (no PTSBE_PLAN_NO_COMPILE)");
   }
   P.tile_bits = tb;
   // flags bits 0..2: phase-scheduler fill threshold (0 = default 2)

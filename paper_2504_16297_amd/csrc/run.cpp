@@ -358,11 +358,15 @@ ptsbe_status run_typed(const Plan& P, TrajSet& ts, const ptsbe_run_opts& o, uint
           rows = r1 - r0;
           pa.route = d_routes + r0;
         }
-        if (rows && use_jit && jit_has(P, (uint32_t)ex.pass))
+        if (rows && use_jit && jit_has(P, (uint32_t)ex.pass)) {
           CK(jit_launch<V>(P, (uint32_t)ex.pass, pa, rows, s), "compiled tile pass");
-        else if (rows)
+        } else if (rows) {
+          if (ps.k > 12)  // the generic kernels hold at most 12-qubit tiles
+            return fail(PTSBE_E_UNSUPPORTED, "pass " + std::to_string(ex.pass) +
+                                                 " has a 13-qubit tile and no compiled kernel loaded here");
           CK(launch_pass<V>(pa, (uint32_t)ps.k, (uint32_t)ps.slots.size(), (uint32_t)ps.ops.size(), rows, s),
              "tile pass");
+        }
         CK(tm.mark(T_PASS), "timer");
         if (timed) {
           o.timing[1] += 1;

@@ -34,10 +34,10 @@ from . import (ptsbe_plan, ptsbe_plan_compile, ptsbe_run_batch, ptsbe_trajset_fr
 def candidates_for(n, precision):
     """(tile_qubits, min_fill, half_tile, pair_fusion) candidates: the two largest
     register-kernel tiles that fit n qubits (0 = the planner's choice when none
-    does), fill 2 or 3, whole or half-tile register changes, pair fusion on or
-    off."""
-    top = 12 if precision == "c64" else 11
-    tiles = [t for t in (top, top - 1) if 6 <= t <= n] or [0]
+    does; 13-qubit tiles for complex64 only), fill 2 or 3, whole or half-tile
+    register changes, pair fusion on or off."""
+    top = 13 if precision == "c64" else 11
+    tiles = [t for t in range(top, 5, -1) if t <= n][:2] or [0]
     return [(t, f, h, pf) for t in tiles for f in (2, 3) for h in (False, True) for pf in (True, False)]
 
 
@@ -110,17 +110,18 @@ def load_cache(path=None):
         return json.load(f)
 
 
-def tuned_plan_options(circuit, precision="c64", cache=None, tune_if_missing=False, **kw):
+def tuned_plan_options(circuit, precision="c64", cache=None, tune_if_missing=False, retune=False, **kw):
     """ptsbe_plan keyword arguments for `circuit` from the tuning cache, tuning
-    (and storing the pick) on a miss if `tune_if_missing`, else None on a miss.
+    (and storing the pick) on a miss if `tune_if_missing`, else None on a miss;
+    `retune` tunes and replaces the entry even on a hit.
     Returns (options or None, cache entry or None)."""
     cands = kw.get("candidates") or candidates_for(circuit["n_qubits"], precision)
     kw["candidates"] = cands
     key = circuit_key(circuit, precision)
     path = _cache_path(cache)
     entries = load_cache(path)
-    e = entries.get(key)
-    if e is None and tune_if_missing:
+    e = None if retune else entries.get(key)
+    if e is None and (tune_if_missing or retune):
         r = autotune(circuit, precision=precision, **kw)
         e = {"n_qubits": circuit["n_qubits"], "precision": precision,
              "pick": {k: r[k] for k in ("tile_qubits", "min_fill", "half_tile", "pair_fusion")},
@@ -145,12 +146,16 @@ def main(argv=None):
     ap.add_argument("--cache", default=None)
     ap.add_argument("--sample", type=int, default=0, help="trajectories timed per candidate (0: by state size)")
     ap.add_argument("--candidates", default=None,
-                    help="comma-separated tile:fill pairs (whole-tile register changes, pair fusion on); "
-                         "default: the full candidate set")
+                    help="comma-separated tile:fill or tile:fill:h (h: half-tile register changes) entries, "
+                         "pair fusion on; default: the full candidate set")
+    ap.add_argument("--retune", action="store_true", help="tune again even where the cache has a pick")
     a = ap.parse_args(argv)
     cands = None
     if a.candidates:
-        cands = [(int(t), int(f), False, True) for t, f in (c.split(":") for c in a.candidates.split(","))]
+        cands = []
+        for c in a.candidates.split(","):
+            f = c.split(":")
+            cands.append((int(f[0]), int(f[1]), len(f) > 2 and f[2] == "h", True))
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     if root not in sys.path:
         sys.path.insert(0, root)
@@ -171,7 +176,7 @@ def main(argv=None):
                                 seed=wl["seed"], cfg=wl["cfg"])
         state = (8 if wl["precision"] == "c64" else 16) << n
         sample = a.sample or int(max(1, min(64, (8 << 30) // state)))
-        opts, e = tuned_plan_options(circ, wl["precision"], cache=a.cache, tune_if_missing=True,
+        opts, e = tuned_plan_options(circ, wl["precision"], cache=a.cache, tune_if_missing=True, retune=a.retune,
                                      records=ts.get()["records"], sample=sample, log=log, candidates=cands)
         log(f"[tune] {n} qubits: {opts} ({e['seconds']:.0f} s)")
 

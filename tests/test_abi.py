@@ -52,6 +52,17 @@ def test_flag_constants_match_the_header():
         used |= f
 
 
+def test_tile_size_limits():
+    """13-qubit tiles exist for complex64 compiled passes only."""
+    circ = random_small_circuit(14, 20, np.random.default_rng(3))
+    assert P.ptsbe_plan(circ, tile_qubits=13).info["tile_qubits"] == 13
+    for kw in ({"tile_qubits": 14}, {"tile_qubits": 13, "precision": "c128"},
+               {"tile_qubits": 13, "compile": False}, {"tile_qubits": 3}):
+        with pytest.raises(P.PtsbeError) as e:
+            P.ptsbe_plan(circ, **kw)
+        assert e.value.status == E_ARG, kw
+
+
 def test_version_and_last_error():
     assert P.lib().ptsbe_version().decode().startswith("ptsbe")
     with pytest.raises(P.PtsbeError):

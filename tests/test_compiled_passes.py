@@ -232,3 +232,21 @@ def test_two_tiles_per_workgroup(n, swizzle):
     assert np.array_equal(st1, st2)
     ref, _ = oracle_states(circ, ts.get()["records"])
     assert max(float(np.max(np.abs(st2[a] - ref[a]))) for a in range(len(ref))) <= 1e-5
+
+
+@pytest.mark.parametrize("n,swizzle,half", [(14, True, False), (13, None, False), (15, False, True)])
+def test_thirteen_qubit_tiles(n, swizzle, half):
+    """13-qubit tiles (512 threads x 16 amplitudes, 64 KiB of LDS, or 32 KiB in
+    two rounds): fewer passes for the same circuit, the states equal the
+    oracle's."""
+    from workloads import brick_circuit
+    circ = brick_circuit(n, 5, np.random.default_rng(40 + n), 0.05, 0.1, eps_sigma=0.05)
+    plan = P.ptsbe_plan(circ, tile_qubits=13, swizzle=swizzle, half_tile=half)
+    assert plan.info["tile_qubits"] == 13
+    assert plan.info["n_passes"] <= P.ptsbe_plan(circ, tile_qubits=12).info["n_passes"]
+    srcs = [pass_source(plan, p) for p in range(plan.info["n_passes"])]
+    assert all("__launch_bounds__(512)" in s for s in srcs)
+    ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=3, total_shots=3, seed=6, cfg=2)
+    st = run_compiled(plan, ts)
+    ref, _ = oracle_states(circ, ts.get()["records"])
+    assert max(float(np.max(np.abs(st[a] - ref[a]))) for a in range(len(ref))) <= 1e-5

@@ -63,12 +63,15 @@ def test_per_shot_baseline_matches_algorithm_1():
     assert np.array_equal(r2["bits"][:n_shots].cpu().numpy(), r["bits"][:n_shots].cpu().numpy())
 
 
-def test_c4_24q_trajectory_against_oracle():
+@pytest.mark.parametrize("tile", [0, 13])
+def test_c4_24q_trajectory_against_oracle(tile):
+    """One 24-qubit trajectory of the mixed batch against stored oracle values,
+    with the default 12-qubit tiles and with 13-qubit tiles (512 threads)."""
     gold = np.load(GOLDEN_C4)
     wl = c4_workload(24)
     circ = wl["circuit"]
     alpha = int(gold["alpha"])
-    plan = P.ptsbe_plan(circ, precision=wl["precision"])
+    plan = P.ptsbe_plan(circ, precision=wl["precision"], tile_qubits=tile)
     pts = wl["pts"]
     ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=pts["n_draws"], total_shots=pts["total_shots"],
                               seed=wl["seed"], cfg=wl["cfg"])

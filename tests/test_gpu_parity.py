@@ -438,11 +438,13 @@ def test_graph_replays_match_eager(wl_name):
 
 @pytest.mark.parametrize("n,prec,swizzle,two,tile", [(14, "c64", True, True, 0), (13, "c128", None, True, 0),
                                                     (14, "c64", False, True, 9), (15, "c64", True, False, 0),
-                                                    (16, "c64", True, False, 10)])
+                                                    (16, "c64", True, False, 10), (14, "c64", True, False, 13),
+                                                    (15, "c64", None, False, 13), (13, "c64", None, False, 13)])
 def test_storage_order_and_two_tiles(n, prec, swizzle, two, tile):
     """Swizzled storage forced at sizes below its default threshold, plain
-    storage, and compiled forward passes running two tiles per workgroup: the
-    states equal the oracle's and the default plan's."""
+    storage, compiled forward passes running two tiles per workgroup, and
+    13-qubit tiles (512 threads, 64 KiB of LDS): the states equal the oracle's
+    and the default plan's."""
     log(f"[layout] n={n} {prec} swizzle={swizzle} two_tiles={two} tile={tile}")
     rng = np.random.default_rng(900 + n + tile)
     circ = random_small_circuit(n, 90, rng, p1=0.1, p2=0.15, with_params=True)
@@ -462,13 +464,15 @@ def test_storage_order_and_two_tiles(n, prec, swizzle, two, tile):
     assert err <= tol
 
 
-def test_two_tiles_surface_code():
-    """Two tiles per workgroup on the surface code's passes (measure-resets
-    decided on the device between them): records and states as with one."""
+@pytest.mark.parametrize("kw", [{"two_tiles": True}, {"tile_qubits": 13}])
+def test_two_tiles_surface_code(kw):
+    """Two tiles per workgroup, and 13-qubit tiles, on the surface code's
+    passes (measure-resets decided on the device between them): records and
+    states as with the default plan."""
     wl = c3_workload()
-    log("[two tiles] surface code")
+    log(f"[{kw}] surface code")
     p1 = P.ptsbe_plan(wl["circuit"])
-    p2 = P.ptsbe_plan(wl["circuit"], two_tiles=True)
+    p2 = P.ptsbe_plan(wl["circuit"], **kw)
     t1 = P.ptsbe_sample_kraus(p1, "most_likely", k_max=64, total_shots=6400, seed=0, cfg=3)
     t2 = P.ptsbe_sample_kraus(p2, "most_likely", k_max=64, total_shots=6400, seed=0, cfg=3)
     r1 = P.ptsbe_run_batch(p1, t1, mode="states")
