@@ -32,8 +32,12 @@ sys.path.insert(0, ROOT)
 
 METRIC = "shots/s batched PTSBE vs per-shot trajectories; gate-kernel HBM GB/s"
 HBM_PEAK_GBS = 8000.0
-# FP32 vector peak of MI355X: 256 CUs x 2.4 GHz x 256 FLOP/clk/CU
-FP32_PEAK_TFLOPS = 157.3
+# FP32 vector peak of MI355X: 256 CUs x 2.4 GHz x 256 FLOP/clk/CU counts packed
+# FP32 (two FMAs per lane and instruction).  The kernels here are built without
+# packed FP32, so their ALU roof is half of it: 256 CUs x 4 SIMDs x 16 lanes x
+# 2 FLOP (one FMA) x 2.4 GHz = 78.6 TFLOP/s (bench.py --rate-probe measures it).
+FP32_PEAK_TFLOPS_PACKED = 157.3
+FP32_PEAK_TFLOPS = 78.6
 TRAFFIC_SUMMARY = {"c2": os.path.join(ROOT, "profiles", "tile_pass_c2_traffic.md"),
                    "c4": os.path.join(ROOT, "profiles", "tile_pass_c4_traffic.md")}
 GOLDEN_C4 = os.path.join(ROOT, "tests", "golden", "c4_24q_trajectory.npz")
@@ -378,7 +382,8 @@ def rate_probe():
         ms = e0.elapsed_time(e1) / 5
         res[name] = {"ms": ms, "iterations": iters, "tflops": flops / (ms * 1e-3) / 1e12}
         log(f"[rate probe] {name}: {res[name]['tflops']:.1f} TFLOP/s ({ms:.3f} ms)")
-    print(json.dumps({"rate_probe": res, "fp32_vector_peak_tflops": FP32_PEAK_TFLOPS,
+    print(json.dumps({"rate_probe": res, "fp32_vector_peak_tflops_unpacked": FP32_PEAK_TFLOPS,
+                      "fp32_vector_peak_tflops_packed": FP32_PEAK_TFLOPS_PACKED,
                       "launch": {"blocks": blocks, "threads": threads}}))
 
 
