@@ -34,9 +34,10 @@ from . import (ptsbe_plan, ptsbe_plan_compile, ptsbe_run_batch, ptsbe_trajset_fr
 def candidates_for(n, precision):
     """(tile_qubits, min_fill, half_tile, pair_fusion) candidates: the two largest
     register-kernel tiles that fit n qubits (0 = the planner's choice when none
-    does; 13-qubit tiles for complex64 only), fill 2 or 3, whole or half-tile
-    register changes, pair fusion on or off."""
-    top = 13 if precision == "c64" else 11
+    does), fill 2 or 3, whole or half-tile register changes, pair fusion on or
+    off.  13-qubit tiles (complex64) are left out: they measured slower on every
+    size tried; name them with `candidates` to try them."""
+    top = 12 if precision == "c64" else 11
     tiles = [t for t in range(top, 5, -1) if t <= n][:2] or [0]
     return [(t, f, h, pf) for t in tiles for f in (2, 3) for h in (False, True) for pf in (True, False)]
 

@@ -258,14 +258,14 @@ def test_state_dependent_channels_in_forward_and_reverse_programs():
 
 
 def test_autotune_candidates():
-    """The tuner's candidates: the two largest register-kernel tiles that fit
-    (13 qubits only for complex64), fill 2 or 3, whole or half-tile register
-    changes, pair fusion on or off; each builds a plan."""
+    """The tuner's candidates: the two largest register-kernel tiles that fit,
+    fill 2 or 3, whole or half-tile register changes, pair fusion on or off;
+    each builds a plan."""
     from paper_2504_16297_amd.tune import candidates_for
     c = candidates_for(20, "c64")
     assert len(c) == 16 and len(set(c)) == 16
-    assert {t for t, _, _, _ in c} == {13, 12} and {pf for _, _, _, pf in c} == {True, False}
-    assert {t for t, _, _, _ in candidates_for(12, "c64")} == {12, 11}
+    assert {t for t, _, _, _ in c} == {12, 11} and {pf for _, _, _, pf in c} == {True, False}
+    assert {t for t, _, _, _ in candidates_for(11, "c64")} == {11, 10}
     assert {t for t, _, _, _ in candidates_for(20, "c128")} == {11, 10}
     assert {t for t, _, _, _ in candidates_for(4, "c64")} == {0}
     circ = random_small_circuit(8, 30, np.random.default_rng(2))
