@@ -116,7 +116,7 @@ def ptsbe_plan_compile(plan):
 
 def ptsbe_plan(circuit, precision="c64", tile_qubits=0, compile=True, min_fill=0, half_tile=False,
                phase_frames=True, waves=0, twirl=False, pair_fusion=True, swizzle=None, nontemporal=False,
-               two_tiles=False):
+               two_tiles=False, tile_search=True):
     """Build the execution plan of a circuit dictionary (ops, channels, rules).
     ``compile=False`` runs the passes through the generic tile kernels instead of
     per-pass compiled kernels; ``min_fill`` (1..7, 0 = 2) is the fewest 2x2
@@ -130,7 +130,9 @@ def ptsbe_plan(circuit, precision="c64", tile_qubits=0, compile=True, min_fill=0
     stores states of PTSBE_SWIZZLE_MIN_QUBITS qubits or more swizzled, True every state above
     12 qubits (PTSBE_PLAN_SWIZZLE), False none (PTSBE_PLAN_NO_SWIZZLE); ``nontemporal`` gives
     the compiled passes' state loads and stores streaming cache hints; ``two_tiles`` has each
-    workgroup of a compiled forward pass run two tiles (PTSBE_PLAN_TWO_TILES)."""
+    workgroup of a compiled forward pass run two tiles (PTSBE_PLAN_TWO_TILES);
+    ``tile_search=False`` builds every tile greedily in circuit order only
+    (PTSBE_PLAN_NO_TILE_SEARCH)."""
     ops = circuit["ops"]
     arr = (L.Op * max(1, len(ops)))()
     keep = []
@@ -201,7 +203,8 @@ def ptsbe_plan(circuit, precision="c64", tile_qubits=0, compile=True, min_fill=0
                     (0 if phase_frames else L.PLAN_NO_PHASE_FRAMES) | (int(waves) << L.PLAN_WAVES_SHIFT) |
                     (L.PLAN_TWIRL if twirl else 0) | (0 if pair_fusion else L.PLAN_NO_PAIR_FUSION) |
                     ({None: 0, True: L.PLAN_SWIZZLE, False: L.PLAN_NO_SWIZZLE}[swizzle]) |
-                    (L.PLAN_NONTEMPORAL if nontemporal else 0) | (L.PLAN_TWO_TILES if two_tiles else 0), 0)
+                    (L.PLAN_NONTEMPORAL if nontemporal else 0) | (L.PLAN_TWO_TILES if two_tiles else 0) |
+                    (0 if tile_search else L.PLAN_NO_TILE_SEARCH), 0)
     h = C.c_void_p()
     check(lib().ptsbe_plan(C.byref(c), C.byref(nm), C.byref(po), C.byref(h)))
     return Plan(h, None)

@@ -37,6 +37,7 @@ PLAN_NONTEMPORAL = 16384
 PLAN_TWO_TILES = 32768
 PLAN_SWIZZLE = 8192
 SWIZZLE_MIN_QUBITS = 22
+PLAN_NO_TILE_SEARCH = 65536
 NOALLOC_SCRATCH_BYTES = 64 << 20
 
 

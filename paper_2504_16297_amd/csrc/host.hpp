@@ -182,6 +182,7 @@ struct Plan {
   bool swizzle = true;         // states stored at swizzle(x) (kernels.hpp)
   bool nontemporal = false;    // compiled passes load and store the states with nontemporal hints
   int tiles_per_block = 1;     // tiles of a state one workgroup of a compiled forward pass runs
+  bool tile_search = true;     // each pass's tile: the best of the greedy one and qubit windows
   std::shared_ptr<JitProgram> jit;
 };
 

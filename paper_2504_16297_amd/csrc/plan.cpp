@@ -797,49 +797,82 @@ static ptsbe_status schedule(Plan& plan, const std::vector<Step>& steps, std::ve
   int guard = 0;
   while (!rem.empty()) {
     if (++guard > 1000000) return fail(PTSBE_E_ARG, "scheduler made no progress");
-    // greedy tile choice + take, in circuit order
-    std::vector<char> inQ(n, 0), blocked(n, 0);
+    // greedy tile choice + take, in circuit order, from an initial tile set
+    std::vector<char> inQ;
     int qcount = 0;
-    for (int q = 0; q < contiguous; ++q) {
-      inQ[q] = 1;
-      ++qcount;
-    }
     std::vector<int> taken, keep;
-    // A state-dependent channel not yet decided (forward) or restored (reverse
-    // sweep) is a wall: nothing after it runs before it, so that the state at
-    // its decision is the state at its place in the circuit (the checkpoint
-    // the reverse sweep restores).
-    bool wall = false;
-    for (int si : rem) {
-      const Step& st = steps[si];
-      bool blk = wall;
-      for (int j = 0; j < st.nq; ++j) blk = blk || blocked[st.q[j]];
-      if (st.kind == ST_GCH && !measured[si]) wall = true;
-      bool can = false;
-      if (!blk) {
-        if ((st.kind == ST_MR || st.kind == ST_GCH) && !measured[si]) {
-          can = false;
-        } else if (st.diag && st.kind != ST_MR) {
-          can = true;
-        } else {
-          int nnew = 0;
-          for (int j = 0; j < st.nq; ++j) nnew += inQ[st.q[j]] ? 0 : 1;
-          if (qcount + nnew <= k) {
-            for (int j = 0; j < st.nq; ++j)
-              if (!inQ[st.q[j]]) {
-                inQ[st.q[j]] = 1;
-                ++qcount;
-              }
+    auto take_with = [&](const std::vector<char>& init) {
+      inQ = init;
+      qcount = 0;
+      for (int q = 0; q < n; ++q) qcount += inQ[q];
+      std::vector<char> blocked(n, 0);
+      taken.clear();
+      keep.clear();
+      // A state-dependent channel not yet decided (forward) or restored (reverse
+      // sweep) is a wall: nothing after it runs before it, so that the state at
+      // its decision is the state at its place in the circuit (the checkpoint
+      // the reverse sweep restores).
+      bool wall = false;
+      for (int si : rem) {
+        const Step& st = steps[si];
+        bool blk = wall;
+        for (int j = 0; j < st.nq; ++j) blk = blk || blocked[st.q[j]];
+        if (st.kind == ST_GCH && !measured[si]) wall = true;
+        bool can = false;
+        if (!blk) {
+          if ((st.kind == ST_MR || st.kind == ST_GCH) && !measured[si]) {
+            can = false;
+          } else if (st.diag && st.kind != ST_MR) {
             can = true;
+          } else {
+            int nnew = 0;
+            for (int j = 0; j < st.nq; ++j) nnew += inQ[st.q[j]] ? 0 : 1;
+            if (qcount + nnew <= k) {
+              for (int j = 0; j < st.nq; ++j)
+                if (!inQ[st.q[j]]) {
+                  inQ[st.q[j]] = 1;
+                  ++qcount;
+                }
+              can = true;
+            }
           }
         }
+        if (can) {
+          taken.push_back(si);
+        } else {
+          for (int j = 0; j < st.nq; ++j) blocked[st.q[j]] = 1;
+          keep.push_back(si);
+        }
       }
-      if (can) {
-        taken.push_back(si);
-      } else {
-        for (int j = 0; j < st.nq; ++j) blocked[st.q[j]] = 1;
-        keep.push_back(si);
+    };
+    auto score = [&]() {
+      int c = 0;
+      for (int si : taken) c += steps[si].diag ? 0 : 1;
+      return c;
+    };
+    std::vector<char> base(n, 0);
+    for (int q = 0; q < contiguous; ++q) base[q] = 1;
+    take_with(base);
+    if (plan.tile_search && !taken.empty() && n > k) {
+      // Tile search: the tile whose greedy take runs the most non-diagonal
+      // operations, among the plain greedy one and every window of consecutive
+      // qubits beside the contiguous ones (on brick-like circuits a window
+      // follows a light cone through many layers, where circuit order stops
+      // at the first layer's boundary).
+      int best = score();
+      std::vector<char> best_init = base;
+      const int free = k - contiguous;
+      for (int w = contiguous; w + free <= n; ++w) {
+        std::vector<char> init = base;
+        for (int q = w; q < w + free; ++q) init[q] = 1;
+        take_with(init);
+        const int sc = score();
+        if (sc > best) {
+          best = sc;
+          best_init = init;
+        }
       }
+      take_with(best_init);
     }
     if (taken.empty() && steps[rem[0]].kind == ST_GCH && steps[rem[0]].dagger) {
       // reverse sweep at a state-dependent channel: restore the state
@@ -1138,6 +1171,7 @@ ptsbe_status build_plan(const ptsbe_circuit* c, const ptsbe_noise_model* nm, con
                                                          : P.n >= (int)PTSBE_SWIZZLE_MIN_QUBITS;
   P.nontemporal = o && (o->flags & PTSBE_PLAN_NONTEMPORAL);
   P.tiles_per_block = (o && (o->flags & PTSBE_PLAN_TWO_TILES)) ? 2 : 1;
+  P.tile_search = !(o && (o->flags & PTSBE_PLAN_NO_TILE_SEARCH));
   if (P.waves > 8) return fail(PTSBE_E_ARG, "waves per SIMD must be 0 (default) or 1..8");
   P.jit = std::make_shared<JitProgram>();
   // channels

@@ -42,6 +42,7 @@ def test_flag_constants_match_the_header():
     defs = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define PTSBE_(\w+) (\d+)u\b", src)}
     for name in ("PLAN_NO_COMPILE", "PLAN_HALF_TILE_LDS", "PLAN_NO_PHASE_FRAMES", "PLAN_WAVES_SHIFT", "PLAN_TWIRL",
                  "PLAN_NO_PAIR_FUSION", "PLAN_NO_SWIZZLE", "PLAN_SWIZZLE", "PLAN_NONTEMPORAL", "PLAN_TWO_TILES",
+                 "PLAN_NO_TILE_SEARCH",
                  "SWIZZLE_MIN_QUBITS", "RUN_NO_PREFIX_SHARING", "RUN_NO_SUPPORT_LISTS"):
         assert getattr(L, name) == defs[name], name
     flags = [v for k, v in defs.items() if k.startswith("PLAN_") and k != "PLAN_WAVES_SHIFT"]

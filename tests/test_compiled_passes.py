@@ -250,3 +250,18 @@ def test_thirteen_qubit_tiles(n, swizzle, half):
     st = run_compiled(plan, ts)
     ref, _ = oracle_states(circ, ts.get()["records"])
     assert max(float(np.max(np.abs(st[a] - ref[a]))) for a in range(len(ref))) <= 1e-5
+
+
+def test_tile_search_windows():
+    """The scheduler's tile search (the best of the greedy tile and windows of
+    consecutive qubits) needs fewer passes on a brick circuit than the greedy
+    tile alone, and its passes give the oracle's states."""
+    from workloads import brick_circuit
+    circ = brick_circuit(14, 12, np.random.default_rng(9), 0.05, 0.1)
+    found = P.ptsbe_plan(circ, tile_qubits=8)
+    greedy = P.ptsbe_plan(circ, tile_qubits=8, tile_search=False)
+    assert found.info["n_passes"] < greedy.info["n_passes"]
+    ts = P.ptsbe_sample_kraus(found, "proportional", n_draws=3, total_shots=3, seed=7, cfg=2)
+    st = run_compiled(found, ts)
+    ref, _ = oracle_states(circ, ts.get()["records"])
+    assert max(float(np.max(np.abs(st[a] - ref[a]))) for a in range(len(ref))) <= 1e-5
