@@ -739,8 +739,10 @@ def bench_c4(args):
                            for r in runs},
               "compile_s": sum(r["compile_s"] for r in runs),
               "host_plan_pts_ms": sum(r["host_ms"] for r in runs)}
+    rl = result["roofline"]
     log(f"[bench c4] {dt * 1e3 / args.steps:.1f} ms/step, {value:.4g} shots/s; passes {T[0] / args.steps:.1f} ms "
-        f"({T[1] / args.steps:.0f} launches, {result['roofline']['achieved']:.0f} GB/s)")
+        f"({T[1] / args.steps:.0f} launches, {rl['bound']}-bound: {rl['achieved']:.1f} {rl['unit']}, "
+        f"{rl['frac']:.3f} of {rl['peak']})")
     err = None
     if not args.no_errors:
         err = c4_oracle_errors(P, runs[0]["plan"], runs[0]["ts"], runs[0]["m"], runs[0]["out"]["bits"],
@@ -755,9 +757,11 @@ def bench_c4(args):
         del r["ws"], r["out"]
     torch.cuda.empty_cache()
     cr = copy_rate(torch)
-    result["roofline"]["copy_gbs"] = cr
-    result["roofline"]["frac_of_copy"] = result["roofline"]["achieved"] / cr
-    log(f"[bench c4] device copy {cr:.0f} GB/s: the passes reach {result['roofline']['achieved'] / cr:.3f} of it")
+    rl = result["roofline"]
+    pass_gbs = rl["achieved"] if rl["bound"] == "hbm" else rl["hbm"]["achieved"]
+    rl["copy_gbs"] = cr
+    rl["frac_of_copy"] = pass_gbs / cr
+    log(f"[bench c4] device copy {cr:.0f} GB/s: the passes move {pass_gbs:.0f} GB/s, {pass_gbs / cr:.3f} of it")
     if not args.no_baseline:
         r = runs[-1]
         nb = 24

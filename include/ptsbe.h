@@ -192,9 +192,11 @@ typedef struct {
 #define PTSBE_PLAN_TWO_TILES 32768u
 /* Plan flag: no tile search.  By default the scheduler builds each pass's tile
  * both by taking operations greedily in circuit order and from every window of
- * consecutive qubits beside the always-present lowest ones, and keeps the tile
- * that runs the most non-diagonal operations (on brick circuits a window
- * follows a light cone through many layers: about half the passes). */
+ * consecutive qubits beside the always-present lowest ones (as wide as the
+ * tile's free part or two qubits narrower), and keeps the tile that runs the
+ * most non-diagonal operations, counting the best take of the pass after it
+ * too (on brick circuits a window follows a light cone through many layers:
+ * about half the passes). */
 #define PTSBE_PLAN_NO_TILE_SEARCH 65536u
 
 typedef struct ptsbe_plan_s* ptsbe_plan_t;

@@ -801,7 +801,7 @@ static ptsbe_status schedule(Plan& plan, const std::vector<Step>& steps, std::ve
     std::vector<char> inQ;
     int qcount = 0;
     std::vector<int> taken, keep;
-    auto take_with = [&](const std::vector<char>& init) {
+    auto take_with = [&](const std::vector<char>& init, const std::vector<int>* from = nullptr) {
       inQ = init;
       qcount = 0;
       for (int q = 0; q < n; ++q) qcount += inQ[q];
@@ -813,7 +813,7 @@ static ptsbe_status schedule(Plan& plan, const std::vector<Step>& steps, std::ve
       // its decision is the state at its place in the circuit (the checkpoint
       // the reverse sweep restores).
       bool wall = false;
-      for (int si : rem) {
+      for (int si : from ? *from : rem) {
         const Step& st = steps[si];
         bool blk = wall;
         for (int j = 0; j < st.nq; ++j) blk = blk || blocked[st.q[j]];
@@ -854,19 +854,34 @@ static ptsbe_status schedule(Plan& plan, const std::vector<Step>& steps, std::ve
     for (int q = 0; q < contiguous; ++q) base[q] = 1;
     take_with(base);
     if (plan.tile_search && !taken.empty() && n > k) {
-      // Tile search: the tile whose greedy take runs the most non-diagonal
-      // operations, among the plain greedy one and every window of consecutive
-      // qubits beside the contiguous ones (on brick-like circuits a window
-      // follows a light cone through many layers, where circuit order stops
-      // at the first layer's boundary).
-      int best = score();
-      std::vector<char> best_init = base;
+      // Tile search: among the greedy tile and every window of consecutive
+      // qubits beside the contiguous ones (as wide as the tile's free part, or
+      // two qubits narrower with the scan filling the rest), the tile whose
+      // greedy take, plus
+      // the best such take of the pass after it, runs the most non-diagonal
+      // operations (on brick-like circuits a window follows a light cone
+      // through many layers, where circuit order stops at the first layer's
+      // boundary; looking one pass ahead avoids windows that strand the rest).
       const int free = k - contiguous;
-      for (int w = contiguous; w + free <= n; ++w) {
-        std::vector<char> init = base;
-        for (int q = w; q < w + free; ++q) init[q] = 1;
+      std::vector<std::vector<char>> cands{base};
+      for (int sz : {free, free - 2})  // a window short of the tile leaves the scan two qubits
+        for (int w = contiguous; sz >= 2 && w + sz <= n; ++w) {
+          std::vector<char> init = base;
+          for (int q = w; q < w + sz; ++q) init[q] = 1;
+          cands.push_back(init);
+        }
+      int best = -1;
+      std::vector<char> best_init = base;
+      for (const auto& init : cands) {
         take_with(init);
-        const int sc = score();
+        int sc = score();
+        const std::vector<int> rest = keep;
+        int next = 0;
+        for (const auto& i2 : cands) {
+          take_with(i2, &rest);
+          next = std::max(next, score());
+        }
+        sc += next;
         if (sc > best) {
           best = sc;
           best_init = init;
