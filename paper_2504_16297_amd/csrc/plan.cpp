@@ -784,7 +784,7 @@ static void schedule_phases(Pass& ps, int min_fill) {
 // |0...0>; `phases`: order the passes for the register kernel.
 static ptsbe_status schedule(Plan& plan, const std::vector<Step>& steps, std::vector<Pass>& passes,
                              std::vector<ExecStep>& exec, std::vector<std::vector<std::pair<int, int>>>& site_slots,
-                             bool init_zero, bool phases, int tile_bits) {
+                             bool init_zero, bool phases, int tile_bits, bool search) {
   const int n = plan.n;
   const int k = std::min(n, tile_bits);
   // The lowest qubits are always in the tile (runs of >= 128 contiguous bytes),
@@ -853,7 +853,7 @@ static ptsbe_status schedule(Plan& plan, const std::vector<Step>& steps, std::ve
     std::vector<char> base(n, 0);
     for (int q = 0; q < contiguous; ++q) base[q] = 1;
     take_with(base);
-    if (plan.tile_search && !taken.empty() && n > k) {
+    if (search && !taken.empty() && n > k) {
       // Tile search: among the greedy tile and every window of consecutive
       // qubits beside the contiguous ones (as wide as the tile's free part, or
       // two qubits narrower with the scan filling the rest), the tile whose
@@ -1012,6 +1012,28 @@ static ptsbe_status schedule(Plan& plan, const std::vector<Step>& steps, std::ve
       for (int site : passes[p].slots[s].sites) site_slots[site].push_back({(int)p, (int)s});
   for (auto& ps : passes)
     if (ps.slots.size() > 4096) return fail(PTSBE_E_UNSUPPORTED, "too many fused slots in one pass");
+  return PTSBE_OK;
+}
+
+// The greedy schedule, or the tile-searched one where it needs at least 10 %
+// fewer passes: a searched tile takes more operations, and on circuits where
+// it saves only a pass or two (the surface code: 17 against 18) its heavier
+// passes measured slower than the greedy ones.
+static ptsbe_status schedule_best(Plan& plan, const std::vector<Step>& steps, std::vector<Pass>& passes,
+                                  std::vector<ExecStep>& exec,
+                                  std::vector<std::vector<std::pair<int, int>>>& site_slots, bool init_zero,
+                                  bool phases, int tile_bits) {
+  ptsbe_status st = schedule(plan, steps, passes, exec, site_slots, init_zero, phases, tile_bits, false);
+  if (st != PTSBE_OK || !plan.tile_search) return st;
+  std::vector<Pass> sp;
+  std::vector<ExecStep> se;
+  std::vector<std::vector<std::pair<int, int>>> ss;
+  if (schedule(plan, steps, sp, se, ss, init_zero, phases, tile_bits, true) != PTSBE_OK) return PTSBE_OK;
+  if (sp.size() * 10 <= passes.size() * 9) {
+    passes.swap(sp);
+    exec.swap(se);
+    site_slots.swap(ss);
+  }
   return PTSBE_OK;
 }
 
@@ -1375,7 +1397,7 @@ ptsbe_status build_plan(const ptsbe_circuit* c, const ptsbe_noise_model* nm, con
     for (double p : ch.p) P.site_p.push_back(p);
     P.site_off.push_back((uint32_t)P.site_p.size());
   }
-  ptsbe_status st = schedule(P, P.steps, P.passes, P.exec, P.site_slots, true, true, P.tile_bits);
+  ptsbe_status st = schedule_best(P, P.steps, P.passes, P.exec, P.site_slots, true, true, P.tile_bits);
   if (st != PTSBE_OK) return st;
   if (!(o && (o->flags & PTSBE_PLAN_NO_PHASE_FRAMES))) assign_frames(P.n, P.steps, P.passes, P.exec);
   // Reverse-sweep program of the adjoint gradient: the steps in reverse order,
@@ -1408,7 +1430,7 @@ ptsbe_status build_plan(const ptsbe_circuit* c, const ptsbe_noise_model* nm, con
       A.steps.push_back(r);
     }
     // two tiles (psi and lambda) share the LDS: one tile bit less
-    st = schedule(P, A.steps, A.passes, A.exec, A.site_slots, false, true, std::max(4, P.tile_bits - 1));
+    st = schedule_best(P, A.steps, A.passes, A.exec, A.site_slots, false, true, std::max(4, P.tile_bits - 1));
     if (st != PTSBE_OK) return st;
     P.has_adjoint = true;
   }
