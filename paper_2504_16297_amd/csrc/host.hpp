@@ -100,6 +100,8 @@ enum FrameRole : uint8_t {
                             // diagonal; the tables hold the identity and the kernels skip it
   FRAME_OVERRIDE_ONLY = 3,  // unitary diagonal 2x2 slot with noise sites: its default becomes the
                             // identity (skipped), a trajectory's override still runs as a 2x2
+  FRAME_UNIT_DIAG = 4,      // fixed 2x2 slot stored with a unit diagonal: its whole diagonal,
+                            // magnitude included, stays pending (x_r + c x_o per amplitude)
 };
 
 struct Slot {

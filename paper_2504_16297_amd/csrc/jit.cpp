@@ -149,14 +149,18 @@ struct Gen {
     pending = true;
   }
 
-  // ---- 2x2 matrix on register position j
-  void gate_body(int j, bool real_diag) {
+  // ---- 2x2 matrix on register position j: form 0 general, 1 real diagonal,
+  // 2 unit diagonal
+  void gate_body(int j, int form) {
     for (const std::string& st : sets()) {
       pre = st;
       for (int r = 0; r < 16; ++r) {
         if ((r >> j) & 1) continue;
         const int r1 = r | (1 << j);
-        if (real_diag)
+        if (form == 2)
+          o << "    { const V x0 = " << S(r) << ", x1 = " << S(r1) << "; " << S(r) << " = cu(x0, m1, x1); " << S(r1)
+            << " = cu(x1, m2, x0); }\n";
+        else if (form == 1)
           o << "    { const V x0 = " << S(r) << ", x1 = " << S(r1) << "; " << S(r) << " = cr(m0.x, x0, m1, x1); "
             << S(r1) << " = cr(m3.x, x1, m2, x0); }\n";
         else
@@ -166,28 +170,28 @@ struct Gen {
     }
     pre = "s";
   }
-  // A slot stored with a real diagonal (phase frame) runs the cheaper form
-  // unless this block's trajectory overrides it with a general matrix; the
-  // block-uniform scalar then stays pending instead of being folded in.
+  // A slot stored with a real or unit diagonal (phase frame) runs the cheaper
+  // form unless this block's trajectory overrides it with a general matrix;
+  // the block-uniform scalar then stays pending instead of being folded in.
   void gate(int j, int slot) {
     const uint8_t role = frame ? frame[slot] : (uint8_t)FRAME_NONE;
     if (role == FRAME_ABSORB) return;  // merged into a pending phase frame
     o << "  {\n";
     load2x2(slot);
-    if (role == FRAME_REAL_DIAG || role == FRAME_OVERRIDE_ONLY) {
+    if (role == FRAME_REAL_DIAG || role == FRAME_OVERRIDE_ONLY || role == FRAME_UNIT_DIAG) {
       o << "  if " << ovcond(slot) << " {\n";
-      gate_body(j, false);
+      gate_body(j, 0);
       o << "  }";
-      if (role == FRAME_REAL_DIAG) {
+      if (role != FRAME_OVERRIDE_ONLY) {
         o << " else {\n";
-        gate_body(j, true);
+        gate_body(j, role == FRAME_UNIT_DIAG ? 2 : 1);
         o << "  }";
       }
       o << "\n  }\n";
       return;
     }
     apply_pending_to("m0", "m1", "m2", "m3");
-    gate_body(j, false);
+    gate_body(j, 0);
     o << "  }\n";
   }
 
@@ -448,7 +452,7 @@ struct Gen {
       << "    V m0 = kp[0], m1 = kp[1], m2 = kp[2], m3 = kp[3];\n"
       << "    m0.x *= sc; m0.y *= sc; m1.x *= sc; m1.y *= sc; m2.x *= sc; m2.y *= sc; m3.x *= sc; m3.y *= sc;\n";
     apply_pending_to("m0", "m1", "m2", "m3");
-    gate_body(j, false);
+    gate_body(j, 0);
     o << "  }\n";
   }
 
@@ -613,6 +617,13 @@ __device__ __forceinline__ V cr(T d, V xd, V m, V xo) {
   r.y = d * xd.y + m.x * xo.y + m.y * xo.x;
   return r;
 }
+// xd + m * xo: a row with a unit diagonal entry
+__device__ __forceinline__ V cu(V xd, V m, V xo) {
+  V r;
+  r.x = xd.x + m.x * xo.x - m.y * xo.y;
+  r.y = xd.y + m.x * xo.y + m.y * xo.x;
+  return r;
+}
 // one row of a 4x4 matrix: one multiply-add chain per component (1 multiply
 // and 7 FMAs, against 2 + 6 + 1 add for two 2-term rows summed)
 __device__ __forceinline__ V cd4(const V* m, V x0, V x1, V x2, V x3) {
@@ -699,7 +710,8 @@ std::string gen_pass(const Pass& ps, int n, int precision, const std::string& na
   std::set<int> ovw_words;  // words of the override bit set that hold a rewritten 2x2 slot
   for (int i = 0; i < n_slots; ++i) {
     frame[i] = ps.slots[i].frame;
-    if (frame[i] == FRAME_REAL_DIAG || frame[i] == FRAME_OVERRIDE_ONLY) ovw_words.insert(i >> 5);
+    if (frame[i] == FRAME_REAL_DIAG || frame[i] == FRAME_OVERRIDE_ONLY || frame[i] == FRAME_UNIT_DIAG)
+      ovw_words.insert(i >> 5);
   }
   g.frame = frame.data();
   const int n_ovw = (n_slots + 31) / 32;

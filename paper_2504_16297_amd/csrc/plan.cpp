@@ -1115,6 +1115,42 @@ void assign_frames(int n, const std::vector<Step>& steps, std::vector<Pass>& pas
   }
 }
 
+// Fixed 2x2 slots (no parameter; both diagonal entries of magnitude >= 1e-2)
+// of real-diagonal role hand their whole diagonal, magnitude included, to the
+// pending frame instead of its phase alone: the kernels then apply them as
+// x_r + c x_o, 4 FMAs per amplitude instead of 6.  The pending magnitudes
+// along a qubit's chain stay within [1e-4, 1e4]; a slot that would leave them
+// keeps the real diagonal (and resets them).
+void unit_frames(Plan& P) {
+  std::vector<std::array<double, 2>> mag(P.n, {1.0, 1.0});
+  const std::map<int, int> none;
+  walk_frames(P.n, P.passes, P.exec, [&](int q, const FrameEvent& e) {
+    if (e.kind == FE_BREAK) {
+      mag[q] = {1.0, 1.0};
+      return;
+    }
+    Slot& s = P.passes[e.pass].slots[e.slot];
+    if (e.kind == FE_M2 || (e.kind == FE_M1 && s.frame == FRAME_NONE)) {  // takes the pending diagonal in
+      mag[q] = {1.0, 1.0};
+      return;
+    }
+    if (e.kind != FE_M1 || s.frame != FRAME_REAL_DIAG) return;  // unitary diagonals keep the magnitude
+    bool fixed = true;
+    for (const Part& pt : s.parts) fixed = fixed && P.steps[pt.step].kind != ST_PARAM;
+    if (fixed) {
+      const Mat M = slot_matrix(P, P.steps, s, nullptr, none);
+      const double a0 = std::abs(M[0]), a1 = std::abs(M[3]);
+      const double m0 = mag[q][0] * a0, m1 = mag[q][1] * a1;
+      if (a0 >= 1e-2 && a1 >= 1e-2 && m0 >= 1e-4 && m0 <= 1e4 && m1 >= 1e-4 && m1 <= 1e4) {
+        s.frame = FRAME_UNIT_DIAG;
+        mag[q] = {m0, m1};
+        return;
+      }
+    }
+    mag[q] = {1.0, 1.0};
+  });
+}
+
 cd unit_phase(cd z) {
   const double a = std::abs(z);
   return a > 0 ? z / a : cd(1, 0);
@@ -1141,12 +1177,15 @@ std::vector<std::vector<SlotFrame>> slot_frames(int n, const std::vector<Pass>& 
       f.in[0][0] = pend[q][0];
       f.in[0][1] = pend[q][1];
       const Mat& M = defaults[e.pass][e.slot];
-      f.out[0] = unit_phase(M[0] * pend[q][0]);
-      f.out[1] = unit_phase(M[3] * pend[q][1]);
+      // a real-diagonal slot leaves the phase pending and keeps the magnitude;
+      // a unit-diagonal one (and a skipped unitary diagonal) leaves it all
+      const bool whole = s.frame == FRAME_UNIT_DIAG || s.frame == FRAME_OVERRIDE_ONLY;
+      f.out[0] = whole ? M[0] * pend[q][0] : unit_phase(M[0] * pend[q][0]);
+      f.out[1] = whole ? M[3] * pend[q][1] : unit_phase(M[3] * pend[q][1]);
       pend[q] = {f.out[0], f.out[1]};
     } else if (s.frame == FRAME_ABSORB) {
-      const Mat& M = defaults[e.pass][e.slot];
-      pend[q] = {unit_phase(pend[q][0] * M[0]), unit_phase(pend[q][1] * M[3])};
+      const Mat& M = defaults[e.pass][e.slot];  // unit-modulus entries: the magnitude passes through
+      pend[q] = {pend[q][0] * M[0], pend[q][1] * M[3]};
     }
   });
   return fr;
@@ -1159,11 +1198,12 @@ Mat frame_matrix(const Slot& s, const SlotFrame& f, const Mat& M) {
   } else if (s.type == DOP_M1) {
     for (int r = 0; r < 2; ++r)
       for (int c = 0; c < 2; ++c) V[r * 2 + c] *= f.in[0][c];
-    if (s.frame == FRAME_REAL_DIAG || s.frame == FRAME_OVERRIDE_ONLY) {
+    if (s.frame == FRAME_REAL_DIAG || s.frame == FRAME_OVERRIDE_ONLY || s.frame == FRAME_UNIT_DIAG) {
       for (int r = 0; r < 2; ++r)
-        for (int c = 0; c < 2; ++c) V[r * 2 + c] *= std::conj(f.out[r]);
-      // the default matrix now has a real diagonal (up to rounding, which the
-      // kernels' real-diagonal form drops); an override's is general
+        for (int c = 0; c < 2; ++c) V[r * 2 + c] /= f.out[r];
+      // the default matrix now has a real (or unit) diagonal, up to rounding,
+      // which the kernels' real- and unit-diagonal forms drop; an override's is
+      // general
     }
   } else if (s.type == DOP_M2) {
     for (int r = 0; r < 4; ++r)
@@ -1399,7 +1439,10 @@ ptsbe_status build_plan(const ptsbe_circuit* c, const ptsbe_noise_model* nm, con
   }
   ptsbe_status st = schedule_best(P, P.steps, P.passes, P.exec, P.site_slots, true, true, P.tile_bits);
   if (st != PTSBE_OK) return st;
-  if (!(o && (o->flags & PTSBE_PLAN_NO_PHASE_FRAMES))) assign_frames(P.n, P.steps, P.passes, P.exec);
+  if (!(o && (o->flags & PTSBE_PLAN_NO_PHASE_FRAMES))) {
+    assign_frames(P.n, P.steps, P.passes, P.exec);
+    unit_frames(P);
+  }
   // Reverse-sweep program of the adjoint gradient: the steps in reverse order,
   // each applied as its adjoint, with a DOT marker (Im<lambda|P|psi>) just before
   // un-applying every parametrised rotation.  Not for circuits with

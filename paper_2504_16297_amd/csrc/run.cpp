@@ -105,11 +105,13 @@ ptsbe_status hip_check(hipError_t e, const char* what) {
 // Useful real floating-point operations per amplitude of a pass, on the path
 // a block without overrides takes: a 2x2 complex matrix makes each output from
 // two complex products and a sum (14); with a real diagonal (phase frame) one
-// product is real times complex (10); a 4x4 costs 30, a diagonal 6, a
+// product is real times complex (10), with a unit diagonal one product and a
+// sum (8); a 4x4 costs 30, a diagonal 6, a
 // measure-reset 2; slots merged into a phase frame, signs and relabellings 0.
 static double m1_flops(const Pass& ps, int slot) {
   switch (ps.slots[slot].frame) {
     case FRAME_REAL_DIAG: return 10;
+    case FRAME_UNIT_DIAG: return 8;
     case FRAME_ABSORB:
     case FRAME_OVERRIDE_ONLY: return 0;
     default: return 14;

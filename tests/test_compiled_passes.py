@@ -103,16 +103,17 @@ def test_adjoint_sweep_kernels(n, prec, seed):
 
 @pytest.mark.parametrize("frames", [True, False])
 def test_brick_phase_frames(frames):
-    """Compiled passes of a brick circuit in phase frames: 2x2 slots run in the
-    real-diagonal form unless the block's trajectory overrides them (noise
-    strong enough that most trajectories carry overrides), and the plain plan
-    (no frames) keeps the general form; both match the oracle."""
+    """Compiled passes of a brick circuit in phase frames: the fixed 2x2 slots
+    run in the unit-diagonal form (x_r + c x_o, the diagonal with its magnitude
+    pending) unless the block's trajectory overrides them (noise strong enough
+    that most trajectories carry overrides), and the plain plan (no frames)
+    keeps the general form; both match the oracle."""
     from compiled_cpu import pass_source
     from workloads import brick_circuit
     circ = brick_circuit(12, 5, np.random.default_rng(8), 0.08, 0.1, eps_sigma=0.05)
     plan = P.ptsbe_plan(circ, phase_frames=frames, pair_fusion=False)
     srcs = "".join(pass_source(plan, p) for p in range(plan.info["n_passes"]))
-    assert ("= cr(m0.x" in srcs) == frames
+    assert ("= cu(x0, m1, x1)" in srcs) == frames      # fixed U3s: unit-diagonal rows
     assert ("  if (__builtin_expect((ovw" in srcs) == frames   # override branch of a rewritten slot
     ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=6, total_shots=6, seed=6, cfg=2)
     g = ts.get()
@@ -265,3 +266,33 @@ def test_tile_search_windows():
     st = run_compiled(found, ts)
     ref, _ = oracle_states(circ, ts.get()["records"])
     assert max(float(np.max(np.abs(st[a] - ref[a]))) for a in range(len(ref))) <= 1e-5
+
+
+def test_unit_and_real_diagonal_frames():
+    """Slots whose diagonal entries are too small to divide by (a U3 with
+    theta = pi, an X) keep the real-diagonal form, parameterised slots too;
+    the others take the unit-diagonal form; the states equal the oracle's."""
+    from compiled_cpu import pass_source
+    rng = np.random.default_rng(21)
+    n = 9
+    ops = []
+    for layer in range(6):
+        for q in range(n):
+            th = np.pi if (q + layer) % 4 == 0 else rng.uniform(0, 2 * np.pi)
+            ops.append({"kind": "gate", "name": "U3", "qubits": (q,), "tag": "U3",
+                        "params": (th, rng.uniform(0, 2 * np.pi), rng.uniform(0, 2 * np.pi))})
+        for q in range(layer % 2, n - 1, 2):
+            ops.append({"kind": "gate", "name": "CZ", "qubits": (q, q + 1), "params": (), "tag": "CZ"})
+    circ = {"n_qubits": n, "ops": ops, "channels": [{"name": "depolarizing", "nq": 1, "p": 0.05}],
+            "rules": [{"when": "after_tag", "tag": "U3", "channel": 0}]}
+    plan = P.ptsbe_plan(circ, pair_fusion=False, tile_qubits=6)
+    srcs = "".join(pass_source(plan, p) for p in range(plan.info["n_passes"]))
+    assert "= cu(x0, m1, x1)" in srcs and "= cr(m0.x, x0, m1, x1)" in srcs
+    ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=5, total_shots=5, seed=3, cfg=4)
+    st = run_compiled(plan, ts)
+    ref, _ = oracle_states(circ, ts.get()["records"])
+    assert max(float(np.max(np.abs(st[a] - ref[a]))) for a in range(len(ref))) <= 1e-5
+    hea = hea_circuit(8, 3, np.random.default_rng(4), 0.05)
+    hp = P.ptsbe_plan(hea, pair_fusion=False)
+    hs = "".join(pass_source(hp, p) for p in range(hp.info["n_passes"]))
+    assert "= cr(m0.x, x0, m1, x1)" in hs        # parameterised rotations keep the real diagonal
