@@ -283,7 +283,7 @@ ptsbe_status ptsbe_graph_launch(ptsbe_graph_t g, void* stream) {
 
 void ptsbe_graph_destroy(ptsbe_graph_t g) {
   if (!g) return;
-  if (g->exec) hipGraphExecDestroy(g->exec);
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
   delete g;
 }
 

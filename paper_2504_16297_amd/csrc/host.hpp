@@ -102,6 +102,8 @@ enum FrameRole : uint8_t {
                             // identity (skipped), a trajectory's override still runs as a 2x2
   FRAME_UNIT_DIAG = 4,      // fixed 2x2 slot stored with a unit diagonal: its whole diagonal,
                             // magnitude included, stays pending (x_r + c x_o per amplitude)
+  FRAME_UNIT4 = 5,          // fixed 4x4 slot stored with rows 0..2 of unit diagonal: a product
+                            // diagonal d_a (x) d_b stays pending on its two qubits
 };
 
 struct Slot {
@@ -111,6 +113,7 @@ struct Slot {
   std::vector<Part> parts;     // applied in order
   std::vector<int> sites;      // sites whose choice changes this slot
   bool uses_params = false;
+  bool m2_next[2] = {false, false};  // 4x4: the next non-diagonal operation on matrix bit j's qubit is a matrix
 };
 
 struct Pass {
@@ -245,7 +248,8 @@ Mat slot_matrix(const Plan& plan, const std::vector<Step>& steps, const Slot& s,
 // leaves pending (`out`).  Computed from the slots' default matrices.
 struct SlotFrame {
   cd in[2][2] = {{cd(1, 0), cd(1, 0)}, {cd(1, 0), cd(1, 0)}};
-  cd out[2] = {cd(1, 0), cd(1, 0)};
+  cd out[2] = {cd(1, 0), cd(1, 0)};   // 2x2, or a 4x4's matrix bit 0 (FRAME_UNIT4)
+  cd out2[2] = {cd(1, 0), cd(1, 0)};  // a 4x4's matrix bit 1 (FRAME_UNIT4)
 };
 std::vector<std::vector<SlotFrame>> slot_frames(int n, const std::vector<Pass>& passes,
                                                 const std::vector<ExecStep>& exec,

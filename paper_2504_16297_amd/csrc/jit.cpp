@@ -361,19 +361,45 @@ struct Gen {
   void m2(const DOp& op) {
     const int ja = reg_pos(op.a), jb = reg_pos(op.b);
     if (ja >= 0 && jb >= 0 && op.slot[0] < m2_off.size() && m2_off[op.slot[0]] >= 0) {
+      // unit4: rows 0..2 of the stored default have a unit diagonal (phase
+      // frame); a block whose trajectory overrides the slot runs all 4 rows
+      // in full
+      const bool unit4 = frame && frame[op.slot[0]] == FRAME_UNIT4;
+      auto rows = [&](bool unit) {
+        for (const std::string& st : sets())
+        for (int r = 0; r < 16; ++r) {
+          pre = st;
+          if ((r >> ja) & 1 || (r >> jb) & 1) continue;
+          const int i0 = r, i1 = r | (1 << ja), i2 = r | (1 << jb), i3 = r | (1 << ja) | (1 << jb);
+          o << "    { const V x0 = " << S(i0) << ", x1 = " << S(i1) << ", x2 = " << S(i2) << ", x3 = " << S(i3)
+            << ";\n";
+          const int idx[4] = {i0, i1, i2, i3};
+          for (int q = 0; q < 4; ++q) {
+            o << "      " << S(idx[q]) << " = ";
+            if (unit && q < 3) {
+              // x_q + the other three entries of row q
+              o << "cu3(x" << q;
+              for (int c = 0; c < 4; ++c)
+                if (c != q) o << ", M[" << 4 * q + c << "], x" << c;
+              o << ");\n";
+            } else {
+              o << "cd4(M + " << 4 * q << ", x0, x1, x2, x3);\n";
+            }
+          }
+          o << "    }\n";
+        }
+        pre = "s";
+      };
       o << "  {\n    const V* M = mats + " << m2_off[op.slot[0]] << ";\n";
-      for (const std::string& st : sets())
-      for (int r = 0; r < 16; ++r) {
-        pre = st;
-        if ((r >> ja) & 1 || (r >> jb) & 1) continue;
-        const int i0 = r, i1 = r | (1 << ja), i2 = r | (1 << jb), i3 = r | (1 << ja) | (1 << jb);
-        o << "    { const V x0 = " << S(i0) << ", x1 = " << S(i1) << ", x2 = " << S(i2) << ", x3 = " << S(i3) << ";\n";
-        const int idx[4] = {i0, i1, i2, i3};
-        for (int q = 0; q < 4; ++q)
-          o << "      " << S(idx[q]) << " = cd4(M + " << 4 * q << ", x0, x1, x2, x3);\n";
-        o << "    }\n";
+      if (unit4) {
+        o << "  if " << ovcond(op.slot[0]) << " {\n";
+        rows(false);
+        o << "  } else {\n";
+        rows(true);
+        o << "  }\n";
+      } else {
+        rows(false);
       }
-      pre = "s";
       o << "  }\n";
       return;
     }
@@ -624,6 +650,13 @@ __device__ __forceinline__ V cu(V xd, V m, V xo) {
   r.y = xd.y + m.x * xo.y + m.y * xo.x;
   return r;
 }
+// xd + m1 * x1 + m2 * x2 + m3 * x3: a 4x4 row with a unit diagonal entry
+__device__ __forceinline__ V cu3(V xd, V m1, V x1, V m2, V x2, V m3, V x3) {
+  V r;
+  r.x = xd.x + m1.x * x1.x - m1.y * x1.y + m2.x * x2.x - m2.y * x2.y + m3.x * x3.x - m3.y * x3.y;
+  r.y = xd.y + m1.x * x1.y + m1.y * x1.x + m2.x * x2.y + m2.y * x2.x + m3.x * x3.y + m3.y * x3.x;
+  return r;
+}
 // one row of a 4x4 matrix: one multiply-add chain per component (1 multiply
 // and 7 FMAs, against 2 + 6 + 1 add for two 2-term rows summed)
 __device__ __forceinline__ V cd4(const V* m, V x0, V x1, V x2, V x3) {
@@ -710,7 +743,8 @@ std::string gen_pass(const Pass& ps, int n, int precision, const std::string& na
   std::set<int> ovw_words;  // words of the override bit set that hold a rewritten 2x2 slot
   for (int i = 0; i < n_slots; ++i) {
     frame[i] = ps.slots[i].frame;
-    if (frame[i] == FRAME_REAL_DIAG || frame[i] == FRAME_OVERRIDE_ONLY || frame[i] == FRAME_UNIT_DIAG)
+    if (frame[i] == FRAME_REAL_DIAG || frame[i] == FRAME_OVERRIDE_ONLY || frame[i] == FRAME_UNIT_DIAG ||
+        frame[i] == FRAME_UNIT4)
       ovw_words.insert(i >> 5);
   }
   g.frame = frame.data();

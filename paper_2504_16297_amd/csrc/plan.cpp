@@ -1101,11 +1101,15 @@ void assign_frames(int n, const std::vector<Step>& steps, std::vector<Pass>& pas
   for (int q = 0; q < n; ++q) {
     const auto& c = chain[q];
     for (size_t i = 0; i < c.size(); ++i) {
-      if (c[i].kind != FE_M1 && c[i].kind != FE_DIAG) continue;
+      if (c[i].kind != FE_M1 && c[i].kind != FE_DIAG && c[i].kind != FE_M2) continue;
       size_t j = i + 1;
       while (j < c.size() && c[j].kind == FE_DIAG) ++j;
       const bool absorbed = j < c.size() && (c[j].kind == FE_M1 || c[j].kind == FE_M2);
       Slot& s = passes[c[i].pass].slots[c[i].slot];
+      if (c[i].kind == FE_M2) {
+        s.m2_next[c[i].j] = absorbed;
+        continue;
+      }
       s.frame = FRAME_NONE;
       if (!absorbed) continue;
       if (unitary_diag(s)) s.frame = s.sites.empty() ? FRAME_ABSORB : (c[i].kind == FE_M1 ? FRAME_OVERRIDE_ONLY
@@ -1130,18 +1134,41 @@ void unit_frames(Plan& P) {
       return;
     }
     Slot& s = P.passes[e.pass].slots[e.slot];
-    if (e.kind == FE_M2 || (e.kind == FE_M1 && s.frame == FRAME_NONE)) {  // takes the pending diagonal in
+    auto in_range = [](double m) { return m >= 1e-4 && m <= 1e4; };
+    if (e.kind == FE_M2) {
+      // A fixed 4x4 both of whose qubits go on to another matrix takes the
+      // pending diagonals in and leaves d_a (x) d_b pending, chosen (d_a0 = 1)
+      // so that rows 0..2 of the stored matrix have a unit diagonal.  Decided
+      // at the slot's second qubit, when both incoming magnitudes are known.
+      if (e.j == 0) return;
+      const int qa = s.q[0], qb = s.q[1];
+      if (!s.uses_params && s.m2_next[0] && s.m2_next[1]) {
+        const Mat M = slot_matrix(P, P.steps, s, nullptr, none);
+        double d[3];
+        for (int i = 0; i < 3; ++i) d[i] = std::abs(M[i * 5]) * mag[qa][i & 1] * mag[qb][i >> 1];
+        bool ok = true;
+        for (int i = 0; i < 3; ++i) ok = ok && std::abs(M[i * 5]) >= 1e-2;
+        if (ok && in_range(d[1] / d[0]) && in_range(d[0]) && in_range(d[2])) {
+          s.frame = FRAME_UNIT4;
+          mag[qa] = {1.0, d[1] / d[0]};
+          mag[qb] = {d[0], d[2]};
+          return;
+        }
+      }
+      mag[qa] = {1.0, 1.0};
+      mag[qb] = {1.0, 1.0};
+      return;
+    }
+    if (e.kind == FE_M1 && s.frame == FRAME_NONE) {  // takes the pending diagonal in
       mag[q] = {1.0, 1.0};
       return;
     }
     if (e.kind != FE_M1 || s.frame != FRAME_REAL_DIAG) return;  // unitary diagonals keep the magnitude
-    bool fixed = true;
-    for (const Part& pt : s.parts) fixed = fixed && P.steps[pt.step].kind != ST_PARAM;
-    if (fixed) {
+    if (!s.uses_params) {
       const Mat M = slot_matrix(P, P.steps, s, nullptr, none);
       const double a0 = std::abs(M[0]), a1 = std::abs(M[3]);
       const double m0 = mag[q][0] * a0, m1 = mag[q][1] * a1;
-      if (a0 >= 1e-2 && a1 >= 1e-2 && m0 >= 1e-4 && m0 <= 1e4 && m1 >= 1e-4 && m1 <= 1e4) {
+      if (a0 >= 1e-2 && a1 >= 1e-2 && in_range(m0) && in_range(m1)) {
         s.frame = FRAME_UNIT_DIAG;
         mag[q] = {m0, m1};
         return;
@@ -1173,6 +1200,18 @@ std::vector<std::vector<SlotFrame>> slot_frames(int n, const std::vector<Pass>& 
       f.in[e.j][0] = pend[q][0];
       f.in[e.j][1] = pend[q][1];
       pend[q] = {cd(1, 0), cd(1, 0)};
+      if (e.kind == FE_M2 && s.frame == FRAME_UNIT4 && e.j == 1) {
+        // diagonal of M' = M (in_a (x) in_b); out_a = (1, M'11 / M'00), out_b = (M'00, M'22)
+        const Mat& M = defaults[e.pass][e.slot];
+        const cd m0 = M[0] * f.in[0][0] * f.in[1][0], m1 = M[5] * f.in[0][1] * f.in[1][0],
+                 m2 = M[10] * f.in[0][0] * f.in[1][1];
+        f.out[0] = cd(1, 0);
+        f.out[1] = m1 / m0;
+        f.out2[0] = m0;
+        f.out2[1] = m2;
+        pend[s.q[0]] = {f.out[0], f.out[1]};
+        pend[s.q[1]] = {f.out2[0], f.out2[1]};
+      }
     } else if (e.kind == FE_M1 && s.frame != FRAME_ABSORB) {
       f.in[0][0] = pend[q][0];
       f.in[0][1] = pend[q][1];
@@ -1208,6 +1247,9 @@ Mat frame_matrix(const Slot& s, const SlotFrame& f, const Mat& M) {
   } else if (s.type == DOP_M2) {
     for (int r = 0; r < 4; ++r)
       for (int c = 0; c < 4; ++c) V[r * 4 + c] *= f.in[0][c & 1] * f.in[1][c >> 1];
+    if (s.frame == FRAME_UNIT4)  // rows 0..2 of the default get a unit diagonal
+      for (int r = 0; r < 4; ++r)
+        for (int c = 0; c < 4; ++c) V[r * 4 + c] /= f.out[r & 1] * f.out2[r >> 1];
   }
   return V;
 }

@@ -127,7 +127,7 @@ double pass_flops_per_amp(const Pass& ps) {
         for (int j = 0; j < 4; ++j)
           if ((op.mask >> j) & 1) f += m1_flops(ps, op.slot[j]);
         break;
-      case DOP_M2: f += 30; break;
+      case DOP_M2: f += ps.slots[op.slot[0]].frame == FRAME_UNIT4 ? 25.5 : 30; break;  // 3 rows of 24, one of 30
       case DOP_D1: f += ps.slots[op.slot[0]].frame == FRAME_ABSORB ? 0 : 6; break;
       case DOP_D2: f += 6; break;
       case DOP_MR: f += 2; break;
@@ -195,7 +195,7 @@ struct StageTimer {
   std::vector<int> cat;
   StageTimer(hipStream_t st, bool enabled) : s(st), on(enabled) {}
   ~StageTimer() {
-    for (auto e : ev) hipEventDestroy(e);
+    for (auto e : ev) (void)hipEventDestroy(e);
   }
   hipError_t mark(int c) {
     if (!on) return hipSuccess;
@@ -605,12 +605,12 @@ ptsbe_status run_batch(const Plan& P, TrajSet& ts, const ptsbe_run_opts* o, void
   hipGraph_t g = nullptr;
   hipError_t ce = hipStreamEndCapture(s, &g);
   if (st != PTSBE_OK) {
-    if (g) hipGraphDestroy(g);
+    if (g) (void)hipGraphDestroy(g);
     return st;
   }
   CK(ce, "end capture");
   hipError_t ie = hipGraphInstantiate(graph_out, g, nullptr, nullptr, 0);
-  hipGraphDestroy(g);
+  (void)hipGraphDestroy(g);
   CK(ie, "graph instantiate");
   return PTSBE_OK;
 }

@@ -127,8 +127,9 @@ def test_brick_pair_fusion():
     """Pair fusion on a brick circuit: each even-layer CZ merges with the 2x2
     runs on its qubits into a 4x4 slot that also takes the next layer's gates on
     them, applied in registers (both bits register bits, no pass through the
-    LDS tile for it); noise overrides of the 4x4 slots included, the states
-    match the oracle, and the plan has fewer 2x2 register groups than without."""
+    LDS tile for it), rows 0..2 in the unit-diagonal form of the phase frame;
+    noise overrides of the 4x4 slots included, the states match the oracle, and
+    the plan has fewer 2x2 register groups than without."""
     from collections import Counter
     from compiled_cpu import pass_source
     from paper_2504_16297_amd.tables import export_tables
@@ -137,6 +138,7 @@ def test_brick_pair_fusion():
     plan = P.ptsbe_plan(circ)
     srcs = [pass_source(plan, p) for p in range(plan.info["n_passes"])]
     assert any("cd4(M + " in s for s in srcs)                 # 4x4 in registers
+    assert any("= cu3(x0, M[1], x1" in s for s in srcs)       # fixed 4x4s: rows 0..2 with a unit diagonal
     assert not any("cd4(m, x0" in s for s in srcs)            # never through the tile
     ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=6, total_shots=6, seed=7, cfg=2)
     g = ts.get()
