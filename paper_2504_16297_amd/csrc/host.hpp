@@ -226,6 +226,7 @@ struct TrajSet {
   std::vector<uint32_t> route_host; // host staging of prefix-sharing launch routes (src, dst pairs)
   std::vector<double> weights_host; // host staging of the ensemble weights (expectation mode)
   std::vector<uint32_t> route_off;
+  std::vector<uint32_t> eff_host;   // host staging of each trajectory's first own execution step (prefix sharing)
   std::vector<uint64_t> uq_host;    // host staging of the distinct-shot pass's offset arrays
 };
 

@@ -766,7 +766,7 @@ std::string gen_pass(const Pass& ps, int n, int precision, const std::string& na
     << "  uint32_t src = blockIdx.y, dst = blockIdx.y;\n"
     << "  if (a.route) { const uint2 e = a.route[blockIdx.y]; src = e.x; dst = e.y; }\n"
     << "  const bool carrier = a.route != nullptr && dst >= a.carrier0;\n"
-    << "  const uint32_t t = a.t0 + dst;\n";
+    << "  const uint32_t t = carrier ? a.carrier_t : a.t0 + dst;\n";
   // The state loads come first: their latency overlaps the matrix set-up.
   // Global offsets: thread part from tid, register parts constant.
   std::vector<int> tpos(g.tq.begin(), g.tq.begin() + (k - 4));

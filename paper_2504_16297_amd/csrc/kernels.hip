@@ -10,6 +10,8 @@
 //              of measured qubits (general Kraus branch of Algorithm 1).
 //  k_mr_decide per trajectory: outcome b = [p1 > 1/2], determinism check,
 //              renormalisation factor.
+//  k_mr_follow under prefix sharing: the prefix state's decisions copied to
+//              the trajectories still on it.
 //  k_blocksum / k_scan_partials / k_cdf
 //              FP64 norm and inclusive prefix sum of |psi|^2 per state:
 //              per-thread sequential sums, wavefront shuffles, an LDS tree,
@@ -77,7 +79,7 @@ __device__ __forceinline__ Route route_of(const PassArgs<V>& a) {
     r.dst = e.y;
   }
   r.carrier = a.route != nullptr && r.dst >= a.carrier0;
-  r.t = a.t0 + r.dst;
+  r.t = r.carrier ? a.carrier_t : a.t0 + r.dst;
   return r;
 }
 
@@ -1016,7 +1018,7 @@ __global__ void k_grad_gather(const double* gdot, const uint32_t* dot_param, uin
 
 template <typename V>
 __global__ __launch_bounds__(256) void k_marginal(MarginalArgs<V> a) {
-  const V* st = a.states + (uint64_t)blockIdx.y * a.N;
+  const V* st = a.states + (uint64_t)(a.rows ? a.rows[blockIdx.y].x : blockIdx.y) * a.N;
   const uint64_t e0 = (uint64_t)blockIdx.x * a.per_block;
   // sums in registers: every index into s is a compile-time constant
   double s[kMaxGroup + 1];
@@ -1082,7 +1084,7 @@ __global__ __launch_bounds__(256) void k_marginal(MarginalArgs<V> a) {
 }
 
 __global__ void k_mr_decide(MrDecideArgs a) {
-  const uint32_t tb = blockIdx.x;  // batch-local trajectory
+  const uint32_t tb = blockIdx.x;  // batch-local trajectory, or entry tb of a.rows
   const uint32_t j = threadIdx.x;
   if (j >= a.nq) return;
   double tot = 0.0, one = 0.0;
@@ -1098,8 +1100,9 @@ __global__ void k_mr_decide(MrDecideArgs a) {
   const uint32_t r = a.idx[j];
   const uint32_t co = a.rec_chan ? a.rec_chan[r] : 0xffffffffu;
   if (co != 0xffffffffu) {
-    // state-dependent channel: p_k = d0[k] P(q=0) + d1[k] P(q=1); the uniform is
-    // word rec_gidx[r] of the stream [seed, key1(4, cfg, alpha)]
+    // state-dependent channel (never with a.rows: such plans share no prefix):
+    // p_k = d0[k] P(q=0) + d1[k] P(q=1); the uniform is word rec_gidx[r] of the
+    // stream [seed, key1(4, cfg, alpha)]
     const double* cp = a.chan_param + co;
     const uint32_t K = (uint32_t)cp[0];
     const uint64_t alpha = a.alpha0 + a.t0 + tb;
@@ -1135,11 +1138,28 @@ __global__ void k_mr_decide(MrDecideArgs a) {
   const uint32_t bit = p1 > 0.5 ? 1u : 0u;
   const double pb = bit ? p1 : 1.0 - p1;
   if (fmin(p1, 1.0 - p1) > a.tol) atomicOr(a.status, 1u);
-  const uint64_t ri = (uint64_t)(a.t0 + tb) * a.n_measure + a.idx[j];
-  a.mr_bits[ri] = (uint8_t)bit;
   // Every measure-reset of the step scales the whole state once; the step's
   // first one also carries the 1/||psi|| renormalisation.
-  a.mr_norm[ri] = norm_here ? 1.0 / sqrt(pb * tot) : 1.0 / sqrt(pb);
+  const double sc = norm_here ? 1.0 / sqrt(pb * tot) : 1.0 / sqrt(pb);
+  const uint32_t row = a.rows == nullptr                ? a.t0 + tb
+                       : a.rows[tb].y >= a.carrier0 ? a.carrier_t
+                                                    : a.t0 + a.rows[tb].y;
+  const uint64_t ri = (uint64_t)row * a.n_measure + a.idx[j];
+  a.mr_bits[ri] = (uint8_t)bit;
+  a.mr_norm[ri] = sc;
+}
+
+// Trajectories still on the error-free prefix at a decision step hold the
+// prefix state, so they take its decisions: copy the group's entries of the
+// prefix state's record row to theirs (one thread per batch trajectory).
+__global__ void k_mr_follow(MrDecideArgs a) {
+  const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= a.bb || a.eff[a.t0 + b] <= a.step) return;
+  const uint64_t src = (uint64_t)a.carrier_t * a.n_measure, dst = (uint64_t)(a.t0 + b) * a.n_measure;
+  for (uint32_t j = 0; j < a.nq; ++j) {
+    a.mr_bits[dst + a.idx[j]] = a.mr_bits[src + a.idx[j]];
+    a.mr_norm[dst + a.idx[j]] = a.mr_norm[src + a.idx[j]];
+  }
 }
 
 // ------------------------------------------------------------------ sampler
@@ -1653,6 +1673,7 @@ template <typename V>
 hipError_t launch_marginal(const MarginalArgs<V>& a, const MrDecideArgs& d, uint32_t batch, hipStream_t s) {
   hipLaunchKernelGGL(k_marginal<V>, dim3(a.nblk, batch), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_mr_decide, dim3(batch), dim3(64), 0, s, d);
+  if (d.rows && d.eff && d.bb) hipLaunchKernelGGL(k_mr_follow, dim3((d.bb + 255) / 256), dim3(256), 0, s, d);
   return hipGetLastError();
 }
 

@@ -49,7 +49,9 @@ __host__ __device__ inline uint64_t swizzle(uint64_t x, uint32_t on) {
 //       read and slot route[y].y written; slots >= carrier0 hold error-free
 //       prefix states and use no overrides, any other slot b is trajectory
 //       t0 + b; route == nullptr means y -> y;
-//   N, n, pass, n_passes, t0, n_measure.
+//   N, n, pass, n_passes, t0, n_measure, swz;
+//   carrier_t          record row (measure-reset bits and factors) of the
+//       error-free prefix state (the row after the set's last trajectory).
 #define PTSBE_PASS_ARGS_FIELDS(V, DPASS, DOP, DOV, U2)                                        \
   const DPASS* passes;                                                                       \
   const DOP* ops;                                                                            \
@@ -68,7 +70,8 @@ __host__ __device__ inline uint64_t swizzle(uint64_t x, uint32_t on) {
   uint32_t n_passes;                                                                         \
   uint32_t t0;                                                                               \
   uint32_t n_measure;                                                                        \
-  uint32_t swz;
+  uint32_t swz;                                                                              \
+  uint32_t carrier_t;
 
 template <typename V>
 struct PassArgs {
@@ -114,6 +117,9 @@ struct MarginalArgs {
   uint32_t per_block;
   uint32_t nq;
   uint32_t q[kMaxGroup];
+  // optional list of the states to sum: row y sums state slot rows[y].x
+  // (nullptr: row y sums slot y)
+  const uint2* rows;
 };
 
 struct MrDecideArgs {
@@ -137,6 +143,16 @@ struct MrDecideArgs {
   // 1/||psi|| renormalisation (a step with more than kMaxGroup entries is
   // decided in several groups from the same state, which is rescaled once)
   uint32_t carries_norm;
+  // Prefix sharing (measure-resets only; nullptr: row tb decides trajectory
+  // t0 + tb): row tb decides the state of rows[tb] as in MarginalArgs, whose
+  // record row is t0 + rows[tb].y, or carrier_t when rows[tb].y >= carrier0
+  // (the error-free prefix state).  A second launch copies that row's
+  // decisions to every batch trajectory b < bb with eff[t0 + b] > step (still
+  // on the prefix).
+  const uint2* rows;
+  uint32_t carrier0, carrier_t;
+  const uint32_t* eff;
+  uint32_t step, bb;
 };
 
 template <typename BitT>

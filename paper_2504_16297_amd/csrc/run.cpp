@@ -18,21 +18,26 @@ namespace {
 uint64_t a256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
 
 struct WsLayout {
-  uint64_t status, tables, routes, states, cdf, partial, offs, total, mr_partial, mr_bits, mr_norm, rec_info, weights,
-      sup_part, sup_offs, sup_count, sup_cdf, sup_idx, maxa, floor, end;
+  uint64_t status, tables, routes, eff, states, cdf, partial, offs, total, mr_partial, mr_bits, mr_norm, rec_info,
+      weights, sup_part, sup_offs, sup_count, sup_cdf, sup_idx, maxa, floor, end;
   bool support;
   uint32_t batch;
   uint32_t nblk, per_block, per_thread;
   bool share;
 };
 
-// Prefix sharing applies to plans without measure-resets whose first pass
-// starts from |0>, when at least two trajectories are run and it is not off.
+// Prefix sharing applies to plans whose first pass starts from |0> and whose
+// last step is a pass, when at least two trajectories are run and it is not
+// off.  Measure-resets may sit between the passes: their outcome is a function
+// of the state alone ([p1 > 1/2]), so a trajectory still on the error-free
+// prefix takes the prefix state's decisions.  State-dependent channels draw a
+// uniform per trajectory and end the sharing for their plans.
 bool prefix_sharing(const Plan& P, const TrajSet& ts, const ptsbe_run_opts* o) {
   if (o->flags & PTSBE_RUN_NO_PREFIX_SHARING) return false;
-  if (P.n_measure || ts.m.size() < 2 || P.exec.empty()) return false;
+  if (P.n_general || ts.m.size() < 2 || P.exec.empty()) return false;
   for (const ExecStep& ex : P.exec)
-    if (ex.pass < 0) return false;
+    if (ex.dense || ex.restore >= 0) return false;
+  if (P.exec.front().pass < 0 || P.exec.back().pass < 0) return false;
   return (P.passes[P.exec[0].pass].flags & PASS_INIT_ZERO) != 0;
 }
 
@@ -53,6 +58,8 @@ WsLayout layout_for(const Plan& P, const TrajSet& ts, uint32_t mode, uint32_t ba
   L.tables = o; o = a256(o + table_bytes);
   L.routes = o;
   if (share) o = a256(o + P.exec.size() * (Btot + n_batches) * sizeof(uint2));
+  L.eff = o;
+  if (share) o = a256(o + Btot * sizeof(uint32_t));
   L.states = o; o = a256(o + (uint64_t)(batch + (share ? 2 : 0)) * N * esz);
   L.cdf = o;
   if (mode == PTSBE_RUN_SHOTS && P.precision == PTSBE_C128) o = a256(o + (uint64_t)batch * N * 8);
@@ -61,8 +68,10 @@ WsLayout layout_for(const Plan& P, const TrajSet& ts, uint32_t mode, uint32_t ba
   L.total = o; o = a256(o + (uint64_t)batch * 8);
   L.mr_partial = o;
   if (P.n_measure) o = a256(o + (uint64_t)batch * L.nblk * (kMaxGroup + 1) * 8);
-  L.mr_bits = o; o = a256(o + std::max<uint64_t>(1, Btot * P.n_measure));
-  L.mr_norm = o; o = a256(o + std::max<uint64_t>(1, Btot * P.n_measure) * 8);
+  // records: one row per trajectory, plus the error-free prefix state's row under sharing
+  const uint64_t rec_rows = Btot + (share ? 1 : 0);
+  L.mr_bits = o; o = a256(o + std::max<uint64_t>(1, rec_rows * P.n_measure));
+  L.mr_norm = o; o = a256(o + std::max<uint64_t>(1, rec_rows * P.n_measure) * 8);
   L.rec_info = o;
   if (P.n_general) o = a256(o + (uint64_t)P.n_measure * 8 + P.rec_info.chan_param.size() * 8);
   L.weights = o;
@@ -139,13 +148,16 @@ double pass_flops_per_amp(const Pass& ps) {
 }
 
 // Launch routes of one batch under prefix sharing.  eff[b] is the first
-// execution step whose pass the trajectory's record changes (the last step if
-// none does); before it the trajectory's state equals the error-free state,
-// which is carried in slots bb and bb + 1 (read one, write the other, swap).
-// At step e: trajectories with eff == e read the carried state, those with
-// eff < e their own, and the carrier advances while some eff > e.
+// execution step whose pass the trajectory's record changes (the last step,
+// a pass, if none does); before it the trajectory's state equals the
+// error-free state, which is carried in slots bb and bb + 1 (read one, write
+// the other, swap).  At pass step e: trajectories with eff == e read the
+// carried state, those with eff < e their own, and the carrier advances while
+// some eff > e.  At a measure-reset step e the rows are the states to decide:
+// each trajectory with eff < e, and the carried state (destination bb) while
+// some eff > e.  eff is appended to eff_out (batch order).
 void build_routes(const Plan& P, const TrajSet& ts, uint32_t b0, uint32_t bb, std::vector<uint32_t>& out,
-                  std::vector<uint32_t>& off) {
+                  std::vector<uint32_t>& off, std::vector<uint32_t>& eff_out) {
   const TableLayout& T = ts.layout;
   const uint32_t* ov_off = reinterpret_cast<const uint32_t*>(ts.table_blob.data() + T.ov_off);
   const uint32_t NP = (uint32_t)P.passes.size();
@@ -154,6 +166,7 @@ void build_routes(const Plan& P, const TrajSet& ts, uint32_t b0, uint32_t bb, st
   for (uint32_t b = 0; b < bb; ++b) {
     const uint64_t row = (uint64_t)(b0 + b) * NP;
     for (uint32_t e = 0; e < E; ++e) {
+      if (P.exec[e].pass < 0) continue;
       const uint32_t p = (uint32_t)P.exec[e].pass;
       if (ov_off[row + p + 1] > ov_off[row + p]) {
         eff[b] = e;
@@ -166,6 +179,21 @@ void build_routes(const Plan& P, const TrajSet& ts, uint32_t b0, uint32_t bb, st
   for (uint32_t e = 0; e < E; ++e) {
     off[e] = (uint32_t)(out.size() / 2);
     bool carry = false;
+    if (P.exec[e].pass < 0) {
+      for (uint32_t b = 0; b < bb; ++b) {
+        if (eff[b] < e) {
+          out.push_back(b);
+          out.push_back(b);
+        } else {
+          carry = true;
+        }
+      }
+      if (carry) {
+        out.push_back(cur);
+        out.push_back(bb);
+      }
+      continue;
+    }
     for (uint32_t b = 0; b < bb; ++b) {
       if (eff[b] < e) {
         out.push_back(b);
@@ -184,6 +212,7 @@ void build_routes(const Plan& P, const TrajSet& ts, uint32_t b0, uint32_t bb, st
     }
   }
   off[E] = (uint32_t)(out.size() / 2);
+  eff_out.insert(eff_out.end(), eff.begin(), eff.end());
 }
 
 // Stage timer: HIP events recorded on the caller's stream between launches;
@@ -311,20 +340,27 @@ ptsbe_status run_typed(const Plan& P, TrajSet& ts, const ptsbe_run_opts& o, uint
   // routes of every batch, uploaded once
   std::vector<uint32_t>& route_off = ts.route_off;
   std::vector<uint32_t>& routes = ts.route_host;
+  std::vector<uint32_t>& eff = ts.eff_host;
   routes.clear();
   route_off.clear();
+  eff.clear();
   if (L.share) {
     std::vector<uint32_t> off;
     for (uint32_t b0 = 0; b0 < B; b0 += L.batch) {
-      build_routes(P, ts, b0, std::min<uint32_t>(L.batch, B - b0), routes, off);
+      build_routes(P, ts, b0, std::min<uint32_t>(L.batch, B - b0), routes, off, eff);
       route_off.insert(route_off.end(), off.begin(), off.end());
     }
-    if (phase & PH_UPLOAD)
+    if (phase & PH_UPLOAD) {
       CK(hipMemcpyAsync(ws + L.routes, routes.data(), routes.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s),
          "route upload");
+      if (P.n_measure)
+        CK(hipMemcpyAsync(ws + L.eff, eff.data(), eff.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s),
+           "route upload");
+    }
   }
   if (!(phase & PH_LAUNCH)) return PTSBE_OK;
   const uint2* d_routes = reinterpret_cast<const uint2*>(ws + L.routes);
+  const uint32_t* d_eff = reinterpret_cast<const uint32_t*>(ws + L.eff);
   CK(tm.mark(T_OTHER), "timer");
 
   PassArgs<V> pa{};
@@ -342,6 +378,7 @@ ptsbe_status run_typed(const Plan& P, TrajSet& ts, const ptsbe_run_opts& o, uint
   pa.n_passes = (uint32_t)P.passes.size();
   pa.n_measure = (uint32_t)P.n_measure;
   pa.swz = P.swizzle ? 1u : 0u;
+  pa.carrier_t = B;  // the record row after the set's last trajectory
 
   const uint32_t E = (uint32_t)P.exec.size();
   for (uint32_t b0 = 0, bi = 0; b0 < B; b0 += L.batch, ++bi) {
@@ -383,7 +420,16 @@ ptsbe_status run_typed(const Plan& P, TrajSet& ts, const ptsbe_run_opts& o, uint
            "state-dependent channel");
         CK(tm.mark(T_MEASURE), "timer");
       } else {
-        for (size_t g0 = 0; g0 < ex.mr_qubits.size(); g0 += kMaxGroup) {
+        // states to decide: the batch, or under sharing the trajectories past
+        // their first own pass and the error-free prefix state
+        uint32_t rows = bb;
+        const uint2* d_rows = nullptr;
+        if (L.share) {
+          const uint32_t r0 = route_off[(size_t)bi * (E + 1) + e], r1 = route_off[(size_t)bi * (E + 1) + e + 1];
+          rows = r1 - r0;
+          d_rows = d_routes + r0;
+        }
+        for (size_t g0 = 0; rows && g0 < ex.mr_qubits.size(); g0 += kMaxGroup) {
           size_t g1 = std::min(ex.mr_qubits.size(), g0 + kMaxGroup);
           MarginalArgs<V> ma{};
           ma.swz = pa.swz;
@@ -414,7 +460,14 @@ ptsbe_status run_typed(const Plan& P, TrajSet& ts, const ptsbe_run_opts& o, uint
             ma.q[j - g0] = (uint32_t)ex.mr_qubits[j];
             da.idx[j - g0] = (uint32_t)ex.mr_index[j];
           }
-          CK(launch_marginal<V>(ma, da, bb, s), "measure-reset");
+          ma.rows = d_rows;
+          da.rows = d_rows;
+          da.carrier0 = bb;
+          da.carrier_t = B;
+          da.eff = d_eff;
+          da.step = e;
+          da.bb = bb;
+          CK(launch_marginal<V>(ma, da, rows, s), "measure-reset");
           CK(tm.mark(T_MEASURE), "timer");
         }
       }

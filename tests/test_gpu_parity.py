@@ -319,21 +319,22 @@ def test_expectation_mode_matches_oracle():
 
 
 def _expected_state_passes(ts, B_batch):
-    """Rows launched under prefix sharing: per batch and execution step, the
+    """Rows launched under prefix sharing: per batch and pass step, the
     trajectories that have diverged by then, plus one carrier row while some
     have not (a trajectory diverges at the first pass its overrides touch, or
-    at the last pass)."""
+    at the last pass; measure-reset steps launch no pass)."""
     from paper_2504_16297_amd.tables import export_tables
     t = export_tables(ts)
     NP = len(t["passes"])
     ex = [int(e["pass"]) for e in t["exec"]]
+    is_pass = [p < NP for p in ex]
     ov = t["ov_off"].astype(np.int64)
     B = ts.n_traj
     eff = []
     for b in range(B):
         f = len(ex) - 1
         for e, p in enumerate(ex):
-            if ov[b * NP + p + 1] > ov[b * NP + p]:
+            if is_pass[e] and ov[b * NP + p + 1] > ov[b * NP + p]:
                 f = e
                 break
         eff.append(f)
@@ -341,7 +342,8 @@ def _expected_state_passes(ts, B_batch):
     for b0 in range(0, B, B_batch):
         sub = eff[b0:b0 + B_batch]
         for e in range(len(ex)):
-            rows += sum(1 for f in sub if f <= e) + (1 if any(f > e for f in sub) else 0)
+            if is_pass[e]:
+                rows += sum(1 for f in sub if f <= e) + (1 if any(f > e for f in sub) else 0)
     return rows
 
 
@@ -373,6 +375,43 @@ def test_prefix_sharing_is_bit_identical(max_batch):
     ref, _ = oracle_states(circ, ts.get()["records"])
     err = max(float(np.max(np.abs(s1[a] - ref[a]))) for a in range(len(ref)))
     assert err <= 1e-5
+
+
+@pytest.mark.parametrize("max_batch", [0, 100])
+def test_prefix_sharing_with_measure_resets(max_batch):
+    """The surface code's measure-resets decide from the state alone, so the
+    error-free prefix is shared across them: states, measure-reset records and
+    tagged shots equal the unshared run bit for bit (trajectories leave the
+    prefix before, between and after the decision steps), and the launched
+    state-passes match the count the records imply."""
+    log(f"[prefix sharing, measure-resets] max_batch={max_batch}")
+    wl = c3_workload()
+    plan = P.ptsbe_plan(wl["circuit"])
+    ts = P.ptsbe_sample_kraus(plan, "most_likely", k_max=512, total_shots=10 ** 5)
+    outs = []
+    for share in (True, False):
+        tm = np.zeros(10)
+        r = P.ptsbe_run_batch(plan, ts, mode="states", max_batch=max_batch, prefix_sharing=share, timing=tm)
+        P.ptsbe_run_status(plan, r["workspace"])
+        s = P.ptsbe_run_batch(plan, ts, seed=0, cfg=3, max_batch=max_batch, prefix_sharing=share)
+        P.ptsbe_run_status(plan, s["workspace"])
+        torch.cuda.synchronize()
+        outs.append((r["states"].cpu().numpy(), r["mr_bits"].cpu().numpy(), s["mr_bits"].cpu().numpy(),
+                     s["bits"].cpu().numpy(), s["traj"].cpu().numpy(), tm))
+        del r, s
+    (st1, m1, sm1, b1, t1, tm1), (st0, m0, sm0, b0, t0, tm0) = outs
+    assert np.array_equal(m1, m0) and np.array_equal(sm1, sm0) and np.array_equal(m1, sm1)
+    assert np.array_equal(st1, st0)
+    assert np.array_equal(b1, b0) and np.array_equal(t1, t0)
+    B = ts.n_traj
+    assert tm0[9] == B * plan.info["n_passes"]
+    assert tm1[9] == _expected_state_passes(ts, max_batch or B)
+    log(f"  state-passes shared {tm1[9]:.0f} vs {tm0[9]:.0f}")
+    assert tm1[9] < 0.8 * tm0[9]
+    g = ts.get()
+    for a, rec in enumerate(g["records"]):
+        fb, _ = frame_run(wl["circuit"], rec)
+        assert list(m1[a]) == fb, f"trajectory {a}"
 
 
 @pytest.mark.parametrize("n,prec,tile", [(12, "c64", 0), (14, "c64", 9), (12, "c128", 0), (13, "c128", 8)])
