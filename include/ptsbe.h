@@ -396,11 +396,15 @@ typedef struct {
                                    summed on the device in trajectory order */
 } ptsbe_run_opts;
 
-/* Prefix sharing (default for plans without measure-resets): a trajectory's
+/* Prefix sharing (default for plans without state-dependent channels whose
+ * first step is a pass from |0> and whose last step is a pass): a trajectory's
  * passes before the first one its noise record changes are not run for it;
  * one error-free state (double-buffered, two extra states of workspace) is
  * carried through those passes and each trajectory's first own pass reads it.
- * Results are bit-identical to running every pass for every trajectory. */
+ * A measure-reset decision (outcome [p1 > 1/2], Sec. 2.2's general Kraus
+ * branch) is taken once for the carried state and copied to the trajectories
+ * still on it.  Results, records included, are bit-identical to running every
+ * pass for every trajectory. */
 #define PTSBE_RUN_NO_PREFIX_SHARING 1u
 /* Sampler support lists (default for states of at most 2^21 amplitudes): the
  * CDF scan also lists, per state, the elements an upper-bound search can return
