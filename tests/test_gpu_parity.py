@@ -439,12 +439,20 @@ def test_compiled_passes_match_generic_kernels(n, prec, tile):
     assert err <= tol
 
 
-@pytest.mark.parametrize("wl_name", ["c1", "random12"])
+@pytest.mark.parametrize("wl_name", ["c1", "random12", "surface_code"])
 def test_graph_replays_match_eager(wl_name):
     """A captured run replayed several times, with eager work and synchronisation
-    between replays, reproduces the eager run's shots bit for bit each time."""
+    between replays, reproduces the eager run's shots bit for bit each time
+    (the surface code: measure-reset decisions and their prefix-sharing copies
+    inside the graph, records checked too)."""
     log(f"[graph] {wl_name}")
-    if wl_name == "c1":
+    if wl_name == "surface_code":
+        wl = c3_workload()
+        circ = wl["circuit"]
+        plan = P.ptsbe_plan(circ)
+        ts = P.ptsbe_sample_kraus(plan, "most_likely", k_max=256, total_shots=50000)
+        seed, cfg = 0, 3
+    elif wl_name == "c1":
         wl = c1_workload()
         circ, prec = wl["circuit"], "c128"
         pts = wl["pts"]
@@ -466,11 +474,15 @@ def test_graph_replays_match_eager(wl_name):
     for rep in range(4):
         cap["bits"].fill_(-1)
         cap["traj"].fill_(-1)
+        if "mr_bits" in cap:
+            cap["mr_bits"].fill_(255)
         torch.cuda.synchronize()
         g.launch(stream=s)
         s.synchronize()
         assert np.array_equal(cap["bits"].cpu().numpy(), eb), rep
         assert np.array_equal(cap["traj"].cpu().numpy(), et), rep
+        if "mr_bits" in eager:
+            assert np.array_equal(cap["mr_bits"].cpu().numpy(), eager["mr_bits"].cpu().numpy()), rep
         x = torch.randn(1 << 16, device="cuda")       # unrelated eager work between replays
         float((x * x).sum())
 
