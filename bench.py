@@ -398,6 +398,7 @@ def main():
     ap.add_argument("--fingerprint", action="store_true",
                     help="only print the kernel fingerprint of the workload's plans (host only)")
     ap.add_argument("--no-q33", action="store_true", help="skip the 33-qubit trajectory (c4)")
+    ap.add_argument("--no-graph", action="store_true", help="skip the captured-graph replay of the step (c4)")
     ap.add_argument("--q35", action="store_true", help="also time one 35-qubit trajectory (c4)")
     ap.add_argument("--no-errors", action="store_true",
                     help="skip the 24-qubit trajectory's comparison with the stored oracle values (c4)")
@@ -629,6 +630,35 @@ def c4_plan(P, wl):
     return P.ptsbe_plan(wl["circuit"], precision=wl["precision"], **(opts or {})), opts
 
 
+def c4_graph_replay(P, torch, runs, steps):
+    """The mixed batch's step as one captured HIP graph per size (every tile
+    pass, scan and sampler launch of that size's run), replayed `steps` times
+    back to back on one created stream after a warm replay, whose shots and
+    tags are compared with the last eager step's."""
+    s = torch.cuda.Stream()
+    ref = [(r["out"]["bits"].clone(), r["out"]["traj"].clone()) for r in runs]
+    caps = [P.ptsbe_run_batch(r["plan"], r["ts"], seed=r["wl"]["seed"], cfg=r["wl"]["cfg"], workspace=r["ws"],
+                              out=r["out"], stream=s, capture=True) for r in runs]
+    for c in caps:
+        c["bits"].fill_(-1)
+        c["traj"].fill_(-1)
+    torch.cuda.synchronize()
+    for c in caps:
+        c["graph"].launch(stream=s)
+    s.synchronize()
+    same = all(torch.equal(c["bits"], b) and torch.equal(c["traj"], t) for c, (b, t) in zip(caps, ref))
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for c in caps:
+            c["graph"].launch(stream=s)
+    s.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    S = sum(r["S"] for r in runs)
+    del caps, ref
+    return {"graphs": len(runs), "steps": steps, "ms_per_step": dt * 1e3, "shots_per_s": S / dt,
+            "bit_identical": bool(same)}
+
+
 def copy_rate(torch, gib=4, reps=5):
     """GB/s (bytes read + written) of torch's device-to-device copy of `gib` GiB
     on the current GPU: a plain streaming kernel that reads and writes every
@@ -753,6 +783,12 @@ def bench_c4(args):
             f"{err['shot_mismatches']} of {err['shots_compared']} shots differ "
             f"({err['shot_mismatches_away_from_cdf_boundary']} away from a boundary), "
             f"TVD {err['histogram_tvd_1024_bins']:.4f} (sampling noise {err['tvd_expected_from_sampling']:.4f})")
+    if not args.no_graph:
+        gr = c4_graph_replay(P, torch, runs, min(args.steps, 5))
+        result["graph_replay"] = gr
+        log(f"[bench c4] captured step: {gr['graphs']} HIP graphs replayed {gr['steps']} times, "
+            f"{gr['ms_per_step']:.1f} ms/step, {gr['shots_per_s']:.4g} shots/s, shots equal to the eager run's: "
+            f"{gr['bit_identical']}")
     for r in runs:
         del r["ws"], r["out"]
     torch.cuda.empty_cache()
