@@ -429,7 +429,10 @@ ptsbe_status ptsbe_workspace_size(ptsbe_plan_t plan, ptsbe_trajset_t ts, const p
  * d_bits[j] is the basis index (uint32 if n <= 32, else uint64), d_traj[j]
  * the global trajectory id.  d_mr_bits (optional, n_traj x n_measure bytes)
  * receives each trajectory's measure-reset record.  All device pointers are
- * caller-owned; the call only enqueues work on `stream`. */
+ * caller-owned; the call only enqueues work on `stream`.  An empty trajectory
+ * set enqueues only the clearing of the workspace's status word and returns
+ * PTSBE_OK, except in expectation mode with d_ensemble set (PTSBE_E_ARG: the
+ * ensemble value has no weights). */
 ptsbe_status ptsbe_run_batch(ptsbe_plan_t plan, ptsbe_trajset_t ts, const ptsbe_run_opts* opts,
                              void* d_ws, size_t ws_bytes, void* d_bits, uint32_t* d_traj,
                              uint64_t capacity, uint8_t* d_mr_bits, void* stream);
@@ -465,7 +468,7 @@ ptsbe_status ptsbe_run_batch_noalloc(ptsbe_plan_t plan, ptsbe_trajset_t ts, cons
  * instantiated.  Each ptsbe_graph_launch replays it: same inputs, same
  * outputs, no host work.  The workspace and output buffers must outlive the
  * graph and must not be reused by other calls in between.  opts->timing must
- * be NULL. */
+ * be NULL; an empty trajectory set fails with PTSBE_E_ARG. */
 typedef struct ptsbe_graph_s* ptsbe_graph_t;
 ptsbe_status ptsbe_graph_create(ptsbe_plan_t plan, ptsbe_trajset_t ts, const ptsbe_run_opts* opts,
                                 void* d_ws, size_t ws_bytes, void* d_bits, uint32_t* d_traj,

@@ -559,14 +559,15 @@ ptsbe_status check_opts(const Plan& P, const TrajSet& ts, const ptsbe_run_opts* 
   uint32_t c = o->sort_chunk ? o->sort_chunk : 4096;
   if (c < 256 || c > 4096 || (c & (c - 1))) return fail(PTSBE_E_ARG, "sort_chunk must be a power of two in 256..4096");
   if (P.n_params && !o->params) return fail(PTSBE_E_ARG, "the circuit has parameters: params required");
-  if (outputs && o->mode == PTSBE_RUN_STATES && !o->d_state_out)
+  // per-trajectory outputs are needed only when there are trajectories
+  const bool any = !ts.m.empty();
+  if (outputs && any && o->mode == PTSBE_RUN_STATES && !o->d_state_out)
     return fail(PTSBE_E_ARG, "STATES mode needs d_state_out");
   if (o->mode == PTSBE_RUN_EXPECTATION) {
-    if (outputs && !o->d_expval) return fail(PTSBE_E_ARG, "EXPECTATION mode needs d_expval");
+    if (outputs && any && !o->d_expval) return fail(PTSBE_E_ARG, "EXPECTATION mode needs d_expval");
     if (o->n_terms > 64 || (o->n_terms && (!o->obs_coef || !o->obs_zmask)))
       return fail(PTSBE_E_ARG, "observable: at most 64 Z-string terms with coefficients and masks");
   }
-  (void)ts;
   return PTSBE_OK;
 }
 
@@ -609,7 +610,18 @@ ptsbe_status run_batch(const Plan& P, TrajSet& ts, const ptsbe_run_opts* o, void
   st = build_tables(ts, o->params, chunk);
   if (st != PTSBE_OK) return st;
   const uint32_t B = (uint32_t)ts.m.size();
-  if (B == 0) return PTSBE_OK;
+  if (B == 0) {
+    // nothing to prepare or draw (an ensemble value or a graph would be
+    // undefined); the status word is cleared so that ptsbe_run_status reads OK
+    if (graph_out) return fail(PTSBE_E_ARG, "empty trajectory set: nothing to capture");
+    if (o->mode == PTSBE_RUN_EXPECTATION && o->d_ensemble)
+      return fail(PTSBE_E_ARG, "empty trajectory set: the ensemble value has no weights");
+    if (ws_bytes < 16) return fail(PTSBE_E_ARG, "workspace smaller than its 16-byte status word");
+    hipStream_t s0 = static_cast<hipStream_t>(stream);
+    CK(launch_fill_u32(static_cast<uint32_t*>(d_ws), 0, 4, s0), "status reset");
+    if (d_status) CK(launch_fill_u32(d_status, 0, 1, s0), "status reset");
+    return PTSBE_OK;
+  }
   uint32_t batch = o->max_batch ? std::min(o->max_batch, B) : B;
   batch = std::min<uint32_t>(batch, 65534);  // grid.y limit of the per-state launches (+1 carrier row)
   const bool share = prefix_sharing(P, ts, o);
