@@ -114,6 +114,8 @@ struct Slot {
   std::vector<int> sites;      // sites whose choice changes this slot
   bool uses_params = false;
   bool m2_next[2] = {false, false};  // 4x4: the next non-diagonal operation on matrix bit j's qubit is a matrix
+  uint8_t form = 0;            // reverse sweep, 2x2 slots no record changes: 3 real, 4 diagonal for every
+                               // parameter value (the compiled sweep applies that form), else 0
 };
 
 struct Pass {

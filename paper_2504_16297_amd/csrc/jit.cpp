@@ -64,6 +64,7 @@ struct Gen {
   bool ok = true;
   std::string why;
   const uint8_t* frame = nullptr;  // FrameRole per slot
+  const uint8_t* form = nullptr;   // reverse sweep: Slot::form per slot
 
   // bit of `slot` in the block's override set (wave-uniform words)
   std::string ovbit(int slot) const {
@@ -150,14 +151,19 @@ struct Gen {
   }
 
   // ---- 2x2 matrix on register position j: form 0 general, 1 real diagonal,
-  // 2 unit diagonal
+  // 2 unit diagonal, 3 real matrix, 4 diagonal matrix
   void gate_body(int j, int form) {
     for (const std::string& st : sets()) {
       pre = st;
       for (int r = 0; r < 16; ++r) {
         if ((r >> j) & 1) continue;
         const int r1 = r | (1 << j);
-        if (form == 2)
+        if (form == 4)
+          o << "    " << S(r) << " = cm(m0, " << S(r) << "); " << S(r1) << " = cm(m3, " << S(r1) << ");\n";
+        else if (form == 3)
+          o << "    { const V x0 = " << S(r) << ", x1 = " << S(r1) << "; " << S(r) << " = crr(m0.x, x0, m1.x, x1); "
+            << S(r1) << " = crr(m2.x, x0, m3.x, x1); }\n";
+        else if (form == 2)
           o << "    { const V x0 = " << S(r) << ", x1 = " << S(r1) << "; " << S(r) << " = cu(x0, m1, x1); " << S(r1)
             << " = cu(x1, m2, x0); }\n";
         else if (form == 1)
@@ -190,8 +196,11 @@ struct Gen {
       o << "\n  }\n";
       return;
     }
+    // a pending block-uniform phase keeps a diagonal matrix diagonal, not a real one real
+    const int f = form ? (int)form[slot] : 0;
+    const int use = f == 4 || (f == 3 && !pending) ? f : 0;
     apply_pending_to("m0", "m1", "m2", "m3");
-    gate_body(j, 0);
+    gate_body(j, use);
     o << "  }\n";
   }
 
@@ -684,6 +693,13 @@ __device__ __forceinline__ void stnt(V* p, V v) {
 // in the state's precision
 const char* kDualHelpers = R"(__device__ __forceinline__ T imc(V a, V b) { return a.x * b.y - a.y * b.x; }
 __device__ __forceinline__ T rec(V a, V b) { return a.x * b.x + a.y * b.y; }
+// a * x0 + b * x1 for real a, b: a row of a real 2x2 matrix
+__device__ __forceinline__ V crr(T a, V x0, T b, V x1) {
+  V r;
+  r.x = a * x0.x + b * x1.x;
+  r.y = a * x0.y + b * x1.y;
+  return r;
+}
 )";
 
 std::string bit_gather(const char* src, const std::vector<int>& dst_pos, int first_src_bit) {
@@ -748,6 +764,9 @@ std::string gen_pass(const Pass& ps, int n, int precision, const std::string& na
       ovw_words.insert(i >> 5);
   }
   g.frame = frame.data();
+  std::vector<uint8_t> form(n_slots);
+  for (int i = 0; i < n_slots; ++i) form[i] = dual ? ps.slots[i].form : 0;
+  g.form = form.data();
   const int n_ovw = (n_slots + 31) / 32;
   std::ostringstream& o = g.o;
   o << kPrelude << (g.c64 ? "typedef float T;\ntypedef float2 V;\n" : "typedef double T;\ntypedef double2 V;\n")

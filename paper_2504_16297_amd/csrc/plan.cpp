@@ -1517,6 +1517,28 @@ ptsbe_status build_plan(const ptsbe_circuit* c, const ptsbe_noise_model* nm, con
     // two tiles (psi and lambda) share the LDS: one tile bit less
     st = schedule_best(P, A.steps, A.passes, A.exec, A.site_slots, false, true, std::max(4, P.tile_bits - 1));
     if (st != PTSBE_OK) return st;
+    // A 2x2 slot that no record changes, made of one-qubit gates that are all
+    // diagonal (Z rotations, phases), or all real (Y rotations, real fixed
+    // gates), keeps that form for every parameter value: the sweep applies it
+    // with half the arithmetic of a general complex matrix.
+    for (Pass& ps : A.passes)
+      for (Slot& sl : ps.slots) {
+        if (sl.type != DOP_M1 || !sl.sites.empty() || sl.parts.empty()) continue;
+        bool diag = true, real = true;
+        for (const Part& pt : sl.parts) {
+          const Step& s = A.steps[pt.step];
+          if (pt.half >= 0 || pt.emb >= 0 || s.nq != 1 || (s.kind != ST_GATE && s.kind != ST_PARAM)) {
+            diag = real = false;
+            break;
+          }
+          diag = diag && s.diag;
+          bool r = s.kind == ST_PARAM ? s.gen == PTSBE_GEN_Y : true;
+          if (s.kind == ST_GATE)
+            for (const cd& z : s.mat) r = r && z.imag() == 0.0;
+          real = real && r;
+        }
+        sl.form = diag ? 4 : real ? 3 : 0;
+      }
     P.has_adjoint = true;
   }
   *out = plan;
