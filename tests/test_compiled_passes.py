@@ -101,6 +101,40 @@ def test_adjoint_sweep_kernels(n, prec, seed):
     assert float(np.max(np.abs(G - Gr))) <= tol * max(1.0, float(np.max(np.abs(Gr))))
 
 
+def test_adjoint_sweep_real_and_diagonal_forms():
+    """Reverse sweep of a hardware-efficient ansatz: Y rotations that no record
+    changes run as real 2x2 matrices, Z rotations as diagonals, noise slots
+    (which records change) in the general form; the gradient equals the
+    oracle's."""
+    from compiled_cpu import pass_source, run_compiled_adjoint
+    from oracle.adjoint import ensemble_value_and_grad, observable_diag
+    from workloads.circuits import hea_circuit, zz_ring
+    n = 8
+    circ = hea_circuit(n, 3, np.random.default_rng(41), 0.2)
+    params = np.asarray(circ["params"])
+    plan = P.ptsbe_plan(circ)
+    ts = P.ptsbe_sample_kraus(plan, "proportional", n_draws=4, total_shots=4, seed=2, cfg=9)
+    srcs = []  # every reverse-sweep pass (their count is not in the plan info)
+    p = 0
+    while True:
+        try:
+            srcs.append(pass_source(plan, p, adjoint=True))
+        except P.PtsbeError:
+            break
+        p += 1
+    body = "".join(srcs)
+    assert "= crr(m0.x, x0, m1.x, x1)" in body     # real form
+    assert "= cm(m0, s" in body and "= cm(m3, l" in body  # diagonal form, psi and lambda
+    assert "= cf(m0, x0, m1, x1)" in body          # general form (noise slots)
+    obs = zz_ring(n)
+    E, G = run_compiled_adjoint(plan, ts, params, observable_diag(n, obs))
+    g = ts.get()
+    w = g["count"].astype(np.float64) / g["count"].sum()
+    Er, Gr = ensemble_value_and_grad(circ, g["records"], w, params, obs)
+    assert abs(E - Er) <= 1e-5
+    assert float(np.max(np.abs(G - Gr))) <= 1e-5 * max(1.0, float(np.max(np.abs(Gr))))
+
+
 @pytest.mark.parametrize("frames", [True, False])
 def test_brick_phase_frames(frames):
     """Compiled passes of a brick circuit in phase frames: the fixed 2x2 slots
