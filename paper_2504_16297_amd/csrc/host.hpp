@@ -115,7 +115,9 @@ struct Slot {
   bool uses_params = false;
   bool m2_next[2] = {false, false};  // 4x4: the next non-diagonal operation on matrix bit j's qubit is a matrix
   uint8_t form = 0;            // reverse sweep, 2x2 slots no record changes: 3 real, 4 diagonal for every
-                               // parameter value (the compiled sweep applies that form), else 0
+                               // parameter value (the compiled sweep applies that form); noise-only slots
+                               // whose default is the identity: 5 (applied only where a record overrides
+                               // them); else 0
 };
 
 struct Pass {

@@ -198,6 +198,13 @@ struct Gen {
     }
     // a pending block-uniform phase keeps a diagonal matrix diagonal, not a real one real
     const int f = form ? (int)form[slot] : 0;
+    if (f == 5 && !pending) {
+      // the identity unless this block's trajectory overrides the slot
+      o << "  if " << ovcond(slot) << " {\n";
+      gate_body(j, 0);
+      o << "  }\n  }\n";
+      return;
+    }
     const int use = f == 4 || (f == 3 && !pending) ? f : 0;
     apply_pending_to("m0", "m1", "m2", "m3");
     gate_body(j, use);
@@ -765,7 +772,10 @@ std::string gen_pass(const Pass& ps, int n, int precision, const std::string& na
   }
   g.frame = frame.data();
   std::vector<uint8_t> form(n_slots);
-  for (int i = 0; i < n_slots; ++i) form[i] = dual ? ps.slots[i].form : 0;
+  for (int i = 0; i < n_slots; ++i) {
+    form[i] = dual ? ps.slots[i].form : 0;
+    if (form[i] == 5) ovw_words.insert(i >> 5);
+  }
   g.form = form.data();
   const int n_ovw = (n_slots + 31) / 32;
   std::ostringstream& o = g.o;

@@ -1521,9 +1521,17 @@ ptsbe_status build_plan(const ptsbe_circuit* c, const ptsbe_noise_model* nm, con
     // diagonal (Z rotations, phases), or all real (Y rotations, real fixed
     // gates), keeps that form for every parameter value: the sweep applies it
     // with half the arithmetic of a general complex matrix.
+    // A 2x2 slot of noise sites only whose default (no error) is the identity
+    // is applied only by the blocks whose trajectory overrides it.
     for (Pass& ps : A.passes)
       for (Slot& sl : ps.slots) {
-        if (sl.type != DOP_M1 || !sl.sites.empty() || sl.parts.empty()) continue;
+        if (sl.type != DOP_M1 || sl.parts.empty()) continue;
+        if (!sl.sites.empty()) {
+          bool sites_only = true;
+          for (const Part& pt : sl.parts) sites_only = sites_only && A.steps[pt.step].kind == ST_SITE;
+          if (sites_only && slot_matrix(P, A.steps, sl, nullptr, {}) == mat_identity(2)) sl.form = 5;
+          continue;
+        }
         bool diag = true, real = true;
         for (const Part& pt : sl.parts) {
           const Step& s = A.steps[pt.step];

@@ -104,8 +104,8 @@ def test_adjoint_sweep_kernels(n, prec, seed):
 def test_adjoint_sweep_real_and_diagonal_forms():
     """Reverse sweep of a hardware-efficient ansatz: Y rotations that no record
     changes run as real 2x2 matrices, Z rotations as diagonals, noise slots
-    (which records change) in the general form; the gradient equals the
-    oracle's."""
+    (which records change) in the general form and only where the block's
+    trajectory overrides them; the gradient equals the oracle's."""
     from compiled_cpu import pass_source, run_compiled_adjoint
     from oracle.adjoint import ensemble_value_and_grad, observable_diag
     from workloads.circuits import hea_circuit, zz_ring
@@ -126,6 +126,7 @@ def test_adjoint_sweep_real_and_diagonal_forms():
     assert "= crr(m0.x, x0, m1.x, x1)" in body     # real form
     assert "= cm(m0, s" in body and "= cm(m3, l" in body  # diagonal form, psi and lambda
     assert "= cf(m0, x0, m1, x1)" in body          # general form (noise slots)
+    assert "  if (__builtin_expect((ovw" in body    # ... applied only where overridden
     obs = zz_ring(n)
     E, G = run_compiled_adjoint(plan, ts, params, observable_diag(n, obs))
     g = ts.get()
