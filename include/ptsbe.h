@@ -155,7 +155,9 @@ typedef struct {
 #define PTSBE_PLAN_NO_PHASE_FRAMES 32u
 /* flags bits 8..11: the number of waves per SIMD (1..8) the compiled passes'
  * register budget is set for (512 / waves VGPRs, the compiler spills beyond
- * it); 0 leaves the budget to the compiler.  Each pass kernel holds its
+ * it); 0 leaves the budget of the forward passes to the compiler and sets
+ * three waves for the reverse sweep of the adjoint gradient (psi and lambda
+ * in registers).  Each pass kernel holds its
  * 4096-amplitude tile (32 KiB in complex64) in LDS, so up to 5 workgroups fit
  * a compute unit. */
 #define PTSBE_PLAN_WAVES_SHIFT 8u

@@ -123,8 +123,9 @@ def ptsbe_plan(circuit, precision="c64", tile_qubits=0, compile=True, min_fill=0
     matrices a partial register group must hold; ``half_tile`` moves amplitudes
     between register sets through half a tile of LDS; ``phase_frames=False``
     keeps every slot matrix as it is (no pending diagonals between matrices);
-    ``waves`` (1..8, 0 = compiler's choice) sets the compiled passes' register
-    budget to 512 / waves VGPRs; ``twirl`` replaces channels that are not unitary
+    ``waves`` (1..8, 0 = compiler's choice for the forward passes, three for
+    the adjoint's reverse sweep) sets the compiled passes' register budget to
+    512 / waves VGPRs; ``twirl`` replaces channels that are not unitary
     mixtures by their Pauli twirl (else they are rejected); ``pair_fusion=False``
     keeps diagonal 2-qubit gates apart from the 2x2 runs on their qubits; ``swizzle``: None
     stores states of PTSBE_SWIZZLE_MIN_QUBITS qubits or more swizzled, True every state above

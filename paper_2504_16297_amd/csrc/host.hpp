@@ -117,7 +117,10 @@ struct Slot {
   uint8_t form = 0;            // reverse sweep, 2x2 slots no record changes: 3 real, 4 diagonal for every
                                // parameter value (the compiled sweep applies that form); noise-only slots
                                // whose default is the identity: 5 (applied only where a record overrides
-                               // them); else 0
+                               // them); 4x4 slots without parameters whose default is a diagonal of +-1: 6
+                               // (negations from sign_mask, the matrix only where a record overrides them);
+                               // else 0
+  uint8_t sign_mask = 0;       // form 6: bit q set where the default's diagonal entry q is -1
 };
 
 struct Pass {

@@ -65,6 +65,7 @@ struct Gen {
   std::string why;
   const uint8_t* frame = nullptr;  // FrameRole per slot
   const uint8_t* form = nullptr;   // reverse sweep: Slot::form per slot
+  const uint8_t* smask = nullptr;  // reverse sweep: Slot::sign_mask per slot
 
   // bit of `slot` in the block's override set (wave-uniform words)
   std::string ovbit(int slot) const {
@@ -406,7 +407,28 @@ struct Gen {
         }
         pre = "s";
       };
+      const int f = form ? (int)form[op.slot[0]] : 0;
       o << "  {\n    const V* M = mats + " << m2_off[op.slot[0]] << ";\n";
+      if (f == 6) {
+        // a default of +-1 on the diagonal: negations, the matrix where overridden
+        o << "  if " << ovcond(op.slot[0]) << " {\n";
+        rows(false);
+        o << "  } else {\n";
+        const uint32_t mk = smask[op.slot[0]];
+        for (const std::string& st : sets()) {
+          pre = st;
+          for (int r = 0; r < 16; ++r) {
+            if ((r >> ja) & 1 || (r >> jb) & 1) continue;
+            const int idx[4] = {r, r | (1 << ja), r | (1 << jb), r | (1 << ja) | (1 << jb)};
+            for (int q = 0; q < 4; ++q)
+              if ((mk >> q) & 1) o << "    " << S(idx[q]) << ".x = -" << S(idx[q]) << ".x; " << S(idx[q]) << ".y = -"
+                                   << S(idx[q]) << ".y;\n";
+          }
+        }
+        pre = "s";
+        o << "  }\n  }\n";
+        return;
+      }
       if (unit4) {
         o << "  if " << ovcond(op.slot[0]) << " {\n";
         rows(false);
@@ -736,6 +758,10 @@ std::string gen_pass(const Pass& ps, int n, int precision, const std::string& na
   const int k = ps.k;
   if (k < (int)kMinRegTile || k > 13 || (dual && k > 12)) return "";
   if (dual && (ps.flags & PASS_INIT_ZERO)) return "";
+  // The reverse sweep holds psi and lambda in registers (64 of them for the
+  // amplitudes); left to itself the compiler can settle on two waves per SIMD
+  // where three fit with a few spilled registers and run faster.
+  if (dual && waves == 0) waves = 3;
   // two tiles per workgroup: tiles 2b and 2b + 1 of the block's state (they
   // differ in the lowest qubit outside the tile); forward passes only
   const bool two = tpb == 2 && !dual && n > k;
@@ -771,12 +797,14 @@ std::string gen_pass(const Pass& ps, int n, int precision, const std::string& na
       ovw_words.insert(i >> 5);
   }
   g.frame = frame.data();
-  std::vector<uint8_t> form(n_slots);
+  std::vector<uint8_t> form(n_slots), smask(n_slots);
   for (int i = 0; i < n_slots; ++i) {
     form[i] = dual ? ps.slots[i].form : 0;
-    if (form[i] == 5) ovw_words.insert(i >> 5);
+    smask[i] = ps.slots[i].sign_mask;
+    if (form[i] == 5 || form[i] == 6) ovw_words.insert(i >> 5);
   }
   g.form = form.data();
+  g.smask = smask.data();
   const int n_ovw = (n_slots + 31) / 32;
   std::ostringstream& o = g.o;
   o << kPrelude << (g.c64 ? "typedef float T;\ntypedef float2 V;\n" : "typedef double T;\ntypedef double2 V;\n")

@@ -1523,8 +1523,30 @@ ptsbe_status build_plan(const ptsbe_circuit* c, const ptsbe_noise_model* nm, con
     // with half the arithmetic of a general complex matrix.
     // A 2x2 slot of noise sites only whose default (no error) is the identity
     // is applied only by the blocks whose trajectory overrides it.
+    // A 4x4 slot without parameters whose default is a diagonal of +-1 (a CZ
+    // and the noise sites after it) negates amplitudes unless overridden.
     for (Pass& ps : A.passes)
       for (Slot& sl : ps.slots) {
+        if (sl.type == DOP_M2 && !sl.parts.empty()) {
+          bool fixed = true;
+          for (const Part& pt : sl.parts) fixed = fixed && A.steps[pt.step].kind != ST_PARAM;
+          if (!fixed) continue;
+          const Mat D = slot_matrix(P, A.steps, sl, nullptr, {});
+          bool signs = true;
+          uint8_t mask = 0;
+          for (int r = 0; r < 4; ++r)
+            for (int c = 0; c < 4; ++c) {
+              const cd z = D[r * 4 + c];
+              if (r != c) signs = signs && z == cd(0, 0);
+              else if (z == cd(-1, 0)) mask |= (uint8_t)(1u << r);
+              else signs = signs && z == cd(1, 0);
+            }
+          if (signs) {
+            sl.form = 6;
+            sl.sign_mask = mask;
+          }
+          continue;
+        }
         if (sl.type != DOP_M1 || sl.parts.empty()) continue;
         if (!sl.sites.empty()) {
           bool sites_only = true;

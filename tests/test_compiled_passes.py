@@ -127,6 +127,8 @@ def test_adjoint_sweep_real_and_diagonal_forms():
     assert "= cm(m0, s" in body and "= cm(m3, l" in body  # diagonal form, psi and lambda
     assert "= cf(m0, x0, m1, x1)" in body          # general form (noise slots)
     assert "  if (__builtin_expect((ovw" in body    # ... applied only where overridden
+    assert "  } else {\n    s" in body               # CZ slots: negations unless overridden
+    assert all("amdgpu_waves_per_eu(3)" in s for s in srcs if s)  # three waves per SIMD
     obs = zz_ring(n)
     E, G = run_compiled_adjoint(plan, ts, params, observable_diag(n, obs))
     g = ts.get()
