@@ -305,12 +305,16 @@ def test_measure_reset_step_wider_than_one_group():
         assert float(np.max(np.abs(gpu[a] - ref[a]))) <= 1e-5
 
 
-def test_nondeterministic_measure_is_reported():
+@pytest.mark.parametrize("n_traj", [1, 3])
+def test_nondeterministic_measure_is_reported(n_traj):
+    """A measure-reset of |+> is reported, also when the trajectories share
+    their prefix and only the carried state is decided."""
     circ = {"n_qubits": 2, "ops": [{"kind": "gate", "name": "H", "qubits": (0,), "params": (), "tag": "H"},
-                                   {"kind": "measure_reset", "qubits": (0,)}],
+                                   {"kind": "measure_reset", "qubits": (0,)},
+                                   {"kind": "gate", "name": "H", "qubits": (1,), "params": (), "tag": "H"}],
             "channels": [], "rules": [], "params": []}
     plan = P.ptsbe_plan(circ)
-    ts = P.ptsbe_trajset_from_records(plan, [()], [4])
+    ts = P.ptsbe_trajset_from_records(plan, [()] * n_traj, [4] * n_traj)
     r = P.ptsbe_run_batch(plan, ts)
     with pytest.raises(P.PtsbeError) as e:
         P.ptsbe_run_status(plan, r["workspace"])
