@@ -40,13 +40,23 @@ namespace {
 uint64_t a256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
 
 struct AdjLayout {
-  uint64_t status, fwd, adj, aux, psi, lam, partial, ev, scan_part, scan_offs, scan_total, gdot;
+  uint64_t status, fwd, adj, aux, routes, psi, lam, partial, ev, scan_part, scan_offs, scan_total, gdot;
   uint64_t mr_partial, mr_bits, mr_norm, rec_info, ckpt, end;
   uint32_t batch, n_tiles, nblk, per_block, per_thread;
+  bool share;
 };
+
+// The forward preparation shares the error-free prefix as a batched run does
+// (plans without state-dependent channels): psi holds two more states, the
+// carried one read and written alternately.
+bool adjoint_share(const Plan& P, const TrajSet& ts) {
+  ptsbe_run_opts o{};
+  return prefix_sharing(P, ts, &o);
+}
 
 AdjLayout adj_layout(const Plan& P, const TrajSet& ts, uint32_t batch) {
   AdjLayout L{};
+  L.share = adjoint_share(P, ts);
   const uint64_t N = 1ull << P.n;
   const uint64_t esz = P.precision == PTSBE_C64 ? 8 : 16;
   const uint64_t B = ts.m.size();
@@ -63,7 +73,10 @@ AdjLayout adj_layout(const Plan& P, const TrajSet& ts, uint32_t batch) {
   L.fwd = o; o = a256(o + ts.table_blob.size());
   L.adj = o; o = a256(o + ts.adj_blob.size());
   L.aux = o; o = a256(o + B * 8 + std::max<uint64_t>(1, n_dot) * 4);   // weights, dot -> parameter
-  L.psi = o; o = a256(o + (uint64_t)batch * N * esz);
+  const uint64_t n_batches = (B + batch - 1) / std::max<uint32_t>(batch, 1);
+  L.routes = o;
+  if (L.share) o = a256(o + P.exec.size() * (B + n_batches) * sizeof(uint2));
+  L.psi = o; o = a256(o + (uint64_t)(batch + (L.share ? 2 : 0)) * N * esz);
   L.lam = o; o = a256(o + (uint64_t)batch * N * esz);
   L.partial = o; o = a256(o + B * L.n_tiles * std::max<uint64_t>(1, n_dot) * 8);
   L.ev = o; o = a256(o + B * 8);
@@ -134,6 +147,23 @@ ptsbe_status adjoint_typed(const Plan& P, TrajSet& ts, const double* coef, const
     std::memcpy(aux.data() + B * 8 + 4 * d, &p, 4);
   }
   CK(hipMemcpyAsync(ws + L.aux, aux.data(), aux.size(), hipMemcpyHostToDevice, s), "weights upload");
+  // launch routes of the forward preparation under prefix sharing
+  std::vector<uint32_t>& routes = ts.route_host;
+  std::vector<uint32_t>& route_off = ts.route_off;
+  routes.clear();
+  route_off.clear();
+  ts.eff_host.clear();
+  const uint32_t E = (uint32_t)P.exec.size();
+  if (L.share) {
+    std::vector<uint32_t> off;
+    for (uint32_t b0 = 0; b0 < B; b0 += L.batch) {
+      build_routes(P, ts, b0, std::min<uint32_t>(L.batch, B - b0), routes, off, ts.eff_host);
+      route_off.insert(route_off.end(), off.begin(), off.end());
+    }
+    CK(hipMemcpyAsync(ws + L.routes, routes.data(), routes.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s),
+       "route upload");
+  }
+  const uint2* d_routes = reinterpret_cast<const uint2*>(ws + L.routes);
   const uint32_t nm = (uint32_t)P.n_measure;
   const uint32_t* d_rec_chan = nullptr;
   const uint32_t* d_rec_gidx = nullptr;
@@ -171,11 +201,14 @@ ptsbe_status adjoint_typed(const Plan& P, TrajSet& ts, const double* coef, const
   aa.lam = lam;
   aa.partial = partial;
   aa.n_dot = n_dot;
-  for (uint32_t b0 = 0; b0 < B; b0 += L.batch) {
+  fa.carrier_t = B;
+  for (uint32_t b0 = 0, bi = 0; b0 < B; b0 += L.batch, ++bi) {
     const uint32_t bb = std::min<uint32_t>(L.batch, B - b0);
     fa.t0 = b0;
+    fa.carrier0 = bb;
     aa.p.t0 = b0;
-    for (const ExecStep& ex : P.exec) {
+    for (uint32_t e = 0; e < E; ++e) {
+      const ExecStep& ex = P.exec[e];
       if (ex.pass < 0) {
         // one state-dependent channel: checkpoint the state, then decide
         if (ex.mr_index.size() != 1 || !d_rec_chan || P.rec_info.rec_chan[ex.mr_index[0]] == 0xffffffffu)
@@ -223,13 +256,21 @@ ptsbe_status adjoint_typed(const Plan& P, TrajSet& ts, const double* coef, const
       }
       const Pass& ps = P.passes[ex.pass];
       fa.pass = (uint32_t)ex.pass;
+      uint32_t rows = bb;
+      fa.route = nullptr;
+      if (L.share) {
+        const uint32_t r0 = route_off[(size_t)bi * (E + 1) + e], r1 = route_off[(size_t)bi * (E + 1) + e + 1];
+        rows = r1 - r0;
+        fa.route = d_routes + r0;
+      }
+      if (!rows) continue;
       if (jit_has(P, (uint32_t)ex.pass)) {
-        CK(jit_launch<V>(P, (uint32_t)ex.pass, fa, bb, s), "compiled forward");
+        CK(jit_launch<V>(P, (uint32_t)ex.pass, fa, rows, s), "compiled forward");
       } else {
         if (ps.k > 12)  // the generic kernels hold at most 12-qubit tiles
           return fail(PTSBE_E_UNSUPPORTED, "forward pass " + std::to_string(ex.pass) +
                                                " has a 13-qubit tile and no compiled kernel");
-        CK(launch_pass<V>(fa, (uint32_t)ps.k, (uint32_t)ps.slots.size(), (uint32_t)ps.ops.size(), bb, s),
+        CK(launch_pass<V>(fa, (uint32_t)ps.k, (uint32_t)ps.slots.size(), (uint32_t)ps.ops.size(), rows, s),
            "forward");
       }
     }

@@ -240,6 +240,15 @@ struct TrajSet {
 // Normalised ensemble weights w_alpha = wbasis_alpha / sum (summed in trajectory order).
 std::vector<double> ensemble_weights(const TrajSet& ts);
 
+// Prefix sharing of the forward program (run.cpp): whether it applies to a run
+// of `ts` with options `o` (flags only), and the launch routes of the batch
+// [b0, b0 + bb): (source slot, destination slot) pairs per execution step,
+// step e's at out[2 off[e] .. 2 off[e + 1]), each trajectory's first own step
+// appended to eff_out.
+bool prefix_sharing(const Plan& P, const TrajSet& ts, const ptsbe_run_opts* o);
+void build_routes(const Plan& P, const TrajSet& ts, uint32_t b0, uint32_t bb, std::vector<uint32_t>& out,
+                  std::vector<uint32_t>& off, std::vector<uint32_t>& eff_out);
+
 // Matrix helpers
 Mat mat_identity(int d);
 Mat mat_mul(const Mat& a, const Mat& b, int d);        // a * b

@@ -13,19 +13,6 @@
 
 namespace ptsbe {
 
-namespace {
-
-uint64_t a256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
-
-struct WsLayout {
-  uint64_t status, tables, routes, eff, states, cdf, partial, offs, total, mr_partial, mr_bits, mr_norm, rec_info,
-      weights, sup_part, sup_offs, sup_count, sup_cdf, sup_idx, maxa, floor, end;
-  bool support;
-  uint32_t batch;
-  uint32_t nblk, per_block, per_thread;
-  bool share;
-};
-
 // Prefix sharing applies to plans whose first pass starts from |0> and whose
 // last step is a pass, when at least two trajectories are run and it is not
 // off.  Measure-resets may sit between the passes: their outcome is a function
@@ -40,6 +27,87 @@ bool prefix_sharing(const Plan& P, const TrajSet& ts, const ptsbe_run_opts* o) {
   if (P.exec.front().pass < 0 || P.exec.back().pass < 0) return false;
   return (P.passes[P.exec[0].pass].flags & PASS_INIT_ZERO) != 0;
 }
+
+// Launch routes of one batch under prefix sharing.  eff[b] is the first
+// execution step whose pass the trajectory's record changes (the last step,
+// a pass, if none does); before it the trajectory's state equals the
+// error-free state, which is carried in slots bb and bb + 1 (read one, write
+// the other, swap).  At pass step e: trajectories with eff == e read the
+// carried state, those with eff < e their own, and the carrier advances while
+// some eff > e.  At a measure-reset step e the rows are the states to decide:
+// each trajectory with eff < e, and the carried state (destination bb) while
+// some eff > e.  eff is appended to eff_out (batch order).
+void build_routes(const Plan& P, const TrajSet& ts, uint32_t b0, uint32_t bb, std::vector<uint32_t>& out,
+                  std::vector<uint32_t>& off, std::vector<uint32_t>& eff_out) {
+  const TableLayout& T = ts.layout;
+  const uint32_t* ov_off = reinterpret_cast<const uint32_t*>(ts.table_blob.data() + T.ov_off);
+  const uint32_t NP = (uint32_t)P.passes.size();
+  const uint32_t E = (uint32_t)P.exec.size();
+  std::vector<uint32_t> eff(bb, E - 1);
+  for (uint32_t b = 0; b < bb; ++b) {
+    const uint64_t row = (uint64_t)(b0 + b) * NP;
+    for (uint32_t e = 0; e < E; ++e) {
+      if (P.exec[e].pass < 0) continue;
+      const uint32_t p = (uint32_t)P.exec[e].pass;
+      if (ov_off[row + p + 1] > ov_off[row + p]) {
+        eff[b] = e;
+        break;
+      }
+    }
+  }
+  uint32_t cur = bb, nxt = bb + 1;
+  off.assign(E + 1, 0);
+  for (uint32_t e = 0; e < E; ++e) {
+    off[e] = (uint32_t)(out.size() / 2);
+    bool carry = false;
+    if (P.exec[e].pass < 0) {
+      for (uint32_t b = 0; b < bb; ++b) {
+        if (eff[b] < e) {
+          out.push_back(b);
+          out.push_back(b);
+        } else {
+          carry = true;
+        }
+      }
+      if (carry) {
+        out.push_back(cur);
+        out.push_back(bb);
+      }
+      continue;
+    }
+    for (uint32_t b = 0; b < bb; ++b) {
+      if (eff[b] < e) {
+        out.push_back(b);
+        out.push_back(b);
+      } else if (eff[b] == e) {
+        out.push_back(e == 0 ? b : cur);
+        out.push_back(b);
+      } else {
+        carry = true;
+      }
+    }
+    if (carry) {
+      out.push_back(cur);
+      out.push_back(nxt);
+      std::swap(cur, nxt);
+    }
+  }
+  off[E] = (uint32_t)(out.size() / 2);
+  eff_out.insert(eff_out.end(), eff.begin(), eff.end());
+}
+
+namespace {
+
+uint64_t a256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+
+struct WsLayout {
+  uint64_t status, tables, routes, eff, states, cdf, partial, offs, total, mr_partial, mr_bits, mr_norm, rec_info,
+      weights, sup_part, sup_offs, sup_count, sup_cdf, sup_idx, maxa, floor, end;
+  bool support;
+  uint32_t batch;
+  uint32_t nblk, per_block, per_thread;
+  bool share;
+};
 
 WsLayout layout_for(const Plan& P, const TrajSet& ts, uint32_t mode, uint32_t batch, uint64_t table_bytes,
                     bool share, bool support) {
@@ -145,74 +213,6 @@ double pass_flops_per_amp(const Pass& ps) {
     }
   }
   return f;
-}
-
-// Launch routes of one batch under prefix sharing.  eff[b] is the first
-// execution step whose pass the trajectory's record changes (the last step,
-// a pass, if none does); before it the trajectory's state equals the
-// error-free state, which is carried in slots bb and bb + 1 (read one, write
-// the other, swap).  At pass step e: trajectories with eff == e read the
-// carried state, those with eff < e their own, and the carrier advances while
-// some eff > e.  At a measure-reset step e the rows are the states to decide:
-// each trajectory with eff < e, and the carried state (destination bb) while
-// some eff > e.  eff is appended to eff_out (batch order).
-void build_routes(const Plan& P, const TrajSet& ts, uint32_t b0, uint32_t bb, std::vector<uint32_t>& out,
-                  std::vector<uint32_t>& off, std::vector<uint32_t>& eff_out) {
-  const TableLayout& T = ts.layout;
-  const uint32_t* ov_off = reinterpret_cast<const uint32_t*>(ts.table_blob.data() + T.ov_off);
-  const uint32_t NP = (uint32_t)P.passes.size();
-  const uint32_t E = (uint32_t)P.exec.size();
-  std::vector<uint32_t> eff(bb, E - 1);
-  for (uint32_t b = 0; b < bb; ++b) {
-    const uint64_t row = (uint64_t)(b0 + b) * NP;
-    for (uint32_t e = 0; e < E; ++e) {
-      if (P.exec[e].pass < 0) continue;
-      const uint32_t p = (uint32_t)P.exec[e].pass;
-      if (ov_off[row + p + 1] > ov_off[row + p]) {
-        eff[b] = e;
-        break;
-      }
-    }
-  }
-  uint32_t cur = bb, nxt = bb + 1;
-  off.assign(E + 1, 0);
-  for (uint32_t e = 0; e < E; ++e) {
-    off[e] = (uint32_t)(out.size() / 2);
-    bool carry = false;
-    if (P.exec[e].pass < 0) {
-      for (uint32_t b = 0; b < bb; ++b) {
-        if (eff[b] < e) {
-          out.push_back(b);
-          out.push_back(b);
-        } else {
-          carry = true;
-        }
-      }
-      if (carry) {
-        out.push_back(cur);
-        out.push_back(bb);
-      }
-      continue;
-    }
-    for (uint32_t b = 0; b < bb; ++b) {
-      if (eff[b] < e) {
-        out.push_back(b);
-        out.push_back(b);
-      } else if (eff[b] == e) {
-        out.push_back(e == 0 ? b : cur);
-        out.push_back(b);
-      } else {
-        carry = true;
-      }
-    }
-    if (carry) {
-      out.push_back(cur);
-      out.push_back(nxt);
-      std::swap(cur, nxt);
-    }
-  }
-  off[E] = (uint32_t)(out.size() / 2);
-  eff_out.insert(eff_out.end(), eff.begin(), eff.end());
 }
 
 // Stage timer: HIP events recorded on the caller's stream between launches;

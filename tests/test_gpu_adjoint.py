@@ -125,6 +125,27 @@ def test_batches_split_by_workspace():
     _check(circ, plan, ts, ref["records"], ref["weights"], params, zz_ring(7), "c128", max_batch=3)
 
 
+def test_shared_prefix_matches_single_trajectories():
+    """The forward preparation shares the error-free prefix across a set's
+    trajectories; each trajectory alone (nothing to share) gives its own
+    value and gradient, and their weighted sum equals the set's (complex128)."""
+    circ = hea_circuit(9, 3, np.random.default_rng(12), 1e-2)
+    params = np.asarray(circ["params"])
+    plan = P.ptsbe_plan(circ, precision="c128")
+    ts, _ = _sample(plan, circ, _prop(40), 4, 6)
+    B = ts.n_traj
+    assert B >= 3
+    E, G = _gpu(plan, ts, params, zz_ring(9))
+    w = ts.weights()
+    Es, Gs = 0.0, np.zeros_like(G)
+    for a in range(B):
+        Ea, Ga = _gpu(plan, ts.slice(a, a + 1), params, zz_ring(9))
+        Es += w[a] * Ea
+        Gs += w[a] * Ga
+    assert abs(E - Es) <= 1e-12
+    assert float(np.max(np.abs(G - Gs))) <= 1e-12
+
+
 def test_deterministic_repeat():
     circ = hea_circuit(9, 3, np.random.default_rng(8), 2e-2)
     params = np.asarray(circ["params"])
